@@ -1,0 +1,360 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix:
+hand-computed tiny meshes, closed-form ray counts (Eqs. L1-L3), canonical PO
+results (plate, dihedral, trihedral), the Mie series for the sphere (Sec. 5.1),
+and invariants of the transport (Algorithm 2)."""
+import numpy as np
+import pytest
+
+import sbr_inputs as si
+from oracle import closed_forms as cf
+from oracle import mie
+
+C0 = 299_792_458.0
+
+
+# --------------------------------------------------------------------------
+# Frame and ray grid, Eqs. (L1)-(L3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("th,ph", [(0, 0), (54.74, 0), (54.74, 45), (90, 0), (123.0, 77.0), (180, 30)])
+def test_frame_is_right_handed_orthonormal(orc, th, ph):
+    k, t, p = orc.frame(th, ph)
+    M = np.stack([p, t, k])
+    assert np.allclose(M @ M.T, np.eye(3), atol=1e-15)
+    # aperture axes u = phi_hat, v = theta_hat span the plane normal to k, u x v = k
+    assert np.allclose(np.cross(p, t), k, atol=1e-15)
+    # the radar sits along r = -k = (sin t cos p, sin t sin p, cos t)
+    thr, phr = np.radians(th), np.radians(ph)
+    assert np.allclose(-k, [np.sin(thr) * np.cos(phr), np.sin(thr) * np.sin(phr), np.cos(thr)], atol=1e-15)
+
+
+def _box_extent(bbox, axis):
+    # projected width of an axis-aligned box on a unit vector: sum |a_i| (hi_i - lo_i)
+    return float(np.sum(np.abs(axis) * (np.asarray(bbox[3:]) - np.asarray(bbox[:3]))))
+
+
+@pytest.mark.parametrize("th,ph,ds,expect", [
+    (0.0, 0.0, C0 / 3e9 / 10, (221, 221)),          # sphere case: 2.2 m at lambda/10
+    (90 - 35.26, 45.0, C0 / 10e9 / 10, (519, 600)),  # trihedral case, phi = 45
+    (90 - 35.26, 0.0, C0 / 10e9 / 10, (367, 512)),   # trihedral case, phi = 0
+])
+def test_ray_counts_eq_L3(orc, th, ph, ds, expect):
+    bbox = [-1, -1, -1, 1, 1, 1] if th == 0.0 else [0, 0, 0, 1, 1, 1]
+    Nu, Nv, uc, vc, s0 = orc.aperture(np.array(bbox, float), th, ph, ds, 0.1)
+    k, t, p = orc.frame(th, ph)
+    Lu, Lv = _box_extent(bbox, p), _box_extent(bbox, t)
+    assert (Nu, Nv) == (int(np.ceil(1.1 * Lu / ds)), int(np.ceil(1.1 * Lv / ds)))
+    assert (Nu, Nv) == expect
+
+
+def test_trihedral_sweep_total_rays(orc):
+    w = si.trihedral_case()
+    tot = 0
+    for th, ph in zip(w.theta_deg, w.phi_deg):
+        Nu, Nv, *_ = orc.aperture(np.array([0, 0, 0, 1, 1, 1.0]), th, ph, w.ds, 0.1)
+        tot += Nu * Nv
+    assert tot == 48_377_932
+
+
+def test_ray_grid_geometry(orc):
+    bbox = np.array([-0.3, -1.0, 0.2, 0.9, 0.4, 1.7])
+    th, ph, ds = 63.0, 21.0, 0.01
+    o, d, Nu, Nv = orc.gen_rays(bbox, th, ph, ds, 0.1)
+    k, t, p = orc.frame(th, ph)
+    assert np.array_equal(d, k.astype(np.float32))
+    O = o.astype(np.float64).reshape(Nv, Nu, 3)
+    # uniform spacing ds along u (i) and v (j), all on one plane normal to k
+    du = (O[:, 1:] - O[:, :-1]) @ p
+    dv = (O[1:, :] - O[:-1, :]) @ t
+    assert np.allclose(du, ds, atol=1e-6) and np.allclose(dv, ds, atol=1e-6)
+    assert np.ptp(O.reshape(-1, 3) @ k) < 1e-6
+    # centred on the projected box, in front of every corner
+    corners = np.array([[bbox[3 * (c & 1)], bbox[1 + 3 * ((c >> 1) & 1)], bbox[2 + 3 * ((c >> 2) & 1)]]
+                        for c in range(8)])
+    cu = 0.5 * ((corners @ p).min() + (corners @ p).max())
+    cv = 0.5 * ((corners @ t).min() + (corners @ t).max())
+    assert abs((O.reshape(-1, 3) @ p).mean() - cu) < 1e-6
+    assert abs((O.reshape(-1, 3) @ t).mean() - cv) < 1e-6
+    assert (O.reshape(-1, 3) @ k).max() < (corners @ k).min()
+
+
+# --------------------------------------------------------------------------
+# Tiny meshes with hand-computed answers
+# --------------------------------------------------------------------------
+def _mesh(orc, V, T):
+    return orc.Mesh(np.array(V, np.float32), np.array(T, np.int32))
+
+
+def _trace1(orc, m, o, d, bmax=5, **kw):
+    k = np.array(d, np.float64) / np.linalg.norm(d)
+    e = np.cross(k, [0.3, 0.5, 0.7])
+    e /= np.linalg.norm(e)
+    return orc.trace(m, np.array([o], np.float32), np.array(d, np.float32), e, np.cross(e, k), k, bmax,
+                     want_path=True, **kw)
+
+
+def test_single_triangle_hit_miss_parallel_back(orc):
+    m = _mesh(orc, [[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[0, 1, 2]])
+    r = _trace1(orc, m, [0.25, 0.25, 1.0], [0, 0, -1])
+    assert r["nb"][0] == 1 and r["tri_first"][0] == 0 and r["tri_last"][0] == 0
+    assert r["path"][0] == 1.0 and np.array_equal(r["x_last"][0], [0.25, 0.25, 0.0])
+    assert r["D"][0] == 0.0   # -1 (origin) + 1 (path) + 0 (last hit) along k = -z
+    assert not (r["flags"][0] & orc.F_BACK_LAST)
+    assert list(r["tri_path"][0]) == [0, -1, -1, -1, -1]
+    assert _trace1(orc, m, [0.75, 0.75, 1.0], [0, 0, -1])["nb"][0] == 0        # beyond the hypotenuse
+    assert _trace1(orc, m, [-1.0, 0.2, 0.0], [1, 0, 0])["nb"][0] == 0          # in-plane: det == 0
+    assert _trace1(orc, m, [0.25, 0.25, 1.0], [0, 0, 1])["nb"][0] == 0         # t <= 0 (behind)
+    rb = _trace1(orc, m, [0.25, 0.25, -2.0], [0, 0, 1])                        # two-sided: back face
+    assert rb["nb"][0] == 1 and rb["path"][0] == 2.0 and (rb["flags"][0] & orc.F_BACK_LAST)
+
+
+@pytest.mark.parametrize("swap", [False, True])
+def test_shared_edge_and_vertex_ties_go_to_smaller_id(orc, swap):
+    A = [[0, 1, 2], [0, 2, 3]]
+    if swap:
+        A = A[::-1]
+    m = _mesh(orc, [[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], A)
+    r = _trace1(orc, m, [0.5, 0.5, 1.0], [0, 0, -1], edge_diag=True)   # on the shared diagonal
+    assert r["nb"][0] == 1 and r["tri_first"][0] == 0
+    assert r["flags"][0] & orc.F_EDGE and r["edge_rays"] == 1
+    r = _trace1(orc, m, [0.0, 0.0, 1.0], [0, 0, -1])                   # on the shared vertex
+    assert r["nb"][0] == 1 and r["tri_first"][0] == 0
+    r = _trace1(orc, m, [0.3, 0.6, 1.0], [0, 0, -1], edge_diag=True)   # interior: not flagged
+    assert r["tri_first"][0] == (1 if not swap else 0) and not (r["flags"][0] & orc.F_EDGE)
+
+
+def test_two_mirror_chain_retroreflects(orc):
+    # mirrors on x = 0 (id 0) and y = 0 (id 1); a ray in the x-y plane at 45 deg
+    V = [[0, -5, -5], [0, 5, -5], [0, 0, 5], [-5, 0, -5], [5, 0, -5], [0, 0, 5]]
+    m = _mesh(orc, V, [[0, 1, 2], [3, 4, 5]])
+    s = np.sqrt(0.5)
+    r = _trace1(orc, m, [1.0, 2.0, 0.1], [-s, -s, 0.0], bmax=5)
+    assert r["nb"][0] == 2 and list(r["tri_path"][0][:3]) == [0, 1, -1]
+    # path sqrt(2) + sqrt(2) (both segments); the second segment starts eps
+    # off the first mirror, which moves the last hit by eps along x
+    eps = float(m.eps)
+    assert abs(r["path"][0] - 2 * np.sqrt(2)) < eps
+    assert np.allclose(r["x_last"][0], [1.0 + eps, 0.0, 0.1], atol=1e-6)
+    # corner line through the origin: round-trip path D = 2 k.(corner) = 0,
+    # kept to first order in eps by the offset correction of the path
+    assert abs(r["D"][0]) < 1e-6
+    rl = _trace1(orc, m, [1.0, 2.0, 0.1], [-s, -s, 0.0], bmax=5, paper_path=True)
+    assert abs(rl["path"][0] - 2 * np.sqrt(2)) < 1e-6 and abs(rl["D"][0] + eps * s) < 1e-6
+
+
+def test_pec_polarisation_after_two_mirrors(orc):
+    # z-polarised field keeps its sign through two reflections; the in-plane
+    # polarisation comes back reversed (the dihedral's even-bounce HH = -VV)
+    V = [[0, -5, -5], [0, 5, -5], [0, 0, 5], [-5, 0, -5], [5, 0, -5], [0, 0, 5]]
+    m = _mesh(orc, V, [[0, 1, 2], [3, 4, 5]])
+    s = np.sqrt(0.5)
+    k = np.array([-s, -s, 0.0])
+    eh = np.array([s, -s, 0.0])
+    ev = np.array([0.0, 0.0, 1.0])
+    r = orc.trace(m, np.array([[1.0, 2.0, 0.1]], np.float32), k.astype(np.float32), eh, ev, k, 5)
+    # arriving at the second mirror (after one reflection on x = 0)
+    assert np.allclose(r["eV_last"][0], [0, 0, -1], atol=1e-7)
+    assert np.allclose(r["eH_last"][0], [s, s, 0], atol=1e-7)
+
+
+def test_trapped_between_parallel_mirrors(orc):
+    V = [[-5, -5, 0], [5, -5, 0], [0, 5, 0], [-5, -5, 1], [5, -5, 1], [0, 5, 1]]
+    m = _mesh(orc, V, [[0, 1, 2], [3, 4, 5]])
+    r = _trace1(orc, m, [0.1, 0.2, 0.5], [0, 0, 1], bmax=4)
+    assert r["nb"][0] == 4 and r["flags"][0] & orc.F_VALID and r["queries"] == 4
+    r = _trace1(orc, m, [0.1, 0.2, 0.5], [0, 0, 1], bmax=4, drop_trapped=True)
+    assert r["nb"][0] == 4 and (r["flags"][0] & orc.F_TRAPPED) and not (r["flags"][0] & orc.F_VALID)
+    assert r["queries"] == 5
+
+
+def test_invalid_and_degenerate_mesh(orc):
+    with pytest.raises(ValueError):
+        orc.Mesh(np.array([[0, 0, np.nan], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 2]], np.int32))
+    with pytest.raises(ValueError):
+        orc.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 3]], np.int32))
+    # a zero-area triangle is skipped, the real one behind it is hit
+    m = _mesh(orc, [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 0.5], [1, 1, 0.5], [2, 2, 0.5]],
+              [[3, 4, 5], [0, 1, 2]])
+    assert m.n_degen == 1
+    r = _trace1(orc, m, [0.25, 0.25, 1.0], [0, 0, -1])
+    assert r["tri_first"][0] == 1
+
+
+# --------------------------------------------------------------------------
+# Closed-form PO targets
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1])
+def test_plate_normal_incidence(orc, mode):
+    V, T = si.plate(1.0, 1.0, 8, 8)
+    m = orc.Mesh(V, T)
+    f = 10e9
+    r = orc.rcs_angle(m, 0.0, 0.0, [f], 10.0, bmax=5, mode=mode)
+    lam = C0 / f
+    # which grid points fall on the plate, counted directly from the grid
+    Nu, Nv, uc, vc, _ = orc.aperture(m.bbox, 0.0, 0.0, r["ds"], 0.1)
+    u = uc + (np.arange(Nu) + 0.5 - Nu / 2) * r["ds"]     # along phi_hat = +y
+    v = vc + (np.arange(Nv) + 0.5 - Nv / 2) * r["ds"]     # along theta_hat = +x
+    n_in = np.sum(np.abs(u) <= 0.5) * np.sum(np.abs(v) <= 0.5)
+    assert (r["nb"] == 1).sum() == n_in and (r["nb"] > 1).sum() == 0
+    A = r["A"][0]
+    exact = 4 * np.pi * (n_in * r["ds"] ** 2) ** 2 / lam ** 2    # every phase equal
+    assert np.isclose(4 * np.pi * abs(A[0, 0]) ** 2, exact, rtol=1e-9)
+    assert np.isclose(4 * np.pi * abs(A[1, 1]) ** 2, exact, rtol=1e-9)
+    assert abs(A[0, 1]) == 0 and abs(A[1, 0]) == 0
+    # discrete area within one perimeter strip of the true area
+    assert abs(n_in * r["ds"] ** 2 - 1.0) <= 4 * 1.0 * r["ds"]
+    assert abs(cf.dbsm(exact) - cf.dbsm(cf.plate_normal(1.0, f))) < 0.1
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.0])
+def test_plate_principal_plane_vector(orc, theta):
+    # tilt about x (side a): incidence in the y-z plane, phi = 90
+    V, T = si.plate(1.0, 1.0, 8, 8)
+    m = orc.Mesh(V, T)
+    f = 10e9
+    r = orc.rcs_angle(m, theta, 90.0, [f], 20.0, bmax=5, mode=0)
+    s = 4 * np.pi * np.abs(r["A"][0]) ** 2
+    ref = cf.plate_principal_plane(1.0, 1.0, f, np.radians(theta))
+    assert abs(cf.dbsm(s[0, 0]) - cf.dbsm(ref)) < 0.1
+    assert abs(cf.dbsm(s[1, 1]) - cf.dbsm(ref)) < 0.1
+
+
+def test_trihedral_axis_peak(orc):
+    V, T = si.trihedral(1.0, 16)
+    m = orc.Mesh(V, T)
+    f = 10e9
+    th = 90.0 - np.degrees(np.arctan(1 / np.sqrt(2)))   # symmetry axis (1,1,1)
+    rv = orc.rcs_angle(m, th, 45.0, [f], 10.0, bmax=5, mode=0)
+    rp = orc.rcs_angle(m, th, 45.0, [f], 10.0, bmax=5, mode=1)
+    peak = cf.dbsm(cf.trihedral_square_peak(1.0, f))
+    sv = orc.sigma_dbsm(rv["A"])[0]
+    sp = orc.sigma_dbsm(rp["A"])[0]
+    assert abs(sv[0, 0] - peak) < 0.1 and abs(sv[1, 1] - peak) < 0.1
+    # the literal Eq. (po_sum) carries the first-hit obliquity: 1/sqrt(3)^2 in power
+    assert abs(sp[0, 0] - (peak + 10 * np.log10(1 / 3))) < 0.1
+    tri = rv["nb"] == 3
+    # triple-bounce rays leave along -k with equal round-trip path
+    k = rv["k"]
+    n_last = m.normals[rv["tri_last"][tri]].astype(np.float64)
+    dl = rv["d_last"][tri].astype(np.float64)
+    d_out = dl - 2 * np.sum(dl * n_last, 1, keepdims=True) * n_last
+    assert np.allclose(d_out, -k, atol=1e-6)
+    assert np.ptp(rv["D"][tri]) < 2e-5
+    # effective area sqrt(3) a^2, within one strip of the hexagon perimeter (6 a sqrt(2/3))
+    assert abs(tri.sum() * rv["ds"] ** 2 - np.sqrt(3)) <= 6 * np.sqrt(2 / 3) * rv["ds"]
+
+
+def test_dihedral_bisector_polarimetric(orc):
+    V, T = si.dihedral(1.0, 1.0, 8)
+    m = orc.Mesh(V, T)
+    f = 10e9
+    r = orc.rcs_angle(m, 90.0, 45.0, [f], 10.0, bmax=5, mode=0)
+    A = r["A"][0]
+    peak = cf.dbsm(cf.dihedral_peak(1.0, 1.0, f))
+    s = orc.sigma_dbsm(r["A"])[0]
+    assert abs(s[0, 0] - peak) < 0.2 and abs(s[1, 1] - peak) < 0.2
+    # even bounce: HH = -VV
+    ratio = A[0, 0] / A[1, 1]
+    assert abs(ratio + 1) < 0.02
+
+
+def test_translation_multiplies_by_phase(orc):
+    V, T = si.trihedral(1.0, 8)
+    shift = np.array([0.25, -0.5, 0.125], np.float32)
+    f = 10e9
+    m0, m1 = orc.Mesh(V, T), orc.Mesh(V + shift, T)
+    r0 = orc.rcs_angle(m0, 60.0, 30.0, [f], 10.0, bmax=5)
+    r1 = orc.rcs_angle(m1, 60.0, 30.0, [f], 10.0, bmax=5)
+    k = 2 * np.pi * f / C0
+    ph = np.exp(-1j * k * 2 * np.dot(r0["k"], shift.astype(np.float64)))
+    assert np.allclose(r1["A"], r0["A"] * ph, rtol=2e-3, atol=2e-3 * np.abs(r0["A"]).max())
+
+
+def test_multi_frequency_equals_single_calls(orc):
+    V, T = si.trihedral(1.0, 8)
+    m = orc.Mesh(V, T)
+    fs = [8e9, 9.5e9, 10e9]
+    r = orc.rcs_angle(m, 60.0, 30.0, fs, 10.0, bmax=5)
+    for i, f in enumerate(fs):
+        A = orc.po(m, r, 0, r["k"], r["th_hat"], r["ph_hat"], r["ds"] ** 2, [f])
+        assert np.array_equal(A[0], r["A"][i])
+
+
+def test_reflection_invariants_random_mesh(orc):
+    V, T = si.random_triangles(300, seed=3, box=1.0, size=0.3)
+    m = orc.Mesh(V, T)
+    o, _ = si.random_rays(4000, seed=4, box=1.5)
+    k, ev, eh = orc.frame(33.0, 57.0)      # one launch direction, transverse H/V
+    o = (o - 3.0 * k).astype(np.float32)   # start every ray upstream of the soup
+    r = orc.trace(m, o, k.astype(np.float32), eh, ev, k, 6)
+    hit = r["nb"] > 0
+    assert hit.sum() > 500 and (r["nb"] >= 2).sum() > 50
+    dl = r["d_last"][hit].astype(np.float64)
+    assert np.allclose(np.linalg.norm(dl, axis=1), 1.0, atol=1e-5)   # |d| kept through reflections
+    # the PEC map 2nn^T - I is a rotation (up to the float32 rounding of the
+    # unit normals): field vectors stay unit and mutually orthogonal
+    for e in (r["eH_last"][hit], r["eV_last"][hit]):
+        assert np.allclose(np.linalg.norm(e, axis=1), 1.0, atol=1e-6)
+    assert np.allclose(np.sum(r["eH_last"][hit] * r["eV_last"][hit], 1), 0.0, atol=1e-6)
+    # and the field stays transverse to the ray
+    for e in (r["eH_last"][hit], r["eV_last"][hit]):
+        assert np.allclose(np.sum(e * dl, 1), 0.0, atol=1e-5)
+    # the direction map I - 2nn^T is a mirror: (eH x d) flips with each bounce
+    N = r["nb"][hit]
+    ok = (N == 1)
+    # at the first hit the incident frame is the launch frame
+    assert np.allclose(r["eH_last"][hit][ok], eh) and np.allclose(r["eV_last"][hit][ok], ev)
+
+
+# --------------------------------------------------------------------------
+# Sphere (Sec. 5.1) and the Mie series
+# --------------------------------------------------------------------------
+def test_mie_limits():
+    for ka in (0.01, 0.02):
+        assert abs(mie.mie_pec_backscatter_norm(ka) / (9 * ka ** 4) - 1) < 0.3 * ka ** 2   # Rayleigh
+    for ka in (1000.0, 3000.0):
+        assert abs(mie.mie_pec_backscatter_norm(ka) - 1) < 1e-5                               # optical
+    # the resonance maximum near ka = 1 of the textbook curve
+    ks = np.linspace(0.8, 1.2, 41)
+    vals = [mie.mie_pec_backscatter_norm(x) for x in ks]
+    assert 3.5 < max(vals) < 3.8 and 0.9 < ks[int(np.argmax(vals))] < 1.1
+
+
+def test_sphere_converges_to_mie(orc):
+    w = si.sphere_case()
+    m = orc.Mesh(w.V, w.T).build_bvh()
+    ref = 10 * np.log10(mie.mie_pec_sigma(1.0, 3e9))
+    for mode in (0, 1):
+        r = orc.rcs_angle(m, 0.0, 0.0, [3e9], 40.0, bmax=5, mode=mode, use_bvh=True)
+        assert abs(orc.sigma_dbsm(r["A"])[0][1, 1] - ref) < 0.05
+    # the paper's literal sum at the lambda/10 grid of the sphere case
+    r = orc.rcs_angle(m, 0.0, 0.0, [3e9], 10.0, bmax=5, mode=1, use_bvh=True)
+    assert abs(orc.sigma_dbsm(r["A"])[0][1, 1] - ref) < 0.4
+    assert (r["nb"] > 1).sum() == 0       # convex: one bounce only
+
+
+# --------------------------------------------------------------------------
+# Fast mode (Algorithm 1 BVH) is bit-exact against brute force
+# --------------------------------------------------------------------------
+KEYS = ("nb", "tri_first", "tri_last", "flags", "path", "D", "d_last", "x_last", "eH_last", "eV_last")
+
+
+@pytest.mark.parametrize("rule", ["sah", "median"])
+def test_bvh_fast_mode_bit_exact(orc, rule):
+    cases = []
+    V, T = si.random_triangles(2000, seed=7, box=1.0, size=0.15)
+    o, d = si.random_rays(20000, seed=8, box=1.3)
+    cases.append((V, T, o, d))
+    V, T = si.trihedral(1.0, 16)
+    o, d, *_ = orc.gen_rays(np.array([0, 0, 0, 1, 1, 1.0]), 54.74, 30.0, 0.006)
+    cases.append((V, T, o, d))
+    V, T = si.icosphere(4)
+    o, d, *_ = orc.gen_rays(np.array([-1, -1, -1, 1, 1, 1.0]), 37.0, 11.0, 0.02)
+    cases.append((V, T, o, d))
+    for V, T, o, d in cases:
+        m = orc.Mesh(V, T).build_bvh(rule)
+        k = np.array([0, 0, -1.0])
+        a = orc.trace(m, o, d, [1.0, 0, 0], [0, 1.0, 0], k, 5, want_path=True)
+        b = orc.trace(m, o, d, [1.0, 0, 0], [0, 1.0, 0], k, 5, want_path=True, use_bvh=True)
+        for key in KEYS + ("tri_path",):
+            assert np.array_equal(a[key], b[key]), key
+        assert b["tri_tests"] < a["tri_tests"]
