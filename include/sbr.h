@@ -1,0 +1,272 @@
+/*
+ * sbr.h -- C ABI of the MI355X (gfx950) SBR trace-integrate library.
+ *
+ * The library computes the monostatic radar cross section of a perfectly
+ * conducting triangle mesh by shooting and bouncing rays (arXiv 2604.09243):
+ * an orthographic ray grid per incidence angle (Sec. 4, Eqs. L1-L3), multi-
+ * bounce specular transport through a BVH (Algorithm 2), and the ray-tube
+ * physical-optics sum over the valid hits (Eq. po_sum; Eqs. em5-em6), giving
+ * sigma = 4 pi |A|^2 (Sec. 4, trace-integrate paragraph).
+ *
+ * Conventions (all entry points):
+ *  - Every call returns an sbr_status; on a non-OK status a message is
+ *    available from sbr_last_error() (thread-local, valid until the next
+ *    failing call on the same thread).  No call throws across the ABI.
+ *  - Inputs are borrowed; the library never frees caller memory.  Output
+ *    buffers are caller-owned and must be large enough for the documented
+ *    shape.  "device" pointers are HIP device (or managed) memory on the
+ *    context's device; "host" pointers are ordinary host memory.
+ *  - Device work is enqueued on the context stream and is asynchronous
+ *    unless the SBR_OPT_SYNC flag is given; results in device buffers are
+ *    valid after the stream has been synchronised.  Statistics structs
+ *    (host) are filled only when the call synchronises (SBR_OPT_SYNC, or a
+ *    non-NULL stats pointer, which implies a synchronisation).
+ *  - Option structs begin with struct_size (set it to sizeof the struct).
+ *  - Units: metres, hertz, degrees at the API.  Polarisation index 0 = H
+ *    (phi_hat), 1 = V (theta_hat).  Complex values are two doubles (re, im).
+ *  - Angles: theta is the polar angle from +z, phi the azimuth; the radar
+ *    sits along r = (sin t cos p, sin t sin p, cos t) and the incident wave
+ *    travels along k = -r.
+ */
+#ifndef SBR_H
+#define SBR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBR_ABI_VERSION 1
+#define SBR_MAX_BOUNCES 64
+
+typedef struct sbr_ctx sbr_ctx; /* device + stream + workspace */
+typedef struct sbr_bvh sbr_bvh; /* prepared mesh + BVH in device memory */
+
+typedef enum {
+    SBR_OK = 0,
+    SBR_ERR_INVALID_ARG = -1,  /* bad pointer, size, enum or option */
+    SBR_ERR_INVALID_MESH = -2, /* non-finite vertex or index out of range */
+    SBR_ERR_SAMPLING = -3,     /* ray spacing coarser than lambda/5 */
+    SBR_ERR_OOM = -4,          /* device or host allocation failed */
+    SBR_ERR_HIP = -5,          /* HIP runtime error (message has details) */
+    SBR_ERR_OVERFLOW = -6,     /* a count exceeds a documented limit */
+    SBR_ERR_UNSUPPORTED = -7   /* feature not available on this device */
+} sbr_status;
+
+enum { SBR_POL_H = 0, SBR_POL_V = 1 };
+
+/* PO sum (Eq. po_sum and its polarimetric reading):
+ *  SBR_MODE_VECTOR: Eqs. em5-em6 applied to each ray tube's footprint on
+ *    its last facet, with the field reflected at every PEC hit; gives all
+ *    four (receive, transmit) polarisation pairs.
+ *  SBR_MODE_PAPER:  Eq. po_sum literally (first-hit obliquity, Gamma = -1);
+ *    co-polar only (HH = VV, cross-polar terms are zero). */
+enum { SBR_MODE_VECTOR = 0, SBR_MODE_PAPER = 1 };
+
+enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
+
+/* per-ray record flags (sbr_hits.flags) */
+#define SBR_REC_VALID 1     /* at least one hit (Algorithm 2 "valid") and not dropped */
+#define SBR_REC_TRAPPED 2   /* still hitting after max_bounces (see SBR_OPT_DROP_TRAPPED) */
+#define SBR_REC_BACK_LAST 4 /* the last hit was on the side opposite the stored normal */
+
+/* option flags (sbr_trace_opts.flags, sbr_sweep.flags) */
+#define SBR_OPT_DROP_TRAPPED 1        /* one extra query at max_bounces; rays that hit are invalid */
+#define SBR_OPT_PAPER_PATH 2          /* path = sum of t only (no offset correction) */
+#define SBR_OPT_ALLOW_UNDERSAMPLING 4 /* accept ray spacing coarser than lambda/5 */
+#define SBR_OPT_SYNC 8                /* synchronise the stream before returning */
+
+/* ------------------------------------------------------------------------ */
+/* Library and context                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* SBR_ABI_VERSION of the built library. */
+int sbr_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *sbr_last_error(void);
+
+/* Creates a context on HIP device `device` enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  *out receives the
+ * context, released with sbr_destroy.  Errors: INVALID_ARG (no device of
+ * that index, NULL out), HIP. */
+int sbr_create(sbr_ctx **out, int device, void *hip_stream);
+
+/* Changes the stream later calls enqueue on. */
+int sbr_set_stream(sbr_ctx *ctx, void *hip_stream);
+
+/* Blocks until all work enqueued by the context has finished. */
+int sbr_synchronize(sbr_ctx *ctx);
+
+/* Frees the context and its workspace.  BVHs built with it must be freed
+ * first.  NULL is accepted. */
+void sbr_destroy(sbr_ctx *ctx);
+
+/* ------------------------------------------------------------------------ */
+/* sbr_build_bvh -- mesh preparation and BVH (Sec. 4 BVH paragraph; the      */
+/* paper's host-built Algorithm 1 is replaced by a GPU LBVH)                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t struct_size;
+    int32_t mem; /* SBR_MEM_HOST or SBR_MEM_DEVICE: where verts/tris live */
+} sbr_bvh_opts;
+
+typedef struct {
+    int64_t n_tris;       /* triangles given */
+    int64_t n_live;       /* non-degenerate triangles (in the BVH) */
+    int64_t n_nodes;      /* internal nodes (n_live - 1, at least 1) */
+    int32_t depth;        /* longest root-to-leaf path (edges) */
+    float eps;            /* surface offset (1e-5 of the bounding-box diagonal) */
+    double bbox[6];       /* lo xyz, hi xyz of the referenced vertices */
+    int64_t device_bytes; /* device memory held by the BVH */
+} sbr_bvh_info;
+
+/* verts: [n_verts][3] float32 (metres); tris: [n_tris][3] int32 vertex
+ * indices; both in host or device memory per opts->mem (NULL opts = host).
+ * Copies what it needs into library-owned device memory; *out is released
+ * by sbr_free_bvh.  Per triangle: e1 = v1 - v0, e2 = v2 - v0 (float32), unit
+ * normal from e1 x e2 evaluated in float64; triangles with area below
+ * 1e-12 * diag^2 are degenerate and skipped (not an error).  Errors:
+ * INVALID_MESH (non-finite vertex, index outside [0, n_verts)),
+ * INVALID_ARG (n_tris < 1 or > 2^28, NULL pointers), OOM, HIP.  Blocks the
+ * host until the BVH is complete. */
+int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                  const sbr_bvh_opts *opts, sbr_bvh **out);
+
+int sbr_bvh_get_info(const sbr_bvh *bvh, sbr_bvh_info *out);
+
+/* Unit normals of all n_tris triangles in input order ([n_tris][3] float32,
+ * host memory; zero for degenerate triangles). */
+int sbr_bvh_normals(const sbr_bvh *bvh, float *out_host);
+
+void sbr_free_bvh(sbr_bvh *bvh);
+
+/* ------------------------------------------------------------------------ */
+/* sbr_trace -- multi-bounce transport of caller rays (Algorithm 2)          */
+/* ------------------------------------------------------------------------ */
+
+/* Rays, device memory, [n][3] float32 each.  eH/eV: transmit polarisation
+ * vectors carried with each ray (unit, orthogonal to d). */
+typedef struct {
+    const float *o;
+    const float *d;
+    const float *eH;
+    const float *eV;
+} sbr_rays;
+
+/* Per-ray results, device memory, caller-allocated, indexed by ray.  Any
+ * pointer may be NULL to skip that output.  "last" quantities are those
+ * arriving at the last hit (before its reflection). */
+typedef struct {
+    int32_t *n_bounce;  /* [n] number of hits N (0 = missed) */
+    int32_t *tri_first; /* [n] input index of the first triangle hit, -1 if none */
+    int32_t *tri_last;  /* [n] input index of the last triangle hit, -1 if none */
+    int32_t *flags;     /* [n] SBR_REC_* */
+    double *path;       /* [n] one-way path P along the ray (float64) */
+    double *D;          /* [n] round-trip phase path k.o + P + k.x_last (float64) */
+    float *d_last;      /* [n][3] */
+    float *x_last;      /* [n][3] */
+    float *eH_last;     /* [n][3] */
+    float *eV_last;     /* [n][3] */
+    int32_t *tri_path;  /* [n][max_bounces] triangle hit at each bounce, -1 after the end */
+} sbr_hits;
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t flags;  /* SBR_OPT_DROP_TRAPPED | SBR_OPT_PAPER_PATH | SBR_OPT_SYNC */
+    double k_hat[3]; /* direction defining D (usually the launch direction) */
+} sbr_trace_opts;
+
+typedef struct {
+    int64_t rays;      /* rays launched */
+    int64_t queries;   /* closest-hit queries (rays x bounces incl. the final miss) */
+    int64_t valid;     /* rays with SBR_REC_VALID */
+    int64_t trapped;   /* rays with SBR_REC_TRAPPED */
+    int64_t hits[SBR_MAX_BOUNCES + 1]; /* hits[b] = rays that hit at bounce b (1-based) */
+    int64_t angles;    /* incidence angles processed */
+    double ms_trace;   /* GPU time of ray generation + all bounces */
+    double ms_po;      /* GPU time of the PO sum + finalize */
+    double ms_total;   /* wall time of the call */
+} sbr_stats;
+
+/* Traces n_rays rays (1 <= n_rays < 2^31) for up to max_bounces (1..64)
+ * reflections.  Closest hit = smallest (t, input triangle index); triangles
+ * are two-sided, the previous triangle is skipped, each new origin is
+ * x + eps * (facing normal).  Errors: INVALID_ARG, OOM, HIP.  stats (host,
+ * nullable) implies a synchronisation. */
+int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays, int max_bounces,
+              const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats);
+
+/* ------------------------------------------------------------------------ */
+/* sbr_po_integrate -- ray-tube physical-optics sum (Eq. po_sum; em5-em6)    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t struct_size;
+    int32_t mode;        /* SBR_MODE_VECTOR or SBR_MODE_PAPER */
+    double k_hat[3];     /* incident direction */
+    double theta_hat[3]; /* V receive/transmit vector */
+    double phi_hat[3];   /* H receive/transmit vector */
+    double dA;           /* ray-tube area ds^2 (m^2) */
+} sbr_po_desc;
+
+/* Sums over the rays of `hits` (device, as written by sbr_trace; needs
+ * n_bounce, tri_first, tri_last, flags, D, d_last, eH_last, eV_last) whose
+ * flags have SBR_REC_VALID.  freqs_hz: host [n_freq] (1..4096).  A_out:
+ * device [n_freq][2 receive][2 transmit] complex128, i.e. n_freq*8 doubles.
+ * The sum is exact-order independent (fixed-point accumulation), so the
+ * result is bitwise reproducible.  Errors: INVALID_ARG, OOM, HIP. */
+int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits *hits, int64_t n_rays,
+                     const sbr_po_desc *desc, const double *freqs_hz, int n_freq, double *A_out);
+
+/* ------------------------------------------------------------------------ */
+/* sbr_rcs_sweep -- monostatic RCS over many incidence angles                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t struct_size;
+    const double *theta_deg; /* host [n_angles] */
+    const double *phi_deg;   /* host [n_angles] */
+    int64_t n_angles;        /* 1 .. 2^24 */
+    const double *freqs_hz;  /* host [n_freq] */
+    int32_t n_freq;          /* 1 .. 4096 */
+    int32_t max_bounces;     /* 1 .. 64 */
+    double ds;               /* ray spacing (m); 0 = c / (f_max * samples_per_lambda) */
+    double samples_per_lambda;
+    double eta;              /* aperture margin of Eq. L2 (0.1 if negative) */
+    int32_t mode;            /* SBR_MODE_* */
+    uint32_t flags;          /* SBR_OPT_* */
+} sbr_sweep;
+
+/* For every angle: ray grid of Eqs. L1-L3 over the mesh bounding box (cell
+ * centred, one trace at the spacing of the highest frequency), transport,
+ * PO sum for every frequency.  A_out: device
+ * [n_angles][n_freq][2][2] complex128; sigma_dbsm: device
+ * [n_angles][n_freq][2][2] float64 (10 log10 of 4 pi |A|^2, -400 for 0),
+ * nullable.  Errors: SAMPLING (ds > lambda_min / 5 without
+ * SBR_OPT_ALLOW_UNDERSAMPLING), INVALID_ARG, OOM, HIP.  stats (host,
+ * nullable) implies a synchronisation. */
+int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sweep, double *A_out, double *sigma_dbsm,
+                  sbr_stats *stats);
+
+/* ------------------------------------------------------------------------ */
+/* Host-only helper (no GPU): the ray grid of one angle, Eqs. L1-L3          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double k_hat[3], theta_hat[3], phi_hat[3];
+    double uc, vc, s0, ds;
+    int64_t nu, nv; /* rays along phi_hat and theta_hat; ray index = j * nu + i */
+} sbr_angle_plan;
+
+/* bbox: lo xyz, hi xyz.  Errors: INVALID_ARG (ds <= 0, non-finite input). */
+int sbr_plan_angle(const double bbox[6], double theta_deg, double phi_deg, double ds, double eta,
+                   sbr_angle_plan *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBR_H */

@@ -1,0 +1,690 @@
+// C ABI of the SBR library: context, workspace, argument checking and the
+// orchestration of the kernels of each entry point.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "sbr_internal.hpp"
+
+namespace sbr {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int status, const std::string &msg)
+{
+    g_err = msg;
+    return status;
+}
+
+// ---------------------------------------------------------------- workspace
+Workspace::~Workspace()
+{
+    for (auto &b : bufs)
+        if (b.p) (void)hipFree(b.p);
+    if (pinned) (void)hipHostFree(pinned);
+}
+
+int Workspace::get(int i, size_t bytes, void **out)
+{
+    if (static_cast<int>(bufs.size()) <= i) bufs.resize(i + 1);
+    Buf &b = bufs[i];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        const size_t want = std::max<size_t>(bytes, 256);
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SBR_ERR_OOM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+        }
+        b.bytes = want;
+    }
+    *out = b.p;
+    return SBR_OK;
+}
+
+int Workspace::get_pinned(size_t bytes, void **out)
+{
+    if (pinned_bytes < bytes) {
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        pinned_bytes = 0;
+        if (hipHostMalloc(&pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SBR_ERR_OOM, "pinned host allocation failed");
+        }
+        pinned_bytes = bytes;
+    }
+    *out = pinned;
+    return SBR_OK;
+}
+
+// workspace slots
+enum Slot {
+    W_COUNTERS = 0,
+    W_QA = 1,   // 6 buffers: 1..6
+    W_QB = 7,   // 7..12
+    W_REC = 13, // 13..16
+    W_PLANS = 17,
+    W_TILEBASE = 18,
+    W_RECBASE = 19,
+    W_BASIS = 20,
+    W_KF = 21,
+    W_PARTIAL = 22,
+    W_SPILL = 23,
+};
+
+static int get_queue(Workspace *ws, int first, size_t cap, RayQueue &q)
+{
+    void *p[6];
+    const size_t sz[6] = {16, 16, 16, 16, 16, 16};
+    for (int i = 0; i < 6; ++i) {
+        int rc = ws->get(first + i, sz[i] * cap, &p[i]);
+        if (rc) return rc;
+    }
+    q.s0 = static_cast<float4 *>(p[0]);
+    q.s1 = static_cast<float4 *>(p[1]);
+    q.s2 = static_cast<float4 *>(p[2]);
+    q.s3 = static_cast<float4 *>(p[3]);
+    q.s4 = static_cast<double2 *>(p[4]);
+    q.s5 = static_cast<double2 *>(p[5]);
+    return SBR_OK;
+}
+
+static int get_records(Workspace *ws, size_t cap, Records &r)
+{
+    void *p[4];
+    int rc;
+    if ((rc = ws->get(W_REC + 0, 16 * cap, &p[0])) || (rc = ws->get(W_REC + 1, 16 * cap, &p[1])) ||
+        (rc = ws->get(W_REC + 2, 16 * cap, &p[2])) || (rc = ws->get(W_REC + 3, 8 * cap, &p[3])))
+        return rc;
+    r.r0 = static_cast<float4 *>(p[0]);
+    r.r1 = static_cast<float4 *>(p[1]);
+    r.r2 = static_cast<float4 *>(p[2]);
+    r.D = static_cast<double *>(p[3]);
+    return SBR_OK;
+}
+
+// Counter block: stat u64[kStatU64], q_cnt u32[kQcnt], rec_cnt u32[n_angles].
+struct Counters {
+    unsigned long long *stat;
+    uint32_t *q_cnt;
+    uint32_t *rec_cnt;
+    size_t bytes;
+};
+
+static int get_counters(Workspace *ws, int n_angles, Counters &c)
+{
+    const size_t bytes = 8 * kStatU64 + 4 * kQcnt + 4 * static_cast<size_t>(n_angles);
+    void *p;
+    int rc = ws->get(W_COUNTERS, bytes, &p);
+    if (rc) return rc;
+    c.stat = static_cast<unsigned long long *>(p);
+    c.q_cnt = reinterpret_cast<uint32_t *>(c.stat + kStatU64);
+    c.rec_cnt = c.q_cnt + kQcnt;
+    c.bytes = bytes;
+    return SBR_OK;
+}
+
+static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int32_t **spill)
+{
+    const int blocks = trace_persistent_blocks(ctx);
+    const int extra = std::max(0, bvh->depth + 2 - trace_stack_lds());
+    const size_t n = static_cast<size_t>(std::max(extra, 1)) * blocks * trace_block_threads();
+    void *p;
+    int rc = ctx->ws->get(W_SPILL, 4 * n, &p);
+    if (rc) return rc;
+    *spill = static_cast<int32_t *>(p);
+    return SBR_OK;
+}
+
+static void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax)
+{
+    st->queries += static_cast<int64_t>(hstat[0]);
+    st->trapped += static_cast<int64_t>(hstat[1]);
+    for (int b = 1; b <= bmax && b <= SBR_MAX_BOUNCES; ++b) st->hits[b] += static_cast<int64_t>(hstat[8 + b]);
+    // a ray is valid when it hit at bounce 1 and was not dropped as trapped
+    st->valid += static_cast<int64_t>(hstat[8 + 1]) - static_cast<int64_t>(hstat[1]);
+}
+
+}  // namespace sbr
+
+using namespace sbr;
+
+// ---------------------------------------------------------------- library
+extern "C" int sbr_version(void) { return SBR_ABI_VERSION; }
+
+extern "C" const char *sbr_last_error(void) { return g_err.c_str(); }
+
+extern "C" int sbr_create(sbr_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return fail(SBR_ERR_INVALID_ARG, "sbr_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return fail(SBR_ERR_INVALID_ARG, "sbr_create: no HIP device with index " + std::to_string(device));
+    }
+    SBR_HIP(hipSetDevice(device));
+    sbr_ctx *c = new (std::nothrow) sbr_ctx();
+    if (!c) return fail(SBR_ERR_OOM, "sbr_create: out of host memory");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws = new (std::nothrow) Workspace();
+    if (hipGetDeviceProperties(&c->prop, device) != hipSuccess || !c->ws) {
+        delete c->ws;
+        delete c;
+        return fail(SBR_ERR_HIP, "sbr_create: hipGetDeviceProperties failed");
+    }
+    *out = c;
+    return SBR_OK;
+}
+
+extern "C" int sbr_set_stream(sbr_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return fail(SBR_ERR_INVALID_ARG, "sbr_set_stream: NULL context");
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return SBR_OK;
+}
+
+extern "C" int sbr_synchronize(sbr_ctx *ctx)
+{
+    if (!ctx) return fail(SBR_ERR_INVALID_ARG, "sbr_synchronize: NULL context");
+    SBR_HIP(hipSetDevice(ctx->device));
+    SBR_HIP(hipStreamSynchronize(ctx->stream));
+    return SBR_OK;
+}
+
+extern "C" void sbr_destroy(sbr_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx->ws;
+    delete ctx;
+}
+
+// ---------------------------------------------------------------- BVH
+extern "C" int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, const int32_t *tris,
+                             int64_t n_tris, const sbr_bvh_opts *opts, sbr_bvh **out)
+{
+    if (!ctx || !out || !verts || !tris) return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: NULL argument");
+    *out = nullptr;
+    if (n_tris < 1 || n_tris > (int64_t(1) << 28) || n_verts < 3 || n_verts > (int64_t(1) << 31) - 1)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: n_tris must be in [1, 2^28] and n_verts >= 3");
+    int mem = SBR_MEM_HOST;
+    if (opts) {
+        if (opts->struct_size < sizeof(uint32_t) + sizeof(int32_t))
+            return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: opts->struct_size too small");
+        mem = opts->mem;
+    }
+    if (mem != SBR_MEM_HOST && mem != SBR_MEM_DEVICE)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: opts->mem must be SBR_MEM_HOST or SBR_MEM_DEVICE");
+    SBR_HIP(hipSetDevice(ctx->device));
+    std::vector<float> hv;
+    std::vector<int32_t> ht;
+    const float *V = verts;
+    const int32_t *T = tris;
+    if (mem == SBR_MEM_DEVICE) {
+        hv.resize(3 * n_verts);
+        ht.resize(3 * n_tris);
+        SBR_HIP(hipMemcpyAsync(hv.data(), verts, 12 * n_verts, hipMemcpyDeviceToHost, ctx->stream));
+        SBR_HIP(hipMemcpyAsync(ht.data(), tris, 12 * n_tris, hipMemcpyDeviceToHost, ctx->stream));
+        SBR_HIP(hipStreamSynchronize(ctx->stream));
+        V = hv.data();
+        T = ht.data();
+    }
+    PreparedMesh pm;
+    int rc = prepare_mesh(V, n_verts, T, n_tris, pm);
+    if (rc) return rc;
+    sbr_bvh *b = new (std::nothrow) sbr_bvh();
+    if (!b) return fail(SBR_ERR_OOM, "sbr_build_bvh: out of host memory");
+    b->device = ctx->device;
+    b->n_tris = n_tris;
+    b->eps = pm.eps;
+    b->diag = pm.diag;
+    std::memcpy(b->bbox, pm.bbox, sizeof(pm.bbox));
+    rc = build_lbvh(ctx, pm, b);
+    if (rc) {
+        sbr_free_bvh(b);
+        return rc;
+    }
+    b->host_normals = pm.n;
+    *out = b;
+    return SBR_OK;
+}
+
+extern "C" int sbr_bvh_get_info(const sbr_bvh *bvh, sbr_bvh_info *out)
+{
+    if (!bvh || !out) return fail(SBR_ERR_INVALID_ARG, "sbr_bvh_get_info: NULL argument");
+    out->n_tris = bvh->n_tris;
+    out->n_live = bvh->n_live;
+    out->n_nodes = bvh->n_nodes;
+    out->depth = bvh->depth;
+    out->eps = bvh->eps;
+    std::memcpy(out->bbox, bvh->bbox, sizeof(bvh->bbox));
+    out->device_bytes = bvh->device_bytes;
+    return SBR_OK;
+}
+
+extern "C" int sbr_bvh_normals(const sbr_bvh *bvh, float *out_host)
+{
+    if (!bvh || !out_host) return fail(SBR_ERR_INVALID_ARG, "sbr_bvh_normals: NULL argument");
+    std::memcpy(out_host, bvh->host_normals.data(), sizeof(float) * bvh->host_normals.size());
+    return SBR_OK;
+}
+
+extern "C" void sbr_free_bvh(sbr_bvh *bvh)
+{
+    if (!bvh) return;
+    (void)hipSetDevice(bvh->device);
+    if (bvh->nodes) (void)hipFree(bvh->nodes);
+    if (bvh->tris) (void)hipFree(bvh->tris);
+    if (bvh->nrm_slot) (void)hipFree(bvh->nrm_slot);
+    if (bvh->nrm_id) (void)hipFree(bvh->nrm_id);
+    delete bvh;
+}
+
+// ---------------------------------------------------------------- trace
+extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays, int max_bounces,
+                         const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!ctx || !bvh || !rays || !out) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: NULL argument");
+    if (!rays->o || !rays->d || !rays->eH || !rays->eV)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_trace: rays->o, d, eH and eV are required");
+    if (n_rays < 1 || n_rays > 2147483647LL) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: n_rays out of range");
+    if (max_bounces < 1 || max_bounces > SBR_MAX_BOUNCES)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_trace: max_bounces must be in [1, 64]");
+    uint32_t flags = 0;
+    double k[3] = {0, 0, -1};
+    if (opts) {
+        if (opts->struct_size < sizeof(sbr_trace_opts))
+            return fail(SBR_ERR_INVALID_ARG, "sbr_trace: opts->struct_size too small");
+        flags = opts->flags;
+        for (int a = 0; a < 3; ++a) k[a] = opts->k_hat[a];
+    }
+    if (bvh->device != ctx->device) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: BVH lives on another device");
+    SBR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    Workspace *ws = ctx->ws;
+    int rc;
+    Counters cn;
+    RayQueue qa, qb;
+    int32_t *spill;
+    if ((rc = get_counters(ws, 1, cn)) || (rc = get_queue(ws, W_QA, n_rays, qa)) ||
+        (rc = get_queue(ws, W_QB, n_rays, qb)) || (rc = get_spill(ctx, bvh, &spill)))
+        return rc;
+    SBR_HIP(hipMemsetAsync(cn.stat, 0, cn.bytes, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool want_stats = stats != nullptr;
+    if (want_stats) {
+        SBR_HIP(hipEventCreate(&e0));
+        SBR_HIP(hipEventCreate(&e1));
+        SBR_HIP(hipEventRecord(e0, s));
+    }
+    TraceArgs a{};
+    a.bvh = bvh;
+    a.bmax = max_bounces;
+    a.flags = flags;
+    a.rays = rays;
+    a.n_rays = n_rays;
+    a.hits = out;
+    for (int i = 0; i < 3; ++i) a.k_hat[i] = k[i];
+    a.rec_cnt = cn.rec_cnt;
+    a.q_cnt = cn.q_cnt;
+    a.stat = cn.stat;
+    a.spill = spill;
+    if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: the mesh has no non-degenerate triangle");
+    a.q_in = qb;
+    a.q_out = qa;
+    if ((rc = launch_trace_rays(s, a))) return rc;
+    for (int b = 2; b <= max_bounces; ++b) {
+        std::swap(a.q_in, a.q_out);
+        if ((rc = launch_trace_queue(s, a, b, true))) return rc;
+    }
+    if (want_stats || (flags & SBR_OPT_SYNC)) {
+        unsigned long long hstat[kStatU64];
+        SBR_HIP(hipMemcpyAsync(hstat, cn.stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
+        if (want_stats) SBR_HIP(hipEventRecord(e1, s));
+        SBR_HIP(hipStreamSynchronize(s));
+        if (want_stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->rays = n_rays;
+            fill_stats(stats, hstat, max_bounces);
+            float ms = 0;
+            SBR_HIP(hipEventElapsedTime(&ms, e0, e1));
+            stats->ms_trace = ms;
+            stats->ms_total =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+    }
+    return SBR_OK;
+}
+
+// ---------------------------------------------------------------- PO
+static int basis_from_desc(const sbr_po_desc *d, double out[9])
+{
+    for (int a = 0; a < 3; ++a) {
+        out[a] = d->k_hat[a];
+        out[3 + a] = d->theta_hat[a];
+        out[6 + a] = d->phi_hat[a];
+    }
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(out[i])) return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: non-finite basis");
+    return SBR_OK;
+}
+
+extern "C" int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits *hits, int64_t n_rays,
+                                const sbr_po_desc *desc, const double *freqs_hz, int n_freq, double *A_out)
+{
+    if (!ctx || !bvh || !hits || !desc || !freqs_hz || !A_out)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: NULL argument");
+    if (desc->struct_size < sizeof(sbr_po_desc))
+        return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: desc->struct_size too small");
+    if (!hits->n_bounce || !hits->tri_first || !hits->tri_last || !hits->flags || !hits->D || !hits->d_last ||
+        !hits->eH_last || !hits->eV_last)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: hits lacks a required array");
+    if (n_rays < 1 || n_rays > 2147483647LL) return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: n_rays out of range");
+    if (n_freq < 1 || n_freq > 4096) return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: n_freq must be in [1, 4096]");
+    if (desc->mode != SBR_MODE_VECTOR && desc->mode != SBR_MODE_PAPER)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: unknown mode");
+    if (!(desc->dA > 0.0)) return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: dA must be positive");
+    for (int f = 0; f < n_freq; ++f)
+        if (!(freqs_hz[f] > 0.0) || !std::isfinite(freqs_hz[f]))
+            return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: frequencies must be positive");
+    SBR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    Workspace *ws = ctx->ws;
+    int rc;
+    double basis[9];
+    if ((rc = basis_from_desc(desc, basis))) return rc;
+    Counters cn;
+    Records rec;
+    void *pb, *pkf, *prb, *ppart, *ph;
+    const int chunks = static_cast<int>((n_rays + kPoRecsPerBlock - 1) / kPoRecsPerBlock);
+    const size_t host_bytes = 9 * 8 + 8 + 8 * static_cast<size_t>(n_freq);
+    if ((rc = get_counters(ws, 1, cn)) || (rc = get_records(ws, n_rays, rec)) || (rc = ws->get(W_BASIS, 72, &pb)) ||
+        (rc = ws->get(W_KF, 8 * n_freq, &pkf)) || (rc = ws->get(W_RECBASE, 8, &prb)) ||
+        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(chunks) * n_freq, &ppart)) ||
+        (rc = ws->get_pinned(host_bytes, &ph)))
+        return rc;
+    SBR_HIP(hipStreamSynchronize(s));  // the pinned staging buffer may still feed an earlier copy
+    double *hb = static_cast<double *>(ph);
+    std::memcpy(hb, basis, 72);
+    int64_t zero = 0;
+    std::memcpy(hb + 9, &zero, 8);
+    for (int f = 0; f < n_freq; ++f) hb[10 + f] = 2.0 * kPi * freqs_hz[f] / kC0;
+    SBR_HIP(hipMemcpyAsync(pb, hb, 72, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(prb, hb + 9, 8, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(pkf, hb + 10, 8 * n_freq, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemsetAsync(cn.stat, 0, cn.bytes, s));
+    if ((rc = launch_pack_hits(s, hits, n_rays, rec, cn.rec_cnt))) return rc;
+    PoArgs pa{};
+    pa.bvh = bvh;
+    pa.rec = rec;
+    pa.rec_cnt = cn.rec_cnt;
+    pa.rec_base = static_cast<const int64_t *>(prb);
+    pa.n_angles = 1;
+    pa.chunks = chunks;
+    pa.mode = desc->mode;
+    pa.kf = static_cast<const double *>(pkf);
+    pa.n_freq = n_freq;
+    pa.basis = static_cast<const double *>(pb);
+    pa.partial = static_cast<long long *>(ppart);
+    if ((rc = launch_po(s, pa)) || (rc = launch_po_finalize(s, pa, desc->dA, A_out, nullptr))) return rc;
+    return SBR_OK;
+}
+
+// ---------------------------------------------------------------- sweep
+extern "C" int sbr_plan_angle(const double bbox[6], double theta_deg, double phi_deg, double ds, double eta,
+                              sbr_angle_plan *out)
+{
+    if (!bbox || !out) return fail(SBR_ERR_INVALID_ARG, "sbr_plan_angle: NULL argument");
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(bbox[i])) return fail(SBR_ERR_INVALID_ARG, "sbr_plan_angle: non-finite bbox");
+    return plan_angle(bbox, theta_deg, phi_deg, ds, eta, *out);
+}
+
+namespace {
+constexpr int64_t kChunkRays = int64_t(1) << 26;  // rays per sweep chunk (queues sized for it)
+}
+
+extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sw, double *A_out,
+                             double *sigma_dbsm, sbr_stats *stats)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!ctx || !bvh || !sw || !A_out) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: NULL argument");
+    if (sw->struct_size < sizeof(sbr_sweep))
+        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: sweep->struct_size too small");
+    if (!sw->theta_deg || !sw->phi_deg || !sw->freqs_hz)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: NULL angle or frequency array");
+    if (sw->n_angles < 1 || sw->n_angles > (int64_t(1) << 24))
+        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: n_angles must be in [1, 2^24]");
+    if (sw->n_freq < 1 || sw->n_freq > 4096)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: n_freq must be in [1, 4096]");
+    if (sw->max_bounces < 1 || sw->max_bounces > SBR_MAX_BOUNCES)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: max_bounces must be in [1, 64]");
+    if (sw->mode != SBR_MODE_VECTOR && sw->mode != SBR_MODE_PAPER)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: unknown mode");
+    if (bvh->device != ctx->device) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: BVH lives on another device");
+    double fmax = 0.0;
+    for (int f = 0; f < sw->n_freq; ++f) {
+        if (!(sw->freqs_hz[f] > 0.0) || !std::isfinite(sw->freqs_hz[f]))
+            return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: frequencies must be positive and finite");
+        fmax = std::max(fmax, sw->freqs_hz[f]);
+    }
+    double ds = sw->ds;
+    if (!(ds > 0.0)) {
+        if (!(sw->samples_per_lambda > 0.0))
+            return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: give ds or samples_per_lambda");
+        ds = kC0 / fmax / sw->samples_per_lambda;
+    }
+    // sampling rule of Sec. 4: ds <= lambda / 5 at the highest frequency
+    if (ds > (kC0 / fmax / 5.0) * (1.0 + 1e-12) && !(sw->flags & SBR_OPT_ALLOW_UNDERSAMPLING))
+        return fail(SBR_ERR_SAMPLING, "sbr_rcs_sweep: ray spacing " + std::to_string(ds) +
+                                          " m exceeds lambda/5 at the highest frequency");
+    const double eta = sw->eta < 0.0 ? 0.1 : sw->eta;
+    if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: the mesh has no non-degenerate triangle");
+    SBR_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    Workspace *ws = ctx->ws;
+    const int64_t na = sw->n_angles;
+    const int nf = sw->n_freq;
+    int rc;
+
+    // plans of every angle (host, float64)
+    std::vector<AnglePlan> plans(na);
+    std::vector<double> basis(9 * na);
+    for (int64_t a = 0; a < na; ++a) {
+        sbr_angle_plan ap;
+        if ((rc = plan_angle(bvh->bbox, sw->theta_deg[a], sw->phi_deg[a], ds, eta, ap))) return rc;
+        if (ap.nu * ap.nv > (int64_t(1) << 31) - 1) return fail(SBR_ERR_OVERFLOW, "sbr_rcs_sweep: too many rays per angle");
+        AnglePlan &p = plans[a];
+        for (int i = 0; i < 3; ++i) {
+            p.k[i] = ap.k_hat[i];
+            p.u[i] = ap.phi_hat[i];
+            p.v[i] = ap.theta_hat[i];
+            p.d32[i] = static_cast<float>(ap.k_hat[i]);
+            p.eH32[i] = static_cast<float>(ap.phi_hat[i]);
+            p.eV32[i] = static_cast<float>(ap.theta_hat[i]);
+            basis[9 * a + i] = ap.k_hat[i];
+            basis[9 * a + 3 + i] = ap.theta_hat[i];
+            basis[9 * a + 6 + i] = ap.phi_hat[i];
+        }
+        p.uc = ap.uc;
+        p.vc = ap.vc;
+        p.s0 = ap.s0;
+        p.ds = ds;
+        p.nu = static_cast<int32_t>(ap.nu);
+        p.nv = static_cast<int32_t>(ap.nv);
+        p.tu = static_cast<int32_t>((ap.nu + 7) / 8);
+        p.tv = static_cast<int32_t>((ap.nv + 7) / 8);
+    }
+    // chunks of consecutive angles holding at most kChunkRays rays (or one angle)
+    std::vector<int64_t> cstart;
+    int64_t max_chunk_rays = 0, max_chunk_angles = 0;
+    {
+        int64_t a = 0;
+        while (a < na) {
+            cstart.push_back(a);
+            int64_t rays = 0, tiles = 0, b = a;
+            while (b < na) {
+                const int64_t r = int64_t(plans[b].nu) * plans[b].nv;
+                if (b > a && rays + r > kChunkRays) break;
+                plans[b].tile_base = tiles;
+                plans[b].rec_base = rays;
+                tiles += int64_t(plans[b].tu) * plans[b].tv;
+                rays += r;
+                ++b;
+            }
+            max_chunk_rays = std::max(max_chunk_rays, rays);
+            max_chunk_angles = std::max(max_chunk_angles, b - a);
+            a = b;
+        }
+        cstart.push_back(na);
+    }
+    const int n_chunks = static_cast<int>(cstart.size()) - 1;
+    int64_t max_rays_angle = 0;
+    for (const auto &p : plans) max_rays_angle = std::max(max_rays_angle, int64_t(p.nu) * p.nv);
+    const int po_chunks = static_cast<int>((max_rays_angle + kPoRecsPerBlock - 1) / kPoRecsPerBlock);
+
+    // device buffers
+    Counters cn;
+    RayQueue qa, qb;
+    Records rec;
+    int32_t *spill;
+    void *dplans, *dtile, *drecb, *dbasis, *dkf, *dpart, *hpin;
+    const size_t tile_words = static_cast<size_t>(na + n_chunks);
+    if ((rc = get_counters(ws, static_cast<int>(max_chunk_angles), cn)) ||
+        (rc = get_queue(ws, W_QA, max_chunk_rays, qa)) || (rc = get_queue(ws, W_QB, max_chunk_rays, qb)) ||
+        (rc = get_records(ws, max_chunk_rays, rec)) || (rc = get_spill(ctx, bvh, &spill)) ||
+        (rc = ws->get(W_PLANS, sizeof(AnglePlan) * na, &dplans)) || (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) ||
+        (rc = ws->get(W_RECBASE, 8 * na, &drecb)) || (rc = ws->get(W_BASIS, 72 * na, &dbasis)) ||
+        (rc = ws->get(W_KF, 8 * nf, &dkf)) ||
+        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(po_chunks) * nf * max_chunk_angles, &dpart)))
+        return rc;
+    // host staging (pinned): plans | tile bases | rec bases | basis | kf
+    const size_t off_plans = 0;
+    const size_t off_tile = off_plans + sizeof(AnglePlan) * na;
+    const size_t off_recb = off_tile + 8 * tile_words;
+    const size_t off_basis = off_recb + 8 * na;
+    const size_t off_kf = off_basis + 72 * na;
+    const size_t host_bytes = off_kf + 8 * nf;
+    if ((rc = ws->get_pinned(host_bytes, &hpin))) return rc;
+    SBR_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed an earlier copy
+    char *hp = static_cast<char *>(hpin);
+    std::memcpy(hp + off_plans, plans.data(), sizeof(AnglePlan) * na);
+    {
+        int64_t *tb = reinterpret_cast<int64_t *>(hp + off_tile);
+        int64_t *rb = reinterpret_cast<int64_t *>(hp + off_recb);
+        size_t w = 0;
+        for (int c = 0; c < n_chunks; ++c) {
+            int64_t tiles = 0;
+            for (int64_t a = cstart[c]; a < cstart[c + 1]; ++a) {
+                tb[w++] = plans[a].tile_base;
+                tiles = plans[a].tile_base + int64_t(plans[a].tu) * plans[a].tv;
+                rb[a] = plans[a].rec_base;
+            }
+            tb[w++] = tiles;
+        }
+    }
+    std::memcpy(hp + off_basis, basis.data(), 72 * na);
+    double *hkf = reinterpret_cast<double *>(hp + off_kf);
+    for (int f = 0; f < nf; ++f) hkf[f] = 2.0 * kPi * sw->freqs_hz[f] / kC0;
+    SBR_HIP(hipMemcpyAsync(dplans, hp + off_plans, sizeof(AnglePlan) * na, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(dtile, hp + off_tile, 8 * tile_words, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(drecb, hp + off_recb, 8 * na, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(dbasis, hp + off_basis, 72 * na, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(dkf, hp + off_kf, 8 * nf, hipMemcpyHostToDevice, s));
+
+    const bool want_stats = stats != nullptr;
+    std::vector<hipEvent_t> ev;
+    if (want_stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        ev.resize(3 * n_chunks);
+        for (auto &e : ev) SBR_HIP(hipEventCreate(&e));
+    }
+    std::vector<unsigned long long> hstat(static_cast<size_t>(kStatU64) * n_chunks);
+    size_t tile_off = 0;
+    for (int c = 0; c < n_chunks; ++c) {
+        const int64_t a0 = cstart[c], a1 = cstart[c + 1];
+        const int m = static_cast<int>(a1 - a0);
+        const AnglePlan *cp = static_cast<const AnglePlan *>(dplans) + a0;
+        const int64_t *ctile = static_cast<const int64_t *>(dtile) + tile_off;
+        tile_off += m + 1;
+        int64_t n_tiles = 0, n_rays = 0;
+        for (int64_t a = a0; a < a1; ++a) {
+            n_tiles += int64_t(plans[a].tu) * plans[a].tv;
+            n_rays += int64_t(plans[a].nu) * plans[a].nv;
+        }
+        SBR_HIP(hipMemsetAsync(cn.stat, 0, cn.bytes, s));
+        if (want_stats) SBR_HIP(hipEventRecord(ev[3 * c], s));
+        TraceArgs ta{};
+        ta.bvh = bvh;
+        ta.bmax = sw->max_bounces;
+        ta.flags = sw->flags;
+        ta.plans = cp;
+        ta.tile_base = ctile;
+        ta.n_angles = m;
+        ta.n_tiles = n_tiles;
+        ta.rec = rec;
+        ta.rec_cnt = cn.rec_cnt;
+        ta.q_cnt = cn.q_cnt;
+        ta.stat = cn.stat;
+        ta.spill = spill;
+        ta.q_in = qb;
+        ta.q_out = qa;
+        if ((rc = launch_trace_grid(s, ta, 1))) return rc;
+        for (int b = 2; b <= sw->max_bounces; ++b) {
+            std::swap(ta.q_in, ta.q_out);
+            if ((rc = launch_trace_queue(s, ta, b, false))) return rc;
+        }
+        if (want_stats) SBR_HIP(hipEventRecord(ev[3 * c + 1], s));
+        PoArgs pa{};
+        pa.bvh = bvh;
+        pa.rec = rec;
+        pa.rec_cnt = cn.rec_cnt;
+        pa.rec_base = static_cast<const int64_t *>(drecb) + a0;
+        pa.n_angles = m;
+        pa.chunks = po_chunks;
+        pa.mode = sw->mode;
+        pa.kf = static_cast<const double *>(dkf);
+        pa.n_freq = nf;
+        pa.basis = static_cast<const double *>(dbasis) + 9 * a0;
+        pa.partial = static_cast<long long *>(dpart);
+        if ((rc = launch_po(s, pa))) return rc;
+        if ((rc = launch_po_finalize(s, pa, ds * ds, A_out + a0 * nf * 8, sigma_dbsm ? sigma_dbsm + a0 * nf * 4 : nullptr)))
+            return rc;
+        if (want_stats) {
+            SBR_HIP(hipEventRecord(ev[3 * c + 2], s));
+            SBR_HIP(hipMemcpyAsync(hstat.data() + static_cast<size_t>(kStatU64) * c, cn.stat, 8 * kStatU64,
+                                   hipMemcpyDeviceToHost, s));
+            stats->rays += n_rays;
+        }
+    }
+    if (want_stats || (sw->flags & SBR_OPT_SYNC)) SBR_HIP(hipStreamSynchronize(s));
+    if (want_stats) {
+        for (int c = 0; c < n_chunks; ++c) {
+            fill_stats(stats, hstat.data() + static_cast<size_t>(kStatU64) * c, sw->max_bounces);
+            float t1 = 0, t2 = 0;
+            SBR_HIP(hipEventElapsedTime(&t1, ev[3 * c], ev[3 * c + 1]));
+            SBR_HIP(hipEventElapsedTime(&t2, ev[3 * c + 1], ev[3 * c + 2]));
+            stats->ms_trace += t1;
+            stats->ms_po += t2;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        stats->angles = na;
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return SBR_OK;
+}

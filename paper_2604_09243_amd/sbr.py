@@ -1,0 +1,312 @@
+"""ctypes binding of ``libsbr.so`` (the C ABI declared in ``include/sbr.h``).
+
+Argument marshalling only: every step of the SBR path runs in the library's
+HIP kernels.  torch supplies device memory (tensors are passed by
+``data_ptr()``) and the stream (``torch.cuda.current_stream().cuda_stream``).
+If the library is missing the import of this module fails: there is no CPU
+fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbr.so")
+
+OK, ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_SAMPLING, ERR_OOM, ERR_HIP, ERR_OVERFLOW, ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+POL_H, POL_V = 0, 1
+MODE_VECTOR, MODE_PAPER = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+REC_VALID, REC_TRAPPED, REC_BACK_LAST = 1, 2, 4
+OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC = 1, 2, 4, 8
+MAX_BOUNCES = 64
+
+_vp = C.c_void_p
+_d3 = C.c_double * 3
+
+
+class BvhOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("mem", C.c_int32)]
+
+
+class BvhInfo(C.Structure):
+    _fields_ = [("n_tris", C.c_int64), ("n_live", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32),
+                ("eps", C.c_float), ("bbox", C.c_double * 6), ("device_bytes", C.c_int64)]
+
+
+class Rays(C.Structure):
+    _fields_ = [("o", _vp), ("d", _vp), ("eH", _vp), ("eV", _vp)]
+
+
+class Hits(C.Structure):
+    _fields_ = [("n_bounce", _vp), ("tri_first", _vp), ("tri_last", _vp), ("flags", _vp), ("path", _vp),
+                ("D", _vp), ("d_last", _vp), ("x_last", _vp), ("eH_last", _vp), ("eV_last", _vp),
+                ("tri_path", _vp)]
+
+
+class TraceOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("flags", C.c_uint32), ("k_hat", _d3)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("rays", C.c_int64), ("queries", C.c_int64), ("valid", C.c_int64), ("trapped", C.c_int64),
+                ("hits", C.c_int64 * (MAX_BOUNCES + 1)), ("angles", C.c_int64), ("ms_trace", C.c_double),
+                ("ms_po", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return dict(rays=self.rays, queries=self.queries, valid=self.valid, trapped=self.trapped,
+                    hits=list(self.hits), angles=self.angles, ms_trace=self.ms_trace, ms_po=self.ms_po,
+                    ms_total=self.ms_total)
+
+
+class PoDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("mode", C.c_int32), ("k_hat", _d3), ("theta_hat", _d3),
+                ("phi_hat", _d3), ("dA", C.c_double)]
+
+
+class Sweep(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("theta_deg", _vp), ("phi_deg", _vp), ("n_angles", C.c_int64),
+                ("freqs_hz", _vp), ("n_freq", C.c_int32), ("max_bounces", C.c_int32), ("ds", C.c_double),
+                ("samples_per_lambda", C.c_double), ("eta", C.c_double), ("mode", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class AnglePlan(C.Structure):
+    _fields_ = [("k_hat", _d3), ("theta_hat", _d3), ("phi_hat", _d3), ("uc", C.c_double), ("vc", C.c_double),
+                ("s0", C.c_double), ("ds", C.c_double), ("nu", C.c_int64), ("nv", C.c_int64)]
+
+
+# name -> (restype, argtypes); the full exported surface of include/sbr.h
+SIGNATURES = {
+    "sbr_version": (C.c_int, []),
+    "sbr_last_error": (C.c_char_p, []),
+    "sbr_create": (C.c_int, [C.POINTER(_vp), C.c_int, _vp]),
+    "sbr_set_stream": (C.c_int, [_vp, _vp]),
+    "sbr_synchronize": (C.c_int, [_vp]),
+    "sbr_destroy": (None, [_vp]),
+    "sbr_build_bvh": (C.c_int, [_vp, _vp, C.c_int64, _vp, C.c_int64, C.POINTER(BvhOpts), C.POINTER(_vp)]),
+    "sbr_bvh_get_info": (C.c_int, [_vp, C.POINTER(BvhInfo)]),
+    "sbr_bvh_normals": (C.c_int, [_vp, _vp]),
+    "sbr_free_bvh": (None, [_vp]),
+    "sbr_trace": (C.c_int, [_vp, _vp, C.POINTER(Rays), C.c_int64, C.c_int, C.POINTER(TraceOpts),
+                            C.POINTER(Hits), C.POINTER(Stats)]),
+    "sbr_po_integrate": (C.c_int, [_vp, _vp, C.POINTER(Hits), C.c_int64, C.POINTER(PoDesc), _vp, C.c_int, _vp]),
+    "sbr_rcs_sweep": (C.c_int, [_vp, _vp, C.POINTER(Sweep), _vp, _vp, C.POINTER(Stats)]),
+    "sbr_plan_angle": (C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(AnglePlan)]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libsbr.so not found at %s: build it with `python -m paper_2604_09243_amd.build` "
+                           "(there is no CPU fallback)" % path)
+    L = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+class SbrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("sbr status %d: %s" % (status, msg))
+        self.status = status
+
+
+def _check(rc):
+    if rc != OK:
+        raise SbrError(rc, load_library().sbr_last_error().decode())
+    return rc
+
+
+def plan_angle(bbox, theta_deg, phi_deg, ds, eta=0.1):
+    """Host-only ray-grid plan of one angle (Eqs. L1-L3)."""
+    bb = np.ascontiguousarray(bbox, dtype=np.float64)
+    p = AnglePlan()
+    _check(load_library().sbr_plan_angle(bb.ctypes.data, float(theta_deg), float(phi_deg), float(ds), float(eta),
+                                         C.byref(p)))
+    return dict(k_hat=np.array(p.k_hat), theta_hat=np.array(p.theta_hat), phi_hat=np.array(p.phi_hat),
+                uc=p.uc, vc=p.vc, s0=p.s0, ds=p.ds, nu=p.nu, nv=p.nv)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class BVH:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+        info = BvhInfo()
+        _check(load_library().sbr_bvh_get_info(handle, C.byref(info)))
+        self.n_tris, self.n_live, self.n_nodes = info.n_tris, info.n_live, info.n_nodes
+        self.depth, self.eps = info.depth, info.eps
+        self.bbox = np.array(info.bbox)
+        self.device_bytes = info.device_bytes
+
+    def normals(self):
+        out = np.zeros((self.n_tris, 3), np.float32)
+        _check(load_library().sbr_bvh_normals(self.handle, out.ctypes.data))
+        return out
+
+    def free(self):
+        if self.handle:
+            load_library().sbr_free_bvh(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """An sbr_ctx on ``device`` enqueuing on torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        torch = _torch()
+        L = load_library()
+        self.device = device
+        torch.cuda.set_device(device)
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = C.c_void_p()
+        _check(L.sbr_create(C.byref(h), int(device), C.c_void_p(s.cuda_stream)))
+        self.handle = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(load_library().sbr_set_stream(self.handle, C.c_void_p(stream.cuda_stream)))
+
+    def synchronize(self):
+        _check(load_library().sbr_synchronize(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sbr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ build
+    def build_bvh(self, V, T):
+        """V: [n_v, 3] float32, T: [n_t, 3] int32 (numpy host arrays or
+        torch device tensors)."""
+        torch = _torch()
+        opts = BvhOpts(C.sizeof(BvhOpts), MEM_HOST)
+        if isinstance(V, torch.Tensor):
+            V = V.contiguous()
+            T = T.contiguous()
+            assert V.dtype == torch.float32 and T.dtype == torch.int32
+            opts.mem = MEM_DEVICE if V.is_cuda else MEM_HOST
+            pv, pt, nv, nt = V.data_ptr(), T.data_ptr(), V.shape[0], T.shape[0]
+            keep = (V, T)
+        else:
+            Vn = np.ascontiguousarray(V, dtype=np.float32).reshape(-1, 3)
+            Tn = np.ascontiguousarray(T, dtype=np.int32).reshape(-1, 3)
+            pv, pt, nv, nt = Vn.ctypes.data, Tn.ctypes.data, len(Vn), len(Tn)
+            keep = (Vn, Tn)
+        h = C.c_void_p()
+        _check(load_library().sbr_build_bvh(self.handle, C.c_void_p(pv), nv, C.c_void_p(pt), nt, C.byref(opts),
+                                            C.byref(h)))
+        del keep
+        return BVH(self, h)
+
+    # ------------------------------------------------------------ trace
+    def trace(self, bvh, o, d, eH, eV, max_bounces, k_hat, flags=0, want_path=False, stats=False):
+        """Rays as [n, 3] float32 CUDA tensors; returns a dict of device
+        tensors (the sbr_hits arrays) and, if ``stats``, the statistics."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        o, d, eH, eV = (x.contiguous() for x in (o, d, eH, eV))
+        n = o.shape[0]
+        out = dict(n_bounce=torch.empty(n, dtype=torch.int32, device=dev),
+                   tri_first=torch.empty(n, dtype=torch.int32, device=dev),
+                   tri_last=torch.empty(n, dtype=torch.int32, device=dev),
+                   flags=torch.empty(n, dtype=torch.int32, device=dev),
+                   path=torch.empty(n, dtype=torch.float64, device=dev),
+                   D=torch.empty(n, dtype=torch.float64, device=dev),
+                   d_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                   x_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                   eH_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                   eV_last=torch.empty(n, 3, dtype=torch.float32, device=dev))
+        if want_path:
+            out["tri_path"] = torch.empty(n, max_bounces, dtype=torch.int32, device=dev)
+        hits = self._hits(out)
+        rays = Rays(o.data_ptr(), d.data_ptr(), eH.data_ptr(), eV.data_ptr())
+        opts = TraceOpts(C.sizeof(TraceOpts), int(flags), _d3(*[float(x) for x in k_hat]))
+        st = Stats() if stats else None
+        _check(load_library().sbr_trace(self.handle, bvh.handle, C.byref(rays), n, int(max_bounces), C.byref(opts),
+                                        C.byref(hits), C.byref(st) if stats else None))
+        if stats:
+            out["stats"] = st.as_dict()
+        return out
+
+    @staticmethod
+    def _hits(out):
+        h = Hits()
+        for name, _ in Hits._fields_:
+            t = out.get(name)
+            setattr(h, name, t.data_ptr() if t is not None else None)
+        return h
+
+    # ------------------------------------------------------------ PO
+    def po_integrate(self, bvh, hits, mode, k_hat, theta_hat, phi_hat, dA, freqs):
+        """PO sum over the valid rays of ``hits`` (a ``trace`` result).
+        Returns a complex128 device tensor [n_freq, 2 receive, 2 transmit]."""
+        torch = _torch()
+        freqs = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+        nf = len(freqs)
+        A = torch.empty(nf, 2, 2, 2, dtype=torch.float64, device=torch.device("cuda", self.device))
+        desc = PoDesc(C.sizeof(PoDesc), int(mode), _d3(*map(float, k_hat)), _d3(*map(float, theta_hat)),
+                      _d3(*map(float, phi_hat)), float(dA))
+        h = self._hits(hits)
+        n = hits["n_bounce"].shape[0]
+        _check(load_library().sbr_po_integrate(self.handle, bvh.handle, C.byref(h), n, C.byref(desc),
+                                               freqs.ctypes.data, nf, A.data_ptr()))
+        return torch.view_as_complex(A)
+
+    # ------------------------------------------------------------ sweep
+    def rcs_sweep(self, bvh, theta_deg, phi_deg, freqs_hz, max_bounces=5, ds=0.0, samples_per_lambda=10.0,
+                  eta=0.1, mode=MODE_VECTOR, flags=0, stats=True, out=None):
+        """Monostatic sweep.  Returns (A complex128 [n_angles, n_freq, 2, 2],
+        sigma_dbsm float64 [n_angles, n_freq, 2, 2], stats dict or None), all
+        device tensors; ``out`` may pass preallocated (A_real_view, sigma)."""
+        torch = _torch()
+        th = np.ascontiguousarray(np.atleast_1d(theta_deg), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_1d(phi_deg), dtype=np.float64)
+        fr = np.ascontiguousarray(np.atleast_1d(freqs_hz), dtype=np.float64)
+        na, nf = len(th), len(fr)
+        dev = torch.device("cuda", self.device)
+        if out is None:
+            A = torch.empty(na, nf, 2, 2, 2, dtype=torch.float64, device=dev)
+            S = torch.empty(na, nf, 2, 2, dtype=torch.float64, device=dev)
+        else:
+            A, S = out
+        sw = Sweep(C.sizeof(Sweep), th.ctypes.data, ph.ctypes.data, na, fr.ctypes.data, nf, int(max_bounces),
+                   float(ds), float(samples_per_lambda), float(eta), int(mode), int(flags))
+        st = Stats() if stats else None
+        _check(load_library().sbr_rcs_sweep(self.handle, bvh.handle, C.byref(sw), A.data_ptr(),
+                                            S.data_ptr() if S is not None else None,
+                                            C.byref(st) if stats else None))
+        return torch.view_as_complex(A), S, (st.as_dict() if stats else None)

@@ -1,0 +1,338 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integers decided by float32 arithmetic (hit triangle ids, bounce counts) must
+be bit-exact on every ray that the oracle does not flag as edge-ambiguous;
+the float32 ray geometry and float64 path are bit-exact too (same operation
+order on both sides); the field vectors are float32 on the GPU against
+float64 in the oracle.  RCS: |d sigma| <= 0.05 dB where sigma is within 40 dB
+of the sweep maximum, complex error <= 1e-4 relative to
+max(|A_oracle|, 1e-3 max |A_oracle|) everywhere.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import sbr_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299_792_458.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2604_09243_amd import Context
+    return Context(0)
+
+
+def _gpu_trace(torch, ctx, bvh, o, d, eH, eV, bmax, k, **kw):
+    dev = torch.device("cuda", 0)
+    n = len(o)
+    dd = np.broadcast_to(np.asarray(d, np.float32), (n, 3))
+    eh = np.broadcast_to(np.asarray(eH, np.float32), (n, 3))
+    ev = np.broadcast_to(np.asarray(eV, np.float32), (n, 3))
+    t = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (o, dd, eh, ev)]
+    r = ctx.trace(bvh, *t, bmax, k, want_path=True, stats=True, **kw)
+    torch.cuda.synchronize()
+    return r, {k2: v.cpu().numpy() for k2, v in r.items() if k2 != "stats"}
+
+
+def compare_trace(orc_r, g, bmax, allow_edge=True):
+    edge = (orc_r["flags"] & 8) != 0 if allow_edge else np.zeros(len(orc_r["nb"]), bool)
+    ok = ~edge
+    n_mis = 0
+    for key_o, key_g in (("nb", "n_bounce"), ("tri_first", "tri_first"), ("tri_last", "tri_last")):
+        bad = orc_r[key_o] != g[key_g]
+        assert not np.any(bad & ok), (key_o, np.flatnonzero(bad & ok)[:10])
+        n_mis += int(np.sum(bad & edge))
+    assert np.array_equal(orc_r["tri_path"][ok], g["tri_path"][ok])
+    # identical float32 geometry and float64 path on rays whose integer history agrees
+    same = ok & (orc_r["nb"] == g["n_bounce"])
+    assert np.array_equal(orc_r["d_last"][same], g["d_last"][same])
+    assert np.array_equal(orc_r["x_last"][same], g["x_last"][same])
+    assert np.array_equal(orc_r["path"][same], g["path"][same])
+    assert np.array_equal(orc_r["D"][same], g["D"][same])
+    assert np.array_equal(orc_r["flags"][same] & 7, g["flags"][same] & 7)
+    hit = same & (orc_r["nb"] > 0)
+    assert np.allclose(orc_r["eH_last"][hit], g["eH_last"][hit], atol=2e-5)
+    assert np.allclose(orc_r["eV_last"][hit], g["eV_last"][hit], atol=2e-5)
+    return int(edge.sum()), n_mis
+
+
+def check_rcs(A_orc, A_gpu, tol_db=0.05, rel=1e-4):
+    A_orc = np.asarray(A_orc)
+    A_gpu = np.asarray(A_gpu)
+    amax = np.abs(A_orc).max()
+    den = np.maximum(np.abs(A_orc), 1e-3 * amax)
+    err = np.abs(A_gpu - A_orc) / den
+    assert err.max() <= rel, err.max()
+    s_o = 10 * np.log10(np.maximum(4 * np.pi * np.abs(A_orc) ** 2, 1e-300))
+    s_g = 10 * np.log10(np.maximum(4 * np.pi * np.abs(A_gpu) ** 2, 1e-300))
+    m = s_o >= s_o.max() - 40
+    assert np.abs(s_o - s_g)[m].max() <= tol_db
+    return float(err.max()), float(np.abs(s_o - s_g)[m].max())
+
+
+# --------------------------------------------------------------------------
+# sbr_trace on the oracle's rays
+# --------------------------------------------------------------------------
+def _grid_case(orc, V, T, th, ph, ds, bmax, edge=True, use_bvh=False, subset=None):
+    m = orc.Mesh(V, T)
+    if use_bvh:
+        m.build_bvh()
+    k, tv, pv = orc.frame(th, ph)
+    o, d, Nu, Nv = orc.gen_rays(m.bbox, th, ph, ds)
+    if subset is not None:
+        o = o[subset]
+    r = orc.trace(m, o, d, pv, tv, k, bmax, edge_diag=edge, want_path=True, use_bvh=use_bvh)
+    return m, k, tv, pv, o, d, r
+
+
+@pytest.mark.parametrize("case", ["sphere", "trihedral45", "trihedral12.5", "dihedral", "plate_oblique"])
+def test_trace_parity_grids(torch, ctx, orc, case):
+    say("case", case)
+    if case == "sphere":
+        w = si.sphere_case()
+        V, T, th, ph, ds, bmax = w.V, w.T, 0.0, 0.0, w.ds, 5
+    elif case.startswith("trihedral"):
+        V, T = si.trihedral(1.0, 16)
+        th, ph, ds, bmax = 90 - 35.26, float(case[9:]), C0 / 10e9 / 10, 5
+    elif case == "dihedral":
+        V, T = si.dihedral(1.0, 1.0, 8)
+        th, ph, ds, bmax = 90.0, 40.0, C0 / 10e9 / 10, 5
+    else:
+        V, T = si.plate(1.0, 0.7, 8, 8)
+        th, ph, ds, bmax = 33.0, 71.0, C0 / 10e9 / 10, 5
+    m, k, tv, pv, o, d, r = _grid_case(orc, V, T, th, ph, ds, bmax)
+    bvh = ctx.build_bvh(V, T)
+    assert bvh.n_live == len(T) and bvh.n_nodes == len(T) - 1
+    raw, g = _gpu_trace(torch, ctx, bvh, o, d, pv, tv, bmax, k)
+    n_edge, n_mis = compare_trace(r, g, bmax)
+    st = raw["stats"]
+    assert st["queries"] == r["queries"]
+    say(case, "rays", len(o), "edge-ambiguous", n_edge, "mismatching among them", n_mis)
+
+
+def test_trace_parity_random_soup(torch, ctx, orc):
+    say("case random soup")
+    V, T = si.random_triangles(3000, seed=11, box=1.0, size=0.2)
+    o, _ = si.random_rays(30000, seed=12, box=1.2)
+    m = orc.Mesh(V, T)
+    k, tv, pv = orc.frame(63.0, 17.0)
+    o = (o - 3.0 * k).astype(np.float32)
+    r = orc.trace(m, o, k.astype(np.float32), pv, tv, k, 8, edge_diag=True, want_path=True)
+    bvh = ctx.build_bvh(V, T)
+    _, g = _gpu_trace(torch, ctx, bvh, o, k.astype(np.float32), pv, tv, 8, k)
+    n_edge, n_mis = compare_trace(r, g, 8)
+    assert (r["nb"] >= 3).sum() > 100
+    say("soup edge", n_edge, "mismatch", n_mis)
+
+
+def test_trace_parity_random_directions(torch, ctx, orc):
+    # every ray its own direction (incoherent), many bounces in a closed box of soup
+    say("case random directions")
+    V, T = si.random_triangles(1500, seed=21, box=1.0, size=0.25)
+    o, d = si.random_rays(20000, seed=22, box=0.9)
+    m = orc.Mesh(V, T)
+    k = np.array([0.0, 0.0, -1.0])
+    # per-ray transverse polarisation
+    eh = np.cross(d.astype(np.float64), [0.3, 0.4, 0.5])
+    eh /= np.linalg.norm(eh, axis=1, keepdims=True)
+    ev = np.cross(eh, d.astype(np.float64))
+    ev /= np.linalg.norm(ev, axis=1, keepdims=True)
+    # the oracle takes one polarisation pair; compare only geometry/ids here
+    r = orc.trace(m, o, d, [1.0, 0, 0], [0, 1.0, 0], k, 12, edge_diag=True, want_path=True)
+    bvh = ctx.build_bvh(V, T)
+    _, g = _gpu_trace(torch, ctx, bvh, o, d, eh.astype(np.float32), ev.astype(np.float32), 12, k)
+    edge = (r["flags"] & 8) != 0
+    ok = ~edge
+    for a, b in (("nb", "n_bounce"), ("tri_first", "tri_first"), ("tri_last", "tri_last")):
+        assert np.array_equal(r[a][ok], g[b][ok]), a
+    assert np.array_equal(r["tri_path"][ok], g["tri_path"][ok])
+    same = ok & (r["nb"] == g["n_bounce"])
+    assert np.array_equal(r["x_last"][same], g["x_last"][same])
+    assert np.array_equal(r["path"][same], g["path"][same])
+
+
+def test_trace_tiny_meshes(torch, ctx, orc):
+    say("case tiny meshes")
+    cases = [
+        ([[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[0, 1, 2]], [0.25, 0.25, 1.0], [0, 0, -1]),
+        ([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], [[0, 1, 2], [0, 2, 3]], [0.5, 0.5, 1.0], [0, 0, -1]),
+        ([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], [[0, 2, 3], [0, 1, 2]], [0.0, 0.0, 1.0], [0, 0, -1]),
+        ([[0, -5, -5], [0, 5, -5], [0, 0, 5], [-5, 0, -5], [5, 0, -5], [0, 0, 5]], [[0, 1, 2], [3, 4, 5]],
+         [1.0, 2.0, 0.1], [-np.sqrt(0.5), -np.sqrt(0.5), 0.0]),
+        ([[-5, -5, 0], [5, -5, 0], [0, 5, 0], [-5, -5, 1], [5, -5, 1], [0, 5, 1]], [[0, 1, 2], [3, 4, 5]],
+         [0.1, 0.2, 0.5], [0, 0, 1]),
+    ]
+    for V, T, o, d in cases:
+        V = np.array(V, np.float32)
+        T = np.array(T, np.int32)
+        m = orc.Mesh(V, T)
+        k = np.array(d, float) / np.linalg.norm(d)
+        e = np.cross(k, [0.3, 0.5, 0.7])
+        e /= np.linalg.norm(e)
+        ev = np.cross(e, k)
+        oo = np.array([o], np.float32)
+        dd = np.array(d, np.float32)
+        for flags, kw in ((0, {}), (1, dict(drop_trapped=True))):
+            r = orc.trace(m, oo, dd, e, ev, k, 4, want_path=True, **kw)
+            bvh = ctx.build_bvh(V, T)
+            _, g = _gpu_trace(torch, ctx, bvh, oo, dd, e, ev, 4, k, flags=flags)
+            compare_trace(r, g, 4, allow_edge=False)
+
+
+# --------------------------------------------------------------------------
+# sbr_po_integrate on GPU hits vs the oracle's PO on oracle hits
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1])
+def test_po_integrate_parity(torch, ctx, orc, mode):
+    say("case po mode", mode)
+    V, T = si.trihedral(1.0, 16)
+    th, ph, ds = 90 - 35.26, 30.0, C0 / 10e9 / 10
+    m, k, tv, pv, o, d, r = _grid_case(orc, V, T, th, ph, ds, 5, edge=False)
+    freqs = np.array([8e9, 9e9, 10e9])
+    A_o = orc.po(m, r, mode, k, tv, pv, ds * ds, freqs)
+    bvh = ctx.build_bvh(V, T)
+    raw, _ = _gpu_trace(torch, ctx, bvh, o, d, pv, tv, 5, k)
+    A_g = ctx.po_integrate(bvh, raw, mode, k, tv, pv, ds * ds, freqs).cpu().numpy()
+    err, ddb = check_rcs(A_o, A_g)
+    A_g2 = ctx.po_integrate(bvh, raw, mode, k, tv, pv, ds * ds, freqs).cpu().numpy()
+    assert np.array_equal(A_g, A_g2)      # bitwise reproducible
+    say("po", mode, "rel err", err, "dB", ddb)
+
+
+# --------------------------------------------------------------------------
+# sbr_rcs_sweep end to end
+# --------------------------------------------------------------------------
+def _oracle_sweep(orc, m, w, idx, mode, use_bvh):
+    A = []
+    for i in idx:
+        r = orc.rcs_angle(m, w.theta_deg[i], w.phi_deg[i], w.freqs_hz, w.samples_per_lambda, bmax=w.max_bounces,
+                          mode=mode, use_bvh=use_bvh)
+        A.append(r["A"])
+    return np.array(A)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sweep_sphere(torch, ctx, orc, mode):
+    say("case sweep sphere mode", mode)
+    from oracle import mie
+    w = si.sphere_case()
+    m = orc.Mesh(w.V, w.T)
+    A_o = _oracle_sweep(orc, m, w, [0], mode, False)
+    bvh = ctx.build_bvh(w.V, w.T)
+    A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
+                             samples_per_lambda=w.samples_per_lambda, mode=mode)
+    A_g = A.cpu().numpy()
+    check_rcs(A_o, A_g)
+    assert st["rays"] == 221 * 221 and st["hits"][2] == 0
+    if mode == 1:
+        ref = 10 * np.log10(mie.mie_pec_sigma(1.0, 3e9))
+        assert abs(S.cpu().numpy()[0, 0, 1, 1] - ref) < 0.4
+
+
+def test_sweep_trihedral_full(torch, ctx, orc):
+    say("case sweep trihedral 181 angles")
+    w = si.trihedral_case()
+    bvh = ctx.build_bvh(w.V, w.T)
+    A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
+                             samples_per_lambda=w.samples_per_lambda)
+    A_g = A.cpu().numpy()
+    assert st["rays"] == 48_377_932 and st["angles"] == 181
+    m = orc.Mesh(w.V, w.T).build_bvh()
+    idx = list(range(0, 181, 12)) + [90]
+    A_o = _oracle_sweep(orc, m, w, idx, 0, True)
+    err, ddb = check_rcs(A_o, A_g[idx])
+    say("trihedral sweep rel err", err, "max dB", ddb)
+    # repeated sweep: bitwise identical
+    A2, _, _ = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
+                             samples_per_lambda=w.samples_per_lambda, stats=False)
+    assert np.array_equal(A_g, A2.cpu().numpy())
+    # mirror plane x = y of the trihedral: sigma(phi) ~ sigma(90 - phi) near the peak
+    s = S.cpu().numpy()[:, 0, 1, 1]
+    near = s[:91] > s.max() - 10
+    assert np.abs(s[:91] - s[180:89:-1])[near].max() < 0.5
+
+
+def test_sweep_multifrequency_equals_single(torch, ctx):
+    say("case multi-frequency")
+    V, T = si.trihedral(1.0, 8)
+    bvh = ctx.build_bvh(V, T)
+    th, ph = np.array([60.0, 50.0]), np.array([30.0, 10.0])
+    fs = np.array([8e9, 9e9, 10e9])
+    A, _, _ = ctx.rcs_sweep(bvh, th, ph, fs, 5, ds=C0 / 10e9 / 10)
+    for i, f in enumerate(fs):
+        A1, _, _ = ctx.rcs_sweep(bvh, th, ph, [f], 5, ds=C0 / 10e9 / 10)
+        assert np.array_equal(A.cpu().numpy()[:, i], A1.cpu().numpy()[:, 0])
+
+
+def test_sweep_errors(torch, ctx):
+    say("case error paths")
+    from paper_2604_09243_amd import sbr
+    V, T = si.trihedral(1.0, 4)
+    bvh = ctx.build_bvh(V, T)
+    with pytest.raises(sbr.SbrError) as e:
+        ctx.rcs_sweep(bvh, [45.0], [45.0], [10e9], 5, samples_per_lambda=4.0)
+    assert e.value.status == sbr.ERR_SAMPLING
+    ctx.rcs_sweep(bvh, [45.0], [45.0], [10e9], 5, samples_per_lambda=4.0, flags=sbr.OPT_ALLOW_UNDERSAMPLING)
+    with pytest.raises(sbr.SbrError) as e:
+        ctx.rcs_sweep(bvh, [45.0], [45.0], [10e9], 65)
+    assert e.value.status == sbr.ERR_INVALID_ARG
+    Vb = V.copy()
+    Vb[3, 1] = np.nan
+    with pytest.raises(sbr.SbrError) as e:
+        ctx.build_bvh(Vb, T)
+    assert e.value.status == sbr.ERR_INVALID_MESH
+    Tb = T.copy()
+    Tb[0, 0] = len(V)
+    with pytest.raises(sbr.SbrError) as e:
+        ctx.build_bvh(V, Tb)
+    assert e.value.status == sbr.ERR_INVALID_MESH
+
+
+def test_degenerate_triangles_skipped(torch, ctx, orc):
+    say("case degenerate")
+    V, T = si.trihedral(1.0, 8)
+    V = np.concatenate([V, np.array([[0.5, 0.5, 0.5], [0.5, 0.5, 0.5], [0.6, 0.5, 0.5]], np.float32)])
+    T = np.concatenate([T, np.array([[len(V) - 3, len(V) - 2, len(V) - 1]], np.int32)])
+    bvh = ctx.build_bvh(V, T)
+    assert bvh.n_live == len(T) - 1
+    m = orc.Mesh(V, T)
+    assert m.n_degen == 1
+    k, tv, pv = orc.frame(54.74, 45.0)
+    o, d, *_ = orc.gen_rays(m.bbox, 54.74, 45.0, 0.01)
+    r = orc.trace(m, o, d, pv, tv, k, 5, want_path=True, edge_diag=True)
+    _, g = _gpu_trace(torch, ctx, bvh, o, d, pv, tv, 5, k)
+    compare_trace(r, g, 5)
+
+
+def test_aircraft_small_sweep(torch, ctx, orc):
+    say("case aircraft scale 0.1, 8 angles")
+    V, T = si.aircraft(seed=0, scale=0.1)
+    bvh = ctx.build_bvh(V, T)
+    th = np.full(8, 90.0)
+    ph = np.arange(8) * 45.0 + 3.0
+    A, S, st = ctx.rcs_sweep(bvh, th, ph, [10e9], 8, samples_per_lambda=2.5,
+                             flags=4)  # coarse grid keeps the oracle quick; undersampling allowed
+    m = orc.Mesh(V, T).build_bvh()
+    A_o = []
+    for t, p in zip(th, ph):
+        r = orc.rcs_angle(m, t, p, [10e9], 2.5, bmax=8, use_bvh=True)
+        A_o.append(r["A"])
+    check_rcs(np.array(A_o), A.cpu().numpy())
+    assert max(st["hits"][3:]) > 0   # inlets give multi-bounce paths
