@@ -76,6 +76,8 @@ enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
 #define SBR_OPT_PAPER_PATH 2          /* path = sum of t only (no offset correction) */
 #define SBR_OPT_ALLOW_UNDERSAMPLING 4 /* accept ray spacing coarser than lambda/5 */
 #define SBR_OPT_SYNC 8                /* synchronise the stream before returning */
+#define SBR_OPT_WAVEFRONT 16          /* one launch per bounce with a compacted ray queue between
+                                         launches (default: one streaming launch for all bounces) */
 
 /* ------------------------------------------------------------------------ */
 /* Library and context                                                       */
@@ -189,6 +191,9 @@ typedef struct {
     double ms_trace;   /* GPU time of ray generation + all bounces */
     double ms_po;      /* GPU time of the PO sum + finalize */
     double ms_total;   /* wall time of the call */
+    double ms_bounce[SBR_MAX_BOUNCES + 1];       /* GPU time of the bounce-b launches (1-based;
+                                                    SBR_OPT_WAVEFRONT only) */
+    int64_t queries_bounce[SBR_MAX_BOUNCES + 1]; /* queries made by the bounce-b launches */
 } sbr_stats;
 
 /* Traces n_rays rays (1 <= n_rays < 2^31) for up to max_bounces (1..64)

@@ -1,0 +1,62 @@
+"""Reference traversal work for the roofline of the trace kernels.
+
+TEST INFRASTRUCTURE.  The algorithmic work of a closest-hit query is priced
+on the oracle's own binned-SAH BVH (Algorithm 1 with the SAH cost, 4
+triangles per leaf, 16 bins), not on the tree the GPU builds, so a worse GPU
+tree cannot inflate the achieved rate.  For each bounce b the script runs the
+oracle's fast mode with B_max = b and differences the cumulative counters,
+giving per-bounce queries, box tests, triangle tests and hits on a fixed
+sample of the trihedral sweep (every 10th angle of the 181).
+
+    python -m oracle.visit_counts  ->  prints the JSON written to
+    oracle/visit_counts_trihedral.json
+"""
+import json
+import os
+
+import numpy as np
+
+import sbr_inputs as si
+from . import oracle as O
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "visit_counts_trihedral.json")
+
+
+def per_bounce_counts(w, angle_idx, bmax):
+    m = O.Mesh(w.V, w.T).build_bvh("sah", 4, 16)
+    cum = []
+    rays = 0
+    for b in range(1, bmax + 1):
+        q = box = tri = hits = 0
+        rays = 0
+        for i in angle_idx:
+            r = O.rcs_angle(m, w.theta_deg[i], w.phi_deg[i], w.freqs_hz, w.samples_per_lambda, bmax=b,
+                            use_bvh=True)
+            q += r["queries"]
+            box += r["box_tests"]
+            tri += r["tri_tests"]
+            hits += int(r["nb"].sum())
+            rays += len(r["nb"])
+        cum.append((q, box, tri, hits))
+    out = []
+    prev = (0, 0, 0, 0)
+    for b, c in enumerate(cum, start=1):
+        d = [c[i] - prev[i] for i in range(4)]
+        out.append(dict(bounce=b, queries=d[0], box_tests=d[1], tri_tests=d[2], hits=d[3],
+                        box_per_query=d[1] / max(d[0], 1), tri_per_query=d[2] / max(d[0], 1),
+                        hits_per_query=d[3] / max(d[0], 1)))
+        prev = c
+    return dict(workload=w.name, angles_sampled=len(angle_idx), rays=rays, tree="binned SAH, leaf<=4, 16 bins",
+                per_bounce=out)
+
+
+def main():
+    w = si.trihedral_case()
+    res = per_bounce_counts(w, list(range(0, w.n_angles, 10)), w.max_bounces)
+    with open(OUT, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+if __name__ == "__main__":
+    main()

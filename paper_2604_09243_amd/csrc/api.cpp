@@ -79,6 +79,7 @@ enum Slot {
     W_KF = 21,
     W_PARTIAL = 22,
     W_SPILL = 23,
+    W_NREC = 24,
 };
 
 static int get_queue(Workspace *ws, int first, size_t cap, RayQueue &q)
@@ -112,24 +113,51 @@ static int get_records(Workspace *ws, size_t cap, Records &r)
     return SBR_OK;
 }
 
-// Counter block: stat u64[kStatU64], q_cnt u32[kQcnt], rec_cnt u32[n_angles].
+// Counter block (layout in sbr_internal.hpp), followed by one extra line
+// used as the record counter of sbr_po_integrate's packing step.
 struct Counters {
-    unsigned long long *stat;
-    uint32_t *q_cnt;
-    uint32_t *rec_cnt;
+    CounterPtrs p;
+    uint32_t *pack_cnt;
+    void *base;
     size_t bytes;
 };
 
-static int get_counters(Workspace *ws, int n_angles, Counters &c)
+static int get_counters(Workspace *ws, Counters &c)
 {
-    const size_t bytes = 8 * kStatU64 + 4 * kQcnt + 4 * static_cast<size_t>(n_angles);
+    const size_t bytes = kCounterBytes + 4 * kLineU32;
     void *p;
     int rc = ws->get(W_COUNTERS, bytes, &p);
     if (rc) return rc;
-    c.stat = static_cast<unsigned long long *>(p);
-    c.q_cnt = reinterpret_cast<uint32_t *>(c.stat + kStatU64);
-    c.rec_cnt = c.q_cnt + kQcnt;
+    char *b = static_cast<char *>(p);
+    c.p.stat = reinterpret_cast<unsigned long long *>(b);
+    c.p.q_cnt = reinterpret_cast<uint32_t *>(b + kStatBytes);
+    c.p.claim = c.p.q_cnt + static_cast<size_t>(kLineU32) * kQcnt;
+    c.pack_cnt = reinterpret_cast<uint32_t *>(b + kCounterBytes);
+    c.base = p;
     c.bytes = bytes;
+    return SBR_OK;
+}
+
+static int schedule_of(uint32_t flags) { return (flags & SBR_OPT_WAVEFRONT) ? kScheduleWavefront : kScheduleStream; }
+
+// Launches every bounce of one trace: one streaming launch, or one launch
+// per bounce with the two queues swapped in between.  ev (nullable) receives
+// an event after each launch (ev[0] must already be recorded).
+static int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector<hipEvent_t> *ev)
+{
+    int rc;
+    if (a.schedule == kScheduleStream) {
+        if ((rc = launch_trace(s, a, 1))) return rc;
+        if (ev) SBR_HIP(hipEventRecord((*ev)[1], s));
+        return SBR_OK;
+    }
+    a.q_in = qb;
+    a.q_out = qa;
+    for (int b = 1; b <= a.bmax; ++b) {
+        if (b > 1) std::swap(a.q_in, a.q_out);
+        if ((rc = launch_trace(s, a, b))) return rc;
+        if (ev) SBR_HIP(hipEventRecord((*ev)[b], s));
+    }
     return SBR_OK;
 }
 
@@ -145,11 +173,15 @@ static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int32_t **spill)
     return SBR_OK;
 }
 
-static void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax)
+// rays: rays launched at bounce 1 of this chunk / call
+static void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped)
 {
     st->queries += static_cast<int64_t>(hstat[0]);
     st->trapped += static_cast<int64_t>(hstat[1]);
     for (int b = 1; b <= bmax && b <= SBR_MAX_BOUNCES; ++b) st->hits[b] += static_cast<int64_t>(hstat[8 + b]);
+    st->queries_bounce[1] += rays;
+    for (int b = 2; b <= bmax; ++b) st->queries_bounce[b] += static_cast<int64_t>(hstat[8 + b - 1]);
+    if (drop_trapped) st->queries_bounce[bmax] += static_cast<int64_t>(hstat[8 + bmax]);
     // a ray is valid when it hit at bounce 1 and was not dropped as trapped
     st->valid += static_cast<int64_t>(hstat[8 + 1]) - static_cast<int64_t>(hstat[1]);
 }
@@ -317,55 +349,52 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
     Workspace *ws = ctx->ws;
     int rc;
     Counters cn;
-    RayQueue qa, qb;
+    RayQueue qa{}, qb{};
     int32_t *spill;
-    if ((rc = get_counters(ws, 1, cn)) || (rc = get_queue(ws, W_QA, n_rays, qa)) ||
-        (rc = get_queue(ws, W_QB, n_rays, qb)) || (rc = get_spill(ctx, bvh, &spill)))
+    const int sched = schedule_of(flags);
+    if ((rc = get_counters(ws, cn)) || (rc = get_spill(ctx, bvh, &spill))) return rc;
+    if (sched == kScheduleWavefront &&
+        ((rc = get_queue(ws, W_QA, n_rays, qa)) || (rc = get_queue(ws, W_QB, n_rays, qb))))
         return rc;
-    SBR_HIP(hipMemsetAsync(cn.stat, 0, cn.bytes, s));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: the mesh has no non-degenerate triangle");
+    SBR_HIP(hipMemsetAsync(cn.base, 0, cn.bytes, s));
     const bool want_stats = stats != nullptr;
+    std::vector<hipEvent_t> ev;
     if (want_stats) {
-        SBR_HIP(hipEventCreate(&e0));
-        SBR_HIP(hipEventCreate(&e1));
-        SBR_HIP(hipEventRecord(e0, s));
+        ev.resize(max_bounces + 1);
+        for (auto &e : ev) SBR_HIP(hipEventCreate(&e));
+        SBR_HIP(hipEventRecord(ev[0], s));
     }
     TraceArgs a{};
     a.bvh = bvh;
     a.bmax = max_bounces;
     a.flags = flags;
+    a.schedule = sched;
     a.rays = rays;
     a.n_rays = n_rays;
     a.hits = out;
     for (int i = 0; i < 3; ++i) a.k_hat[i] = k[i];
-    a.rec_cnt = cn.rec_cnt;
-    a.q_cnt = cn.q_cnt;
-    a.stat = cn.stat;
+    a.ctrs = cn.p;
     a.spill = spill;
-    if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: the mesh has no non-degenerate triangle");
-    a.q_in = qb;
-    a.q_out = qa;
-    if ((rc = launch_trace_rays(s, a))) return rc;
-    for (int b = 2; b <= max_bounces; ++b) {
-        std::swap(a.q_in, a.q_out);
-        if ((rc = launch_trace_queue(s, a, b, true))) return rc;
-    }
+    if ((rc = run_trace(s, a, qa, qb, want_stats ? &ev : nullptr))) return rc;
     if (want_stats || (flags & SBR_OPT_SYNC)) {
         unsigned long long hstat[kStatU64];
-        SBR_HIP(hipMemcpyAsync(hstat, cn.stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
-        if (want_stats) SBR_HIP(hipEventRecord(e1, s));
+        SBR_HIP(hipMemcpyAsync(hstat, cn.p.stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
         SBR_HIP(hipStreamSynchronize(s));
         if (want_stats) {
             std::memset(stats, 0, sizeof(*stats));
             stats->rays = n_rays;
-            fill_stats(stats, hstat, max_bounces);
-            float ms = 0;
-            SBR_HIP(hipEventElapsedTime(&ms, e0, e1));
-            stats->ms_trace = ms;
+            fill_stats(stats, hstat, max_bounces, n_rays, (flags & SBR_OPT_DROP_TRAPPED) != 0);
+            const int nl = sched == kScheduleStream ? 1 : max_bounces;
+            for (int b = 1; b <= nl; ++b) {
+                float ms = 0;
+                SBR_HIP(hipEventElapsedTime(&ms, ev[b - 1], ev[b]));
+                if (sched == kScheduleWavefront) stats->ms_bounce[b] = ms;
+                stats->ms_trace += ms;
+            }
             stats->ms_total =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
+            for (auto &e : ev) (void)hipEventDestroy(e);
         }
     }
     return SBR_OK;
@@ -413,7 +442,7 @@ extern "C" int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits
     void *pb, *pkf, *prb, *ppart, *ph;
     const int chunks = static_cast<int>((n_rays + kPoRecsPerBlock - 1) / kPoRecsPerBlock);
     const size_t host_bytes = 9 * 8 + 8 + 8 * static_cast<size_t>(n_freq);
-    if ((rc = get_counters(ws, 1, cn)) || (rc = get_records(ws, n_rays, rec)) || (rc = ws->get(W_BASIS, 72, &pb)) ||
+    if ((rc = get_counters(ws, cn)) || (rc = get_records(ws, n_rays, rec)) || (rc = ws->get(W_BASIS, 72, &pb)) ||
         (rc = ws->get(W_KF, 8 * n_freq, &pkf)) || (rc = ws->get(W_RECBASE, 8, &prb)) ||
         (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(chunks) * n_freq, &ppart)) ||
         (rc = ws->get_pinned(host_bytes, &ph)))
@@ -427,12 +456,13 @@ extern "C" int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits
     SBR_HIP(hipMemcpyAsync(pb, hb, 72, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(prb, hb + 9, 8, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(pkf, hb + 10, 8 * n_freq, hipMemcpyHostToDevice, s));
-    SBR_HIP(hipMemsetAsync(cn.stat, 0, cn.bytes, s));
-    if ((rc = launch_pack_hits(s, hits, n_rays, rec, cn.rec_cnt))) return rc;
+    SBR_HIP(hipMemsetAsync(cn.base, 0, cn.bytes, s));
+    if ((rc = launch_pack_hits(s, hits, n_rays, rec, cn.pack_cnt))) return rc;
     PoArgs pa{};
     pa.bvh = bvh;
     pa.rec = rec;
-    pa.rec_cnt = cn.rec_cnt;
+    pa.rec_cnt = cn.pack_cnt;
+    pa.cnt_stride = 1;
     pa.rec_base = static_cast<const int64_t *>(prb);
     pa.n_angles = 1;
     pa.chunks = chunks;
@@ -560,24 +590,28 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
 
     // device buffers
     Counters cn;
-    RayQueue qa, qb;
+    RayQueue qa{}, qb{};
     Records rec;
     int32_t *spill;
-    void *dplans, *dtile, *drecb, *dbasis, *dkf, *dpart, *hpin;
+    void *dplans, *dtile, *drecb, *dnrec, *dbasis, *dkf, *dpart, *hpin;
+    const int sched = schedule_of(sw->flags);
     const size_t tile_words = static_cast<size_t>(na + n_chunks);
-    if ((rc = get_counters(ws, static_cast<int>(max_chunk_angles), cn)) ||
-        (rc = get_queue(ws, W_QA, max_chunk_rays, qa)) || (rc = get_queue(ws, W_QB, max_chunk_rays, qb)) ||
-        (rc = get_records(ws, max_chunk_rays, rec)) || (rc = get_spill(ctx, bvh, &spill)) ||
-        (rc = ws->get(W_PLANS, sizeof(AnglePlan) * na, &dplans)) || (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) ||
-        (rc = ws->get(W_RECBASE, 8 * na, &drecb)) || (rc = ws->get(W_BASIS, 72 * na, &dbasis)) ||
+    if ((rc = get_counters(ws, cn)) || (rc = get_records(ws, max_chunk_rays, rec)) ||
+        (rc = get_spill(ctx, bvh, &spill)) || (rc = ws->get(W_PLANS, sizeof(AnglePlan) * na, &dplans)) ||
+        (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) || (rc = ws->get(W_RECBASE, 8 * na, &drecb)) ||
+        (rc = ws->get(W_NREC, 4 * na, &dnrec)) || (rc = ws->get(W_BASIS, 72 * na, &dbasis)) ||
         (rc = ws->get(W_KF, 8 * nf, &dkf)) ||
         (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(po_chunks) * nf * max_chunk_angles, &dpart)))
         return rc;
-    // host staging (pinned): plans | tile bases | rec bases | basis | kf
+    if (sched == kScheduleWavefront &&
+        ((rc = get_queue(ws, W_QA, max_chunk_rays, qa)) || (rc = get_queue(ws, W_QB, max_chunk_rays, qb))))
+        return rc;
+    // host staging (pinned): plans | tile bases | record bases | records per angle | basis | kf
     const size_t off_plans = 0;
     const size_t off_tile = off_plans + sizeof(AnglePlan) * na;
     const size_t off_recb = off_tile + 8 * tile_words;
-    const size_t off_basis = off_recb + 8 * na;
+    const size_t off_nrec = off_recb + 8 * na;
+    const size_t off_basis = off_nrec + ((4 * na + 7) & ~size_t(7));
     const size_t off_kf = off_basis + 72 * na;
     const size_t host_bytes = off_kf + 8 * nf;
     if ((rc = ws->get_pinned(host_bytes, &hpin))) return rc;
@@ -587,6 +621,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     {
         int64_t *tb = reinterpret_cast<int64_t *>(hp + off_tile);
         int64_t *rb = reinterpret_cast<int64_t *>(hp + off_recb);
+        uint32_t *nr = reinterpret_cast<uint32_t *>(hp + off_nrec);
         size_t w = 0;
         for (int c = 0; c < n_chunks; ++c) {
             int64_t tiles = 0;
@@ -594,6 +629,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
                 tb[w++] = plans[a].tile_base;
                 tiles = plans[a].tile_base + int64_t(plans[a].tu) * plans[a].tv;
                 rb[a] = plans[a].rec_base;
+                nr[a] = static_cast<uint32_t>(int64_t(plans[a].nu) * plans[a].nv);
             }
             tb[w++] = tiles;
         }
@@ -604,14 +640,18 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     SBR_HIP(hipMemcpyAsync(dplans, hp + off_plans, sizeof(AnglePlan) * na, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(dtile, hp + off_tile, 8 * tile_words, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(drecb, hp + off_recb, 8 * na, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(dnrec, hp + off_nrec, 4 * na, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(dbasis, hp + off_basis, 72 * na, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(dkf, hp + off_kf, 8 * nf, hipMemcpyHostToDevice, s));
 
     const bool want_stats = stats != nullptr;
+    const int bm = sw->max_bounces;
+    const int epc = bm + 2;  // events per chunk: start, after each bounce, after the PO stage
     std::vector<hipEvent_t> ev;
+    std::vector<int64_t> chunk_rays(n_chunks, 0);
     if (want_stats) {
         std::memset(stats, 0, sizeof(*stats));
-        ev.resize(3 * n_chunks);
+        ev.resize(static_cast<size_t>(epc) * n_chunks);
         for (auto &e : ev) SBR_HIP(hipEventCreate(&e));
     }
     std::vector<unsigned long long> hstat(static_cast<size_t>(kStatU64) * n_chunks);
@@ -627,33 +667,30 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
             n_tiles += int64_t(plans[a].tu) * plans[a].tv;
             n_rays += int64_t(plans[a].nu) * plans[a].nv;
         }
-        SBR_HIP(hipMemsetAsync(cn.stat, 0, cn.bytes, s));
-        if (want_stats) SBR_HIP(hipEventRecord(ev[3 * c], s));
+        chunk_rays[c] = n_rays;
+        SBR_HIP(hipMemsetAsync(cn.base, 0, cn.bytes, s));
+        if (want_stats) SBR_HIP(hipEventRecord(ev[epc * c], s));
         TraceArgs ta{};
         ta.bvh = bvh;
-        ta.bmax = sw->max_bounces;
+        ta.bmax = bm;
         ta.flags = sw->flags;
+        ta.schedule = sched;
         ta.plans = cp;
         ta.tile_base = ctile;
         ta.n_angles = m;
         ta.n_tiles = n_tiles;
         ta.rec = rec;
-        ta.rec_cnt = cn.rec_cnt;
-        ta.q_cnt = cn.q_cnt;
-        ta.stat = cn.stat;
+        ta.ctrs = cn.p;
         ta.spill = spill;
-        ta.q_in = qb;
-        ta.q_out = qa;
-        if ((rc = launch_trace_grid(s, ta, 1))) return rc;
-        for (int b = 2; b <= sw->max_bounces; ++b) {
-            std::swap(ta.q_in, ta.q_out);
-            if ((rc = launch_trace_queue(s, ta, b, false))) return rc;
-        }
-        if (want_stats) SBR_HIP(hipEventRecord(ev[3 * c + 1], s));
+        std::vector<hipEvent_t> cev;
+        if (want_stats) cev.assign(ev.begin() + epc * c, ev.begin() + epc * (c + 1));
+        if ((rc = run_trace(s, ta, qa, qb, want_stats ? &cev : nullptr))) return rc;
+        const int trace_launches = sched == kScheduleStream ? 1 : bm;
         PoArgs pa{};
         pa.bvh = bvh;
         pa.rec = rec;
-        pa.rec_cnt = cn.rec_cnt;
+        pa.rec_cnt = static_cast<const uint32_t *>(dnrec) + a0;
+        pa.cnt_stride = 1;
         pa.rec_base = static_cast<const int64_t *>(drecb) + a0;
         pa.n_angles = m;
         pa.chunks = po_chunks;
@@ -666,8 +703,8 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         if ((rc = launch_po_finalize(s, pa, ds * ds, A_out + a0 * nf * 8, sigma_dbsm ? sigma_dbsm + a0 * nf * 4 : nullptr)))
             return rc;
         if (want_stats) {
-            SBR_HIP(hipEventRecord(ev[3 * c + 2], s));
-            SBR_HIP(hipMemcpyAsync(hstat.data() + static_cast<size_t>(kStatU64) * c, cn.stat, 8 * kStatU64,
+            SBR_HIP(hipEventRecord(ev[epc * c + trace_launches + 1], s));
+            SBR_HIP(hipMemcpyAsync(hstat.data() + static_cast<size_t>(kStatU64) * c, cn.p.stat, 8 * kStatU64,
                                    hipMemcpyDeviceToHost, s));
             stats->rays += n_rays;
         }
@@ -675,11 +712,17 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     if (want_stats || (sw->flags & SBR_OPT_SYNC)) SBR_HIP(hipStreamSynchronize(s));
     if (want_stats) {
         for (int c = 0; c < n_chunks; ++c) {
-            fill_stats(stats, hstat.data() + static_cast<size_t>(kStatU64) * c, sw->max_bounces);
-            float t1 = 0, t2 = 0;
-            SBR_HIP(hipEventElapsedTime(&t1, ev[3 * c], ev[3 * c + 1]));
-            SBR_HIP(hipEventElapsedTime(&t2, ev[3 * c + 1], ev[3 * c + 2]));
-            stats->ms_trace += t1;
+            fill_stats(stats, hstat.data() + static_cast<size_t>(kStatU64) * c, bm, chunk_rays[c],
+                       (sw->flags & SBR_OPT_DROP_TRAPPED) != 0);
+            const int nl = sched == kScheduleStream ? 1 : bm;
+            for (int b = 1; b <= nl; ++b) {
+                float t = 0;
+                SBR_HIP(hipEventElapsedTime(&t, ev[epc * c + b - 1], ev[epc * c + b]));
+                if (sched == kScheduleWavefront) stats->ms_bounce[b] += t;
+                stats->ms_trace += t;
+            }
+            float t2 = 0;
+            SBR_HIP(hipEventElapsedTime(&t2, ev[epc * c + nl], ev[epc * c + nl + 1]));
             stats->ms_po += t2;
         }
         for (auto &e : ev) (void)hipEventDestroy(e);

@@ -14,8 +14,10 @@
 //      the root and stops at the first parent whose other child is not done
 //      yet (per-node arrival counter);
 //   5. relayout into preorder, with both child boxes stored in the parent.
-// Leaves hold one triangle.  Boxes are padded so the traversal's box test
-// never culls a triangle the float32 intersection test would accept.
+// Subtrees of at most kLeafMax triangles are collapsed into leaves (their
+// triangles are contiguous in sorted order), the leaf threshold of the
+// paper's build.  Boxes are padded so the traversal's box test never culls a
+// triangle the float32 intersection test would accept.
 #include <algorithm>
 #include <cmath>
 
@@ -25,6 +27,7 @@ namespace sbr {
 namespace {
 
 constexpr int kSortThreads = 256;
+constexpr int kLeafMax = 4;  // triangles per leaf (at most 4: the leaf code keeps 2 count bits)
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
@@ -163,7 +166,7 @@ __device__ inline int lcp(const uint64_t *__restrict__ k, int n, int i, int j)
 // internal >= 0, leaf = ~index.
 __global__ void k_karras(const uint64_t *__restrict__ keys, int n, int *__restrict__ left, int *__restrict__ right,
                          int *__restrict__ parent_int, int *__restrict__ parent_leaf, int *__restrict__ range_first,
-                         uint8_t *__restrict__ is_left)
+                         int *__restrict__ range_last, uint8_t *__restrict__ is_left)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
@@ -203,6 +206,7 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, int n, int *__restri
     left[i] = lc;
     right[i] = rc;
     range_first[i] = lo;
+    range_last[i] = hi;
     if (i == 0) parent_int[0] = -1;
 }
 
@@ -280,37 +284,67 @@ __global__ void k_preorder(int n_int, const int *__restrict__ parent_int, const 
     atomicMax(depth, dep + 1);
 }
 
-__global__ void k_relayout(int n_int, const int *__restrict__ left, const int *__restrict__ right,
-                           const int *__restrict__ pre, const float *__restrict__ lbox,
-                           const float *__restrict__ nbox, BNode *__restrict__ out)
+// Internal nodes whose range holds more than kLeafMax triangles are kept;
+// flag them at their full preorder position so a scan numbers the kept
+// nodes in preorder.
+__global__ void k_mark_kept(int n_int, const int *__restrict__ pre, const int *__restrict__ range_first,
+                            const int *__restrict__ range_last, uint32_t *__restrict__ flag)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_int) return;
+    flag[pre[i]] = (range_last[i] - range_first[i] + 1 > kLeafMax) ? 1u : 0u;
+}
+
+__device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }
+
+__global__ void k_relayout(int n_int, const int *__restrict__ left, const int *__restrict__ right,
+                           const int *__restrict__ pre, const uint32_t *__restrict__ newidx,
+                           const int *__restrict__ range_first, const int *__restrict__ range_last,
+                           const float *__restrict__ lbox, const float *__restrict__ nbox, BNode *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_int) return;
+    if (range_last[i] - range_first[i] + 1 <= kLeafMax) return;  // inside a collapsed leaf
     const int c[2] = {left[i], right[i]};
     float bx[2][6];
     int ref[2];
     for (int s = 0; s < 2; ++s) {
         const float *b = c[s] < 0 ? lbox + 6 * (~c[s]) : nbox + 6 * c[s];
         for (int k = 0; k < 6; ++k) bx[s][k] = b[k];
-        ref[s] = c[s] < 0 ? c[s] : pre[c[s]];
+        if (c[s] < 0) {
+            ref[s] = leaf_ref(~c[s], 1);
+        } else {
+            const int cnt = range_last[c[s]] - range_first[c[s]] + 1;
+            ref[s] = cnt <= kLeafMax ? leaf_ref(range_first[c[s]], cnt) : static_cast<int>(newidx[pre[c[s]]]);
+        }
     }
     BNode nd;
     nd.a = make_float4(bx[0][0], bx[0][1], bx[0][2], bx[0][3]);
     nd.b = make_float4(bx[0][4], bx[0][5], bx[1][0], bx[1][1]);
     nd.c = make_float4(bx[1][2], bx[1][3], bx[1][4], bx[1][5]);
     nd.ch = make_int4(ref[0], ref[1], 0, 0);
-    out[pre[i]] = nd;
+    out[newidx[pre[i]]] = nd;
 }
 
-// Tree of a single triangle: one node whose two children are that leaf.
-__global__ void k_single(const float *__restrict__ lbox, BNode *__restrict__ out)
+// Tree of at most kLeafMax triangles: one node whose two children are the
+// same leaf (tested twice, with the same result).
+__global__ void k_single(int n, const float *__restrict__ lbox, BNode *__restrict__ out)
 {
-    const float *b = lbox;
+    float b[6];
+    for (int k = 0; k < 3; ++k) {
+        b[k] = INFINITY;
+        b[3 + k] = -INFINITY;
+    }
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < 3; ++k) {
+            b[k] = fminf(b[k], lbox[6 * j + k]);
+            b[3 + k] = fmaxf(b[3 + k], lbox[6 * j + 3 + k]);
+        }
     BNode nd;
     nd.a = make_float4(b[0], b[1], b[2], b[3]);
     nd.b = make_float4(b[4], b[5], b[0], b[1]);
     nd.c = make_float4(b[2], b[3], b[4], b[5]);
-    nd.ch = make_int4(~0, ~0, 0, 0);
+    nd.ch = make_int4(leaf_ref(0, n), leaf_ref(0, n), 0, 0);
     out[0] = nd;
 }
 
@@ -429,33 +463,43 @@ int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, sbr_bvh *bvh)
     k_leaves<<<blocks_for(n, 256), 256, 0, s>>>(n, vin, dv0, de1, de2, dn, dids, pad, bvh->tris, bvh->nrm_slot,
                                                 lbox);
     SBR_HIP(hipGetLastError());
-    if (n == 1) {
-        k_single<<<1, 1, 0, s>>>(lbox, bvh->nodes);
+    if (n <= kLeafMax) {
+        k_single<<<1, 1, 0, s>>>(n, lbox, bvh->nodes);
         SBR_HIP(hipGetLastError());
         SBR_HIP(hipStreamSynchronize(s));
+        bvh->n_nodes = 1;
         bvh->depth = 1;
         return SBR_OK;
     }
-    int *left, *right, *pint, *pleaf, *rfirst, *arrive, *pre, *depth;
+    int *left, *right, *pint, *pleaf, *rfirst, *rlast, *arrive, *pre, *depth;
+    uint32_t *newidx;
     uint8_t *isleft;
     float *nbox;
     if ((rc = tmp.alloc(&left, n_int)) || (rc = tmp.alloc(&right, n_int)) || (rc = tmp.alloc(&pint, n_int)) ||
-        (rc = tmp.alloc(&pleaf, n)) || (rc = tmp.alloc(&rfirst, n_int)) || (rc = tmp.alloc(&arrive, n_int)) ||
-        (rc = tmp.alloc(&pre, n_int)) || (rc = tmp.alloc(&depth, 1)) || (rc = tmp.alloc(&isleft, n_int)) ||
+        (rc = tmp.alloc(&pleaf, n)) || (rc = tmp.alloc(&rfirst, n_int)) || (rc = tmp.alloc(&rlast, n_int)) ||
+        (rc = tmp.alloc(&arrive, n_int)) || (rc = tmp.alloc(&pre, n_int)) || (rc = tmp.alloc(&depth, 1)) ||
+        (rc = tmp.alloc(&isleft, n_int)) || (rc = tmp.alloc(&newidx, n_int + 1)) ||
         (rc = tmp.alloc(&nbox, 6 * static_cast<size_t>(n_int))))
         return rc;
     SBR_HIP(hipMemsetAsync(arrive, 0, sizeof(int) * n_int, s));
     SBR_HIP(hipMemsetAsync(depth, 0, sizeof(int), s));
     SBR_HIP(hipMemsetAsync(isleft, 0, n_int, s));
-    k_karras<<<blocks_for(n_int, 256), 256, 0, s>>>(kin, n, left, right, pint, pleaf, rfirst, isleft);
+    SBR_HIP(hipMemsetAsync(newidx, 0, sizeof(uint32_t) * (n_int + 1), s));
+    k_karras<<<blocks_for(n_int, 256), 256, 0, s>>>(kin, n, left, right, pint, pleaf, rfirst, rlast, isleft);
     k_refit<<<blocks_for(n, 256), 256, 0, s>>>(n, left, right, pint, pleaf, lbox, nbox, arrive);
     k_preorder<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, pint, isleft, rfirst, pre, depth);
-    k_relayout<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, left, right, pre, lbox, nbox, bvh->nodes);
+    k_mark_kept<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, pre, rfirst, rlast, newidx);
+    k_scan<<<1, 1024, 0, s>>>(newidx, n_int + 1);  // newidx[n_int] becomes the kept-node count
+    k_relayout<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, left, right, pre, newidx, rfirst, rlast, lbox, nbox,
+                                                      bvh->nodes);
     SBR_HIP(hipGetLastError());
     int hdepth = 0;
+    uint32_t kept = 0;
     SBR_HIP(hipMemcpyAsync(&hdepth, depth, sizeof(int), hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipMemcpyAsync(&kept, newidx + n_int, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SBR_HIP(hipStreamSynchronize(s));
     bvh->depth = hdepth;
+    bvh->n_nodes = kept;
     return SBR_OK;
 }
 

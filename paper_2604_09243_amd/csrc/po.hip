@@ -32,6 +32,7 @@ constexpr int kFT = 2;  // frequencies per pass over a block's records
 struct PoP {
     Records rec;
     const uint32_t *rec_cnt;
+    int cnt_stride;
     const int64_t *rec_base;
     const float4 *nrm_id;
     int chunks;
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
     __shared__ long long red[kPoThreads / 64][kFT * 8];
     const int a = blockIdx.y, c = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t cnt = p.rec_cnt[a];
+    const int64_t cnt = p.rec_cnt[static_cast<int64_t>(a) * p.cnt_stride];
     const int64_t base = p.rec_base[a];
     const int64_t r0i = static_cast<int64_t>(c) * kPoRecsPerBlock;
     long long *out = p.partial + ((static_cast<int64_t>(a) * p.chunks + c) * p.n_freq) * 8;
@@ -138,7 +139,9 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
         for (int ft = 0; ft < kFT; ++ft)
             for (int e = 0; e < 8; ++e) acc[ft][e] = 0;
         for (int64_t e = base + r0i + tid; e < base + r1i; e += kPoThreads) {
-            const float4 q0 = p.rec.r0[e], q1 = p.rec.r1[e], q2 = p.rec.r2[e];
+            const float4 q2 = p.rec.r2[e];
+            if (!((__float_as_int(q2.w) >> 8) & SBR_REC_VALID)) continue;  // no hit (or dropped): no term
+            const float4 q0 = p.rec.r0[e], q1 = p.rec.r1[e];
             const double D = p.rec.D[e];
             float w[4];
             weights(p, a, q0, q1, q2, w);
@@ -175,14 +178,15 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
 }
 
 // One thread per (angle, frequency): fixed-order sum of the block partials.
-__global__ void k_po_final(const long long *__restrict__ partial, const uint32_t *__restrict__ rec_cnt, int n_angles,
-                           int chunks, int n_freq, const double *__restrict__ kf, double dA,
+__global__ void k_po_final(const long long *__restrict__ partial, const uint32_t *__restrict__ rec_cnt, int cnt_stride,
+                           int n_angles, int chunks, int n_freq, const double *__restrict__ kf, double dA,
                            double *__restrict__ A_out, double *__restrict__ sigma)
 {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= static_cast<int64_t>(n_angles) * n_freq) return;
     const int a = static_cast<int>(idx / n_freq), f = static_cast<int>(idx % n_freq);
-    const int64_t nch = (static_cast<int64_t>(rec_cnt[a]) + kPoRecsPerBlock - 1) / kPoRecsPerBlock;
+    const int64_t nch = (static_cast<int64_t>(rec_cnt[static_cast<int64_t>(a) * cnt_stride]) + kPoRecsPerBlock - 1) /
+                        kPoRecsPerBlock;
     double S[8];
     for (int e = 0; e < 8; ++e) S[e] = 0.0;
     for (int64_t c = 0; c < nch; ++c) {
@@ -232,6 +236,7 @@ int launch_po(hipStream_t s, const PoArgs &a)
     PoP p;
     p.rec = a.rec;
     p.rec_cnt = a.rec_cnt;
+    p.cnt_stride = a.cnt_stride;
     p.rec_base = a.rec_base;
     p.nrm_id = a.bvh->nrm_id;
     p.chunks = a.chunks;
@@ -249,7 +254,7 @@ int launch_po(hipStream_t s, const PoArgs &a)
 int launch_po_finalize(hipStream_t s, const PoArgs &a, double dA, double *A_out, double *sigma_out)
 {
     const int64_t n = static_cast<int64_t>(a.n_angles) * a.n_freq;
-    k_po_final<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(a.partial, a.rec_cnt, a.n_angles, a.chunks,
+    k_po_final<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(a.partial, a.rec_cnt, a.cnt_stride, a.n_angles, a.chunks,
                                                                       a.n_freq, a.kf, dA, A_out, sigma_out);
     SBR_HIP(hipGetLastError());
     return SBR_OK;

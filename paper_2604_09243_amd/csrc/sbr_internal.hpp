@@ -28,7 +28,8 @@ int fail(int status, const std::string &msg);
 // BVH2 node: both child boxes inline (one 64-byte fetch tests two boxes).
 //   a = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)  b = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
 //   c = (R.lo.z, R.hi.x, R.hi.y, R.hi.z)  ch = (left, right, -, -)
-// child >= 0: internal node index; child < 0: leaf holding triangle slot ~child.
+// child >= 0: internal node index; child < 0: leaf, ~child = first_slot * 8 +
+// (count - 1): triangles [first_slot, first_slot + count) of the slot order.
 struct __align__(16) BNode {
     float4 a, b, c;
     int4 ch;
@@ -50,17 +51,18 @@ struct AnglePlan {
     int64_t rec_base;          // first record slot of this angle
 };
 
-// In-flight ray state, 6 x 16 bytes (structure of arrays of float4).
-//   s0 = (o.xyz, tri_prev)   s1 = (d.xyz, tri_first)   s2 = (eH.xyz, ray_id)
-//   s3 = (eV.xyz, meta)      s4 = (P, comp) as double2  s5 = (k.o0 as double, rec, -)
+// In-flight ray state of the wavefront schedule's queues, 6 x 16 bytes
+// (structure of arrays): s0 = (o.xyz, tri_prev)  s1 = (d.xyz, tri_first)
+// s2 = (eH.xyz, ray_id)  s3 = (eV.xyz, meta)  s4 = (P, comp)  s5 = (k.o0, -)
 // meta = N | back << 7 | angle_slot << 8
 struct RayQueue {
     float4 *s0, *s1, *s2, *s3;
     double2 *s4;
-    double2 *s5;  // .x = k.o0, .y = record slot (stored as double bits of int64)
+    double2 *s5;
 };
 
-// Compact hit record of one valid ray (sweep path), structure of arrays.
+// Hit record of one ray (structure of arrays); r2.w carries N | flags << 8,
+// zero for a ray that never hit.
 //   r0 = (d_last.xyz, tri_last)  r1 = (eH_last.xyz, tri_first)
 //   r2 = (eV_last.xyz, N | flags << 8)  D
 struct Records {
@@ -68,14 +70,25 @@ struct Records {
     double *D;
 };
 
-// Counter block zeroed before each sweep chunk / trace call:
-//   u64 stat[kStatU64]: [0] queries, [1] trapped, [8 + b] hits at bounce b,
-//     then 8 uint32 tile counters per bounce launch (0..kMaxLaunch-1)
-//   u32 q_cnt[kQcnt]: q_cnt[b] = rays pushed during bounce b
-//   u32 rec_cnt[n_angles]
+// Counter block, zeroed before each sweep chunk / trace call.  Counters that
+// many waves update sit on separate 256-byte lines (kLineU32 uint32 apart):
+//   stat:  u64[kStatU64] = [0] queries, [1] trapped, [8 + b] hits at bounce b
+//   q_cnt: kQcnt lines; q_cnt[b] = rays pushed during bounce-b launch
+//   claim: kMaxLaunch x 8 lines; the 8 tile-claim counters of each launch
+constexpr int kLineU32 = 64;
+constexpr int kStatU64 = 8 + SBR_MAX_BOUNCES + 1;
 constexpr int kMaxLaunch = SBR_MAX_BOUNCES + 2;
-constexpr int kStatU64 = 8 + SBR_MAX_BOUNCES + 1 + (8 * kMaxLaunch) / 2;
-constexpr int kQcnt = SBR_MAX_BOUNCES + 8;
+constexpr int kQcnt = SBR_MAX_BOUNCES + 2;
+constexpr size_t kStatBytes = 1024;
+constexpr size_t kCounterBytes = kStatBytes + 4ull * kLineU32 * (kQcnt + 8 * kMaxLaunch);
+struct CounterPtrs {
+    unsigned long long *stat;
+    uint32_t *q_cnt;
+    uint32_t *claim;
+};
+
+constexpr int kScheduleStream = 0;
+constexpr int kScheduleWavefront = 1;
 
 struct Workspace;
 
@@ -143,6 +156,7 @@ struct TraceArgs {
     const sbr_bvh *bvh;
     int bmax;
     uint32_t flags;
+    int schedule;             // kScheduleStream or kScheduleWavefront
     // grid source (sweep)
     const AnglePlan *plans;   // device [n_angles]
     const int64_t *tile_base; // device [n_angles + 1]
@@ -153,19 +167,14 @@ struct TraceArgs {
     int64_t n_rays;
     const sbr_hits *hits;
     double k_hat[3];
-    // queues, records, counters
+    // queues (wavefront schedule), records (sweep), counters
     RayQueue q_in, q_out;
     Records rec;
-    uint32_t *rec_cnt;        // device [n_angles]
-    uint32_t *q_cnt;          // device [bmax + 1]: q_cnt[b] = rays entering bounce b+1
-    unsigned long long *stat; // device [8 + SBR_MAX_BOUNCES + 1]
+    CounterPtrs ctrs;
     int32_t *spill;           // device traversal-stack spill
-    int64_t spill_stride;
-    int spill_depth;
 };
-int launch_trace_grid(hipStream_t s, const TraceArgs &a, int bounce);
-int launch_trace_rays(hipStream_t s, const TraceArgs &a);
-int launch_trace_queue(hipStream_t s, const TraceArgs &a, int bounce, bool user_sink);
+// bounce = 1 for the stream schedule (one launch does every bounce)
+int launch_trace(hipStream_t s, const TraceArgs &a, int bounce);
 int trace_persistent_blocks(sbr_ctx *ctx);
 int trace_block_threads();
 int trace_stack_lds();
@@ -174,8 +183,9 @@ int trace_stack_lds();
 struct PoArgs {
     const sbr_bvh *bvh;
     Records rec;
-    const uint32_t *rec_cnt;  // [n_angles]
-    const int64_t *rec_base;  // [n_angles]
+    const uint32_t *rec_cnt;  // [n_angles * cnt_stride]: record slots of each angle
+    int cnt_stride;
+    const int64_t *rec_base;  // [n_angles]: first record slot of each angle
     int n_angles;
     int chunks;               // blocks per angle along x
     int mode;

@@ -1,24 +1,37 @@
 // Multi-bounce ray transport (Algorithm 2) on gfx950.
 //
-// Wavefront organisation: one kernel launch per bounce.  Bounce 1 takes its
-// rays either from the incidence-angle plans (the orthographic grid of
-// Eqs. L1-L3, generated in-register, 8x8 aperture tiles per 64-lane wave) or
-// from caller arrays; later bounces take them from a queue.  Rays that hit
-// and have bounces left are appended to the next queue with one atomic per
-// wave (ballot + prefix popcount); every hit overwrites the ray's hit record,
-// so the record of a terminated ray is its last hit.
+// Two schedules share the traversal, the bounce update and the record sinks:
 //
-// Launches are persistent: a fixed grid of waves pulls 64-ray tiles from
-// eight counters, one per XCD-sized range of tiles (a block's XCD is taken as
-// blockIdx % 8, the order in which workgroups are spread over the dies), and
-// steals from the other ranges once its own is empty.
+// STREAM (default): one persistent launch carries every ray through all of
+//   its bounces in registers.  Between bounces the lanes whose ray ended are
+//   refilled: a wave ballot of the idle lanes ranks them (mbcnt prefix count)
+//   and idle lane k takes the k-th unused ray of the wave's current batch,
+//   so the active rays stay packed into the wave without moving any ray
+//   state.  A batch (kClaimTiles 64-ray tiles) is claimed with one atomic on
+//   one of eight counters, each counter on its own 256-byte line and owning
+//   an XCD-sized contiguous range of tiles (a block's XCD is taken as
+//   blockIdx % 8, the order in which workgroups are spread over the dies);
+//   a wave whose range is empty steals from the others.
+// WAVEFRONT: one launch per bounce.  Rays that hit and have bounces left are
+//   compacted into the next bounce's queue with one atomic per wave (ballot
+//   + prefix popcount); the next launch reads that queue.
+//
+// Rays of the incidence-angle grid (Eqs. L1-L3) are generated in-register:
+// a 64-ray tile is an 8x8 patch of the aperture.  Every hit overwrites the
+// ray's record (one slot per ray), so a terminated ray's record holds its
+// last hit; a ray that never hits writes an empty record.
 //
 // Closest hit: BVH2 traversal, both child boxes of a node per 64-byte fetch,
 // nearer child first, the farther one on a per-lane stack that lives in LDS
-// (spilling to a global array beyond kStackLds entries).  The triangle test
-// and the reflection arithmetic follow the float32 specification shared with
-// the CPU oracle; this file is compiled with -ffp-contract=off, and fused
-// multiply-adds are written explicitly only in the (conservative) box test.
+// (spilling to a global array beyond kStackLds entries).  The loop is split
+// in two phases per step: lanes descend through internal nodes until each
+// holds a leaf (or is done), then the wave tests leaf triangles together;
+// a leaf's triangles are read as whole 48-byte records with the next one
+// prefetched.  The triangle test and the reflection arithmetic follow the
+// float32 specification shared with the CPU oracle; this file is compiled
+// with -ffp-contract=off, and fused multiply-adds are written explicitly
+// only in the (conservative) box test.
+#include <climits>
 #include <cmath>
 
 #include "sbr_internal.hpp"
@@ -27,11 +40,12 @@ namespace sbr {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kStackLds = 24;
+constexpr int kStackLds = 16;
 constexpr int kTileRays = 64;
-
-// stat slots
-enum { ST_QUERIES = 0, ST_TRAPPED = 1, ST_VALID = 2, ST_HITS = 8 };
+constexpr int kClaimTiles = 4;
+#ifndef SBR_TRACE_WAVES_PER_SIMD
+#define SBR_TRACE_WAVES_PER_SIMD 1  // occupancy floor handed to the register allocator
+#endif
 
 struct Params {
     const BNode *nodes;
@@ -44,21 +58,20 @@ struct Params {
     const AnglePlan *plans;
     const int64_t *tile_base;
     int n_angles;
-    // user source / sink
+    // caller source / sink
     const float *uo, *ud, *uh, *uv;
     int64_t n_rays;
     sbr_hits hits;
     double kx, ky, kz;
-    // queues
+    // wavefront queues
     RayQueue qin, qout;
     const uint32_t *qin_cnt;
     uint32_t *qout_cnt;
-    // records (compact sink)
+    // records of the sweep (one slot per ray: plan.rec_base + ray id)
     Records rec;
-    uint32_t *rec_cnt;
     // misc
-    int64_t n_tiles;  // for grid/user sources
-    uint32_t *ctr;    // 8 tile counters for this launch
+    int64_t n_tiles;
+    uint32_t *ctr;  // 8 claim counters, kLineU32 apart
     unsigned long long *stat;
     int32_t *spill;
     int bounce;
@@ -68,9 +81,14 @@ struct Params {
 struct Ray {
     float ox, oy, oz, dx, dy, dz;
     float hx, hy, hz, vx, vy, vz;
-    int prev, first, id, meta;
+    int prev, first, id, meta;  // meta = N | back << 7 | angle slot << 8
     double P, comp, kdo;
-    int rec;
+};
+
+struct Best {
+    float t;
+    int id;
+    int slot;
 };
 
 __device__ __forceinline__ bool tri_test(const BTri &tr, const Ray &r, float &t_out)
@@ -95,24 +113,18 @@ __device__ __forceinline__ bool tri_test(const BTri &tr, const Ray &r, float &t_
     return u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f && t < INFINITY;
 }
 
-struct Best {
-    float t;
-    int id;
-    int slot;
-};
-
-__device__ __forceinline__ void leaf(const Params &p, int slot, const Ray &r, Best &b)
+__device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r, Best &b)
 {
-    const BTri tr = p.tris[slot];
     const int id = __float_as_int(tr.p0.w);
-    if (id == r.prev) return;
     float t;
-    if (tri_test(tr, r, t) && (t < b.t || (t == b.t && id < b.id))) {
+    if (tri_test(tr, r, t) && id != r.prev && (t < b.t || (t == b.t && id < b.id))) {
         b.t = t;
         b.id = id;
         b.slot = slot;
     }
 }
+
+constexpr int kEmpty = INT_MIN;  // never a valid node or leaf reference
 
 // Closest hit of ray r, skipping triangle r.prev.  lst: this lane's LDS stack
 // column (stride kBlock); gst: its spill column (stride gstride).
@@ -129,70 +141,70 @@ __device__ Best closest(const Params &p, const Ray &r, int *lst, int32_t *gst, i
     const float ix = __builtin_amdgcn_rcpf(ddx), iy = __builtin_amdgcn_rcpf(ddy), iz = __builtin_amdgcn_rcpf(ddz);
     const float ox = r.ox * ix, oy = r.oy * iy, oz = r.oz * iz;
     int sp = 0;
-    int node = 0;
+    int cur = 0;  // the root is an internal node
     for (;;) {
-        const BNode n = p.nodes[node];
-        const float tlim = __builtin_fmaf(b.t, 1.000001f, p.slack);
-        // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
-        const float ax0 = __builtin_fmaf(n.a.x, ix, -ox), ax1 = __builtin_fmaf(n.a.w, ix, -ox);
-        const float ay0 = __builtin_fmaf(n.a.y, iy, -oy), ay1 = __builtin_fmaf(n.b.x, iy, -oy);
-        const float az0 = __builtin_fmaf(n.a.z, iz, -oz), az1 = __builtin_fmaf(n.b.y, iz, -oz);
-        const float t0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-        const float u0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tlim));
-        // child 1: lo = (b.z, b.w, c.x), hi = (c.y, c.z, c.w)
-        const float bx0 = __builtin_fmaf(n.b.z, ix, -ox), bx1 = __builtin_fmaf(n.c.y, ix, -ox);
-        const float by0 = __builtin_fmaf(n.b.w, iy, -oy), by1 = __builtin_fmaf(n.c.z, iy, -oy);
-        const float bz0 = __builtin_fmaf(n.c.x, iz, -oz), bz1 = __builtin_fmaf(n.c.w, iz, -oz);
-        const float t1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-        const float u1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tlim));
-        bool h0 = t0 <= u0, h1 = t1 <= u1;
-        int c0 = n.ch.x, c1 = n.ch.y;
-        if (h0 && c0 < 0) {
-            leaf(p, ~c0, r, b);
-            h0 = false;
-        }
-        if (h1 && c1 < 0) {
-            leaf(p, ~c1, r, b);
-            h1 = false;
-        }
-        if (h0 && h1) {
-            int nr = c0, fr = c1;
-            if (t1 < t0) {
-                nr = c1;
-                fr = c0;
+        // phase 1: descend through internal nodes until a leaf (or nothing) is next
+        while (cur >= 0) {
+            const BNode n = p.nodes[cur];
+            const float tlim = __builtin_fmaf(b.t, 1.000001f, p.slack);
+            // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
+            const float ax0 = __builtin_fmaf(n.a.x, ix, -ox), ax1 = __builtin_fmaf(n.a.w, ix, -ox);
+            const float ay0 = __builtin_fmaf(n.a.y, iy, -oy), ay1 = __builtin_fmaf(n.b.x, iy, -oy);
+            const float az0 = __builtin_fmaf(n.a.z, iz, -oz), az1 = __builtin_fmaf(n.b.y, iz, -oz);
+            const float t0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+            const float u0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tlim));
+            // child 1: lo = (b.z, b.w, c.x), hi = (c.y, c.z, c.w)
+            const float bx0 = __builtin_fmaf(n.b.z, ix, -ox), bx1 = __builtin_fmaf(n.c.y, ix, -ox);
+            const float by0 = __builtin_fmaf(n.b.w, iy, -oy), by1 = __builtin_fmaf(n.c.z, iy, -oy);
+            const float bz0 = __builtin_fmaf(n.c.x, iz, -oz), bz1 = __builtin_fmaf(n.c.w, iz, -oz);
+            const float t1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+            const float u1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tlim));
+            const bool h0 = t0 <= u0, h1 = t1 <= u1;
+            if (h0 && h1) {
+                int nr = n.ch.x, fr = n.ch.y;
+                if (t1 < t0) {
+                    nr = n.ch.y;
+                    fr = n.ch.x;
+                }
+                if (sp < kStackLds) lst[sp * kBlock] = fr;
+                else gst[(sp - kStackLds) * gstride] = fr;
+                ++sp;
+                cur = nr;
+            } else if (h0) {
+                cur = n.ch.x;
+            } else if (h1) {
+                cur = n.ch.y;
+            } else if (sp > 0) {
+                --sp;
+                cur = sp < kStackLds ? lst[sp * kBlock] : gst[(sp - kStackLds) * gstride];
+            } else {
+                cur = kEmpty;
             }
-            if (sp < kStackLds) lst[sp * kBlock] = fr;
-            else gst[(sp - kStackLds) * gstride] = fr;
-            ++sp;
-            node = nr;
-        } else if (h0) {
-            node = c0;
-        } else if (h1) {
-            node = c1;
-        } else {
-            if (sp == 0) break;
+        }
+        if (cur == kEmpty) break;
+        // phase 2: the triangles of leaf `cur`, next record prefetched
+        const int code = ~cur;
+        const int first = code >> 3, cnt = (code & 7) + 1;
+        BTri tr = p.tris[first];
+        for (int k = 0; k < cnt; ++k) {
+            BTri nx = tr;
+            if (k + 1 < cnt) nx = p.tris[first + k + 1];
+            test_tri(tr, first + k, r, b);
+            tr = nx;
+        }
+        if (sp > 0) {
             --sp;
-            node = sp < kStackLds ? lst[sp * kBlock] : gst[(sp - kStackLds) * gstride];
+            cur = sp < kStackLds ? lst[sp * kBlock] : gst[(sp - kStackLds) * gstride];
+        } else {
+            break;
         }
     }
     return b;
 }
 
-__device__ __forceinline__ double dotk(const Params &p, const double *k, float x, float y, float z)
+__device__ __forceinline__ double dotk(const double *k, float x, float y, float z)
 {
     return (k[0] * static_cast<double>(x) + k[1] * static_cast<double>(y)) + k[2] * static_cast<double>(z);
-}
-
-__device__ __forceinline__ int64_t fetch_tile(uint32_t *ctr, int64_t n_tiles, int xcd)
-{
-    for (int kk = 0; kk < 8; ++kk) {
-        const int c = (xcd + kk) & 7;
-        const int64_t lo = n_tiles * c / 8, hi = n_tiles * (c + 1) / 8;
-        if (hi <= lo) continue;
-        const uint32_t t = atomicAdd(&ctr[c], 1u);
-        if (lo + static_cast<int64_t>(t) < hi) return lo + t;
-    }
-    return -1;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt()
@@ -201,12 +213,29 @@ __device__ __forceinline__ uint64_t lanemask_lt()
     return (1ull << lane) - 1ull;
 }
 
-// Wave-aggregated atomic add: every active lane with `want` gets a distinct
-// slot from *ctr (consecutive within the wave, in lane order).
-__device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool want, uint64_t &mask_out)
+// Claims a batch of up to `batch` units from eight contiguous ranges of
+// [0, n_units), starting with range `xcd`.  Returns the first unit and sets
+// *end, or returns -1 when every range is exhausted.
+__device__ __forceinline__ int64_t claim(uint32_t *ctr, int64_t n_units, int xcd, int batch, int64_t *end)
+{
+    for (int kk = 0; kk < 8; ++kk) {
+        const int c = (xcd + kk) & 7;
+        const int64_t lo = n_units * c / 8, hi = n_units * (c + 1) / 8;
+        if (hi <= lo) continue;
+        const uint32_t t = atomicAdd(&ctr[c * kLineU32], static_cast<uint32_t>(batch));
+        if (lo + static_cast<int64_t>(t) < hi) {
+            *end = min(lo + static_cast<int64_t>(t) + batch, hi);
+            return lo + t;
+        }
+    }
+    return -1;
+}
+
+// Wave-aggregated atomic add: every lane with `want` gets a distinct slot
+// from *ctr (consecutive within the wave, in lane order).
+__device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool want)
 {
     const uint64_t m = __ballot(want);
-    mask_out = m;
     uint32_t base = 0;
     if (m) {
         const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
@@ -216,106 +245,357 @@ __device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool want, uint64_
     return base + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
 }
 
-template <int SRC>  // 0 = angle grid, 1 = caller rays, 2 = queue
-__global__ __launch_bounds__(kBlock) void k_trace(Params p)
+// Position q of the angle grid (tile = q / 64, lane of the 8x8 patch =
+// q % 64) -> a fresh ray; false if q lies outside the angle's N_u x N_v grid.
+__device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r)
+{
+    const int64_t tile = q >> 6;
+    const int k = static_cast<int>(q & 63);
+    int lo = 0, hi = p.n_angles;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (p.tile_base[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const AnglePlan &pl = p.plans[lo];
+    const int64_t t = tile - pl.tile_base;
+    const int i = static_cast<int>(t % pl.tu) * 8 + (k & 7);
+    const int j = static_cast<int>(t / pl.tu) * 8 + (k >> 3);
+    if (i >= pl.nu || j >= pl.nv) return false;
+    const double ui = pl.uc + ((static_cast<double>(i) + 0.5) - 0.5 * static_cast<double>(pl.nu)) * pl.ds;
+    const double vj = pl.vc + ((static_cast<double>(j) + 0.5) - 0.5 * static_cast<double>(pl.nv)) * pl.ds;
+    r.ox = static_cast<float>((ui * pl.u[0] + vj * pl.v[0]) + pl.s0 * pl.k[0]);
+    r.oy = static_cast<float>((ui * pl.u[1] + vj * pl.v[1]) + pl.s0 * pl.k[1]);
+    r.oz = static_cast<float>((ui * pl.u[2] + vj * pl.v[2]) + pl.s0 * pl.k[2]);
+    r.dx = pl.d32[0];
+    r.dy = pl.d32[1];
+    r.dz = pl.d32[2];
+    r.hx = pl.eH32[0];
+    r.hy = pl.eH32[1];
+    r.hz = pl.eH32[2];
+    r.vx = pl.eV32[0];
+    r.vy = pl.eV32[1];
+    r.vz = pl.eV32[2];
+    r.prev = -1;
+    r.first = -1;
+    r.id = j * pl.nu + i;
+    r.meta = lo << 8;
+    r.P = 0.0;
+    r.comp = 0.0;
+    r.kdo = dotk(pl.k, r.ox, r.oy, r.oz);
+    return true;
+}
+
+// Ray e of the caller's arrays; false if e >= n_rays.
+__device__ __forceinline__ bool user_ray(const Params &p, int64_t e, Ray &r)
+{
+    if (e >= p.n_rays) return false;
+    r.ox = p.uo[3 * e];
+    r.oy = p.uo[3 * e + 1];
+    r.oz = p.uo[3 * e + 2];
+    r.dx = p.ud[3 * e];
+    r.dy = p.ud[3 * e + 1];
+    r.dz = p.ud[3 * e + 2];
+    r.hx = p.uh[3 * e];
+    r.hy = p.uh[3 * e + 1];
+    r.hz = p.uh[3 * e + 2];
+    r.vx = p.uv[3 * e];
+    r.vy = p.uv[3 * e + 1];
+    r.vz = p.uv[3 * e + 2];
+    r.prev = -1;
+    r.first = -1;
+    r.id = static_cast<int>(e);
+    r.meta = 0;
+    r.P = 0.0;
+    r.comp = 0.0;
+    const double k[3] = {p.kx, p.ky, p.kz};
+    r.kdo = dotk(k, r.ox, r.oy, r.oz);
+    if (p.hits.tri_path)
+        for (int b = 0; b < p.bmax; ++b) p.hits.tri_path[e * p.bmax + b] = -1;
+    return true;
+}
+
+struct Last {
+    float dlx, dly, dlz, xlx, xly, xlz, hlx, hly, hlz, vlx, vly, vlz;
+    double D;
+    int flags;
+};
+
+// Algorithm 2 bookkeeping for a hit b of ray r, then the specular
+// reflection of the direction and of both field vectors, and the new origin
+// eps off the surface on the side the ray came from.  Returns whether the
+// ray has bounces left.
+__device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, const double *kv, Last &L)
+{
+    const float t = b.t;
+    L.xlx = r.ox + t * r.dx;
+    L.xly = r.oy + t * r.dy;
+    L.xlz = r.oz + t * r.dz;
+    int N = r.meta & 127;
+    r.P = r.P + static_cast<double>(t);
+    if (N >= 1 && !(p.flags & SBR_OPT_PAPER_PATH)) r.P = r.P + r.comp;
+    N += 1;
+    if (N == 1) r.first = b.id;
+    L.dlx = r.dx;
+    L.dly = r.dy;
+    L.dlz = r.dz;
+    L.hlx = r.hx;
+    L.hly = r.hy;
+    L.hlz = r.hz;
+    L.vlx = r.vx;
+    L.vly = r.vy;
+    L.vlz = r.vz;
+    const float4 n = p.nrm[b.slot];
+    const float dn = (r.dx * n.x + r.dy * n.y) + r.dz * n.z;
+    const bool back = !(dn < 0.0f);
+    const float nfx = back ? -n.x : n.x, nfy = back ? -n.y : n.y, nfz = back ? -n.z : n.z;
+    const float s = 2.0f * dn;
+    r.dx = r.dx - s * n.x;
+    r.dy = r.dy - s * n.y;
+    r.dz = r.dz - s * n.z;
+    const float cH = 2.0f * ((n.x * r.hx + n.y * r.hy) + n.z * r.hz);
+    const float cV = 2.0f * ((n.x * r.vx + n.y * r.vy) + n.z * r.vz);
+    r.hx = cH * n.x - r.hx;
+    r.hy = cH * n.y - r.hy;
+    r.hz = cH * n.z - r.hz;
+    r.vx = cV * n.x - r.vx;
+    r.vy = cV * n.y - r.vy;
+    r.vz = cV * n.z - r.vz;
+    r.ox = L.xlx + p.eps * nfx;
+    r.oy = L.xly + p.eps * nfy;
+    r.oz = L.xlz + p.eps * nfz;
+    r.comp = static_cast<double>(p.eps) * ((static_cast<double>(nfx) * r.dx + static_cast<double>(nfy) * r.dy) +
+                                           static_cast<double>(nfz) * r.dz);
+    r.prev = b.id;
+    r.meta = (r.meta & ~0xff) | N | (back ? 128 : 0);
+    L.D = (r.kdo + r.P) + dotk(kv, L.xlx, L.xly, L.xlz);
+    L.flags = SBR_REC_VALID | (back ? SBR_REC_BACK_LAST : 0);
+    return N < p.bmax;
+}
+
+__device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Best &b, const Last &L)
+{
+    const int N = r.meta & 127;
+    if (p.user_sink) {
+        const sbr_hits &h = p.hits;
+        const int64_t e = r.id;
+        if (h.n_bounce) h.n_bounce[e] = N;
+        if (h.tri_first) h.tri_first[e] = r.first;
+        if (h.tri_last) h.tri_last[e] = b.id;
+        if (h.flags) h.flags[e] = L.flags;
+        if (h.path) h.path[e] = r.P;
+        if (h.D) h.D[e] = L.D;
+        if (h.d_last) { h.d_last[3 * e] = L.dlx; h.d_last[3 * e + 1] = L.dly; h.d_last[3 * e + 2] = L.dlz; }
+        if (h.x_last) { h.x_last[3 * e] = L.xlx; h.x_last[3 * e + 1] = L.xly; h.x_last[3 * e + 2] = L.xlz; }
+        if (h.eH_last) { h.eH_last[3 * e] = L.hlx; h.eH_last[3 * e + 1] = L.hly; h.eH_last[3 * e + 2] = L.hlz; }
+        if (h.eV_last) { h.eV_last[3 * e] = L.vlx; h.eV_last[3 * e + 1] = L.vly; h.eV_last[3 * e + 2] = L.vlz; }
+        if (h.tri_path) h.tri_path[e * p.bmax + (N - 1)] = b.id;
+    } else {
+        const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
+        p.rec.r0[e] = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(b.id));
+        p.rec.r1[e] = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
+        p.rec.r2[e] = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (L.flags << 8)));
+        p.rec.D[e] = L.D;
+    }
+}
+
+// A ray whose first query missed: an empty record.
+__device__ __forceinline__ void sink_miss(const Params &p, const Ray &r)
+{
+    if (p.user_sink) {
+        const sbr_hits &h = p.hits;
+        const int64_t e = r.id;
+        if (h.n_bounce) h.n_bounce[e] = 0;
+        if (h.tri_first) h.tri_first[e] = -1;
+        if (h.tri_last) h.tri_last[e] = -1;
+        if (h.flags) h.flags[e] = 0;
+        if (h.path) h.path[e] = 0.0;
+        if (h.D) h.D[e] = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (h.d_last) h.d_last[3 * e + a] = 0.f;
+            if (h.x_last) h.x_last[3 * e + a] = 0.f;
+            if (h.eH_last) h.eH_last[3 * e + a] = 0.f;
+            if (h.eV_last) h.eV_last[3 * e + a] = 0.f;
+        }
+    } else {
+        const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
+        p.rec.r2[e] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
+    }
+}
+
+__device__ __forceinline__ void flag_trapped(const Params &p, const Ray &r)
+{
+    const int N = r.meta & 127;
+    if (p.user_sink) {
+        if (p.hits.flags) p.hits.flags[r.id] = (p.hits.flags[r.id] | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
+    } else {
+        const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
+        float4 v = p.rec.r2[e];
+        const int fl = ((__float_as_int(v.w) >> 8) | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
+        v.w = __int_as_float(N | (fl << 8));
+        p.rec.r2[e] = v;
+    }
+}
+
+__device__ __forceinline__ const double *kvec(const Params &p, const Ray &r, double *kloc)
+{
+    if (p.user_sink) {
+        kloc[0] = p.kx;
+        kloc[1] = p.ky;
+        kloc[2] = p.kz;
+        return kloc;
+    }
+    return p.plans[r.meta >> 8].k;
+}
+
+// Per-block counters in LDS, flushed with one global atomic each at the end.
+struct BlockStats {
+    unsigned int queries, trapped;
+    unsigned int hits[SBR_MAX_BOUNCES + 1];
+};
+
+__device__ __forceinline__ void flush_stats(const Params &p, BlockStats &bs)
+{
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t == 0 && bs.queries) atomicAdd(p.stat + 0, static_cast<unsigned long long>(bs.queries));
+    if (t == 1 && bs.trapped) atomicAdd(p.stat + 1, static_cast<unsigned long long>(bs.trapped));
+    if (t >= 8 && t <= 8 + SBR_MAX_BOUNCES && bs.hits[t - 8])
+        atomicAdd(p.stat + t, static_cast<unsigned long long>(bs.hits[t - 8]));
+}
+
+__device__ __forceinline__ void init_stats(BlockStats &bs)
+{
+    const int t = threadIdx.x;
+    if (t == 0) {
+        bs.queries = 0;
+        bs.trapped = 0;
+    }
+    if (t <= SBR_MAX_BOUNCES) bs.hits[t] = 0;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// STREAM schedule
+// ---------------------------------------------------------------------------
+template <int SRC>  // 0 = angle grid, 1 = caller rays
+__global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Params p)
 {
     __shared__ int lds_stack[kStackLds * kBlock];
+    __shared__ BlockStats bs;
+    init_stats(bs);
     int *lst = lds_stack + threadIdx.x;
     const int64_t gstride = static_cast<int64_t>(gridDim.x) * kBlock;
     int32_t *gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int xcd = blockIdx.x & 7;
-    const bool drop_trapped = (p.flags & SBR_OPT_DROP_TRAPPED) != 0;
-    const bool paper_path = (p.flags & SBR_OPT_PAPER_PATH) != 0;
-    int64_t n_tiles = p.n_tiles;
-    uint32_t n_in = 0;
-    if (SRC == 2) {
-        n_in = *p.qin_cnt;
-        n_tiles = (static_cast<int64_t>(n_in) + kTileRays - 1) / kTileRays;
-    }
-    unsigned long long my_queries = 0, my_hits = 0, my_trapped = 0;
+    const uint64_t lt = lanemask_lt();
+    const int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
+    int64_t pos = 0, end = 0;  // wave-uniform: unused positions [pos, end) of the claimed batch
+    bool src_done = false;
+    bool has = false;
+    Ray r;
 
     for (;;) {
-        int64_t tile = 0;
-        if (lane == 0) tile = fetch_tile(p.ctr, n_tiles, xcd);
-        tile = __shfl(tile, 0);
-        if (tile < 0) break;
+        // ---- refill: idle lanes, ranked by a ballot prefix count, take the next positions
+        for (;;) {
+            const uint64_t idle = __ballot(!has);
+            if (idle == 0 || src_done) break;
+            if (pos >= end) {
+                int64_t u = -1, e = 0;
+                if (lane == 0) u = claim(p.ctr, n_units, xcd, kClaimTiles, &e);
+                u = __shfl(u, 0);
+                e = __shfl(e, 0);
+                if (u < 0) {
+                    src_done = true;
+                    break;
+                }
+                pos = u * kTileRays;
+                end = e * kTileRays;
+            }
+            const int64_t q = pos + static_cast<int64_t>(__popcll(idle & lt));
+            if (!has && q < end) has = SRC == 0 ? grid_ray(p, q, r) : user_ray(p, q, r);
+            pos = min(pos + static_cast<int64_t>(__popcll(idle)), end);
+        }
+        if (__ballot(has) == 0) break;
 
+        // ---- one bounce for every lane holding a ray
+        Best b;
+        b.slot = -1;
+        if (has) b = closest(p, r, lst, gst, gstride);
+        if (has) atomicAdd(&bs.queries, 1u);
+        if (has) {
+            if (b.slot >= 0) {
+                double kloc[3];
+                const double *kv = kvec(p, r, kloc);
+                Last L;
+                const bool cont = bounce(p, r, b, kv, L);
+                atomicAdd(&bs.hits[r.meta & 127], 1u);
+                sink_hit(p, r, b, L);
+                if (!cont) {
+                    if (p.flags & SBR_OPT_DROP_TRAPPED) {
+                        const Best b2 = closest(p, r, lst, gst, gstride);
+                        atomicAdd(&bs.queries, 1u);
+                        if (b2.slot >= 0) {
+                            flag_trapped(p, r);
+                            atomicAdd(&bs.trapped, 1u);
+                        }
+                    }
+                    has = false;
+                }
+            } else {
+                if ((r.meta & 127) == 0) sink_miss(p, r);
+                has = false;
+            }
+        }
+    }
+    flush_stats(p, bs);
+}
+
+// ---------------------------------------------------------------------------
+// WAVEFRONT schedule (one launch per bounce, queue between launches)
+// ---------------------------------------------------------------------------
+template <int SRC>  // 0 = angle grid, 1 = caller rays, 2 = queue
+__global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Params p)
+{
+    __shared__ int lds_stack[kStackLds * kBlock];
+    __shared__ BlockStats bs;
+    init_stats(bs);
+    int *lst = lds_stack + threadIdx.x;
+    const int64_t gstride = static_cast<int64_t>(gridDim.x) * kBlock;
+    int32_t *gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int xcd = blockIdx.x & 7;
+    int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
+    int64_t n_in = 0;
+    if (SRC == 2) {
+        n_in = *p.qin_cnt;
+        n_units = (n_in + kTileRays - 1) / kTileRays;
+    }
+    int64_t tile = 0, tend = 0;  // wave-uniform claimed batch of tiles
+    for (;;) {
+        if (tile >= tend) {
+            int64_t u = -1, e = 0;
+            if (lane == 0) u = claim(p.ctr, n_units, xcd, kClaimTiles, &e);
+            u = __shfl(u, 0);
+            e = __shfl(e, 0);
+            if (u < 0) break;
+            tile = u;
+            tend = e;
+        }
+        const int64_t q = tile * kTileRays + lane;
+        ++tile;
         Ray r;
         bool active;
-        int slot = 0;
-        const double *kv = nullptr;
-        double kloc[3];
         if (SRC == 0) {
-            int lo = 0, hi = p.n_angles;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (p.tile_base[mid] <= tile) lo = mid;
-                else hi = mid;
-            }
-            slot = lo;
-            const AnglePlan &pl = p.plans[slot];
-            const int64_t t = tile - pl.tile_base;
-            const int i = static_cast<int>(t % pl.tu) * 8 + (lane & 7);
-            const int j = static_cast<int>(t / pl.tu) * 8 + (lane >> 3);
-            active = i < pl.nu && j < pl.nv;
-            const double ui = pl.uc + ((static_cast<double>(i) + 0.5) - 0.5 * static_cast<double>(pl.nu)) * pl.ds;
-            const double vj = pl.vc + ((static_cast<double>(j) + 0.5) - 0.5 * static_cast<double>(pl.nv)) * pl.ds;
-            r.ox = static_cast<float>((ui * pl.u[0] + vj * pl.v[0]) + pl.s0 * pl.k[0]);
-            r.oy = static_cast<float>((ui * pl.u[1] + vj * pl.v[1]) + pl.s0 * pl.k[1]);
-            r.oz = static_cast<float>((ui * pl.u[2] + vj * pl.v[2]) + pl.s0 * pl.k[2]);
-            r.dx = pl.d32[0];
-            r.dy = pl.d32[1];
-            r.dz = pl.d32[2];
-            r.hx = pl.eH32[0];
-            r.hy = pl.eH32[1];
-            r.hz = pl.eH32[2];
-            r.vx = pl.eV32[0];
-            r.vy = pl.eV32[1];
-            r.vz = pl.eV32[2];
-            r.prev = -1;
-            r.first = -1;
-            r.id = j * pl.nu + i;
-            r.meta = slot << 8;
-            r.P = 0.0;
-            r.comp = 0.0;
-            kv = pl.k;
-            r.kdo = dotk(p, kv, r.ox, r.oy, r.oz);
-            r.rec = -1;
+            active = grid_ray(p, q, r);
         } else if (SRC == 1) {
-            const int64_t e = tile * kTileRays + lane;
-            active = e < p.n_rays;
-            const int64_t ee = active ? e : 0;
-            r.ox = p.uo[3 * ee];
-            r.oy = p.uo[3 * ee + 1];
-            r.oz = p.uo[3 * ee + 2];
-            r.dx = p.ud[3 * ee];
-            r.dy = p.ud[3 * ee + 1];
-            r.dz = p.ud[3 * ee + 2];
-            r.hx = p.uh[3 * ee];
-            r.hy = p.uh[3 * ee + 1];
-            r.hz = p.uh[3 * ee + 2];
-            r.vx = p.uv[3 * ee];
-            r.vy = p.uv[3 * ee + 1];
-            r.vz = p.uv[3 * ee + 2];
-            r.prev = -1;
-            r.first = -1;
-            r.id = static_cast<int>(ee);
-            r.meta = 0;
-            r.P = 0.0;
-            r.comp = 0.0;
-            kloc[0] = p.kx;
-            kloc[1] = p.ky;
-            kloc[2] = p.kz;
-            kv = kloc;
-            r.kdo = dotk(p, kv, r.ox, r.oy, r.oz);
-            r.rec = -1;
+            active = user_ray(p, q, r);
         } else {
-            const int64_t e = tile * kTileRays + lane;
-            active = e < static_cast<int64_t>(n_in);
-            const int64_t ee = active ? e : 0;
-            const float4 s0 = p.qin.s0[ee], s1 = p.qin.s1[ee], s2 = p.qin.s2[ee], s3 = p.qin.s3[ee];
-            const double2 s4 = p.qin.s4[ee], s5 = p.qin.s5[ee];
+            active = q < n_in;
+            const int64_t e = active ? q : 0;
+            const float4 s0 = p.qin.s0[e], s1 = p.qin.s1[e], s2 = p.qin.s2[e], s3 = p.qin.s3[e];
+            const double2 s4 = p.qin.s4[e], s5 = p.qin.s5[e];
             r.ox = s0.x;
             r.oy = s0.y;
             r.oz = s0.z;
@@ -335,163 +615,43 @@ __global__ __launch_bounds__(kBlock) void k_trace(Params p)
             r.P = s4.x;
             r.comp = s4.y;
             r.kdo = s5.x;
-            r.rec = static_cast<int>(__double_as_longlong(s5.y));
-            slot = r.meta >> 8;
-            if (p.user_sink) {
-                kloc[0] = p.kx;
-                kloc[1] = p.ky;
-                kloc[2] = p.kz;
-                kv = kloc;
-            } else {
-                kv = p.plans[slot].k;
-            }
         }
-
-        // ---- closest hit
         Best b;
         b.slot = -1;
         if (active) b = closest(p, r, lst, gst, gstride);
-        const bool hit = active && b.slot >= 0;
-        my_queries += active ? 1 : 0;
-        my_hits += hit ? 1 : 0;
-
-        // ---- bounce update (Algorithm 2) and record of the last hit
-        int N = r.meta & 127;
+        if (active) atomicAdd(&bs.queries, 1u);
         bool cont = false;
-        int flags = 0;
-        float dlx = 0, dly = 0, dlz = 0, xlx = 0, xly = 0, xlz = 0;
-        float hlx = 0, hly = 0, hlz = 0, vlx = 0, vly = 0, vlz = 0;
-        double D = 0.0;
-        if (hit) {
-            const float t = b.t;
-            xlx = r.ox + t * r.dx;
-            xly = r.oy + t * r.dy;
-            xlz = r.oz + t * r.dz;
-            r.P = r.P + static_cast<double>(t);
-            if (N >= 1 && !paper_path) r.P = r.P + r.comp;
-            N += 1;
-            if (N == 1) r.first = b.id;
-            dlx = r.dx;
-            dly = r.dy;
-            dlz = r.dz;
-            hlx = r.hx;
-            hly = r.hy;
-            hlz = r.hz;
-            vlx = r.vx;
-            vly = r.vy;
-            vlz = r.vz;
-            const float4 n = p.nrm[b.slot];
-            const float dn = (r.dx * n.x + r.dy * n.y) + r.dz * n.z;
-            const bool back = !(dn < 0.0f);
-            const float nfx = back ? -n.x : n.x, nfy = back ? -n.y : n.y, nfz = back ? -n.z : n.z;
-            const float s = 2.0f * dn;
-            r.dx = r.dx - s * n.x;
-            r.dy = r.dy - s * n.y;
-            r.dz = r.dz - s * n.z;
-            const float cH = 2.0f * ((n.x * r.hx + n.y * r.hy) + n.z * r.hz);
-            const float cV = 2.0f * ((n.x * r.vx + n.y * r.vy) + n.z * r.vz);
-            r.hx = cH * n.x - r.hx;
-            r.hy = cH * n.y - r.hy;
-            r.hz = cH * n.z - r.hz;
-            r.vx = cV * n.x - r.vx;
-            r.vy = cV * n.y - r.vy;
-            r.vz = cV * n.z - r.vz;
-            r.ox = xlx + p.eps * nfx;
-            r.oy = xly + p.eps * nfy;
-            r.oz = xlz + p.eps * nfz;
-            r.comp = static_cast<double>(p.eps) *
-                     ((static_cast<double>(nfx) * r.dx + static_cast<double>(nfy) * r.dy) +
-                      static_cast<double>(nfz) * r.dz);
-            r.prev = b.id;
-            r.meta = (r.meta & ~0xff) | N | (back ? 128 : 0);
-            D = (r.kdo + r.P) + dotk(p, kv, xlx, xly, xlz);
-            flags = SBR_REC_VALID | (back ? SBR_REC_BACK_LAST : 0);
-            cont = N < p.bmax;
-            if (!cont && drop_trapped) {
-                const Best b2 = closest(p, r, lst, gst, gstride);
-                my_queries += 1;
-                if (b2.slot >= 0) {
-                    flags = (flags | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
-                    my_trapped += 1;
-                }
-            }
-        }
-
-        // ---- record sink
-        if (p.user_sink) {
-            const sbr_hits &h = p.hits;
-            const int64_t e = r.id;
-            if (hit) {
-                if (h.n_bounce) h.n_bounce[e] = N;
-                if (h.tri_first) h.tri_first[e] = r.first;
-                if (h.tri_last) h.tri_last[e] = b.id;
-                if (h.flags) h.flags[e] = flags;
-                if (h.path) h.path[e] = r.P;
-                if (h.D) h.D[e] = D;
-                if (h.d_last) { h.d_last[3 * e] = dlx; h.d_last[3 * e + 1] = dly; h.d_last[3 * e + 2] = dlz; }
-                if (h.x_last) { h.x_last[3 * e] = xlx; h.x_last[3 * e + 1] = xly; h.x_last[3 * e + 2] = xlz; }
-                if (h.eH_last) { h.eH_last[3 * e] = hlx; h.eH_last[3 * e + 1] = hly; h.eH_last[3 * e + 2] = hlz; }
-                if (h.eV_last) { h.eV_last[3 * e] = vlx; h.eV_last[3 * e + 1] = vly; h.eV_last[3 * e + 2] = vlz; }
-                if (h.tri_path) h.tri_path[e * p.bmax + (N - 1)] = b.id;
-            }
-            if (SRC == 1 && active) {
-                if (!hit) {
-                    if (h.n_bounce) h.n_bounce[e] = 0;
-                    if (h.tri_first) h.tri_first[e] = -1;
-                    if (h.tri_last) h.tri_last[e] = -1;
-                    if (h.flags) h.flags[e] = 0;
-                    if (h.path) h.path[e] = 0.0;
-                    if (h.D) h.D[e] = 0.0;
-                    for (int a = 0; a < 3; ++a) {
-                        if (h.d_last) h.d_last[3 * e + a] = 0.f;
-                        if (h.x_last) h.x_last[3 * e + a] = 0.f;
-                        if (h.eH_last) h.eH_last[3 * e + a] = 0.f;
-                        if (h.eV_last) h.eV_last[3 * e + a] = 0.f;
+        if (active) {
+            if (b.slot >= 0) {
+                double kloc[3];
+                const double *kv = kvec(p, r, kloc);
+                Last L;
+                cont = bounce(p, r, b, kv, L);
+                atomicAdd(&bs.hits[r.meta & 127], 1u);
+                sink_hit(p, r, b, L);
+                if (!cont && (p.flags & SBR_OPT_DROP_TRAPPED)) {
+                    const Best b2 = closest(p, r, lst, gst, gstride);
+                    atomicAdd(&bs.queries, 1u);
+                    if (b2.slot >= 0) {
+                        flag_trapped(p, r);
+                        atomicAdd(&bs.trapped, 1u);
                     }
                 }
-                if (h.tri_path)
-                    for (int bb = (hit ? 1 : 0); bb < p.bmax; ++bb) h.tri_path[e * p.bmax + bb] = -1;
-            }
-        } else {
-            if (SRC == 0) {
-                // first hits happen only here; a tile never spans two angles
-                uint64_t m;
-                const uint32_t pos = wave_alloc(p.rec_cnt + slot, hit, m);
-                if (hit) r.rec = static_cast<int>(p.plans[slot].rec_base + pos);
-            }
-            if (hit) {
-                const int e = r.rec;
-                p.rec.r0[e] = make_float4(dlx, dly, dlz, __int_as_float(b.id));
-                p.rec.r1[e] = make_float4(hlx, hly, hlz, __int_as_float(r.first));
-                p.rec.r2[e] = make_float4(vlx, vly, vlz, __int_as_float(N | (flags << 8)));
-                p.rec.D[e] = D;
+            } else if ((r.meta & 127) == 0) {
+                sink_miss(p, r);
             }
         }
-
-        // ---- survivors to the next queue (one atomic per wave)
-        uint64_t m;
-        const uint32_t pos = wave_alloc(p.qout_cnt, cont, m);
+        const uint32_t pos = wave_alloc(p.qout_cnt, cont);
         if (cont) {
             p.qout.s0[pos] = make_float4(r.ox, r.oy, r.oz, __int_as_float(r.prev));
             p.qout.s1[pos] = make_float4(r.dx, r.dy, r.dz, __int_as_float(r.first));
             p.qout.s2[pos] = make_float4(r.hx, r.hy, r.hz, __int_as_float(r.id));
             p.qout.s3[pos] = make_float4(r.vx, r.vy, r.vz, __int_as_float(r.meta));
             p.qout.s4[pos] = make_double2(r.P, r.comp);
-            p.qout.s5[pos] = make_double2(r.kdo, __longlong_as_double(static_cast<long long>(r.rec)));
+            p.qout.s5[pos] = make_double2(r.kdo, 0.0);
         }
     }
-
-    // ---- statistics: one atomic per wave
-    for (int off = 32; off >= 1; off >>= 1) {
-        my_queries += __shfl_xor(my_queries, off);
-        my_hits += __shfl_xor(my_hits, off);
-        my_trapped += __shfl_xor(my_trapped, off);
-    }
-    if (lane == 0) {
-        if (my_queries) atomicAdd(p.stat + ST_QUERIES, my_queries);
-        if (my_hits) atomicAdd(p.stat + ST_HITS + p.bounce, my_hits);
-        if (my_trapped) atomicAdd(p.stat + ST_TRAPPED, my_trapped);
-    }
+    flush_stats(p, bs);
 }
 
 int g_blocks_cache = 0;
@@ -504,7 +664,7 @@ int trace_stack_lds() { return kStackLds; }
 int trace_persistent_blocks(sbr_ctx *ctx)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<2>, kBlock, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stream<0>, kBlock, 0) != hipSuccess || per_cu < 1)
         per_cu = 4;
     int blocks = ctx->prop.multiProcessorCount * per_cu;
     blocks = (blocks + 7) / 8 * 8;
@@ -512,7 +672,7 @@ int trace_persistent_blocks(sbr_ctx *ctx)
     return blocks;
 }
 
-static Params make_params(const TraceArgs &a, int bounce)
+static Params make_params(const TraceArgs &a, int launch)
 {
     Params p;
     p.nodes = a.bvh->nodes;
@@ -530,50 +690,37 @@ static Params make_params(const TraceArgs &a, int bounce)
     p.uh = a.rays ? a.rays->eH : nullptr;
     p.uv = a.rays ? a.rays->eV : nullptr;
     p.n_rays = a.n_rays;
-    if (a.hits) p.hits = *a.hits;
-    else p.hits = sbr_hits{};
+    p.hits = a.hits ? *a.hits : sbr_hits{};
     p.kx = a.k_hat[0];
     p.ky = a.k_hat[1];
     p.kz = a.k_hat[2];
     p.qin = a.q_in;
     p.qout = a.q_out;
-    p.qin_cnt = a.q_cnt + (bounce - 1);
-    p.qout_cnt = a.q_cnt + bounce;
+    p.qin_cnt = a.ctrs.q_cnt + (launch - 1) * kLineU32;
+    p.qout_cnt = a.ctrs.q_cnt + launch * kLineU32;
     p.rec = a.rec;
-    p.rec_cnt = a.rec_cnt;
     p.n_tiles = a.n_tiles;
-    p.ctr = reinterpret_cast<uint32_t *>(a.stat + 8 + SBR_MAX_BOUNCES + 1) + 8 * bounce;
-    p.stat = a.stat;
+    p.ctr = a.ctrs.claim + launch * 8 * kLineU32;
+    p.stat = a.ctrs.stat;
     p.spill = a.spill;
-    p.bounce = bounce;
+    p.bounce = launch;
     p.user_sink = a.hits != nullptr;
     return p;
 }
 
-int launch_trace_grid(hipStream_t s, const TraceArgs &a, int bounce)
+int launch_trace(hipStream_t s, const TraceArgs &a, int bounce)
 {
     Params p = make_params(a, bounce);
-    p.user_sink = 0;
-    k_trace<0><<<g_blocks_cache, kBlock, 0, s>>>(p);
-    SBR_HIP(hipGetLastError());
-    return SBR_OK;
-}
-
-int launch_trace_rays(hipStream_t s, const TraceArgs &a)
-{
-    Params p = make_params(a, 1);
-    p.user_sink = 1;
-    p.n_tiles = (a.n_rays + kTileRays - 1) / kTileRays;
-    k_trace<1><<<g_blocks_cache, kBlock, 0, s>>>(p);
-    SBR_HIP(hipGetLastError());
-    return SBR_OK;
-}
-
-int launch_trace_queue(hipStream_t s, const TraceArgs &a, int bounce, bool user_sink)
-{
-    Params p = make_params(a, bounce);
-    p.user_sink = user_sink ? 1 : 0;
-    k_trace<2><<<g_blocks_cache, kBlock, 0, s>>>(p);
+    const bool user = a.hits != nullptr;
+    if (a.schedule == kScheduleStream) {
+        if (user) k_stream<1><<<g_blocks_cache, kBlock, 0, s>>>(p);
+        else k_stream<0><<<g_blocks_cache, kBlock, 0, s>>>(p);
+    } else if (bounce == 1) {
+        if (user) k_wave<1><<<g_blocks_cache, kBlock, 0, s>>>(p);
+        else k_wave<0><<<g_blocks_cache, kBlock, 0, s>>>(p);
+    } else {
+        k_wave<2><<<g_blocks_cache, kBlock, 0, s>>>(p);
+    }
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

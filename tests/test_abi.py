@@ -42,7 +42,7 @@ def test_struct_sizes_match_header():
     # sizes of the option structs as laid out by a C compiler for this header
     from paper_2604_09243_amd import sbr
     assert ctypes.sizeof(sbr.Sweep) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(sbr.Stats) == 8 * (4 + 65 + 1) + 8 * 3
+    assert ctypes.sizeof(sbr.Stats) == 8 * (4 + 65 + 1) + 8 * 3 + 8 * 65 * 2
     assert ctypes.sizeof(sbr.PoDesc) == 8 + 8 * 10
     assert ctypes.sizeof(sbr.AnglePlan) == 8 * 13 + 16
 
