@@ -112,7 +112,8 @@ void sbr_destroy(sbr_ctx *ctx);
 
 typedef struct {
     uint32_t struct_size;
-    int32_t mem; /* SBR_MEM_HOST or SBR_MEM_DEVICE: where verts/tris live */
+    int32_t mem;       /* SBR_MEM_HOST or SBR_MEM_DEVICE: where verts/tris live */
+    int32_t leaf_size; /* triangles per leaf, 1..4 (subtrees that small become leaves); 0 = 4 */
 } sbr_bvh_opts;
 
 typedef struct {
@@ -194,6 +195,9 @@ typedef struct {
     double ms_bounce[SBR_MAX_BOUNCES + 1];       /* GPU time of the bounce-b launches (1-based;
                                                     SBR_OPT_WAVEFRONT only) */
     int64_t queries_bounce[SBR_MAX_BOUNCES + 1]; /* queries made by the bounce-b launches */
+    int64_t trav[6]; /* libraries built with SBR_TRACE_COUNTERS only (else 0): node visits, leaf
+                        visits, triangle tests (summed over queries), and wave-level trips of the
+                        node loop, the leaf step and the bounce loop */
 } sbr_stats;
 
 /* Traces n_rays rays (1 <= n_rays < 2^31) for up to max_bounces (1..64)
@@ -230,6 +234,21 @@ int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits *hits, int
 /* sbr_rcs_sweep -- monostatic RCS over many incidence angles                */
 /* ------------------------------------------------------------------------ */
 
+/* Launch parameters of the trace kernels (all have defaults; see
+ * sbr_default_tune).  They change speed only, never results. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t schedule;      /* 0 = streaming launch, 1 = one launch per bounce (SBR_OPT_WAVEFRONT) */
+    int32_t tile_w;        /* aperture tile of one 64-lane wave: tile_w x (64 / tile_w) rays; 4, 8, 16, 32, 64 */
+    int32_t claim_tiles;   /* tiles a wave claims per atomic, 1..64 */
+    int32_t refill_min;    /* idle lanes that trigger a refill (streaming launch), 1..64 */
+    int32_t blocks_per_cu; /* persistent blocks of 256 threads per compute unit; 0 = occupancy limit */
+} sbr_tune;
+
+/* Fills *out with the built-in defaults. */
+int sbr_default_tune(sbr_tune *out);
+
+
 typedef struct {
     uint32_t struct_size;
     const double *theta_deg; /* host [n_angles] */
@@ -243,7 +262,17 @@ typedef struct {
     double eta;              /* aperture margin of Eq. L2 (0.1 if negative) */
     int32_t mode;            /* SBR_MODE_* */
     uint32_t flags;          /* SBR_OPT_* */
+    const sbr_tune *tune;    /* NULL = defaults (SBR_OPT_WAVEFRONT still selects that schedule) */
 } sbr_sweep;
+
+/* Picks launch parameters for this BVH and sweep by timing candidates on a
+ * sample of its angles (at most 16, evenly spaced) with a coordinate search
+ * over refill_min, tile_w, claim_tiles and blocks_per_cu.  Results are cached
+ * per (device, triangle-count bucket, rays-per-angle bucket, max_bounces) in
+ * the context and, if the environment variable SBR_TUNE_CACHE names a file,
+ * in that JSON file.  sweep->tune is ignored.  Synchronises the stream.
+ * Errors: as sbr_rcs_sweep. */
+int sbr_autotune(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sweep, sbr_tune *out);
 
 /* For every angle: ray grid of Eqs. L1-L3 over the mesh bounding box (cell
  * centred, one trace at the spacing of the highest frequency), transport,

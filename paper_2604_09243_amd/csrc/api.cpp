@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -80,6 +82,7 @@ enum Slot {
     W_PARTIAL = 22,
     W_SPILL = 23,
     W_NREC = 24,
+    W_TUNE = 25,
 };
 
 static int get_queue(Workspace *ws, int first, size_t cap, RayQueue &q)
@@ -161,11 +164,10 @@ static int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std:
     return SBR_OK;
 }
 
-static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int32_t **spill)
+static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int blocks, int32_t **spill)
 {
-    const int blocks = trace_persistent_blocks(ctx);
-    const int extra = std::max(0, bvh->depth + 2 - trace_stack_lds());
-    const size_t n = static_cast<size_t>(std::max(extra, 1)) * blocks * trace_block_threads();
+    const int extra = trace_needs_spill(bvh) ? std::max(1, bvh->depth + 2 - trace_stack_lds()) : 1;
+    const size_t n = static_cast<size_t>(extra) * blocks * trace_block_threads();
     void *p;
     int rc = ctx->ws->get(W_SPILL, 4 * n, &p);
     if (rc) return rc;
@@ -173,7 +175,25 @@ static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int32_t **spill)
     return SBR_OK;
 }
 
-// rays: rays launched at bounce 1 of this chunk / call
+static sbr_tune default_tune()
+{
+    sbr_tune t;
+    t.struct_size = sizeof(sbr_tune);
+    t.schedule = kScheduleStream;
+    t.tile_w = 8;
+    t.claim_tiles = 4;
+    t.refill_min = 64;
+    t.blocks_per_cu = 0;
+    return t;
+}
+
+static int log2i(int x)
+{
+    int s = 0;
+    while ((1 << s) < x) ++s;
+    return s;
+}
+
 static void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped)
 {
     st->queries += static_cast<int64_t>(hstat[0]);
@@ -184,6 +204,7 @@ static void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax,
     if (drop_trapped) st->queries_bounce[bmax] += static_cast<int64_t>(hstat[8 + bmax]);
     // a ray is valid when it hit at bounce 1 and was not dropped as trapped
     st->valid += static_cast<int64_t>(hstat[8 + 1]) - static_cast<int64_t>(hstat[1]);
+    for (int i = 0; i < 6; ++i) st->trav[i] += static_cast<int64_t>(hstat[2 + i]);
 }
 
 }  // namespace sbr
@@ -251,12 +272,14 @@ extern "C" int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, 
     *out = nullptr;
     if (n_tris < 1 || n_tris > (int64_t(1) << 28) || n_verts < 3 || n_verts > (int64_t(1) << 31) - 1)
         return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: n_tris must be in [1, 2^28] and n_verts >= 3");
-    int mem = SBR_MEM_HOST;
+    int mem = SBR_MEM_HOST, leaf = 4;
     if (opts) {
-        if (opts->struct_size < sizeof(uint32_t) + sizeof(int32_t))
+        if (opts->struct_size < sizeof(sbr_bvh_opts))
             return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: opts->struct_size too small");
         mem = opts->mem;
+        if (opts->leaf_size != 0) leaf = opts->leaf_size;
     }
+    if (leaf < 1 || leaf > 4) return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: leaf_size must be in [0, 4]");
     if (mem != SBR_MEM_HOST && mem != SBR_MEM_DEVICE)
         return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: opts->mem must be SBR_MEM_HOST or SBR_MEM_DEVICE");
     SBR_HIP(hipSetDevice(ctx->device));
@@ -283,7 +306,8 @@ extern "C" int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, 
     b->eps = pm.eps;
     b->diag = pm.diag;
     std::memcpy(b->bbox, pm.bbox, sizeof(pm.bbox));
-    rc = build_lbvh(ctx, pm, b);
+    b->leaf_size = leaf;
+    rc = build_lbvh(ctx, pm, leaf, b);
     if (rc) {
         sbr_free_bvh(b);
         return rc;
@@ -352,7 +376,9 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
     RayQueue qa{}, qb{};
     int32_t *spill;
     const int sched = schedule_of(flags);
-    if ((rc = get_counters(ws, cn)) || (rc = get_spill(ctx, bvh, &spill))) return rc;
+    const sbr_tune tune = default_tune();
+    const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
+    if ((rc = get_counters(ws, cn)) || (rc = get_spill(ctx, bvh, blocks, &spill))) return rc;
     if (sched == kScheduleWavefront &&
         ((rc = get_queue(ws, W_QA, n_rays, qa)) || (rc = get_queue(ws, W_QB, n_rays, qb))))
         return rc;
@@ -370,6 +396,10 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
     a.bmax = max_bounces;
     a.flags = flags;
     a.schedule = sched;
+    a.tile_shift = log2i(tune.tile_w);
+    a.claim_tiles = tune.claim_tiles;
+    a.refill_min = tune.refill_min;
+    a.blocks = blocks;
     a.rays = rays;
     a.n_rays = n_rays;
     a.hits = out;
@@ -476,6 +506,13 @@ extern "C" int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits
 }
 
 // ---------------------------------------------------------------- sweep
+extern "C" int sbr_default_tune(sbr_tune *out)
+{
+    if (!out) return fail(SBR_ERR_INVALID_ARG, "sbr_default_tune: NULL argument");
+    *out = default_tune();
+    return SBR_OK;
+}
+
 extern "C" int sbr_plan_angle(const double bbox[6], double theta_deg, double phi_deg, double ds, double eta,
                               sbr_angle_plan *out)
 {
@@ -524,6 +561,16 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         return fail(SBR_ERR_SAMPLING, "sbr_rcs_sweep: ray spacing " + std::to_string(ds) +
                                           " m exceeds lambda/5 at the highest frequency");
     const double eta = sw->eta < 0.0 ? 0.1 : sw->eta;
+    sbr_tune tune = default_tune();
+    if (sw->tune) {
+        if (sw->tune->struct_size < sizeof(sbr_tune))
+            return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: tune->struct_size too small");
+        tune = *sw->tune;
+    }
+    if (sw->flags & SBR_OPT_WAVEFRONT) tune.schedule = kScheduleWavefront;
+    int rc0 = check_tune(tune);
+    if (rc0) return rc0;
+    const int tw = tune.tile_w, th = 64 / tune.tile_w;
     if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: the mesh has no non-degenerate triangle");
     SBR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
@@ -557,8 +604,8 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         p.ds = ds;
         p.nu = static_cast<int32_t>(ap.nu);
         p.nv = static_cast<int32_t>(ap.nv);
-        p.tu = static_cast<int32_t>((ap.nu + 7) / 8);
-        p.tv = static_cast<int32_t>((ap.nv + 7) / 8);
+        p.tu = static_cast<int32_t>((ap.nu + tw - 1) / tw);
+        p.tv = static_cast<int32_t>((ap.nv + th - 1) / th);
     }
     // chunks of consecutive angles holding at most kChunkRays rays (or one angle)
     std::vector<int64_t> cstart;
@@ -594,10 +641,11 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     Records rec;
     int32_t *spill;
     void *dplans, *dtile, *drecb, *dnrec, *dbasis, *dkf, *dpart, *hpin;
-    const int sched = schedule_of(sw->flags);
+    const int sched = tune.schedule;
+    const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
     const size_t tile_words = static_cast<size_t>(na + n_chunks);
     if ((rc = get_counters(ws, cn)) || (rc = get_records(ws, max_chunk_rays, rec)) ||
-        (rc = get_spill(ctx, bvh, &spill)) || (rc = ws->get(W_PLANS, sizeof(AnglePlan) * na, &dplans)) ||
+        (rc = get_spill(ctx, bvh, blocks, &spill)) || (rc = ws->get(W_PLANS, sizeof(AnglePlan) * na, &dplans)) ||
         (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) || (rc = ws->get(W_RECBASE, 8 * na, &drecb)) ||
         (rc = ws->get(W_NREC, 4 * na, &dnrec)) || (rc = ws->get(W_BASIS, 72 * na, &dbasis)) ||
         (rc = ws->get(W_KF, 8 * nf, &dkf)) ||
@@ -675,6 +723,10 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         ta.bmax = bm;
         ta.flags = sw->flags;
         ta.schedule = sched;
+        ta.tile_shift = log2i(tw);
+        ta.claim_tiles = tune.claim_tiles;
+        ta.refill_min = tune.refill_min;
+        ta.blocks = blocks;
         ta.plans = cp;
         ta.tile_base = ctile;
         ta.n_angles = m;
@@ -729,5 +781,139 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         stats->angles = na;
         stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
+    return SBR_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+
+int bucket(double x) { return x < 1.0 ? 0 : static_cast<int>(std::floor(std::log2(x))); }
+
+std::string tune_key(const sbr_ctx *ctx, const sbr_bvh *bvh, int64_t rays_per_angle, int bmax)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s|t%d|r%d|b%d", ctx->prop.gcnArchName, bucket(static_cast<double>(bvh->n_live)),
+                  bucket(static_cast<double>(rays_per_angle)), bmax);
+    return buf;
+}
+
+// One line per entry: {"key": "...", "schedule": s, "tile_w": w, "claim_tiles": c, "refill_min": r, "blocks_per_cu": b}
+bool file_lookup(const char *path, const std::string &key, sbr_tune *out)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[256];
+        sbr_tune t = default_tune();
+        if (std::sscanf(line,
+                        "{\"key\": \"%255[^\"]\", \"schedule\": %d, \"tile_w\": %d, \"claim_tiles\": %d, "
+                        "\"refill_min\": %d, \"blocks_per_cu\": %d}",
+                        k, &t.schedule, &t.tile_w, &t.claim_tiles, &t.refill_min, &t.blocks_per_cu) == 6 &&
+            key == k && check_tune(t) == SBR_OK) {
+            *out = t;  // the last matching line wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void file_store(const char *path, const std::string &key, const sbr_tune &t)
+{
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"schedule\": %d, \"tile_w\": %d, \"claim_tiles\": %d, \"refill_min\": %d, "
+                 "\"blocks_per_cu\": %d}\n",
+                 key.c_str(), t.schedule, t.tile_w, t.claim_tiles, t.refill_min, t.blocks_per_cu);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" int sbr_autotune(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sw, sbr_tune *out)
+{
+    if (!ctx || !bvh || !sw || !out) return fail(SBR_ERR_INVALID_ARG, "sbr_autotune: NULL argument");
+    if (sw->struct_size < sizeof(sbr_sweep)) return fail(SBR_ERR_INVALID_ARG, "sbr_autotune: sweep->struct_size too small");
+    if (sw->n_angles < 1 || !sw->theta_deg || !sw->phi_deg || !sw->freqs_hz || sw->n_freq < 1)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_autotune: empty sweep");
+    // sample of at most 16 evenly spaced angles, one frequency (the trace does not depend on it)
+    const int64_t na = sw->n_angles;
+    const int ns = static_cast<int>(std::min<int64_t>(na, 16));
+    std::vector<double> th(ns), ph(ns);
+    for (int i = 0; i < ns; ++i) {
+        const int64_t a = (ns == 1) ? 0 : (i * (na - 1)) / (ns - 1);
+        th[i] = sw->theta_deg[a];
+        ph[i] = sw->phi_deg[a];
+    }
+    double fmax = 0.0;
+    for (int f = 0; f < sw->n_freq; ++f) fmax = std::max(fmax, sw->freqs_hz[f]);
+    sbr_sweep sub = *sw;
+    sub.theta_deg = th.data();
+    sub.phi_deg = ph.data();
+    sub.n_angles = ns;
+    sub.freqs_hz = &fmax;
+    sub.n_freq = 1;
+    sub.flags &= ~static_cast<uint32_t>(SBR_OPT_WAVEFRONT | SBR_OPT_SYNC);
+    // rays per angle of the sample, for the cache key
+    double ds = sw->ds;
+    if (!(ds > 0.0)) ds = (sw->samples_per_lambda > 0.0 && fmax > 0.0) ? kC0 / fmax / sw->samples_per_lambda : 0.0;
+    sbr_angle_plan ap;
+    int rc = plan_angle(bvh->bbox, th[0], ph[0], ds, sw->eta < 0.0 ? 0.1 : sw->eta, ap);
+    if (rc) return rc;
+    const std::string key = tune_key(ctx, bvh, ap.nu * ap.nv, sw->max_bounces);
+    auto it = ctx->tune_cache.find(key);
+    if (it != ctx->tune_cache.end()) {
+        *out = it->second;
+        return SBR_OK;
+    }
+    const char *path = std::getenv("SBR_TUNE_CACHE");
+    if (path && *path && file_lookup(path, key, out)) {
+        ctx->tune_cache[key] = *out;
+        return SBR_OK;
+    }
+    void *dA;
+    if ((rc = ctx->ws->get(W_TUNE, 64 * static_cast<size_t>(ns), &dA))) return rc;
+    auto eval = [&](const sbr_tune &t, double *ms) -> int {
+        sbr_sweep s2 = sub;
+        s2.tune = &t;
+        double best = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+            sbr_stats st;
+            int r = sbr_rcs_sweep(ctx, bvh, &s2, static_cast<double *>(dA), nullptr, &st);
+            if (r) return r;
+            if (rep > 0) best = std::min(best, st.ms_trace);  // the first run also warms caches
+        }
+        *ms = best;
+        return SBR_OK;
+    };
+    sbr_tune cur = default_tune();
+    double cur_ms;
+    if ((rc = eval(cur, &cur_ms))) return rc;
+    const int refills[] = {1, 16, 32, 48, 64};
+    const int tiles[] = {4, 8, 16, 32};
+    const int claims[] = {1, 2, 4, 8};
+    const int blocks[] = {0, 2, 3};
+    for (int pass = 0; pass < 4; ++pass) {
+        const int *vals = pass == 0 ? refills : pass == 1 ? tiles : pass == 2 ? claims : blocks;
+        const int nv = pass == 0 ? 5 : pass == 3 ? 3 : 4;
+        for (int v = 0; v < nv; ++v) {
+            sbr_tune t = cur;
+            int &field = pass == 0 ? t.refill_min : pass == 1 ? t.tile_w : pass == 2 ? t.claim_tiles : t.blocks_per_cu;
+            if (field == vals[v]) continue;
+            field = vals[v];
+            double ms;
+            if ((rc = eval(t, &ms))) return rc;
+            if (ms < cur_ms) {
+                cur_ms = ms;
+                cur = t;
+            }
+        }
+    }
+    ctx->tune_cache[key] = cur;
+    if (path && *path) file_store(path, key, cur);
+    *out = cur;
     return SBR_OK;
 }

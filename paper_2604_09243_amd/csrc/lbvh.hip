@@ -14,7 +14,7 @@
 //      the root and stops at the first parent whose other child is not done
 //      yet (per-node arrival counter);
 //   5. relayout into preorder, with both child boxes stored in the parent.
-// Subtrees of at most kLeafMax triangles are collapsed into leaves (their
+// Subtrees of at most leaf_max triangles are collapsed into leaves (their
 // triangles are contiguous in sorted order), the leaf threshold of the
 // paper's build.  Boxes are padded so the traversal's box test never culls a
 // triangle the float32 intersection test would accept.
@@ -27,7 +27,7 @@ namespace sbr {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kLeafMax = 4;  // triangles per leaf (at most 4: the leaf code keeps 2 count bits)
+constexpr int kLeafMaxLimit = 4;  // the leaf code keeps 2 count bits
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
@@ -284,27 +284,27 @@ __global__ void k_preorder(int n_int, const int *__restrict__ parent_int, const 
     atomicMax(depth, dep + 1);
 }
 
-// Internal nodes whose range holds more than kLeafMax triangles are kept;
+// Internal nodes whose range holds more than leaf_max triangles are kept;
 // flag them at their full preorder position so a scan numbers the kept
 // nodes in preorder.
 __global__ void k_mark_kept(int n_int, const int *__restrict__ pre, const int *__restrict__ range_first,
-                            const int *__restrict__ range_last, uint32_t *__restrict__ flag)
+                            const int *__restrict__ range_last, int leaf_max, uint32_t *__restrict__ flag)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_int) return;
-    flag[pre[i]] = (range_last[i] - range_first[i] + 1 > kLeafMax) ? 1u : 0u;
+    flag[pre[i]] = (range_last[i] - range_first[i] + 1 > leaf_max) ? 1u : 0u;
 }
 
 __device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }
 
 __global__ void k_relayout(int n_int, const int *__restrict__ left, const int *__restrict__ right,
                            const int *__restrict__ pre, const uint32_t *__restrict__ newidx,
-                           const int *__restrict__ range_first, const int *__restrict__ range_last,
+                           const int *__restrict__ range_first, const int *__restrict__ range_last, int leaf_max,
                            const float *__restrict__ lbox, const float *__restrict__ nbox, BNode *__restrict__ out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_int) return;
-    if (range_last[i] - range_first[i] + 1 <= kLeafMax) return;  // inside a collapsed leaf
+    if (range_last[i] - range_first[i] + 1 <= leaf_max) return;  // inside a collapsed leaf
     const int c[2] = {left[i], right[i]};
     float bx[2][6];
     int ref[2];
@@ -315,7 +315,7 @@ __global__ void k_relayout(int n_int, const int *__restrict__ left, const int *_
             ref[s] = leaf_ref(~c[s], 1);
         } else {
             const int cnt = range_last[c[s]] - range_first[c[s]] + 1;
-            ref[s] = cnt <= kLeafMax ? leaf_ref(range_first[c[s]], cnt) : static_cast<int>(newidx[pre[c[s]]]);
+            ref[s] = cnt <= leaf_max ? leaf_ref(range_first[c[s]], cnt) : static_cast<int>(newidx[pre[c[s]]]);
         }
     }
     BNode nd;
@@ -326,7 +326,7 @@ __global__ void k_relayout(int n_int, const int *__restrict__ left, const int *_
     out[newidx[pre[i]]] = nd;
 }
 
-// Tree of at most kLeafMax triangles: one node whose two children are the
+// Tree of at most leaf_max triangles: one node whose two children are the
 // same leaf (tested twice, with the same result).
 __global__ void k_single(int n, const float *__restrict__ lbox, BNode *__restrict__ out)
 {
@@ -377,8 +377,9 @@ inline unsigned blocks_for(int64_t n, int t) { return static_cast<unsigned>((n +
 
 }  // namespace
 
-int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, sbr_bvh *bvh)
+int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
 {
+    if (leaf_max < 1 || leaf_max > kLeafMaxLimit) return fail(SBR_ERR_INVALID_ARG, "leaf size must be in [1, 4]");
     hipStream_t s = ctx->stream;
     const int64_t nt = bvh->n_tris;
     const int n = static_cast<int>(pm.live.size());
@@ -463,7 +464,7 @@ int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, sbr_bvh *bvh)
     k_leaves<<<blocks_for(n, 256), 256, 0, s>>>(n, vin, dv0, de1, de2, dn, dids, pad, bvh->tris, bvh->nrm_slot,
                                                 lbox);
     SBR_HIP(hipGetLastError());
-    if (n <= kLeafMax) {
+    if (n <= leaf_max) {
         k_single<<<1, 1, 0, s>>>(n, lbox, bvh->nodes);
         SBR_HIP(hipGetLastError());
         SBR_HIP(hipStreamSynchronize(s));
@@ -488,9 +489,9 @@ int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, sbr_bvh *bvh)
     k_karras<<<blocks_for(n_int, 256), 256, 0, s>>>(kin, n, left, right, pint, pleaf, rfirst, rlast, isleft);
     k_refit<<<blocks_for(n, 256), 256, 0, s>>>(n, left, right, pint, pleaf, lbox, nbox, arrive);
     k_preorder<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, pint, isleft, rfirst, pre, depth);
-    k_mark_kept<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, pre, rfirst, rlast, newidx);
+    k_mark_kept<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, pre, rfirst, rlast, leaf_max, newidx);
     k_scan<<<1, 1024, 0, s>>>(newidx, n_int + 1);  // newidx[n_int] becomes the kept-node count
-    k_relayout<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, left, right, pre, newidx, rfirst, rlast, lbox, nbox,
+    k_relayout<<<blocks_for(n_int, 256), 256, 0, s>>>(n_int, left, right, pre, newidx, rfirst, rlast, leaf_max, lbox, nbox,
                                                       bvh->nodes);
     SBR_HIP(hipGetLastError());
     int hdepth = 0;

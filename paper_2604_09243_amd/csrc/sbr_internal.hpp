@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,7 @@ struct AnglePlan {
     double k[3], u[3], v[3];   // k = wave direction, u = phi_hat, v = theta_hat
     double uc, vc, s0, ds;
     float d32[3], eH32[3], eV32[3];
-    int32_t nu, nv, tu, tv;    // rays and 8x8 tiles along u and v
+    int32_t nu, nv, tu, tv;    // rays, and tiles (tile_w x 64/tile_w rays) along u and v
     int64_t tile_base;         // first tile of this angle in the launch
     int64_t rec_base;          // first record slot of this angle
 };
@@ -96,6 +97,7 @@ struct Workspace;
 
 struct sbr_bvh {
     int device = 0;
+    int leaf_size = 4;
     int64_t n_tris = 0, n_live = 0, n_nodes = 0;
     int32_t depth = 0;
     float eps = 0.f;
@@ -114,6 +116,7 @@ struct sbr_ctx {
     hipStream_t stream = nullptr;
     sbr::Workspace *ws = nullptr;
     hipDeviceProp_t prop;
+    std::map<std::string, sbr_tune> tune_cache;  // autotuned launch parameters
 };
 
 namespace sbr {
@@ -149,7 +152,7 @@ int plan_angle(const double bbox[6], double theta_deg, double phi_deg, double ds
                sbr_angle_plan &out);
 
 // lbvh.hip: builds nodes/tris on the device from a prepared mesh.
-int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, sbr_bvh *bvh);
+int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
 
 // trace.hip
 struct TraceArgs {
@@ -157,6 +160,8 @@ struct TraceArgs {
     int bmax;
     uint32_t flags;
     int schedule;             // kScheduleStream or kScheduleWavefront
+    int tile_shift;           // log2 of the tile width
+    int claim_tiles, refill_min, blocks;
     // grid source (sweep)
     const AnglePlan *plans;   // device [n_angles]
     const int64_t *tile_base; // device [n_angles + 1]
@@ -175,9 +180,11 @@ struct TraceArgs {
 };
 // bounce = 1 for the stream schedule (one launch does every bounce)
 int launch_trace(hipStream_t s, const TraceArgs &a, int bounce);
-int trace_persistent_blocks(sbr_ctx *ctx);
+int trace_persistent_blocks(sbr_ctx *ctx, int blocks_per_cu);  // 0 = occupancy limit
+int check_tune(const sbr_tune &t);
 int trace_block_threads();
-int trace_stack_lds();
+int trace_stack_lds();  // LDS entries of the stack when it spills
+bool trace_needs_spill(const sbr_bvh *bvh);
 
 // po.hip
 struct PoArgs {

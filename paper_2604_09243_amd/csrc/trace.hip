@@ -17,7 +17,7 @@
 //   + prefix popcount); the next launch reads that queue.
 //
 // Rays of the incidence-angle grid (Eqs. L1-L3) are generated in-register:
-// a 64-ray tile is an 8x8 patch of the aperture.  Every hit overwrites the
+// a 64-ray tile is a tile_w x (64 / tile_w) patch of the aperture.  Every hit overwrites the
 // ray's record (one slot per ray), so a terminated ray's record holds its
 // last hit; a ray that never hits writes an empty record.
 //
@@ -40,11 +40,19 @@ namespace sbr {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kStackLds = 16;
+constexpr int kStackLds = 32;     // LDS stack entries per lane
+constexpr int kStackSpillLds = 16;  // LDS part of the stack when deeper trees spill to global memory
 constexpr int kTileRays = 64;
-constexpr int kClaimTiles = 4;
 #ifndef SBR_TRACE_WAVES_PER_SIMD
 #define SBR_TRACE_WAVES_PER_SIMD 1  // occupancy floor handed to the register allocator
+#endif
+// Build with -DSBR_TRACE_COUNTERS to count traversal work into stat[2..7]:
+// lane node visits, lane leaf visits, lane triangle tests, and wave-level
+// trips of the internal-node loop, of the leaf step and of the bounce loop.
+#ifdef SBR_TRACE_COUNTERS
+#define SBR_COUNT(stmt) stmt
+#else
+#define SBR_COUNT(stmt)
 #endif
 
 struct Params {
@@ -76,6 +84,7 @@ struct Params {
     int32_t *spill;
     int bounce;
     int user_sink;
+    int tile_shift, claim_tiles, refill_min;  // launch parameters (sbr_tune)
 };
 
 struct Ray {
@@ -89,7 +98,15 @@ struct Best {
     float t;
     int id;
     int slot;
+#ifdef SBR_TRACE_COUNTERS
+    unsigned nodes, leaves, tris, wnode, wleaf;
+#endif
 };
+
+__device__ __forceinline__ bool wave_leader()
+{
+    return static_cast<int>(threadIdx.x & 63) == __ffsll(static_cast<unsigned long long>(__ballot(1))) - 1;
+}
 
 __device__ __forceinline__ bool tri_test(const BTri &tr, const Ray &r, float &t_out)
 {
@@ -126,14 +143,57 @@ __device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r,
 
 constexpr int kEmpty = INT_MIN;  // never a valid node or leaf reference
 
-// Closest hit of ray r, skipping triangle r.prev.  lst: this lane's LDS stack
-// column (stride kBlock); gst: its spill column (stride gstride).
-__device__ Best closest(const Params &p, const Ray &r, int *lst, int32_t *gst, int64_t gstride)
+// Stack of node/leaf references: kStackLds entries in LDS when the tree is
+// shallow enough (SPILL = false), otherwise kStackSpillLds in LDS and the
+// rest in a global spill array.
+template <bool SPILL>
+struct Stack {
+    int *lst;        // this lane's LDS column (stride kBlock)
+    int32_t *gst;    // this lane's spill column (stride gstride)
+    int64_t gstride;
+    __device__ __forceinline__ void push(int sp, int v)
+    {
+        if (!SPILL) {
+            lst[sp * kBlock] = v;
+        } else if (sp < kStackSpillLds) {
+            lst[sp * kBlock] = v;
+        } else {
+            gst[(sp - kStackSpillLds) * gstride] = v;
+        }
+    }
+    __device__ __forceinline__ int pop(int sp)
+    {
+        if (!SPILL) return lst[sp * kBlock];
+        if (sp < kStackSpillLds) return lst[sp * kBlock];
+        return gst[(sp - kStackSpillLds) * gstride];
+    }
+};
+
+// The triangles [first, first + cnt) of a leaf, cnt <= 4, each 48-byte
+// record loaded one test ahead.
+__device__ __forceinline__ void test_leaf(const Params &p, int first, int cnt, const Ray &r, Best &b)
+{
+    SBR_COUNT(b.leaves += 1; b.tris += cnt);
+    const BTri t0 = p.tris[first];
+    BTri t1, t2, t3;
+    if (cnt > 1) t1 = p.tris[first + 1];
+    test_tri(t0, first, r, b);
+    if (cnt > 2) t2 = p.tris[first + 2];
+    if (cnt > 1) test_tri(t1, first + 1, r, b);
+    if (cnt > 3) t3 = p.tris[first + 3];
+    if (cnt > 2) test_tri(t2, first + 2, r, b);
+    if (cnt > 3) test_tri(t3, first + 3, r, b);
+}
+
+// Closest hit of ray r, skipping triangle r.prev.
+template <bool SPILL>
+__device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st)
 {
     Best b;
     b.t = INFINITY;
     b.id = 0x7fffffff;
     b.slot = -1;
+    SBR_COUNT(b.nodes = b.leaves = b.tris = b.wnode = b.wleaf = 0);
     const float tiny = 1e-20f;
     const float ddx = fabsf(r.dx) < tiny ? copysignf(tiny, r.dx) : r.dx;
     const float ddy = fabsf(r.dy) < tiny ? copysignf(tiny, r.dy) : r.dy;
@@ -145,6 +205,7 @@ __device__ Best closest(const Params &p, const Ray &r, int *lst, int32_t *gst, i
     for (;;) {
         // phase 1: descend through internal nodes until a leaf (or nothing) is next
         while (cur >= 0) {
+            SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
             const BNode n = p.nodes[cur];
             const float tlim = __builtin_fmaf(b.t, 1.000001f, p.slack);
             // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
@@ -166,8 +227,7 @@ __device__ Best closest(const Params &p, const Ray &r, int *lst, int32_t *gst, i
                     nr = n.ch.y;
                     fr = n.ch.x;
                 }
-                if (sp < kStackLds) lst[sp * kBlock] = fr;
-                else gst[(sp - kStackLds) * gstride] = fr;
+                st.push(sp, fr);
                 ++sp;
                 cur = nr;
             } else if (h0) {
@@ -176,25 +236,19 @@ __device__ Best closest(const Params &p, const Ray &r, int *lst, int32_t *gst, i
                 cur = n.ch.y;
             } else if (sp > 0) {
                 --sp;
-                cur = sp < kStackLds ? lst[sp * kBlock] : gst[(sp - kStackLds) * gstride];
+                cur = st.pop(sp);
             } else {
                 cur = kEmpty;
             }
         }
         if (cur == kEmpty) break;
-        // phase 2: the triangles of leaf `cur`, next record prefetched
+        // phase 2: the triangles of leaf `cur`
+        SBR_COUNT(if (wave_leader()) b.wleaf += 1);
         const int code = ~cur;
-        const int first = code >> 3, cnt = (code & 7) + 1;
-        BTri tr = p.tris[first];
-        for (int k = 0; k < cnt; ++k) {
-            BTri nx = tr;
-            if (k + 1 < cnt) nx = p.tris[first + k + 1];
-            test_tri(tr, first + k, r, b);
-            tr = nx;
-        }
+        test_leaf(p, code >> 3, (code & 7) + 1, r, b);
         if (sp > 0) {
             --sp;
-            cur = sp < kStackLds ? lst[sp * kBlock] : gst[(sp - kStackLds) * gstride];
+            cur = st.pop(sp);
         } else {
             break;
         }
@@ -202,10 +256,16 @@ __device__ Best closest(const Params &p, const Ray &r, int *lst, int32_t *gst, i
     return b;
 }
 
-__device__ __forceinline__ double dotk(const double *k, float x, float y, float z)
+struct K3 {
+    double x, y, z;
+};
+
+__device__ __forceinline__ double dotk(const K3 &k, float x, float y, float z)
 {
-    return (k[0] * static_cast<double>(x) + k[1] * static_cast<double>(y)) + k[2] * static_cast<double>(z);
+    return (k.x * static_cast<double>(x) + k.y * static_cast<double>(y)) + k.z * static_cast<double>(z);
 }
+
+__device__ __forceinline__ K3 plan_k(const AnglePlan &pl) { return K3{pl.k[0], pl.k[1], pl.k[2]}; }
 
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
@@ -245,8 +305,9 @@ __device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool want)
     return base + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
 }
 
-// Position q of the angle grid (tile = q / 64, lane of the 8x8 patch =
-// q % 64) -> a fresh ray; false if q lies outside the angle's N_u x N_v grid.
+// Position q of the angle grid (tile = q / 64, position in the tile's
+// tile_w-wide patch = q % 64) -> a fresh ray; false if q lies outside the
+// angle's N_u x N_v grid.
 __device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r)
 {
     const int64_t tile = q >> 6;
@@ -259,8 +320,9 @@ __device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r)
     }
     const AnglePlan &pl = p.plans[lo];
     const int64_t t = tile - pl.tile_base;
-    const int i = static_cast<int>(t % pl.tu) * 8 + (k & 7);
-    const int j = static_cast<int>(t / pl.tu) * 8 + (k >> 3);
+    const int tw = 1 << p.tile_shift;
+    const int i = static_cast<int>(t % pl.tu) * tw + (k & (tw - 1));
+    const int j = static_cast<int>(t / pl.tu) * (kTileRays >> p.tile_shift) + (k >> p.tile_shift);
     if (i >= pl.nu || j >= pl.nv) return false;
     const double ui = pl.uc + ((static_cast<double>(i) + 0.5) - 0.5 * static_cast<double>(pl.nu)) * pl.ds;
     const double vj = pl.vc + ((static_cast<double>(j) + 0.5) - 0.5 * static_cast<double>(pl.nv)) * pl.ds;
@@ -282,7 +344,7 @@ __device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r)
     r.meta = lo << 8;
     r.P = 0.0;
     r.comp = 0.0;
-    r.kdo = dotk(pl.k, r.ox, r.oy, r.oz);
+    r.kdo = dotk(plan_k(pl), r.ox, r.oy, r.oz);
     return true;
 }
 
@@ -308,8 +370,7 @@ __device__ __forceinline__ bool user_ray(const Params &p, int64_t e, Ray &r)
     r.meta = 0;
     r.P = 0.0;
     r.comp = 0.0;
-    const double k[3] = {p.kx, p.ky, p.kz};
-    r.kdo = dotk(k, r.ox, r.oy, r.oz);
+    r.kdo = dotk(K3{p.kx, p.ky, p.kz}, r.ox, r.oy, r.oz);
     if (p.hits.tri_path)
         for (int b = 0; b < p.bmax; ++b) p.hits.tri_path[e * p.bmax + b] = -1;
     return true;
@@ -325,7 +386,7 @@ struct Last {
 // reflection of the direction and of both field vectors, and the new origin
 // eps off the surface on the side the ray came from.  Returns whether the
 // ray has bounces left.
-__device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, const double *kv, Last &L)
+__device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, const K3 &kv, Last &L)
 {
     const float t = b.t;
     L.xlx = r.ox + t * r.dx;
@@ -437,22 +498,29 @@ __device__ __forceinline__ void flag_trapped(const Params &p, const Ray &r)
     }
 }
 
-__device__ __forceinline__ const double *kvec(const Params &p, const Ray &r, double *kloc)
+__device__ __forceinline__ K3 kvec(const Params &p, const Ray &r)
 {
-    if (p.user_sink) {
-        kloc[0] = p.kx;
-        kloc[1] = p.ky;
-        kloc[2] = p.kz;
-        return kloc;
-    }
-    return p.plans[r.meta >> 8].k;
+    if (p.user_sink) return K3{p.kx, p.ky, p.kz};
+    return plan_k(p.plans[r.meta >> 8]);
 }
 
 // Per-block counters in LDS, flushed with one global atomic each at the end.
 struct BlockStats {
     unsigned int queries, trapped;
     unsigned int hits[SBR_MAX_BOUNCES + 1];
+    unsigned long long diag[6];
 };
+
+__device__ __forceinline__ void count_query(BlockStats &bs, const Best &b)
+{
+#ifdef SBR_TRACE_COUNTERS
+    atomicAdd(&bs.diag[0], static_cast<unsigned long long>(b.nodes));
+    atomicAdd(&bs.diag[1], static_cast<unsigned long long>(b.leaves));
+    atomicAdd(&bs.diag[2], static_cast<unsigned long long>(b.tris));
+    atomicAdd(&bs.diag[3], static_cast<unsigned long long>(b.wnode));
+    atomicAdd(&bs.diag[4], static_cast<unsigned long long>(b.wleaf));
+#endif
+}
 
 __device__ __forceinline__ void flush_stats(const Params &p, BlockStats &bs)
 {
@@ -462,6 +530,9 @@ __device__ __forceinline__ void flush_stats(const Params &p, BlockStats &bs)
     if (t == 1 && bs.trapped) atomicAdd(p.stat + 1, static_cast<unsigned long long>(bs.trapped));
     if (t >= 8 && t <= 8 + SBR_MAX_BOUNCES && bs.hits[t - 8])
         atomicAdd(p.stat + t, static_cast<unsigned long long>(bs.hits[t - 8]));
+#ifdef SBR_TRACE_COUNTERS
+    if (t >= 2 && t < 8 && bs.diag[t - 2]) atomicAdd(p.stat + t, bs.diag[t - 2]);
+#endif
 }
 
 __device__ __forceinline__ void init_stats(BlockStats &bs)
@@ -472,21 +543,23 @@ __device__ __forceinline__ void init_stats(BlockStats &bs)
         bs.trapped = 0;
     }
     if (t <= SBR_MAX_BOUNCES) bs.hits[t] = 0;
+    if (t < 6) bs.diag[t] = 0;
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // STREAM schedule
 // ---------------------------------------------------------------------------
-template <int SRC>  // 0 = angle grid, 1 = caller rays
+template <int SRC, bool SPILL>  // SRC: 0 = angle grid, 1 = caller rays
 __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Params p)
 {
-    __shared__ int lds_stack[kStackLds * kBlock];
+    __shared__ int lds_stack[(SPILL ? kStackSpillLds : kStackLds) * kBlock];
     __shared__ BlockStats bs;
     init_stats(bs);
-    int *lst = lds_stack + threadIdx.x;
-    const int64_t gstride = static_cast<int64_t>(gridDim.x) * kBlock;
-    int32_t *gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    Stack<SPILL> st;
+    st.lst = lds_stack + threadIdx.x;
+    st.gstride = static_cast<int64_t>(gridDim.x) * kBlock;
+    st.gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int xcd = blockIdx.x & 7;
     const uint64_t lt = lanemask_lt();
@@ -501,9 +574,10 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
         for (;;) {
             const uint64_t idle = __ballot(!has);
             if (idle == 0 || src_done) break;
+            if (__popcll(idle) < p.refill_min && idle != __ballot(1)) break;
             if (pos >= end) {
                 int64_t u = -1, e = 0;
-                if (lane == 0) u = claim(p.ctr, n_units, xcd, kClaimTiles, &e);
+                if (lane == 0) u = claim(p.ctr, n_units, xcd, p.claim_tiles, &e);
                 u = __shfl(u, 0);
                 e = __shfl(e, 0);
                 if (u < 0) {
@@ -522,19 +596,19 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
         // ---- one bounce for every lane holding a ray
         Best b;
         b.slot = -1;
-        if (has) b = closest(p, r, lst, gst, gstride);
+        if (has) b = closest(p, r, st);
         if (has) atomicAdd(&bs.queries, 1u);
+        SBR_COUNT(if (has) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         if (has) {
             if (b.slot >= 0) {
-                double kloc[3];
-                const double *kv = kvec(p, r, kloc);
+                const K3 kv = kvec(p, r);
                 Last L;
                 const bool cont = bounce(p, r, b, kv, L);
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
                 sink_hit(p, r, b, L);
                 if (!cont) {
                     if (p.flags & SBR_OPT_DROP_TRAPPED) {
-                        const Best b2 = closest(p, r, lst, gst, gstride);
+                        const Best b2 = closest(p, r, st);
                         atomicAdd(&bs.queries, 1u);
                         if (b2.slot >= 0) {
                             flag_trapped(p, r);
@@ -555,15 +629,16 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
 // ---------------------------------------------------------------------------
 // WAVEFRONT schedule (one launch per bounce, queue between launches)
 // ---------------------------------------------------------------------------
-template <int SRC>  // 0 = angle grid, 1 = caller rays, 2 = queue
+template <int SRC, bool SPILL>  // SRC: 0 = angle grid, 1 = caller rays, 2 = queue
 __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Params p)
 {
-    __shared__ int lds_stack[kStackLds * kBlock];
+    __shared__ int lds_stack[(SPILL ? kStackSpillLds : kStackLds) * kBlock];
     __shared__ BlockStats bs;
     init_stats(bs);
-    int *lst = lds_stack + threadIdx.x;
-    const int64_t gstride = static_cast<int64_t>(gridDim.x) * kBlock;
-    int32_t *gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    Stack<SPILL> st;
+    st.lst = lds_stack + threadIdx.x;
+    st.gstride = static_cast<int64_t>(gridDim.x) * kBlock;
+    st.gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int xcd = blockIdx.x & 7;
     int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
@@ -576,7 +651,7 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Param
     for (;;) {
         if (tile >= tend) {
             int64_t u = -1, e = 0;
-            if (lane == 0) u = claim(p.ctr, n_units, xcd, kClaimTiles, &e);
+            if (lane == 0) u = claim(p.ctr, n_units, xcd, p.claim_tiles, &e);
             u = __shfl(u, 0);
             e = __shfl(e, 0);
             if (u < 0) break;
@@ -618,19 +693,19 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Param
         }
         Best b;
         b.slot = -1;
-        if (active) b = closest(p, r, lst, gst, gstride);
+        if (active) b = closest(p, r, st);
         if (active) atomicAdd(&bs.queries, 1u);
+        SBR_COUNT(if (active) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         bool cont = false;
         if (active) {
             if (b.slot >= 0) {
-                double kloc[3];
-                const double *kv = kvec(p, r, kloc);
+                const K3 kv = kvec(p, r);
                 Last L;
                 cont = bounce(p, r, b, kv, L);
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
                 sink_hit(p, r, b, L);
                 if (!cont && (p.flags & SBR_OPT_DROP_TRAPPED)) {
-                    const Best b2 = closest(p, r, lst, gst, gstride);
+                    const Best b2 = closest(p, r, st);
                     atomicAdd(&bs.queries, 1u);
                     if (b2.slot >= 0) {
                         flag_trapped(p, r);
@@ -654,22 +729,36 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Param
     flush_stats(p, bs);
 }
 
-int g_blocks_cache = 0;
 
 }  // namespace
 
 int trace_block_threads() { return kBlock; }
-int trace_stack_lds() { return kStackLds; }
+int trace_stack_lds() { return kStackSpillLds; }
+bool trace_needs_spill(const sbr_bvh *bvh) { return bvh->depth > kStackLds; }
 
-int trace_persistent_blocks(sbr_ctx *ctx)
+int trace_persistent_blocks(sbr_ctx *ctx, int blocks_per_cu)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stream<0>, kBlock, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stream<0, false>, kBlock, 0) != hipSuccess ||
+        per_cu < 1)
         per_cu = 4;
+    if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
     int blocks = ctx->prop.multiProcessorCount * per_cu;
     blocks = (blocks + 7) / 8 * 8;
-    g_blocks_cache = blocks;
     return blocks;
+}
+
+int check_tune(const sbr_tune &t)
+{
+    if (t.schedule != kScheduleStream && t.schedule != kScheduleWavefront)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: schedule must be 0 or 1");
+    if (t.tile_w != 4 && t.tile_w != 8 && t.tile_w != 16 && t.tile_w != 32 && t.tile_w != 64)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: tile_w must be 4, 8, 16, 32 or 64");
+    if (t.claim_tiles < 1 || t.claim_tiles > 64) return fail(SBR_ERR_INVALID_ARG, "sbr_tune: claim_tiles in [1, 64]");
+    if (t.refill_min < 1 || t.refill_min > 64) return fail(SBR_ERR_INVALID_ARG, "sbr_tune: refill_min in [1, 64]");
+    if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: blocks_per_cu in [0, 32]");
+    return SBR_OK;
 }
 
 static Params make_params(const TraceArgs &a, int launch)
@@ -705,22 +794,33 @@ static Params make_params(const TraceArgs &a, int launch)
     p.spill = a.spill;
     p.bounce = launch;
     p.user_sink = a.hits != nullptr;
+    p.tile_shift = a.tile_shift;
+    p.claim_tiles = a.claim_tiles;
+    p.refill_min = a.refill_min;
     return p;
+}
+
+template <bool SPILL>
+static void launch_trace_t(hipStream_t s, const TraceArgs &a, const Params &p, int bounce)
+{
+    const bool user = a.hits != nullptr;
+    if (a.schedule == kScheduleStream) {
+        if (user) k_stream<1, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+        else k_stream<0, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+    } else if (bounce == 1) {
+        if (user) k_wave<1, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+        else k_wave<0, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+    } else {
+        k_wave<2, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+    }
 }
 
 int launch_trace(hipStream_t s, const TraceArgs &a, int bounce)
 {
-    Params p = make_params(a, bounce);
-    const bool user = a.hits != nullptr;
-    if (a.schedule == kScheduleStream) {
-        if (user) k_stream<1><<<g_blocks_cache, kBlock, 0, s>>>(p);
-        else k_stream<0><<<g_blocks_cache, kBlock, 0, s>>>(p);
-    } else if (bounce == 1) {
-        if (user) k_wave<1><<<g_blocks_cache, kBlock, 0, s>>>(p);
-        else k_wave<0><<<g_blocks_cache, kBlock, 0, s>>>(p);
-    } else {
-        k_wave<2><<<g_blocks_cache, kBlock, 0, s>>>(p);
-    }
+    const Params p = make_params(a, bounce);
+    // the stack holds at most one entry per level of the current path
+    if (trace_needs_spill(a.bvh)) launch_trace_t<true>(s, a, p, bounce);
+    else launch_trace_t<false>(s, a, p, bounce);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

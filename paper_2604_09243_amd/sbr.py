@@ -28,7 +28,7 @@ _d3 = C.c_double * 3
 
 
 class BvhOpts(C.Structure):
-    _fields_ = [("struct_size", C.c_uint32), ("mem", C.c_int32)]
+    _fields_ = [("struct_size", C.c_uint32), ("mem", C.c_int32), ("leaf_size", C.c_int32)]
 
 
 class BvhInfo(C.Structure):
@@ -54,13 +54,13 @@ class Stats(C.Structure):
     _fields_ = [("rays", C.c_int64), ("queries", C.c_int64), ("valid", C.c_int64), ("trapped", C.c_int64),
                 ("hits", C.c_int64 * (MAX_BOUNCES + 1)), ("angles", C.c_int64), ("ms_trace", C.c_double),
                 ("ms_po", C.c_double), ("ms_total", C.c_double), ("ms_bounce", C.c_double * (MAX_BOUNCES + 1)),
-                ("queries_bounce", C.c_int64 * (MAX_BOUNCES + 1))]
+                ("queries_bounce", C.c_int64 * (MAX_BOUNCES + 1)), ("trav", C.c_int64 * 6)]
 
     def as_dict(self):
         return dict(rays=self.rays, queries=self.queries, valid=self.valid, trapped=self.trapped,
                     hits=list(self.hits), angles=self.angles, ms_trace=self.ms_trace, ms_po=self.ms_po,
                     ms_total=self.ms_total, ms_bounce=list(self.ms_bounce),
-                    queries_bounce=list(self.queries_bounce))
+                    queries_bounce=list(self.queries_bounce), trav=list(self.trav))
 
 
 class PoDesc(C.Structure):
@@ -68,11 +68,32 @@ class PoDesc(C.Structure):
                 ("phi_hat", _d3), ("dA", C.c_double)]
 
 
+class Tune(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("schedule", C.c_int32), ("tile_w", C.c_int32),
+                ("claim_tiles", C.c_int32), ("refill_min", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
+
+
+def default_tune():
+    t = Tune()
+    _check(load_library().sbr_default_tune(C.byref(t)))
+    return t
+
+
+def make_tune(**kw):
+    t = default_tune()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
 class Sweep(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("theta_deg", _vp), ("phi_deg", _vp), ("n_angles", C.c_int64),
                 ("freqs_hz", _vp), ("n_freq", C.c_int32), ("max_bounces", C.c_int32), ("ds", C.c_double),
                 ("samples_per_lambda", C.c_double), ("eta", C.c_double), ("mode", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("tune", C.POINTER(Tune))]
 
 
 class AnglePlan(C.Structure):
@@ -97,6 +118,8 @@ SIGNATURES = {
     "sbr_po_integrate": (C.c_int, [_vp, _vp, C.POINTER(Hits), C.c_int64, C.POINTER(PoDesc), _vp, C.c_int, _vp]),
     "sbr_rcs_sweep": (C.c_int, [_vp, _vp, C.POINTER(Sweep), _vp, _vp, C.POINTER(Stats)]),
     "sbr_plan_angle": (C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(AnglePlan)]),
+    "sbr_default_tune": (C.c_int, [C.POINTER(Tune)]),
+    "sbr_autotune": (C.c_int, [_vp, _vp, C.POINTER(Sweep), C.POINTER(Tune)]),
 }
 
 _lib = None
@@ -211,11 +234,11 @@ class Context:
             pass
 
     # ------------------------------------------------------------ build
-    def build_bvh(self, V, T):
+    def build_bvh(self, V, T, leaf_size=0):
         """V: [n_v, 3] float32, T: [n_t, 3] int32 (numpy host arrays or
-        torch device tensors)."""
+        torch device tensors); leaf_size 1..4 (0 = library default)."""
         torch = _torch()
-        opts = BvhOpts(C.sizeof(BvhOpts), MEM_HOST)
+        opts = BvhOpts(C.sizeof(BvhOpts), MEM_HOST, int(leaf_size))
         if isinstance(V, torch.Tensor):
             V = V.contiguous()
             T = T.contiguous()
@@ -289,8 +312,20 @@ class Context:
         return torch.view_as_complex(A)
 
     # ------------------------------------------------------------ sweep
+    def autotune(self, bvh, theta_deg, phi_deg, freqs_hz, max_bounces=5, ds=0.0, samples_per_lambda=10.0, eta=0.1,
+                 mode=MODE_VECTOR, flags=0):
+        """Launch parameters for this BVH and sweep (sbr_autotune)."""
+        th = np.ascontiguousarray(np.atleast_1d(theta_deg), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_1d(phi_deg), dtype=np.float64)
+        fr = np.ascontiguousarray(np.atleast_1d(freqs_hz), dtype=np.float64)
+        sw = Sweep(C.sizeof(Sweep), th.ctypes.data, ph.ctypes.data, len(th), fr.ctypes.data, len(fr),
+                   int(max_bounces), float(ds), float(samples_per_lambda), float(eta), int(mode), int(flags), None)
+        t = Tune()
+        _check(load_library().sbr_autotune(self.handle, bvh.handle, C.byref(sw), C.byref(t)))
+        return t
+
     def rcs_sweep(self, bvh, theta_deg, phi_deg, freqs_hz, max_bounces=5, ds=0.0, samples_per_lambda=10.0,
-                  eta=0.1, mode=MODE_VECTOR, flags=0, stats=True, out=None):
+                  eta=0.1, mode=MODE_VECTOR, flags=0, stats=True, out=None, tune=None):
         """Monostatic sweep.  Returns (A complex128 [n_angles, n_freq, 2, 2],
         sigma_dbsm float64 [n_angles, n_freq, 2, 2], stats dict or None), all
         device tensors; ``out`` may pass preallocated (A_real_view, sigma)."""
@@ -306,7 +341,8 @@ class Context:
         else:
             A, S = out
         sw = Sweep(C.sizeof(Sweep), th.ctypes.data, ph.ctypes.data, na, fr.ctypes.data, nf, int(max_bounces),
-                   float(ds), float(samples_per_lambda), float(eta), int(mode), int(flags))
+                   float(ds), float(samples_per_lambda), float(eta), int(mode), int(flags),
+                   C.pointer(tune) if tune is not None else None)
         st = Stats() if stats else None
         _check(load_library().sbr_rcs_sweep(self.handle, bvh.handle, C.byref(sw), A.data_ptr(),
                                             S.data_ptr() if S is not None else None,

@@ -41,8 +41,9 @@ def test_version_and_error_string(lib):
 def test_struct_sizes_match_header():
     # sizes of the option structs as laid out by a C compiler for this header
     from paper_2604_09243_amd import sbr
-    assert ctypes.sizeof(sbr.Sweep) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(sbr.Stats) == 8 * (4 + 65 + 1) + 8 * 3 + 8 * 65 * 2
+    assert ctypes.sizeof(sbr.Sweep) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(sbr.Tune) == 24
+    assert ctypes.sizeof(sbr.Stats) == 8 * (4 + 65 + 1) + 8 * 3 + 8 * 65 * 2 + 8 * 6
     assert ctypes.sizeof(sbr.PoDesc) == 8 + 8 * 10
     assert ctypes.sizeof(sbr.AnglePlan) == 8 * 13 + 16
 
@@ -63,6 +64,12 @@ def test_plan_matches_oracle_exactly(orc, bbox, th, ph, ds):
     assert (p["nu"], p["nv"]) == (Nu, Nv)
     assert (p["uc"], p["vc"], p["s0"]) == (uc, vc, s0)
     assert np.array_equal(p["k_hat"], k) and np.array_equal(p["theta_hat"], t) and np.array_equal(p["phi_hat"], f)
+
+
+def test_default_tune():
+    from paper_2604_09243_amd import sbr
+    t = sbr.default_tune().as_dict()
+    assert t == dict(schedule=0, tile_w=8, claim_tiles=4, refill_min=64, blocks_per_cu=0)
 
 
 def test_plan_rejects_bad_spacing():

@@ -1,0 +1,115 @@
+"""Launch parameters change speed only, and the full-size aircraft workload
+(1.5M triangles, 360 azimuths) matches the oracle on sampled outputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import sbr_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299_792_458.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2604_09243_amd import Context
+    return Context(0)
+
+
+def test_tune_and_leaf_size_do_not_change_results(torch, ctx):
+    say("case tune invariance")
+    from paper_2604_09243_amd import sbr
+    V, T = si.trihedral(1.0, 16)
+    th, ph = np.full(9, 54.74), np.linspace(0.0, 90.0, 9)
+    ref = None
+    for leaf in (1, 2, 4):
+        bvh = ctx.build_bvh(V, T, leaf_size=leaf)
+        for kw in ({}, dict(tile_w=4), dict(tile_w=32), dict(claim_tiles=1), dict(claim_tiles=16),
+                   dict(refill_min=1), dict(refill_min=33), dict(blocks_per_cu=2)):
+            A, _, st = ctx.rcs_sweep(bvh, th, ph, [10e9], 5, samples_per_lambda=10.0, tune=sbr.make_tune(**kw))
+            A = A.cpu().numpy()
+            if ref is None:
+                ref = (A, st["queries"])
+            assert np.array_equal(A, ref[0]), (leaf, kw)
+            assert st["queries"] == ref[1]
+    t = ctx.autotune(bvh, th, ph, [10e9], 5, samples_per_lambda=10.0)
+    A, _, _ = ctx.rcs_sweep(bvh, th, ph, [10e9], 5, samples_per_lambda=10.0, tune=t)
+    assert np.array_equal(A.cpu().numpy(), ref[0])
+    say("autotuned", t.as_dict())
+    with pytest.raises(sbr.SbrError):
+        ctx.rcs_sweep(bvh, th, ph, [10e9], 5, tune=sbr.make_tune(tile_w=7))
+
+
+@pytest.fixture(scope="module")
+def aircraft(torch, ctx, orc):
+    w = si.aircraft_case()
+    say("aircraft", len(w.T), "triangles")
+    bvh = ctx.build_bvh(w.V, w.T)
+    m = orc.Mesh(w.V, w.T).build_bvh()     # fast mode: bit-exact with brute force
+    return w, bvh, m
+
+
+def test_aircraft_full_sweep_sampled_parity(torch, ctx, orc, aircraft):
+    w, bvh, m = aircraft
+    say("case aircraft full sweep 360 angles")
+    A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
+                             samples_per_lambda=w.samples_per_lambda)
+    A = A.cpu().numpy()
+    assert st["angles"] == 360 and st["rays"] > 1.5e9
+    assert st["hits"][6] > 0                     # the inlets produce deep bounce chains
+    say("rays", st["rays"], "queries", st["queries"], "trace ms", st["ms_trace"])
+    idx = [0, 37, 90, 181]
+    A_o = []
+    for i in idx:
+        r = orc.rcs_angle(m, w.theta_deg[i], w.phi_deg[i], w.freqs_hz, w.samples_per_lambda, bmax=w.max_bounces,
+                          use_bvh=True)
+        A_o.append(r["A"])
+    A_o = np.array(A_o)
+    amax = np.abs(A_o).max()
+    err = np.abs(A[idx] - A_o) / np.maximum(np.abs(A_o), 1e-3 * amax)
+    assert err.max() <= 1e-4, err.max()
+    s_o = 10 * np.log10(4 * np.pi * np.abs(A_o) ** 2)
+    s_g = 10 * np.log10(4 * np.pi * np.abs(A[idx]) ** 2)
+    sel = s_o >= s_o.max() - 40
+    assert np.abs(s_o - s_g)[sel].max() <= 0.05
+    say("aircraft rel err", err.max(), "dB", np.abs(s_o - s_g)[sel].max())
+
+
+def test_aircraft_trace_bit_exact_on_sampled_rays(torch, ctx, orc, aircraft):
+    w, bvh, m = aircraft
+    say("case aircraft sampled rays")
+    rng = np.random.default_rng(3)
+    for phi in (23.0, 180.0):
+        k, tv, pv = orc.frame(90.0, phi)
+        o, d, Nu, Nv = orc.gen_rays(m.bbox, 90.0, phi, C0 / 10e9 / 8)
+        sel = rng.choice(len(o), 20000, replace=False)
+        o = o[sel]
+        r = orc.trace(m, o, d, pv, tv, k, 8, want_path=True, use_bvh=True)
+        dev = torch.device("cuda", 0)
+        n = len(o)
+        t = [torch.from_numpy(np.ascontiguousarray(np.broadcast_to(x, (n, 3)).astype(np.float32))).to(dev)
+             for x in (o, d, pv, tv)]
+        g = ctx.trace(bvh, *t, 8, k, want_path=True)
+        g = {kk: v.cpu().numpy() for kk, v in g.items()}
+        for a, b in (("nb", "n_bounce"), ("tri_first", "tri_first"), ("tri_last", "tri_last")):
+            assert np.array_equal(r[a], g[b]), (phi, a)
+        assert np.array_equal(r["tri_path"], g["tri_path"])
+        same = r["nb"] > 0
+        assert np.array_equal(r["x_last"][same], g["x_last"][same])
+        assert np.array_equal(r["D"][same], g["D"][same])
+        say("phi", phi, "hits", int(same.sum()), "max N", int(r["nb"].max()))
