@@ -15,4 +15,7 @@ Parity status per function (pins are in ``tests/test_oracle_*.py``):
   po (PAPER, VECTOR)         pinned (plate closed form, trihedral peak,
                              dihedral polarimetric sign, translation phase)
   mie                        pinned (Rayleigh and optical limits)
+  mlp (surrogate network)    pinned (finite differences of the float64
+                             network, bf16 rounding cases, hand-written
+                             special cases, Adam first-step property)
 """
