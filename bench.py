@@ -119,6 +119,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--workload", choices=("trihedral", "batch"), default="trihedral",
+                    help="trihedral: the 181-angle sweep (default); batch: the 64-scene uneven batch, one graph "
+                         "replay per step (a secondary measurement)")
+    ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch parameters first")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -146,6 +150,8 @@ def main():
     import sbr_inputs as si
     from paper_2604_09243_amd import Context
 
+    if args.workload == "batch":
+        return bench_batch(args)
     w = si.trihedral_case()
     ctx = Context(0)
 
@@ -195,7 +201,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (intersection, field) + f64 (path, phase)",
+        "dtype": "f32 (intersection, field) + f64 (path, phase, PO weights)",
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": w.name + "_181az_lambda10_b5", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
@@ -209,6 +215,53 @@ def main():
         cb, parity = cpu_baseline(w, A.cpu().numpy(), args.cpu_seconds)
         out["cpu_baseline"] = cb
         out["parity_sample"] = parity
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """64 seeded scenes (10k-500k triangles), 16-256 directions and 1-32
+    frequencies each (9,084 items, 1.7e10 rays), one graph replay per step;
+    scene set and batch planning are set-up, outside the timed steps."""
+    import torch
+    import sbr_inputs as si
+    from paper_2604_09243_amd import Context
+    t0 = time.perf_counter()
+    w = si.batch_case()
+    ctx = Context(0)
+    bvhs = [ctx.build_bvh(s.V, s.T) for s in w.scenes]
+    scn = ctx.pack_scenes(bvhs)
+    for b in bvhs:
+        b.free()
+    b = ctx.batch(scn, w.items(), w.freqs(), w.max_bounces, samples_per_lambda=w.samples_per_lambda)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    tune = b.autotune().as_dict() if args.autotune else b.info()["tune"]
+    for _ in range(args.warmup):
+        b.run(stats=False)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, st = b.run()
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = b.info()
+    out = {
+        "metric": METRIC, "value": sum(s["queries"] for s in stats) / dt, "unit": "rays*bounces/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (intersection, field) + f64 (path, phase, weights)",
+        "data": "synthetic (seeded procedural meshes)",
+        "config": {"workload": w.name + "_uneven_lambda10_b6", "scenes": len(w.scenes), "items": info["n_items"],
+                   "rows": info["n_rows"], "rays_per_step": info["rays"], "queries_per_step": stats[-1]["queries"],
+                   "triangles": int(scn.n_tris), "min_item_rays": info["min_item_rays"],
+                   "max_item_rays": info["max_item_rays"], "chunks": info["n_chunks"], "tune": tune,
+                   "mode": "VECTOR"},
+        "items_per_s": info["n_items"] * args.steps / dt,
+        "rows_per_s": info["n_rows"] * args.steps / dt,
+        "graph_ms_per_step": sum(s["ms_total"] for s in stats) / args.steps,
+        "setup_s": t_setup,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -78,6 +78,8 @@ enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
 #define SBR_OPT_SYNC 8                /* synchronise the stream before returning */
 #define SBR_OPT_WAVEFRONT 16          /* one launch per bounce with a compacted ray queue between
                                          launches (default: one streaming launch for all bounces) */
+#define SBR_OPT_NO_GRAPH 32           /* sbr_batch_run: launch eagerly instead of replaying the
+                                         captured graph (gives per-stage times in sbr_stats) */
 
 /* ------------------------------------------------------------------------ */
 /* Library and context                                                       */
@@ -124,6 +126,8 @@ typedef struct {
     float eps;            /* surface offset (1e-5 of the bounding-box diagonal) */
     double bbox[6];       /* lo xyz, hi xyz of the referenced vertices */
     int64_t device_bytes; /* device memory held by the BVH */
+    int32_t n_scenes;     /* 1, or the scene count of a set made by sbr_pack_scenes */
+    int32_t reserved;
 } sbr_bvh_info;
 
 /* verts: [n_verts][3] float32 (metres); tris: [n_tris][3] int32 vertex
@@ -243,6 +247,9 @@ typedef struct {
     int32_t claim_tiles;   /* tiles a wave claims per atomic, 1..64 */
     int32_t refill_min;    /* idle lanes that trigger a refill (streaming launch), 1..64 */
     int32_t blocks_per_cu; /* persistent blocks of 256 threads per compute unit; 0 = occupancy limit */
+    int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..26; 0 = 26.  Records of a
+                              chunk stay in device memory between its trace and its PO stage. */
+    int32_t reserved;
 } sbr_tune;
 
 /* Fills *out with the built-in defaults. */
@@ -284,6 +291,215 @@ int sbr_autotune(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sweep, sbr_t
  * nullable) implies a synchronisation. */
 int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sweep, double *A_out, double *sigma_dbsm,
                   sbr_stats *stats);
+
+/* ------------------------------------------------------------------------ */
+/* Batched sweeps: many scenes, angles and frequencies in one launch         */
+/* ------------------------------------------------------------------------ */
+
+/* Copies the BVHs bvhs[0..n_bvhs) (built with this context, 1 <= n_bvhs <=
+ * 65536, at most 2^28 triangles in total) into one multi-scene set *out;
+ * scene s of the set is bvhs[s].  Triangle ids of scene s become
+ * (sum of n_tris of the earlier scenes) + id.  The inputs stay valid and
+ * may be freed afterwards.  A set serves sbr_batch_create only (sbr_trace,
+ * sbr_po_integrate and sbr_rcs_sweep reject it); free it with
+ * sbr_free_bvh.  Synchronises the stream.  Errors: INVALID_ARG, OVERFLOW,
+ * OOM, HIP. */
+int sbr_pack_scenes(sbr_ctx *ctx, const sbr_bvh *const *bvhs, int n_bvhs, sbr_bvh **out);
+
+typedef struct {
+    int32_t scene;       /* scene index in the set (0 for a single BVH) */
+    int32_t n_freq;      /* 1 .. 4096 */
+    int64_t freq_offset; /* its frequencies are freqs_hz[freq_offset, freq_offset + n_freq) */
+    double theta_deg, phi_deg;
+    double ds;           /* ray spacing (m); <= 0: c / (f_max of the item * samples_per_lambda) */
+} sbr_batch_item;
+
+typedef struct {
+    uint32_t struct_size;
+    const sbr_batch_item *items; /* host [n_items] */
+    int64_t n_items;             /* 1 .. 2^24 */
+    const double *freqs_hz;      /* host [n_freqs_total] */
+    int64_t n_freqs_total;
+    int32_t max_bounces;         /* 1 .. 64 */
+    int32_t mode;                /* SBR_MODE_* */
+    uint32_t flags;              /* SBR_OPT_* */
+    int32_t reserved;
+    double samples_per_lambda;   /* used by items with ds <= 0 */
+    double eta;                  /* aperture margin of Eq. L2 (0.1 if negative) */
+    const sbr_tune *tune;        /* NULL = defaults */
+} sbr_batch_desc;
+
+typedef struct sbr_batch sbr_batch; /* planned batch: device buffers + captured graph */
+
+typedef struct {
+    int64_t n_items;
+    int64_t n_rows;         /* output rows = sum of n_freq over the items */
+    int64_t rays;           /* rays over all items */
+    int64_t min_item_rays, max_item_rays;
+    int32_t n_chunks;       /* trace + PO chunks of the graph */
+    int32_t graph_ready;    /* 1 once a graph has been captured for the current outputs and tune */
+    int64_t device_bytes;   /* device memory held by the batch */
+    sbr_tune tune;          /* launch parameters in use */
+} sbr_batch_info;
+
+/* Plans every item of desc against the scene set (or single BVH) `scenes`:
+ * per item, the ray grid of Eqs. L1-L3 over its scene's bounding box at its
+ * spacing, checked against lambda/5 at its highest frequency (SAMPLING
+ * unless SBR_OPT_ALLOW_UNDERSAMPLING).  Items are grouped, in order, into
+ * chunks of at most 2^chunk_log2 rays (an item larger than that is a chunk
+ * of its own); all device buffers are allocated here.  `scenes` must outlive
+ * the batch.  Errors: INVALID_ARG, SAMPLING, OVERFLOW, OOM, HIP. */
+int sbr_batch_create(sbr_ctx *ctx, const sbr_bvh *scenes, const sbr_batch_desc *desc, sbr_batch **out);
+
+int sbr_batch_get_info(const sbr_batch *batch, sbr_batch_info *out);
+
+/* Replaces the launch parameters (re-plans tiles and chunks; the next run
+ * captures a new graph).  Errors: INVALID_ARG, OOM, HIP. */
+int sbr_batch_set_tune(sbr_batch *batch, const sbr_tune *tune);
+
+/* Times candidate launch parameters on a sample of the batch's items (every
+ * k-th item, about 1/8 of its rays, at least one item) with a coordinate
+ * search over refill_min, tile_w, claim_tiles, blocks_per_cu and chunk_log2,
+ * then applies the best with sbr_batch_set_tune and returns it.
+ * Synchronises the stream.  Errors: as sbr_batch_run. */
+int sbr_batch_autotune(sbr_batch *batch, sbr_tune *out);
+
+/* Runs every item: for each chunk, clear the work counters, one trace
+ * launch for all bounces of all its items, the PO launch and the finalize
+ * launch.  The whole sequence is captured once into a HIP graph (on a
+ * private stream) and replayed on the context stream; a different A_out or
+ * sigma_dbsm, or a new tune, triggers a new capture.  A_out: device
+ * [n_rows][2][2] complex128, row = (sum of n_freq of the earlier items) + f;
+ * sigma_dbsm: device [n_rows][2][2] float64, nullable.  Results are bitwise
+ * identical to sbr_rcs_sweep of each item's scene alone and across replays.
+ * stats (host, nullable) implies a synchronisation; with a graph only
+ * ms_total (GPU time of the graph) is timed, SBR_OPT_NO_GRAPH also fills
+ * ms_trace and ms_po.  Concurrent runs of one batch are not allowed.
+ * Errors: INVALID_ARG, HIP. */
+int sbr_batch_run(sbr_batch *batch, double *A_out, double *sigma_dbsm, sbr_stats *stats);
+
+/* Frees the batch after the device has finished all its work (it does not
+ * use the context, which may already be gone).  NULL is accepted.  The
+ * context must outlive every other call on the batch. */
+void sbr_batch_destroy(sbr_batch *batch);
+
+/* ------------------------------------------------------------------------ */
+/* Learned surrogate: Fourier-feature MLP over (theta, phi, f)               */
+/* ------------------------------------------------------------------------ */
+/* The network maps one point (theta_deg, phi_deg, f_hz) to the co-polarised
+ * field (A_HH, A_VV) of the same convention as sbr_rcs_sweep:
+ *   xn = 2 (x - lo) / (hi - lo) - 1 per coordinate,
+ *   gamma = [sin(2 pi B xn), cos(2 pi B xn)]  (B: [n_ff][3] fixed, N(0, ff_sigma^2)),
+ *   h_0 = bf16(gamma), h_l = bf16(act(h_{l-1} bf16(W_l)^T + b_l)), l = 1..depth,
+ *   y = h_depth bf16(W_out)^T + b_out (4 outputs),
+ *   A_HH = out_scale (y0 + j y1), A_VV = out_scale (y2 + j y3).
+ * Products run on the matrix cores in bf16 with fp32 accumulation; master
+ * weights are fp32 and trained with Adam (b1 0.9, b2 0.999, eps 1e-8) on the
+ * mean squared error of y against targets / out_scale. */
+
+#define SBR_ACT_SILU 0
+#define SBR_ACT_RELU 1
+
+typedef struct sbr_mlp sbr_mlp;
+
+typedef struct {
+    uint32_t struct_size;
+    int32_t n_ff;       /* Fourier features, multiple of 64 in [64, 512] (64) */
+    int32_t width;      /* hidden width, multiple of 128 in [128, 1024] (256) */
+    int32_t depth;      /* hidden layers, 1..8 (4) */
+    int32_t act;        /* SBR_ACT_* */
+    int32_t reserved;
+    double ff_sigma;    /* standard deviation of the feature matrix B */
+    uint64_t seed;      /* seeds B and the initial weights */
+    double lo[3], hi[3]; /* input ranges of theta_deg, phi_deg, f_hz */
+    double out_scale;   /* output scale (e.g. the RMS of the training targets) */
+} sbr_mlp_desc;
+
+typedef struct {
+    int64_t n_params;   /* W_1, b_1, ..., W_out, b_out, row-major, fp32 */
+    int32_t n_ff, width, depth, act;
+    double out_scale;
+    int64_t adam_steps;
+    double flops_per_point; /* 2 (2 n_ff width + (depth - 1) width^2 + 4 width) */
+} sbr_mlp_info;
+
+typedef struct {
+    uint32_t struct_size;
+    int32_t epochs;
+    int32_t batch;      /* points per step, 1..65536 */
+    int32_t reserved;
+    double lr, lr_min;  /* cosine decay from lr to lr_min over all steps */
+    uint64_t seed;      /* shuffling */
+} sbr_train_opts;
+
+/* Creates a network with seeded initial weights.  Errors: INVALID_ARG, OOM,
+ * HIP. */
+int sbr_mlp_create(sbr_ctx *ctx, const sbr_mlp_desc *desc, sbr_mlp **out);
+int sbr_mlp_get_info(const sbr_mlp *mlp, sbr_mlp_info *out);
+/* Parameters as fp32 host arrays of n_params values (set resets Adam). */
+int sbr_mlp_get_params(const sbr_mlp *mlp, float *host, int64_t n);
+int sbr_mlp_set_params(sbr_mlp *mlp, const float *host, int64_t n);
+/* The feature matrix B, host [n_ff][3]. */
+int sbr_mlp_get_features(const sbr_mlp *mlp, float *host);
+int sbr_mlp_set_scale(sbr_mlp *mlp, double out_scale);
+/* pts: device [n][3] (theta_deg, phi_deg, f_hz); A_out: device [n][2]
+ * complex128 (HH, VV).  Errors: INVALID_ARG, OOM, HIP. */
+int sbr_mlp_predict(sbr_mlp *mlp, const double *pts, int64_t n, double *A_out);
+/* Gradients of the loss over n (1..65536) points: targets device [n][2]
+ * complex128; grads device [n_params] fp32; loss (host, nullable) = mean
+ * squared error.  Synchronises. */
+int sbr_mlp_gradients(sbr_mlp *mlp, const double *pts, const double *targets, int64_t n, float *grads, float *loss);
+/* Adam training over shuffled batches; loss_per_epoch host [epochs],
+ * nullable.  Synchronises once per epoch. */
+int sbr_mlp_train(sbr_mlp *mlp, const double *pts, const double *targets, int64_t n, const sbr_train_opts *opts,
+                  float *loss_per_epoch);
+void sbr_mlp_destroy(sbr_mlp *mlp);
+
+/* Dense grid fill: surrogate everywhere, SBR probes judge it per tile, SBR
+ * replaces it on every failing tile.  The grid is n_angles directions
+ * (theta_deg[a], phi_deg[a]) x n_freq frequencies, cut into tiles of
+ * tile_angles consecutive directions x tile_freqs consecutive frequencies.
+ * Each angle tile has one probe direction (probe_dir[2 t]: theta, phi) and
+ * each frequency tile probes_per_tile probe frequencies (probe_freq
+ * [tf * probes_per_tile + q]); SBR at those points (one batch, all of a
+ * probe direction's frequencies from one trace) is compared with the
+ * network; a tile falls back when, on its probes whose SBR co-polar sigma is
+ * at least (largest probe sigma - floor_db), |sigma_net - sigma_sbr| exceeds
+ * tol_db in either co-polar channel.  Fallback runs SBR for every point of
+ * the failing tiles.  Every SBR call traces at spacing ds. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t mode;               /* SBR_MODE_* of every SBR call */
+    const double *theta_deg;    /* host [n_angles] */
+    const double *phi_deg;      /* host [n_angles] */
+    int64_t n_angles;
+    const double *freqs_hz;     /* host [n_freq] */
+    int32_t n_freq;
+    int32_t tile_angles;        /* >= 1 */
+    int32_t tile_freqs;         /* >= 1 */
+    int32_t probes_per_tile;    /* >= 1 */
+    const double *probe_dir;    /* host [n_angle_tiles][2] */
+    const double *probe_freq;   /* host [n_freq_tiles * probes_per_tile] */
+    int32_t max_bounces;
+    uint32_t flags;             /* SBR_OPT_* of every SBR call */
+    double ds;                  /* ray spacing (m) */
+    double eta;
+    double tol_db;              /* 0.5 */
+    double floor_db;            /* 40 */
+} sbr_fill_desc;
+
+typedef struct {
+    int64_t tiles, fallback_tiles, points, fallback_points, probe_points;
+    double ms_predict, ms_probe, ms_check, ms_fallback, ms_total;
+    int64_t sbr_rays;           /* rays traced by the probe and fallback SBR calls */
+} sbr_fill_stats;
+
+/* A_out: device [n_angles][n_freq][2] complex128 (HH, VV).  tile_err (host
+ * [n_angle_tiles][n_freq_tiles], nullable): the largest probe error of each
+ * tile (dB); fallback (host, same shape, nullable): 1 where SBR was used.
+ * Synchronises.  Errors: as sbr_batch_create and sbr_mlp_predict. */
+int sbr_surrogate_fill(sbr_ctx *ctx, const sbr_bvh *bvh, sbr_mlp *mlp, const sbr_fill_desc *desc, double *A_out,
+                       double *tile_err, uint8_t *fallback, sbr_fill_stats *stats);
 
 /* ------------------------------------------------------------------------ */
 /* Host-only helper (no GPU): the ray grid of one angle, Eqs. L1-L3          */

@@ -76,12 +76,10 @@ enum Slot {
     W_REC = 13, // 13..16
     W_PLANS = 17,
     W_TILEBASE = 18,
-    W_RECBASE = 19,
     W_BASIS = 20,
     W_KF = 21,
     W_PARTIAL = 22,
     W_SPILL = 23,
-    W_NREC = 24,
     W_TUNE = 25,
 };
 
@@ -116,18 +114,16 @@ static int get_records(Workspace *ws, size_t cap, Records &r)
     return SBR_OK;
 }
 
-// Counter block (layout in sbr_internal.hpp), followed by one extra line
-// used as the record counter of sbr_po_integrate's packing step.
+// Counter block (layout in sbr_internal.hpp).
 struct Counters {
     CounterPtrs p;
-    uint32_t *pack_cnt;
     void *base;
     size_t bytes;
 };
 
 static int get_counters(Workspace *ws, Counters &c)
 {
-    const size_t bytes = kCounterBytes + 4 * kLineU32;
+    const size_t bytes = kCounterBytes;
     void *p;
     int rc = ws->get(W_COUNTERS, bytes, &p);
     if (rc) return rc;
@@ -135,7 +131,6 @@ static int get_counters(Workspace *ws, Counters &c)
     c.p.stat = reinterpret_cast<unsigned long long *>(b);
     c.p.q_cnt = reinterpret_cast<uint32_t *>(b + kStatBytes);
     c.p.claim = c.p.q_cnt + static_cast<size_t>(kLineU32) * kQcnt;
-    c.pack_cnt = reinterpret_cast<uint32_t *>(b + kCounterBytes);
     c.base = p;
     c.bytes = bytes;
     return SBR_OK;
@@ -146,7 +141,7 @@ static int schedule_of(uint32_t flags) { return (flags & SBR_OPT_WAVEFRONT) ? kS
 // Launches every bounce of one trace: one streaming launch, or one launch
 // per bounce with the two queues swapped in between.  ev (nullable) receives
 // an event after each launch (ev[0] must already be recorded).
-static int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector<hipEvent_t> *ev)
+int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector<hipEvent_t> *ev)
 {
     int rc;
     if (a.schedule == kScheduleStream) {
@@ -164,10 +159,15 @@ static int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std:
     return SBR_OK;
 }
 
-static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int blocks, int32_t **spill)
+size_t spill_words(const sbr_bvh *bvh, int blocks)
 {
     const int extra = trace_needs_spill(bvh) ? std::max(1, bvh->depth + 2 - trace_stack_lds()) : 1;
-    const size_t n = static_cast<size_t>(extra) * blocks * trace_block_threads();
+    return static_cast<size_t>(extra) * blocks * trace_block_threads();
+}
+
+static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int blocks, int32_t **spill)
+{
+    const size_t n = spill_words(bvh, blocks);
     void *p;
     int rc = ctx->ws->get(W_SPILL, 4 * n, &p);
     if (rc) return rc;
@@ -175,7 +175,7 @@ static int get_spill(sbr_ctx *ctx, const sbr_bvh *bvh, int blocks, int32_t **spi
     return SBR_OK;
 }
 
-static sbr_tune default_tune()
+sbr_tune default_tune()
 {
     sbr_tune t;
     t.struct_size = sizeof(sbr_tune);
@@ -184,17 +184,54 @@ static sbr_tune default_tune()
     t.claim_tiles = 4;
     t.refill_min = 64;
     t.blocks_per_cu = 0;
+    t.chunk_log2 = kDefaultChunkLog2;
+    t.reserved = 0;
     return t;
 }
 
-static int log2i(int x)
+int normalize_tune(sbr_tune &t)
+{
+    int rc = check_tune(t);
+    if (rc) return rc;
+    if (t.chunk_log2 == 0) t.chunk_log2 = kDefaultChunkLog2;
+    return SBR_OK;
+}
+
+void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p)
+{
+    const int th = 64 / tile_w;
+    for (int i = 0; i < 3; ++i) {
+        p.k[i] = ap.k_hat[i];
+        p.u[i] = ap.phi_hat[i];
+        p.v[i] = ap.theta_hat[i];
+        p.d32[i] = static_cast<float>(ap.k_hat[i]);
+        p.eH32[i] = static_cast<float>(ap.phi_hat[i]);
+        p.eV32[i] = static_cast<float>(ap.theta_hat[i]);
+    }
+    p.uc = ap.uc;
+    p.vc = ap.vc;
+    p.s0 = ap.s0;
+    p.ds = ds;
+    p.nu = static_cast<int32_t>(ap.nu);
+    p.nv = static_cast<int32_t>(ap.nv);
+    p.tu = static_cast<int32_t>((ap.nu + tile_w - 1) / tile_w);
+    p.tv = static_cast<int32_t>((ap.nv + th - 1) / th);
+    p.tile_base = 0;
+    p.rec_base = 0;
+    p.root = 0;
+    p.eps = 0.f;
+    p.slack = 0.f;
+    p.pad_ = 0;
+}
+
+int log2i(int x)
 {
     int s = 0;
     while ((1 << s) < x) ++s;
     return s;
 }
 
-static void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped)
+void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped)
 {
     st->queries += static_cast<int64_t>(hstat[0]);
     st->trapped += static_cast<int64_t>(hstat[1]);
@@ -327,6 +364,8 @@ extern "C" int sbr_bvh_get_info(const sbr_bvh *bvh, sbr_bvh_info *out)
     out->eps = bvh->eps;
     std::memcpy(out->bbox, bvh->bbox, sizeof(bvh->bbox));
     out->device_bytes = bvh->device_bytes;
+    out->n_scenes = bvh->scenes.empty() ? 1 : static_cast<int32_t>(bvh->scenes.size());
+    out->reserved = 0;
     return SBR_OK;
 }
 
@@ -368,6 +407,7 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
         for (int a = 0; a < 3; ++a) k[a] = opts->k_hat[a];
     }
     if (bvh->device != ctx->device) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: BVH lives on another device");
+    if (!bvh->scenes.empty()) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: a multi-scene set serves batches only");
     SBR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     Workspace *ws = ctx->ws;
@@ -431,7 +471,7 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
 }
 
 // ---------------------------------------------------------------- PO
-static int basis_from_desc(const sbr_po_desc *d, double out[9])
+static int basis_from_desc(const sbr_po_desc *d, double *out)
 {
     for (int a = 0; a < 3; ++a) {
         out[a] = d->k_hat[a];
@@ -461,47 +501,49 @@ extern "C" int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits
     for (int f = 0; f < n_freq; ++f)
         if (!(freqs_hz[f] > 0.0) || !std::isfinite(freqs_hz[f]))
             return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: frequencies must be positive");
+    if (!bvh->scenes.empty())
+        return fail(SBR_ERR_INVALID_ARG, "sbr_po_integrate: a multi-scene set serves batches only");
     SBR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     Workspace *ws = ctx->ws;
     int rc;
-    double basis[9];
-    if ((rc = basis_from_desc(desc, basis))) return rc;
-    Counters cn;
+    PoAngle ang{};
+    if ((rc = basis_from_desc(desc, ang.basis))) return rc;
+    ang.dA = desc->dA;
+    ang.rec_base = 0;
+    ang.rec_cnt = n_rays;
+    ang.unit_base = 0;
+    ang.part_base = 0;
+    ang.out_base = 0;
+    ang.kf_off = 0;
+    ang.n_f = n_freq;
+    const int64_t units = po_units(n_rays);
     Records rec;
-    void *pb, *pkf, *prb, *ppart, *ph;
-    const int chunks = static_cast<int>((n_rays + kPoRecsPerBlock - 1) / kPoRecsPerBlock);
-    const size_t host_bytes = 9 * 8 + 8 + 8 * static_cast<size_t>(n_freq);
-    if ((rc = get_counters(ws, cn)) || (rc = get_records(ws, n_rays, rec)) || (rc = ws->get(W_BASIS, 72, &pb)) ||
-        (rc = ws->get(W_KF, 8 * n_freq, &pkf)) || (rc = ws->get(W_RECBASE, 8, &prb)) ||
-        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(chunks) * n_freq, &ppart)) ||
+    void *pang, *pkf, *ppart, *ph;
+    const size_t host_bytes = sizeof(PoAngle) + 8 * static_cast<size_t>(n_freq);
+    if ((rc = get_records(ws, n_rays, rec)) || (rc = ws->get(W_BASIS, sizeof(PoAngle), &pang)) ||
+        (rc = ws->get(W_KF, 8 * n_freq, &pkf)) ||
+        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(units) * n_freq, &ppart)) ||
         (rc = ws->get_pinned(host_bytes, &ph)))
         return rc;
     SBR_HIP(hipStreamSynchronize(s));  // the pinned staging buffer may still feed an earlier copy
-    double *hb = static_cast<double *>(ph);
-    std::memcpy(hb, basis, 72);
-    int64_t zero = 0;
-    std::memcpy(hb + 9, &zero, 8);
-    for (int f = 0; f < n_freq; ++f) hb[10 + f] = 2.0 * kPi * freqs_hz[f] / kC0;
-    SBR_HIP(hipMemcpyAsync(pb, hb, 72, hipMemcpyHostToDevice, s));
-    SBR_HIP(hipMemcpyAsync(prb, hb + 9, 8, hipMemcpyHostToDevice, s));
-    SBR_HIP(hipMemcpyAsync(pkf, hb + 10, 8 * n_freq, hipMemcpyHostToDevice, s));
-    SBR_HIP(hipMemsetAsync(cn.base, 0, cn.bytes, s));
-    if ((rc = launch_pack_hits(s, hits, n_rays, rec, cn.pack_cnt))) return rc;
+    std::memcpy(ph, &ang, sizeof(PoAngle));
+    double *hkf = reinterpret_cast<double *>(static_cast<char *>(ph) + sizeof(PoAngle));
+    for (int f = 0; f < n_freq; ++f) hkf[f] = 2.0 * kPi * freqs_hz[f] / kC0;
+    SBR_HIP(hipMemcpyAsync(pang, ph, sizeof(PoAngle), hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(pkf, hkf, 8 * n_freq, hipMemcpyHostToDevice, s));
+    if ((rc = launch_pack_hits(s, hits, n_rays, rec))) return rc;
     PoArgs pa{};
     pa.bvh = bvh;
     pa.rec = rec;
-    pa.rec_cnt = cn.pack_cnt;
-    pa.cnt_stride = 1;
-    pa.rec_base = static_cast<const int64_t *>(prb);
+    pa.ang = static_cast<const PoAngle *>(pang);
     pa.n_angles = 1;
-    pa.chunks = chunks;
+    pa.n_units = units;
+    pa.max_nf = n_freq;
     pa.mode = desc->mode;
     pa.kf = static_cast<const double *>(pkf);
-    pa.n_freq = n_freq;
-    pa.basis = static_cast<const double *>(pb);
     pa.partial = static_cast<long long *>(ppart);
-    if ((rc = launch_po(s, pa)) || (rc = launch_po_finalize(s, pa, desc->dA, A_out, nullptr))) return rc;
+    if ((rc = launch_po(s, pa)) || (rc = launch_po_finalize(s, pa, A_out, nullptr))) return rc;
     return SBR_OK;
 }
 
@@ -522,9 +564,6 @@ extern "C" int sbr_plan_angle(const double bbox[6], double theta_deg, double phi
     return plan_angle(bbox, theta_deg, phi_deg, ds, eta, *out);
 }
 
-namespace {
-constexpr int64_t kChunkRays = int64_t(1) << 26;  // rays per sweep chunk (queues sized for it)
-}
 
 extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sw, double *A_out,
                              double *sigma_dbsm, sbr_stats *stats)
@@ -568,10 +607,12 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         tune = *sw->tune;
     }
     if (sw->flags & SBR_OPT_WAVEFRONT) tune.schedule = kScheduleWavefront;
-    int rc0 = check_tune(tune);
+    int rc0 = normalize_tune(tune);
     if (rc0) return rc0;
-    const int tw = tune.tile_w, th = 64 / tune.tile_w;
+    const int tw = tune.tile_w;
+    const int64_t chunk_cap = int64_t(1) << tune.chunk_log2;
     if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: the mesh has no non-degenerate triangle");
+    if (!bvh->scenes.empty()) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: a multi-scene set serves batches only");
     SBR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     Workspace *ws = ctx->ws;
@@ -581,86 +622,82 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
 
     // plans of every angle (host, float64)
     std::vector<AnglePlan> plans(na);
-    std::vector<double> basis(9 * na);
+    std::vector<PoAngle> pang(na);
     for (int64_t a = 0; a < na; ++a) {
         sbr_angle_plan ap;
         if ((rc = plan_angle(bvh->bbox, sw->theta_deg[a], sw->phi_deg[a], ds, eta, ap))) return rc;
         if (ap.nu * ap.nv > (int64_t(1) << 31) - 1) return fail(SBR_ERR_OVERFLOW, "sbr_rcs_sweep: too many rays per angle");
         AnglePlan &p = plans[a];
+        fill_plan(ap, ds, tw, p);
+        p.root = 0;
+        p.eps = bvh->eps;
+        p.slack = box_slack(bvh->diag);
+        PoAngle &q = pang[a];
         for (int i = 0; i < 3; ++i) {
-            p.k[i] = ap.k_hat[i];
-            p.u[i] = ap.phi_hat[i];
-            p.v[i] = ap.theta_hat[i];
-            p.d32[i] = static_cast<float>(ap.k_hat[i]);
-            p.eH32[i] = static_cast<float>(ap.phi_hat[i]);
-            p.eV32[i] = static_cast<float>(ap.theta_hat[i]);
-            basis[9 * a + i] = ap.k_hat[i];
-            basis[9 * a + 3 + i] = ap.theta_hat[i];
-            basis[9 * a + 6 + i] = ap.phi_hat[i];
+            q.basis[i] = ap.k_hat[i];
+            q.basis[3 + i] = ap.theta_hat[i];
+            q.basis[6 + i] = ap.phi_hat[i];
         }
-        p.uc = ap.uc;
-        p.vc = ap.vc;
-        p.s0 = ap.s0;
-        p.ds = ds;
-        p.nu = static_cast<int32_t>(ap.nu);
-        p.nv = static_cast<int32_t>(ap.nv);
-        p.tu = static_cast<int32_t>((ap.nu + tw - 1) / tw);
-        p.tv = static_cast<int32_t>((ap.nv + th - 1) / th);
+        q.dA = ds * ds;
+        q.rec_cnt = ap.nu * ap.nv;
+        q.out_base = a * nf;
+        q.kf_off = 0;
+        q.n_f = nf;
     }
-    // chunks of consecutive angles holding at most kChunkRays rays (or one angle)
+    // chunks of consecutive angles holding at most chunk_cap rays (or one angle)
     std::vector<int64_t> cstart;
-    int64_t max_chunk_rays = 0, max_chunk_angles = 0;
+    std::vector<int64_t> chunk_units;
+    int64_t max_chunk_rays = 0, max_chunk_units = 0;
     {
         int64_t a = 0;
         while (a < na) {
             cstart.push_back(a);
-            int64_t rays = 0, tiles = 0, b = a;
+            int64_t rays = 0, tiles = 0, units = 0, b = a;
             while (b < na) {
                 const int64_t r = int64_t(plans[b].nu) * plans[b].nv;
-                if (b > a && rays + r > kChunkRays) break;
+                if (b > a && rays + r > chunk_cap) break;
                 plans[b].tile_base = tiles;
                 plans[b].rec_base = rays;
+                pang[b].rec_base = rays;
+                pang[b].unit_base = units;
+                pang[b].part_base = units * nf;
                 tiles += int64_t(plans[b].tu) * plans[b].tv;
                 rays += r;
+                units += po_units(r);
                 ++b;
             }
+            chunk_units.push_back(units);
             max_chunk_rays = std::max(max_chunk_rays, rays);
-            max_chunk_angles = std::max(max_chunk_angles, b - a);
+            max_chunk_units = std::max(max_chunk_units, units);
             a = b;
         }
         cstart.push_back(na);
     }
     const int n_chunks = static_cast<int>(cstart.size()) - 1;
-    int64_t max_rays_angle = 0;
-    for (const auto &p : plans) max_rays_angle = std::max(max_rays_angle, int64_t(p.nu) * p.nv);
-    const int po_chunks = static_cast<int>((max_rays_angle + kPoRecsPerBlock - 1) / kPoRecsPerBlock);
 
     // device buffers
     Counters cn;
     RayQueue qa{}, qb{};
     Records rec;
     int32_t *spill;
-    void *dplans, *dtile, *drecb, *dnrec, *dbasis, *dkf, *dpart, *hpin;
+    void *dplans, *dtile, *dang, *dkf, *dpart, *hpin;
     const int sched = tune.schedule;
     const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
     const size_t tile_words = static_cast<size_t>(na + n_chunks);
     if ((rc = get_counters(ws, cn)) || (rc = get_records(ws, max_chunk_rays, rec)) ||
         (rc = get_spill(ctx, bvh, blocks, &spill)) || (rc = ws->get(W_PLANS, sizeof(AnglePlan) * na, &dplans)) ||
-        (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) || (rc = ws->get(W_RECBASE, 8 * na, &drecb)) ||
-        (rc = ws->get(W_NREC, 4 * na, &dnrec)) || (rc = ws->get(W_BASIS, 72 * na, &dbasis)) ||
+        (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) || (rc = ws->get(W_BASIS, sizeof(PoAngle) * na, &dang)) ||
         (rc = ws->get(W_KF, 8 * nf, &dkf)) ||
-        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(po_chunks) * nf * max_chunk_angles, &dpart)))
+        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(max_chunk_units) * nf, &dpart)))
         return rc;
     if (sched == kScheduleWavefront &&
         ((rc = get_queue(ws, W_QA, max_chunk_rays, qa)) || (rc = get_queue(ws, W_QB, max_chunk_rays, qb))))
         return rc;
-    // host staging (pinned): plans | tile bases | record bases | records per angle | basis | kf
+    // host staging (pinned): plans | tile bases | PO angles | kf
     const size_t off_plans = 0;
     const size_t off_tile = off_plans + sizeof(AnglePlan) * na;
-    const size_t off_recb = off_tile + 8 * tile_words;
-    const size_t off_nrec = off_recb + 8 * na;
-    const size_t off_basis = off_nrec + ((4 * na + 7) & ~size_t(7));
-    const size_t off_kf = off_basis + 72 * na;
+    const size_t off_ang = off_tile + 8 * tile_words;
+    const size_t off_kf = off_ang + sizeof(PoAngle) * na;
     const size_t host_bytes = off_kf + 8 * nf;
     if ((rc = ws->get_pinned(host_bytes, &hpin))) return rc;
     SBR_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed an earlier copy
@@ -668,28 +705,22 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     std::memcpy(hp + off_plans, plans.data(), sizeof(AnglePlan) * na);
     {
         int64_t *tb = reinterpret_cast<int64_t *>(hp + off_tile);
-        int64_t *rb = reinterpret_cast<int64_t *>(hp + off_recb);
-        uint32_t *nr = reinterpret_cast<uint32_t *>(hp + off_nrec);
         size_t w = 0;
         for (int c = 0; c < n_chunks; ++c) {
             int64_t tiles = 0;
             for (int64_t a = cstart[c]; a < cstart[c + 1]; ++a) {
                 tb[w++] = plans[a].tile_base;
                 tiles = plans[a].tile_base + int64_t(plans[a].tu) * plans[a].tv;
-                rb[a] = plans[a].rec_base;
-                nr[a] = static_cast<uint32_t>(int64_t(plans[a].nu) * plans[a].nv);
             }
             tb[w++] = tiles;
         }
     }
-    std::memcpy(hp + off_basis, basis.data(), 72 * na);
+    std::memcpy(hp + off_ang, pang.data(), sizeof(PoAngle) * na);
     double *hkf = reinterpret_cast<double *>(hp + off_kf);
     for (int f = 0; f < nf; ++f) hkf[f] = 2.0 * kPi * sw->freqs_hz[f] / kC0;
     SBR_HIP(hipMemcpyAsync(dplans, hp + off_plans, sizeof(AnglePlan) * na, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(dtile, hp + off_tile, 8 * tile_words, hipMemcpyHostToDevice, s));
-    SBR_HIP(hipMemcpyAsync(drecb, hp + off_recb, 8 * na, hipMemcpyHostToDevice, s));
-    SBR_HIP(hipMemcpyAsync(dnrec, hp + off_nrec, 4 * na, hipMemcpyHostToDevice, s));
-    SBR_HIP(hipMemcpyAsync(dbasis, hp + off_basis, 72 * na, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(dang, hp + off_ang, sizeof(PoAngle) * na, hipMemcpyHostToDevice, s));
     SBR_HIP(hipMemcpyAsync(dkf, hp + off_kf, 8 * nf, hipMemcpyHostToDevice, s));
 
     const bool want_stats = stats != nullptr;
@@ -741,19 +772,15 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         PoArgs pa{};
         pa.bvh = bvh;
         pa.rec = rec;
-        pa.rec_cnt = static_cast<const uint32_t *>(dnrec) + a0;
-        pa.cnt_stride = 1;
-        pa.rec_base = static_cast<const int64_t *>(drecb) + a0;
+        pa.ang = static_cast<const PoAngle *>(dang) + a0;
         pa.n_angles = m;
-        pa.chunks = po_chunks;
+        pa.n_units = chunk_units[c];
+        pa.max_nf = nf;
         pa.mode = sw->mode;
         pa.kf = static_cast<const double *>(dkf);
-        pa.n_freq = nf;
-        pa.basis = static_cast<const double *>(dbasis) + 9 * a0;
         pa.partial = static_cast<long long *>(dpart);
         if ((rc = launch_po(s, pa))) return rc;
-        if ((rc = launch_po_finalize(s, pa, ds * ds, A_out + a0 * nf * 8, sigma_dbsm ? sigma_dbsm + a0 * nf * 4 : nullptr)))
-            return rc;
+        if ((rc = launch_po_finalize(s, pa, A_out, sigma_dbsm))) return rc;
         if (want_stats) {
             SBR_HIP(hipEventRecord(ev[epc * c + trace_launches + 1], s));
             SBR_HIP(hipMemcpyAsync(hstat.data() + static_cast<size_t>(kStatU64) * c, cn.p.stat, 8 * kStatU64,
@@ -797,7 +824,8 @@ std::string tune_key(const sbr_ctx *ctx, const sbr_bvh *bvh, int64_t rays_per_an
     return buf;
 }
 
-// One line per entry: {"key": "...", "schedule": s, "tile_w": w, "claim_tiles": c, "refill_min": r, "blocks_per_cu": b}
+// One line per entry: {"key": "...", "schedule": s, "tile_w": w, "claim_tiles": c, "refill_min": r,
+// "blocks_per_cu": b, "chunk_log2": k}
 bool file_lookup(const char *path, const std::string &key, sbr_tune *out)
 {
     FILE *f = std::fopen(path, "r");
@@ -807,16 +835,18 @@ bool file_lookup(const char *path, const std::string &key, sbr_tune *out)
     while (std::fgets(line, sizeof(line), f)) {
         char k[256];
         sbr_tune t = default_tune();
-        if (std::sscanf(line,
-                        "{\"key\": \"%255[^\"]\", \"schedule\": %d, \"tile_w\": %d, \"claim_tiles\": %d, "
-                        "\"refill_min\": %d, \"blocks_per_cu\": %d}",
-                        k, &t.schedule, &t.tile_w, &t.claim_tiles, &t.refill_min, &t.blocks_per_cu) == 6 &&
-            key == k && check_tune(t) == SBR_OK) {
+        const int n = std::sscanf(line,
+                                  "{\"key\": \"%255[^\"]\", \"schedule\": %d, \"tile_w\": %d, \"claim_tiles\": %d, "
+                                  "\"refill_min\": %d, \"blocks_per_cu\": %d, \"chunk_log2\": %d}",
+                                  k, &t.schedule, &t.tile_w, &t.claim_tiles, &t.refill_min, &t.blocks_per_cu,
+                                  &t.chunk_log2);
+        if (n >= 6 && key == k && normalize_tune(t) == SBR_OK) {
             *out = t;  // the last matching line wins
             found = true;
         }
     }
     std::fclose(f);
+    set_error("");
     return found;
 }
 
@@ -826,16 +856,45 @@ void file_store(const char *path, const std::string &key, const sbr_tune &t)
     if (!f) return;
     std::fprintf(f,
                  "{\"key\": \"%s\", \"schedule\": %d, \"tile_w\": %d, \"claim_tiles\": %d, \"refill_min\": %d, "
-                 "\"blocks_per_cu\": %d}\n",
-                 key.c_str(), t.schedule, t.tile_w, t.claim_tiles, t.refill_min, t.blocks_per_cu);
+                 "\"blocks_per_cu\": %d, \"chunk_log2\": %d}\n",
+                 key.c_str(), t.schedule, t.tile_w, t.claim_tiles, t.refill_min, t.blocks_per_cu, t.chunk_log2);
     std::fclose(f);
 }
 
 }  // namespace
 
+namespace sbr {
+
+bool tune_lookup(sbr_ctx *ctx, const std::string &key, sbr_tune *out)
+{
+    auto it = ctx->tune_cache.find(key);
+    if (it != ctx->tune_cache.end()) {
+        *out = it->second;
+        return true;
+    }
+    const char *path = std::getenv("SBR_TUNE_CACHE");
+    if (path && *path && file_lookup(path, key, out)) {
+        ctx->tune_cache[key] = *out;
+        return true;
+    }
+    return false;
+}
+
+void tune_store(sbr_ctx *ctx, const std::string &key, const sbr_tune &t)
+{
+    ctx->tune_cache[key] = t;
+    const char *path = std::getenv("SBR_TUNE_CACHE");
+    if (path && *path) file_store(path, key, t);
+}
+
+int size_bucket(double x) { return bucket(x); }
+
+}  // namespace sbr
+
 extern "C" int sbr_autotune(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *sw, sbr_tune *out)
 {
     if (!ctx || !bvh || !sw || !out) return fail(SBR_ERR_INVALID_ARG, "sbr_autotune: NULL argument");
+    if (!bvh->scenes.empty()) return fail(SBR_ERR_INVALID_ARG, "sbr_autotune: a multi-scene set serves batches only");
     if (sw->struct_size < sizeof(sbr_sweep)) return fail(SBR_ERR_INVALID_ARG, "sbr_autotune: sweep->struct_size too small");
     if (sw->n_angles < 1 || !sw->theta_deg || !sw->phi_deg || !sw->freqs_hz || sw->n_freq < 1)
         return fail(SBR_ERR_INVALID_ARG, "sbr_autotune: empty sweep");
@@ -864,16 +923,7 @@ extern "C" int sbr_autotune(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *s
     int rc = plan_angle(bvh->bbox, th[0], ph[0], ds, sw->eta < 0.0 ? 0.1 : sw->eta, ap);
     if (rc) return rc;
     const std::string key = tune_key(ctx, bvh, ap.nu * ap.nv, sw->max_bounces);
-    auto it = ctx->tune_cache.find(key);
-    if (it != ctx->tune_cache.end()) {
-        *out = it->second;
-        return SBR_OK;
-    }
-    const char *path = std::getenv("SBR_TUNE_CACHE");
-    if (path && *path && file_lookup(path, key, out)) {
-        ctx->tune_cache[key] = *out;
-        return SBR_OK;
-    }
+    if (tune_lookup(ctx, key, out)) return SBR_OK;
     void *dA;
     if ((rc = ctx->ws->get(W_TUNE, 64 * static_cast<size_t>(ns), &dA))) return rc;
     auto eval = [&](const sbr_tune &t, double *ms) -> int {
@@ -912,8 +962,7 @@ extern "C" int sbr_autotune(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *s
             }
         }
     }
-    ctx->tune_cache[key] = cur;
-    if (path && *path) file_store(path, key, cur);
+    tune_store(ctx, key, cur);
     *out = cur;
     return SBR_OK;
 }

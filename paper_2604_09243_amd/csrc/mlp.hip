@@ -1,0 +1,476 @@
+// Fourier-feature MLP surrogate of the scattered field A(theta, phi, f):
+// training and inference kernels for gfx950.
+//
+// The dense layers are bf16 x bf16 -> fp32 matrix products on the matrix
+// cores (v_mfma_f32_32x32x16_bf16) with the bias, the activation and the
+// bf16 rounding fused into the epilogue.  One kernel computes
+// C[m][n] = sum_k A[m][k] B[n][k] with both operands stored k-contiguous,
+// which serves the forward product (A = activations, B = weights), the
+// backward product for the input gradient (B = transposed weights) and the
+// weight gradient (A = transposed output gradient, B = transposed
+// activations; the forward and backward epilogues write those transposes).
+// A 256-thread block owns a 64 x 128 tile of C; each wave owns a 32 x 64
+// sub-tile (two 32 x 32 MFMA blocks) and walks k in steps of 16.
+//
+// Fragment layout of v_mfma_f32_32x32x16_bf16: lane l supplies row l % 32
+// of A (and of B), elements k0 + 8 (l / 32) .. + 7 (the same k split for
+// both operands, so the product does not depend on how the hardware orders
+// k); accumulator register r of lane l holds C[8 (r / 4) + 4 (l / 32) +
+// r % 4][l % 32].
+//
+// Rounding points (fp32 -> bf16, nearest-even, written out below): the
+// Fourier features, every hidden activation, and the activation-gradient
+// operand of the two backward products.  Reductions over the batch (weight
+// and bias gradients, the loss) run in a fixed order: results are bitwise
+// reproducible.
+#include <cmath>
+
+#include "sbr_internal.hpp"
+
+namespace sbr {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+__device__ __forceinline__ float act_f(float z, int kind)
+{
+    if (kind == kActSilu) return z / (1.0f + expf(-z));
+    return fmaxf(z, 0.0f);
+}
+
+__device__ __forceinline__ float act_d(float z, int kind)
+{
+    if (kind == kActSilu) {
+        const float s = 1.0f / (1.0f + expf(-z));
+        return s * (1.0f + z * (1.0f - s));
+    }
+    return z > 0.0f ? 1.0f : 0.0f;
+}
+
+// ---------------------------------------------------------------- GEMM
+constexpr int kGemmThreads = 256;
+constexpr int kTileM = 64, kTileN = 128;
+
+template <int EPI>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * kTileM + (wv & 1) * 32;
+    const int n0 = blockIdx.y * kTileN + (wv >> 1) * 64;
+    const int r = lane & 31, kh = (lane >> 5) * 8;
+    const uint16_t *pa = g.A + static_cast<int64_t>(m0 + r) * g.lda + kh;
+    const uint16_t *pb0 = g.B + static_cast<int64_t>(n0 + r) * g.ldb + kh;
+    const uint16_t *pb1 = g.B + static_cast<int64_t>(n0 + 32 + r) * g.ldb + kh;
+    f32x16 acc0 = {}, acc1 = {};
+    for (int k0 = 0; k0 < g.K; k0 += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(pa + k0);
+        const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0 + k0);
+        const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+    }
+    for (int c = 0; c < 2; ++c) {
+        const f32x16 &acc = c ? acc1 : acc0;
+        const int n = n0 + 32 * c + r;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int m = m0 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            const float v = acc[q];
+            if (EPI == kEpiHidden) {
+                const float z = v + g.bias[n];
+                if (g.zout) g.zout[static_cast<int64_t>(m) * g.ldz + n] = z;
+                const uint16_t h = to_bf16(act_f(z, g.act));
+                g.hout[static_cast<int64_t>(m) * g.ldh + n] = h;
+                if (g.htout) g.htout[static_cast<int64_t>(n) * g.ldht + m] = h;
+            } else if (EPI == kEpiDz) {
+                const float dz = v * act_d(g.zin[static_cast<int64_t>(m) * g.ldzi + n], g.act);
+                g.fout[static_cast<int64_t>(m) * g.ldf + n] = dz;
+                const uint16_t h = to_bf16(dz);
+                g.hout[static_cast<int64_t>(m) * g.ldh + n] = h;
+                g.htout[static_cast<int64_t>(n) * g.ldht + m] = h;
+            } else {
+                g.fout[static_cast<int64_t>(m) * g.ldf + n] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- features
+// Row m < M: normalised input xn = 2 (x - lo) / (hi - lo) - 1 and features
+// sin / cos(2 pi t), t = B xn in float64, reduced to t - rint(t) before the
+// float32 sine and cosine.  Rows in [M, Mpad) are zero.
+__global__ void k_embed(const double *__restrict__ pts, int64_t M, int64_t Mpad, MlpNorm nm,
+                        const float *__restrict__ Bff, int n_ff, uint16_t *__restrict__ h0, uint16_t *__restrict__ h0t)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= Mpad * n_ff) return;
+    const int64_t m = i / n_ff;
+    const int f = static_cast<int>(i % n_ff);
+    uint16_t hs = 0, hc = 0;
+    if (m < M) {
+        double t = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double xn = 2.0 * (pts[3 * m + c] - nm.lo[c]) / (nm.hi[c] - nm.lo[c]) - 1.0;
+            t += static_cast<double>(Bff[3 * f + c]) * xn;
+        }
+        const float fr = static_cast<float>(t - rint(t));
+        float s, co;
+        sincosf(6.2831853071795865f * fr, &s, &co);
+        hs = to_bf16(s);
+        hc = to_bf16(co);
+    }
+    const int w = 2 * n_ff;
+    h0[m * w + f] = hs;
+    h0[m * w + n_ff + f] = hc;
+    if (h0t) {
+        h0t[static_cast<int64_t>(f) * Mpad + m] = hs;
+        h0t[static_cast<int64_t>(n_ff + f) * Mpad + m] = hc;
+    }
+}
+
+// ---------------------------------------------------------------- output layer
+// 16 rows per 256-thread block, 16 lanes per row (a row of width bf16
+// activations read as 16 contiguous pieces).  y = h W_out^T + b_out in
+// float32.  Mode 0 (inference): A[m] = scale (y0 + j y1, y2 + j y3) as
+// float64.  Mode 1 (training): y, dy = 2 (y - t) / (4 M) (zero for padding
+// rows) and a per-block partial of the squared error.
+__global__ __launch_bounds__(256) void k_out(const uint16_t *__restrict__ h, int width, const uint16_t *__restrict__ wo,
+                                             const float *__restrict__ bo, int64_t M, int64_t Mrows, int mode,
+                                             double scale, double *__restrict__ A, const float *__restrict__ tgt,
+                                             float *__restrict__ dy, float *__restrict__ partial)
+{
+    __shared__ float red[16];
+    const int row = threadIdx.x >> 4, sub = threadIdx.x & 15;
+    const int64_t m = static_cast<int64_t>(blockIdx.x) * 16 + row;
+    float y[4] = {0.f, 0.f, 0.f, 0.f};
+    if (m < Mrows) {
+        const int per = width / 16;
+        for (int k = sub * per; k < (sub + 1) * per; ++k) {
+            const float hv = from_bf16(h[m * width + k]);
+            for (int o = 0; o < 4; ++o) y[o] += hv * from_bf16(wo[o * width + k]);
+        }
+    }
+    for (int off = 8; off >= 1; off >>= 1)
+        for (int o = 0; o < 4; ++o) y[o] += __shfl_xor(y[o], off, 16);
+    float e2 = 0.f;
+    if (sub == 0 && m < Mrows) {
+        for (int o = 0; o < 4; ++o) y[o] += bo[o];
+        if (mode == 0) {
+            if (m < M) {
+                A[4 * m + 0] = scale * y[0];
+                A[4 * m + 1] = scale * y[1];
+                A[4 * m + 2] = scale * y[2];
+                A[4 * m + 3] = scale * y[3];
+            }
+        } else {
+            for (int o = 0; o < 4; ++o) {
+                const float d = m < M ? y[o] - tgt[4 * m + o] : 0.f;
+                e2 += d * d;
+                dy[4 * m + o] = m < M ? 2.0f * d / (4.0f * static_cast<float>(M)) : 0.f;
+            }
+        }
+    }
+    if (mode == 1) {
+        if (sub == 0) red[row] = e2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float s = 0.f;
+            for (int q = 0; q < 16; ++q) s += red[q];
+            partial[blockIdx.x] = s;
+        }
+    }
+}
+
+// dh = dy W_out (float32, bf16 weights), dz = dh act'(z); writes dz, bf16(dz)
+// and its transpose.  One thread per (row, column).
+__global__ void k_out_back(const float *__restrict__ dy, const uint16_t *__restrict__ wo, int width, int64_t Mrows,
+                           const float *__restrict__ z, int act, float *__restrict__ dz, uint16_t *__restrict__ dzb,
+                           uint16_t *__restrict__ dzbt)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= Mrows * width) return;
+    const int64_t m = i / width;
+    const int k = static_cast<int>(i % width);
+    float dh = 0.f;
+    for (int o = 0; o < 4; ++o) dh += dy[4 * m + o] * from_bf16(wo[o * width + k]);
+    const float d = dh * act_d(z[i], act);
+    dz[i] = d;
+    const uint16_t b = to_bf16(d);
+    dzb[i] = b;
+    dzbt[static_cast<int64_t>(k) * Mrows + m] = b;
+}
+
+// Output-layer gradients: dW_out[o][k] = sum_m dy[m][o] h[m][k] and
+// db_out[o] = sum_m dy[m][o], summed in row order.
+__global__ void k_out_wgrad(const float *__restrict__ dy, const uint16_t *__restrict__ h, int width, int64_t Mrows,
+                            float *__restrict__ gw, float *__restrict__ gb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 4 * width) {
+        const int o = i / width, k = i % width;
+        float s = 0.f;
+        for (int64_t m = 0; m < Mrows; ++m) s += dy[4 * m + o] * from_bf16(h[m * width + k]);
+        gw[i] = s;
+    } else if (i < 4 * width + 4) {
+        const int o = i - 4 * width;
+        float s = 0.f;
+        for (int64_t m = 0; m < Mrows; ++m) s += dy[4 * m + o];
+        gb[o] = s;
+    }
+}
+
+// Column sums of a row-major float32 matrix (bias gradients), in row order.
+__global__ void k_colsum(const float *__restrict__ x, int64_t rows, int cols, float *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int64_t m = 0; m < rows; ++m) s += x[m * cols + c];
+    out[c] = s;
+}
+
+__global__ void k_sum(const float *__restrict__ x, int n, float *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.f;
+        for (int i = 0; i < n; ++i) s += x[i];
+        *out = s;
+    }
+}
+
+// Training rows of a batch: rows idx[b] of the points and of the complex
+// targets (divided by the output scale, as 4 reals); rows b >= count are
+// zero.
+__global__ void k_gather(const double *__restrict__ pts, const double *__restrict__ tc, const int32_t *__restrict__ idx,
+                         int64_t count, int64_t Mrows, double inv_scale, double *__restrict__ pb, float *__restrict__ tb)
+{
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= Mrows) return;
+    if (b < count) {
+        const int64_t s = idx[b];
+        for (int c = 0; c < 3; ++c) pb[3 * b + c] = pts[3 * s + c];
+        for (int c = 0; c < 4; ++c) tb[4 * b + c] = static_cast<float>(tc[4 * s + c] * inv_scale);
+    } else {
+        for (int c = 0; c < 3; ++c) pb[3 * b + c] = 0.0;
+        for (int c = 0; c < 4; ++c) tb[4 * b + c] = 0.f;
+    }
+}
+
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int64_t n, float lr, float b1, float b2, float bc1, float bc2,
+                       float eps)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// bf16 copy of one weight matrix [rows][cols] and, if wt, of its transpose.
+__global__ void k_refresh(const float *__restrict__ w, int rows, int cols, uint16_t *__restrict__ wb,
+                          uint16_t *__restrict__ wt)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= static_cast<int64_t>(rows) * cols) return;
+    const uint16_t b = to_bf16(w[i]);
+    wb[i] = b;
+    if (wt) wt[static_cast<int64_t>(i % cols) * rows + i / cols] = b;
+}
+
+// ---------------------------------------------------------------- grid fill
+// Points of an angle x frequency grid: pts[a * nf + f] = (theta_a, phi_a, f).
+__global__ void k_grid_pts(const double *__restrict__ th, const double *__restrict__ ph, const double *__restrict__ fr,
+                           int64_t na, int nf, double *__restrict__ pts)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= na * nf) return;
+    const int64_t a = i / nf;
+    const int f = static_cast<int>(i % nf);
+    pts[3 * i] = th[a];
+    pts[3 * i + 1] = ph[a];
+    pts[3 * i + 2] = fr[f];
+}
+
+__device__ __forceinline__ double sig_db(double re, double im)
+{
+    const double s = 4.0 * 3.14159265358979323846 * (re * re + im * im);
+    return s > 0.0 ? 10.0 * log10(s) : -400.0;
+}
+
+// Largest co-polar sigma (dBsm) of the SBR probe results [n][2][2] complex.
+__global__ void k_probe_max(const double *__restrict__ A, int64_t n, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    double m = -400.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double *q = A + 8 * i;
+        m = fmax(m, fmax(sig_db(q[0], q[1]), sig_db(q[6], q[7])));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// One thread per tile (ta, tf): largest |sigma_sur - sigma_sbr| (dB) over the
+// tile's probes (per_tile consecutive probe frequencies of angle tile ta),
+// both co-polar channels, counting only probes whose SBR sigma is at least
+// smax - floor_db; flag = 1 when it exceeds tol_db.
+__global__ void k_probe_check(const double *__restrict__ A_sbr, const double *__restrict__ A_sur, int64_t n_ta,
+                              int n_tf, int per_tile, const double *__restrict__ smax, double floor_db, double tol_db,
+                              uint8_t *__restrict__ flag, double *__restrict__ err)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_ta * n_tf) return;
+    const int64_t ta = t / n_tf;
+    const int tf = static_cast<int>(t % n_tf);
+    const double lim = *smax - floor_db;
+    double e = 0.0;
+    for (int q = 0; q < per_tile; ++q) {
+        const int64_t row = ta * static_cast<int64_t>(n_tf) * per_tile + static_cast<int64_t>(tf) * per_tile + q;
+        const double *s = A_sbr + 8 * row;
+        const double *u = A_sur + 4 * row;
+        const double sh = sig_db(s[0], s[1]), sv = sig_db(s[6], s[7]);
+        if (sh >= lim) e = fmax(e, fabs(sig_db(u[0], u[1]) - sh));
+        if (sv >= lim) e = fmax(e, fabs(sig_db(u[2], u[3]) - sv));
+    }
+    err[t] = e;
+    flag[t] = e > tol_db ? 1 : 0;
+}
+
+// SBR rows [n][2][2] complex -> grid entries dst[r] of [.][2] complex (HH, VV).
+__global__ void k_scatter_copol(const double *__restrict__ A, const int64_t *__restrict__ dst, int64_t n,
+                                double *__restrict__ out)
+{
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const double *q = A + 8 * r;
+    double *o = out + 4 * dst[r];
+    o[0] = q[0];
+    o[1] = q[1];
+    o[2] = q[6];
+    o[3] = q[7];
+}
+
+inline unsigned nblk(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
+
+}  // namespace
+
+int launch_gemm(hipStream_t s, int epi, const GemmArgs &g)
+{
+    if (g.M % kTileM || g.N % kTileN || g.K % 16 || g.K <= 0)
+        return fail(SBR_ERR_INVALID_ARG, "MLP product: shape not a multiple of the 64 x 128 x 16 tile");
+    dim3 grid(g.M / kTileM, g.N / kTileN);
+    if (epi == kEpiHidden) k_gemm<kEpiHidden><<<grid, kGemmThreads, 0, s>>>(g);
+    else if (epi == kEpiDz) k_gemm<kEpiDz><<<grid, kGemmThreads, 0, s>>>(g);
+    else k_gemm<kEpiF32><<<grid, kGemmThreads, 0, s>>>(g);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_embed(hipStream_t s, const double *pts, int64_t M, int64_t Mpad, const MlpNorm &nm, const float *Bff,
+                 int n_ff, uint16_t *h0, uint16_t *h0t)
+{
+    k_embed<<<nblk(Mpad * n_ff, 256), 256, 0, s>>>(pts, M, Mpad, nm, Bff, n_ff, h0, h0t);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_out(hipStream_t s, const uint16_t *h, int width, const uint16_t *wo, const float *bo, int64_t M,
+               int64_t Mrows, int mode, double scale, double *A, const float *tgt, float *dy, float *partial)
+{
+    k_out<<<nblk(Mrows, 16), 256, 0, s>>>(h, width, wo, bo, M, Mrows, mode, scale, A, tgt, dy, partial);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_out_back(hipStream_t s, const float *dy, const uint16_t *wo, int width, int64_t Mrows, const float *z,
+                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h)
+{
+    k_out_back<<<nblk(Mrows * width, 256), 256, 0, s>>>(dy, wo, width, Mrows, z, act, dz, dzb, dzbt);
+    k_out_wgrad<<<nblk(4 * width + 4, 256), 256, 0, s>>>(dy, h, width, Mrows, gw, gb);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out)
+{
+    k_colsum<<<nblk(cols, 256), 256, 0, s>>>(x, rows, cols, out);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_sum(hipStream_t s, const float *x, int n, float *out)
+{
+    k_sum<<<1, 64, 0, s>>>(x, n, out);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_gather(hipStream_t s, const double *pts, const double *tc, const int32_t *idx, int64_t count,
+                  int64_t Mrows, double inv_scale, double *pb, float *tb)
+{
+    k_gather<<<nblk(Mrows, 256), 256, 0, s>>>(pts, tc, idx, count, Mrows, inv_scale, pb, tb);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
+                float bc1, float bc2, float eps)
+{
+    k_adam<<<nblk(n, 256), 256, 0, s>>>(w, m, v, g, n, lr, b1, b2, bc1, bc2, eps);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_refresh(hipStream_t s, const float *w, int rows, int cols, uint16_t *wb, uint16_t *wt)
+{
+    k_refresh<<<nblk(static_cast<int64_t>(rows) * cols, 256), 256, 0, s>>>(w, rows, cols, wb, wt);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_grid_pts(hipStream_t s, const double *th, const double *ph, const double *fr, int64_t na, int nf,
+                    double *pts)
+{
+    k_grid_pts<<<nblk(na * nf, 256), 256, 0, s>>>(th, ph, fr, na, nf, pts);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_probe_check(hipStream_t s, const double *A_sbr, const double *A_sur, int64_t n_ta, int n_tf, int per_tile,
+                       double *smax, double floor_db, double tol_db, uint8_t *flag, double *err)
+{
+    k_probe_max<<<1, 256, 0, s>>>(A_sbr, n_ta * n_tf * per_tile, smax);
+    k_probe_check<<<nblk(n_ta * n_tf, 256), 256, 0, s>>>(A_sbr, A_sur, n_ta, n_tf, per_tile, smax, floor_db, tol_db,
+                                                       flag, err);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_scatter_copol(hipStream_t s, const double *A, const int64_t *dst, int64_t n, double *out)
+{
+    if (n <= 0) return SBR_OK;
+    k_scatter_copol<<<nblk(n, 256), 256, 0, s>>>(A, dst, n, out);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+}  // namespace sbr

@@ -11,7 +11,8 @@
 // -(k dA / 2 pi) is applied in the finalize step.
 //
 // Numerics: the phase k_f * D is formed and reduced modulo 2 pi in float64
-// (k D reaches 1e3-1e4 rad), sin/cos and w are float32.  Each term is
+// (k D reaches 1e3-1e4 rad) and sin/cos are float32; the weights w are
+// formed in float64 from the float32 records.  Each term is
 // converted to a 64-bit fixed-point integer (unit 2^-32) and summed as an
 // integer, so the per-block partials do not depend on the order in which the
 // trace stage appended its records: results are bitwise reproducible without
@@ -31,15 +32,11 @@ constexpr int kFT = 2;  // frequencies per pass over a block's records
 
 struct PoP {
     Records rec;
-    const uint32_t *rec_cnt;
-    int cnt_stride;
-    const int64_t *rec_base;
+    const PoAngle *ang;
+    int n_angles;
     const float4 *nrm_id;
-    int chunks;
     int mode;
     const double *kf;
-    int n_freq;
-    const double *basis;
     long long *partial;
 };
 
@@ -74,88 +71,97 @@ __device__ __forceinline__ long long wave_sum64(long long x)
 
 // round(x * 2^32) as a 64-bit integer for |x| < 2^19, via the float64
 // rounding of x * 2^32 + 1.5 * 2^52.
-__device__ __forceinline__ long long fix32(float x)
+__device__ __forceinline__ long long fix32(double x)
 {
     const double magic = 6755399441055744.0;  // 1.5 * 2^52
-    const double y = __builtin_fma(static_cast<double>(x), 4294967296.0, magic);
+    const double y = __builtin_fma(x, 4294967296.0, magic);
     return __double_as_longlong(y) - __double_as_longlong(magic);
 }
 
-__device__ __forceinline__ void weights(const PoP &p, int a, const float4 r0, const float4 r1, const float4 r2,
-                                        float w[4])
+// Per-record weights w[p * 2 + q] in float64 from the float32 record fields:
+// the cross-polar weights of VECTOR mode are differences of nearly equal
+// products, and their float32 rounding, identical for the many rays of a flat
+// facet, would add up coherently.
+__device__ __forceinline__ void weights(const PoP &p, const double *B, const float4 r0, const float4 r1,
+                                        const float4 r2, double w[4])
 {
     const int meta = __float_as_int(r2.w);
     const int N = meta & 255;
     const int flags = meta >> 8;
-    w[0] = w[1] = w[2] = w[3] = 0.0f;
+    w[0] = w[1] = w[2] = w[3] = 0.0;
     if (!(flags & SBR_REC_VALID)) return;
-    const double *B = p.basis + 9 * a;
     if (p.mode == SBR_MODE_PAPER) {
         const float4 n0 = p.nrm_id[__float_as_int(r1.w)];
-        const float c0 = fabsf((n0.x * static_cast<float>(B[0]) + n0.y * static_cast<float>(B[1])) +
-                               n0.z * static_cast<float>(B[2]));
-        const float s = (N & 1) ? c0 : -c0;
+        const double c0 = fabs((static_cast<double>(n0.x) * B[0] + static_cast<double>(n0.y) * B[1]) +
+                               static_cast<double>(n0.z) * B[2]);
+        const double s = (N & 1) ? c0 : -c0;
         w[0] = s;
         w[3] = s;
         return;
     }
-    float4 n = p.nrm_id[__float_as_int(r0.w)];
-    if (flags & SBR_REC_BACK_LAST) {
-        n.x = -n.x;
-        n.y = -n.y;
-        n.z = -n.z;
-    }
-    const float ndl = (n.x * r0.x + n.y * r0.y) + n.z * r0.z;
-    const float c = fmaxf(-ndl, 1e-3f);
-    const float ic = 1.0f / c;
-    const float thx = static_cast<float>(B[3]), thy = static_cast<float>(B[4]), thz = static_cast<float>(B[5]);
-    const float phx = static_cast<float>(B[6]), phy = static_cast<float>(B[7]), phz = static_cast<float>(B[8]);
-    // q = 0: H (r1.xyz), q = 1: V (r2.xyz); p = 0: H (phi_hat), p = 1: V (theta_hat)
+    const float4 n32 = p.nrm_id[__float_as_int(r0.w)];
+    const double sg = (flags & SBR_REC_BACK_LAST) ? -1.0 : 1.0;
+    const double nx = sg * n32.x, ny = sg * n32.y, nz = sg * n32.z;
+    const double dx = r0.x, dy = r0.y, dz = r0.z;
+    const double ndl = (nx * dx + ny * dy) + nz * dz;
+    const double c = fmax(-ndl, 1e-3);
+    const double ic = 1.0 / c;
+    // q = 0: H (r1.xyz), q = 1: V (r2.xyz); p = 0: H (phi_hat = B[6..8]), p = 1: V (theta_hat = B[3..5])
     for (int q = 0; q < 2; ++q) {
-        const float ex = q ? r2.x : r1.x, ey = q ? r2.y : r1.y, ez = q ? r2.z : r1.z;
-        const float ne = (n.x * ex + n.y * ey) + n.z * ez;
-        const float jx = r0.x * ne - ex * ndl, jy = r0.y * ne - ey * ndl, jz = r0.z * ne - ez * ndl;
-        w[0 * 2 + q] = ((jx * phx + jy * phy) + jz * phz) * ic;
-        w[1 * 2 + q] = ((jx * thx + jy * thy) + jz * thz) * ic;
+        const double ex = q ? r2.x : r1.x, ey = q ? r2.y : r1.y, ez = q ? r2.z : r1.z;
+        const double ne = (nx * ex + ny * ey) + nz * ez;
+        const double jx = dx * ne - ex * ndl, jy = dy * ne - ey * ndl, jz = dz * ne - ez * ndl;
+        w[0 * 2 + q] = ((jx * B[6] + jy * B[7]) + jz * B[8]) * ic;
+        w[1 * 2 + q] = ((jx * B[3] + jy * B[4]) + jz * B[5]) * ic;
     }
 }
 
+// Block u of the launch: records [c * kPoRecsPerBlock, (c + 1) * kPoRecsPerBlock)
+// of angle a, where a is the angle whose blocks hold u and c = u - unit_base.
 __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
 {
     __shared__ long long red[kPoThreads / 64][kFT * 8];
-    const int a = blockIdx.y, c = blockIdx.x;
+    const int64_t u = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t cnt = p.rec_cnt[static_cast<int64_t>(a) * p.cnt_stride];
-    const int64_t base = p.rec_base[a];
-    const int64_t r0i = static_cast<int64_t>(c) * kPoRecsPerBlock;
-    long long *out = p.partial + ((static_cast<int64_t>(a) * p.chunks + c) * p.n_freq) * 8;
-    if (r0i >= cnt) return;  // the finalize step reads only the chunks that hold records
-    const int64_t r1i = min(r0i + kPoRecsPerBlock, cnt);
+    int lo = 0, hi = p.n_angles;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (p.ang[mid].unit_base <= u) lo = mid;
+        else hi = mid;
+    }
+    const PoAngle &A = p.ang[lo];
+    const int64_t c = u - A.unit_base;
+    const int nf = A.n_f;
+    const double *kf = p.kf + A.kf_off;
+    long long *out = p.partial + (A.part_base + c * nf) * 8;
+    const int64_t r0i = c * kPoRecsPerBlock;
+    const int64_t r1i = min(r0i + kPoRecsPerBlock, A.rec_cnt);
     const double two_pi_hi = 6.283185307179586;       // fl64(2 pi)
     const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - fl64(2 pi)
     const double inv_two_pi = 0.15915494309189535;
-    for (int f0 = 0; f0 < p.n_freq; f0 += kFT) {
+    for (int f0 = 0; f0 < nf; f0 += kFT) {
         long long acc[kFT][8];
         for (int ft = 0; ft < kFT; ++ft)
             for (int e = 0; e < 8; ++e) acc[ft][e] = 0;
-        for (int64_t e = base + r0i + tid; e < base + r1i; e += kPoThreads) {
+        for (int64_t e = A.rec_base + r0i + tid; e < A.rec_base + r1i; e += kPoThreads) {
             const float4 q2 = p.rec.r2[e];
             if (!((__float_as_int(q2.w) >> 8) & SBR_REC_VALID)) continue;  // no hit (or dropped): no term
             const float4 q0 = p.rec.r0[e], q1 = p.rec.r1[e];
             const double D = p.rec.D[e];
-            float w[4];
-            weights(p, a, q0, q1, q2, w);
+            double w[4];
+            weights(p, A.basis, q0, q1, q2, w);
             for (int ft = 0; ft < kFT; ++ft) {
                 const int f = f0 + ft;
-                if (f >= p.n_freq) break;
-                const double ph = p.kf[f] * D;
+                if (f >= nf) break;
+                const double ph = kf[f] * D;
                 const double nturn = rint(ph * inv_two_pi);
                 const double red_ph = __builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph));
                 float s, co;
                 sincosf(static_cast<float>(red_ph), &s, &co);
+                const double sd = s, cd = co;
                 for (int k = 0; k < 4; ++k) {
-                    acc[ft][2 * k] += fix32(w[k] * s);
-                    acc[ft][2 * k + 1] += fix32(w[k] * co);
+                    acc[ft][2 * k] += fix32(w[k] * sd);
+                    acc[ft][2 * k + 1] += fix32(w[k] * cd);
                 }
             }
         }
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
         __syncthreads();
         if (tid < kFT * 8) {
             const int ft = tid / 8, k = tid % 8;
-            if (f0 + ft < p.n_freq) {
+            if (f0 + ft < nf) {
                 long long s = 0;
                 for (int x = 0; x < kPoThreads / 64; ++x) s += red[x][tid];
                 out[(f0 + ft) * 8 + k] = s;
@@ -177,92 +183,89 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
     }
 }
 
-// One thread per (angle, frequency): fixed-order sum of the block partials.
-__global__ void k_po_final(const long long *__restrict__ partial, const uint32_t *__restrict__ rec_cnt, int cnt_stride,
-                           int n_angles, int chunks, int n_freq, const double *__restrict__ kf, double dA,
-                           double *__restrict__ A_out, double *__restrict__ sigma)
+// One thread per (angle, frequency): fixed-order sum of the angle's block
+// partials, then A = -(k dA / 2 pi) 2^-32 S and sigma in dBsm.
+__global__ void k_po_final(PoP p, int max_nf, double *__restrict__ A_out, double *__restrict__ sigma)
 {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= static_cast<int64_t>(n_angles) * n_freq) return;
-    const int a = static_cast<int>(idx / n_freq), f = static_cast<int>(idx % n_freq);
-    const int64_t nch = (static_cast<int64_t>(rec_cnt[static_cast<int64_t>(a) * cnt_stride]) + kPoRecsPerBlock - 1) /
-                        kPoRecsPerBlock;
+    if (idx >= static_cast<int64_t>(p.n_angles) * max_nf) return;
+    const int a = static_cast<int>(idx / max_nf), f = static_cast<int>(idx % max_nf);
+    const PoAngle &A = p.ang[a];
+    if (f >= A.n_f) return;
+    const int64_t nch = po_units(A.rec_cnt);
     double S[8];
     for (int e = 0; e < 8; ++e) S[e] = 0.0;
     for (int64_t c = 0; c < nch; ++c) {
-        const long long *q = partial + ((static_cast<int64_t>(a) * chunks + c) * n_freq + f) * 8;
+        const long long *q = p.partial + (A.part_base + c * A.n_f + f) * 8;
         for (int e = 0; e < 8; ++e) S[e] += static_cast<double>(q[e]);
     }
-    const double C = -(kf[f] * dA / (2.0 * kPi)) * 2.3283064365386963e-10;  // 2^-32
-    double *A = A_out + idx * 8;
+    const double C = -(p.kf[A.kf_off + f] * A.dA / (2.0 * kPi)) * 2.3283064365386963e-10;  // 2^-32
+    const int64_t row = A.out_base + f;
+    double *Ao = A_out + row * 8;
     for (int k = 0; k < 4; ++k) {
         const double re = C * S[2 * k], im = C * S[2 * k + 1];
-        A[2 * k] = re;
-        A[2 * k + 1] = im;
+        Ao[2 * k] = re;
+        Ao[2 * k + 1] = im;
         if (sigma) {
             const double sg = 4.0 * kPi * (re * re + im * im);
-            sigma[idx * 4 + k] = sg > 0.0 ? 10.0 * log10(sg) : -400.0;
+            sigma[row * 4 + k] = sg > 0.0 ? 10.0 * log10(sg) : -400.0;
         }
     }
 }
 
-__global__ void k_pack(sbr_hits h, int64_t n, Records rec, uint32_t *cnt)
+// Caller hit e -> record slot e.
+__global__ void k_pack(sbr_hits h, int64_t n, Records rec)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool in = e < n;
-    const int fl = in ? h.flags[e] : 0;
-    const bool want = in && (fl & SBR_REC_VALID);
-    const uint64_t m = __ballot(want);
-    uint32_t base = 0;
-    if (m) {
-        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-        if ((threadIdx.x & 63) == leader) base = atomicAdd(cnt, static_cast<uint32_t>(__popcll(m)));
-        base = __shfl(base, leader);
+    if (e >= n) return;
+    const int fl = h.flags[e];
+    if (!(fl & SBR_REC_VALID)) {
+        rec.r2[e] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
+        return;
     }
-    if (!want) return;
-    const uint32_t pos = base + __popcll(m & ((1ull << (threadIdx.x & 63)) - 1ull));
-    rec.r0[pos] = make_float4(h.d_last[3 * e], h.d_last[3 * e + 1], h.d_last[3 * e + 2], __int_as_float(h.tri_last[e]));
-    rec.r1[pos] = make_float4(h.eH_last[3 * e], h.eH_last[3 * e + 1], h.eH_last[3 * e + 2],
-                              __int_as_float(h.tri_first[e]));
-    rec.r2[pos] = make_float4(h.eV_last[3 * e], h.eV_last[3 * e + 1], h.eV_last[3 * e + 2],
-                              __int_as_float((h.n_bounce[e] & 255) | (fl << 8)));
-    rec.D[pos] = h.D[e];
+    rec.r0[e] = make_float4(h.d_last[3 * e], h.d_last[3 * e + 1], h.d_last[3 * e + 2], __int_as_float(h.tri_last[e]));
+    rec.r1[e] = make_float4(h.eH_last[3 * e], h.eH_last[3 * e + 1], h.eH_last[3 * e + 2],
+                            __int_as_float(h.tri_first[e]));
+    rec.r2[e] = make_float4(h.eV_last[3 * e], h.eV_last[3 * e + 1], h.eV_last[3 * e + 2],
+                            __int_as_float((h.n_bounce[e] & 255) | (fl << 8)));
+    rec.D[e] = h.D[e];
 }
 
 }  // namespace
 
-int launch_po(hipStream_t s, const PoArgs &a)
+static PoP make_pop(const PoArgs &a)
 {
     PoP p;
     p.rec = a.rec;
-    p.rec_cnt = a.rec_cnt;
-    p.cnt_stride = a.cnt_stride;
-    p.rec_base = a.rec_base;
+    p.ang = a.ang;
+    p.n_angles = a.n_angles;
     p.nrm_id = a.bvh->nrm_id;
-    p.chunks = a.chunks;
     p.mode = a.mode;
     p.kf = a.kf;
-    p.n_freq = a.n_freq;
-    p.basis = a.basis;
     p.partial = a.partial;
-    dim3 grid(a.chunks, a.n_angles);
-    k_po<<<grid, kPoThreads, 0, s>>>(p);
+    return p;
+}
+
+int launch_po(hipStream_t s, const PoArgs &a)
+{
+    if (a.n_units <= 0) return SBR_OK;
+    if (a.n_units > 2147483647LL) return fail(SBR_ERR_OVERFLOW, "PO launch: too many blocks");
+    k_po<<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
-int launch_po_finalize(hipStream_t s, const PoArgs &a, double dA, double *A_out, double *sigma_out)
+int launch_po_finalize(hipStream_t s, const PoArgs &a, double *A_out, double *sigma_out)
 {
-    const int64_t n = static_cast<int64_t>(a.n_angles) * a.n_freq;
-    k_po_final<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(a.partial, a.rec_cnt, a.cnt_stride, a.n_angles, a.chunks,
-                                                                      a.n_freq, a.kf, dA, A_out, sigma_out);
+    const int64_t n = static_cast<int64_t>(a.n_angles) * a.max_nf;
+    k_po_final<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(make_pop(a), a.max_nf, A_out, sigma_out);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
-int launch_pack_hits(hipStream_t s, const sbr_hits *h, int64_t n, Records rec, uint32_t *cnt)
+int launch_pack_hits(hipStream_t s, const sbr_hits *h, int64_t n, Records rec)
 {
-    k_pack<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(*h, n, rec, cnt);
+    k_pack<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(*h, n, rec);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

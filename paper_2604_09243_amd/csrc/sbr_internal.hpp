@@ -50,6 +50,10 @@ struct AnglePlan {
     int32_t nu, nv, tu, tv;    // rays, and tiles (tile_w x 64/tile_w rays) along u and v
     int64_t tile_base;         // first tile of this angle in the launch
     int64_t rec_base;          // first record slot of this angle
+    int32_t root;              // root node of the angle's scene in the node array
+    float eps;                 // the scene's surface offset
+    float slack;               // the scene's box padding for entry distances
+    int32_t pad_;
 };
 
 // In-flight ray state of the wavefront schedule's queues, 6 x 16 bytes
@@ -93,6 +97,19 @@ constexpr int kScheduleWavefront = 1;
 
 struct Workspace;
 
+// One scene of a multi-scene set (sbr_pack_scenes): where its nodes, leaf
+// slots and triangle ids start in the set's arrays, and its geometry.
+struct SceneInfo {
+    int32_t root, slot_base, id_base, depth;
+    int64_t n_tris, n_live, n_nodes;
+    float eps;
+    double diag;
+    double bbox[6];
+};
+
+// Box padding added to entry distances (scales with the scene size).
+inline float box_slack(double diag) { return static_cast<float>(1e-6 * diag) + 1e-30f; }
+
 }  // namespace sbr
 
 struct sbr_bvh {
@@ -109,6 +126,7 @@ struct sbr_bvh {
     float4 *nrm_id = nullptr;     // [n_tris] unit normal by input index
     std::vector<float> host_normals;  // [n_tris*3]
     int64_t device_bytes = 0;
+    std::vector<sbr::SceneInfo> scenes;  // a multi-scene set only (empty for one mesh)
 };
 
 struct sbr_ctx {
@@ -186,24 +204,110 @@ int trace_block_threads();
 int trace_stack_lds();  // LDS entries of the stack when it spills
 bool trace_needs_spill(const sbr_bvh *bvh);
 
+// api.cpp helpers shared with the batch entry points
+sbr_tune default_tune();
+int normalize_tune(sbr_tune &t);           // check_tune, then chunk_log2 0 -> default
+int log2i(int x);
+void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped);
+// Every bounce of one trace (one streaming launch, or one launch per bounce
+// with the queues swapped); ev (nullable) gets an event after each launch.
+int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector<hipEvent_t> *ev);
+size_t spill_words(const sbr_bvh *bvh, int blocks);
+// Device plan of one angle from its host plan (tiles of tile_w x 64/tile_w).
+void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p);
+constexpr int kDefaultChunkLog2 = 26;
+// Autotuner cache: the context's map, then the JSON-lines file named by
+// $SBR_TUNE_CACHE (if any).
+bool tune_lookup(sbr_ctx *ctx, const std::string &key, sbr_tune *out);
+void tune_store(sbr_ctx *ctx, const std::string &key, const sbr_tune &t);
+int size_bucket(double x);  // floor(log2(x)), 0 below 1
+
 // po.hip
+// One incidence angle of a PO launch (device copy, built on the host).
+struct PoAngle {
+    double basis[9];            // k_hat, theta_hat, phi_hat
+    double dA;                  // ray-tube area (ray spacing squared)
+    int64_t rec_base, rec_cnt;  // record slots [rec_base, rec_base + rec_cnt)
+    int64_t unit_base;          // first PO block of the angle in the launch
+    int64_t part_base;          // first partial row (8 int64) of the angle
+    int64_t out_base;           // output row of the angle's first frequency
+    int32_t kf_off, n_f;        // its wavenumbers kf[kf_off, kf_off + n_f)
+};
 struct PoArgs {
     const sbr_bvh *bvh;
     Records rec;
-    const uint32_t *rec_cnt;  // [n_angles * cnt_stride]: record slots of each angle
-    int cnt_stride;
-    const int64_t *rec_base;  // [n_angles]: first record slot of each angle
+    const PoAngle *ang;  // device [n_angles]
     int n_angles;
-    int chunks;               // blocks per angle along x
+    int64_t n_units;     // blocks of the launch: sum over angles of ceil(rec_cnt / kPoRecsPerBlock)
+    int max_nf;          // largest n_f of the angles
     int mode;
-    const double *kf;         // device [n_freq] wavenumbers
-    int n_freq;
-    const double *basis;      // device [n_angles][9]: k, theta_hat, phi_hat
-    long long *partial;       // device [n_angles][chunks][n_freq][8]
+    const double *kf;    // device wavenumbers
+    long long *partial;  // device partial rows
 };
 constexpr int kPoRecsPerBlock = 4096;
+__host__ __device__ inline int64_t po_units(int64_t rec_cnt) { return (rec_cnt + kPoRecsPerBlock - 1) / kPoRecsPerBlock; }
 int launch_po(hipStream_t s, const PoArgs &a);
-int launch_po_finalize(hipStream_t s, const PoArgs &a, double dA, double *A_out, double *sigma_out);
-int launch_pack_hits(hipStream_t s, const sbr_hits *h, int64_t n, Records rec, uint32_t *cnt);
+// A_out rows (8 doubles) and sigma rows (4 doubles) are indexed by out_base + f.
+int launch_po_finalize(hipStream_t s, const PoArgs &a, double *A_out, double *sigma_out);
+// Converts caller hit arrays into n record slots (invalid rays keep no flags).
+int launch_pack_hits(hipStream_t s, const sbr_hits *h, int64_t n, Records rec);
+
+// scene.hip
+// Fills n uint32 words with zero (usable inside a captured graph).
+int launch_zero_u32(hipStream_t s, uint32_t *p, int64_t n);
+// Relocation of one scene's nodes and triangles into a multi-scene arena.
+int launch_relocate(hipStream_t s, const BNode *src_nodes, int64_t n_nodes, BNode *dst_nodes, int32_t node_off,
+                    const BTri *src_tris, int64_t n_slots, BTri *dst_tris, int32_t slot_off, int32_t id_off);
+
+// mlp.hip: surrogate network kernels
+constexpr int kActSilu = 0, kActRelu = 1;
+constexpr int kEpiHidden = 0, kEpiDz = 1, kEpiF32 = 2;
+// C[m][n] = sum_k A[m][k] B[n][k] (bf16, fp32 accumulation); M % 64 == 0,
+// N % 128 == 0, K % 16 == 0.  Epilogues:
+//   kEpiHidden: z = C + bias[n] (zout, optional), h = bf16(act(z)) to hout
+//               and, optional, to htout transposed
+//   kEpiDz:     dz = C act'(zin) to fout, bf16(dz) to hout and htout (transposed)
+//   kEpiF32:    C to fout
+struct GemmArgs {
+    const uint16_t *A;
+    int64_t lda;
+    const uint16_t *B;
+    int64_t ldb;
+    int M, N, K;
+    const float *bias;
+    int act;
+    float *zout;
+    int64_t ldz;
+    uint16_t *hout;
+    int64_t ldh;
+    uint16_t *htout;
+    int64_t ldht;
+    const float *zin;
+    int64_t ldzi;
+    float *fout;
+    int64_t ldf;
+};
+struct MlpNorm {
+    double lo[3], hi[3];
+};
+int launch_gemm(hipStream_t s, int epi, const GemmArgs &g);
+int launch_embed(hipStream_t s, const double *pts, int64_t M, int64_t Mpad, const MlpNorm &nm, const float *Bff,
+                 int n_ff, uint16_t *h0, uint16_t *h0t);
+int launch_out(hipStream_t s, const uint16_t *h, int width, const uint16_t *wo, const float *bo, int64_t M,
+               int64_t Mrows, int mode, double scale, double *A, const float *tgt, float *dy, float *partial);
+int launch_out_back(hipStream_t s, const float *dy, const uint16_t *wo, int width, int64_t Mrows, const float *z,
+                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h);
+int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out);
+int launch_sum(hipStream_t s, const float *x, int n, float *out);
+int launch_gather(hipStream_t s, const double *pts, const double *tc, const int32_t *idx, int64_t count,
+                  int64_t Mrows, double inv_scale, double *pb, float *tb);
+int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
+                float bc1, float bc2, float eps);
+int launch_refresh(hipStream_t s, const float *w, int rows, int cols, uint16_t *wb, uint16_t *wt);
+int launch_grid_pts(hipStream_t s, const double *th, const double *ph, const double *fr, int64_t na, int nf,
+                    double *pts);
+int launch_probe_check(hipStream_t s, const double *A_sbr, const double *A_sur, int64_t n_ta, int n_tf, int per_tile,
+                       double *smax, double floor_db, double tol_db, uint8_t *flag, double *err);
+int launch_scatter_copol(hipStream_t s, const double *A, const int64_t *dst, int64_t n, double *out);
 
 }  // namespace sbr

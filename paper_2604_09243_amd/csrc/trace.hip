@@ -185,9 +185,23 @@ __device__ __forceinline__ void test_leaf(const Params &p, int first, int cnt, c
     if (cnt > 3) test_tri(t3, first + 3, r, b);
 }
 
+// The scene a ray belongs to: its root node in the (possibly multi-scene)
+// node array, its surface offset and its box padding.
+struct SceneRef {
+    int root;
+    float eps, slack;
+};
+
+__device__ __forceinline__ SceneRef scene_of(const Params &p, const Ray &r)
+{
+    if (p.user_sink) return SceneRef{0, p.eps, p.slack};
+    const AnglePlan &pl = p.plans[r.meta >> 8];
+    return SceneRef{pl.root, pl.eps, pl.slack};
+}
+
 // Closest hit of ray r, skipping triangle r.prev.
 template <bool SPILL>
-__device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st)
+__device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc)
 {
     Best b;
     b.t = INFINITY;
@@ -201,13 +215,13 @@ __device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st)
     const float ix = __builtin_amdgcn_rcpf(ddx), iy = __builtin_amdgcn_rcpf(ddy), iz = __builtin_amdgcn_rcpf(ddz);
     const float ox = r.ox * ix, oy = r.oy * iy, oz = r.oz * iz;
     int sp = 0;
-    int cur = 0;  // the root is an internal node
+    int cur = sc.root;  // the root is an internal node
     for (;;) {
         // phase 1: descend through internal nodes until a leaf (or nothing) is next
         while (cur >= 0) {
             SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
             const BNode n = p.nodes[cur];
-            const float tlim = __builtin_fmaf(b.t, 1.000001f, p.slack);
+            const float tlim = __builtin_fmaf(b.t, 1.000001f, sc.slack);
             // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
             const float ax0 = __builtin_fmaf(n.a.x, ix, -ox), ax1 = __builtin_fmaf(n.a.w, ix, -ox);
             const float ay0 = __builtin_fmaf(n.a.y, iy, -oy), ay1 = __builtin_fmaf(n.b.x, iy, -oy);
@@ -308,16 +322,34 @@ __device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool want)
 // Position q of the angle grid (tile = q / 64, position in the tile's
 // tile_w-wide patch = q % 64) -> a fresh ray; false if q lies outside the
 // angle's N_u x N_v grid.
-__device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r)
+// The angle whose tiles hold `tile`, searched in angles [lo, hi).
+__device__ __forceinline__ int find_angle(const Params &p, int64_t tile, int lo, int hi)
 {
-    const int64_t tile = q >> 6;
-    const int k = static_cast<int>(q & 63);
-    int lo = 0, hi = p.n_angles;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (p.tile_base[mid] <= tile) lo = mid;
         else hi = mid;
     }
+    return lo;
+}
+
+// Angles of the first and the last tile of a claimed batch [u, e), found by
+// lanes 0 and 1 together; every later lookup in the batch searches only
+// between them (usually a single angle).
+__device__ __forceinline__ void batch_angles(const Params &p, int64_t u, int64_t e, int &a_lo, int &a_hi)
+{
+    const int lane = threadIdx.x & 63;
+    int a = 0;
+    if (lane < 2) a = find_angle(p, lane == 0 ? u : e - 1, 0, p.n_angles);
+    a_lo = __shfl(a, 0);
+    a_hi = __shfl(a, 1);
+}
+
+__device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r, int a_lo, int a_hi)
+{
+    const int64_t tile = q >> 6;
+    const int k = static_cast<int>(q & 63);
+    const int lo = find_angle(p, tile, a_lo, a_hi + 1);
     const AnglePlan &pl = p.plans[lo];
     const int64_t t = tile - pl.tile_base;
     const int tw = 1 << p.tile_shift;
@@ -386,7 +418,7 @@ struct Last {
 // reflection of the direction and of both field vectors, and the new origin
 // eps off the surface on the side the ray came from.  Returns whether the
 // ray has bounces left.
-__device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, const K3 &kv, Last &L)
+__device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, const K3 &kv, const float eps, Last &L)
 {
     const float t = b.t;
     L.xlx = r.ox + t * r.dx;
@@ -422,10 +454,10 @@ __device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, c
     r.vx = cV * n.x - r.vx;
     r.vy = cV * n.y - r.vy;
     r.vz = cV * n.z - r.vz;
-    r.ox = L.xlx + p.eps * nfx;
-    r.oy = L.xly + p.eps * nfy;
-    r.oz = L.xlz + p.eps * nfz;
-    r.comp = static_cast<double>(p.eps) * ((static_cast<double>(nfx) * r.dx + static_cast<double>(nfy) * r.dy) +
+    r.ox = L.xlx + eps * nfx;
+    r.oy = L.xly + eps * nfy;
+    r.oz = L.xlz + eps * nfz;
+    r.comp = static_cast<double>(eps) * ((static_cast<double>(nfx) * r.dx + static_cast<double>(nfy) * r.dy) +
                                            static_cast<double>(nfz) * r.dz);
     r.prev = b.id;
     r.meta = (r.meta & ~0xff) | N | (back ? 128 : 0);
@@ -565,6 +597,7 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
     const uint64_t lt = lanemask_lt();
     const int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
     int64_t pos = 0, end = 0;  // wave-uniform: unused positions [pos, end) of the claimed batch
+    int a_lo = 0, a_hi = 0;    // wave-uniform: angles spanned by the claimed batch
     bool src_done = false;
     bool has = false;
     Ray r;
@@ -586,9 +619,10 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
                 }
                 pos = u * kTileRays;
                 end = e * kTileRays;
+                if (SRC == 0) batch_angles(p, u, e, a_lo, a_hi);
             }
             const int64_t q = pos + static_cast<int64_t>(__popcll(idle & lt));
-            if (!has && q < end) has = SRC == 0 ? grid_ray(p, q, r) : user_ray(p, q, r);
+            if (!has && q < end) has = SRC == 0 ? grid_ray(p, q, r, a_lo, a_hi) : user_ray(p, q, r);
             pos = min(pos + static_cast<int64_t>(__popcll(idle)), end);
         }
         if (__ballot(has) == 0) break;
@@ -596,19 +630,21 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
         // ---- one bounce for every lane holding a ray
         Best b;
         b.slot = -1;
-        if (has) b = closest(p, r, st);
+        SceneRef sc{0, 0.f, 0.f};
+        if (has) sc = scene_of(p, r);
+        if (has) b = closest(p, r, st, sc);
         if (has) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (has) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         if (has) {
             if (b.slot >= 0) {
                 const K3 kv = kvec(p, r);
                 Last L;
-                const bool cont = bounce(p, r, b, kv, L);
+                const bool cont = bounce(p, r, b, kv, sc.eps, L);
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
                 sink_hit(p, r, b, L);
                 if (!cont) {
                     if (p.flags & SBR_OPT_DROP_TRAPPED) {
-                        const Best b2 = closest(p, r, st);
+                        const Best b2 = closest(p, r, st, sc);
                         atomicAdd(&bs.queries, 1u);
                         if (b2.slot >= 0) {
                             flag_trapped(p, r);
@@ -648,6 +684,7 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Param
         n_units = (n_in + kTileRays - 1) / kTileRays;
     }
     int64_t tile = 0, tend = 0;  // wave-uniform claimed batch of tiles
+    int a_lo = 0, a_hi = 0;
     for (;;) {
         if (tile >= tend) {
             int64_t u = -1, e = 0;
@@ -657,13 +694,14 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Param
             if (u < 0) break;
             tile = u;
             tend = e;
+            if (SRC == 0) batch_angles(p, u, e, a_lo, a_hi);
         }
         const int64_t q = tile * kTileRays + lane;
         ++tile;
         Ray r;
         bool active;
         if (SRC == 0) {
-            active = grid_ray(p, q, r);
+            active = grid_ray(p, q, r, a_lo, a_hi);
         } else if (SRC == 1) {
             active = user_ray(p, q, r);
         } else {
@@ -693,7 +731,9 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Param
         }
         Best b;
         b.slot = -1;
-        if (active) b = closest(p, r, st);
+        SceneRef sc{0, 0.f, 0.f};
+        if (active) sc = scene_of(p, r);
+        if (active) b = closest(p, r, st, sc);
         if (active) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (active) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         bool cont = false;
@@ -701,11 +741,11 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Param
             if (b.slot >= 0) {
                 const K3 kv = kvec(p, r);
                 Last L;
-                cont = bounce(p, r, b, kv, L);
+                cont = bounce(p, r, b, kv, sc.eps, L);
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
                 sink_hit(p, r, b, L);
                 if (!cont && (p.flags & SBR_OPT_DROP_TRAPPED)) {
-                    const Best b2 = closest(p, r, st);
+                    const Best b2 = closest(p, r, st, sc);
                     atomicAdd(&bs.queries, 1u);
                     if (b2.slot >= 0) {
                         flag_trapped(p, r);
@@ -758,6 +798,8 @@ int check_tune(const sbr_tune &t)
     if (t.refill_min < 1 || t.refill_min > 64) return fail(SBR_ERR_INVALID_ARG, "sbr_tune: refill_min in [1, 64]");
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32)
         return fail(SBR_ERR_INVALID_ARG, "sbr_tune: blocks_per_cu in [0, 32]");
+    if (t.chunk_log2 != 0 && (t.chunk_log2 < 16 || t.chunk_log2 > 26))
+        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: chunk_log2 must be 0 or in [16, 26]");
     return SBR_OK;
 }
 
@@ -768,7 +810,7 @@ static Params make_params(const TraceArgs &a, int launch)
     p.tris = a.bvh->tris;
     p.nrm = a.bvh->nrm_slot;
     p.eps = a.bvh->eps;
-    p.slack = static_cast<float>(1e-6 * a.bvh->diag) + 1e-30f;
+    p.slack = box_slack(a.bvh->diag);
     p.bmax = a.bmax;
     p.flags = a.flags;
     p.plans = a.plans;

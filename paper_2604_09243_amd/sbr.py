@@ -8,6 +8,7 @@ fallback.
 """
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -20,7 +21,7 @@ POL_H, POL_V = 0, 1
 MODE_VECTOR, MODE_PAPER = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 REC_VALID, REC_TRAPPED, REC_BACK_LAST = 1, 2, 4
-OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRONT = 1, 2, 4, 8, 16
+OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRONT, OPT_NO_GRAPH = 1, 2, 4, 8, 16, 32
 MAX_BOUNCES = 64
 
 _vp = C.c_void_p
@@ -33,7 +34,8 @@ class BvhOpts(C.Structure):
 
 class BvhInfo(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_live", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32),
-                ("eps", C.c_float), ("bbox", C.c_double * 6), ("device_bytes", C.c_int64)]
+                ("eps", C.c_float), ("bbox", C.c_double * 6), ("device_bytes", C.c_int64), ("n_scenes", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Rays(C.Structure):
@@ -70,10 +72,11 @@ class PoDesc(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("schedule", C.c_int32), ("tile_w", C.c_int32),
-                ("claim_tiles", C.c_int32), ("refill_min", C.c_int32), ("blocks_per_cu", C.c_int32)]
+                ("claim_tiles", C.c_int32), ("refill_min", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("chunk_log2", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
 
 
 def default_tune():
@@ -94,6 +97,67 @@ class Sweep(C.Structure):
                 ("freqs_hz", _vp), ("n_freq", C.c_int32), ("max_bounces", C.c_int32), ("ds", C.c_double),
                 ("samples_per_lambda", C.c_double), ("eta", C.c_double), ("mode", C.c_int32),
                 ("flags", C.c_uint32), ("tune", C.POINTER(Tune))]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("scene", C.c_int32), ("n_freq", C.c_int32), ("freq_offset", C.c_int64),
+                ("theta_deg", C.c_double), ("phi_deg", C.c_double), ("ds", C.c_double)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("items", C.POINTER(BatchItem)), ("n_items", C.c_int64),
+                ("freqs_hz", _vp), ("n_freqs_total", C.c_int64), ("max_bounces", C.c_int32), ("mode", C.c_int32),
+                ("flags", C.c_uint32), ("reserved", C.c_int32), ("samples_per_lambda", C.c_double),
+                ("eta", C.c_double), ("tune", C.POINTER(Tune))]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("n_items", C.c_int64), ("n_rows", C.c_int64), ("rays", C.c_int64), ("min_item_rays", C.c_int64),
+                ("max_item_rays", C.c_int64), ("n_chunks", C.c_int32), ("graph_ready", C.c_int32),
+                ("device_bytes", C.c_int64), ("tune", Tune)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "tune"}
+        d["tune"] = self.tune.as_dict()
+        return d
+
+
+ACT_SILU, ACT_RELU = 0, 1
+
+
+class MlpDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_ff", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
+                ("act", C.c_int32), ("reserved", C.c_int32), ("ff_sigma", C.c_double), ("seed", C.c_uint64),
+                ("lo", _d3), ("hi", _d3), ("out_scale", C.c_double)]
+
+
+class MlpInfo(C.Structure):
+    _fields_ = [("n_params", C.c_int64), ("n_ff", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
+                ("act", C.c_int32), ("out_scale", C.c_double), ("adam_steps", C.c_int64),
+                ("flops_per_point", C.c_double)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("epochs", C.c_int32), ("batch", C.c_int32), ("reserved", C.c_int32),
+                ("lr", C.c_double), ("lr_min", C.c_double), ("seed", C.c_uint64)]
+
+
+class FillDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("mode", C.c_int32), ("theta_deg", _vp), ("phi_deg", _vp),
+                ("n_angles", C.c_int64), ("freqs_hz", _vp), ("n_freq", C.c_int32), ("tile_angles", C.c_int32),
+                ("tile_freqs", C.c_int32), ("probes_per_tile", C.c_int32), ("probe_dir", _vp), ("probe_freq", _vp),
+                ("max_bounces", C.c_int32), ("flags", C.c_uint32), ("ds", C.c_double), ("eta", C.c_double),
+                ("tol_db", C.c_double), ("floor_db", C.c_double)]
+
+
+class FillStats(C.Structure):
+    _fields_ = [("tiles", C.c_int64), ("fallback_tiles", C.c_int64), ("points", C.c_int64),
+                ("fallback_points", C.c_int64), ("probe_points", C.c_int64), ("ms_predict", C.c_double),
+                ("ms_probe", C.c_double), ("ms_check", C.c_double), ("ms_fallback", C.c_double),
+                ("ms_total", C.c_double), ("sbr_rays", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class AnglePlan(C.Structure):
@@ -120,6 +184,24 @@ SIGNATURES = {
     "sbr_plan_angle": (C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(AnglePlan)]),
     "sbr_default_tune": (C.c_int, [C.POINTER(Tune)]),
     "sbr_autotune": (C.c_int, [_vp, _vp, C.POINTER(Sweep), C.POINTER(Tune)]),
+    "sbr_pack_scenes": (C.c_int, [_vp, C.POINTER(_vp), C.c_int, C.POINTER(_vp)]),
+    "sbr_batch_create": (C.c_int, [_vp, _vp, C.POINTER(BatchDesc), C.POINTER(_vp)]),
+    "sbr_batch_get_info": (C.c_int, [_vp, C.POINTER(BatchInfo)]),
+    "sbr_batch_set_tune": (C.c_int, [_vp, C.POINTER(Tune)]),
+    "sbr_batch_autotune": (C.c_int, [_vp, C.POINTER(Tune)]),
+    "sbr_batch_run": (C.c_int, [_vp, _vp, _vp, C.POINTER(Stats)]),
+    "sbr_batch_destroy": (None, [_vp]),
+    "sbr_mlp_create": (C.c_int, [_vp, C.POINTER(MlpDesc), C.POINTER(_vp)]),
+    "sbr_mlp_get_info": (C.c_int, [_vp, C.POINTER(MlpInfo)]),
+    "sbr_mlp_get_params": (C.c_int, [_vp, _vp, C.c_int64]),
+    "sbr_mlp_set_params": (C.c_int, [_vp, _vp, C.c_int64]),
+    "sbr_mlp_get_features": (C.c_int, [_vp, _vp]),
+    "sbr_mlp_set_scale": (C.c_int, [_vp, C.c_double]),
+    "sbr_mlp_predict": (C.c_int, [_vp, _vp, C.c_int64, _vp]),
+    "sbr_mlp_gradients": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, C.POINTER(C.c_float)]),
+    "sbr_mlp_train": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.POINTER(TrainOpts), _vp]),
+    "sbr_mlp_destroy": (None, [_vp]),
+    "sbr_surrogate_fill": (C.c_int, [_vp, _vp, _vp, C.POINTER(FillDesc), _vp, _vp, _vp, C.POINTER(FillStats)]),
 }
 
 _lib = None
@@ -183,6 +265,7 @@ class BVH:
         self.depth, self.eps = info.depth, info.eps
         self.bbox = np.array(info.bbox)
         self.device_bytes = info.device_bytes
+        self.n_scenes = info.n_scenes
 
     def normals(self):
         out = np.zeros((self.n_tris, 3), np.float32)
@@ -201,6 +284,151 @@ class BVH:
             pass
 
 
+class Batch:
+    """A planned batch (sbr_batch_create): ``run()`` replays its graph.
+
+    ``row_offset[i]`` is the first output row of item i; rows of item i are
+    its frequencies in order."""
+
+    def __init__(self, ctx, scenes, handle, n_freq):
+        self.ctx = ctx
+        self.scenes = scenes  # the scene set must outlive the batch
+        self.handle = handle
+        self.row_offset = np.concatenate([[0], np.cumsum(n_freq)[:-1]]).astype(np.int64)
+        self.n_freq = np.asarray(n_freq, np.int64)
+        self._out = None
+
+    def info(self):
+        i = BatchInfo()
+        _check(load_library().sbr_batch_get_info(self.handle, C.byref(i)))
+        return i.as_dict()
+
+    def set_tune(self, tune):
+        _check(load_library().sbr_batch_set_tune(self.handle, C.byref(tune)))
+
+    def autotune(self):
+        t = Tune()
+        _check(load_library().sbr_batch_autotune(self.handle, C.byref(t)))
+        return t
+
+    def run(self, stats=True, out=None):
+        """Returns (A complex128 [n_rows, 2, 2], sigma_dbsm [n_rows, 2, 2],
+        stats dict or None) as device tensors.  The output tensors are kept
+        and reused by later calls (so the captured graph is replayed)."""
+        torch = _torch()
+        if out is None:
+            if self._out is None:
+                n = int(self.info()["n_rows"])
+                dev = torch.device("cuda", self.ctx.device)
+                self._out = (torch.empty(n, 2, 2, 2, dtype=torch.float64, device=dev),
+                             torch.empty(n, 2, 2, dtype=torch.float64, device=dev))
+            out = self._out
+        A, S = out
+        st = Stats() if stats else None
+        _check(load_library().sbr_batch_run(self.handle, A.data_ptr(), S.data_ptr() if S is not None else None,
+                                            C.byref(st) if stats else None))
+        return torch.view_as_complex(A), S, (st.as_dict() if stats else None)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sbr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The surrogate network (sbr_mlp_*).  Points are (theta_deg, phi_deg,
+    f_hz) rows; fields are complex (A_HH, A_VV) pairs."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    def info(self):
+        i = MlpInfo()
+        _check(load_library().sbr_mlp_get_info(self.handle, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in MlpInfo._fields_}
+
+    def params(self):
+        n = self.info()["n_params"]
+        out = np.zeros(n, np.float32)
+        _check(load_library().sbr_mlp_get_params(self.handle, out.ctypes.data, n))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(load_library().sbr_mlp_set_params(self.handle, p.ctypes.data, len(p)))
+
+    def features(self):
+        n = self.info()["n_ff"]
+        out = np.zeros((n, 3), np.float32)
+        _check(load_library().sbr_mlp_get_features(self.handle, out.ctypes.data))
+        return out
+
+    def set_scale(self, scale):
+        _check(load_library().sbr_mlp_set_scale(self.handle, float(scale)))
+
+    def _dev(self, x, dtype):
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        if isinstance(x, torch.Tensor):
+            return x.to(dev, dtype).contiguous()
+        return torch.from_numpy(np.ascontiguousarray(x)).to(dev, dtype).contiguous()
+
+    def predict(self, pts):
+        """pts [n, 3] -> complex128 device tensor [n, 2]."""
+        torch = _torch()
+        p = self._dev(pts, torch.float64)
+        n = p.shape[0]
+        A = torch.empty(n, 2, 2, dtype=torch.float64, device=p.device)
+        _check(load_library().sbr_mlp_predict(self.handle, p.data_ptr(), n, A.data_ptr()))
+        return torch.view_as_complex(A)
+
+    def _targets(self, t):
+        torch = _torch()
+        if isinstance(t, torch.Tensor) and t.is_complex():
+            t = torch.view_as_real(t.to(torch.complex128))
+        elif not isinstance(t, torch.Tensor) and np.iscomplexobj(t):
+            t = np.stack([np.real(t), np.imag(t)], axis=-1)
+        return self._dev(t, torch.float64)
+
+    def gradients(self, pts, targets):
+        """(grads float32 numpy [n_params], loss) for the points."""
+        torch = _torch()
+        p, t = self._dev(pts, torch.float64), self._targets(targets)
+        g = torch.empty(self.info()["n_params"], dtype=torch.float32, device=p.device)
+        loss = C.c_float()
+        _check(load_library().sbr_mlp_gradients(self.handle, p.data_ptr(), t.data_ptr(), p.shape[0], g.data_ptr(),
+                                                C.byref(loss)))
+        return g.cpu().numpy(), loss.value
+
+    def train(self, pts, targets, epochs, batch=1024, lr=1e-3, lr_min=1e-5, seed=0):
+        """Adam training; returns the mean loss of every epoch."""
+        torch = _torch()
+        p, t = self._dev(pts, torch.float64), self._targets(targets)
+        o = TrainOpts(C.sizeof(TrainOpts), int(epochs), int(batch), 0, float(lr), float(lr_min), int(seed))
+        hist = np.zeros(int(epochs), np.float32)
+        _check(load_library().sbr_mlp_train(self.handle, p.data_ptr(), t.data_ptr(), p.shape[0], C.byref(o),
+                                            hist.ctypes.data))
+        return hist
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sbr_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """An sbr_ctx on ``device`` enqueuing on torch's current stream."""
 
@@ -214,7 +442,7 @@ class Context:
         h = C.c_void_p()
         _check(L.sbr_create(C.byref(h), int(device), C.c_void_p(s.cuda_stream)))
         self.handle = h
-
+        self._batches = weakref.WeakSet()  # closed before the context
     def set_stream(self, stream):
         self.stream = stream
         _check(load_library().sbr_set_stream(self.handle, C.c_void_p(stream.cuda_stream)))
@@ -224,6 +452,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for b in list(getattr(self, "_batches", ())):
+                b.close()
             load_library().sbr_destroy(self.handle)
             self.handle = None
 
@@ -348,3 +578,69 @@ class Context:
                                             S.data_ptr() if S is not None else None,
                                             C.byref(st) if stats else None))
         return torch.view_as_complex(A), S, (st.as_dict() if stats else None)
+
+    # ------------------------------------------------------------ batches
+    def pack_scenes(self, bvhs):
+        """One multi-scene set from several BVHs (sbr_pack_scenes)."""
+        arr = (_vp * len(bvhs))(*[b.handle for b in bvhs])
+        h = C.c_void_p()
+        _check(load_library().sbr_pack_scenes(self.handle, arr, len(bvhs), C.byref(h)))
+        return BVH(self, h)
+
+    def batch(self, scenes, items, freqs_hz, max_bounces=6, samples_per_lambda=10.0, eta=0.1, mode=MODE_VECTOR,
+              flags=0, tune=None):
+        """Plans a batch.  ``items``: sequence of (scene, theta_deg, phi_deg,
+        freq_offset, n_freq[, ds]) tuples; ``freqs_hz`` the frequency array
+        the offsets index."""
+        fr = np.ascontiguousarray(np.atleast_1d(freqs_hz), dtype=np.float64)
+        arr = (BatchItem * len(items))()
+        nf = []
+        for i, it in enumerate(items):
+            sc, th, ph, off, n = it[:5]
+            ds = it[5] if len(it) > 5 else 0.0
+            arr[i] = BatchItem(int(sc), int(n), int(off), float(th), float(ph), float(ds))
+            nf.append(int(n))
+        d = BatchDesc(C.sizeof(BatchDesc), arr, len(items), fr.ctypes.data, len(fr), int(max_bounces), int(mode),
+                      int(flags), 0, float(samples_per_lambda), float(eta),
+                      C.pointer(tune) if tune is not None else None)
+        h = C.c_void_p()
+        _check(load_library().sbr_batch_create(self.handle, scenes.handle, C.byref(d), C.byref(h)))
+        b = Batch(self, scenes, h, nf)
+        self._batches.add(b)
+        return b
+
+    # ------------------------------------------------------------ surrogate
+    def mlp(self, lo, hi, out_scale=1.0, n_ff=64, width=256, depth=4, act=ACT_SILU, ff_sigma=4.0, seed=0):
+        """A new surrogate network (sbr_mlp_create)."""
+        d = MlpDesc(C.sizeof(MlpDesc), int(n_ff), int(width), int(depth), int(act), 0, float(ff_sigma), int(seed),
+                    _d3(*map(float, lo)), _d3(*map(float, hi)), float(out_scale))
+        h = C.c_void_p()
+        _check(load_library().sbr_mlp_create(self.handle, C.byref(d), C.byref(h)))
+        return MLP(self, h)
+
+    def surrogate_fill(self, bvh, mlp, theta_deg, phi_deg, freqs_hz, tile_angles, tile_freqs, probe_dir,
+                       probe_freq, ds, max_bounces=8, mode=MODE_VECTOR, flags=0, eta=0.1, tol_db=0.5,
+                       floor_db=40.0):
+        """Dense grid fill (sbr_surrogate_fill).  Returns (A complex128
+        device [n_angles, n_freq, 2], tile_err [n_at, n_ft], fallback mask,
+        stats dict)."""
+        torch = _torch()
+        th = np.ascontiguousarray(theta_deg, dtype=np.float64)
+        ph = np.ascontiguousarray(phi_deg, dtype=np.float64)
+        fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
+        pdir = np.ascontiguousarray(probe_dir, dtype=np.float64).reshape(-1, 2)
+        pfr = np.ascontiguousarray(probe_freq, dtype=np.float64).ravel()
+        na, nf = len(th), len(fr)
+        n_at = (na + tile_angles - 1) // tile_angles
+        n_ft = (nf + tile_freqs - 1) // tile_freqs
+        ppt = len(pfr) // n_ft
+        d = FillDesc(C.sizeof(FillDesc), int(mode), th.ctypes.data, ph.ctypes.data, na, fr.ctypes.data, nf,
+                     int(tile_angles), int(tile_freqs), int(ppt), pdir.ctypes.data, pfr.ctypes.data,
+                     int(max_bounces), int(flags), float(ds), float(eta), float(tol_db), float(floor_db))
+        A = torch.empty(na, nf, 2, 2, dtype=torch.float64, device=torch.device("cuda", self.device))
+        err = np.zeros((n_at, n_ft), np.float64)
+        fb = np.zeros((n_at, n_ft), np.uint8)
+        st = FillStats()
+        _check(load_library().sbr_surrogate_fill(self.handle, bvh.handle, mlp.handle, C.byref(d), A.data_ptr(),
+                                                 err.ctypes.data, fb.ctypes.data, C.byref(st)))
+        return torch.view_as_complex(A), err, fb, st.as_dict()

@@ -10,7 +10,9 @@ from .meshes import (icosphere, plate, dihedral, trihedral, aircraft,
                      random_triangles, mesh_area)
 from .workloads import (C_LIGHT, sphere_case, trihedral_case, aircraft_case,
                         random_rays, Workload)
+from .batch import batch_case, BatchWorkload, Scene, ellipsoid
 
 __all__ = ["icosphere", "plate", "dihedral", "trihedral", "aircraft",
            "random_triangles", "mesh_area", "C_LIGHT", "sphere_case",
-           "trihedral_case", "aircraft_case", "random_rays", "Workload"]
+           "trihedral_case", "aircraft_case", "random_rays", "Workload",
+           "batch_case", "BatchWorkload", "Scene", "ellipsoid"]

@@ -38,14 +38,43 @@ def test_version_and_error_string(lib):
     assert isinstance(lib.sbr_last_error(), bytes)
 
 
-def test_struct_sizes_match_header():
-    # sizes of the option structs as laid out by a C compiler for this header
+# binding struct name -> header typedef
+STRUCTS = {"BvhOpts": "sbr_bvh_opts", "BvhInfo": "sbr_bvh_info", "Rays": "sbr_rays", "Hits": "sbr_hits",
+           "TraceOpts": "sbr_trace_opts", "Stats": "sbr_stats", "PoDesc": "sbr_po_desc", "Tune": "sbr_tune",
+           "Sweep": "sbr_sweep", "BatchItem": "sbr_batch_item", "BatchDesc": "sbr_batch_desc",
+           "BatchInfo": "sbr_batch_info", "AnglePlan": "sbr_angle_plan", "MlpDesc": "sbr_mlp_desc",
+           "MlpInfo": "sbr_mlp_info", "TrainOpts": "sbr_train_opts", "FillDesc": "sbr_fill_desc",
+           "FillStats": "sbr_fill_stats"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof and every field offset of the ctypes mirrors equal what a C
+    compiler lays out for include/sbr.h."""
+    import subprocess
     from paper_2604_09243_amd import sbr
-    assert ctypes.sizeof(sbr.Sweep) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 8
-    assert ctypes.sizeof(sbr.Tune) == 24
-    assert ctypes.sizeof(sbr.Stats) == 8 * (4 + 65 + 1) + 8 * 3 + 8 * 65 * 2 + 8 * 6
-    assert ctypes.sizeof(sbr.PoDesc) == 8 + 8 * 10
-    assert ctypes.sizeof(sbr.AnglePlan) == 8 * 13 + 16
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sbr.h"', "int main(void) {"]
+    for py, c in STRUCTS.items():
+        cls = getattr(sbr, py)
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (py, c))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (py, f, c, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            a, b, v = ln.split()
+            got[(a, b)] = int(v)
+    for py in STRUCTS:
+        cls = getattr(sbr, py)
+        assert got[(py, "size")] == ctypes.sizeof(cls), py
+        for f, _ in cls._fields_:
+            assert got[(py, f)] == getattr(cls, f).offset, (py, f)
+    assert set(STRUCTS.values()) == set(re.findall(r"\}\s*(sbr_[a-z_]+)\s*;", open(HEADER).read())) - {"sbr_status"}
 
 
 @pytest.mark.parametrize("bbox,th,ph,ds", [
@@ -69,7 +98,7 @@ def test_plan_matches_oracle_exactly(orc, bbox, th, ph, ds):
 def test_default_tune():
     from paper_2604_09243_amd import sbr
     t = sbr.default_tune().as_dict()
-    assert t == dict(schedule=0, tile_w=8, claim_tiles=4, refill_min=64, blocks_per_cu=0)
+    assert t == dict(schedule=0, tile_w=8, claim_tiles=4, refill_min=64, blocks_per_cu=0, chunk_log2=26)
 
 
 def test_plan_rejects_bad_spacing():
