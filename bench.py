@@ -5,13 +5,14 @@ Workload: square trihedral corner reflector (a = 1 m, 1,536 triangles),
 10 GHz, elevation 35.26 deg, azimuth 0..90 deg in 0.5 deg steps (181 angles),
 ray spacing lambda/10 (48,377,932 rays in all), at most 5 bounces, VECTOR PO
 (all four H/V pairs from one trace).  One step = the whole path for the
-sweep: mesh preparation and BVH build, ray generation, multi-bounce
-transport, PO sum and RCS for all 181 angles.
+sweep: mesh preparation and BVH build (host binned SAH by default, GPU LBVH
+with --builder lbvh), ray generation, multi-bounce transport, PO sum and RCS
+for all 181 angles.
 
 Prints one JSON line.  ``value`` is closest-hit queries (rays x bounces) per
 second over the timed steps; angles/s is reported beside it.  ``roofline``
 prices the dominant trace kernel by the reference traversal work of the
-oracle's SAH tree (see DESIGN.md) against the non-packed VALU issue rate;
+oracle's SAH tree against the non-packed VALU issue rate;
 ``cpu_baseline`` times the CPU oracle (brute force, as it stands) on a
 bounded sample of the same sweep.
 """
@@ -48,7 +49,11 @@ C_BOX, C_TRI, C_QUERY, C_HIT = 15, 66, 12, 80
 # non-packed VALU issue (the 157.3 TFLOP/s fp32 figure counts packed FMA as 4).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-PMC_FILE = os.path.join(ROOT, "profiles", "trace_trihedral_pmc.json")
+def pmc_file(builder):
+    return os.path.join(ROOT, "profiles", "trace_trihedral_%s_pmc.json" % builder)
+
+
+BUILDER_SOURCE = {"lbvh": "lbvh.hip", "sah": "sah.cpp"}
 
 
 def work_per_query(b):
@@ -56,24 +61,27 @@ def work_per_query(b):
     return box * C_BOX + tri * C_TRI + C_QUERY + hit * C_HIT
 
 
-def source_hash():
+def source_hash(builder):
+    """Hash of the sources the trace kernel's memory traffic depends on: the
+    kernel and the builder that lays out its tree."""
     h = hashlib.sha256()
-    for f in ("trace.hip", "sbr_internal.hpp"):
+    for f in ("trace.hip", BUILDER_SOURCE[builder]):
         with open(os.path.join(ROOT, "paper_2604_09243_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(kernel, launches_per_step):
+def pmc_traffic(kernel, builder):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, scaled by the plain-copy calibration; None if absent or if the
-    trace source changed since the counters were taken."""
+    summary of this builder's tree, scaled by the plain-copy calibration;
+    None if absent or if the trace or builder source changed since the
+    counters were taken."""
     try:
-        with open(PMC_FILE) as f:
+        with open(pmc_file(builder)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != source_hash() or kernel not in d.get("kernels", {}):
+    if d.get("source_hash") != source_hash(builder) or kernel not in d.get("kernels", {}):
         return None
     k = d["kernels"][kernel]
     return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0
@@ -119,15 +127,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=("trihedral", "batch"), default="trihedral",
+    ap.add_argument("--workload", choices=("trihedral", "batch", "surrogate", "mlp"), default="trihedral",
                     help="trihedral: the 181-angle sweep (default); batch: the 64-scene uneven batch, one graph "
-                         "replay per step (a secondary measurement)")
+                         "replay per step; surrogate: surrogate-plus-fallback fill vs plain SBR on a "
+                         "3600 x 512 grid; mlp: network inference and training throughput (secondary "
+                         "measurements)")
+    ap.add_argument("--target", choices=("trihedral", "aircraft"), default="trihedral",
+                    help="surrogate: band-limited trihedral or the procedural aircraft")
     ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch parameters first")
+    ap.add_argument("--builder", choices=("lbvh", "sah"), default="sah",
+                    help="BVH builder of each step: host binned SAH (default; fewer node and triangle tests "
+                         "per ray) or the GPU LBVH")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: every incidence angle is independent, so a sweep shards by "
-              "angle with no communication beyond gathering the per-angle results (DESIGN.md, sharding); "
+              "angle with no communication beyond gathering the per-angle results; "
               "no multi-GPU figure is measured here.", file=sys.stderr)
         sys.exit(2)
 
@@ -152,11 +167,17 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
+    if args.workload == "mlp":
+        return bench_mlp(args)
     w = si.trihedral_case()
     ctx = Context(0)
 
+    builder = 1 if args.builder == "sah" else 0
+
     def step():
-        bvh = ctx.build_bvh(w.V, w.T)
+        bvh = ctx.build_bvh(w.V, w.T, builder=builder)
         A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
                                  samples_per_lambda=w.samples_per_lambda)
         bvh.free()
@@ -186,7 +207,7 @@ def main():
     t_kernel = sum(s["ms_trace"] for s in stats) * 1e-3
     launches = args.steps
     achieved = work / t_kernel
-    traffic = pmc_traffic("k_stream", 1)
+    traffic = pmc_traffic("k_stream", args.builder)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlaneop/s",
                 "frac": achieved / PEAK_LANE_OPS, "traffic": traffic, "kernel": "k_stream<0> (all bounces, angle grid)",
                 "avg_launch_ms": 1e3 * t_kernel / launches, "work_per_launch_lane_ops": work / launches}
@@ -205,6 +226,7 @@ def main():
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": w.name + "_181az_lambda10_b5", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
+                   "bvh": args.builder,
                    "polarisations": "HH,HV,VH,VV"},
         "angles_per_s": angles / dt,
         "trace_ms_per_step": sum(s["ms_trace"] for s in stats) / args.steps,
@@ -228,7 +250,7 @@ def bench_batch(args):
     t0 = time.perf_counter()
     w = si.batch_case()
     ctx = Context(0)
-    bvhs = [ctx.build_bvh(s.V, s.T) for s in w.scenes]
+    bvhs = [ctx.build_bvh(s.V, s.T, builder=1 if args.builder == "sah" else 0) for s in w.scenes]
     scn = ctx.pack_scenes(bvhs)
     for b in bvhs:
         b.free()
@@ -256,11 +278,134 @@ def bench_batch(args):
                    "rows": info["n_rows"], "rays_per_step": info["rays"], "queries_per_step": stats[-1]["queries"],
                    "triangles": int(scn.n_tris), "min_item_rays": info["min_item_rays"],
                    "max_item_rays": info["max_item_rays"], "chunks": info["n_chunks"], "tune": tune,
-                   "mode": "VECTOR"},
+                   "mode": "VECTOR", "bvh": args.builder},
         "items_per_s": info["n_items"] * args.steps / dt,
         "rows_per_s": info["n_rows"] * args.steps / dt,
         "graph_ms_per_step": sum(s["ms_total"] for s in stats) / args.steps,
         "setup_s": t_setup,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _copol_db(A):
+    """sigma (dBsm) of (HH, VV) of an [..., 2] or [..., 2, 2] complex array."""
+    if A.ndim >= 2 and A.shape[-2:] == (2, 2):
+        A = np.stack([A[..., 0, 0], A[..., 1, 1]], axis=-1)
+    return 10 * np.log10(np.maximum(4 * np.pi * np.abs(A) ** 2, 1e-300))
+
+
+def bench_surrogate(args):
+    """Dense grid 0.1 deg x 512 frequencies (3600 x 512 points, 8-12 GHz,
+    ray spacing lambda(12 GHz)/8) filled two ways on the same GPU: plain SBR
+    (one trace per direction + 512-frequency PO) and the surrogate pipeline
+    (SBR training sweep at 1 deg x 64 frequencies, training, inference, SBR
+    probes per tile of 1 deg x 32 frequencies, SBR fallback on failing
+    tiles).  Steps alternate the two; the error is audited on every grid
+    point against the plain result."""
+    import torch
+    import sbr_inputs as si
+    from paper_2604_09243_amd import Context, pipeline
+    C0 = 299_792_458.0
+    ctx = Context(0)
+    if args.target == "trihedral":
+        V, T = si.trihedral(1.0, 16)
+        th0, bm = 54.74, 5
+    else:
+        w = si.aircraft_case()
+        V, T = w.V, w.T
+        th0, bm = 90.0, 8
+    bvh = ctx.build_bvh(V, T)
+    ds = C0 / 12e9 / 8
+    train = (np.full(360, th0), np.arange(360.0), np.linspace(8e9, 12e9, 64))
+    query = (np.full(3600, th0), np.arange(3600) * 0.1, np.linspace(8e9, 12e9, 512))
+    kw = dict(net_kw=dict(ff_sigma=2.0, seed=1), train_kw=dict(epochs=100, batch=4096, lr=3e-3, lr_min=3e-5, seed=0),
+              tile_angles=10, tile_freqs=32, tol_db=0.25, floor_db=40.0)
+    for _ in range(args.warmup):
+        pipeline.surrogate_fill(ctx, bvh, train, query, ds, bm, **kw)
+        ctx.rcs_sweep(bvh, *query, bm, ds=ds, stats=False)
+    t_sur, t_plain = [], []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A, info = pipeline.surrogate_fill(ctx, bvh, train, query, ds, bm, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Ap, _, st = ctx.rcs_sweep(bvh, *query, bm, ds=ds)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_sur.append(t1 - t0)
+        t_plain.append(t2 - t1)
+    sp = _copol_db(Ap.cpu().numpy())
+    ss = _copol_db(A.cpu().numpy())
+    n = sp.shape[0] * sp.shape[1]
+    audit = {}
+    for fl in (20, 30, 40):
+        sel = sp >= sp.max() - fl
+        e = np.abs(ss - sp)[sel]
+        audit["floor_%ddB" % fl] = dict(frac_points=float(sel.mean()), p50=float(np.median(e)),
+                                        p99=float(np.percentile(e, 99)), max=float(e.max()),
+                                        within_0p5dB=float(np.mean(e <= 0.5)))
+    fb = info["fallback"]
+    ts, tp = float(np.median(t_sur)), float(np.median(t_plain))
+    out = {
+        "metric": METRIC, "value": n / ts, "unit": "grid points/s (surrogate + fallback)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * ts, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 MFMA (fp32 accumulation) + SBR f32/f64",
+        "data": "synthetic (seeded procedural mesh)",
+        "config": {"workload": "surrogate_%s_3600x512" % args.target, "train": "360 x 64", "query": "3600 x 512",
+                   "tiles": "1 deg x 32 f", "probes": "1 direction x 2 f per tile", "tol_db": 0.25,
+                   "floor_db": 40.0, "audit_floor_db": 30.0, "epochs": 100, "batch": 4096},
+        "plain_points_per_s": n / tp, "plain_ms": 1e3 * tp, "gain": tp / ts,
+        "fallback_tile_frac": float(fb.mean()), "stage_s": {k: v for k, v in info.items() if k.startswith("s_")},
+        "fill_ms": {k: v for k, v in info["fill"].items() if k.startswith("ms_")},
+        "final_loss": float(info["loss"][-1]), "audit_vs_plain": audit,
+        "plain_trace_ms": st["ms_trace"], "plain_po_ms": st["ms_po"], "plain_rays": st["rays"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_mlp(args):
+    """The surrogate network alone: inference over the 3600 x 512 query grid
+    (1,843,200 points) and training steps on the 360 x 64 training set,
+    against the bf16 dense MFMA peak (2.5 PFLOP/s)."""
+    import torch
+    from paper_2604_09243_amd import Context, pipeline
+    ctx = Context(0)
+    net = ctx.mlp([0, 0, 8e9], [180, 360, 12e9], out_scale=1.0, ff_sigma=2.0, seed=3)
+    info = net.info()
+    pts = torch.from_numpy(pipeline.grid_points(np.full(3600, 90.0), np.arange(3600) * 0.1,
+                                                np.linspace(8e9, 12e9, 512))).cuda()
+    M = pts.shape[0]
+    for _ in range(args.warmup):
+        net.predict(pts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.predict(pts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    flops = info["flops_per_point"] * M
+    tp = torch.from_numpy(pipeline.grid_points(np.full(360, 90.0), np.arange(360.0),
+                                               np.linspace(8e9, 12e9, 64))).cuda()
+    tg = torch.randn(tp.shape[0], 2, dtype=torch.complex128, device="cuda")
+    net.train(tp, tg, epochs=2, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    epochs = 20
+    net.train(tp, tg, epochs=epochs, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    dtt = time.perf_counter() - t0
+    steps = epochs * ((tp.shape[0] + 4095) // 4096)
+    out = {
+        "metric": "surrogate inference points/s", "value": M / dt, "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulation)", "data": "synthetic",
+        "config": {"workload": "mlp_ff64_4x256_grid_3600x512", "params": info["n_params"],
+                   "flops_per_point": info["flops_per_point"]},
+        "roofline": {"bound": "mfma", "achieved": flops / dt / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flops / dt / 2.5e15, "traffic": None},
+        "train_ms_per_step": 1e3 * dtt / steps, "train_batch": 4096,
+        "train_tflops": 3 * info["flops_per_point"] * 4096 * steps / dtt / 1e12,
     }
     print(json.dumps(out), flush=True)
 

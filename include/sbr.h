@@ -112,10 +112,15 @@ void sbr_destroy(sbr_ctx *ctx);
 /* paper's host-built Algorithm 1 is replaced by a GPU LBVH)                 */
 /* ------------------------------------------------------------------------ */
 
+enum { SBR_BUILD_LBVH = 0, SBR_BUILD_SAH = 1 };
+
 typedef struct {
     uint32_t struct_size;
     int32_t mem;       /* SBR_MEM_HOST or SBR_MEM_DEVICE: where verts/tris live */
     int32_t leaf_size; /* triangles per leaf, 1..4 (subtrees that small become leaves); 0 = 4 */
+    int32_t builder;   /* SBR_BUILD_LBVH: Morton-code LBVH on the GPU (default);
+                          SBR_BUILD_SAH: binned surface-area-heuristic build on the host (Algorithm 1
+                          with its SAH cost), slower to build, fewer node and triangle tests per ray */
 } sbr_bvh_opts;
 
 typedef struct {

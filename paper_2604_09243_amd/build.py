@@ -14,8 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(ROOT, "_build", "sbr")
 LIB = os.path.join(HERE, "libsbr.so")
-SOURCES = ["api.cpp", "batch.cpp", "surrogate.cpp", "mesh_prep.cpp", "plan.cpp", "lbvh.hip", "trace.hip", "po.hip",
-           "scene.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "surrogate.cpp", "mesh_prep.cpp", "plan.cpp", "sah.cpp", "lbvh.hip", "trace.hip",
+           "po.hip", "scene.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SBR_OFFLOAD_ARCH", "gfx950")

@@ -224,6 +224,16 @@ void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p)
     p.pad_ = 0;
 }
 
+double uniform_step(const double *kf, int n)
+{
+    if (n < 2) return 0.0;
+    const double dk = (kf[n - 1] - kf[0]) / (n - 1);
+    if (!(dk != 0.0)) return 0.0;
+    for (int i = 1; i < n - 1; ++i)
+        if (std::fabs(kf[i] - (kf[0] + i * dk)) > 1e-14 * std::fabs(kf[i])) return 0.0;
+    return dk;
+}
+
 int log2i(int x)
 {
     int s = 0;
@@ -309,13 +319,16 @@ extern "C" int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, 
     *out = nullptr;
     if (n_tris < 1 || n_tris > (int64_t(1) << 28) || n_verts < 3 || n_verts > (int64_t(1) << 31) - 1)
         return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: n_tris must be in [1, 2^28] and n_verts >= 3");
-    int mem = SBR_MEM_HOST, leaf = 4;
+    int mem = SBR_MEM_HOST, leaf = 4, builder = SBR_BUILD_LBVH;
     if (opts) {
         if (opts->struct_size < sizeof(sbr_bvh_opts))
             return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: opts->struct_size too small");
         mem = opts->mem;
         if (opts->leaf_size != 0) leaf = opts->leaf_size;
+        builder = opts->builder;
     }
+    if (builder != SBR_BUILD_LBVH && builder != SBR_BUILD_SAH)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: unknown builder");
     if (leaf < 1 || leaf > 4) return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: leaf_size must be in [0, 4]");
     if (mem != SBR_MEM_HOST && mem != SBR_MEM_DEVICE)
         return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: opts->mem must be SBR_MEM_HOST or SBR_MEM_DEVICE");
@@ -344,7 +357,7 @@ extern "C" int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, 
     b->diag = pm.diag;
     std::memcpy(b->bbox, pm.bbox, sizeof(pm.bbox));
     b->leaf_size = leaf;
-    rc = build_lbvh(ctx, pm, leaf, b);
+    rc = builder == SBR_BUILD_SAH ? build_sah(ctx, pm, leaf, b) : build_lbvh(ctx, pm, leaf, b);
     if (rc) {
         sbr_free_bvh(b);
         return rc;
@@ -517,6 +530,11 @@ extern "C" int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits
     ang.out_base = 0;
     ang.kf_off = 0;
     ang.n_f = n_freq;
+    {
+        std::vector<double> kfv(n_freq);
+        for (int f = 0; f < n_freq; ++f) kfv[f] = 2.0 * kPi * freqs_hz[f] / kC0;
+        ang.dk = uniform_step(kfv.data(), n_freq);
+    }
     const int64_t units = po_units(n_rays);
     Records rec;
     void *pang, *pkf, *ppart, *ph;
@@ -643,6 +661,13 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         q.out_base = a * nf;
         q.kf_off = 0;
         q.n_f = nf;
+        q.dk = 0.0;
+    }
+    {
+        std::vector<double> kfv(nf);
+        for (int f = 0; f < nf; ++f) kfv[f] = 2.0 * kPi * sw->freqs_hz[f] / kC0;
+        const double dk = uniform_step(kfv.data(), nf);
+        for (auto &q : pang) q.dk = dk;
     }
     // chunks of consecutive angles holding at most chunk_cap rays (or one angle)
     std::vector<int64_t> cstart;

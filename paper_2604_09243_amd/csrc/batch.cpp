@@ -145,6 +145,8 @@ int plan_batch(sbr_batch *b)
     const int64_t cap = int64_t(1) << b->tune.chunk_log2;
     std::vector<AnglePlan> plans(ni);
     std::vector<PoAngle> ang(ni);
+    std::vector<double> kf(b->freqs.size());
+    for (size_t f = 0; f < kf.size(); ++f) kf[f] = 2.0 * kPi * b->freqs[f] / kC0;
     for (int64_t i = 0; i < ni; ++i) {
         const sbr_batch_item &it = b->items[i];
         const sbr_angle_plan &ap = b->hplan[i];
@@ -165,6 +167,7 @@ int plan_batch(sbr_batch *b)
         q.out_base = b->out_base[i];
         q.kf_off = static_cast<int32_t>(it.freq_offset);
         q.n_f = it.n_freq;
+        q.dk = uniform_step(kf.data() + it.freq_offset, it.n_freq);
     }
     b->cstart.clear();
     b->c_tiles.clear();
@@ -238,8 +241,6 @@ int plan_batch(sbr_batch *b)
         b->qa = RayQueue{};
         b->qb = RayQueue{};
     }
-    std::vector<double> kf(b->freqs.size());
-    for (size_t f = 0; f < kf.size(); ++f) kf[f] = 2.0 * kPi * b->freqs[f] / kC0;
     SBR_HIP(hipMemcpy(b->d_plans, plans.data(), sizeof(AnglePlan) * ni, hipMemcpyHostToDevice));
     SBR_HIP(hipMemcpy(b->d_tile, tb.data(), 8 * tile_words, hipMemcpyHostToDevice));
     SBR_HIP(hipMemcpy(b->d_ang, ang.data(), sizeof(PoAngle) * ni, hipMemcpyHostToDevice));

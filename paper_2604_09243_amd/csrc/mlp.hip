@@ -68,11 +68,14 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
     const int m0 = blockIdx.x * kTileM + (wv & 1) * 32;
     const int n0 = blockIdx.y * kTileN + (wv >> 1) * 64;
     const int r = lane & 31, kh = (lane >> 5) * 8;
-    const uint16_t *pa = g.A + static_cast<int64_t>(m0 + r) * g.lda + kh;
-    const uint16_t *pb0 = g.B + static_cast<int64_t>(n0 + r) * g.ldb + kh;
-    const uint16_t *pb1 = g.B + static_cast<int64_t>(n0 + 32 + r) * g.ldb + kh;
+    // split-K (kEpiF32): block z sums k in [z Kc, (z + 1) Kc) into slice z of fout
+    const int kc = g.K / g.ksplit, kb = blockIdx.z * kc;
+    const uint16_t *pa = g.A + static_cast<int64_t>(m0 + r) * g.lda + kh + kb;
+    const uint16_t *pb0 = g.B + static_cast<int64_t>(n0 + r) * g.ldb + kh + kb;
+    const uint16_t *pb1 = g.B + static_cast<int64_t>(n0 + 32 + r) * g.ldb + kh + kb;
+    float *fout = g.fout ? g.fout + blockIdx.z * g.split_stride : nullptr;
     f32x16 acc0 = {}, acc1 = {};
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int k0 = 0; k0 < kc; k0 += 16) {
         const bf16x8 a = *reinterpret_cast<const bf16x8 *>(pa + k0);
         const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0 + k0);
         const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0);
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
                 g.hout[static_cast<int64_t>(m) * g.ldh + n] = h;
                 g.htout[static_cast<int64_t>(n) * g.ldht + m] = h;
             } else {
-                g.fout[static_cast<int64_t>(m) * g.ldf + n] = v;
+                fout[static_cast<int64_t>(m) * g.ldf + n] = v;
             }
         }
     }
@@ -210,33 +213,62 @@ __global__ void k_out_back(const float *__restrict__ dy, const uint16_t *__restr
     dzbt[static_cast<int64_t>(k) * Mrows + m] = b;
 }
 
-// Output-layer gradients: dW_out[o][k] = sum_m dy[m][o] h[m][k] and
-// db_out[o] = sum_m dy[m][o], summed in row order.
-__global__ void k_out_wgrad(const float *__restrict__ dy, const uint16_t *__restrict__ h, int width, int64_t Mrows,
-                            float *__restrict__ gw, float *__restrict__ gb)
+// Output-layer gradient partials of rows [64 y, 64 y + 64) (block y):
+// pw[y][o][k] = sum dy[m][o] h[m][k], pb[y][o] = sum dy[m][o]; 256 threads =
+// 4 row phases x 64 columns, combined in a fixed order.
+__global__ __launch_bounds__(256) void k_out_wgrad_part(const float *__restrict__ dy, const uint16_t *__restrict__ h,
+                                                        int width, int64_t Mrows, float *__restrict__ pw,
+                                                        float *__restrict__ pb)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 4 * width) {
-        const int o = i / width, k = i % width;
-        float s = 0.f;
-        for (int64_t m = 0; m < Mrows; ++m) s += dy[4 * m + o] * from_bf16(h[m * width + k]);
-        gw[i] = s;
-    } else if (i < 4 * width + 4) {
-        const int o = i - 4 * width;
-        float s = 0.f;
-        for (int64_t m = 0; m < Mrows; ++m) s += dy[4 * m + o];
-        gb[o] = s;
+    __shared__ float red[4][5][64];
+    const int c = threadIdx.x & 63, t4 = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + c;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 64, r1 = min(r0 + 64, Mrows);
+    float a[4] = {0.f, 0.f, 0.f, 0.f}, b = 0.f;
+    for (int64_t m = r0 + t4; m < r1; m += 4) {
+        const float hv = k < width ? from_bf16(h[m * width + k]) : 0.f;
+        for (int o = 0; o < 4; ++o) a[o] += dy[4 * m + o] * hv;
+        if (c < 4) b += dy[4 * m + c];
+    }
+    for (int o = 0; o < 4; ++o) red[t4][o][c] = a[o];
+    red[t4][4][c] = b;
+    __syncthreads();
+    if (t4 == 0) {
+        if (k < width)
+            for (int o = 0; o < 4; ++o)
+                pw[(static_cast<int64_t>(blockIdx.y) * 4 + o) * width + k] =
+                    ((red[0][o][c] + red[1][o][c]) + red[2][o][c]) + red[3][o][c];
+        if (blockIdx.x == 0 && c < 4)
+            pb[static_cast<int64_t>(blockIdx.y) * 4 + c] = ((red[0][4][c] + red[1][4][c]) + red[2][4][c]) + red[3][4][c];
     }
 }
 
-// Column sums of a row-major float32 matrix (bias gradients), in row order.
-__global__ void k_colsum(const float *__restrict__ x, int64_t rows, int cols, float *__restrict__ out)
+// Column-sum partials of rows [64 y, 64 y + 64) of a row-major float32
+// matrix (bias gradients), same layout of threads.
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ x, int64_t rows, int cols,
+                                                     float *__restrict__ part)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    float s = 0.f;
-    for (int64_t m = 0; m < rows; ++m) s += x[m * cols + c];
-    out[c] = s;
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, t4 = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + c;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 64, r1 = min(r0 + 64, rows);
+    float sum = 0.f;
+    if (col < cols)
+        for (int64_t m = r0 + t4; m < r1; m += 4) sum += x[m * cols + col];
+    red[t4][c] = sum;
+    __syncthreads();
+    if (t4 == 0 && col < cols)
+        part[static_cast<int64_t>(blockIdx.y) * cols + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+// out[i] = sum over z = 0..nz-1 of part[z][i], in z order.
+__global__ void k_sum_slices(const float *__restrict__ part, int nz, int64_t n, float *__restrict__ out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float sum = 0.f;
+    for (int z = 0; z < nz; ++z) sum += part[static_cast<int64_t>(z) * n + i];
+    out[i] = sum;
 }
 
 __global__ void k_sum(const float *__restrict__ x, int n, float *__restrict__ out)
@@ -266,12 +298,19 @@ __global__ void k_gather(const double *__restrict__ pts, const double *__restric
     }
 }
 
+// Adam step number t = *step + 1 (steps already taken, kept on the device so
+// that a captured training epoch replays unchanged), learning rate
+// lr_sched[*step - step0], bias corrections 1 - b^t.
 __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, int64_t n, float lr, float b1, float b2, float bc1, float bc2,
-                       float eps)
+                       const float *__restrict__ g, int64_t n, const float *__restrict__ lr_sched,
+                       const int64_t *__restrict__ step, int64_t step0, float b1, float b2, float eps)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t s = *step;
+    const float lr = lr_sched[s - step0];
+    const float t = static_cast<float>(s + 1);
+    const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -280,15 +319,126 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// bf16 copy of one weight matrix [rows][cols] and, if wt, of its transpose.
-__global__ void k_refresh(const float *__restrict__ w, int rows, int cols, uint16_t *__restrict__ wb,
-                          uint16_t *__restrict__ wt)
+__global__ void k_step_inc(int64_t *step)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= static_cast<int64_t>(rows) * cols) return;
-    const uint16_t b = to_bf16(w[i]);
-    wb[i] = b;
-    if (wt) wt[static_cast<int64_t>(i % cols) * rows + i / cols] = b;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+// bf16 copies of every weight matrix [rows][cols] and, where a transposed
+// copy exists, of its transpose; blockIdx.y = layer.
+__global__ void k_refresh(RefreshTable t)
+{
+    const int l = blockIdx.y;
+    const int rows = t.rows[l], cols = t.cols[l];
+    const float *w = t.w + t.woff[l];
+    uint16_t *wb = t.wb + t.woff[l];
+    uint16_t *wt = t.toff[l] >= 0 ? t.wt + t.toff[l] : nullptr;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < static_cast<int64_t>(rows) * cols;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const uint16_t b = to_bf16(w[i]);
+        wb[i] = b;
+        if (wt) wt[static_cast<int64_t>(i % cols) * rows + i / cols] = b;
+    }
+}
+
+// ---------------------------------------------------------------- fused inference
+// The whole network for 128 points per 256-thread block, width 256: the
+// features and every hidden activation stay in LDS (two 128 x 264 bf16
+// buffers, rows padded by 8 elements), so HBM sees only the points and the
+// outputs.  Wave w computes output columns [64 w, 64 w + 64) of every layer
+// for all 128 rows: four row blocks x two column blocks of 32 x 32 MFMA
+// accumulators; the A fragments come from LDS, the wave's quarter of the
+// bf16 weights from global memory (L2-resident, 128 KB per layer), one k step
+// loaded ahead.  The accumulation order over k is the one of k_gemm, so the
+// hidden activations equal those of the layer-by-layer kernels bit for bit.
+constexpr int kFusedRows = 128, kFusedW = 256, kFusedLd = kFusedW + 8;
+
+__global__ __launch_bounds__(256, 1) void k_mlp_fused(FusedArgs f)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t act[2][kFusedRows * kFusedLd];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kFusedRows;
+    // features -> act[0] columns [0, 2 n_ff)
+    for (int i = tid; i < kFusedRows * f.n_ff; i += 256) {
+        const int r = i / f.n_ff, q = i % f.n_ff;
+        const int64_t m = row0 + r;
+        uint16_t hs = 0, hc = 0;
+        if (m < f.M) {
+            double t = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double xn = 2.0 * (f.pts[3 * m + c] - f.norm.lo[c]) / (f.norm.hi[c] - f.norm.lo[c]) - 1.0;
+                t += static_cast<double>(f.Bff[3 * q + c]) * xn;
+            }
+            const float fr = static_cast<float>(t - rint(t));
+            float sn, co;
+            sincosf(6.2831853071795865f * fr, &sn, &co);
+            hs = to_bf16(sn);
+            hc = to_bf16(co);
+        }
+        act[0][r * kFusedLd + q] = hs;
+        act[0][r * kFusedLd + f.n_ff + q] = hc;
+    }
+    __syncthreads();
+    const int r = lane & 31, kh = (lane >> 5) * 8;
+    const int col0 = wv * 64;
+    int cur = 0;
+    for (int l = 0; l < f.depth; ++l) {
+        const int K = l == 0 ? 2 * f.n_ff : kFusedW;
+        const uint16_t *W = f.w[l];  // [256][K]
+        const uint16_t *in = act[cur];
+        uint16_t *out = act[cur ^ 1];
+        f32x16 acc[4][2];
+        for (int rb = 0; rb < 4; ++rb)
+            for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x16{};
+        const uint16_t *pb0 = W + static_cast<int64_t>(col0 + r) * K + kh;
+        const uint16_t *pb1 = W + static_cast<int64_t>(col0 + 32 + r) * K + kh;
+        bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0);
+        bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1);
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            bf16x8 nb0 = b0, nb1 = b1;
+            if (k0 + 16 < K) {
+                nb0 = *reinterpret_cast<const bf16x8 *>(pb0 + k0 + 16);
+                nb1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0 + 16);
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(in + (rb * 32 + r) * kFusedLd + k0 + kh);
+                acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[rb][0], 0, 0, 0);
+                acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[rb][1], 0, 0, 0);
+            }
+            b0 = nb0;
+            b1 = nb1;
+        }
+        const float *bias = f.b[l];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const int n = col0 + 32 * cb + r;
+                const float bn = bias[n];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int m = rb * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    out[m * kFusedLd + n] = to_bf16(act_f(acc[rb][cb][q] + bn, f.act));
+                }
+            }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // output layer: two threads per row, two outputs each
+    const int rr = tid >> 1, o0 = 2 * (tid & 1);
+    const int64_t m = row0 + rr;
+    const uint16_t *h = act[cur] + rr * kFusedLd;
+    float y0 = 0.f, y1 = 0.f;
+    for (int k = 0; k < kFusedW; ++k) {
+        const float hv = from_bf16(h[k]);
+        y0 += hv * from_bf16(f.wo[o0 * kFusedW + k]);
+        y1 += hv * from_bf16(f.wo[(o0 + 1) * kFusedW + k]);
+    }
+    if (m < f.M) {
+        f.A[4 * m + o0] = f.scale * (y0 + f.bo[o0]);
+        f.A[4 * m + o0 + 1] = f.scale * (y1 + f.bo[o0 + 1]);
+    }
 }
 
 // ---------------------------------------------------------------- grid fill
@@ -377,7 +527,9 @@ int launch_gemm(hipStream_t s, int epi, const GemmArgs &g)
 {
     if (g.M % kTileM || g.N % kTileN || g.K % 16 || g.K <= 0)
         return fail(SBR_ERR_INVALID_ARG, "MLP product: shape not a multiple of the 64 x 128 x 16 tile");
-    dim3 grid(g.M / kTileM, g.N / kTileN);
+    if (g.ksplit < 1 || (g.K / g.ksplit) % 16 || g.K % g.ksplit || (g.ksplit > 1 && epi != kEpiF32))
+        return fail(SBR_ERR_INVALID_ARG, "MLP product: bad k split");
+    dim3 grid(g.M / kTileM, g.N / kTileN, g.ksplit);
     if (epi == kEpiHidden) k_gemm<kEpiHidden><<<grid, kGemmThreads, 0, s>>>(g);
     else if (epi == kEpiDz) k_gemm<kEpiDz><<<grid, kGemmThreads, 0, s>>>(g);
     else k_gemm<kEpiF32><<<grid, kGemmThreads, 0, s>>>(g);
@@ -402,17 +554,31 @@ int launch_out(hipStream_t s, const uint16_t *h, int width, const uint16_t *wo, 
 }
 
 int launch_out_back(hipStream_t s, const float *dy, const uint16_t *wo, int width, int64_t Mrows, const float *z,
-                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h)
+                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h,
+                    float *scratch)
 {
+    const int R = static_cast<int>((Mrows + 63) / 64);
+    float *pw = scratch, *pb = scratch + static_cast<int64_t>(R) * 4 * width;
     k_out_back<<<nblk(Mrows * width, 256), 256, 0, s>>>(dy, wo, width, Mrows, z, act, dz, dzb, dzbt);
-    k_out_wgrad<<<nblk(4 * width + 4, 256), 256, 0, s>>>(dy, h, width, Mrows, gw, gb);
+    k_out_wgrad_part<<<dim3((width + 63) / 64, R), 256, 0, s>>>(dy, h, width, Mrows, pw, pb);
+    k_sum_slices<<<nblk(4 * width, 256), 256, 0, s>>>(pw, R, 4 * width, gw);
+    k_sum_slices<<<1, 64, 0, s>>>(pb, R, 4, gb);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
-int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out)
+int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out, float *scratch)
 {
-    k_colsum<<<nblk(cols, 256), 256, 0, s>>>(x, rows, cols, out);
+    const int R = static_cast<int>((rows + 63) / 64);
+    k_colsum_part<<<dim3((cols + 63) / 64, R), 256, 0, s>>>(x, rows, cols, scratch);
+    k_sum_slices<<<nblk(cols, 256), 256, 0, s>>>(scratch, R, cols, out);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_sum_slices(hipStream_t s, const float *part, int nz, int64_t n, float *out)
+{
+    k_sum_slices<<<nblk(n, 256), 256, 0, s>>>(part, nz, n, out);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
@@ -432,17 +598,20 @@ int launch_gather(hipStream_t s, const double *pts, const double *tc, const int3
     return SBR_OK;
 }
 
-int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
-                float bc1, float bc2, float eps)
+int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, const float *lr_sched,
+                int64_t *step, int64_t step0, float b1, float b2, float eps)
 {
-    k_adam<<<nblk(n, 256), 256, 0, s>>>(w, m, v, g, n, lr, b1, b2, bc1, bc2, eps);
+    k_adam<<<nblk(n, 256), 256, 0, s>>>(w, m, v, g, n, lr_sched, step, step0, b1, b2, eps);
+    k_step_inc<<<1, 64, 0, s>>>(step);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
-int launch_refresh(hipStream_t s, const float *w, int rows, int cols, uint16_t *wb, uint16_t *wt)
+int launch_refresh(hipStream_t s, const RefreshTable &t)
 {
-    k_refresh<<<nblk(static_cast<int64_t>(rows) * cols, 256), 256, 0, s>>>(w, rows, cols, wb, wt);
+    if (t.n_layers < 1 || t.n_layers > kMaxLayers) return fail(SBR_ERR_INVALID_ARG, "refresh: layer count");
+    dim3 grid(64, t.n_layers);
+    k_refresh<<<grid, 256, 0, s>>>(t);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
@@ -469,6 +638,16 @@ int launch_scatter_copol(hipStream_t s, const double *A, const int64_t *dst, int
 {
     if (n <= 0) return SBR_OK;
     k_scatter_copol<<<nblk(n, 256), 256, 0, s>>>(A, dst, n, out);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+bool fused_ok(int n_ff, int width, int depth) { return width == kFusedW && 2 * n_ff <= kFusedW && depth <= kMaxLayers - 1; }
+
+int launch_mlp_fused(hipStream_t s, const FusedArgs &f)
+{
+    if (f.M <= 0) return SBR_OK;
+    k_mlp_fused<<<nblk(f.M, kFusedRows), 256, 0, s>>>(f);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

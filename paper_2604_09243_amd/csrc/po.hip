@@ -11,15 +11,20 @@
 // -(k dA / 2 pi) is applied in the finalize step.
 //
 // Numerics: the phase k_f * D is formed and reduced modulo 2 pi in float64
-// (k D reaches 1e3-1e4 rad) and sin/cos are float32; the weights w are
-// formed in float64 from the float32 records.  Each term is
-// converted to a 64-bit fixed-point integer (unit 2^-32) and summed as an
-// integer, so the per-block partials do not depend on the order in which the
-// trace stage appended its records: results are bitwise reproducible without
-// any float atomics.  The wave reduction uses DPP row permutations (quad
-// swaps, half-row and row mirrors) and four lane reads; waves are combined
-// through LDS into one partial per block; the finalize kernel sums the
-// partials of an angle in fixed block order in float64.
+// (k D reaches 1e3-1e4 rad); its sine and cosine and the weights w are
+// float64 (from the float32 records).  Float32 sine and cosine of the phase
+// are not enough: on weak, strongly cancelling returns their rounding of
+// ~1e-7 per term reaches 1e-4 of the result.  For evenly spaced wavenumbers
+// the phasor of the next frequency is the previous one turned by dk D.
+// A thread sums its own records (the slots tid, tid + 256, ... of its block,
+// in that order) in float64; each thread sum is converted to a 64-bit
+// fixed-point integer (unit 2^-32) and reduced as an integer.  The slots of
+// a ray are fixed by its position in the aperture, so the result is bitwise
+// reproducible across runs, schedules and launch parameters without any
+// float atomics.  The wave reduction uses DPP row permutations (quad swaps,
+// half-row and row mirrors) and four lane reads; waves are combined through
+// LDS into one partial per block; the finalize kernel sums the partials of
+// an angle in fixed block order in float64.
 #include <cmath>
 
 #include "sbr_internal.hpp"
@@ -28,7 +33,6 @@ namespace sbr {
 namespace {
 
 constexpr int kPoThreads = 256;
-constexpr int kFT = 2;  // frequencies per pass over a block's records
 
 struct PoP {
     Records rec;
@@ -67,6 +71,44 @@ __device__ __forceinline__ long long wave_sum64(long long x)
     x += dpp64<0x141>(x);  // row_half_mirror
     x += dpp64<0x140>(x);  // row_mirror: every lane holds its row's sum
     return readlane64(x, 0) + readlane64(x, 16) + readlane64(x, 32) + readlane64(x, 48);
+}
+
+// sin and cos of x in [-pi, pi] in float64: x = q pi/2 + r with q = rint(x 2/pi)
+// (pi/2 as a two-term sum, so r is exact to ~1e-17), |r| <= pi/4, then the
+// Taylor polynomials of sin (through r^17) and cos (through r^18) in Horner
+// form (truncation below 1e-18 on |r| <= pi/4), and the quadrant symmetries
+// of sin and cos.  Absolute error about 1e-16.
+__device__ __forceinline__ void sincos_pi(double x, double &so, double &co)
+{
+    const double pio2_hi = 1.5707963267948966;     // fl64(pi / 2)
+    const double pio2_lo = 6.123233995736766e-17;  // pi / 2 - fl64(pi / 2)
+    const double q = rint(x * 0.6366197723675814);
+    double r = __builtin_fma(-q, pio2_hi, x);
+    r = __builtin_fma(-q, pio2_lo, r);
+    const double z = r * r;
+    // (-1)^i / (2i + 1)!, i = 1..8 and (-1)^i / (2i)!, i = 1..9
+    double ps = 1.0 / 355687428096000.0;
+    ps = __builtin_fma(ps, z, -1.0 / 1307674368000.0);
+    ps = __builtin_fma(ps, z, 1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, z, -1.0 / 39916800.0);
+    ps = __builtin_fma(ps, z, 1.0 / 362880.0);
+    ps = __builtin_fma(ps, z, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, z, 1.0 / 120.0);
+    ps = __builtin_fma(ps, z, -1.0 / 6.0);
+    const double sn = __builtin_fma(r * z, ps, r);
+    double pc = -1.0 / 6402373705728000.0;
+    pc = __builtin_fma(pc, z, 1.0 / 20922789888000.0);
+    pc = __builtin_fma(pc, z, -1.0 / 87178291200.0);
+    pc = __builtin_fma(pc, z, 1.0 / 479001600.0);
+    pc = __builtin_fma(pc, z, -1.0 / 3628800.0);
+    pc = __builtin_fma(pc, z, 1.0 / 40320.0);
+    pc = __builtin_fma(pc, z, -1.0 / 720.0);
+    pc = __builtin_fma(pc, z, 1.0 / 24.0);
+    pc = __builtin_fma(pc, z, -0.5);
+    const double cs = __builtin_fma(z, pc, 1.0);
+    const int qi = static_cast<int>(q) & 3;  // two's complement: -1 -> 3, -2 -> 2
+    so = qi == 0 ? sn : qi == 1 ? cs : qi == 2 ? -sn : -cs;
+    co = qi == 0 ? cs : qi == 1 ? -sn : qi == 2 ? -cs : sn;
 }
 
 // round(x * 2^32) as a 64-bit integer for |x| < 2^19, via the float64
@@ -118,6 +160,7 @@ __device__ __forceinline__ void weights(const PoP &p, const double *B, const flo
 
 // Block u of the launch: records [c * kPoRecsPerBlock, (c + 1) * kPoRecsPerBlock)
 // of angle a, where a is the angle whose blocks hold u and c = u - unit_base.
+template <int kFT>  // frequencies per pass over a block's records
 __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
 {
     __shared__ long long red[kPoThreads / 64][kFT * 8];
@@ -139,10 +182,14 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
     const double two_pi_hi = 6.283185307179586;       // fl64(2 pi)
     const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - fl64(2 pi)
     const double inv_two_pi = 0.15915494309189535;
+    const bool uniform = A.dk != 0.0;
     for (int f0 = 0; f0 < nf; f0 += kFT) {
-        long long acc[kFT][8];
+        // each thread sums its records (a fixed subset, in a fixed order) in
+        // float64; the per-thread sums become fixed point before the exact
+        // integer reduction over threads, waves and blocks
+        double acc[kFT][8];
         for (int ft = 0; ft < kFT; ++ft)
-            for (int e = 0; e < 8; ++e) acc[ft][e] = 0;
+            for (int e = 0; e < 8; ++e) acc[ft][e] = 0.0;
         for (int64_t e = A.rec_base + r0i + tid; e < A.rec_base + r1i; e += kPoThreads) {
             const float4 q2 = p.rec.r2[e];
             if (!((__float_as_int(q2.w) >> 8) & SBR_REC_VALID)) continue;  // no hit (or dropped): no term
@@ -150,24 +197,41 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
             const double D = p.rec.D[e];
             double w[4];
             weights(p, A.basis, q0, q1, q2, w);
+            double sd, cd, rs = 0.0, rc = 1.0;
+            {
+                const double ph = kf[f0] * D;
+                const double nturn = rint(ph * inv_two_pi);
+                sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), sd, cd);
+            }
+            if (uniform) {  // evenly spaced wavenumbers: each step turns the phasor by dk D
+                const double ph = A.dk * D;
+                const double nturn = rint(ph * inv_two_pi);
+                sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), rs, rc);
+            }
+#pragma unroll
             for (int ft = 0; ft < kFT; ++ft) {
                 const int f = f0 + ft;
                 if (f >= nf) break;
-                const double ph = kf[f] * D;
-                const double nturn = rint(ph * inv_two_pi);
-                const double red_ph = __builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph));
-                float s, co;
-                sincosf(static_cast<float>(red_ph), &s, &co);
-                const double sd = s, cd = co;
+                if (ft > 0) {
+                    if (uniform) {
+                        const double s2 = __builtin_fma(sd, rc, cd * rs);
+                        cd = __builtin_fma(cd, rc, -(sd * rs));
+                        sd = s2;
+                    } else {
+                        const double ph = kf[f] * D;
+                        const double nturn = rint(ph * inv_two_pi);
+                        sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), sd, cd);
+                    }
+                }
                 for (int k = 0; k < 4; ++k) {
-                    acc[ft][2 * k] += fix32(w[k] * sd);
-                    acc[ft][2 * k + 1] += fix32(w[k] * cd);
+                    acc[ft][2 * k] = __builtin_fma(w[k], sd, acc[ft][2 * k]);
+                    acc[ft][2 * k + 1] = __builtin_fma(w[k], cd, acc[ft][2 * k + 1]);
                 }
             }
         }
         for (int ft = 0; ft < kFT; ++ft)
             for (int k = 0; k < 8; ++k) {
-                const long long s = wave_sum64(acc[ft][k]);
+                const long long s = wave_sum64(fix32(acc[ft][k]));
                 if (lane == 0) red[wv][ft * 8 + k] = s;
             }
         __syncthreads();
@@ -250,7 +314,10 @@ int launch_po(hipStream_t s, const PoArgs &a)
 {
     if (a.n_units <= 0) return SBR_OK;
     if (a.n_units > 2147483647LL) return fail(SBR_ERR_OVERFLOW, "PO launch: too many blocks");
-    k_po<<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
+    // one frequency: the 1-wide pass keeps the register count (and the
+    // occupancy that hides the record loads) of a single accumulator set
+    if (a.max_nf == 1) k_po<1><<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
+    else k_po<4><<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

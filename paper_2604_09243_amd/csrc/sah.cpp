@@ -1,0 +1,346 @@
+// Host binned-SAH BVH builder (the top-down surface-area split of the
+// paper's Algorithm 1 and its SAH cost), emitting exactly the node and
+// triangle layout of the GPU LBVH so that the same traversal kernels run on
+// it: nodes in preorder with the root at 0, both child boxes inline, leaves
+// of at most leaf_max triangles coded ~(first * 8 + count - 1), triangles in
+// leaf order.  Boxes are the same padded float32 triangle boxes as the LBVH
+// (pad = 1e-6 |diag| plus 4e-7 of the coordinate), so the box test stays
+// conservative.
+//
+// Split choice per node: 32 bins of the centroid extent on each axis; the
+// cost of a split is C_node + (A_L n_L + A_R n_R) / A with C_node = 0.5 (one
+// node fetch tests both child boxes, about half the work of a triangle
+// test); a node becomes a leaf when it holds at most leaf_max triangles and
+// no split is cheaper than testing them all; a node whose centroids coincide
+// splits at the middle index.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sbr_internal.hpp"
+
+namespace sbr {
+namespace {
+
+constexpr int kBins = 32;
+constexpr float kNodeCost = 0.5f;
+
+struct Box {
+    float lo[3], hi[3];
+    void empty()
+    {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = INFINITY;
+            hi[k] = -INFINITY;
+        }
+    }
+    void grow(const Box &b)
+    {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], b.lo[k]);
+            hi[k] = std::max(hi[k], b.hi[k]);
+        }
+    }
+    float area() const
+    {
+        const float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+        if (!(dx >= 0.f)) return 0.f;
+        return 2.f * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+struct TNode {
+    Box box;
+    int left = -1, right = -1;  // tree children (internal) or -1
+    int first = 0, count = 0;   // leaf range (count > 0)
+};
+
+struct Builder {
+    const std::vector<Box> &pb;
+    const std::vector<float> &cen;  // [n][3]
+    std::vector<int> &idx;
+    int leaf_max;
+    std::vector<TNode> nodes;
+    int depth = 0;
+
+    Builder(const std::vector<Box> &b, const std::vector<float> &c, std::vector<int> &i, int lm)
+        : pb(b), cen(c), idx(i), leaf_max(lm) {}
+
+    int make_leaf(int b, int e, const Box &box)
+    {
+        TNode t;
+        t.box = box;
+        t.first = b;
+        t.count = e - b;
+        nodes.push_back(t);
+        return static_cast<int>(nodes.size()) - 1;
+    }
+
+    // builds the subtree of idx[b, e); returns its node
+    int build(int b, int e, int d)
+    {
+        depth = std::max(depth, d);
+        Box box, cb;
+        box.empty();
+        cb.empty();
+        for (int i = b; i < e; ++i) {
+            box.grow(pb[idx[i]]);
+            const float *c = &cen[3 * idx[i]];
+            for (int k = 0; k < 3; ++k) {
+                cb.lo[k] = std::min(cb.lo[k], c[k]);
+                cb.hi[k] = std::max(cb.hi[k], c[k]);
+            }
+        }
+        const int n = e - b;
+        if (n == 1) return make_leaf(b, e, box);
+        // best binned split over the three axes
+        float best = INFINITY;
+        int best_axis = -1, best_bin = -1;
+        const float parent_area = std::max(box.area(), 1e-30f);
+        for (int ax = 0; ax < 3; ++ax) {
+            const float ext = cb.hi[ax] - cb.lo[ax];
+            if (!(ext > 0.f)) continue;
+            Box bb[kBins];
+            int bc[kBins] = {0};
+            for (auto &x : bb) x.empty();
+            const float sc = kBins / ext;
+            for (int i = b; i < e; ++i) {
+                int q = static_cast<int>((cen[3 * idx[i] + ax] - cb.lo[ax]) * sc);
+                q = std::min(std::max(q, 0), kBins - 1);
+                bb[q].grow(pb[idx[i]]);
+                ++bc[q];
+            }
+            float ra[kBins];
+            int rn[kBins];
+            Box acc;
+            acc.empty();
+            int cnt = 0;
+            for (int q = kBins - 1; q >= 1; --q) {
+                acc.grow(bb[q]);
+                cnt += bc[q];
+                ra[q] = acc.area();
+                rn[q] = cnt;
+            }
+            acc.empty();
+            cnt = 0;
+            for (int q = 0; q < kBins - 1; ++q) {
+                acc.grow(bb[q]);
+                cnt += bc[q];
+                if (cnt == 0 || rn[q + 1] == 0) continue;
+                const float cost = kNodeCost + (acc.area() * cnt + ra[q + 1] * rn[q + 1]) / parent_area;
+                if (cost < best) {
+                    best = cost;
+                    best_axis = ax;
+                    best_bin = q;
+                }
+            }
+        }
+        if (n <= leaf_max && !(best < static_cast<float>(n))) return make_leaf(b, e, box);
+        int mid;
+        if (best_axis < 0) {
+            mid = b + n / 2;  // coincident centroids: split by index
+        } else {
+            const float ext = cb.hi[best_axis] - cb.lo[best_axis];
+            const float sc = kBins / ext;
+            auto it = std::partition(idx.begin() + b, idx.begin() + e, [&](int t) {
+                int q = static_cast<int>((cen[3 * t + best_axis] - cb.lo[best_axis]) * sc);
+                q = std::min(std::max(q, 0), kBins - 1);
+                return q <= best_bin;
+            });
+            mid = static_cast<int>(it - idx.begin());
+            if (mid == b || mid == e) mid = b + n / 2;
+        }
+        const int me = static_cast<int>(nodes.size());
+        nodes.push_back(TNode());
+        nodes[me].box = box;
+        const int l = build(b, mid, d + 1);
+        const int r = build(mid, e, d + 1);
+        nodes[me].left = l;
+        nodes[me].right = r;
+        return me;
+    }
+};
+
+void put_child(BNode &bn, int s, const Box &b)
+{
+    float *f = reinterpret_cast<float *>(&bn);  // a, b, c: 12 floats, child 0 then child 1
+    for (int k = 0; k < 3; ++k) {
+        f[6 * s + k] = b.lo[k];
+        f[6 * s + 3 + k] = b.hi[k];
+    }
+}
+
+}  // namespace
+
+int sah_layout(const PreparedMesh &pm, int leaf_max, std::vector<BNode> &hn, std::vector<BTri> &ht,
+               std::vector<float4> &hs, int &depth)
+{
+    const int n = static_cast<int>(pm.live.size());
+    // padded triangle boxes and centroids (same float32 arithmetic as the LBVH leaves)
+    const float pad = static_cast<float>(1e-6 * pm.diag) + 1e-30f;
+    std::vector<Box> pb(n);
+    std::vector<float> cen(3 * static_cast<size_t>(n));
+    for (int j = 0; j < n; ++j) {
+        const int li = pm.live[j];
+        const float *a = &pm.v0[3 * li], *b = &pm.e1[3 * li], *c = &pm.e2[3 * li];
+        for (int k = 0; k < 3; ++k) {
+            const float p0 = a[k], p1 = a[k] + b[k], p2 = a[k] + c[k];
+            const float lo = std::min(p0, std::min(p1, p2)), hi = std::max(p0, std::max(p1, p2));
+            pb[j].lo[k] = lo - pad - std::fabs(lo) * 4e-7f;
+            pb[j].hi[k] = hi + pad + std::fabs(hi) * 4e-7f;
+            cen[3 * j + k] = 0.5f * (pb[j].lo[k] + pb[j].hi[k]);
+        }
+    }
+    std::vector<int> idx(n);
+    for (int j = 0; j < n; ++j) idx[j] = j;
+    Builder B(pb, cen, idx, leaf_max);
+    B.nodes.reserve(2 * static_cast<size_t>(n) / std::max(1, leaf_max) + 2);
+    const int root = B.build(0, n, 0);
+    // flatten: internal nodes in preorder (the root first), leaves as codes
+    std::vector<int> pre(B.nodes.size(), -1);
+    std::vector<int> order;
+    {
+        std::vector<int> st{root};
+        while (!st.empty()) {
+            const int t = st.back();
+            st.pop_back();
+            if (B.nodes[t].count > 0) continue;
+            pre[t] = static_cast<int>(order.size());
+            order.push_back(t);
+            st.push_back(B.nodes[t].right);
+            st.push_back(B.nodes[t].left);
+        }
+    }
+    auto ref = [&](int t) {
+        const TNode &x = B.nodes[t];
+        if (x.count > 0) return ~((x.first << 3) | (x.count - 1));
+        return pre[t];
+    };
+    hn.clear();
+    if (order.empty()) {  // the whole mesh is one leaf: a root whose two children are that leaf
+        BNode bn;
+        put_child(bn, 0, B.nodes[root].box);
+        put_child(bn, 1, B.nodes[root].box);
+        bn.ch = make_int4(ref(root), ref(root), 0, 0);
+        hn.push_back(bn);
+    } else {
+        hn.resize(order.size());
+        for (size_t i = 0; i < order.size(); ++i) {
+            const TNode &x = B.nodes[order[i]];
+            BNode bn;
+            put_child(bn, 0, B.nodes[x.left].box);
+            put_child(bn, 1, B.nodes[x.right].box);
+            bn.ch = make_int4(ref(x.left), ref(x.right), 0, 0);
+            hn[i] = bn;
+        }
+    }
+    ht.resize(n);
+    hs.resize(n);
+    for (int j = 0; j < n; ++j) {
+        const int li = pm.live[idx[j]];
+        const float *a = &pm.v0[3 * li], *b = &pm.e1[3 * li], *c = &pm.e2[3 * li];
+        BTri t;
+        t.p0 = make_float4(a[0], a[1], a[2], 0.f);
+        std::memcpy(&t.p0.w, &li, 4);
+        t.p1 = make_float4(b[0], b[1], b[2], 0.0f);
+        t.p2 = make_float4(c[0], c[1], c[2], 0.0f);
+        ht[j] = t;
+        hs[j] = make_float4(pm.n[3 * li], pm.n[3 * li + 1], pm.n[3 * li + 2], 0.0f);
+    }
+    depth = std::max(1, B.depth);
+    return SBR_OK;
+}
+
+int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth)
+{
+    // every reference in range, every leaf slot covered exactly once, child
+    // boxes inside their parent's box, the stack bound respected
+    const int nn = static_cast<int>(hn.size());
+    std::vector<uint8_t> covered(n, 0);
+    std::vector<std::pair<int, int>> st{{0, 0}};
+    std::vector<uint8_t> seen(nn, 0);
+    int maxd = 0;
+    const bool single = nn == 1 && hn[0].ch.x == hn[0].ch.y && hn[0].ch.x < 0;
+    while (!st.empty()) {
+        const int t = st.back().first, d = st.back().second;
+        st.pop_back();
+        if (t < 0 || t >= nn || seen[t]) return fail(SBR_ERR_INVALID_MESH, "SAH build: bad node reference");
+        seen[t] = 1;
+        maxd = std::max(maxd, d + 1);
+        const int refs[2] = {hn[t].ch.x, hn[t].ch.y};
+        for (int s = 0; s < (single ? 1 : 2); ++s) {
+            const int c = refs[s];
+            if (c >= 0) {
+                if (c <= t) return fail(SBR_ERR_INVALID_MESH, "SAH build: child before parent");
+                const float *pf = reinterpret_cast<const float *>(&hn[t]);
+                const float *cf = reinterpret_cast<const float *>(&hn[c]);
+                for (int k = 0; k < 3; ++k)
+                    for (int cs = 0; cs < 2; ++cs)
+                        if (cf[6 * cs + k] < pf[6 * s + k] || cf[6 * cs + 3 + k] > pf[6 * s + 3 + k])
+                            return fail(SBR_ERR_INVALID_MESH, "SAH build: child box outside its parent");
+                st.push_back({c, d + 1});
+            } else {
+                const int code = ~c, first = code >> 3, cnt = (code & 7) + 1;
+                if (cnt > leaf_max || first < 0 || first + cnt > n)
+                    return fail(SBR_ERR_INVALID_MESH, "SAH build: bad leaf");
+                for (int q = first; q < first + cnt; ++q) {
+                    if (covered[q]) return fail(SBR_ERR_INVALID_MESH, "SAH build: slot in two leaves");
+                    covered[q] = 1;
+                }
+            }
+        }
+    }
+    for (int q = 0; q < n; ++q)
+        if (!covered[q]) return fail(SBR_ERR_INVALID_MESH, "SAH build: slot in no leaf");
+    for (int t = 0; t < nn; ++t)
+        if (!seen[t]) return fail(SBR_ERR_INVALID_MESH, "SAH build: unreachable node");
+    if (maxd > depth + 1) return fail(SBR_ERR_INVALID_MESH, "SAH build: depth bound");
+    return SBR_OK;
+}
+
+int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
+{
+    if (leaf_max < 1 || leaf_max > 4) return fail(SBR_ERR_INVALID_ARG, "leaf size must be in [1, 4]");
+    const int64_t nt = bvh->n_tris;
+    const int n = static_cast<int>(pm.live.size());
+    auto dalloc = [&](void **p, size_t bytes) -> int {
+        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SBR_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        bvh->device_bytes += static_cast<int64_t>(std::max<size_t>(bytes, 256));
+        return SBR_OK;
+    };
+    int rc;
+    {
+        std::vector<float4> nid(nt);
+        for (int64_t j = 0; j < nt; ++j) nid[j] = make_float4(pm.n[3 * j], pm.n[3 * j + 1], pm.n[3 * j + 2], 0.f);
+        if ((rc = dalloc(reinterpret_cast<void **>(&bvh->nrm_id), sizeof(float4) * nt))) return rc;
+        SBR_HIP(hipMemcpy(bvh->nrm_id, nid.data(), sizeof(float4) * nt, hipMemcpyHostToDevice));
+    }
+    bvh->n_live = n;
+    if (n == 0) {
+        bvh->n_nodes = 0;
+        bvh->depth = 0;
+        return SBR_OK;
+    }
+    std::vector<BNode> hn;
+    std::vector<BTri> ht;
+    std::vector<float4> hs;
+    int depth = 0;
+    if ((rc = sah_layout(pm, leaf_max, hn, ht, hs, depth)) || (rc = validate_layout(hn, n, leaf_max, depth))) return rc;
+    if ((rc = dalloc(reinterpret_cast<void **>(&bvh->nodes), sizeof(BNode) * hn.size())) ||
+        (rc = dalloc(reinterpret_cast<void **>(&bvh->tris), sizeof(BTri) * n)) ||
+        (rc = dalloc(reinterpret_cast<void **>(&bvh->nrm_slot), sizeof(float4) * n)))
+        return rc;
+    SBR_HIP(hipMemcpy(bvh->nodes, hn.data(), sizeof(BNode) * hn.size(), hipMemcpyHostToDevice));
+    SBR_HIP(hipMemcpy(bvh->tris, ht.data(), sizeof(BTri) * n, hipMemcpyHostToDevice));
+    SBR_HIP(hipMemcpy(bvh->nrm_slot, hs.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
+    bvh->n_nodes = static_cast<int64_t>(hn.size());
+    bvh->depth = depth;
+    (void)ctx;
+    return SBR_OK;
+}
+
+}  // namespace sbr

@@ -171,6 +171,8 @@ int plan_angle(const double bbox[6], double theta_deg, double phi_deg, double ds
 
 // lbvh.hip: builds nodes/tris on the device from a prepared mesh.
 int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
+// sah.cpp: the same node/triangle layout from a host binned-SAH build.
+int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
 
 // trace.hip
 struct TraceArgs {
@@ -232,7 +234,11 @@ struct PoAngle {
     int64_t part_base;          // first partial row (8 int64) of the angle
     int64_t out_base;           // output row of the angle's first frequency
     int32_t kf_off, n_f;        // its wavenumbers kf[kf_off, kf_off + n_f)
+    double dk;                  // their spacing if evenly spaced, else 0
 };
+// Spacing of n wavenumbers if they form an arithmetic progression (to a few
+// ulps), else 0.
+double uniform_step(const double *kf, int n);
 struct PoArgs {
     const sbr_bvh *bvh;
     Records rec;
@@ -286,6 +292,8 @@ struct GemmArgs {
     int64_t ldzi;
     float *fout;
     int64_t ldf;
+    int ksplit = 1;           // kEpiF32 only: K split over blockIdx.z ...
+    int64_t split_stride = 0; // ... into fout slices this many floats apart
 };
 struct MlpNorm {
     double lo[3], hi[3];
@@ -295,15 +303,45 @@ int launch_embed(hipStream_t s, const double *pts, int64_t M, int64_t Mpad, cons
                  int n_ff, uint16_t *h0, uint16_t *h0t);
 int launch_out(hipStream_t s, const uint16_t *h, int width, const uint16_t *wo, const float *bo, int64_t M,
                int64_t Mrows, int mode, double scale, double *A, const float *tgt, float *dy, float *partial);
+// scratch: at least ceil(Mrows / 64) (4 width + 4) floats
 int launch_out_back(hipStream_t s, const float *dy, const uint16_t *wo, int width, int64_t Mrows, const float *z,
-                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h);
-int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out);
+                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h,
+                    float *scratch);
+// scratch: at least ceil(rows / 64) cols floats
+int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out, float *scratch);
+int launch_sum_slices(hipStream_t s, const float *part, int nz, int64_t n, float *out);
 int launch_sum(hipStream_t s, const float *x, int n, float *out);
 int launch_gather(hipStream_t s, const double *pts, const double *tc, const int32_t *idx, int64_t count,
                   int64_t Mrows, double inv_scale, double *pb, float *tb);
-int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
-                float bc1, float bc2, float eps);
-int launch_refresh(hipStream_t s, const float *w, int rows, int cols, uint16_t *wb, uint16_t *wt);
+// Adam over n parameters at step *step (device) with lr_sched[*step - step0],
+// then *step += 1.
+int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, const float *lr_sched,
+                int64_t *step, int64_t step0, float b1, float b2, float eps);
+constexpr int kMaxLayers = 9;
+struct RefreshTable {
+    const float *w;
+    uint16_t *wb, *wt;
+    int n_layers;
+    int rows[kMaxLayers], cols[kMaxLayers];
+    int64_t woff[kMaxLayers], toff[kMaxLayers];
+};
+int launch_refresh(hipStream_t s, const RefreshTable &t);
+// Whole-network inference for width 256 (activations in LDS).
+struct FusedArgs {
+    const double *pts;
+    int64_t M;
+    MlpNorm norm;
+    const float *Bff;
+    int n_ff, depth, act;
+    const uint16_t *w[kMaxLayers];  // hidden layer weights, bf16 [256][n_in]
+    const float *b[kMaxLayers];
+    const uint16_t *wo;             // output layer bf16 [4][256]
+    const float *bo;
+    double scale;
+    double *A;                      // [M][4]
+};
+bool fused_ok(int n_ff, int width, int depth);
+int launch_mlp_fused(hipStream_t s, const FusedArgs &f);
 int launch_grid_pts(hipStream_t s, const double *th, const double *ph, const double *fr, int64_t na, int nf,
                     double *pts);
 int launch_probe_check(hipStream_t s, const double *A_sbr, const double *A_sur, int64_t n_ta, int n_tf, int per_tile,

@@ -66,7 +66,8 @@ struct sbr_mlp {
     Bufs keep;                           // parameters and state
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *Bff = nullptr;
     uint16_t *wb = nullptr, *wt = nullptr;
-    int64_t adam_t = 0;
+    int64_t *step = nullptr;  // device: Adam steps taken
+    int64_t adam_t = 0;       // host mirror of *step
     // workspaces (grown on demand)
     Bufs ws_pred;
     int64_t pred_rows = 0;
@@ -79,6 +80,8 @@ struct sbr_mlp {
     uint16_t *dzb[2] = {nullptr, nullptr}, *dzbt[2] = {nullptr, nullptr};
     double *pb = nullptr;
     float *tb = nullptr, *dy = nullptr, *part = nullptr, *losses = nullptr;
+    float *red = nullptr;  // reduction scratch (split-K slices, column-sum partials)
+    int ksplit = 1;
     int32_t *idx = nullptr;
     int64_t idx_cap = 0;
     int64_t loss_cap = 0;
@@ -89,12 +92,18 @@ namespace {
 
 int refresh_bf16(sbr_mlp *M, hipStream_t s)
 {
-    int rc;
-    for (int l = 0; l <= M->depth; ++l)
-        if ((rc = launch_refresh(s, M->w + M->woff[l], M->n_out[l], M->n_in[l], M->wb + M->woff[l],
-                                 M->toff[l] >= 0 ? M->wt + M->toff[l] : nullptr)))
-            return rc;
-    return SBR_OK;
+    RefreshTable t{};
+    t.w = M->w;
+    t.wb = M->wb;
+    t.wt = M->wt;
+    t.n_layers = M->depth + 1;
+    for (int l = 0; l <= M->depth; ++l) {
+        t.rows[l] = M->n_out[l];
+        t.cols[l] = M->n_in[l];
+        t.woff[l] = M->woff[l];
+        t.toff[l] = M->toff[l];
+    }
+    return launch_refresh(s, t);
 }
 
 int ensure_pred(sbr_mlp *M, int64_t rows)
@@ -138,6 +147,14 @@ int ensure_train(sbr_mlp *M, int64_t rows)
         (rc = M->ws_train.alloc(&M->dy, static_cast<size_t>(rows) * 4)) ||
         (rc = M->ws_train.alloc(&M->part, static_cast<size_t>(rows / 16 + 1))))
         return rc;
+    // weight gradients sum over the batch: split it so that each block walks 128..256 rows
+    int ks = 1;
+    while (ks * 2 <= 32 && rows % (static_cast<int64_t>(ks) * 2 * 16) == 0 && rows / (ks * 2) >= 128) ks *= 2;
+    M->ksplit = ks;
+    const int64_t kin_max = std::max(W, 2 * M->n_ff);
+    const int64_t R = (rows + 63) / 64;
+    const int64_t red = std::max({static_cast<int64_t>(ks) * W * kin_max, R * (4 * W + 4), R * W});
+    if ((rc = M->ws_train.alloc(&M->red, static_cast<size_t>(red)))) return rc;
     M->train_rows = rows;
     return SBR_OK;
 }
@@ -175,7 +192,7 @@ int batch_grad(sbr_mlp *M, hipStream_t s, int64_t count, int64_t rows, float *lo
         (rc = launch_sum(s, M->part, static_cast<int>(nblk), loss_slot)))
         return rc;
     if ((rc = launch_out_back(s, M->dy, M->wb + M->woff[D], W, rows, M->z[D - 1], M->act, M->dz[0], M->dzb[0],
-                              M->dzbt[0], M->g + M->woff[D], M->g + M->boff[D], M->h[D])))
+                              M->dzbt[0], M->g + M->woff[D], M->g + M->boff[D], M->h[D], M->red)))
         return rc;
     int cur = 0;
     for (int l = D; l >= 1; --l) {
@@ -188,10 +205,14 @@ int batch_grad(sbr_mlp *M, hipStream_t s, int64_t count, int64_t rows, float *lo
         a.M = W;
         a.N = kin;
         a.K = static_cast<int>(rows);
-        a.fout = M->g + M->woff[l - 1];
+        a.fout = M->red;
         a.ldf = kin;
-        if ((rc = launch_gemm(s, kEpiF32, a))) return rc;
-        if ((rc = launch_colsum(s, M->dz[cur], rows, W, M->g + M->boff[l - 1]))) return rc;
+        a.ksplit = M->ksplit;
+        a.split_stride = static_cast<int64_t>(W) * kin;
+        if ((rc = launch_gemm(s, kEpiF32, a)) ||
+            (rc = launch_sum_slices(s, M->red, M->ksplit, static_cast<int64_t>(W) * kin, M->g + M->woff[l - 1])))
+            return rc;
+        if ((rc = launch_colsum(s, M->dz[cur], rows, W, M->g + M->boff[l - 1], M->red))) return rc;
         if (l > 1) {
             const int nxt = cur ^ 1;
             GemmArgs b{};
@@ -279,7 +300,7 @@ extern "C" int sbr_mlp_create(sbr_ctx *ctx, const sbr_mlp_desc *d, sbr_mlp **out
     int rc;
     if ((rc = M->keep.alloc(&M->w, M->P)) || (rc = M->keep.alloc(&M->m, M->P)) || (rc = M->keep.alloc(&M->v, M->P)) ||
         (rc = M->keep.alloc(&M->g, M->P)) || (rc = M->keep.alloc(&M->wb, M->P)) ||
-        (rc = M->keep.alloc(&M->wt, std::max<int64_t>(toff, 1))) ||
+        (rc = M->keep.alloc(&M->wt, std::max<int64_t>(toff, 1))) || (rc = M->keep.alloc(&M->step, 1)) ||
         (rc = M->keep.alloc(&M->Bff, 3 * static_cast<size_t>(d->n_ff)))) {
         delete M;
         return rc;
@@ -299,7 +320,7 @@ extern "C" int sbr_mlp_create(sbr_ctx *ctx, const sbr_mlp_desc *d, sbr_mlp **out
     if (hipMemcpy(M->Bff, hB.data(), 4 * hB.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(M->w, hw.data(), 4 * hw.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemsetAsync(M->m, 0, 4 * M->P, s) != hipSuccess || hipMemsetAsync(M->v, 0, 4 * M->P, s) != hipSuccess ||
-        hipMemsetAsync(M->g, 0, 4 * M->P, s) != hipSuccess) {
+        hipMemsetAsync(M->g, 0, 4 * M->P, s) != hipSuccess || hipMemsetAsync(M->step, 0, 8, s) != hipSuccess) {
         delete M;
         return fail(SBR_ERR_HIP, "sbr_mlp_create: initial upload failed");
     }
@@ -344,6 +365,7 @@ extern "C" int sbr_mlp_set_params(sbr_mlp *M, const float *host, int64_t n)
     SBR_HIP(hipMemcpy(M->w, host, 4 * M->P, hipMemcpyHostToDevice));
     SBR_HIP(hipMemsetAsync(M->m, 0, 4 * M->P, s));
     SBR_HIP(hipMemsetAsync(M->v, 0, 4 * M->P, s));
+    SBR_HIP(hipMemsetAsync(M->step, 0, 8, s));
     M->adam_t = 0;
     return refresh_bf16(M, s);
 }
@@ -370,6 +392,25 @@ extern "C" int sbr_mlp_predict(sbr_mlp *M, const double *pts, int64_t n, double 
     if (rc) return rc;
     SBR_HIP(hipSetDevice(M->device));
     hipStream_t s = M->ctx->stream;
+    if (fused_ok(M->n_ff, M->width, M->depth)) {  // one launch, activations never leave LDS
+        FusedArgs f{};
+        f.pts = pts;
+        f.M = n;
+        f.norm = M->norm;
+        f.Bff = M->Bff;
+        f.n_ff = M->n_ff;
+        f.depth = M->depth;
+        f.act = M->act;
+        for (int l = 0; l < M->depth; ++l) {
+            f.w[l] = M->wb + M->woff[l];
+            f.b[l] = M->w + M->boff[l];
+        }
+        f.wo = M->wb + M->woff[M->depth];
+        f.bo = M->w + M->boff[M->depth];
+        f.scale = M->scale;
+        f.A = A_out;
+        return launch_mlp_fused(s, f);
+    }
     const int64_t chunk = std::min(kPredictRows, pad64(n));
     if ((rc = ensure_pred(M, chunk))) return rc;
     const int W = M->width, K0 = 2 * M->n_ff;
@@ -430,6 +471,10 @@ extern "C" int sbr_mlp_gradients(sbr_mlp *M, const double *pts, const double *ta
     return SBR_OK;
 }
 
+// One epoch of training steps, captured once per call into a HIP graph and
+// replayed for every epoch: the shuffled order is uploaded before each
+// replay, the Adam step count and the learning-rate schedule live on the
+// device.
 extern "C" int sbr_mlp_train(sbr_mlp *M, const double *pts, const double *targets, int64_t n,
                              const sbr_train_opts *o, float *loss_per_epoch)
 {
@@ -445,55 +490,60 @@ extern "C" int sbr_mlp_train(sbr_mlp *M, const double *pts, const double *target
     const int64_t bsz = std::min<int64_t>(o->batch, n);
     const int64_t rows = pad64(bsz);
     const int64_t steps = (n + bsz - 1) / bsz;
+    const int64_t total = static_cast<int64_t>(o->epochs) * steps;
     if ((rc = ensure_train(M, rows))) return rc;
     Bufs tmp;
     int32_t *didx = nullptr;
-    float *dl = nullptr, *hl = nullptr;
-    if ((rc = tmp.alloc(&didx, n)) || (rc = tmp.alloc(&dl, steps))) return rc;
-    if (hipHostMalloc(reinterpret_cast<void **>(&hl), 4 * static_cast<size_t>(std::max<int64_t>(steps, n)),
-                      hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(SBR_ERR_OOM, "sbr_mlp_train: pinned allocation failed");
+    float *dl = nullptr, *dlr = nullptr;
+    if ((rc = tmp.alloc(&didx, n)) || (rc = tmp.alloc(&dl, steps)) || (rc = tmp.alloc(&dlr, total))) return rc;
+    // cosine decay from lr to lr_min over all steps of this call
+    std::vector<float> lr(total);
+    for (int64_t t = 0; t < total; ++t)
+        lr[t] = static_cast<float>(o->lr_min + 0.5 * (o->lr - o->lr_min) *
+                                                   (1.0 + std::cos(kPi * static_cast<double>(t) / static_cast<double>(total))));
+    SBR_HIP(hipMemcpyAsync(dlr, lr.data(), 4 * total, hipMemcpyHostToDevice, s));
+    const int64_t step0 = M->adam_t;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    // capture one epoch
+    hipStream_t cap = nullptr;
+    SBR_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return fail(SBR_ERR_HIP, "sbr_mlp_train: graph capture failed to start");
     }
-    int32_t *hidx = reinterpret_cast<int32_t *>(hl);  // shares the pinned buffer (used before the losses)
+    for (int64_t st = 0; st < steps && rc == SBR_OK; ++st) {
+        const int64_t cnt = std::min(bsz, n - st * bsz);
+        if ((rc = launch_gather(cap, pts, targets, didx + st * bsz, cnt, rows, 1.0 / M->scale, M->pb, M->tb)) ||
+            (rc = batch_grad(M, cap, cnt, rows, dl + st)) ||
+            (rc = launch_adam(cap, M->w, M->m, M->v, M->g, M->P, dlr, M->step, step0, b1, b2, eps)) ||
+            (rc = refresh_bf16(M, cap)))
+            break;
+    }
+    const hipError_t ec = hipStreamEndCapture(cap, &graph);
+    if (rc == SBR_OK && (ec != hipSuccess || !graph)) rc = fail(SBR_ERR_HIP, "sbr_mlp_train: graph capture failed");
+    if (rc == SBR_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(SBR_ERR_HIP, "sbr_mlp_train: graph instantiation failed");
+    float *hl = nullptr;
+    if (rc == SBR_OK && hipHostMalloc(reinterpret_cast<void **>(&hl), 4 * static_cast<size_t>(std::max<int64_t>(steps, n)),
+                                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        hl = nullptr;
+        rc = fail(SBR_ERR_OOM, "sbr_mlp_train: pinned allocation failed");
+    }
+    int32_t *hidx = reinterpret_cast<int32_t *>(hl);  // one pinned buffer: the order, then the losses
     std::mt19937_64 rng(o->seed);
     std::vector<int32_t> perm(n);
     for (int64_t i = 0; i < n; ++i) perm[i] = static_cast<int32_t>(i);
-    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
-    const int64_t total = static_cast<int64_t>(o->epochs) * steps;
-    int64_t step_no = 0;
     for (int e = 0; e < o->epochs && rc == SBR_OK; ++e) {
         std::shuffle(perm.begin(), perm.end(), rng);
-        if (hipStreamSynchronize(s) != hipSuccess) {
-            rc = fail(SBR_ERR_HIP, "sbr_mlp_train: stream error");
-            break;
-        }
         std::memcpy(hidx, perm.data(), 4 * n);
-        if (hipMemcpyAsync(didx, hidx, 4 * n, hipMemcpyHostToDevice, s) != hipSuccess) {
-            rc = fail(SBR_ERR_HIP, "sbr_mlp_train: index upload failed");
-            break;
-        }
-        for (int64_t st = 0; st < steps && rc == SBR_OK; ++st, ++step_no) {
-            const int64_t cnt = std::min(bsz, n - st * bsz);
-            if ((rc = launch_gather(s, pts, targets, didx + st * bsz, cnt, rows, 1.0 / M->scale, M->pb, M->tb)) ||
-                (rc = batch_grad(M, s, cnt, rows, dl + st)))
-                break;
-            // cosine decay from lr to lr_min over all steps
-            const double lr = o->lr_min + 0.5 * (o->lr - o->lr_min) *
-                                              (1.0 + std::cos(kPi * static_cast<double>(step_no) / std::max<int64_t>(total, 1)));
-            M->adam_t += 1;
-            const double bc1 = 1.0 - std::pow(b1, static_cast<double>(M->adam_t));
-            const double bc2 = 1.0 - std::pow(b2, static_cast<double>(M->adam_t));
-            if ((rc = launch_adam(s, M->w, M->m, M->v, M->g, M->P, static_cast<float>(lr), static_cast<float>(b1),
-                                  static_cast<float>(b2), static_cast<float>(bc1), static_cast<float>(bc2),
-                                  static_cast<float>(eps))) ||
-                (rc = refresh_bf16(M, s)))
-                break;
-        }
-        if (rc) break;
-        if (hipMemcpyAsync(hl, dl, 4 * steps, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        if (hipMemcpyAsync(didx, hidx, 4 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipGraphLaunch(exec, s) != hipSuccess ||
+            hipMemcpyAsync(hl, dl, 4 * steps, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
-            rc = fail(SBR_ERR_HIP, "sbr_mlp_train: loss read-back failed");
+            rc = fail(SBR_ERR_HIP, "sbr_mlp_train: epoch launch failed");
             break;
         }
         if (loss_per_epoch) {
@@ -503,7 +553,11 @@ extern "C" int sbr_mlp_train(sbr_mlp *M, const double *pts, const double *target
         }
     }
     (void)hipStreamSynchronize(s);
-    (void)hipHostFree(hl);
+    if (rc == SBR_OK) M->adam_t += total;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (hl) (void)hipHostFree(hl);
     return rc;
 }
 

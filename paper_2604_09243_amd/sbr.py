@@ -20,6 +20,7 @@ OK, ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_SAMPLING, ERR_OOM, ERR_HIP, ERR_OVERF
 POL_H, POL_V = 0, 1
 MODE_VECTOR, MODE_PAPER = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
+BUILD_LBVH, BUILD_SAH = 0, 1
 REC_VALID, REC_TRAPPED, REC_BACK_LAST = 1, 2, 4
 OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRONT, OPT_NO_GRAPH = 1, 2, 4, 8, 16, 32
 MAX_BOUNCES = 64
@@ -29,7 +30,7 @@ _d3 = C.c_double * 3
 
 
 class BvhOpts(C.Structure):
-    _fields_ = [("struct_size", C.c_uint32), ("mem", C.c_int32), ("leaf_size", C.c_int32)]
+    _fields_ = [("struct_size", C.c_uint32), ("mem", C.c_int32), ("leaf_size", C.c_int32), ("builder", C.c_int32)]
 
 
 class BvhInfo(C.Structure):
@@ -464,11 +465,12 @@ class Context:
             pass
 
     # ------------------------------------------------------------ build
-    def build_bvh(self, V, T, leaf_size=0):
+    def build_bvh(self, V, T, leaf_size=0, builder=BUILD_LBVH):
         """V: [n_v, 3] float32, T: [n_t, 3] int32 (numpy host arrays or
-        torch device tensors); leaf_size 1..4 (0 = library default)."""
+        torch device tensors); leaf_size 1..4 (0 = library default);
+        builder BUILD_LBVH (GPU) or BUILD_SAH (host binned SAH)."""
         torch = _torch()
-        opts = BvhOpts(C.sizeof(BvhOpts), MEM_HOST, int(leaf_size))
+        opts = BvhOpts(C.sizeof(BvhOpts), MEM_HOST, int(leaf_size), int(builder))
         if isinstance(V, torch.Tensor):
             V = V.contiguous()
             T = T.contiguous()

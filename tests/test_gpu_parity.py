@@ -102,9 +102,10 @@ def _grid_case(orc, V, T, th, ph, ds, bmax, edge=True, use_bvh=False, subset=Non
     return m, k, tv, pv, o, d, r
 
 
+@pytest.mark.parametrize("builder", [0, 1])
 @pytest.mark.parametrize("case", ["sphere", "trihedral45", "trihedral12.5", "dihedral", "plate_oblique"])
-def test_trace_parity_grids(torch, ctx, orc, case):
-    say("case", case)
+def test_trace_parity_grids(torch, ctx, orc, case, builder):
+    say("case", case, "builder", builder)
     if case == "sphere":
         w = si.sphere_case()
         V, T, th, ph, ds, bmax = w.V, w.T, 0.0, 0.0, w.ds, 5
@@ -118,7 +119,7 @@ def test_trace_parity_grids(torch, ctx, orc, case):
         V, T = si.plate(1.0, 0.7, 8, 8)
         th, ph, ds, bmax = 33.0, 71.0, C0 / 10e9 / 10, 5
     m, k, tv, pv, o, d, r = _grid_case(orc, V, T, th, ph, ds, bmax)
-    bvh = ctx.build_bvh(V, T)
+    bvh = ctx.build_bvh(V, T, builder=builder)
     assert bvh.n_live == len(T) and 1 <= bvh.n_nodes <= len(T) - 1
     raw, g = _gpu_trace(torch, ctx, bvh, o, d, pv, tv, bmax, k)
     n_edge, n_mis = compare_trace(r, g, bmax)
@@ -127,22 +128,24 @@ def test_trace_parity_grids(torch, ctx, orc, case):
     say(case, "rays", len(o), "edge-ambiguous", n_edge, "mismatching among them", n_mis)
 
 
-def test_trace_parity_random_soup(torch, ctx, orc):
-    say("case random soup")
+@pytest.mark.parametrize("builder", [0, 1])
+def test_trace_parity_random_soup(torch, ctx, orc, builder):
+    say("case random soup", builder)
     V, T = si.random_triangles(3000, seed=11, box=1.0, size=0.2)
     o, _ = si.random_rays(30000, seed=12, box=1.2)
     m = orc.Mesh(V, T)
     k, tv, pv = orc.frame(63.0, 17.0)
     o = (o - 3.0 * k).astype(np.float32)
     r = orc.trace(m, o, k.astype(np.float32), pv, tv, k, 8, edge_diag=True, want_path=True)
-    bvh = ctx.build_bvh(V, T)
+    bvh = ctx.build_bvh(V, T, builder=builder)
     _, g = _gpu_trace(torch, ctx, bvh, o, k.astype(np.float32), pv, tv, 8, k)
     n_edge, n_mis = compare_trace(r, g, 8)
     assert (r["nb"] >= 3).sum() > 100
     say("soup edge", n_edge, "mismatch", n_mis)
 
 
-def test_trace_parity_random_directions(torch, ctx, orc):
+@pytest.mark.parametrize("builder", [0, 1])
+def test_trace_parity_random_directions(torch, ctx, orc, builder):
     # every ray its own direction (incoherent), many bounces in a closed box of soup
     say("case random directions")
     V, T = si.random_triangles(1500, seed=21, box=1.0, size=0.25)
@@ -156,7 +159,7 @@ def test_trace_parity_random_directions(torch, ctx, orc):
     ev /= np.linalg.norm(ev, axis=1, keepdims=True)
     # the oracle takes one polarisation pair; compare only geometry/ids here
     r = orc.trace(m, o, d, [1.0, 0, 0], [0, 1.0, 0], k, 12, edge_diag=True, want_path=True)
-    bvh = ctx.build_bvh(V, T)
+    bvh = ctx.build_bvh(V, T, builder=builder)
     _, g = _gpu_trace(torch, ctx, bvh, o, d, eh.astype(np.float32), ev.astype(np.float32), 12, k)
     edge = (r["flags"] & 8) != 0
     ok = ~edge
@@ -191,9 +194,10 @@ def test_trace_tiny_meshes(torch, ctx, orc):
         dd = np.array(d, np.float32)
         for flags, kw in ((0, {}), (1, dict(drop_trapped=True))):
             r = orc.trace(m, oo, dd, e, ev, k, 4, want_path=True, **kw)
-            bvh = ctx.build_bvh(V, T)
-            _, g = _gpu_trace(torch, ctx, bvh, oo, dd, e, ev, 4, k, flags=flags)
-            compare_trace(r, g, 4, allow_edge=False)
+            for builder in (0, 1):
+                bvh = ctx.build_bvh(V, T, builder=builder)
+                _, g = _gpu_trace(torch, ctx, bvh, oo, dd, e, ev, 4, k, flags=flags)
+                compare_trace(r, g, 4, allow_edge=False)
 
 
 # --------------------------------------------------------------------------
@@ -274,11 +278,22 @@ def test_sweep_multifrequency_equals_single(torch, ctx):
     V, T = si.trihedral(1.0, 8)
     bvh = ctx.build_bvh(V, T)
     th, ph = np.array([60.0, 50.0]), np.array([30.0, 10.0])
-    fs = np.array([8e9, 9e9, 10e9])
+    # unevenly spaced: every frequency is evaluated directly -> bit for bit
+    fs = np.array([8e9, 9.3e9, 10e9, 8.5e9, 9.9e9])
     A, _, _ = ctx.rcs_sweep(bvh, th, ph, fs, 5, ds=C0 / 10e9 / 10)
+    singles = []
     for i, f in enumerate(fs):
         A1, _, _ = ctx.rcs_sweep(bvh, th, ph, [f], 5, ds=C0 / 10e9 / 10)
-        assert np.array_equal(A.cpu().numpy()[:, i], A1.cpu().numpy()[:, 0])
+        singles.append(A1.cpu().numpy()[:, 0])
+        assert np.array_equal(A.cpu().numpy()[:, i], singles[-1])
+    # evenly spaced: the phasor recurrence over frequencies agrees to rounding
+    fe = np.linspace(8e9, 10e9, 9)
+    A, _, _ = ctx.rcs_sweep(bvh, th, ph, fe, 5, ds=C0 / 10e9 / 10)
+    A = A.cpu().numpy()
+    for i, f in enumerate(fe):
+        A1, _, _ = ctx.rcs_sweep(bvh, th, ph, [f], 5, ds=C0 / 10e9 / 10)
+        A1 = A1.cpu().numpy()[:, 0]
+        assert np.max(np.abs(A[:, i] - A1)) <= 1e-12 * np.max(np.abs(A1))
 
 
 def test_sweep_errors(torch, ctx):

@@ -37,15 +37,15 @@ def test_tune_and_leaf_size_do_not_change_results(torch, ctx):
     V, T = si.trihedral(1.0, 16)
     th, ph = np.full(9, 54.74), np.linspace(0.0, 90.0, 9)
     ref = None
-    for leaf in (1, 2, 4):
-        bvh = ctx.build_bvh(V, T, leaf_size=leaf)
+    for leaf, builder in ((1, 0), (2, 0), (4, 0), (1, 1), (4, 1)):
+        bvh = ctx.build_bvh(V, T, leaf_size=leaf, builder=builder)
         for kw in ({}, dict(tile_w=4), dict(tile_w=32), dict(claim_tiles=1), dict(claim_tiles=16),
                    dict(refill_min=1), dict(refill_min=33), dict(blocks_per_cu=2)):
             A, _, st = ctx.rcs_sweep(bvh, th, ph, [10e9], 5, samples_per_lambda=10.0, tune=sbr.make_tune(**kw))
             A = A.cpu().numpy()
             if ref is None:
                 ref = (A, st["queries"])
-            assert np.array_equal(A, ref[0]), (leaf, kw)
+            assert np.array_equal(A, ref[0]), (leaf, builder, kw)
             assert st["queries"] == ref[1]
     t = ctx.autotune(bvh, th, ph, [10e9], 5, samples_per_lambda=10.0)
     A, _, _ = ctx.rcs_sweep(bvh, th, ph, [10e9], 5, samples_per_lambda=10.0, tune=t)
@@ -90,9 +90,12 @@ def test_aircraft_full_sweep_sampled_parity(torch, ctx, orc, aircraft):
     say("aircraft rel err", err.max(), "dB", np.abs(s_o - s_g)[sel].max())
 
 
-def test_aircraft_trace_bit_exact_on_sampled_rays(torch, ctx, orc, aircraft):
+@pytest.mark.parametrize("builder", [0, 1])
+def test_aircraft_trace_bit_exact_on_sampled_rays(torch, ctx, orc, aircraft, builder):
     w, bvh, m = aircraft
-    say("case aircraft sampled rays")
+    say("case aircraft sampled rays, builder", builder)
+    if builder == 1:
+        bvh = ctx.build_bvh(w.V, w.T, builder=1)
     rng = np.random.default_rng(3)
     for phi in (23.0, 180.0):
         k, tv, pv = orc.frame(90.0, phi)
