@@ -247,22 +247,27 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
     }
 }
 
-// One thread per (angle, frequency): fixed-order sum of the angle's block
-// partials, then A = -(k dA / 2 pi) 2^-32 S and sigma in dBsm.
-__global__ void k_po_final(PoP p, int max_nf, double *__restrict__ A_out, double *__restrict__ sigma)
+// One wave per (angle, frequency): lane t sums the angle's block partials
+// t, t + 64, ... in float64, the lanes are combined by a fixed xor-shuffle
+// tree (the same order on every run), then A = -(k dA / 2 pi) 2^-32 S and
+// sigma in dBsm.
+__global__ __launch_bounds__(64) void k_po_final(PoP p, int max_nf, double *__restrict__ A_out,
+                                                 double *__restrict__ sigma)
 {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= static_cast<int64_t>(p.n_angles) * max_nf) return;
-    const int a = static_cast<int>(idx / max_nf), f = static_cast<int>(idx % max_nf);
+    const int a = static_cast<int>(blockIdx.x / max_nf), f = static_cast<int>(blockIdx.x % max_nf);
     const PoAngle &A = p.ang[a];
     if (f >= A.n_f) return;
+    const int lane = threadIdx.x;
     const int64_t nch = po_units(A.rec_cnt);
     double S[8];
     for (int e = 0; e < 8; ++e) S[e] = 0.0;
-    for (int64_t c = 0; c < nch; ++c) {
+    for (int64_t c = lane; c < nch; c += 64) {
         const long long *q = p.partial + (A.part_base + c * A.n_f + f) * 8;
         for (int e = 0; e < 8; ++e) S[e] += static_cast<double>(q[e]);
     }
+    for (int off = 32; off >= 1; off >>= 1)
+        for (int e = 0; e < 8; ++e) S[e] += __shfl_xor(S[e], off, 64);
+    if (lane != 0) return;
     const double C = -(p.kf[A.kf_off + f] * A.dA / (2.0 * kPi)) * 2.3283064365386963e-10;  // 2^-32
     const int64_t row = A.out_base + f;
     double *Ao = A_out + row * 8;
@@ -325,7 +330,8 @@ int launch_po(hipStream_t s, const PoArgs &a)
 int launch_po_finalize(hipStream_t s, const PoArgs &a, double *A_out, double *sigma_out)
 {
     const int64_t n = static_cast<int64_t>(a.n_angles) * a.max_nf;
-    k_po_final<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(make_pop(a), a.max_nf, A_out, sigma_out);
+    if (n > 2147483647LL) return fail(SBR_ERR_OVERFLOW, "PO finalize: too many outputs");
+    k_po_final<<<static_cast<unsigned>(n), 64, 0, s>>>(make_pop(a), a.max_nf, A_out, sigma_out);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
