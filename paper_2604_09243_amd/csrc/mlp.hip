@@ -33,28 +33,63 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ uint16_t to_bf16(float x)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// float32 -> bf16, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t to_bf16x2(float lo, float hi)
 {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{lo, hi}), bf16x2));
 }
+
+__device__ __forceinline__ uint16_t to_bf16(float x) { return static_cast<uint16_t>(to_bf16x2(x, 0.0f)); }
 
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
-__device__ __forceinline__ float act_f(float z, int kind)
+// SiLU through the logistic function sigma(z) = 1 / (1 + 2^(-z log2 e)),
+// with the hardware base-2 exponential and reciprocal (about 1 ulp each;
+// the activations are rounded to bf16 afterwards).  At z -> -inf the
+// exponential overflows to +inf and sigma to 0, so SiLU -> -0.
+__device__ __forceinline__ float sigmoid_f(float z)
 {
-    if (kind == kActSilu) return z / (1.0f + expf(-z));
-    return fmaxf(z, 0.0f);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
+
+template <int kAct>
+__device__ __forceinline__ float act_t(float z)
+{
+    if constexpr (kAct == kActSilu) return z * sigmoid_f(z);
+    else return fmaxf(z, 0.0f);
+}
+
+__device__ __forceinline__ float act_f(float z, int kind) { return kind == kActSilu ? act_t<kActSilu>(z) : act_t<kActRelu>(z); }
 
 __device__ __forceinline__ float act_d(float z, int kind)
 {
     if (kind == kActSilu) {
-        const float s = 1.0f / (1.0f + expf(-z));
+        const float s = sigmoid_f(z);
         return s * (1.0f + z * (1.0f - s));
     }
     return z > 0.0f ? 1.0f : 0.0f;
+}
+
+// Fourier features of one point: xn = the point mapped to [-1, 1]^3, then
+// for feature q (sin 2 pi t, cos 2 pi t) with t = B_q . xn in float64,
+// reduced to [-1/2, 1/2] before the float32 sine and cosine.
+__device__ __forceinline__ double norm_coord(const double *p, const MlpNorm &nm, int c)
+{
+    return 2.0 * (p[c] - nm.lo[c]) / (nm.hi[c] - nm.lo[c]) - 1.0;
+}
+
+__device__ __forceinline__ void ff_pair(const double *xn, const float *Bq, uint16_t &hs, uint16_t &hc)
+{
+    double t = 0.0;
+    for (int c = 0; c < 3; ++c) t += static_cast<double>(Bq[c]) * xn[c];
+    const float fr = static_cast<float>(t - rint(t));
+    float sn, co;
+    sincosf(6.2831853071795865f * fr, &sn, &co);
+    hs = to_bf16(sn);
+    hc = to_bf16(co);
 }
 
 // ---------------------------------------------------------------- GEMM
@@ -121,16 +156,9 @@ __global__ void k_embed(const double *__restrict__ pts, int64_t M, int64_t Mpad,
     const int f = static_cast<int>(i % n_ff);
     uint16_t hs = 0, hc = 0;
     if (m < M) {
-        double t = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            const double xn = 2.0 * (pts[3 * m + c] - nm.lo[c]) / (nm.hi[c] - nm.lo[c]) - 1.0;
-            t += static_cast<double>(Bff[3 * f + c]) * xn;
-        }
-        const float fr = static_cast<float>(t - rint(t));
-        float s, co;
-        sincosf(6.2831853071795865f * fr, &s, &co);
-        hs = to_bf16(s);
-        hc = to_bf16(co);
+        double xn[3];
+        for (int c = 0; c < 3; ++c) xn[c] = norm_coord(pts + 3 * m, nm, c);
+        ff_pair(xn, Bff + 3 * f, hs, hc);
     }
     const int w = 2 * n_ff;
     h0[m * w + f] = hs;
@@ -262,22 +290,34 @@ __global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ x
 }
 
 // out[i] = sum over z = 0..nz-1 of part[z][i], in z order.
-__global__ void k_sum_slices(const float *__restrict__ part, int nz, int64_t n, float *__restrict__ out)
+// out[i] = sum over z of part[z][i].  A block of 256 threads takes 64
+// consecutive i; wave w sums the slices z = w, w + 4, ... in order, and the
+// four wave sums are added in wave order: a fixed order for every launch.
+__global__ __launch_bounds__(256) void k_sum_slices(const float *__restrict__ part, int nz, int64_t n,
+                                                    float *__restrict__ out)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
     float sum = 0.f;
-    for (int z = 0; z < nz; ++z) sum += part[static_cast<int64_t>(z) * n + i];
-    out[i] = sum;
+    if (i < n) {
+#pragma unroll 4
+        for (int z = w; z < nz; z += 4) sum += part[static_cast<int64_t>(z) * n + i];
+    }
+    red[w][lane] = sum;
+    __syncthreads();
+    if (w == 0 && i < n) out[i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-__global__ void k_sum(const float *__restrict__ x, int n, float *__restrict__ out)
+// *out = sum of x[0 .. n): one wave, lane-strided sums, then a fixed
+// butterfly over the 64 lanes.
+__global__ __launch_bounds__(64) void k_sum(const float *__restrict__ x, int n, float *__restrict__ out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        float s = 0.f;
-        for (int i = 0; i < n; ++i) s += x[i];
-        *out = s;
-    }
+    const int lane = threadIdx.x;
+    float s = 0.f;
+    for (int i = lane; i < n; i += 64) s += x[i];
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) *out = s;
 }
 
 // Training rows of a batch: rows idx[b] of the points and of the complex
@@ -324,8 +364,18 @@ __global__ void k_step_inc(int64_t *step)
     if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
 }
 
+// Fragment-major position of element (m, n) of a [rows][K] bf16 matrix
+// (rows a multiple of 32, K of 16): 32 x 16 blocks, row block major, each
+// block stored as the 64 lanes x 8 elements of a v_mfma_f32_32x32x16_bf16
+// operand (lane m % 32 + 32 ((n / 8) % 2), element n % 8).
+__device__ __forceinline__ int frag_index(int m, int n, int K)
+{
+    return ((((m >> 5) * (K >> 4) + (n >> 4)) * 64 + ((m & 31) + 32 * ((n >> 3) & 1))) << 3) + (n & 7);
+}
+
 // bf16 copies of every weight matrix [rows][cols] and, where a transposed
-// copy exists, of its transpose; blockIdx.y = layer.
+// copy exists, of its transpose, and where asked a fragment-major copy;
+// blockIdx.y = layer.
 __global__ void k_refresh(RefreshTable t)
 {
     const int l = blockIdx.y;
@@ -333,111 +383,129 @@ __global__ void k_refresh(RefreshTable t)
     const float *w = t.w + t.woff[l];
     uint16_t *wb = t.wb + t.woff[l];
     uint16_t *wt = t.toff[l] >= 0 ? t.wt + t.toff[l] : nullptr;
+    uint16_t *wf = t.frag[l] ? t.wf + t.woff[l] : nullptr;  // fragment-major copy (fused inference)
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < static_cast<int64_t>(rows) * cols;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const uint16_t b = to_bf16(w[i]);
         wb[i] = b;
         if (wt) wt[static_cast<int64_t>(i % cols) * rows + i / cols] = b;
+        if (wf) wf[frag_index(static_cast<int>(i / cols), static_cast<int>(i % cols), cols)] = b;
     }
 }
 
 // ---------------------------------------------------------------- fused inference
-// The whole network for 128 points per 256-thread block, width 256: the
-// features and every hidden activation stay in LDS (two 128 x 264 bf16
-// buffers, rows padded by 8 elements), so HBM sees only the points and the
-// outputs.  Wave w computes output columns [64 w, 64 w + 64) of every layer
-// for all 128 rows: four row blocks x two column blocks of 32 x 32 MFMA
-// accumulators; the A fragments come from LDS, the wave's quarter of the
-// bf16 weights from global memory (L2-resident, 128 KB per layer), one k step
-// loaded ahead.  The accumulation order over k is the one of k_gemm, so the
-// hidden activations equal those of the layer-by-layer kernels bit for bit.
-constexpr int kFusedRows = 128, kFusedW = 256, kFusedLd = kFusedW + 8;
+// The whole network for 128 points per 256-thread block, width 256, two
+// blocks per CU: the features and every hidden activation stay in one
+// 128 x 256 bf16 LDS buffer, overwritten in place layer by layer, so HBM sees
+// only the points and the outputs.  Each layer is computed transposed,
+// z^T = W h^T: wave w owns output features [64 w, 64 w + 64) of all 128
+// points, two 32-feature blocks of W (the A operand) times four 32-point
+// blocks of h^T (the B operand), eight 32 x 32 MFMA accumulators.  Weights
+// and activations are both stored fragment-major (frag_index: points, resp.
+// output features, as rows), so every operand load is one contiguous 1 KB
+// per wave; the weight fragments are loaded kPrefetch k steps ahead into a
+// register ring.  The accumulators start at the bias.  An accumulator
+// register holds four consecutive features of one point, which the epilogue
+// stores as one 8-byte LDS write.  The
+// output layer (4 features) is one more MFMA pass with W_out padded to 32
+// rows by zero lanes.
+constexpr int kFusedRows = 128, kFusedW = 256, kPrefetch = 4;
 
-__global__ __launch_bounds__(256, 1) void k_mlp_fused(FusedArgs f)
+template <int kAct>
+__global__ __launch_bounds__(256, 2) void k_mlp_fused(FusedArgs f)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t act[2][kFusedRows * kFusedLd];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ __attribute__((aligned(16))) uint16_t act[kFusedRows * kFusedW];
+    __shared__ double xs[kFusedRows][3];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 5, c32 = lane & 31;
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kFusedRows;
-    // features -> act[0] columns [0, 2 n_ff)
-    for (int i = tid; i < kFusedRows * f.n_ff; i += 256) {
-        const int r = i / f.n_ff, q = i % f.n_ff;
-        const int64_t m = row0 + r;
-        uint16_t hs = 0, hc = 0;
-        if (m < f.M) {
-            double t = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                const double xn = 2.0 * (f.pts[3 * m + c] - f.norm.lo[c]) / (f.norm.hi[c] - f.norm.lo[c]) - 1.0;
-                t += static_cast<double>(f.Bff[3 * q + c]) * xn;
-            }
-            const float fr = static_cast<float>(t - rint(t));
-            float sn, co;
-            sincosf(6.2831853071795865f * fr, &sn, &co);
-            hs = to_bf16(sn);
-            hc = to_bf16(co);
-        }
-        act[0][r * kFusedLd + q] = hs;
-        act[0][r * kFusedLd + f.n_ff + q] = hc;
+    const int K0 = 2 * f.n_ff;
+    if (tid < kFusedRows) {
+        const int64_t m = row0 + tid;
+        for (int c = 0; c < 3; ++c) xs[tid][c] = m < f.M ? norm_coord(f.pts + 3 * m, f.norm, c) : 0.0;
     }
     __syncthreads();
-    const int r = lane & 31, kh = (lane >> 5) * 8;
-    const int col0 = wv * 64;
-    int cur = 0;
-    for (int l = 0; l < f.depth; ++l) {
-        const int K = l == 0 ? 2 * f.n_ff : kFusedW;
-        const uint16_t *W = f.w[l];  // [256][K]
-        const uint16_t *in = act[cur];
-        uint16_t *out = act[cur ^ 1];
-        f32x16 acc[4][2];
-        for (int rb = 0; rb < 4; ++rb)
-            for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x16{};
-        const uint16_t *pb0 = W + static_cast<int64_t>(col0 + r) * K + kh;
-        const uint16_t *pb1 = W + static_cast<int64_t>(col0 + 32 + r) * K + kh;
-        bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0);
-        bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1);
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            bf16x8 nb0 = b0, nb1 = b1;
-            if (k0 + 16 < K) {
-                nb0 = *reinterpret_cast<const bf16x8 *>(pb0 + k0 + 16);
-                nb1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0 + 16);
-            }
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(in + (rb * 32 + r) * kFusedLd + k0 + kh);
-                acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[rb][0], 0, 0, 0);
-                acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[rb][1], 0, 0, 0);
-            }
-            b0 = nb0;
-            b1 = nb1;
+    {   // features -> act, width K0; n_ff divides 256, so each thread keeps one feature q
+        const int q = tid % f.n_ff;
+        const float Bq[3] = {f.Bff[3 * q], f.Bff[3 * q + 1], f.Bff[3 * q + 2]};
+        for (int r = tid / f.n_ff; r < kFusedRows; r += 256 / f.n_ff) {
+            uint16_t hs = 0, hc = 0;
+            if (row0 + r < f.M) ff_pair(xs[r], Bq, hs, hc);
+            act[frag_index(r, q, K0)] = hs;
+            act[frag_index(r, f.n_ff + q, K0)] = hc;
         }
+    }
+    __syncthreads();
+    const bf16x8 *in = reinterpret_cast<const bf16x8 *>(act);
+    const int fb0 = 2 * wv;  // this wave's two 32-feature blocks
+    for (int l = 0; l < f.depth; ++l) {
+        const int K = l == 0 ? K0 : kFusedW;
+        const int nks = K >> 4;
+        const bf16x8 *W = reinterpret_cast<const bf16x8 *>(f.wf[l]);
+        // accumulators start at the bias: register q of a 32 x 32 block holds
+        // feature 8 (q / 4) + 4 h + q % 4 of the block
         const float *bias = f.b[l];
+        f32x16 acc[2][4];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int fb = 0; fb < 2; ++fb) {
+            f32x16 b0;
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                const int n = col0 + 32 * cb + r;
-                const float bn = bias[n];
+            for (int q = 0; q < 16; ++q) b0[q] = bias[(fb0 + fb) * 32 + 8 * (q >> 2) + 4 * h + (q & 3)];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int m = rb * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    out[m * kFusedLd + n] = to_bf16(act_f(acc[rb][cb][q] + bn, f.act));
+            for (int pb = 0; pb < 4; ++pb) acc[fb][pb] = b0;
+        }
+        bf16x8 wq[kPrefetch][2];
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) {
+            wq[u][0] = W[(fb0 * nks + u) * 64 + lane];
+            wq[u][1] = W[((fb0 + 1) * nks + u) * 64 + lane];
+        }
+        for (int ks0 = 0; ks0 < nks; ks0 += kPrefetch) {
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                const int ks = ks0 + u;
+                const bf16x8 a0 = wq[u][0], a1 = wq[u][1];
+                if (ks + kPrefetch < nks) {
+                    wq[u][0] = W[(fb0 * nks + ks + kPrefetch) * 64 + lane];
+                    wq[u][1] = W[((fb0 + 1) * nks + ks + kPrefetch) * 64 + lane];
+                }
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) {
+                    const bf16x8 b = in[(pb * nks + ks) * 64 + lane];
+                    acc[0][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][pb], 0, 0, 0);
+                    acc[1][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][pb], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // every wave has read the layer input: overwrite it
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n0 = (fb0 + fb) * 32 + 8 * j + 4 * h;  // features n0 .. n0 + 3
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) {
+                    const f32x16 &c = acc[fb][pb];
+                    const uint32_t lo = to_bf16x2(act_t<kAct>(c[4 * j]), act_t<kAct>(c[4 * j + 1]));
+                    const uint32_t hi = to_bf16x2(act_t<kAct>(c[4 * j + 2]), act_t<kAct>(c[4 * j + 3]));
+                    *reinterpret_cast<uint2 *>(act + frag_index(pb * 32 + c32, n0, kFusedW)) = make_uint2(lo, hi);
                 }
             }
         __syncthreads();
-        cur ^= 1;
     }
-    // output layer: two threads per row, two outputs each
-    const int rr = tid >> 1, o0 = 2 * (tid & 1);
-    const int64_t m = row0 + rr;
-    const uint16_t *h = act[cur] + rr * kFusedLd;
-    float y0 = 0.f, y1 = 0.f;
-    for (int k = 0; k < kFusedW; ++k) {
-        const float hv = from_bf16(h[k]);
-        y0 += hv * from_bf16(f.wo[o0 * kFusedW + k]);
-        y1 += hv * from_bf16(f.wo[(o0 + 1) * kFusedW + k]);
+    // output layer: wave w takes points [32 w, 32 w + 32); lanes 0..3 (and
+    // 32..35) of the A operand carry W_out's rows, the rest are zero
+    f32x16 y = f32x16{};
+    const int nks = kFusedW >> 4;
+    for (int ks = 0; ks < nks; ++ks) {
+        bf16x8 a = bf16x8{};
+        if (c32 < 4) a = *reinterpret_cast<const bf16x8 *>(f.wo + c32 * kFusedW + ks * 16 + 8 * h);
+        const bf16x8 b = in[(wv * nks + ks) * 64 + lane];
+        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, y, 0, 0, 0);
     }
-    if (m < f.M) {
-        f.A[4 * m + o0] = f.scale * (y0 + f.bo[o0]);
-        f.A[4 * m + o0 + 1] = f.scale * (y1 + f.bo[o0 + 1]);
+    // rows 0..3 of the result (outputs) sit in registers 0..3 of lanes 0..31
+    const int64_t m = row0 + wv * 32 + c32;
+    if (h == 0 && m < f.M) {
+        for (int o = 0; o < 4; ++o) f.A[4 * m + o] = f.scale * (y[o] + f.bo[o]);
     }
 }
 
@@ -561,8 +629,8 @@ int launch_out_back(hipStream_t s, const float *dy, const uint16_t *wo, int widt
     float *pw = scratch, *pb = scratch + static_cast<int64_t>(R) * 4 * width;
     k_out_back<<<nblk(Mrows * width, 256), 256, 0, s>>>(dy, wo, width, Mrows, z, act, dz, dzb, dzbt);
     k_out_wgrad_part<<<dim3((width + 63) / 64, R), 256, 0, s>>>(dy, h, width, Mrows, pw, pb);
-    k_sum_slices<<<nblk(4 * width, 256), 256, 0, s>>>(pw, R, 4 * width, gw);
-    k_sum_slices<<<1, 64, 0, s>>>(pb, R, 4, gb);
+    k_sum_slices<<<nblk(4 * width, 64), 256, 0, s>>>(pw, R, 4 * width, gw);
+    k_sum_slices<<<1, 256, 0, s>>>(pb, R, 4, gb);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
@@ -571,14 +639,14 @@ int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *
 {
     const int R = static_cast<int>((rows + 63) / 64);
     k_colsum_part<<<dim3((cols + 63) / 64, R), 256, 0, s>>>(x, rows, cols, scratch);
-    k_sum_slices<<<nblk(cols, 256), 256, 0, s>>>(scratch, R, cols, out);
+    k_sum_slices<<<nblk(cols, 64), 256, 0, s>>>(scratch, R, cols, out);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
 int launch_sum_slices(hipStream_t s, const float *part, int nz, int64_t n, float *out)
 {
-    k_sum_slices<<<nblk(n, 256), 256, 0, s>>>(part, nz, n, out);
+    k_sum_slices<<<nblk(n, 64), 256, 0, s>>>(part, nz, n, out);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
@@ -642,12 +710,19 @@ int launch_scatter_copol(hipStream_t s, const double *A, const int64_t *dst, int
     return SBR_OK;
 }
 
-bool fused_ok(int n_ff, int width, int depth) { return width == kFusedW && 2 * n_ff <= kFusedW && depth <= kMaxLayers - 1; }
+// (the k loop of k_mlp_fused steps kPrefetch fragments at a time)
+bool fused_ok(int n_ff, int width, int depth)
+{
+    return width == kFusedW && 2 * n_ff <= kFusedW && (2 * n_ff / 16) % kPrefetch == 0 && depth <= kMaxLayers - 1;
+}
 
 int launch_mlp_fused(hipStream_t s, const FusedArgs &f)
 {
     if (f.M <= 0) return SBR_OK;
-    k_mlp_fused<<<nblk(f.M, kFusedRows), 256, 0, s>>>(f);
+    if (f.act == kActSilu)
+        k_mlp_fused<kActSilu><<<nblk(f.M, kFusedRows), 256, 0, s>>>(f);
+    else
+        k_mlp_fused<kActRelu><<<nblk(f.M, kFusedRows), 256, 0, s>>>(f);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

@@ -321,8 +321,9 @@ constexpr int kMaxLayers = 9;
 struct RefreshTable {
     const float *w;
     uint16_t *wb, *wt;
+    uint16_t *wf;  // fragment-major copies (layers with frag[l] != 0), at woff[l]
     int n_layers;
-    int rows[kMaxLayers], cols[kMaxLayers];
+    int rows[kMaxLayers], cols[kMaxLayers], frag[kMaxLayers];
     int64_t woff[kMaxLayers], toff[kMaxLayers];
 };
 int launch_refresh(hipStream_t s, const RefreshTable &t);
@@ -333,7 +334,7 @@ struct FusedArgs {
     MlpNorm norm;
     const float *Bff;
     int n_ff, depth, act;
-    const uint16_t *w[kMaxLayers];  // hidden layer weights, bf16 [256][n_in]
+    const uint16_t *wf[kMaxLayers];  // hidden layer weights, bf16 [256][n_in], fragment-major
     const float *b[kMaxLayers];
     const uint16_t *wo;             // output layer bf16 [4][256]
     const float *bo;

@@ -65,7 +65,7 @@ struct sbr_mlp {
     int64_t P = 0;
     Bufs keep;                           // parameters and state
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *Bff = nullptr;
-    uint16_t *wb = nullptr, *wt = nullptr;
+    uint16_t *wb = nullptr, *wt = nullptr, *wf = nullptr;  // wf: fragment-major hidden weights (fused inference)
     int64_t *step = nullptr;  // device: Adam steps taken
     int64_t adam_t = 0;       // host mirror of *step
     // workspaces (grown on demand)
@@ -96,10 +96,13 @@ int refresh_bf16(sbr_mlp *M, hipStream_t s)
     t.w = M->w;
     t.wb = M->wb;
     t.wt = M->wt;
+    t.wf = M->wf;
     t.n_layers = M->depth + 1;
+    const bool fused = fused_ok(M->n_ff, M->width, M->depth);
     for (int l = 0; l <= M->depth; ++l) {
         t.rows[l] = M->n_out[l];
         t.cols[l] = M->n_in[l];
+        t.frag[l] = fused && l < M->depth;
         t.woff[l] = M->woff[l];
         t.toff[l] = M->toff[l];
     }
@@ -300,7 +303,7 @@ extern "C" int sbr_mlp_create(sbr_ctx *ctx, const sbr_mlp_desc *d, sbr_mlp **out
     int rc;
     if ((rc = M->keep.alloc(&M->w, M->P)) || (rc = M->keep.alloc(&M->m, M->P)) || (rc = M->keep.alloc(&M->v, M->P)) ||
         (rc = M->keep.alloc(&M->g, M->P)) || (rc = M->keep.alloc(&M->wb, M->P)) ||
-        (rc = M->keep.alloc(&M->wt, std::max<int64_t>(toff, 1))) || (rc = M->keep.alloc(&M->step, 1)) ||
+        (rc = M->keep.alloc(&M->wf, M->P)) || (rc = M->keep.alloc(&M->wt, std::max<int64_t>(toff, 1))) || (rc = M->keep.alloc(&M->step, 1)) ||
         (rc = M->keep.alloc(&M->Bff, 3 * static_cast<size_t>(d->n_ff)))) {
         delete M;
         return rc;
@@ -402,7 +405,7 @@ extern "C" int sbr_mlp_predict(sbr_mlp *M, const double *pts, int64_t n, double 
         f.depth = M->depth;
         f.act = M->act;
         for (int l = 0; l < M->depth; ++l) {
-            f.w[l] = M->wb + M->woff[l];
+            f.wf[l] = M->wf + M->woff[l];
             f.b[l] = M->w + M->boff[l];
         }
         f.wo = M->wb + M->woff[M->depth];
