@@ -75,7 +75,9 @@ __device__ __forceinline__ float act_d(float z, int kind)
 
 // Fourier features of one point: xn = the point mapped to [-1, 1]^3, then
 // for feature q (sin 2 pi t, cos 2 pi t) with t = B_q . xn in float64,
-// reduced to [-1/2, 1/2] before the float32 sine and cosine.
+// reduced to [-1/2, 1/2] revolutions before the hardware float32 sine and
+// cosine (which take revolutions, so no rounded 2 pi factor enters; their
+// error on [-1/2, 1/2] is about 1.3e-7 absolute, below a float32 ulp of 1).
 __device__ __forceinline__ double norm_coord(const double *p, const MlpNorm &nm, int c)
 {
     return 2.0 * (p[c] - nm.lo[c]) / (nm.hi[c] - nm.lo[c]) - 1.0;
@@ -86,10 +88,8 @@ __device__ __forceinline__ void ff_pair(const double *xn, const float *Bq, uint1
     double t = 0.0;
     for (int c = 0; c < 3; ++c) t += static_cast<double>(Bq[c]) * xn[c];
     const float fr = static_cast<float>(t - rint(t));
-    float sn, co;
-    sincosf(6.2831853071795865f * fr, &sn, &co);
-    hs = to_bf16(sn);
-    hc = to_bf16(co);
+    hs = to_bf16(__builtin_amdgcn_sinf(fr));  // v_sin_f32 / v_cos_f32 take revolutions
+    hc = to_bf16(__builtin_amdgcn_cosf(fr));
 }
 
 // ---------------------------------------------------------------- GEMM
@@ -401,24 +401,89 @@ __global__ void k_refresh(RefreshTable t)
 // z^T = W h^T: wave w owns output features [64 w, 64 w + 64) of all 128
 // points, two 32-feature blocks of W (the A operand) times four 32-point
 // blocks of h^T (the B operand), eight 32 x 32 MFMA accumulators.  Weights
-// and activations are both stored fragment-major (frag_index: points, resp.
-// output features, as rows), so every operand load is one contiguous 1 KB
-// per wave; the weight fragments are loaded kPrefetch k steps ahead into a
-// register ring.  The accumulators start at the bias.  An accumulator
-// register holds four consecutive features of one point, which the epilogue
-// stores as one 8-byte LDS write.  The
-// output layer (4 features) is one more MFMA pass with W_out padded to 32
-// rows by zero lanes.
-constexpr int kFusedRows = 128, kFusedW = 256, kPrefetch = 4;
+// and activations are both stored fragment-major (frag_index: output
+// features, resp. points, as rows), so every operand load is one contiguous
+// 1 KB per wave.  The k loop is unrolled and its issue order pinned: per k
+// step (LDS read, two MFMAs) per point block, the LDS reads running two
+// ahead, then the weight loads for kPrefetch steps ahead (continuing into
+// the next layer's first steps).  An accumulator register holds four
+// consecutive features of one point: the epilogue adds the bias, applies the
+// activation and stores them as one 8-byte LDS write.  The output layer (4
+// features) is one more MFMA pass with W_out padded to 32 rows by zero lanes.
+#ifndef SBR_FUSED_PB
+#define SBR_FUSED_PB 4  // 32-point blocks per workgroup
+#endif
+#ifndef SBR_FUSED_OCC
+#define SBR_FUSED_OCC 2  // workgroups per CU the register budget is set for
+#endif
+constexpr int kFusedPB = SBR_FUSED_PB, kFusedRows = 32 * kFusedPB, kFusedW = 256, kPrefetch = 4;
+
+// One hidden layer's products for one wave: acc[fb][pb] += W block (fb0 +
+// fb) times h^T block pb over NKS k steps, fully unrolled.  The B fragments
+// (LDS) are read one step ahead; the weight ring wq is refilled kPrefetch
+// steps ahead, from Wn (the next layer's weights) past the last steps.
+template <int NKS>
+__device__ __forceinline__ void fused_products(const bf16x8 *in, const bf16x8 *W, const bf16x8 *Wn, int fb0, int lane,
+                                               bf16x8 (&wq)[kPrefetch][2], f32x16 (&acc)[2][kFusedPB])
+{
+    constexpr int nksn = kFusedW >> 4;  // k steps of every later layer
+    bf16x8 bq[2][kFusedPB];
+#pragma unroll
+    for (int pb = 0; pb < kFusedPB; ++pb) bq[0][pb] = in[(pb * NKS) * 64 + lane];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+        const int u = ks % kPrefetch;
+        const bf16x8 a0 = wq[u][0], a1 = wq[u][1];
+        if (ks + kPrefetch < NKS) {
+            wq[u][0] = W[(fb0 * NKS + ks + kPrefetch) * 64 + lane];
+            wq[u][1] = W[((fb0 + 1) * NKS + ks + kPrefetch) * 64 + lane];
+        } else {
+            wq[u][0] = Wn[(fb0 * nksn + ks + kPrefetch - NKS) * 64 + lane];
+            wq[u][1] = Wn[((fb0 + 1) * nksn + ks + kPrefetch - NKS) * 64 + lane];
+        }
+        if (ks + 1 < NKS) {
+#pragma unroll
+            for (int pb = 0; pb < kFusedPB; ++pb) bq[(ks + 1) & 1][pb] = in[(pb * NKS + ks + 1) * 64 + lane];
+        }
+#pragma unroll
+        for (int pb = 0; pb < kFusedPB; ++pb) {
+            acc[0][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bq[ks & 1][pb], acc[0][pb], 0, 0, 0);
+            acc[1][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bq[ks & 1][pb], acc[1][pb], 0, 0, 0);
+        }
+        // issue order of the step: (one LDS read, two MFMAs) x PB, then the two weight loads
+#pragma unroll
+        for (int pb = 0; pb < kFusedPB; ++pb) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+    }
+}
 
 template <int kAct>
-__global__ __launch_bounds__(256, 2) void k_mlp_fused(FusedArgs f)
+__global__ __launch_bounds__(256, SBR_FUSED_OCC) void k_mlp_fused(FusedArgs f)
 {
     __shared__ __attribute__((aligned(16))) uint16_t act[kFusedRows * kFusedW];
     __shared__ double xs[kFusedRows][3];
+    __shared__ __attribute__((aligned(16))) float bsh[kMaxLayers - 1][kFusedW];  // hidden-layer biases
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 5, c32 = lane & 31;
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kFusedRows;
     const int K0 = 2 * f.n_ff;
+    const int fb0 = 2 * wv;  // this wave's two 32-feature blocks
+    // weight ring: slot u holds the k steps = u (mod kPrefetch) of the current
+    // layer and, past its last steps, the first steps of the next layer; the
+    // first layer's are in flight during the feature computation
+    bf16x8 wq[kPrefetch][2];
+    {
+        const bf16x8 *W = reinterpret_cast<const bf16x8 *>(f.wf[0]);
+        const int nks = K0 >> 4;
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) {
+            wq[u][0] = W[(fb0 * nks + u) * 64 + lane];
+            wq[u][1] = W[((fb0 + 1) * nks + u) * 64 + lane];
+        }
+    }
+    for (int i = tid; i < f.depth * kFusedW; i += 256) bsh[i / kFusedW][i % kFusedW] = f.b[i / kFusedW][i % kFusedW];
     if (tid < kFusedRows) {
         const int64_t m = row0 + tid;
         for (int c = 0; c < 3; ++c) xs[tid][c] = m < f.M ? norm_coord(f.pts + 3 * m, f.norm, c) : 0.0;
@@ -436,76 +501,55 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fused(FusedArgs f)
     }
     __syncthreads();
     const bf16x8 *in = reinterpret_cast<const bf16x8 *>(act);
-    const int fb0 = 2 * wv;  // this wave's two 32-feature blocks
     for (int l = 0; l < f.depth; ++l) {
-        const int K = l == 0 ? K0 : kFusedW;
-        const int nks = K >> 4;
         const bf16x8 *W = reinterpret_cast<const bf16x8 *>(f.wf[l]);
-        // accumulators start at the bias: register q of a 32 x 32 block holds
-        // feature 8 (q / 4) + 4 h + q % 4 of the block
-        const float *bias = f.b[l];
-        f32x16 acc[2][4];
+        // (past the last layer the ring reloads its own weights, unused)
+        const bf16x8 *Wn = reinterpret_cast<const bf16x8 *>(f.wf[l + 1 < f.depth ? l + 1 : l]);
+        // register q of a 32 x 32 accumulator holds feature 8 (q / 4) + 4 h +
+        // q % 4 of its block; the bias is added in the epilogue
+        f32x16 acc[2][kFusedPB];
 #pragma unroll
-        for (int fb = 0; fb < 2; ++fb) {
-            f32x16 b0;
+        for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-            for (int q = 0; q < 16; ++q) b0[q] = bias[(fb0 + fb) * 32 + 8 * (q >> 2) + 4 * h + (q & 3)];
-#pragma unroll
-            for (int pb = 0; pb < 4; ++pb) acc[fb][pb] = b0;
-        }
-        bf16x8 wq[kPrefetch][2];
-#pragma unroll
-        for (int u = 0; u < kPrefetch; ++u) {
-            wq[u][0] = W[(fb0 * nks + u) * 64 + lane];
-            wq[u][1] = W[((fb0 + 1) * nks + u) * 64 + lane];
-        }
-        for (int ks0 = 0; ks0 < nks; ks0 += kPrefetch) {
-#pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) {
-                const int ks = ks0 + u;
-                const bf16x8 a0 = wq[u][0], a1 = wq[u][1];
-                if (ks + kPrefetch < nks) {
-                    wq[u][0] = W[(fb0 * nks + ks + kPrefetch) * 64 + lane];
-                    wq[u][1] = W[((fb0 + 1) * nks + ks + kPrefetch) * 64 + lane];
-                }
-#pragma unroll
-                for (int pb = 0; pb < 4; ++pb) {
-                    const bf16x8 b = in[(pb * nks + ks) * 64 + lane];
-                    acc[0][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][pb], 0, 0, 0);
-                    acc[1][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][pb], 0, 0, 0);
-                }
-            }
-        }
+            for (int pb = 0; pb < kFusedPB; ++pb) acc[fb][pb] = f32x16{};
+        if (l == 0 && K0 == 128)
+            fused_products<8>(in, W, Wn, fb0, lane, wq, acc);
+        else
+            fused_products<16>(in, W, Wn, fb0, lane, wq, acc);
         __syncthreads();  // every wave has read the layer input: overwrite it
 #pragma unroll
         for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int n0 = (fb0 + fb) * 32 + 8 * j + 4 * h;  // features n0 .. n0 + 3
+                const float4 bn4 = *reinterpret_cast<const float4 *>(&bsh[l][n0]);
+                const float bn[4] = {bn4.x, bn4.y, bn4.z, bn4.w};
 #pragma unroll
-                for (int pb = 0; pb < 4; ++pb) {
+                for (int pb = 0; pb < kFusedPB; ++pb) {
                     const f32x16 &c = acc[fb][pb];
-                    const uint32_t lo = to_bf16x2(act_t<kAct>(c[4 * j]), act_t<kAct>(c[4 * j + 1]));
-                    const uint32_t hi = to_bf16x2(act_t<kAct>(c[4 * j + 2]), act_t<kAct>(c[4 * j + 3]));
+                    const uint32_t lo = to_bf16x2(act_t<kAct>(c[4 * j] + bn[0]), act_t<kAct>(c[4 * j + 1] + bn[1]));
+                    const uint32_t hi = to_bf16x2(act_t<kAct>(c[4 * j + 2] + bn[2]), act_t<kAct>(c[4 * j + 3] + bn[3]));
                     *reinterpret_cast<uint2 *>(act + frag_index(pb * 32 + c32, n0, kFusedW)) = make_uint2(lo, hi);
                 }
             }
         __syncthreads();
     }
-    // output layer: wave w takes points [32 w, 32 w + 32); lanes 0..3 (and
-    // 32..35) of the A operand carry W_out's rows, the rest are zero
-    f32x16 y = f32x16{};
+    // output layer: wave w takes the 32-point blocks w, w + 4, ...; lanes
+    // 0..3 (and 32..35) of the A operand carry W_out's rows, the rest are zero
     const int nks = kFusedW >> 4;
-    for (int ks = 0; ks < nks; ++ks) {
-        bf16x8 a = bf16x8{};
-        if (c32 < 4) a = *reinterpret_cast<const bf16x8 *>(f.wo + c32 * kFusedW + ks * 16 + 8 * h);
-        const bf16x8 b = in[(wv * nks + ks) * 64 + lane];
-        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, y, 0, 0, 0);
-    }
-    // rows 0..3 of the result (outputs) sit in registers 0..3 of lanes 0..31
-    const int64_t m = row0 + wv * 32 + c32;
-    if (h == 0 && m < f.M) {
-        for (int o = 0; o < 4; ++o) f.A[4 * m + o] = f.scale * (y[o] + f.bo[o]);
+    for (int pb = wv; pb < kFusedPB; pb += 4) {
+        f32x16 y = f32x16{};
+        for (int ks = 0; ks < nks; ++ks) {
+            bf16x8 a = bf16x8{};
+            if (c32 < 4) a = *reinterpret_cast<const bf16x8 *>(f.wo + c32 * kFusedW + ks * 16 + 8 * h);
+            const bf16x8 b = in[(pb * nks + ks) * 64 + lane];
+            y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, y, 0, 0, 0);
+        }
+        // rows 0..3 of the result (outputs) sit in registers 0..3 of lanes 0..31
+        const int64_t m = row0 + pb * 32 + c32;
+        if (h == 0 && m < f.M) {
+            for (int o = 0; o < 4; ++o) f.A[4 * m + o] = f.scale * (y[o] + f.bo[o]);
+        }
     }
 }
 
@@ -710,10 +754,10 @@ int launch_scatter_copol(hipStream_t s, const double *A, const int64_t *dst, int
     return SBR_OK;
 }
 
-// (the k loop of k_mlp_fused steps kPrefetch fragments at a time)
+// (k_mlp_fused unrolls the first layer for 8 or 16 k steps)
 bool fused_ok(int n_ff, int width, int depth)
 {
-    return width == kFusedW && 2 * n_ff <= kFusedW && (2 * n_ff / 16) % kPrefetch == 0 && depth <= kMaxLayers - 1;
+    return width == kFusedW && (n_ff == 64 || n_ff == 128) && depth >= 1 && depth <= kMaxLayers - 1;
 }
 
 int launch_mlp_fused(hipStream_t s, const FusedArgs &f)
