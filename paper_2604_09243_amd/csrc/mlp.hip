@@ -24,6 +24,7 @@
 // and bias gradients, the loss) run in a fixed order: results are bitwise
 // reproducible.
 #include <cmath>
+#include <type_traits>
 
 #include "sbr_internal.hpp"
 
@@ -94,9 +95,12 @@ __device__ __forceinline__ void ff_pair(const double *xn, const float *Bq, uint1
 
 // ---------------------------------------------------------------- GEMM
 constexpr int kGemmThreads = 256;
-constexpr int kTileM = 64, kTileN = 128;
+constexpr int kTileM = 64, kTileN = 128, kGemmRing = 4;
 
-template <int EPI>
+// C = A B^T over k (both operands k-contiguous, bf16), 64 x 128 tiles, one
+// 32 x 64 piece per wave; NK > 0: exactly NK k steps per block (unrolled),
+// NK = 0: any multiple of 16.
+template <int EPI, int NK>
 __global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -110,34 +114,67 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
     const uint16_t *pb1 = g.B + static_cast<int64_t>(n0 + 32 + r) * g.ldb + kh + kb;
     float *fout = g.fout ? g.fout + blockIdx.z * g.split_stride : nullptr;
     f32x16 acc0 = {}, acc1 = {};
-    for (int k0 = 0; k0 < kc; k0 += 16) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(pa + k0);
-        const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0 + k0);
-        const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+    if constexpr (NK > 0) {
+        // NK k steps, unrolled, with the fragments of kGemmRing steps in flight
+        bf16x8 ra[kGemmRing], rb0[kGemmRing], rb1[kGemmRing];
+#pragma unroll
+        for (int u = 0; u < kGemmRing && u < NK; ++u) {
+            ra[u] = *reinterpret_cast<const bf16x8 *>(pa + 16 * u);
+            rb0[u] = *reinterpret_cast<const bf16x8 *>(pb0 + 16 * u);
+            rb1[u] = *reinterpret_cast<const bf16x8 *>(pb1 + 16 * u);
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int u = k % kGemmRing;
+            const bf16x8 a = ra[u], b0 = rb0[u], b1 = rb1[u];
+            if (k + kGemmRing < NK) {
+                ra[u] = *reinterpret_cast<const bf16x8 *>(pa + 16 * (k + kGemmRing));
+                rb0[u] = *reinterpret_cast<const bf16x8 *>(pb0 + 16 * (k + kGemmRing));
+                rb1[u] = *reinterpret_cast<const bf16x8 *>(pb1 + 16 * (k + kGemmRing));
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+        }
+    } else {
+        for (int k0 = 0; k0 < kc; k0 += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(pa + k0);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0 + k0);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+        }
     }
+    // register q holds row m0 + 8 (q / 4) + 4 (lane / 32) + q % 4 of column n:
+    // the four rows of a quad are consecutive, so the transposed bf16 copy is
+    // written as one 8-byte store per quad
     for (int c = 0; c < 2; ++c) {
         const f32x16 &acc = c ? acc1 : acc0;
         const int n = n0 + 32 * c + r;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int m = m0 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-            const float v = acc[q];
-            if (EPI == kEpiHidden) {
-                const float z = v + g.bias[n];
-                if (g.zout) g.zout[static_cast<int64_t>(m) * g.ldz + n] = z;
-                const uint16_t h = to_bf16(act_f(z, g.act));
-                g.hout[static_cast<int64_t>(m) * g.ldh + n] = h;
-                if (g.htout) g.htout[static_cast<int64_t>(n) * g.ldht + m] = h;
-            } else if (EPI == kEpiDz) {
-                const float dz = v * act_d(g.zin[static_cast<int64_t>(m) * g.ldzi + n], g.act);
-                g.fout[static_cast<int64_t>(m) * g.ldf + n] = dz;
-                const uint16_t h = to_bf16(dz);
-                g.hout[static_cast<int64_t>(m) * g.ldh + n] = h;
-                g.htout[static_cast<int64_t>(n) * g.ldht + m] = h;
-            } else {
-                fout[static_cast<int64_t>(m) * g.ldf + n] = v;
+        for (int j = 0; j < 4; ++j) {
+            const int mq = m0 + 8 * j + 4 * (lane >> 5);
+            uint16_t hq[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = mq + i;
+                const float v = acc[4 * j + i];
+                if (EPI == kEpiHidden) {
+                    const float z = v + g.bias[n];
+                    if (g.zout) g.zout[static_cast<int64_t>(m) * g.ldz + n] = z;
+                    hq[i] = to_bf16(act_f(z, g.act));
+                    g.hout[static_cast<int64_t>(m) * g.ldh + n] = hq[i];
+                } else if (EPI == kEpiDz) {
+                    const float dz = v * act_d(g.zin[static_cast<int64_t>(m) * g.ldzi + n], g.act);
+                    g.fout[static_cast<int64_t>(m) * g.ldf + n] = dz;
+                    hq[i] = to_bf16(dz);
+                    g.hout[static_cast<int64_t>(m) * g.ldh + n] = hq[i];
+                } else {
+                    fout[static_cast<int64_t>(m) * g.ldf + n] = v;
+                }
+            }
+            if (EPI != kEpiF32 && g.htout) {
+                const uint2 w = make_uint2(hq[0] | static_cast<uint32_t>(hq[1]) << 16, hq[2] | static_cast<uint32_t>(hq[3]) << 16);
+                *reinterpret_cast<uint2 *>(g.htout + static_cast<int64_t>(n) * g.ldht + mq) = w;
             }
         }
     }
@@ -641,10 +678,22 @@ int launch_gemm(hipStream_t s, int epi, const GemmArgs &g)
         return fail(SBR_ERR_INVALID_ARG, "MLP product: shape not a multiple of the 64 x 128 x 16 tile");
     if (g.ksplit < 1 || (g.K / g.ksplit) % 16 || g.K % g.ksplit || (g.ksplit > 1 && epi != kEpiF32))
         return fail(SBR_ERR_INVALID_ARG, "MLP product: bad k split");
+    if (g.htout && (g.ldht % 4 || reinterpret_cast<uintptr_t>(g.htout) % 8))
+        return fail(SBR_ERR_INVALID_ARG, "MLP product: transposed output not 8-byte aligned");
     dim3 grid(g.M / kTileM, g.N / kTileN, g.ksplit);
-    if (epi == kEpiHidden) k_gemm<kEpiHidden><<<grid, kGemmThreads, 0, s>>>(g);
-    else if (epi == kEpiDz) k_gemm<kEpiDz><<<grid, kGemmThreads, 0, s>>>(g);
-    else k_gemm<kEpiF32><<<grid, kGemmThreads, 0, s>>>(g);
+    const int nk = g.K / g.ksplit / 16;
+    auto go = [&](auto epi_c) {
+        constexpr int E = decltype(epi_c)::value;
+        if (nk == 8)
+            k_gemm<E, 8><<<grid, kGemmThreads, 0, s>>>(g);
+        else if (nk == 16)
+            k_gemm<E, 16><<<grid, kGemmThreads, 0, s>>>(g);
+        else
+            k_gemm<E, 0><<<grid, kGemmThreads, 0, s>>>(g);
+    };
+    if (epi == kEpiHidden) go(std::integral_constant<int, kEpiHidden>{});
+    else if (epi == kEpiDz) go(std::integral_constant<int, kEpiDz>{});
+    else go(std::integral_constant<int, kEpiF32>{});
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
