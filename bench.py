@@ -318,7 +318,7 @@ def bench_surrogate(args):
     ds = C0 / 12e9 / 8
     train = (np.full(360, th0), np.arange(360.0), np.linspace(8e9, 12e9, 64))
     query = (np.full(3600, th0), np.arange(3600) * 0.1, np.linspace(8e9, 12e9, 512))
-    kw = dict(net_kw=dict(ff_sigma=2.0, seed=1), train_kw=dict(epochs=100, batch=4096, lr=3e-3, lr_min=3e-5, seed=0),
+    kw = dict(net_kw=dict(ff_sigma=2.0, seed=1), train_kw=dict(epochs=40, batch=4096, lr=4e-3, lr_min=4e-5, seed=0),
               tile_angles=10, tile_freqs=32, tol_db=0.25, floor_db=40.0)
     for _ in range(args.warmup):
         pipeline.surrogate_fill(ctx, bvh, train, query, ds, bm, **kw)
@@ -354,7 +354,7 @@ def bench_surrogate(args):
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": "surrogate_%s_3600x512" % args.target, "train": "360 x 64", "query": "3600 x 512",
                    "tiles": "1 deg x 32 f", "probes": "1 direction x 2 f per tile", "tol_db": 0.25,
-                   "floor_db": 40.0, "audit_floor_db": 30.0, "epochs": 100, "batch": 4096},
+                   "floor_db": 40.0, "audit_floor_db": 30.0, "epochs": 40, "batch": 4096, "lr": 4e-3},
         "plain_points_per_s": n / tp, "plain_ms": 1e3 * tp, "gain": tp / ts,
         "fallback_tile_frac": float(fb.mean()), "stage_s": {k: v for k, v in info.items() if k.startswith("s_")},
         "fill_ms": {k: v for k, v in info["fill"].items() if k.startswith("ms_")},

@@ -107,8 +107,21 @@ __device__ __forceinline__ void sincos_pi(double x, double &so, double &co)
     pc = __builtin_fma(pc, z, -0.5);
     const double cs = __builtin_fma(z, pc, 1.0);
     const int qi = static_cast<int>(q) & 3;  // two's complement: -1 -> 3, -2 -> 2
-    so = qi == 0 ? sn : qi == 1 ? cs : qi == 2 ? -sn : -cs;
-    co = qi == 0 ? cs : qi == 1 ? -sn : qi == 2 ? -cs : sn;
+    // quadrant qi: (sin, cos) = (sn, cs), (cs, -sn), (-sn, -cs), (-cs, sn)
+    const bool odd = qi & 1;
+    const double a = odd ? cs : sn, b = odd ? sn : cs;
+    so = (qi & 2) ? -a : a;
+    co = ((qi + 1) & 2) ? -b : b;
+}
+
+// sin and cos of the phase ph (any size; float64): ph reduced by the nearest
+// multiple of 2 pi (2 pi as a two-term sum), then sincos_pi.
+__device__ __forceinline__ void phase_sincos(double ph, double &so, double &co)
+{
+    const double two_pi_hi = 6.283185307179586;       // fl64(2 pi)
+    const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - fl64(2 pi)
+    const double nturn = rint(ph * 0.15915494309189535);
+    sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), so, co);
 }
 
 // round(x * 2^32) as a 64-bit integer for |x| < 2^19, via the float64
@@ -158,35 +171,36 @@ __device__ __forceinline__ void weights(const PoP &p, const double *B, const flo
     }
 }
 
-// Block u of the launch: records [c * kPoRecsPerBlock, (c + 1) * kPoRecsPerBlock)
-// of angle a, where a is the angle whose blocks hold u and c = u - unit_base.
-template <int kFT>  // frequencies per pass over a block's records
-__global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
+// Angle of block u of a launch: the last angle whose first block is <= u.
+__device__ __forceinline__ int po_angle_of(const PoP &p, int64_t u)
 {
-    __shared__ long long red[kPoThreads / 64][kFT * 8];
-    const int64_t u = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int lo = 0, hi = p.n_angles;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (p.ang[mid].unit_base <= u) lo = mid;
         else hi = mid;
     }
-    const PoAngle &A = p.ang[lo];
-    const int64_t c = u - A.unit_base;
+    return lo;
+}
+
+// Frequencies [f_begin, f_end) of records [c * kPoRecsPerBlock, (c + 1) *
+// kPoRecsPerBlock) of angle A, kFT frequencies per pass over the records, in
+// a block of kNT threads of which the first 256 take records: each sums the
+// slots tid, tid + 256, ... (a fixed subset, in a fixed order) in float64;
+// the per-thread sums become fixed point before the exact integer reduction
+// over threads, waves and blocks.
+template <int kFT, int kNT>
+__device__ __forceinline__ void po_passes(const PoP &p, const PoAngle &A, int64_t c, int f_begin, int f_end,
+                                          long long (*red)[kFT * 8])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nf = A.n_f;
     const double *kf = p.kf + A.kf_off;
     long long *out = p.partial + (A.part_base + c * nf) * 8;
     const int64_t r0i = c * kPoRecsPerBlock;
-    const int64_t r1i = min(r0i + kPoRecsPerBlock, A.rec_cnt);
-    const double two_pi_hi = 6.283185307179586;       // fl64(2 pi)
-    const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - fl64(2 pi)
-    const double inv_two_pi = 0.15915494309189535;
+    const int64_t r1i = tid < kPoThreads ? min(r0i + kPoRecsPerBlock, A.rec_cnt) : r0i;
     const bool uniform = A.dk != 0.0;
-    for (int f0 = 0; f0 < nf; f0 += kFT) {
-        // each thread sums its records (a fixed subset, in a fixed order) in
-        // float64; the per-thread sums become fixed point before the exact
-        // integer reduction over threads, waves and blocks
+    for (int f0 = f_begin; f0 < f_end; f0 += kFT) {
         double acc[kFT][8];
         for (int ft = 0; ft < kFT; ++ft)
             for (int e = 0; e < 8; ++e) acc[ft][e] = 0.0;
@@ -198,29 +212,19 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
             double w[4];
             weights(p, A.basis, q0, q1, q2, w);
             double sd, cd, rs = 0.0, rc = 1.0;
-            {
-                const double ph = kf[f0] * D;
-                const double nturn = rint(ph * inv_two_pi);
-                sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), sd, cd);
-            }
-            if (uniform) {  // evenly spaced wavenumbers: each step turns the phasor by dk D
-                const double ph = A.dk * D;
-                const double nturn = rint(ph * inv_two_pi);
-                sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), rs, rc);
-            }
+            phase_sincos(kf[f0] * D, sd, cd);
+            if (uniform) phase_sincos(A.dk * D, rs, rc);  // evenly spaced: each step turns the phasor by dk D
 #pragma unroll
             for (int ft = 0; ft < kFT; ++ft) {
                 const int f = f0 + ft;
-                if (f >= nf) break;
+                if (f >= f_end) break;
                 if (ft > 0) {
                     if (uniform) {
                         const double s2 = __builtin_fma(sd, rc, cd * rs);
                         cd = __builtin_fma(cd, rc, -(sd * rs));
                         sd = s2;
                     } else {
-                        const double ph = kf[f] * D;
-                        const double nturn = rint(ph * inv_two_pi);
-                        sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), sd, cd);
+                        phase_sincos(kf[f] * D, sd, cd);
                     }
                 }
                 for (int k = 0; k < 4; ++k) {
@@ -237,13 +241,257 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
         __syncthreads();
         if (tid < kFT * 8) {
             const int ft = tid / 8, k = tid % 8;
-            if (f0 + ft < nf) {
+            if (f0 + ft < f_end) {
                 long long s = 0;
-                for (int x = 0; x < kPoThreads / 64; ++x) s += red[x][tid];
+                for (int x = 0; x < kNT / 64; ++x) s += red[x][tid];
                 out[(f0 + ft) * 8 + k] = s;
             }
         }
         __syncthreads();
+    }
+}
+
+// Block u of the launch: records [c * kPoRecsPerBlock, (c + 1) * kPoRecsPerBlock)
+// of angle a, where a is the angle whose blocks hold u and c = u - unit_base;
+// all frequencies of the angle, kFT per pass over the records.
+template <int kFT>  // frequencies per pass over a block's records
+__global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
+{
+    __shared__ long long red[kPoThreads / 64][kFT * 8];
+    const int64_t u = blockIdx.x;
+    const PoAngle &A = p.ang[po_angle_of(p, u)];
+    po_passes<kFT, kPoThreads>(p, A, u - A.unit_base, 0, A.n_f, red);
+}
+
+// Many frequencies: block (u, y) takes the records of unit u (as k_po) and
+// the frequencies [64 y, 64 y + 64) of its angle.  The records are staged in
+// LDS once per round of 512 (every field of a thread's two slots loaded in
+// one round trip), the valid ones packed in a fixed order (thread-major,
+// then the thread's slots in order), with what every frequency needs
+// computed once per record: the weights, D and, for evenly spaced
+// wavenumbers, the phasor exp(j k_fc D) at the chunk's first frequency and
+// the steps exp(j s dk D) for s = 1, F, 2F, 4F (F = kMfFT = 8, by repeated
+// squaring).  So the records leave HBM once per 64 frequencies, not once
+// per pass.  Thread t takes frequency group g = t mod G (F consecutive
+// frequencies; G = 1, 2, 4 or 8 groups as the chunk needs) and the packed
+// records t / G, t / G + 256 / G, ... of every round; its phasor starts at
+// exp(j k_fc D) turned by F g dk D (three complex products by a staged step
+// or by 1) and turns by dk D per frequency (where the spacing is uneven: one
+// sine and cosine per frequency).  Two blocks share a CU, so one stages
+// while the other sums.  A chunk of one frequency takes the k_po<1>
+// summation, so single-frequency angles give the same bits in either kernel.
+#ifndef SBR_PO_FT
+#define SBR_PO_FT 8  // frequencies per thread in k_po_mf
+#endif
+#ifndef SBR_PO_QUNROLL
+#define SBR_PO_QUNROLL 1  // packed records per iteration of the common-case loop
+#endif
+#ifndef SBR_PO_SUB
+#define SBR_PO_SUB 512  // records staged per round in k_po_mf
+#endif
+constexpr int kMfFT = SBR_PO_FT, kMfChunk = 8 * kMfFT, kMfSub = SBR_PO_SUB;
+constexpr int kMfLogFT = kMfFT == 2 ? 1 : kMfFT == 4 ? 2 : kMfFT == 8 ? 3 : 4;
+static_assert((1 << kMfLogFT) == kMfFT, "k_po_mf: frequencies per thread must be 2, 4, 8 or 16");
+
+__device__ __forceinline__ long long shfl_xor64(long long x, int off)
+{
+    const int lo = __shfl_xor(static_cast<int>(x), off, 64);
+    const int hi = __shfl_xor(static_cast<int>(x >> 32), off, 64);
+    return static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                  static_cast<unsigned>(lo));
+}
+
+__global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
+{
+    __shared__ double sw[4][kMfSub];    // weights
+    __shared__ double sD[kMfSub];       // path length
+    __shared__ double sph[10][kMfSub];  // (cos, sin) of k_fc D, dk D, F dk D, 2F dk D, 4F dk D (F = kMfFT)
+    __shared__ int scnt[kPoThreads / 64];
+    __shared__ long long red[kPoThreads / 64][kMfChunk * 8];
+    const int64_t u = blockIdx.x;
+    const PoAngle &A = p.ang[po_angle_of(p, u)];
+    const int nf = A.n_f;
+    const int fc = static_cast<int>(blockIdx.y) * kMfChunk;
+    if (fc >= nf) return;  // the whole block
+    const int nfc = min(kMfChunk, nf - fc);
+    const int64_t c = u - A.unit_base;
+    if (nfc == 1) {
+        po_passes<1, kPoThreads>(p, A, c, fc, fc + 1, reinterpret_cast<long long (*)[8]>(&red[0][0]));
+        return;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lg = nfc <= kMfFT ? 0 : nfc <= 2 * kMfFT ? 1 : nfc <= 4 * kMfFT ? 2 : 3;
+    const int G = 1 << lg, g = tid & (G - 1), rl = tid >> lg, RL = kPoThreads >> lg;
+    const int fs = fc + g * kMfFT;                       // this thread's first frequency
+    const int nft = max(0, min(kMfFT, fc + nfc - fs));  // and how many
+    const double *kf = p.kf + A.kf_off;
+    const bool uniform = A.dk != 0.0;
+    const int64_t r0i = c * kPoRecsPerBlock;
+    const int64_t r1i = min(r0i + kPoRecsPerBlock, A.rec_cnt);
+    double acc[kMfFT][8];
+#pragma unroll
+    for (int ft = 0; ft < kMfFT; ++ft)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[ft][e] = 0.0;
+    for (int64_t s0 = r0i; s0 < r1i; s0 += kMfSub) {
+        // stage: thread t holds slots s0 + t + 256 j, j = 0, 1
+        constexpr int kPer = kMfSub / kPoThreads;
+        int vmask = 0, cnt = 0;
+        // all fields of the thread's slots are loaded at once (one round trip;
+        // empty slots cost their bytes)
+        float4 q0[kPer], q1[kPer], q2[kPer];
+        double Dj[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int64_t e = s0 + tid + j * kPoThreads;
+            const int64_t ec = A.rec_base + (e < r1i ? e : r0i);  // a valid address for every lane
+            q0[j] = p.rec.r0[ec];
+            q1[j] = p.rec.r1[ec];
+            q2[j] = p.rec.r2[ec];
+            Dj[j] = p.rec.D[ec];
+            if (e < r1i && ((__float_as_int(q2[j].w) >> 8) & SBR_REC_VALID)) {
+                vmask |= 1 << j;
+                ++cnt;
+            }
+        }
+        // exclusive scan of the counts over the block (thread order)
+        int inc = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += v;
+        }
+        if (lane == 63) scnt[wv] = inc;
+        __syncthreads();
+        int pos = inc - cnt, nvalid = 0;
+        for (int x = 0; x < kPoThreads / 64; ++x) {
+            if (x < wv) pos += scnt[x];
+            nvalid += scnt[x];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (!((vmask >> j) & 1)) continue;
+            const double D = Dj[j];
+            double w[4];
+            weights(p, A.basis, q0[j], q1[j], q2[j], w);
+            for (int k = 0; k < 4; ++k) sw[k][pos] = w[k];
+            sD[pos] = D;
+            if (uniform) {
+                double bs, bc, rs, rc;
+                phase_sincos(kf[fc] * D, bs, bc);
+                phase_sincos(A.dk * D, rs, rc);
+                sph[0][pos] = bc;
+                sph[1][pos] = bs;
+                sph[2][pos] = rc;
+                sph[3][pos] = rs;
+                // (rc + j rs)^F, ^2F, ^4F (F = kMfFT) by repeated squaring
+                for (int sq = 1; sq <= kMfLogFT + 2; ++sq) {
+                    const double c2 = __builtin_fma(rc, rc, -(rs * rs)), s2 = 2.0 * (rc * rs);
+                    rc = c2;
+                    rs = s2;
+                    if (sq >= kMfLogFT) {
+                        sph[4 + 2 * (sq - kMfLogFT)][pos] = rc;
+                        sph[5 + 2 * (sq - kMfLogFT)][pos] = rs;
+                    }
+                }
+            }
+            ++pos;
+        }
+        __syncthreads();
+        if (uniform && nft == kMfFT) {
+            // the common case, branch free: evenly spaced, a full group
+#pragma unroll SBR_PO_QUNROLL
+            for (int q = rl; q < nvalid; q += RL) {
+                const double w0 = sw[0][q], w1 = sw[1][q], w2 = sw[2][q], w3 = sw[3][q];
+                double cd = sph[0][q], sd = sph[1][q];
+                const double rc = sph[2][q], rs = sph[3][q];
+                // start at frequency fc + F g: turn by F g dk D (g < 8: the staged steps F, 2F, 4F)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    // by the step (tc, ts) or by 1 (exactly: 0 t + 1 and 0 t), without a branch
+                    const double on = static_cast<double>((g >> b) & 1);
+                    const double tc = __builtin_fma(on, sph[4 + 2 * b][q], 1.0 - on), ts = on * sph[5 + 2 * b][q];
+                    const double c2 = __builtin_fma(cd, tc, -(sd * ts));
+                    sd = __builtin_fma(cd, ts, sd * tc);
+                    cd = c2;
+                }
+#pragma unroll
+                for (int ft = 0; ft < kMfFT; ++ft) {
+                    if (ft > 0) {
+                        const double s2 = __builtin_fma(sd, rc, cd * rs);
+                        cd = __builtin_fma(cd, rc, -(sd * rs));
+                        sd = s2;
+                    }
+                    acc[ft][0] = __builtin_fma(w0, sd, acc[ft][0]);
+                    acc[ft][1] = __builtin_fma(w0, cd, acc[ft][1]);
+                    acc[ft][2] = __builtin_fma(w1, sd, acc[ft][2]);
+                    acc[ft][3] = __builtin_fma(w1, cd, acc[ft][3]);
+                    acc[ft][4] = __builtin_fma(w2, sd, acc[ft][4]);
+                    acc[ft][5] = __builtin_fma(w2, cd, acc[ft][5]);
+                    acc[ft][6] = __builtin_fma(w3, sd, acc[ft][6]);
+                    acc[ft][7] = __builtin_fma(w3, cd, acc[ft][7]);
+                }
+            }
+        } else if (nft > 0) {
+            for (int q = rl; q < nvalid; q += RL) {
+                const double w0 = sw[0][q], w1 = sw[1][q], w2 = sw[2][q], w3 = sw[3][q];
+                double sd, cd, rc = 1.0, rs = 0.0;
+                if (uniform) {
+                    cd = sph[0][q];
+                    sd = sph[1][q];
+                    rc = sph[2][q];
+                    rs = sph[3][q];
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const bool on = (g >> b) & 1;
+                        const double tc = on ? sph[4 + 2 * b][q] : 1.0, ts = on ? sph[5 + 2 * b][q] : 0.0;
+                        const double c2 = __builtin_fma(cd, tc, -(sd * ts));
+                        sd = __builtin_fma(cd, ts, sd * tc);
+                        cd = c2;
+                    }
+                } else {
+                    phase_sincos(kf[fs] * sD[q], sd, cd);
+                }
+#pragma unroll
+                for (int ft = 0; ft < kMfFT; ++ft) {
+                    if (ft >= nft) break;
+                    if (ft > 0) {
+                        if (uniform) {
+                            const double s2 = __builtin_fma(sd, rc, cd * rs);
+                            cd = __builtin_fma(cd, rc, -(sd * rs));
+                            sd = s2;
+                        } else {
+                            phase_sincos(kf[fs + ft] * sD[q], sd, cd);
+                        }
+                    }
+                    acc[ft][0] = __builtin_fma(w0, sd, acc[ft][0]);
+                    acc[ft][1] = __builtin_fma(w0, cd, acc[ft][1]);
+                    acc[ft][2] = __builtin_fma(w1, sd, acc[ft][2]);
+                    acc[ft][3] = __builtin_fma(w1, cd, acc[ft][3]);
+                    acc[ft][4] = __builtin_fma(w2, sd, acc[ft][4]);
+                    acc[ft][5] = __builtin_fma(w2, cd, acc[ft][5]);
+                    acc[ft][6] = __builtin_fma(w3, sd, acc[ft][6]);
+                    acc[ft][7] = __builtin_fma(w3, cd, acc[ft][7]);
+                }
+            }
+        }
+        __syncthreads();  // before the next round overwrites the stage
+    }
+    // fixed point, summed over the lanes of a group (lane = g mod G) of each
+    // wave, then over the waves
+#pragma unroll
+    for (int ft = 0; ft < kMfFT; ++ft)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            long long v = fix32(acc[ft][k]);
+            for (int off = 32; off >= G; off >>= 1) v += shfl_xor64(v, off);
+            if (lane < G) red[wv][(lane * kMfFT + ft) * 8 + k] = v;
+        }
+    __syncthreads();
+    long long *out = p.partial + (A.part_base + c * nf + fc) * 8;
+    for (int i = tid; i < nfc * 8; i += kPoThreads) {
+        long long v = 0;
+        for (int x = 0; x < kPoThreads / 64; ++x) v += red[x][i];
+        out[i] = v;
     }
 }
 
@@ -321,8 +569,12 @@ int launch_po(hipStream_t s, const PoArgs &a)
     if (a.n_units > 2147483647LL) return fail(SBR_ERR_OVERFLOW, "PO launch: too many blocks");
     // one frequency: the 1-wide pass keeps the register count (and the
     // occupancy that hides the record loads) of a single accumulator set
-    if (a.max_nf == 1) k_po<1><<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
-    else k_po<4><<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
+    if (a.max_nf == 1) {
+        k_po<1><<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
+    } else {
+        const dim3 grid(static_cast<unsigned>(a.n_units), static_cast<unsigned>((a.max_nf + kMfChunk - 1) / kMfChunk));
+        k_po_mf<<<grid, kPoThreads, 0, s>>>(make_pop(a));
+    }
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

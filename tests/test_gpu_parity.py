@@ -278,22 +278,47 @@ def test_sweep_multifrequency_equals_single(torch, ctx):
     V, T = si.trihedral(1.0, 8)
     bvh = ctx.build_bvh(V, T)
     th, ph = np.array([60.0, 50.0]), np.array([30.0, 10.0])
-    # unevenly spaced: every frequency is evaluated directly -> bit for bit
-    fs = np.array([8e9, 9.3e9, 10e9, 8.5e9, 9.9e9])
-    A, _, _ = ctx.rcs_sweep(bvh, th, ph, fs, 5, ds=C0 / 10e9 / 10)
-    singles = []
-    for i, f in enumerate(fs):
-        A1, _, _ = ctx.rcs_sweep(bvh, th, ph, [f], 5, ds=C0 / 10e9 / 10)
-        singles.append(A1.cpu().numpy()[:, 0])
-        assert np.array_equal(A.cpu().numpy()[:, i], singles[-1])
-    # evenly spaced: the phasor recurrence over frequencies agrees to rounding
-    fe = np.linspace(8e9, 10e9, 9)
-    A, _, _ = ctx.rcs_sweep(bvh, th, ph, fe, 5, ds=C0 / 10e9 / 10)
-    A = A.cpu().numpy()
-    for i, f in enumerate(fe):
-        A1, _, _ = ctx.rcs_sweep(bvh, th, ph, [f], 5, ds=C0 / 10e9 / 10)
-        A1 = A1.cpu().numpy()[:, 0]
-        assert np.max(np.abs(A[:, i] - A1)) <= 1e-12 * np.max(np.abs(A1))
+    # the many-frequency kernel sums the records in another fixed order than
+    # the one-frequency kernel (packed per round; for evenly spaced
+    # frequencies with the phasor recurrence), so the two agree to rounding:
+    # each is within ~1e-12 of the largest amplitude of a float64 direct sum
+    # over the same records (test_po_many_frequencies_on_gpu_records)
+    for fs in (np.array([8e9, 9.3e9, 10e9, 8.5e9, 9.9e9]), np.linspace(8e9, 10e9, 9)):
+        A, _, _ = ctx.rcs_sweep(bvh, th, ph, fs, 5, ds=C0 / 10e9 / 10)
+        A = A.cpu().numpy()
+        for i, f in enumerate(fs):
+            A1, _, _ = ctx.rcs_sweep(bvh, th, ph, [f], 5, ds=C0 / 10e9 / 10)
+            A1 = A1.cpu().numpy()[:, 0]
+            assert np.max(np.abs(A[:, i] - A1)) <= 1e-11 * np.max(np.abs(A1))
+        A2, _, _ = ctx.rcs_sweep(bvh, th, ph, fs, 5, ds=C0 / 10e9 / 10)
+        assert np.array_equal(A, A2.cpu().numpy())  # each bitwise reproducible
+
+
+@pytest.mark.parametrize("fs", [np.array([8e9, 9.3e9, 10e9, 8.5e9, 9.9e9]), np.linspace(8e9, 10e9, 9),
+                                np.linspace(8e9, 10e9, 65), np.sort(np.random.default_rng(5).uniform(8e9, 10e9, 100))],
+                         ids=["uneven5", "even9", "even65", "uneven100"])
+def test_po_many_frequencies_on_gpu_records(torch, ctx, orc, fs):
+    """sbr_po_integrate over many frequencies (frequency chunks of 64, the
+    last one of 1 for 65) against the oracle's float64 PO sum (Eq. po_sum)
+    over the very records the GPU traced."""
+    say("case po many frequencies", len(fs))
+    V, T = si.trihedral(1.0, 8)
+    m = orc.Mesh(V, T)
+    bvh = ctx.build_bvh(V, T)
+    ds = C0 / 10e9 / 10
+    k, tv, pv = orc.frame(50.0, 10.0)
+    o, d, *_ = orc.gen_rays(m.bbox, 50.0, 10.0, ds)
+    raw, g = _gpu_trace(torch, ctx, bvh, o, d, pv, tv, 5, k)
+    rec = dict(nb=g["n_bounce"].astype(np.int32), tri_first=g["tri_first"].astype(np.int32),
+               tri_last=g["tri_last"].astype(np.int32), flags=g["flags"].astype(np.int32), D=g["D"],
+               d_last=np.ascontiguousarray(g["d_last"], np.float32), eH_last=g["eH_last"].astype(np.float64),
+               eV_last=g["eV_last"].astype(np.float64))
+    for mode in (0, 1):
+        A_o = orc.po(m, rec, mode, k, tv, pv, ds * ds, fs)
+        A_g = ctx.po_integrate(bvh, raw, mode, k, tv, pv, ds * ds, fs).cpu().numpy()
+        err = np.max(np.abs(A_g - A_o)) / np.max(np.abs(A_o))
+        say("mode", mode, "max error / max amplitude", err)
+        assert err <= 1e-11
 
 
 def test_sweep_errors(torch, ctx):

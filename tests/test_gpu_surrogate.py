@@ -100,7 +100,7 @@ def test_surrogate_beats_plain_sbr_on_band_limited_grid(torch, ctx, tri):
     th0, ds, bm = 54.74, C0 / 12e9 / 8, 5
     train = (np.full(360, th0), np.arange(360.0), np.linspace(8e9, 12e9, 64))
     query = (np.full(3600, th0), np.arange(3600) * 0.1, np.linspace(8e9, 12e9, 512))
-    kw = dict(net_kw=dict(ff_sigma=2.0, seed=1), train_kw=dict(epochs=100, batch=4096, lr=3e-3, lr_min=3e-5, seed=0),
+    kw = dict(net_kw=dict(ff_sigma=2.0, seed=1), train_kw=dict(epochs=40, batch=4096, lr=4e-3, lr_min=4e-5, seed=0),
               tile_angles=10, tile_freqs=32, tol_db=0.25, floor_db=40.0)
     pipeline.surrogate_fill(ctx, tri, train, query, ds, bm, **kw)      # warm-up (allocations, captures)
     ctx.rcs_sweep(tri, *query, bm, ds=ds, stats=False)
