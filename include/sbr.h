@@ -471,7 +471,11 @@ void sbr_mlp_destroy(sbr_mlp *mlp);
  * network; a tile falls back when, on its probes whose SBR co-polar sigma is
  * at least (largest probe sigma - floor_db), |sigma_net - sigma_sbr| exceeds
  * tol_db in either co-polar channel.  Fallback runs SBR for every point of
- * the failing tiles.  Every SBR call traces at spacing ds. */
+ * the failing tiles: per direction, runs of failing tiles separated by
+ * passing tiles share one trace when the PO of the passing tiles between
+ * them costs less than a trace (the cost ratio is measured on the probe
+ * sweep); the points of passing tiles keep the network's value.  Every SBR
+ * call traces at spacing ds. */
 typedef struct {
     uint32_t struct_size;
     int32_t mode;               /* SBR_MODE_* of every SBR call */
@@ -494,7 +498,7 @@ typedef struct {
 } sbr_fill_desc;
 
 typedef struct {
-    int64_t tiles, fallback_tiles, points, fallback_points, probe_points;
+    int64_t tiles, fallback_tiles, points, fallback_points, probe_points;  /* fallback_points: of failing tiles */
     double ms_predict, ms_probe, ms_check, ms_fallback, ms_total;
     int64_t sbr_rays;           /* rays traced by the probe and fallback SBR calls */
 } sbr_fill_stats;

@@ -659,7 +659,7 @@ __global__ void k_scatter_copol(const double *__restrict__ A, const int64_t *__r
                                 double *__restrict__ out)
 {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
+    if (r >= n || dst[r] < 0) return;  // dst < 0: a row computed but not wanted
     const double *q = A + 8 * r;
     double *o = out + 4 * dst[r];
     o[0] = q[0];

@@ -584,7 +584,7 @@ struct HostTimer {
 };
 
 int run_batch(sbr_ctx *ctx, const sbr_bvh *bvh, const std::vector<sbr_batch_item> &items, const double *freqs,
-              int64_t n_freqs, const sbr_fill_desc *d, double *A, int64_t *rays)
+              int64_t n_freqs, const sbr_fill_desc *d, double *A, int64_t *rays, sbr_stats *st = nullptr)
 {
     sbr_batch_desc bd{};
     bd.struct_size = sizeof(bd);
@@ -603,7 +603,7 @@ int run_batch(sbr_ctx *ctx, const sbr_bvh *bvh, const std::vector<sbr_batch_item
     sbr_batch_info bi;
     (void)sbr_batch_get_info(b, &bi);
     *rays += bi.rays;
-    rc = sbr_batch_run(b, A, nullptr, nullptr);
+    rc = sbr_batch_run(b, A, nullptr, st);
     sbr_batch_destroy(b);
     return rc;
 }
@@ -666,7 +666,8 @@ extern "C" int sbr_surrogate_fill(sbr_ctx *ctx, const sbr_bvh *bvh, sbr_mlp *M, 
         (rc = tmp.alloc(&derr, n_ta * n_tf)) || (rc = tmp.alloc(&dflag, n_ta * n_tf)))
         return rc;
     SBR_HIP(hipMemcpyAsync(ppts, hpp.data(), 8 * hpp.size(), hipMemcpyHostToDevice, s));
-    if ((rc = run_batch(ctx, bvh, items, d->probe_freq, np_dir, d, A_sbr, &rays)) ||
+    sbr_stats pst{};
+    if ((rc = run_batch(ctx, bvh, items, d->probe_freq, np_dir, d, A_sbr, &rays, &pst)) ||
         (rc = sbr_mlp_predict(M, ppts, n_probe, A_sur)))
         return rc;
     SBR_HIP(hipEventRecord(tm.ev[2], s));
@@ -678,30 +679,47 @@ extern "C" int sbr_surrogate_fill(sbr_ctx *ctx, const sbr_bvh *bvh, sbr_mlp *M, 
     SBR_HIP(hipMemcpyAsync(herr.data(), derr, 8 * herr.size(), hipMemcpyDeviceToHost, s));
     SBR_HIP(hipEventRecord(tm.ev[3], s));
     SBR_HIP(hipStreamSynchronize(s));
-    // 4. SBR on every point of the failing tiles
+    // 4. SBR on every point of the failing tiles.  A direction is traced once
+    // per item, so the failing runs of tiles of a direction share one item
+    // when the PO of the passing tiles between them costs less than another
+    // trace: the probe sweep measured what one trace costs in frequencies of
+    // PO (its trace time over its PO time per frequency).  Points of passing
+    // tiles inside such an item are computed and dropped (dst = -1).
+    const double trace_freqs = pst.ms_po > 0.0 ? static_cast<double>(np_dir) * pst.ms_trace / pst.ms_po : 0.0;
     std::vector<sbr_batch_item> fb;
     std::vector<int64_t> dst;
-    int64_t n_fail = 0;
+    int64_t n_fail = 0, n_fb_points = 0;
     for (int64_t t = 0; t < n_ta; ++t) {
         for (int tf = 0; tf < n_tf; ++tf) n_fail += hflag[t * n_tf + tf];
+        // runs [b, e) of failing tiles of this tile row, merged across cheap gaps
+        std::vector<std::pair<int, int>> runs;
+        for (int tf = 0; tf < n_tf;) {
+            if (!hflag[t * n_tf + tf]) {
+                ++tf;
+                continue;
+            }
+            int e = tf;
+            while (e < n_tf && hflag[t * n_tf + e]) ++e;
+            if (!runs.empty() && static_cast<double>((tf - runs.back().second) * d->tile_freqs) <= trace_freqs)
+                runs.back().second = e;
+            else
+                runs.emplace_back(tf, e);
+            tf = e;
+        }
         for (int64_t a = t * d->tile_angles; a < std::min(na, (t + 1) * d->tile_angles); ++a) {
-            int tf = 0;
-            while (tf < n_tf) {
-                if (!hflag[t * n_tf + tf]) {
-                    ++tf;
-                    continue;
-                }
-                int e = tf;
-                while (e < n_tf && hflag[t * n_tf + e]) ++e;
-                int f0 = tf * d->tile_freqs;
-                const int f1 = std::min(nf, e * d->tile_freqs);
+            for (const auto &r : runs) {
+                int f0 = r.first * d->tile_freqs;
+                const int f1 = std::min(nf, r.second * d->tile_freqs);
                 while (f0 < f1) {
                     const int cnt = std::min(4096, f1 - f0);
                     fb.push_back(sbr_batch_item{0, cnt, f0, d->theta_deg[a], d->phi_deg[a], d->ds});
-                    for (int f = f0; f < f0 + cnt; ++f) dst.push_back(a * nf + f);
+                    for (int f = f0; f < f0 + cnt; ++f) {
+                        const bool fails = hflag[t * n_tf + f / d->tile_freqs] != 0;
+                        dst.push_back(fails ? a * nf + f : -1);
+                        n_fb_points += fails;
+                    }
                     f0 += cnt;
                 }
-                tf = e;
             }
         }
     }
@@ -723,7 +741,7 @@ extern "C" int sbr_surrogate_fill(sbr_ctx *ctx, const sbr_bvh *bvh, sbr_mlp *M, 
         stats->tiles = n_ta * n_tf;
         stats->fallback_tiles = n_fail;
         stats->points = na * nf;
-        stats->fallback_points = static_cast<int64_t>(dst.size());
+        stats->fallback_points = n_fb_points;
         stats->probe_points = n_probe;
         float t01 = 0, t12 = 0, t23 = 0, t34 = 0;
         SBR_HIP(hipEventElapsedTime(&t01, tm.ev[0], tm.ev[1]));
