@@ -169,20 +169,94 @@ struct Stack {
     }
 };
 
+// Node and triangle records read through the scalar unit when every active
+// lane of the wave wants the same one (coherent rays mostly do): the scalar
+// loads bypass the vector memory pipeline, whose address unit otherwise
+// limits the traversal.  Reads only.
+typedef float sf4 __attribute__((ext_vector_type(4)));
+typedef int si4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) sf4 *ScalarF4;
+typedef const __attribute__((address_space(4))) si4 *ScalarI4;
+
+__device__ __forceinline__ BNode node_scalar(const BNode *nodes, int i)
+{
+    const ScalarF4 q = (ScalarF4)(nodes + i);
+    const sf4 a = q[0], b = q[1], c = q[2];
+    const si4 ch = ((ScalarI4)(nodes + i))[3];
+    BNode n;
+    n.a = make_float4(a.x, a.y, a.z, a.w);
+    n.b = make_float4(b.x, b.y, b.z, b.w);
+    n.c = make_float4(c.x, c.y, c.z, c.w);
+    n.ch = make_int4(ch.x, ch.y, ch.z, ch.w);
+    return n;
+}
+
+struct ScalarTriLoader {
+    const BTri *tris;
+    __device__ __forceinline__ BTri operator[](int i) const
+    {
+        const ScalarF4 q = (ScalarF4)(tris + i);
+        const sf4 a = q[0], b = q[1], c = q[2];
+        BTri t;
+        t.p0 = make_float4(a.x, a.y, a.z, a.w);
+        t.p1 = make_float4(b.x, b.y, b.z, b.w);
+        t.p2 = make_float4(c.x, c.y, c.z, c.w);
+        return t;
+    }
+};
+
+__device__ __forceinline__ bool wave_uniform(int v, int &v0)
+{
+    v0 = __builtin_amdgcn_readfirstlane(v);
+    return __ballot(v != v0) == 0;
+}
+
 // The triangles [first, first + cnt) of a leaf, cnt <= 4, each 48-byte
 // record loaded one test ahead.
-__device__ __forceinline__ void test_leaf(const Params &p, int first, int cnt, const Ray &r, Best &b)
+template <typename TriPtr>
+__device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, const Ray &r, Best &b)
 {
     SBR_COUNT(b.leaves += 1; b.tris += cnt);
-    const BTri t0 = p.tris[first];
+    const BTri t0 = tris[first];
     BTri t1, t2, t3;
-    if (cnt > 1) t1 = p.tris[first + 1];
+    if (cnt > 1) t1 = tris[first + 1];
     test_tri(t0, first, r, b);
-    if (cnt > 2) t2 = p.tris[first + 2];
+    if (cnt > 2) t2 = tris[first + 2];
     if (cnt > 1) test_tri(t1, first + 1, r, b);
-    if (cnt > 3) t3 = p.tris[first + 3];
+    if (cnt > 3) t3 = tris[first + 3];
     if (cnt > 2) test_tri(t2, first + 2, r, b);
     if (cnt > 3) test_tri(t3, first + 3, r, b);
+}
+
+// Leaf `code` (first triangle << 3 | count - 1).
+__device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &r, Best &b)
+{
+    int c0;
+    if (wave_uniform(code, c0))
+        test_leaf_from(ScalarTriLoader{p.tris}, c0 >> 3, (c0 & 7) + 1, r, b);
+    else
+        test_leaf_from(p.tris, code >> 3, (code & 7) + 1, r, b);
+}
+
+// Entry and exit distances of the ray (inverse direction i, origin term o)
+// through both child boxes of node n, the exit clamped to tlim.
+__device__ __forceinline__ void node_boxes(const BNode &n, float ix, float iy, float iz, float ox, float oy, float oz,
+                                           float tlim, float &t0, float &u0, float &t1, float &u1, int &cx, int &cy)
+{
+    // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
+    const float ax0 = __builtin_fmaf(n.a.x, ix, -ox), ax1 = __builtin_fmaf(n.a.w, ix, -ox);
+    const float ay0 = __builtin_fmaf(n.a.y, iy, -oy), ay1 = __builtin_fmaf(n.b.x, iy, -oy);
+    const float az0 = __builtin_fmaf(n.a.z, iz, -oz), az1 = __builtin_fmaf(n.b.y, iz, -oz);
+    t0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+    u0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tlim));
+    // child 1: lo = (b.z, b.w, c.x), hi = (c.y, c.z, c.w)
+    const float bx0 = __builtin_fmaf(n.b.z, ix, -ox), bx1 = __builtin_fmaf(n.c.y, ix, -ox);
+    const float by0 = __builtin_fmaf(n.b.w, iy, -oy), by1 = __builtin_fmaf(n.c.z, iy, -oy);
+    const float bz0 = __builtin_fmaf(n.c.x, iz, -oz), bz1 = __builtin_fmaf(n.c.w, iz, -oz);
+    t1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+    u1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tlim));
+    cx = n.ch.x;
+    cy = n.ch.y;
 }
 
 // The scene a ray belongs to: its root node in the (possibly multi-scene)
@@ -220,34 +294,27 @@ __device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const Sc
         // phase 1: descend through internal nodes until a leaf (or nothing) is next
         while (cur >= 0) {
             SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
-            const BNode n = p.nodes[cur];
             const float tlim = __builtin_fmaf(b.t, 1.000001f, sc.slack);
-            // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
-            const float ax0 = __builtin_fmaf(n.a.x, ix, -ox), ax1 = __builtin_fmaf(n.a.w, ix, -ox);
-            const float ay0 = __builtin_fmaf(n.a.y, iy, -oy), ay1 = __builtin_fmaf(n.b.x, iy, -oy);
-            const float az0 = __builtin_fmaf(n.a.z, iz, -oz), az1 = __builtin_fmaf(n.b.y, iz, -oz);
-            const float t0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-            const float u0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tlim));
-            // child 1: lo = (b.z, b.w, c.x), hi = (c.y, c.z, c.w)
-            const float bx0 = __builtin_fmaf(n.b.z, ix, -ox), bx1 = __builtin_fmaf(n.c.y, ix, -ox);
-            const float by0 = __builtin_fmaf(n.b.w, iy, -oy), by1 = __builtin_fmaf(n.c.z, iy, -oy);
-            const float bz0 = __builtin_fmaf(n.c.x, iz, -oz), bz1 = __builtin_fmaf(n.c.w, iz, -oz);
-            const float t1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-            const float u1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tlim));
+            float t0, u0, t1, u1;
+            int cx, cy, c0;
+            if (wave_uniform(cur, c0))
+                node_boxes(node_scalar(p.nodes, c0), ix, iy, iz, ox, oy, oz, tlim, t0, u0, t1, u1, cx, cy);
+            else
+                node_boxes(p.nodes[cur], ix, iy, iz, ox, oy, oz, tlim, t0, u0, t1, u1, cx, cy);
             const bool h0 = t0 <= u0, h1 = t1 <= u1;
             if (h0 && h1) {
-                int nr = n.ch.x, fr = n.ch.y;
+                int nr = cx, fr = cy;
                 if (t1 < t0) {
-                    nr = n.ch.y;
-                    fr = n.ch.x;
+                    nr = cy;
+                    fr = cx;
                 }
                 st.push(sp, fr);
                 ++sp;
                 cur = nr;
             } else if (h0) {
-                cur = n.ch.x;
+                cur = cx;
             } else if (h1) {
-                cur = n.ch.y;
+                cur = cy;
             } else if (sp > 0) {
                 --sp;
                 cur = st.pop(sp);
@@ -258,8 +325,7 @@ __device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const Sc
         if (cur == kEmpty) break;
         // phase 2: the triangles of leaf `cur`
         SBR_COUNT(if (wave_leader()) b.wleaf += 1);
-        const int code = ~cur;
-        test_leaf(p, code >> 3, (code & 7) + 1, r, b);
+        test_leaf(p, ~cur, r, b);
         if (sp > 0) {
             --sp;
             cur = st.pop(sp);
