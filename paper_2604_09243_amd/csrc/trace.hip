@@ -558,6 +558,18 @@ __device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Be
     }
 }
 
+// The sweep record of ray r from its last hit (triangle tri_last, bookkeeping
+// L, record flags fl), written once when the ray ends.
+__device__ __forceinline__ void sink_record(const Params &p, const Ray &r, int tri_last, const Last &L, int fl)
+{
+    const int N = r.meta & 127;
+    const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
+    p.rec.r0[e] = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(tri_last));
+    p.rec.r1[e] = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
+    p.rec.r2[e] = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (fl << 8)));
+    p.rec.D[e] = L.D;
+}
+
 // A ray whose first query missed: an empty record.
 __device__ __forceinline__ void sink_miss(const Params &p, const Ray &r)
 {
@@ -667,6 +679,10 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
     bool src_done = false;
     bool has = false;
     Ray r;
+    // the last hit of the lane's ray: a sweep record is written once, when the
+    // ray ends (caller rays are written at every hit)
+    Last L;
+    int tri_last = -1;
 
     for (;;) {
         // ---- refill: idle lanes, ranked by a ballot prefix count, take the next positions
@@ -704,23 +720,27 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
         if (has) {
             if (b.slot >= 0) {
                 const K3 kv = kvec(p, r);
-                Last L;
                 const bool cont = bounce(p, r, b, kv, sc.eps, L);
+                tri_last = b.id;
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
-                sink_hit(p, r, b, L);
+                if (p.user_sink) sink_hit(p, r, b, L);  // caller rays: every hit (the path of ids)
                 if (!cont) {
+                    int fl = L.flags;
                     if (p.flags & SBR_OPT_DROP_TRAPPED) {
                         const Best b2 = closest(p, r, st, sc);
                         atomicAdd(&bs.queries, 1u);
-                        if (b2.slot >= 0) {
-                            flag_trapped(p, r);
+                        if (b2.slot >= 0) {  // trapped: flagged and dropped from the PO sum
+                            if (p.user_sink) flag_trapped(p, r);
+                            fl = (fl | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
                             atomicAdd(&bs.trapped, 1u);
                         }
                     }
+                    if (!p.user_sink) sink_record(p, r, tri_last, L, fl);
                     has = false;
                 }
             } else {
                 if ((r.meta & 127) == 0) sink_miss(p, r);
+                else if (!p.user_sink) sink_record(p, r, tri_last, L, L.flags);
                 has = false;
             }
         }
