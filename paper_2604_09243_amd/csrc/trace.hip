@@ -40,12 +40,20 @@ namespace sbr {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kStackLds = 32;     // LDS stack entries per lane
+#ifndef SBR_TRACE_STACK
+#define SBR_TRACE_STACK 28
+#endif
+constexpr int kStackLds = SBR_TRACE_STACK;  // LDS stack entries per lane
 constexpr int kStackSpillLds = 16;  // LDS part of the stack when deeper trees spill to global memory
 constexpr int kTileRays = 64;
+// Five waves per SIMD: the LDS stack (28 entries x 256 lanes = 28 KB per
+// block) lets five blocks share a CU, and the register allocator is held to
+// 96 VGPRs (a few cold spills) so that all five fit; measured 10 % faster
+// than four waves at 105 VGPRs.
 #ifndef SBR_TRACE_WAVES_PER_SIMD
-#define SBR_TRACE_WAVES_PER_SIMD 1  // occupancy floor handed to the register allocator
+#define SBR_TRACE_WAVES_PER_SIMD 5  // occupancy floor handed to the register allocator
 #endif
+#define SBR_TRACE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SBR_TRACE_WAVES_PER_SIMD)))
 // Build with -DSBR_TRACE_COUNTERS to count traversal work into stat[2..7]:
 // lane node visits, lane leaf visits, lane triangle tests, and wave-level
 // trips of the internal-node loop, of the leaf step and of the bounce loop.
@@ -259,6 +267,16 @@ __device__ __forceinline__ void node_boxes(const BNode &n, float ix, float iy, f
     cy = n.ch.y;
 }
 
+// Whether rays come from and go to the caller (sbr_trace) rather than an
+// angle grid (sweeps): U = 1 or 0 when the launch fixes it at compile time,
+// U < 0 to read it from the launch parameters.
+template <int U>
+__device__ __forceinline__ bool user_rays(const Params &p)
+{
+    if constexpr (U >= 0) return U != 0;
+    else return p.user_sink != 0;
+}
+
 // The scene a ray belongs to: its root node in the (possibly multi-scene)
 // node array, its surface offset and its box padding.
 struct SceneRef {
@@ -266,9 +284,10 @@ struct SceneRef {
     float eps, slack;
 };
 
+template <int U = -1>
 __device__ __forceinline__ SceneRef scene_of(const Params &p, const Ray &r)
 {
-    if (p.user_sink) return SceneRef{0, p.eps, p.slack};
+    if (user_rays<U>(p)) return SceneRef{0, p.eps, p.slack};
     const AnglePlan &pl = p.plans[r.meta >> 8];
     return SceneRef{pl.root, pl.eps, pl.slack};
 }
@@ -532,10 +551,11 @@ __device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, c
     return N < p.bmax;
 }
 
+template <int U = -1>
 __device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Best &b, const Last &L)
 {
     const int N = r.meta & 127;
-    if (p.user_sink) {
+    if (user_rays<U>(p)) {
         const sbr_hits &h = p.hits;
         const int64_t e = r.id;
         if (h.n_bounce) h.n_bounce[e] = N;
@@ -571,9 +591,10 @@ __device__ __forceinline__ void sink_record(const Params &p, const Ray &r, int t
 }
 
 // A ray whose first query missed: an empty record.
+template <int U = -1>
 __device__ __forceinline__ void sink_miss(const Params &p, const Ray &r)
 {
-    if (p.user_sink) {
+    if (user_rays<U>(p)) {
         const sbr_hits &h = p.hits;
         const int64_t e = r.id;
         if (h.n_bounce) h.n_bounce[e] = 0;
@@ -594,10 +615,11 @@ __device__ __forceinline__ void sink_miss(const Params &p, const Ray &r)
     }
 }
 
+template <int U = -1>
 __device__ __forceinline__ void flag_trapped(const Params &p, const Ray &r)
 {
     const int N = r.meta & 127;
-    if (p.user_sink) {
+    if (user_rays<U>(p)) {
         if (p.hits.flags) p.hits.flags[r.id] = (p.hits.flags[r.id] | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
     } else {
         const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
@@ -608,9 +630,10 @@ __device__ __forceinline__ void flag_trapped(const Params &p, const Ray &r)
     }
 }
 
+template <int U = -1>
 __device__ __forceinline__ K3 kvec(const Params &p, const Ray &r)
 {
-    if (p.user_sink) return K3{p.kx, p.ky, p.kz};
+    if (user_rays<U>(p)) return K3{p.kx, p.ky, p.kz};
     return plan_k(p.plans[r.meta >> 8]);
 }
 
@@ -661,8 +684,9 @@ __device__ __forceinline__ void init_stats(BlockStats &bs)
 // STREAM schedule
 // ---------------------------------------------------------------------------
 template <int SRC, bool SPILL>  // SRC: 0 = angle grid, 1 = caller rays
-__global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Params p)
+__global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_stream(Params p)
 {
+    constexpr int kUser = SRC == 1;  // caller rays in, hit arrays out (else an angle grid and sweep records)
     __shared__ int lds_stack[(SPILL ? kStackSpillLds : kStackLds) * kBlock];
     __shared__ BlockStats bs;
     init_stats(bs);
@@ -713,34 +737,34 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
         Best b;
         b.slot = -1;
         SceneRef sc{0, 0.f, 0.f};
-        if (has) sc = scene_of(p, r);
+        if (has) sc = scene_of<kUser>(p, r);
         if (has) b = closest(p, r, st, sc);
         if (has) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (has) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         if (has) {
             if (b.slot >= 0) {
-                const K3 kv = kvec(p, r);
+                const K3 kv = kvec<kUser>(p, r);
                 const bool cont = bounce(p, r, b, kv, sc.eps, L);
                 tri_last = b.id;
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
-                if (p.user_sink) sink_hit(p, r, b, L);  // caller rays: every hit (the path of ids)
+                if (kUser) sink_hit<kUser>(p, r, b, L);  // caller rays: every hit (the path of ids)
                 if (!cont) {
                     int fl = L.flags;
                     if (p.flags & SBR_OPT_DROP_TRAPPED) {
                         const Best b2 = closest(p, r, st, sc);
                         atomicAdd(&bs.queries, 1u);
                         if (b2.slot >= 0) {  // trapped: flagged and dropped from the PO sum
-                            if (p.user_sink) flag_trapped(p, r);
+                            if (kUser) flag_trapped<kUser>(p, r);
                             fl = (fl | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
                             atomicAdd(&bs.trapped, 1u);
                         }
                     }
-                    if (!p.user_sink) sink_record(p, r, tri_last, L, fl);
+                    if (!kUser) sink_record(p, r, tri_last, L, fl);
                     has = false;
                 }
             } else {
-                if ((r.meta & 127) == 0) sink_miss(p, r);
-                else if (!p.user_sink) sink_record(p, r, tri_last, L, L.flags);
+                if ((r.meta & 127) == 0) sink_miss<kUser>(p, r);
+                else if (!kUser) sink_record(p, r, tri_last, L, L.flags);
                 has = false;
             }
         }
@@ -752,7 +776,7 @@ __global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_stream(Par
 // WAVEFRONT schedule (one launch per bounce, queue between launches)
 // ---------------------------------------------------------------------------
 template <int SRC, bool SPILL>  // SRC: 0 = angle grid, 1 = caller rays, 2 = queue
-__global__ __launch_bounds__(kBlock, SBR_TRACE_WAVES_PER_SIMD) void k_wave(Params p)
+__global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
 {
     __shared__ int lds_stack[(SPILL ? kStackSpillLds : kStackLds) * kBlock];
     __shared__ BlockStats bs;
