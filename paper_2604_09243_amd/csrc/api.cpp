@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "sbr_internal.hpp"
@@ -21,6 +23,92 @@ int fail(int status, const std::string &msg)
 {
     g_err = msg;
     return status;
+}
+
+// ---------------------------------------------------------------- BVH blocks
+namespace {
+struct BlockCache {
+    std::mutex m;
+    std::map<int, std::multimap<size_t, void *>> free;  // device -> (size class, block)
+    size_t held = 0;
+};
+BlockCache &block_cache()
+{
+    static BlockCache *c = new BlockCache();  // lives to the end of the process
+    return *c;
+}
+constexpr size_t kBlockCacheMax = size_t(1) << 30;
+size_t size_class(size_t bytes)
+{
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+}  // namespace
+
+int device_block_get(int device, size_t bytes, void **p, size_t *cap)
+{
+    const size_t c = size_class(bytes);
+    *cap = c;
+    {
+        BlockCache &bc = block_cache();
+        std::lock_guard<std::mutex> g(bc.m);
+        auto &fl = bc.free[device];
+        auto it = fl.find(c);
+        if (it != fl.end()) {
+            *p = it->second;
+            fl.erase(it);
+            bc.held -= c;
+            return SBR_OK;
+        }
+    }
+    if (hipMalloc(p, c) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(SBR_ERR_OOM, "device allocation of " + std::to_string(c) + " bytes failed");
+    }
+    return SBR_OK;
+}
+
+void device_block_put(int device, void *p, size_t cap)
+{
+    if (!p) return;
+    BlockCache &bc = block_cache();
+    std::lock_guard<std::mutex> g(bc.m);
+    if (bc.held + cap <= kBlockCacheMax) {
+        bc.free[device].emplace(cap, p);
+        bc.held += cap;
+    } else {
+        (void)hipFree(p);
+    }
+}
+
+int bvh_alloc(sbr_bvh *bvh, void **p, size_t bytes)
+{
+    size_t c = 0;
+    const int rc = device_block_get(bvh->device, bytes, p, &c);
+    if (rc) return rc;
+    bvh->blocks.emplace_back(*p, c);
+    bvh->device_bytes += static_cast<int64_t>(c);
+    return SBR_OK;
+}
+
+int upload_async(sbr_ctx *ctx, const std::vector<Upload> &ups)
+{
+    size_t total = 0;
+    for (const auto &u : ups) total += (u.bytes + 255) & ~size_t(255);
+    if (total == 0) return SBR_OK;
+    SBR_HIP(hipStreamSynchronize(ctx->stream));  // the staging buffer may still feed an earlier copy
+    void *pin = nullptr;
+    int rc = ctx->ws->get_pinned(total, &pin);
+    if (rc) return rc;
+    char *q = static_cast<char *>(pin);
+    for (const auto &u : ups) {
+        std::memcpy(q, u.src, u.bytes);
+        SBR_HIP(hipMemcpyAsync(u.dst, q, u.bytes, hipMemcpyHostToDevice, ctx->stream));
+        q += (u.bytes + 255) & ~size_t(255);
+    }
+    return SBR_OK;
 }
 
 // ---------------------------------------------------------------- workspace
@@ -393,10 +481,10 @@ extern "C" void sbr_free_bvh(sbr_bvh *bvh)
 {
     if (!bvh) return;
     (void)hipSetDevice(bvh->device);
-    if (bvh->nodes) (void)hipFree(bvh->nodes);
-    if (bvh->tris) (void)hipFree(bvh->tris);
-    if (bvh->nrm_slot) (void)hipFree(bvh->nrm_slot);
-    if (bvh->nrm_id) (void)hipFree(bvh->nrm_id);
+    if (!bvh->blocks.empty()) {
+        (void)hipDeviceSynchronize();  // no kernel may still read the arrays when their blocks are handed on
+        for (const auto &b : bvh->blocks) device_block_put(bvh->device, b.first, b.second);
+    }
     delete bvh;
 }
 

@@ -364,14 +364,7 @@ extern "C" int sbr_pack_scenes(sbr_ctx *ctx, const sbr_bvh *const *bvhs, int n_b
     sbr_bvh *set = new (std::nothrow) sbr_bvh();
     if (!set) return fail(SBR_ERR_OOM, "sbr_pack_scenes: out of host memory");
     set->device = ctx->device;
-    auto dalloc = [&](void **p, size_t bytes) -> int {
-        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(SBR_ERR_OOM, "sbr_pack_scenes: device allocation failed");
-        }
-        set->device_bytes += static_cast<int64_t>(std::max<size_t>(bytes, 256));
-        return SBR_OK;
-    };
+    auto dalloc = [&](void **p, size_t bytes) -> int { return bvh_alloc(set, p, bytes); };
     int rc;
     if ((rc = dalloc(reinterpret_cast<void **>(&set->nodes), sizeof(BNode) * tn)) ||
         (rc = dalloc(reinterpret_cast<void **>(&set->tris), sizeof(BTri) * tl)) ||

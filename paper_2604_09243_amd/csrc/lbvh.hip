@@ -348,27 +348,27 @@ __global__ void k_single(int n, const float *__restrict__ lbox, BNode *__restric
     out[0] = nd;
 }
 
-template <class T>
-int dalloc(T **p, size_t n, int64_t *acc = nullptr)
-{
-    const size_t bytes = sizeof(T) * (n ? n : 1);
-    if (hipMalloc(reinterpret_cast<void **>(p), bytes) != hipSuccess)
-        return fail(SBR_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    if (acc) *acc += static_cast<int64_t>(bytes);
-    return SBR_OK;
-}
-
+// Scratch arrays of one build, from the device block cache; handed back when
+// the build returns (after the device is idle: error paths return early).
 struct Temp {
-    std::vector<void *> ptrs;
+    int device = 0;
+    std::vector<std::pair<void *, size_t>> blocks;
     ~Temp()
     {
-        for (void *p : ptrs) (void)hipFree(p);
+        if (blocks.empty()) return;
+        (void)hipDeviceSynchronize();
+        for (const auto &b : blocks) device_block_put(device, b.first, b.second);
     }
     template <class T>
     int alloc(T **p, size_t n)
     {
-        int rc = dalloc(p, n);
-        if (rc == SBR_OK) ptrs.push_back(*p);
+        size_t cap = 0;
+        void *q = nullptr;
+        const int rc = device_block_get(device, sizeof(T) * (n ? n : 1), &q, &cap);
+        if (rc == SBR_OK) {
+            *p = static_cast<T *>(q);
+            blocks.emplace_back(q, cap);
+        }
         return rc;
     }
 };
@@ -384,12 +384,13 @@ int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
     const int64_t nt = bvh->n_tris;
     const int n = static_cast<int>(pm.live.size());
     Temp tmp;
+    tmp.device = ctx->device;
     int rc;
     // normals by input id (float4) for the PO stage
     {
         std::vector<float4> nid(nt);
         for (int64_t j = 0; j < nt; ++j) nid[j] = make_float4(pm.n[3 * j], pm.n[3 * j + 1], pm.n[3 * j + 2], 0.f);
-        if ((rc = dalloc(&bvh->nrm_id, nt, &bvh->device_bytes))) return rc;
+        if ((rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nrm_id), sizeof(float4) * (nt ? nt : 1)))) return rc;
         SBR_HIP(hipMemcpy(bvh->nrm_id, nid.data(), sizeof(float4) * nt, hipMemcpyHostToDevice));
     }
     bvh->n_live = n;
@@ -455,8 +456,9 @@ int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
     // 3-5. hierarchy, leaves, refit, preorder relayout
     const int n_int = std::max(1, n - 1);
     bvh->n_nodes = n_int;
-    if ((rc = dalloc(&bvh->nodes, n_int, &bvh->device_bytes)) || (rc = dalloc(&bvh->tris, n, &bvh->device_bytes)) ||
-        (rc = dalloc(&bvh->nrm_slot, n, &bvh->device_bytes)))
+    if ((rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nodes), sizeof(BNode) * n_int)) ||
+        (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->tris), sizeof(BTri) * n)) ||
+        (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nrm_slot), sizeof(float4) * n)))
         return rc;
     float *lbox;
     if ((rc = tmp.alloc(&lbox, 6 * static_cast<size_t>(n)))) return rc;

@@ -304,42 +304,32 @@ int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
     if (leaf_max < 1 || leaf_max > 4) return fail(SBR_ERR_INVALID_ARG, "leaf size must be in [1, 4]");
     const int64_t nt = bvh->n_tris;
     const int n = static_cast<int>(pm.live.size());
-    auto dalloc = [&](void **p, size_t bytes) -> int {
-        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(SBR_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        }
-        bvh->device_bytes += static_cast<int64_t>(std::max<size_t>(bytes, 256));
-        return SBR_OK;
-    };
     int rc;
-    {
-        std::vector<float4> nid(nt);
-        for (int64_t j = 0; j < nt; ++j) nid[j] = make_float4(pm.n[3 * j], pm.n[3 * j + 1], pm.n[3 * j + 2], 0.f);
-        if ((rc = dalloc(reinterpret_cast<void **>(&bvh->nrm_id), sizeof(float4) * nt))) return rc;
-        SBR_HIP(hipMemcpy(bvh->nrm_id, nid.data(), sizeof(float4) * nt, hipMemcpyHostToDevice));
-    }
+    std::vector<float4> nid(nt);
+    for (int64_t j = 0; j < nt; ++j) nid[j] = make_float4(pm.n[3 * j], pm.n[3 * j + 1], pm.n[3 * j + 2], 0.f);
+    if ((rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nrm_id), sizeof(float4) * nt))) return rc;
     bvh->n_live = n;
     if (n == 0) {
         bvh->n_nodes = 0;
         bvh->depth = 0;
-        return SBR_OK;
+        return upload_async(ctx, {{bvh->nrm_id, nid.data(), sizeof(float4) * nt}});
     }
     std::vector<BNode> hn;
     std::vector<BTri> ht;
     std::vector<float4> hs;
     int depth = 0;
     if ((rc = sah_layout(pm, leaf_max, hn, ht, hs, depth)) || (rc = validate_layout(hn, n, leaf_max, depth))) return rc;
-    if ((rc = dalloc(reinterpret_cast<void **>(&bvh->nodes), sizeof(BNode) * hn.size())) ||
-        (rc = dalloc(reinterpret_cast<void **>(&bvh->tris), sizeof(BTri) * n)) ||
-        (rc = dalloc(reinterpret_cast<void **>(&bvh->nrm_slot), sizeof(float4) * n)))
+    if ((rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nodes), sizeof(BNode) * hn.size())) ||
+        (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->tris), sizeof(BTri) * n)) ||
+        (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nrm_slot), sizeof(float4) * n)))
         return rc;
-    SBR_HIP(hipMemcpy(bvh->nodes, hn.data(), sizeof(BNode) * hn.size(), hipMemcpyHostToDevice));
-    SBR_HIP(hipMemcpy(bvh->tris, ht.data(), sizeof(BTri) * n, hipMemcpyHostToDevice));
-    SBR_HIP(hipMemcpy(bvh->nrm_slot, hs.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
+    if ((rc = upload_async(ctx, {{bvh->nrm_id, nid.data(), sizeof(float4) * nt},
+                                 {bvh->nodes, hn.data(), sizeof(BNode) * hn.size()},
+                                 {bvh->tris, ht.data(), sizeof(BTri) * n},
+                                 {bvh->nrm_slot, hs.data(), sizeof(float4) * n}})))
+        return rc;
     bvh->n_nodes = static_cast<int64_t>(hn.size());
     bvh->depth = depth;
-    (void)ctx;
     return SBR_OK;
 }
 

@@ -127,6 +127,7 @@ struct sbr_bvh {
     std::vector<float> host_normals;  // [n_tris*3]
     int64_t device_bytes = 0;
     std::vector<sbr::SceneInfo> scenes;  // a multi-scene set only (empty for one mesh)
+    std::vector<std::pair<void *, size_t>> blocks;  // device blocks of the arrays above (block cache)
 };
 
 struct sbr_ctx {
@@ -171,6 +172,22 @@ int plan_angle(const double bbox[6], double theta_deg, double phi_deg, double ds
 
 // lbvh.hip: builds nodes/tris on the device from a prepared mesh.
 int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
+// api.cpp: device memory of a BVH's arrays.  Blocks come from a per-device
+// cache of blocks released by sbr_free_bvh (power-of-two size classes, at
+// most 1 GiB held), so that repeated builds do not pay hipMalloc/hipFree.
+int bvh_alloc(sbr_bvh *bvh, void **p, size_t bytes);
+// A block of at least `bytes` of the cache (capacity in *cap), and its return;
+// the caller guarantees that no work still uses a returned block.
+int device_block_get(int device, size_t bytes, void **p, size_t *cap);
+void device_block_put(int device, void *p, size_t cap);
+// Host -> device copies on the context stream through its pinned staging
+// buffer (the stream is synchronised before the buffer is refilled).
+struct Upload {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+int upload_async(sbr_ctx *ctx, const std::vector<Upload> &ups);
 // sah.cpp: the same node/triangle layout from a host binned-SAH build.
 int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
 
