@@ -53,7 +53,8 @@ def pmc_file(builder):
     return os.path.join(ROOT, "profiles", "trace_trihedral_%s_pmc.json" % builder)
 
 
-BUILDER_SOURCE = {"lbvh": "lbvh.hip", "sah": "sah.cpp"}
+BUILDER_SOURCE = {"lbvh": "lbvh.hip", "sah": "sah.cpp", "ploc": "lbvh.hip"}
+BUILDER_ID = {"lbvh": 0, "sah": 1, "ploc": 2}
 
 
 def work_per_query(b):
@@ -135,9 +136,9 @@ def main():
     ap.add_argument("--target", choices=("trihedral", "aircraft"), default="trihedral",
                     help="surrogate: band-limited trihedral or the procedural aircraft")
     ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch parameters first")
-    ap.add_argument("--builder", choices=("lbvh", "sah"), default="sah",
+    ap.add_argument("--builder", choices=("lbvh", "sah", "ploc"), default="sah",
                     help="BVH builder of each step: host binned SAH (default; fewer node and triangle tests "
-                         "per ray) or the GPU LBVH")
+                         "per ray), the GPU LBVH, or GPU PLOC clustering")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -174,7 +175,7 @@ def main():
     w = si.trihedral_case()
     ctx = Context(0)
 
-    builder = 1 if args.builder == "sah" else 0
+    builder = BUILDER_ID[args.builder]
 
     def step():
         bvh = ctx.build_bvh(w.V, w.T, builder=builder)
@@ -250,7 +251,7 @@ def bench_batch(args):
     t0 = time.perf_counter()
     w = si.batch_case()
     ctx = Context(0)
-    bvhs = [ctx.build_bvh(s.V, s.T, builder=1 if args.builder == "sah" else 0) for s in w.scenes]
+    bvhs = [ctx.build_bvh(s.V, s.T, builder=BUILDER_ID[args.builder]) for s in w.scenes]
     scn = ctx.pack_scenes(bvhs)
     for b in bvhs:
         b.free()

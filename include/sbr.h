@@ -112,7 +112,7 @@ void sbr_destroy(sbr_ctx *ctx);
 /* paper's host-built Algorithm 1 is replaced by a GPU LBVH)                 */
 /* ------------------------------------------------------------------------ */
 
-enum { SBR_BUILD_LBVH = 0, SBR_BUILD_SAH = 1 };
+enum { SBR_BUILD_LBVH = 0, SBR_BUILD_SAH = 1, SBR_BUILD_PLOC = 2 };
 
 typedef struct {
     uint32_t struct_size;
@@ -120,13 +120,16 @@ typedef struct {
     int32_t leaf_size; /* triangles per leaf, 1..4 (subtrees that small become leaves); 0 = 4 */
     int32_t builder;   /* SBR_BUILD_LBVH: Morton-code LBVH on the GPU (default);
                           SBR_BUILD_SAH: binned surface-area-heuristic build on the host (Algorithm 1
-                          with its SAH cost), slower to build, fewer node and triangle tests per ray */
+                          with its SAH cost), slower to build, fewer node and triangle tests per ray;
+                          SBR_BUILD_PLOC: on the GPU, agglomerative clustering of the LBVH's Morton
+                          order by merged surface area, leaves chosen by the SAH cost: a tree of
+                          the host SAH build's quality at GPU build speed */
 } sbr_bvh_opts;
 
 typedef struct {
     int64_t n_tris;       /* triangles given */
     int64_t n_live;       /* non-degenerate triangles (in the BVH) */
-    int64_t n_nodes;      /* internal nodes (n_live - 1, at least 1) */
+    int64_t n_nodes;      /* internal nodes of the layout (at most n_live - 1, at least 1) */
     int32_t depth;        /* longest root-to-leaf path (edges) */
     float eps;            /* surface offset (1e-5 of the bounding-box diagonal) */
     double bbox[6];       /* lo xyz, hi xyz of the referenced vertices */
@@ -148,6 +151,32 @@ int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, const int32
                   const sbr_bvh_opts *opts, sbr_bvh **out);
 
 int sbr_bvh_get_info(const sbr_bvh *bvh, sbr_bvh_info *out);
+
+/* Checks the layout of a one-mesh BVH (any builder) on the host: every node
+ * reachable once from the root in preorder, child boxes inside their
+ * parent's box, every leaf slot in exactly one leaf of at most leaf_size
+ * triangles, every triangle's corners inside the box its leaf is reached
+ * through, every input id in at most one slot, the depth bound kept.
+ * Copies the arrays to the host (synchronous).  Errors: INVALID_MESH with
+ * the first violation, UNSUPPORTED for a scene set, INVALID_ARG, HIP. */
+int sbr_bvh_validate(const sbr_bvh *bvh);
+
+/* Surface-area estimates of a layout's traversal work (the cost model of
+ * the SAH build, Sec. 4): for straight lines that meet the root box, a node
+ * is reached with probability area(node box) / area(root box).  Lets
+ * callers compare trees of different builders without tracing. */
+typedef struct {
+    double node_visits; /* expected internal-node visits (each tests two child boxes) */
+    double tri_tests;   /* expected triangle tests */
+    int64_t leaves;     /* leaf references */
+    int64_t leaf_tris;  /* triangles over all leaves */
+    int32_t max_depth;  /* internal nodes on the longest root-to-leaf path */
+    int32_t reserved;
+} sbr_bvh_quality;
+
+/* One-mesh BVH only (UNSUPPORTED for a scene set); copies the nodes to the
+ * host (synchronous).  Errors: INVALID_ARG, UNSUPPORTED, HIP. */
+int sbr_bvh_quality_of(const sbr_bvh *bvh, sbr_bvh_quality *out);
 
 /* Unit normals of all n_tris triangles in input order ([n_tris][3] float32,
  * host memory; zero for degenerate triangles). */

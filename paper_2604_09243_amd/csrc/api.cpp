@@ -415,7 +415,7 @@ extern "C" int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, 
         if (opts->leaf_size != 0) leaf = opts->leaf_size;
         builder = opts->builder;
     }
-    if (builder != SBR_BUILD_LBVH && builder != SBR_BUILD_SAH)
+    if (builder != SBR_BUILD_LBVH && builder != SBR_BUILD_SAH && builder != SBR_BUILD_PLOC)
         return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: unknown builder");
     if (leaf < 1 || leaf > 4) return fail(SBR_ERR_INVALID_ARG, "sbr_build_bvh: leaf_size must be in [0, 4]");
     if (mem != SBR_MEM_HOST && mem != SBR_MEM_DEVICE)
@@ -445,7 +445,9 @@ extern "C" int sbr_build_bvh(sbr_ctx *ctx, const float *verts, int64_t n_verts, 
     b->diag = pm.diag;
     std::memcpy(b->bbox, pm.bbox, sizeof(pm.bbox));
     b->leaf_size = leaf;
-    rc = builder == SBR_BUILD_SAH ? build_sah(ctx, pm, leaf, b) : build_lbvh(ctx, pm, leaf, b);
+    rc = builder == SBR_BUILD_SAH    ? build_sah(ctx, pm, leaf, b)
+         : builder == SBR_BUILD_PLOC ? build_ploc(ctx, pm, leaf, b)
+                                     : build_lbvh(ctx, pm, leaf, b);
     if (rc) {
         sbr_free_bvh(b);
         return rc;
@@ -467,6 +469,32 @@ extern "C" int sbr_bvh_get_info(const sbr_bvh *bvh, sbr_bvh_info *out)
     out->device_bytes = bvh->device_bytes;
     out->n_scenes = bvh->scenes.empty() ? 1 : static_cast<int32_t>(bvh->scenes.size());
     out->reserved = 0;
+    return SBR_OK;
+}
+
+extern "C" int sbr_bvh_validate(const sbr_bvh *bvh)
+{
+    if (!bvh) return fail(SBR_ERR_INVALID_ARG, "sbr_bvh_validate: NULL argument");
+    if (!bvh->scenes.empty()) return fail(SBR_ERR_UNSUPPORTED, "sbr_bvh_validate: a scene set is checked per scene");
+    if (bvh->n_live == 0) return bvh->n_nodes == 0 ? SBR_OK : fail(SBR_ERR_INVALID_MESH, "BVH layout: nodes without triangles");
+    SBR_HIP(hipSetDevice(bvh->device));
+    std::vector<BNode> hn(static_cast<size_t>(bvh->n_nodes));
+    std::vector<BTri> ht(static_cast<size_t>(bvh->n_live));
+    SBR_HIP(hipMemcpy(hn.data(), bvh->nodes, sizeof(BNode) * hn.size(), hipMemcpyDeviceToHost));
+    SBR_HIP(hipMemcpy(ht.data(), bvh->tris, sizeof(BTri) * ht.size(), hipMemcpyDeviceToHost));
+    return validate_layout(hn, static_cast<int>(bvh->n_live), bvh->leaf_size, bvh->depth, &ht, bvh->n_tris);
+}
+
+extern "C" int sbr_bvh_quality_of(const sbr_bvh *bvh, sbr_bvh_quality *out)
+{
+    if (!bvh || !out) return fail(SBR_ERR_INVALID_ARG, "sbr_bvh_quality_of: NULL argument");
+    if (!bvh->scenes.empty()) return fail(SBR_ERR_UNSUPPORTED, "sbr_bvh_quality_of: a scene set is measured per scene");
+    *out = sbr_bvh_quality{};
+    if (bvh->n_nodes == 0) return SBR_OK;
+    SBR_HIP(hipSetDevice(bvh->device));
+    std::vector<BNode> hn(static_cast<size_t>(bvh->n_nodes));
+    SBR_HIP(hipMemcpy(hn.data(), bvh->nodes, sizeof(BNode) * hn.size(), hipMemcpyDeviceToHost));
+    layout_quality(hn, *out);
     return SBR_OK;
 }
 

@@ -252,10 +252,13 @@ int sah_layout(const PreparedMesh &pm, int leaf_max, std::vector<BNode> &hn, std
     return SBR_OK;
 }
 
-int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth)
+int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth, const std::vector<BTri> *tris,
+                    int64_t n_ids)
 {
     // every reference in range, every leaf slot covered exactly once, child
-    // boxes inside their parent's box, the stack bound respected
+    // boxes inside their parent's box, the stack bound respected; with the
+    // triangles: every input id in exactly one slot and every triangle's
+    // corners inside the box its leaf is reached through
     const int nn = static_cast<int>(hn.size());
     std::vector<uint8_t> covered(n, 0);
     std::vector<std::pair<int, int>> st{{0, 0}};
@@ -265,38 +268,97 @@ int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth
     while (!st.empty()) {
         const int t = st.back().first, d = st.back().second;
         st.pop_back();
-        if (t < 0 || t >= nn || seen[t]) return fail(SBR_ERR_INVALID_MESH, "SAH build: bad node reference");
+        if (t < 0 || t >= nn || seen[t]) return fail(SBR_ERR_INVALID_MESH, "BVH layout: bad node reference");
         seen[t] = 1;
         maxd = std::max(maxd, d + 1);
         const int refs[2] = {hn[t].ch.x, hn[t].ch.y};
+        const float *pf = reinterpret_cast<const float *>(&hn[t]);
         for (int s = 0; s < (single ? 1 : 2); ++s) {
             const int c = refs[s];
             if (c >= 0) {
-                if (c <= t) return fail(SBR_ERR_INVALID_MESH, "SAH build: child before parent");
-                const float *pf = reinterpret_cast<const float *>(&hn[t]);
+                if (c <= t) return fail(SBR_ERR_INVALID_MESH, "BVH layout: child before parent");
                 const float *cf = reinterpret_cast<const float *>(&hn[c]);
                 for (int k = 0; k < 3; ++k)
                     for (int cs = 0; cs < 2; ++cs)
                         if (cf[6 * cs + k] < pf[6 * s + k] || cf[6 * cs + 3 + k] > pf[6 * s + 3 + k])
-                            return fail(SBR_ERR_INVALID_MESH, "SAH build: child box outside its parent");
+                            return fail(SBR_ERR_INVALID_MESH, "BVH layout: child box outside its parent");
                 st.push_back({c, d + 1});
             } else {
                 const int code = ~c, first = code >> 3, cnt = (code & 7) + 1;
                 if (cnt > leaf_max || first < 0 || first + cnt > n)
-                    return fail(SBR_ERR_INVALID_MESH, "SAH build: bad leaf");
+                    return fail(SBR_ERR_INVALID_MESH, "BVH layout: bad leaf");
                 for (int q = first; q < first + cnt; ++q) {
-                    if (covered[q]) return fail(SBR_ERR_INVALID_MESH, "SAH build: slot in two leaves");
+                    if (covered[q]) return fail(SBR_ERR_INVALID_MESH, "BVH layout: slot in two leaves");
                     covered[q] = 1;
+                    if (!tris) continue;
+                    const BTri &tr = (*tris)[q];
+                    const float v[3][3] = {{tr.p0.x, tr.p0.y, tr.p0.z},
+                                           {tr.p0.x + tr.p1.x, tr.p0.y + tr.p1.y, tr.p0.z + tr.p1.z},
+                                           {tr.p0.x + tr.p2.x, tr.p0.y + tr.p2.y, tr.p0.z + tr.p2.z}};
+                    for (int corner = 0; corner < 3; ++corner)
+                        for (int k = 0; k < 3; ++k)
+                            if (!(v[corner][k] >= pf[6 * s + k] && v[corner][k] <= pf[6 * s + 3 + k]))
+                                return fail(SBR_ERR_INVALID_MESH, "BVH layout: triangle outside its leaf box");
                 }
             }
         }
     }
     for (int q = 0; q < n; ++q)
-        if (!covered[q]) return fail(SBR_ERR_INVALID_MESH, "SAH build: slot in no leaf");
+        if (!covered[q]) return fail(SBR_ERR_INVALID_MESH, "BVH layout: slot in no leaf");
     for (int t = 0; t < nn; ++t)
-        if (!seen[t]) return fail(SBR_ERR_INVALID_MESH, "SAH build: unreachable node");
-    if (maxd > depth + 1) return fail(SBR_ERR_INVALID_MESH, "SAH build: depth bound");
+        if (!seen[t]) return fail(SBR_ERR_INVALID_MESH, "BVH layout: unreachable node");
+    if (maxd > depth + 1) return fail(SBR_ERR_INVALID_MESH, "BVH layout: depth bound");
+    if (tris) {
+        std::vector<uint8_t> used(n_ids, 0);
+        for (int q = 0; q < n; ++q) {
+            int32_t id;
+            std::memcpy(&id, &(*tris)[q].p0.w, 4);
+            if (id < 0 || id >= n_ids || used[id]) return fail(SBR_ERR_INVALID_MESH, "BVH layout: bad triangle id");
+            used[id] = 1;
+        }
+    }
     return SBR_OK;
+}
+
+void layout_quality(const std::vector<BNode> &hn, sbr_bvh_quality &q)
+{
+    // surface-area estimates for lines that meet the root box: a node is
+    // visited (both child boxes tested) with probability area(node)/area(root),
+    // a leaf's triangles are tested with probability area(leaf)/area(root)
+    auto area = [](const float *b) {
+        const double dx = double(b[3]) - b[0], dy = double(b[4]) - b[1], dz = double(b[5]) - b[2];
+        return dx * dy + dy * dz + dz * dx;
+    };
+    q = sbr_bvh_quality{};
+    if (hn.empty()) return;
+    const float *r = reinterpret_cast<const float *>(&hn[0]);
+    const float root[6] = {std::min(r[0], r[6]), std::min(r[1], r[7]), std::min(r[2], r[8]),
+                           std::max(r[3], r[9]), std::max(r[4], r[10]), std::max(r[5], r[11])};
+    const double a0 = std::max(area(root), 1e-300);
+    const bool single = hn.size() == 1 && hn[0].ch.x == hn[0].ch.y && hn[0].ch.x < 0;
+    std::vector<std::pair<int, int>> st{{0, 0}};
+    std::vector<double> anode(hn.size(), 0.0);
+    anode[0] = 1.0;
+    while (!st.empty()) {
+        const int t = st.back().first, d = st.back().second;
+        st.pop_back();
+        q.node_visits += anode[t];
+        q.max_depth = std::max(q.max_depth, d + 1);
+        const float *pf = reinterpret_cast<const float *>(&hn[t]);
+        const int refs[2] = {hn[t].ch.x, hn[t].ch.y};
+        for (int s = 0; s < (single ? 1 : 2); ++s) {
+            const double ac = area(pf + 6 * s) / a0;
+            if (refs[s] >= 0) {
+                anode[refs[s]] = ac;
+                st.push_back({refs[s], d + 1});
+            } else {
+                const int cnt = ((~refs[s]) & 7) + 1;
+                q.tri_tests += ac * cnt;
+                q.leaves += 1;
+                q.leaf_tris += cnt;
+            }
+        }
+    }
 }
 
 int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
@@ -318,7 +380,7 @@ int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
     std::vector<BTri> ht;
     std::vector<float4> hs;
     int depth = 0;
-    if ((rc = sah_layout(pm, leaf_max, hn, ht, hs, depth)) || (rc = validate_layout(hn, n, leaf_max, depth))) return rc;
+    if ((rc = sah_layout(pm, leaf_max, hn, ht, hs, depth)) || (rc = validate_layout(hn, n, leaf_max, depth, nullptr, 0))) return rc;
     if ((rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nodes), sizeof(BNode) * hn.size())) ||
         (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->tris), sizeof(BTri) * n)) ||
         (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nrm_slot), sizeof(float4) * n)))

@@ -170,8 +170,10 @@ int prepare_mesh(const float *V, int64_t nv, const int32_t *T, int64_t nt, Prepa
 int plan_angle(const double bbox[6], double theta_deg, double phi_deg, double ds, double eta,
                sbr_angle_plan &out);
 
-// lbvh.hip: builds nodes/tris on the device from a prepared mesh.
+// lbvh.hip: builds nodes/tris on the device from a prepared mesh (linear
+// BVH, or PLOC clustering over the same Morton order).
 int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
+int build_ploc(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
 // api.cpp: device memory of a BVH's arrays.  Blocks come from a per-device
 // cache of blocks released by sbr_free_bvh (power-of-two size classes, at
 // most 1 GiB held), so that repeated builds do not pay hipMalloc/hipFree.
@@ -190,6 +192,12 @@ struct Upload {
 int upload_async(sbr_ctx *ctx, const std::vector<Upload> &ups);
 // sah.cpp: the same node/triangle layout from a host binned-SAH build.
 int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
+// sah.cpp: structural check of a node layout over n leaf slots (and, given
+// the triangles in leaf order, of their ids in [0, n_ids) and leaf boxes).
+int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth, const std::vector<BTri> *tris,
+                    int64_t n_ids);
+// sah.cpp: surface-area estimates of the traversal work of a node layout.
+void layout_quality(const std::vector<BNode> &hn, sbr_bvh_quality &q);
 
 // trace.hip
 struct TraceArgs {

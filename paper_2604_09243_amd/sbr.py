@@ -20,7 +20,7 @@ OK, ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_SAMPLING, ERR_OOM, ERR_HIP, ERR_OVERF
 POL_H, POL_V = 0, 1
 MODE_VECTOR, MODE_PAPER = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-BUILD_LBVH, BUILD_SAH = 0, 1
+BUILD_LBVH, BUILD_SAH, BUILD_PLOC = 0, 1, 2
 REC_VALID, REC_TRAPPED, REC_BACK_LAST = 1, 2, 4
 OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRONT, OPT_NO_GRAPH = 1, 2, 4, 8, 16, 32
 MAX_BOUNCES = 64
@@ -37,6 +37,11 @@ class BvhInfo(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_live", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32),
                 ("eps", C.c_float), ("bbox", C.c_double * 6), ("device_bytes", C.c_int64), ("n_scenes", C.c_int32),
                 ("reserved", C.c_int32)]
+
+
+class BvhQuality(C.Structure):
+    _fields_ = [("node_visits", C.c_double), ("tri_tests", C.c_double), ("leaves", C.c_int64),
+                ("leaf_tris", C.c_int64), ("max_depth", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Rays(C.Structure):
@@ -176,6 +181,8 @@ SIGNATURES = {
     "sbr_destroy": (None, [_vp]),
     "sbr_build_bvh": (C.c_int, [_vp, _vp, C.c_int64, _vp, C.c_int64, C.POINTER(BvhOpts), C.POINTER(_vp)]),
     "sbr_bvh_get_info": (C.c_int, [_vp, C.POINTER(BvhInfo)]),
+    "sbr_bvh_validate": (C.c_int, [_vp]),
+    "sbr_bvh_quality_of": (C.c_int, [_vp, C.POINTER(BvhQuality)]),
     "sbr_bvh_normals": (C.c_int, [_vp, _vp]),
     "sbr_free_bvh": (None, [_vp]),
     "sbr_trace": (C.c_int, [_vp, _vp, C.POINTER(Rays), C.c_int64, C.c_int, C.POINTER(TraceOpts),
@@ -267,6 +274,18 @@ class BVH:
         self.bbox = np.array(info.bbox)
         self.device_bytes = info.device_bytes
         self.n_scenes = info.n_scenes
+
+    def quality(self):
+        """Surface-area estimates of the traversal work (sbr_bvh_quality_of):
+        dict of node_visits, tri_tests, leaves, leaf_tris, max_depth."""
+        q = BvhQuality()
+        _check(load_library().sbr_bvh_quality_of(self.handle, C.byref(q)))
+        return {k: getattr(q, k) for k, _ in BvhQuality._fields_ if k != "reserved"}
+
+    def validate(self):
+        """Structural check of the node and triangle layout (sbr_bvh_validate);
+        raises SbrError with the first violation."""
+        _check(load_library().sbr_bvh_validate(self.handle))
 
     def normals(self):
         out = np.zeros((self.n_tris, 3), np.float32)
@@ -468,7 +487,8 @@ class Context:
     def build_bvh(self, V, T, leaf_size=0, builder=BUILD_LBVH):
         """V: [n_v, 3] float32, T: [n_t, 3] int32 (numpy host arrays or
         torch device tensors); leaf_size 1..4 (0 = library default);
-        builder BUILD_LBVH (GPU) or BUILD_SAH (host binned SAH)."""
+        builder BUILD_LBVH (GPU), BUILD_SAH (host binned SAH) or BUILD_PLOC
+        (GPU clustering by surface area)."""
         torch = _torch()
         opts = BvhOpts(C.sizeof(BvhOpts), MEM_HOST, int(leaf_size), int(builder))
         if isinstance(V, torch.Tensor):

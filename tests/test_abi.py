@@ -39,7 +39,7 @@ def test_version_and_error_string(lib):
 
 
 # binding struct name -> header typedef
-STRUCTS = {"BvhOpts": "sbr_bvh_opts", "BvhInfo": "sbr_bvh_info", "Rays": "sbr_rays", "Hits": "sbr_hits",
+STRUCTS = {"BvhOpts": "sbr_bvh_opts", "BvhInfo": "sbr_bvh_info", "BvhQuality": "sbr_bvh_quality", "Rays": "sbr_rays", "Hits": "sbr_hits",
            "TraceOpts": "sbr_trace_opts", "Stats": "sbr_stats", "PoDesc": "sbr_po_desc", "Tune": "sbr_tune",
            "Sweep": "sbr_sweep", "BatchItem": "sbr_batch_item", "BatchDesc": "sbr_batch_desc",
            "BatchInfo": "sbr_batch_info", "AnglePlan": "sbr_angle_plan", "MlpDesc": "sbr_mlp_desc",

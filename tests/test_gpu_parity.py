@@ -102,7 +102,7 @@ def _grid_case(orc, V, T, th, ph, ds, bmax, edge=True, use_bvh=False, subset=Non
     return m, k, tv, pv, o, d, r
 
 
-@pytest.mark.parametrize("builder", [0, 1])
+@pytest.mark.parametrize("builder", [0, 1, 2])
 @pytest.mark.parametrize("case", ["sphere", "trihedral45", "trihedral12.5", "dihedral", "plate_oblique"])
 def test_trace_parity_grids(torch, ctx, orc, case, builder):
     say("case", case, "builder", builder)
@@ -120,6 +120,7 @@ def test_trace_parity_grids(torch, ctx, orc, case, builder):
         th, ph, ds, bmax = 33.0, 71.0, C0 / 10e9 / 10, 5
     m, k, tv, pv, o, d, r = _grid_case(orc, V, T, th, ph, ds, bmax)
     bvh = ctx.build_bvh(V, T, builder=builder)
+    bvh.validate()
     assert bvh.n_live == len(T) and 1 <= bvh.n_nodes <= len(T) - 1
     raw, g = _gpu_trace(torch, ctx, bvh, o, d, pv, tv, bmax, k)
     n_edge, n_mis = compare_trace(r, g, bmax)
@@ -128,7 +129,7 @@ def test_trace_parity_grids(torch, ctx, orc, case, builder):
     say(case, "rays", len(o), "edge-ambiguous", n_edge, "mismatching among them", n_mis)
 
 
-@pytest.mark.parametrize("builder", [0, 1])
+@pytest.mark.parametrize("builder", [0, 1, 2])
 def test_trace_parity_random_soup(torch, ctx, orc, builder):
     say("case random soup", builder)
     V, T = si.random_triangles(3000, seed=11, box=1.0, size=0.2)
@@ -138,13 +139,14 @@ def test_trace_parity_random_soup(torch, ctx, orc, builder):
     o = (o - 3.0 * k).astype(np.float32)
     r = orc.trace(m, o, k.astype(np.float32), pv, tv, k, 8, edge_diag=True, want_path=True)
     bvh = ctx.build_bvh(V, T, builder=builder)
+    bvh.validate()
     _, g = _gpu_trace(torch, ctx, bvh, o, k.astype(np.float32), pv, tv, 8, k)
     n_edge, n_mis = compare_trace(r, g, 8)
     assert (r["nb"] >= 3).sum() > 100
     say("soup edge", n_edge, "mismatch", n_mis)
 
 
-@pytest.mark.parametrize("builder", [0, 1])
+@pytest.mark.parametrize("builder", [0, 1, 2])
 def test_trace_parity_random_directions(torch, ctx, orc, builder):
     # every ray its own direction (incoherent), many bounces in a closed box of soup
     say("case random directions")
@@ -160,6 +162,7 @@ def test_trace_parity_random_directions(torch, ctx, orc, builder):
     # the oracle takes one polarisation pair; compare only geometry/ids here
     r = orc.trace(m, o, d, [1.0, 0, 0], [0, 1.0, 0], k, 12, edge_diag=True, want_path=True)
     bvh = ctx.build_bvh(V, T, builder=builder)
+    bvh.validate()
     _, g = _gpu_trace(torch, ctx, bvh, o, d, eh.astype(np.float32), ev.astype(np.float32), 12, k)
     edge = (r["flags"] & 8) != 0
     ok = ~edge
@@ -194,8 +197,9 @@ def test_trace_tiny_meshes(torch, ctx, orc):
         dd = np.array(d, np.float32)
         for flags, kw in ((0, {}), (1, dict(drop_trapped=True))):
             r = orc.trace(m, oo, dd, e, ev, k, 4, want_path=True, **kw)
-            for builder in (0, 1):
+            for builder in (0, 1, 2):
                 bvh = ctx.build_bvh(V, T, builder=builder)
+                bvh.validate()
                 _, g = _gpu_trace(torch, ctx, bvh, oo, dd, e, ev, 4, k, flags=flags)
                 compare_trace(r, g, 4, allow_edge=False)
 

@@ -44,7 +44,7 @@ def test_builds_into_reused_blocks_match_fresh_builds(torch, ctx):
     meshes = [si.trihedral(1.0, 8), si.trihedral(0.5, 16), si.trihedral(1.0, 4)]
     ref = {}
     for i, (V, T) in enumerate(meshes):
-        for builder in (0, 1):
+        for builder in (0, 1, 2):
             b = ctx.build_bvh(V, T, builder=builder)
             ref[(i, builder)] = sweep(ctx, b, th, ph)
             b.free()
@@ -53,7 +53,7 @@ def test_builds_into_reused_blocks_match_fresh_builds(torch, ctx):
     rng = np.random.default_rng(3)
     live = []
     for rep in range(12):
-        i, builder = int(rng.integers(len(meshes))), int(rng.integers(2))
+        i, builder = int(rng.integers(len(meshes))), int(rng.integers(3))
         V, T = meshes[i]
         b = ctx.build_bvh(V, T, builder=builder)
         assert np.array_equal(sweep(ctx, b, th, ph), ref[(i, builder)]), (rep, i, builder)

@@ -37,7 +37,7 @@ def test_tune_and_leaf_size_do_not_change_results(torch, ctx):
     V, T = si.trihedral(1.0, 16)
     th, ph = np.full(9, 54.74), np.linspace(0.0, 90.0, 9)
     ref = None
-    for leaf, builder in ((1, 0), (2, 0), (4, 0), (1, 1), (4, 1)):
+    for leaf, builder in ((1, 0), (2, 0), (4, 0), (1, 1), (4, 1), (1, 2), (4, 2)):
         bvh = ctx.build_bvh(V, T, leaf_size=leaf, builder=builder)
         for kw in ({}, dict(tile_w=4), dict(tile_w=32), dict(claim_tiles=1), dict(claim_tiles=16),
                    dict(refill_min=1), dict(refill_min=33), dict(blocks_per_cu=2)):
@@ -90,12 +90,13 @@ def test_aircraft_full_sweep_sampled_parity(torch, ctx, orc, aircraft):
     say("aircraft rel err", err.max(), "dB", np.abs(s_o - s_g)[sel].max())
 
 
-@pytest.mark.parametrize("builder", [0, 1])
+@pytest.mark.parametrize("builder", [0, 1, 2])
 def test_aircraft_trace_bit_exact_on_sampled_rays(torch, ctx, orc, aircraft, builder):
     w, bvh, m = aircraft
     say("case aircraft sampled rays, builder", builder)
-    if builder == 1:
-        bvh = ctx.build_bvh(w.V, w.T, builder=1)
+    if builder != 0:
+        bvh = ctx.build_bvh(w.V, w.T, builder=builder)
+        bvh.validate()
     rng = np.random.default_rng(3)
     for phi in (23.0, 180.0):
         k, tv, pv = orc.frame(90.0, phi)
