@@ -122,17 +122,20 @@ def cpu_baseline(w, A_gpu, seconds):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed steps first (the GPU clock settles over the first ~8 sweeps)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=("trihedral", "batch", "surrogate", "mlp"), default="trihedral",
+    ap.add_argument("--workload", choices=("trihedral", "batch", "surrogate", "mlp", "builders"),
+                    default="trihedral",
                     help="trihedral: the 181-angle sweep (default); batch: the 64-scene uneven batch, one graph "
                          "replay per step; surrogate: surrogate-plus-fallback fill vs plain SBR on a "
-                         "3600 x 512 grid; mlp: network inference and training throughput (secondary "
-                         "measurements)")
+                         "3600 x 512 grid; mlp: network inference and training throughput; builders: build "
+                         "time, tree quality and trace time of the three BVH builders on the trihedral and "
+                         "the aircraft (secondary measurements)")
     ap.add_argument("--target", choices=("trihedral", "aircraft"), default="trihedral",
                     help="surrogate: band-limited trihedral or the procedural aircraft")
     ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch parameters first")
@@ -170,6 +173,8 @@ def main():
         return bench_batch(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "builders":
+        return bench_builders(args)
     if args.workload == "mlp":
         return bench_mlp(args)
     w = si.trihedral_case()
@@ -407,6 +412,58 @@ def bench_mlp(args):
                      "frac": flops / dt / 2.5e15, "traffic": None},
         "train_ms_per_step": 1e3 * dtt / steps, "train_batch": 4096,
         "train_tflops": 3 * info["flops_per_point"] * 4096 * steps / dtt / 1e12,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_builders(args):
+    """Each builder on the trihedral (1,536 triangles, all 181 angles) and the
+    aircraft (1.5 M triangles, 8 of its 360 angles): build time (median of
+    the timed steps, build and free), the tree's surface-area estimates of
+    node visits and triangle tests per line (sbr_bvh_quality_of), and the
+    trace kernel's time.  value = closest-hit queries/s of the PLOC tree on
+    the aircraft sample."""
+    import torch
+    import sbr_inputs as si
+    from paper_2604_09243_amd import Context
+    ctx = Context(0)
+    rows = []
+    value = None
+    for w in (si.trihedral_case(), si.aircraft_case()):
+        sel = slice(None) if w.n_angles <= 181 else slice(None, None, 45)
+        th, ph = w.theta_deg[sel], w.phi_deg[sel]
+        for name, builder in (("sah", 1), ("lbvh", 0), ("ploc", 2)):
+            reps = args.steps if len(w.T) < 100_000 or builder != 1 else 1
+            times = []
+            for it in range(args.warmup + reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                bvh = ctx.build_bvh(w.V, w.T, builder=builder)
+                torch.cuda.synchronize()
+                if it >= args.warmup or reps == 1:
+                    times.append(time.perf_counter() - t0)
+                if it < args.warmup + reps - 1:
+                    bvh.free()
+            q = bvh.quality()
+            tr = []
+            for it in range(8):  # the GPU clock settles over the first sweeps; the minimum is reported
+                A, _, st = ctx.rcs_sweep(bvh, th, ph, w.freqs_hz, w.max_bounces,
+                                         samples_per_lambda=w.samples_per_lambda)
+                tr.append(st["ms_trace"])
+            bvh.free()
+            row = {"mesh": w.name, "triangles": len(w.T), "angles": len(th), "builder": name,
+                   "build_ms": 1e3 * float(np.median(times)), "nodes": bvh.n_nodes, "depth": bvh.depth,
+                   "node_visits": q["node_visits"], "tri_tests": q["tri_tests"], "trace_ms": min(tr),
+                   "queries": st["queries"]}
+            rows.append(row)
+            if name == "ploc" and len(w.T) > 100_000:
+                value = st["queries"] / (min(tr) * 1e-3)
+    out = {
+        "metric": "rays*bounces/s", "value": value, "unit": "rays*bounces/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (intersection) + f64 (path)",
+        "data": "synthetic (seeded procedural meshes)",
+        "config": {"workload": "bvh_builders_trihedral_aircraft"}, "builders": rows,
     }
     print(json.dumps(out), flush=True)
 

@@ -934,7 +934,8 @@ struct Front {
     bool done = false;
 };
 
-int build_front(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh, Temp &tmp, Front &f)
+int build_front(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, bool cubic, sbr_bvh *bvh, Temp &tmp,
+                Front &f)
 {
     if (leaf_max < 1 || leaf_max > kLeafMaxLimit) return fail(SBR_ERR_INVALID_ARG, "leaf size must be in [1, 4]");
     hipStream_t s = ctx->stream;
@@ -982,10 +983,14 @@ int build_front(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh
     if ((rc = tmp.alloc(&k0, n)) || (rc = tmp.alloc(&k1, n)) || (rc = tmp.alloc(&v0i, n)) ||
         (rc = tmp.alloc(&v1i, n)))
         return rc;
+    // per-axis scale (LBVH), or one scale for all axes (PLOC: cube cells keep
+    // the curve's neighbourhoods isotropic on elongated meshes)
     float lo[3], sc[3];
+    double ext_max = 0.0;
+    for (int a = 0; a < 3; ++a) ext_max = std::max(ext_max, pm.bbox[3 + a] - pm.bbox[a]);
     for (int a = 0; a < 3; ++a) {
         lo[a] = static_cast<float>(pm.bbox[a]);
-        const double ext = pm.bbox[3 + a] - pm.bbox[a];
+        const double ext = cubic ? ext_max : pm.bbox[3 + a] - pm.bbox[a];
         sc[a] = ext > 0.0 ? static_cast<float>(2097152.0 / ext) : 0.0f;
     }
     k_morton<<<blocks_for(n, 256), 256, 0, s>>>(f.v0, f.e1, f.e2, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], k0,
@@ -1049,7 +1054,7 @@ int build_lbvh(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
     Temp tmp;
     tmp.device = ctx->device;
     Front f;
-    int rc = build_front(ctx, pm, leaf_max, bvh, tmp, f);
+    int rc = build_front(ctx, pm, leaf_max, false, bvh, tmp, f);
     if (rc || f.done) return rc;
     const int n = f.n, n_int = n - 1;
 
@@ -1095,7 +1100,7 @@ int build_ploc(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
     Temp tmp;
     tmp.device = ctx->device;
     Front f;
-    int rc = build_front(ctx, pm, leaf_max, bvh, tmp, f);
+    int rc = build_front(ctx, pm, leaf_max, true, bvh, tmp, f);
     if (rc || f.done) return rc;
     const int n = f.n, n_int = n - 1;
     const int n_tiles = static_cast<int>(blocks_for(n, kPlocTile));
