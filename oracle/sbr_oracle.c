@@ -543,7 +543,13 @@ static int32_t closest_bvh(const orc_mesh *m, const float o[3], const float d[3]
             }
             continue;
         }
-        double lim = (best < INFINITY) ? (double)best * (1.0 + 1e-6) + slack : INFINITY;
+        /* A box is skipped only when it starts beyond the best hit by more than
+         * 2^-11 of its distance (plus the box padding): the float32
+         * intersection t of an ill-conditioned triangle (a sliver seen from
+         * far away) can fall short of the triangle's own padded box, by
+         * 7e-6 of t on the aircraft's symmetry seam, so a tighter margin
+         * would let the visiting order decide which of two hits is kept. */
+        double lim = (best < INFINITY) ? (double)best * (1.0 + 0x1p-11) + slack : INFINITY;
         double tl, tr;
         cnt->box_tests += 2;
         int hl = box_hit(&m->nodes[nd->left], od, dd, lim, &tl);

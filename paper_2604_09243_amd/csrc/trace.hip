@@ -44,7 +44,17 @@ constexpr int kBlock = 256;
 #define SBR_TRACE_STACK 28
 #endif
 constexpr int kStackLds = SBR_TRACE_STACK;  // LDS stack entries per lane
-constexpr int kStackSpillLds = 16;  // LDS part of the stack when deeper trees spill to global memory
+#ifndef SBR_TRACE_SPILL_LDS
+#define SBR_TRACE_SPILL_LDS 16
+#endif
+constexpr int kStackSpillLds = SBR_TRACE_SPILL_LDS;  // LDS part of the stack when deeper trees spill to global memory
+// A child box is skipped only when it starts beyond the best hit so far by
+// more than 2^-11 of that distance plus the box slack: the float32
+// intersection t of an ill-conditioned triangle (a sliver seen from far
+// away) can fall short of the triangle's own padded box (by 7e-6 of t on
+// the aircraft's symmetry seam), and a tighter margin would let the tree's
+// visiting order decide which of two hits is kept.  Costs under 1 % here.
+constexpr float kCullFactor = 1.0f + 0x1p-11f;
 constexpr int kTileRays = 64;
 // Five waves per SIMD: the LDS stack (28 entries x 256 lanes = 28 KB per
 // block) lets five blocks share a CU, and the register allocator is held to
@@ -313,7 +323,7 @@ __device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const Sc
         // phase 1: descend through internal nodes until a leaf (or nothing) is next
         while (cur >= 0) {
             SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
-            const float tlim = __builtin_fmaf(b.t, 1.000001f, sc.slack);
+            const float tlim = __builtin_fmaf(b.t, kCullFactor, sc.slack);
             float t0, u0, t1, u1;
             int cx, cy, c0;
             if (wave_uniform(cur, c0))

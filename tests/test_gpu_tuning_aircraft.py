@@ -117,3 +117,26 @@ def test_aircraft_trace_bit_exact_on_sampled_rays(torch, ctx, orc, aircraft, bui
         assert np.array_equal(r["x_last"][same], g["x_last"][same])
         assert np.array_equal(r["D"][same], g["D"][same])
         say("phi", phi, "hits", int(same.sum()), "max N", int(r["nb"].max()))
+
+
+@pytest.mark.parametrize("builder", [0, 1, 2])
+def test_aircraft_sliver_seam_rays_match_brute_force(torch, ctx, orc, aircraft, builder):
+    """Rays crossing the symmetry seam where two mirror-image slivers meet:
+    the float32 t of the nearer sliver lies in front of its own padded box,
+    and every tree must still keep it (the brute-force result)."""
+    w, bvh, m = aircraft
+    say("case aircraft seam rays, builder", builder)
+    if builder != 0:
+        bvh = ctx.build_bvh(w.V, w.T, builder=builder)
+    dev = torch.device("cuda", 0)
+    for phi, ray in ((135.0, 2869565), (225.0, 2871510)):
+        k, tv, pv = orc.frame(90.0, phi)
+        o, d, _, _ = orc.gen_rays(m.bbox, 90.0, phi, C0 / 10e9 / 8)
+        o = o[ray:ray + 1]
+        r = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True)
+        t = [torch.from_numpy(np.ascontiguousarray(np.broadcast_to(x, (1, 3)).astype(np.float32))).to(dev)
+             for x in (o, d, pv, tv)]
+        g = {kk: v.cpu().numpy() for kk, v in ctx.trace(bvh, *t, w.max_bounces, k, want_path=True).items()}
+        for a, b in (("nb", "n_bounce"), ("tri_first", "tri_first"), ("tri_last", "tri_last")):
+            assert np.array_equal(r[a], g[b]), (phi, a)
+        assert np.array_equal(r["tri_path"], g["tri_path"]) and np.array_equal(r["D"], g["D"])
