@@ -140,3 +140,18 @@ def test_aircraft_sliver_seam_rays_match_brute_force(torch, ctx, orc, aircraft, 
         for a, b in (("nb", "n_bounce"), ("tri_first", "tri_first"), ("tri_last", "tri_last")):
             assert np.array_equal(r[a], g[b]), (phi, a)
         assert np.array_equal(r["tri_path"], g["tri_path"]) and np.array_equal(r["D"], g["D"])
+
+
+def test_aircraft_sweeps_identical_across_builders(torch, ctx, orc, aircraft):
+    """8 of the 360 azimuths (77 M rays, including the two that cross the
+    symmetry seam at 135 and 225 degrees) give the same bits on the LBVH, the
+    host SAH and the PLOC tree."""
+    w, bvh, m = aircraft
+    say("case aircraft sweeps across builders")
+    th, ph = w.theta_deg[::45], w.phi_deg[::45]
+    ref = ctx.rcs_sweep(bvh, th, ph, w.freqs_hz, w.max_bounces, samples_per_lambda=w.samples_per_lambda)[0].cpu().numpy()
+    for builder in (1, 2):
+        b = ctx.build_bvh(w.V, w.T, builder=builder)
+        A = ctx.rcs_sweep(b, th, ph, w.freqs_hz, w.max_bounces, samples_per_lambda=w.samples_per_lambda)[0].cpu().numpy()
+        assert np.array_equal(A, ref), builder
+        b.free()
