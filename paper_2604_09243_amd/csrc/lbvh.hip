@@ -438,6 +438,9 @@ constexpr int kPlocSmall = 2048;  // clusters finished inside one workgroup
 constexpr int kPlocSmallThreads = 1024;
 constexpr int kPlocPer = kPlocSmall / kPlocSmallThreads;
 constexpr int kPlocMaxSteps = 1 << 16;
+// A node visit (two box tests) in triangle tests, the host SAH build's
+// measured constant (0.5 → 1.5: batch 3.16 → 2.90 s, aircraft 8.84 → 8.34 ms).
+constexpr float kPlocNodeCost = 1.5f;
 
 struct PlocState {
     int m;          // live clusters
@@ -520,9 +523,9 @@ __device__ inline int2 cluster_stats(const float4 &lo, const PlocNodes &nd)
 // Node p from the clusters (la, ha, sa) and (lb, hb, sb); the merged
 // cluster goes to (olo, ohi) and its stats are returned.  A cluster's hi.w
 // is its subtree cost, in units of one triangle test per unit of half area
-// with two box tests counted as half a triangle test (the host SAH build's
-// constants): a subtree of at most leaf_max triangles becomes one leaf when
-// that costs no more than the node and its two subtrees.
+// with a node visit counted as kPlocNodeCost triangle tests (the host SAH
+// build's constant): a subtree of at most leaf_max triangles becomes one
+// leaf when that costs no more than the node and its two subtrees.
 __device__ inline int2 ploc_merge(int p, const float4 &la, const float4 &ha, int2 sa, const float4 &lb,
                                   const float4 &hb, int2 sb, const PlocNodes &nd, int leaf_max, float4 &olo,
                                   float4 &ohi)
@@ -531,7 +534,7 @@ __device__ inline int2 ploc_merge(int p, const float4 &la, const float4 &ha, int
     const float hx = fmaxf(ha.x, hb.x), hy = fmaxf(ha.y, hb.y), hz = fmaxf(ha.z, hb.z);
     const float A = half_area(lx, ly, lz, hx, hy, hz);
     const int cnt = sa.x + sb.x;
-    const float c_node = 0.5f * A + ha.w + hb.w;
+    const float c_node = kPlocNodeCost * A + ha.w + hb.w;
     const float c_leaf = A * static_cast<float>(cnt);
     const bool leaf = cnt <= leaf_max && c_leaf <= c_node;
     const float cost = leaf ? c_leaf : c_node;
