@@ -24,6 +24,7 @@ namespace sbr {
 namespace {
 
 constexpr int kBins = 32;
+static_assert(kBins <= 32, "bin occupancy is a 32-bit mask");
 // A node visit (both child boxes) costs about 1.5 triangle tests in the
 // trace kernel (stack and loop work, lanes diverging between the two
 // phases, while a leaf's triangles are tested together): 0.5, 1.0, 1.5 and
@@ -99,45 +100,64 @@ struct Builder {
         }
         const int n = e - b;
         if (n == 1) return make_leaf(b, e, box);
-        // best binned split over the three axes
+        // best binned split over the three axes: one pass bins every
+        // triangle on all axes, then each axis sweeps only its occupied bins
+        // (an empty bin changes neither side of a split, so the costs, and
+        // the first minimum, are those of a sweep over all kBins)
         float best = INFINITY;
         int best_axis = -1, best_bin = -1;
         const float parent_area = std::max(box.area(), 1e-30f);
+        float sc[3];
+        bool ok[3];
         for (int ax = 0; ax < 3; ++ax) {
             const float ext = cb.hi[ax] - cb.lo[ax];
-            if (!(ext > 0.f)) continue;
-            Box bb[kBins];
-            int bc[kBins] = {0};
-            for (auto &x : bb) x.empty();
-            const float sc = kBins / ext;
-            for (int i = b; i < e; ++i) {
-                int q = static_cast<int>((cen[3 * idx[i] + ax] - cb.lo[ax]) * sc);
+            ok[ax] = ext > 0.f;
+            sc[ax] = ok[ax] ? kBins / ext : 0.f;
+        }
+        Box bb[3][kBins];
+        int bc[3][kBins];
+        uint32_t occ[3] = {0u, 0u, 0u};
+        for (int i = b; i < e; ++i) {
+            const int t = idx[i];
+            for (int ax = 0; ax < 3; ++ax) {
+                if (!ok[ax]) continue;
+                int q = static_cast<int>((cen[3 * t + ax] - cb.lo[ax]) * sc[ax]);
                 q = std::min(std::max(q, 0), kBins - 1);
-                bb[q].grow(pb[idx[i]]);
-                ++bc[q];
+                if (occ[ax] >> q & 1u) {
+                    bb[ax][q].grow(pb[t]);
+                    ++bc[ax][q];
+                } else {
+                    occ[ax] |= 1u << q;
+                    bb[ax][q] = pb[t];
+                    bc[ax][q] = 1;
+                }
             }
+        }
+        for (int ax = 0; ax < 3; ++ax) {
+            if (!ok[ax]) continue;
+            int qs[kBins], m = 0;
+            for (uint32_t bits = occ[ax]; bits; bits &= bits - 1) qs[m++] = __builtin_ctz(bits);
             float ra[kBins];
             int rn[kBins];
             Box acc;
             acc.empty();
             int cnt = 0;
-            for (int q = kBins - 1; q >= 1; --q) {
-                acc.grow(bb[q]);
-                cnt += bc[q];
-                ra[q] = acc.area();
-                rn[q] = cnt;
+            for (int j = m - 1; j >= 1; --j) {
+                acc.grow(bb[ax][qs[j]]);
+                cnt += bc[ax][qs[j]];
+                ra[j] = acc.area();
+                rn[j] = cnt;
             }
             acc.empty();
             cnt = 0;
-            for (int q = 0; q < kBins - 1; ++q) {
-                acc.grow(bb[q]);
-                cnt += bc[q];
-                if (cnt == 0 || rn[q + 1] == 0) continue;
-                const float cost = kNodeCost + (acc.area() * cnt + ra[q + 1] * rn[q + 1]) / parent_area;
+            for (int j = 0; j < m - 1; ++j) {
+                acc.grow(bb[ax][qs[j]]);
+                cnt += bc[ax][qs[j]];
+                const float cost = kNodeCost + (acc.area() * cnt + ra[j + 1] * rn[j + 1]) / parent_area;
                 if (cost < best) {
                     best = cost;
                     best_axis = ax;
-                    best_bin = q;
+                    best_bin = qs[j];
                 }
             }
         }
