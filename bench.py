@@ -116,15 +116,30 @@ def cpu_baseline(w, A_gpu, seconds):
     dt = time.perf_counter() - t0
     return dict(value=q / dt, unit="rays*bounces/s", cores=O.num_threads(), kind="oracle",
                 sample="%d of the 181 angles (full ray grids), brute-force closest hit, %.1f s" % (n, dt),
-                angles_per_s=n / dt), dict(angles_checked=n, max_abs_db=worst_db, max_rel_complex=worst_rel)
+                angles_per_s=n / dt, cpu=cpu_model()), dict(angles_checked=n, max_abs_db=worst_db,
+                                                            max_rel_complex=worst_rel)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=10,
-                    help="untimed steps first (the GPU clock settles over the first ~8 sweeps)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 for the trihedral sweep, 3 for batch, mlp and builders, "
+                         "3 for the trihedral surrogate and 1 for the aircraft surrogate)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 10 for the trihedral sweep: the GPU clock settles over "
+                         "the first ~8 sweeps; 1 elsewhere, 0 for the aircraft surrogate)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -143,6 +158,11 @@ def main():
                     help="BVH builder of each step: host binned SAH (default; fewer node and triangle tests "
                          "per ray), the GPU LBVH, or GPU PLOC clustering")
     args = ap.parse_args()
+    if args.steps is None or args.warmup is None:
+        big = args.workload == "surrogate" and args.target == "aircraft"
+        steps, warmup = {"trihedral": (20, 10)}.get(args.workload, (1, 0) if big else (3, 1))
+        args.steps = steps if args.steps is None else args.steps
+        args.warmup = warmup if args.warmup is None else args.warmup
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: every incidence angle is independent, so a sweep shards by "
@@ -182,8 +202,12 @@ def main():
 
     builder = BUILDER_ID[args.builder]
 
+    build_s = []
+
     def step():
-        bvh = ctx.build_bvh(w.V, w.T, builder=builder)
+        tb = time.perf_counter()
+        bvh = ctx.build_bvh(w.V, w.T, builder=builder)  # returns with the tree on the device
+        build_s.append(time.perf_counter() - tb)
         A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
                                  samples_per_lambda=w.samples_per_lambda)
         bvh.free()
@@ -237,6 +261,11 @@ def main():
         "angles_per_s": angles / dt,
         "trace_ms_per_step": sum(s["ms_trace"] for s in stats) / args.steps,
         "po_ms_per_step": sum(s["ms_po"] for s in stats) / args.steps,
+        "build_ms_per_step": 1e3 * float(np.mean(build_s[-args.steps:])),
+        # the same queries over the trace kernel's GPU time alone, and angles over
+        # the GPU time of trace + PO + finalize (value divides by the whole step)
+        "trace_queries_per_s": queries / t_kernel,
+        "angles_per_s_gpu": angles / (sum(s["ms_trace"] + s["ms_po"] for s in stats) * 1e-3),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
