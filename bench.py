@@ -36,6 +36,12 @@ METRIC = "rays*bounces/s + RCS angles/s at <=0.05 dB vs oracle; surrogate vs pla
 # (`python -m oracle.visit_counts`).
 REF_VISITS = {1: (14.09, 2.41, 0.677), 2: (23.25, 3.34, 0.928), 3: (19.89, 1.96, 0.541),
               4: (11.97, 0.02, 0.0), 5: (0.0, 0.0, 0.0)}
+# The same on the 1.5 M-triangle aircraft sweep: every 45th of its 360
+# azimuths, 200,000 seeded rays of each (`python -m oracle.visit_counts
+# --aircraft`).
+REF_VISITS_AIRCRAFT = {1: (18.686, 1.370, 0.2516), 2: (53.527, 4.864, 0.0836), 3: (60.471, 5.368, 0.2803),
+                       4: (67.081, 6.678, 0.6555), 5: (68.911, 6.138, 0.8434), 6: (78.534, 7.216, 0.9329),
+                       7: (67.586, 5.829, 0.6012), 8: (66.504, 6.346, 0.5812)}
 # VALU lane operations per unit of work (float32 spec arithmetic, no fused
 # multiply-add in the triangle test): slab test of one box 15 (6 FMA, 6
 # min/max, min3/max3, compare); triangle test 66 (two cross products 18, four
@@ -57,8 +63,8 @@ BUILDER_SOURCE = {"lbvh": "lbvh.hip", "sah": "sah.cpp", "ploc": "lbvh.hip"}
 BUILDER_ID = {"lbvh": 0, "sah": 1, "ploc": 2}
 
 
-def work_per_query(b):
-    box, tri, hit = REF_VISITS.get(b, (0.0, 0.0, 0.0))
+def work_per_query(b, ref=None):
+    box, tri, hit = (REF_VISITS if ref is None else ref).get(b, (0.0, 0.0, 0.0))
     return box * C_BOX + tri * C_TRI + C_QUERY + hit * C_HIT
 
 
@@ -144,9 +150,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=("trihedral", "batch", "surrogate", "mlp", "builders"),
+    ap.add_argument("--workload", choices=("trihedral", "aircraft", "batch", "surrogate", "mlp", "builders"),
                     default="trihedral",
-                    help="trihedral: the 181-angle sweep (default); batch: the 64-scene uneven batch, one graph "
+                    help="trihedral: the 181-angle sweep (default); aircraft: the 360-angle sweep of the "
+                         "1.5 M-triangle aircraft (tree built once); batch: the 64-scene uneven batch, one graph "
                          "replay per step; surrogate: surrogate-plus-fallback fill vs plain SBR on a "
                          "3600 x 512 grid; mlp: network inference and training throughput; builders: build "
                          "time, tree quality and trace time of the three BVH builders on the trihedral and "
@@ -160,7 +167,7 @@ def main():
     args = ap.parse_args()
     if args.steps is None or args.warmup is None:
         big = args.workload == "surrogate" and args.target == "aircraft"
-        steps, warmup = {"trihedral": (20, 10)}.get(args.workload, (1, 0) if big else (3, 1))
+        steps, warmup = {"trihedral": (20, 10), "aircraft": (5, 3)}.get(args.workload, (1, 0) if big else (3, 1))
         args.steps = steps if args.steps is None else args.steps
         args.warmup = warmup if args.warmup is None else args.warmup
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -195,6 +202,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "builders":
         return bench_builders(args)
+    if args.workload == "aircraft":
+        return bench_aircraft(args)
     if args.workload == "mlp":
         return bench_mlp(args)
     w = si.trihedral_case()
@@ -441,6 +450,65 @@ def bench_mlp(args):
                      "frac": flops / dt / 2.5e15, "traffic": None},
         "train_ms_per_step": 1e3 * dtt / steps, "train_batch": 4096,
         "train_tflops": 3 * info["flops_per_point"] * 4096 * steps / dtt / 1e12,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_aircraft(args):
+    """The aircraft sweep (1.5 M triangles, 360 azimuths at elevation 0, 10 GHz,
+    lambda/8, up to 8 bounces, HH/HV/VH/VV): the tree is built once (its
+    time reported), each step is the whole 360-angle sweep (ray generation,
+    every bounce, PO, RCS).  Roofline of the trace kernel as for the
+    trihedral, priced on the oracle's SAH tree of the aircraft."""
+    import torch
+    import sbr_inputs as si
+    from paper_2604_09243_amd import Context
+    w = si.aircraft_case()
+    ctx = Context(0)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    bvh = ctx.build_bvh(w.V, w.T, builder=BUILDER_ID[args.builder])
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - tb)
+
+    def step():
+        A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
+                                 samples_per_lambda=w.samples_per_lambda)
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    queries = sum(s["queries"] for s in stats)
+    nb = w.max_bounces
+    q_b = np.zeros(nb + 1)
+    for s in stats:
+        q_b += np.array(s["queries_bounce"][:nb + 1])
+    work = sum(q_b[b] * work_per_query(b, REF_VISITS_AIRCRAFT) for b in range(1, nb + 1))
+    t_kernel = sum(s["ms_trace"] for s in stats) * 1e-3
+    out = {
+        "metric": METRIC, "value": queries / dt, "unit": "rays*bounces/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (intersection, field) + f64 (path, phase, PO weights)",
+        "data": "synthetic (seeded procedural mesh)",
+        "config": {"workload": w.name + "_360az_lambda8_b8", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
+                   "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
+                   "bvh": args.builder, "polarisations": "HH,HV,VH,VV"},
+        "angles_per_s": w.n_angles * args.steps / dt,
+        "trace_ms_per_step": 1e3 * t_kernel / args.steps,
+        "po_ms_per_step": sum(s["ms_po"] for s in stats) / args.steps,
+        "build_ms_once": build_ms,
+        "trace_queries_per_s": queries / t_kernel,
+        "roofline": {"bound": "alu", "achieved": work / t_kernel / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "Tlaneop/s", "frac": work / t_kernel / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "k_stream<0> (all bounces, angle grid)",
+                     "avg_launch_ms": 1e3 * t_kernel / args.steps, "work_per_launch_lane_ops": work / args.steps},
     }
     print(json.dumps(out), flush=True)
 

@@ -8,11 +8,13 @@ oracle's fast mode with B_max = b and differences the cumulative counters,
 giving per-bounce queries, box tests, triangle tests and hits on a fixed
 sample of the trihedral sweep (every 10th angle of the 181).
 
-    python -m oracle.visit_counts  ->  prints the JSON written to
-    oracle/visit_counts_trihedral.json
+    python -m oracle.visit_counts             ->  oracle/visit_counts_trihedral.json
+    python -m oracle.visit_counts --aircraft  ->  oracle/visit_counts_aircraft.json
+      (every 45th of the aircraft's 360 azimuths, 200,000 seeded rays each)
 """
 import json
 import os
+import sys
 
 import numpy as np
 
@@ -20,10 +22,20 @@ import sbr_inputs as si
 from . import oracle as O
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "visit_counts_trihedral.json")
+OUT_AIRCRAFT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "visit_counts_aircraft.json")
 
 
-def per_bounce_counts(w, angle_idx, bmax):
+def per_bounce_counts(w, angle_idx, bmax, ray_sample=None, seed=0):
+    """ray_sample: trace only this many rays of each angle, drawn with a
+    seeded generator (the per-query averages of a large grid)."""
     m = O.Mesh(w.V, w.T).build_bvh("sah", 4, 16)
+    subsets = {}
+    if ray_sample:
+        rng = np.random.default_rng(seed)
+        for i in angle_idx:
+            Nu, Nv, *_ = O.aperture(m.bbox, w.theta_deg[i], w.phi_deg[i], O.C0 / float(np.max(w.freqs_hz)) /
+                                    w.samples_per_lambda)
+            subsets[i] = np.sort(rng.choice(Nu * Nv, size=min(ray_sample, Nu * Nv), replace=False))
     cum = []
     rays = 0
     for b in range(1, bmax + 1):
@@ -31,7 +43,7 @@ def per_bounce_counts(w, angle_idx, bmax):
         rays = 0
         for i in angle_idx:
             r = O.rcs_angle(m, w.theta_deg[i], w.phi_deg[i], w.freqs_hz, w.samples_per_lambda, bmax=b,
-                            use_bvh=True)
+                            use_bvh=True, ray_subset=subsets.get(i))
             q += r["queries"]
             box += r["box_tests"]
             tri += r["tri_tests"]
@@ -47,13 +59,21 @@ def per_bounce_counts(w, angle_idx, bmax):
                         hits_per_query=d[3] / max(d[0], 1)))
         prev = c
     return dict(workload=w.name, angles_sampled=len(angle_idx), rays=rays, tree="binned SAH, leaf<=4, 16 bins",
-                per_bounce=out)
+                ray_sample=ray_sample, per_bounce=out)
 
 
 def main():
-    w = si.trihedral_case()
-    res = per_bounce_counts(w, list(range(0, w.n_angles, 10)), w.max_bounces)
-    with open(OUT, "w") as f:
+    if "--aircraft" in sys.argv:
+        # the 1.5 M-triangle aircraft: every 45th of its 360 azimuths, 200,000
+        # seeded rays of each (of ~9.6 M)
+        w = si.aircraft_case()
+        res = per_bounce_counts(w, list(range(0, w.n_angles, 45)), w.max_bounces, ray_sample=200_000, seed=0)
+        out = OUT_AIRCRAFT
+    else:
+        w = si.trihedral_case()
+        res = per_bounce_counts(w, list(range(0, w.n_angles, 10)), w.max_bounces)
+        out = OUT
+    with open(out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
 
