@@ -42,6 +42,10 @@ REF_VISITS = {1: (14.09, 2.41, 0.677), 2: (23.25, 3.34, 0.928), 3: (19.89, 1.96,
 REF_VISITS_AIRCRAFT = {1: (18.686, 1.370, 0.2516), 2: (53.527, 4.864, 0.0836), 3: (60.471, 5.368, 0.2803),
                        4: (67.081, 6.678, 0.6555), 5: (68.911, 6.138, 0.8434), 6: (78.534, 7.216, 0.9329),
                        7: (67.586, 5.829, 0.6012), 8: (66.504, 6.346, 0.5812)}
+# The same on the 64-scene batch: 64 items drawn in proportion to their rays,
+# 20,000 seeded rays of each (`python -m oracle.visit_counts --batch`).
+REF_VISITS_BATCH = {1: (20.201, 2.204, 0.2682), 2: (48.168, 6.442, 0.0506), 3: (57.043, 8.326, 0.1284),
+                    4: (68.321, 10.404, 0.3818), 5: (71.418, 10.881, 0.4266), 6: (74.625, 11.287, 0.4904)}
 # VALU lane operations per unit of work (float32 spec arithmetic, no fused
 # multiply-add in the triangle test): slab test of one box 15 (6 FMA, 6
 # min/max, min3/max3, compare); triangle test 66 (two cross products 18, four
@@ -61,6 +65,11 @@ def pmc_file(builder):
 
 BUILDER_SOURCE = {"lbvh": "lbvh.hip", "sah": "sah.cpp", "ploc": "lbvh.hip"}
 BUILDER_ID = {"lbvh": 0, "sah": 1, "ploc": 2}
+
+
+def C_sizeof_tune(sbr):
+    import ctypes
+    return ctypes.sizeof(sbr.Tune)
 
 
 def work_per_query(b, ref=None):
@@ -328,6 +337,27 @@ def bench_batch(args):
         "graph_ms_per_step": sum(s["ms_total"] for s in stats) / args.steps,
         "setup_s": t_setup,
     }
+    # roofline of the trace launches (one streaming launch per chunk): the
+    # graph replay has one clock, so one more run, launched eagerly with the
+    # same plan and events around each chunk's trace, gives their GPU time
+    b.close()
+    from paper_2604_09243_amd import sbr
+    be = ctx.batch(scn, w.items(), w.freqs(), w.max_bounces, samples_per_lambda=w.samples_per_lambda,
+                   flags=sbr.OPT_NO_GRAPH, tune=sbr.Tune(C_sizeof_tune(sbr), **tune))
+    _, _, se = be.run()
+    be.close()
+    nb = w.max_bounces
+    q_b = np.array(se["queries_bounce"][:nb + 1], np.float64)
+    work = sum(q_b[k] * work_per_query(k, REF_VISITS_BATCH) for k in range(1, nb + 1))
+    t_kernel = se["ms_trace"] * 1e-3
+    nc = info["n_chunks"]
+    out["trace_ms_eager"] = se["ms_trace"]
+    out["po_ms_eager"] = se["ms_po"]
+    out["trace_queries_per_s"] = se["queries"] / t_kernel
+    out["roofline"] = {"bound": "alu", "achieved": work / t_kernel / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                       "unit": "Tlaneop/s", "frac": work / t_kernel / PEAK_LANE_OPS, "traffic": None,
+                       "kernel": "k_stream<0> (one launch per chunk, all bounces of its items)", "launches": nc,
+                       "avg_launch_ms": se["ms_trace"] / nc, "work_per_launch_lane_ops": work / nc}
     print(json.dumps(out), flush=True)
 
 
