@@ -46,6 +46,18 @@ REF_VISITS_AIRCRAFT = {1: (18.686, 1.370, 0.2516), 2: (53.527, 4.864, 0.0836), 3
 # 20,000 seeded rays of each (`python -m oracle.visit_counts --batch`).
 REF_VISITS_BATCH = {1: (20.201, 2.204, 0.2682), 2: (48.168, 6.442, 0.0506), 3: (57.043, 8.326, 0.1284),
                     4: (68.321, 10.404, 0.3818), 5: (71.418, 10.881, 0.4266), 6: (74.625, 11.287, 0.4904)}
+# The same over the rays a primary-ray mask keeps (8 x 8-ray cells touched
+# by a projected leaf box of the oracle's tree): the sweeps' default.  Later
+# bounces equal the all-ray figures (only hits bounce); the oracle's masks
+# keep 72 % of the trihedral's, 26 % of the aircraft's and 29 % of the
+# batch's primary rays.
+REF_VISITS_UNMASKED = {1: (19.176, 3.341, 0.9406), 2: (23.248, 3.345, 0.9282), 3: (19.887, 1.955, 0.5408),
+                       4: (11.966, 0.023, 0.0), 5: (0.0, 0.0, 0.0)}
+REF_VISITS_AIRCRAFT_UNMASKED = {1: (53.375, 5.299, 0.9734), 2: (53.527, 4.864, 0.0836), 3: (60.471, 5.368, 0.2803),
+                                4: (67.081, 6.678, 0.6555), 5: (68.911, 6.138, 0.8434), 6: (78.534, 7.216, 0.9329),
+                                7: (67.586, 5.829, 0.6012), 8: (66.504, 6.346, 0.5812)}
+REF_VISITS_BATCH_UNMASKED = {1: (53.718, 7.731, 0.9405), 2: (48.168, 6.442, 0.0506), 3: (57.043, 8.326, 0.1284),
+                             4: (68.321, 10.404, 0.3818), 5: (71.418, 10.881, 0.4266), 6: (74.625, 11.287, 0.4904)}
 # VALU lane operations per unit of work (float32 spec arithmetic, no fused
 # multiply-add in the triangle test): slab test of one box 15 (6 FMA, 6
 # min/max, min3/max3, compare); triangle test 66 (two cross products 18, four
@@ -65,6 +77,22 @@ def pmc_file(builder):
 
 BUILDER_SOURCE = {"lbvh": "lbvh.hip", "sah": "sah.cpp", "ploc": "lbvh.hip"}
 BUILDER_ID = {"lbvh": 0, "sah": 1, "ploc": 2}
+
+
+def priced_work(q_b, masked, nb, ref_all, ref_unmasked, mask_on):
+    """Reference lane operations of a trace: every query at its bounce's price.
+    With the primary-ray mask the masked rays (misses, no traversal) are left
+    out and the other first-bounce queries take the price of unmasked rays;
+    later bounces only ever follow hits, which the mask never touches."""
+    if not mask_on:
+        return sum(q_b[b] * work_per_query(b, ref_all) for b in range(1, nb + 1))
+    return ((q_b[1] - masked) * work_per_query(1, ref_unmasked) +
+            sum(q_b[b] * work_per_query(b, ref_unmasked) for b in range(2, nb + 1)))
+
+
+def mask_flag(args):
+    from paper_2604_09243_amd import sbr
+    return sbr.OPT_NO_MASK if args.no_mask else 0
 
 
 def C_sizeof_tune(sbr):
@@ -170,6 +198,8 @@ def main():
     ap.add_argument("--target", choices=("trihedral", "aircraft"), default="trihedral",
                     help="surrogate: band-limited trihedral or the procedural aircraft")
     ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch parameters first")
+    ap.add_argument("--no-mask", action="store_true",
+                    help="trace every primary ray (no per-angle mask of empty cells)")
     ap.add_argument("--builder", choices=("lbvh", "sah", "ploc"), default="sah",
                     help="BVH builder of each step: host binned SAH (default; fewer node and triangle tests "
                          "per ray), the GPU LBVH, or GPU PLOC clustering")
@@ -227,7 +257,7 @@ def main():
         bvh = ctx.build_bvh(w.V, w.T, builder=builder)  # returns with the tree on the device
         build_s.append(time.perf_counter() - tb)
         A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
-                                 samples_per_lambda=w.samples_per_lambda)
+                                 samples_per_lambda=w.samples_per_lambda, flags=mask_flag(args))
         bvh.free()
         return A, st
 
@@ -251,7 +281,8 @@ def main():
     q_b = np.zeros(nb + 1)
     for s in stats:
         q_b += np.array(s["queries_bounce"][:nb + 1])
-    work = sum(q_b[b] * work_per_query(b) for b in range(1, nb + 1))
+    masked = sum(s["masked"] for s in stats)
+    work = priced_work(q_b, masked, nb, REF_VISITS, REF_VISITS_UNMASKED, not args.no_mask)
     t_kernel = sum(s["ms_trace"] for s in stats) * 1e-3
     launches = args.steps
     achieved = work / t_kernel
@@ -274,8 +305,9 @@ def main():
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": w.name + "_181az_lambda10_b5", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
-                   "bvh": args.builder,
+                   "bvh": args.builder, "primary_mask": not args.no_mask,
                    "polarisations": "HH,HV,VH,VV"},
+        "masked_rays_per_step": masked / args.steps,
         "angles_per_s": angles / dt,
         "trace_ms_per_step": sum(s["ms_trace"] for s in stats) / args.steps,
         "po_ms_per_step": sum(s["ms_po"] for s in stats) / args.steps,
@@ -307,7 +339,8 @@ def bench_batch(args):
     scn = ctx.pack_scenes(bvhs)
     for b in bvhs:
         b.free()
-    b = ctx.batch(scn, w.items(), w.freqs(), w.max_bounces, samples_per_lambda=w.samples_per_lambda)
+    b = ctx.batch(scn, w.items(), w.freqs(), w.max_bounces, samples_per_lambda=w.samples_per_lambda,
+                  flags=mask_flag(args))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     tune = b.autotune().as_dict() if args.autotune else b.info()["tune"]
@@ -343,14 +376,16 @@ def bench_batch(args):
     b.close()
     from paper_2604_09243_amd import sbr
     be = ctx.batch(scn, w.items(), w.freqs(), w.max_bounces, samples_per_lambda=w.samples_per_lambda,
-                   flags=sbr.OPT_NO_GRAPH, tune=sbr.Tune(C_sizeof_tune(sbr), **tune))
+                   flags=sbr.OPT_NO_GRAPH | mask_flag(args), tune=sbr.Tune(C_sizeof_tune(sbr), **tune))
     _, _, se = be.run()
     be.close()
     nb = w.max_bounces
     q_b = np.array(se["queries_bounce"][:nb + 1], np.float64)
-    work = sum(q_b[k] * work_per_query(k, REF_VISITS_BATCH) for k in range(1, nb + 1))
+    work = priced_work(q_b, se["masked"], nb, REF_VISITS_BATCH, REF_VISITS_BATCH_UNMASKED, not args.no_mask)
     t_kernel = se["ms_trace"] * 1e-3
     nc = info["n_chunks"]
+    out["masked_rays_per_step"] = se["masked"]
+    out["config"]["primary_mask"] = not args.no_mask
     out["trace_ms_eager"] = se["ms_trace"]
     out["po_ms_eager"] = se["ms_po"]
     out["trace_queries_per_s"] = se["queries"] / t_kernel
@@ -503,7 +538,7 @@ def bench_aircraft(args):
 
     def step():
         A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
-                                 samples_per_lambda=w.samples_per_lambda)
+                                 samples_per_lambda=w.samples_per_lambda, flags=mask_flag(args))
         return st
 
     for _ in range(args.warmup):
@@ -520,7 +555,8 @@ def bench_aircraft(args):
     q_b = np.zeros(nb + 1)
     for s in stats:
         q_b += np.array(s["queries_bounce"][:nb + 1])
-    work = sum(q_b[b] * work_per_query(b, REF_VISITS_AIRCRAFT) for b in range(1, nb + 1))
+    masked = sum(s["masked"] for s in stats)
+    work = priced_work(q_b, masked, nb, REF_VISITS_AIRCRAFT, REF_VISITS_AIRCRAFT_UNMASKED, not args.no_mask)
     t_kernel = sum(s["ms_trace"] for s in stats) * 1e-3
     out = {
         "metric": METRIC, "value": queries / dt, "unit": "rays*bounces/s", "n_gpus": 1, "steps": args.steps,
@@ -529,7 +565,8 @@ def bench_aircraft(args):
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": w.name + "_360az_lambda8_b8", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
-                   "bvh": args.builder, "polarisations": "HH,HV,VH,VV"},
+                   "bvh": args.builder, "primary_mask": not args.no_mask, "polarisations": "HH,HV,VH,VV"},
+        "masked_rays_per_step": masked / args.steps,
         "angles_per_s": w.n_angles * args.steps / dt,
         "trace_ms_per_step": 1e3 * t_kernel / args.steps,
         "po_ms_per_step": sum(s["ms_po"] for s in stats) / args.steps,

@@ -80,6 +80,11 @@ enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
                                          launches (default: one streaming launch for all bounces) */
 #define SBR_OPT_NO_GRAPH 32           /* sbr_batch_run: launch eagerly instead of replaying the
                                          captured graph (gives per-stage times in sbr_stats) */
+#define SBR_OPT_NO_MASK 64            /* sweeps and batches: trace every primary ray.  By default a
+                                         per-angle mask of 8 x 8-ray cells, built on the device from
+                                         the projected leaf boxes of the tree (with a margin above
+                                         the box test's float32 rounding), resolves rays of empty
+                                         cells as misses without traversal; results are identical */
 
 /* ------------------------------------------------------------------------ */
 /* Library and context                                                       */
@@ -236,6 +241,7 @@ typedef struct {
     int64_t trav[6]; /* libraries built with SBR_TRACE_COUNTERS only (else 0): node visits, leaf
                         visits, triangle tests (summed over queries), and wave-level trips of the
                         node loop, the leaf step and the bounce loop */
+    int64_t masked;  /* primary rays resolved as misses by the mask (included in queries) */
 } sbr_stats;
 
 /* Traces n_rays rays (1 <= n_rays < 2^31) for up to max_bounces (1..64)

@@ -48,6 +48,8 @@ def lib():
         L.orc_mesh_free.argtypes = [C.c_void_p]
         L.orc_mesh_info.argtypes = [C.c_void_p, _dp, _fp, _lp, _lp, C.POINTER(C.c_int)]
         L.orc_mesh_normals.argtypes = [C.c_void_p, _fp]
+        L.orc_mesh_leaf_boxes.argtypes = [C.c_void_p, _dp, C.c_int64]
+        L.orc_mesh_leaf_boxes.restype = C.c_int64
         L.orc_mesh_build_bvh.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
         L.orc_frame.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp]
         L.orc_aperture.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -106,6 +108,14 @@ class Mesh:
         out = np.zeros((self.nt, 3), np.float32)
         lib().orc_mesh_normals(self._h, _ptr(out, _fp))
         return out
+
+    def leaf_boxes(self):
+        """(n_leaves, 6) float64 boxes (lo, hi) of the BVH's leaves (for
+        pricing traversal work only)."""
+        n = lib().orc_mesh_leaf_boxes(self._h, None, 0)
+        out = np.zeros((max(n, 1), 6))
+        lib().orc_mesh_leaf_boxes(self._h, _ptr(out, _dp), n)
+        return out[:n]
 
     def build_bvh(self, rule="sah", nleaf=4, nbins=16):
         """Algorithm 1: recursive split by the median centroid (``median``) or

@@ -174,6 +174,25 @@ void orc_mesh_normals(const orc_mesh *m, float *out)
     memcpy(out, m->n, sizeof(float) * 3 * m->nt);
 }
 
+/* Boxes (lo.xyz, hi.xyz) of the leaves of the mesh's BVH, in node order, into
+ * out[6 * cap]; returns the number of leaves (0 without a BVH).  Used only to
+ * price traversal work, never in the method itself. */
+int64_t orc_mesh_leaf_boxes(const orc_mesh *m, double *out, int64_t cap)
+{
+    int64_t k = 0;
+    for (int64_t i = 0; i < m->n_nodes; ++i) {
+        const orc_node *nd = &m->nodes[i];
+        if (nd->left >= 0) continue;
+        if (k < cap)
+            for (int a = 0; a < 3; ++a) {
+                out[6 * k + a] = nd->lo[a];
+                out[6 * k + 3 + a] = nd->hi[a];
+            }
+        ++k;
+    }
+    return k;
+}
+
 /* ------------------------------------------------------------------------ */
 /* BVH of Algorithm 1 (fast mode): median split or binned SAH                 */
 /* ------------------------------------------------------------------------ */

@@ -168,6 +168,7 @@ enum Slot {
     W_KF = 21,
     W_PARTIAL = 22,
     W_SPILL = 23,
+    W_MASK = 24,
     W_TUNE = 25,
 };
 
@@ -309,7 +310,39 @@ void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p)
     p.root = 0;
     p.eps = 0.f;
     p.slack = 0.f;
-    p.pad_ = 0;
+    p.mcu = 0;
+    p.mask_base = 0;
+    p.mwork_base = 0;
+    p.node_cnt = 0;
+    p.mslack = 0.f;
+}
+
+void mask_plan(AnglePlan &p, const double bbox[6], int64_t node_cnt)
+{
+    p.mcu = (p.nu + kMaskCell - 1) >> kMaskShift;
+    p.node_cnt = static_cast<int32_t>(node_cnt);
+    // A ray passes a (padded) box test only if its line comes within a few
+    // float32 rounding errors of the box: of the order 2^-24 times the
+    // magnitudes of the origin and of the box corners.  The margin takes 64
+    // times that bound, plus half a ray spacing.
+    double r = 0.0;
+    for (int i = 0; i < 3; ++i) r += std::max(std::fabs(bbox[i]), std::fabs(bbox[3 + i]));
+    const double ro = std::fabs(p.uc) + std::fabs(p.vc) + std::fabs(p.s0) + 0.5 * (double(p.nu) + p.nv) * p.ds;
+    p.mslack = static_cast<float>(0.5 + 64.0 * 0x1p-24 * (r + ro) / p.ds);
+}
+
+void mask_layout(AnglePlan *plans, int64_t a0, int64_t a1, int64_t &bytes, int64_t &units)
+{
+    bytes = 0;
+    units = 0;
+    for (int64_t a = a0; a < a1; ++a) {
+        AnglePlan &p = plans[a];
+        const int64_t mcv = (p.nv + kMaskCell - 1) >> kMaskShift;
+        p.mask_base = bytes;
+        p.mwork_base = units;
+        bytes += (int64_t(p.mcu) * mcv + 3) & ~int64_t(3);
+        units += p.node_cnt;
+    }
 }
 
 double uniform_step(const double *kf, int n)
@@ -340,6 +373,7 @@ void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_
     // a ray is valid when it hit at bounce 1 and was not dropped as trapped
     st->valid += static_cast<int64_t>(hstat[8 + 1]) - static_cast<int64_t>(hstat[1]);
     for (int i = 0; i < 6; ++i) st->trav[i] += static_cast<int64_t>(hstat[2 + i]);
+    st->masked += static_cast<int64_t>(hstat[kStatMasked]);
 }
 
 }  // namespace sbr
@@ -766,6 +800,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         p.root = 0;
         p.eps = bvh->eps;
         p.slack = box_slack(bvh->diag);
+        mask_plan(p, bvh->bbox, bvh->n_nodes);
         PoAngle &q = pang[a];
         for (int i = 0; i < 3; ++i) {
             q.basis[i] = ap.k_hat[i];
@@ -787,8 +822,8 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     }
     // chunks of consecutive angles holding at most chunk_cap rays (or one angle)
     std::vector<int64_t> cstart;
-    std::vector<int64_t> chunk_units;
-    int64_t max_chunk_rays = 0, max_chunk_units = 0;
+    std::vector<int64_t> chunk_units, chunk_mask_bytes, chunk_mask_units;
+    int64_t max_chunk_rays = 0, max_chunk_units = 0, max_mask_bytes = 0;
     {
         int64_t a = 0;
         while (a < na) {
@@ -808,6 +843,11 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
                 ++b;
             }
             chunk_units.push_back(units);
+            int64_t mb = 0, mu = 0;
+            mask_layout(plans.data(), a, b, mb, mu);
+            chunk_mask_bytes.push_back(mb);
+            chunk_mask_units.push_back(mu);
+            max_mask_bytes = std::max(max_mask_bytes, mb);
             max_chunk_rays = std::max(max_chunk_rays, rays);
             max_chunk_units = std::max(max_chunk_units, units);
             a = b;
@@ -821,15 +861,17 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     RayQueue qa{}, qb{};
     Records rec;
     int32_t *spill;
-    void *dplans, *dtile, *dang, *dkf, *dpart, *hpin;
+    void *dplans, *dtile, *dang, *dkf, *dpart, *hpin, *dmask = nullptr;
     const int sched = tune.schedule;
+    const bool use_mask = !(sw->flags & SBR_OPT_NO_MASK);
     const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
     const size_t tile_words = static_cast<size_t>(na + n_chunks);
     if ((rc = get_counters(ws, cn)) || (rc = get_records(ws, max_chunk_rays, rec)) ||
         (rc = get_spill(ctx, bvh, blocks, &spill)) || (rc = ws->get(W_PLANS, sizeof(AnglePlan) * na, &dplans)) ||
         (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) || (rc = ws->get(W_BASIS, sizeof(PoAngle) * na, &dang)) ||
         (rc = ws->get(W_KF, 8 * nf, &dkf)) ||
-        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(max_chunk_units) * nf, &dpart)))
+        (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(max_chunk_units) * nf, &dpart)) ||
+        (use_mask && (rc = ws->get(W_MASK, static_cast<size_t>(std::max<int64_t>(max_mask_bytes, 4)), &dmask))))
         return rc;
     if (sched == kScheduleWavefront &&
         ((rc = get_queue(ws, W_QA, max_chunk_rays, qa)) || (rc = get_queue(ws, W_QB, max_chunk_rays, qb))))
@@ -906,6 +948,12 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         ta.rec = rec;
         ta.ctrs = cn.p;
         ta.spill = spill;
+        if (use_mask) {
+            ta.mask = static_cast<const uint8_t *>(dmask);
+            if ((rc = launch_mask(s, bvh->nodes, cp, m, chunk_mask_units[c], static_cast<uint8_t *>(dmask),
+                                  chunk_mask_bytes[c])))
+                return rc;
+        }
         std::vector<hipEvent_t> cev;
         if (want_stats) cev.assign(ev.begin() + epc * c, ev.begin() + epc * (c + 1));
         if ((rc = run_trace(s, ta, qa, qb, want_stats ? &cev : nullptr))) return rc;

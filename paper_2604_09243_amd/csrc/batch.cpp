@@ -84,6 +84,7 @@ struct sbr_batch {
     // chunks: items [cstart[c], cstart[c + 1])
     std::vector<int64_t> cstart, c_tiles, c_units, tile_off;
     std::vector<int> c_maxnf;
+    std::vector<int64_t> c_mask_bytes, c_mask_units;  // primary-ray mask of each chunk
     int blocks = 0;
     // device
     DevBufs dev;
@@ -96,6 +97,7 @@ struct sbr_batch {
     uint32_t *d_ctr = nullptr;
     CounterPtrs ctrs{};
     int32_t *d_spill = nullptr;
+    uint8_t *d_mask = nullptr;  // NULL with SBR_OPT_NO_MASK
     RayQueue qa{}, qb{};
     unsigned long long *h_stat = nullptr;  // pinned [kStatU64]
     // graph
@@ -112,13 +114,14 @@ struct SceneView {
     int32_t root;
     float eps, slack;
     const double *bbox;
+    int64_t n_nodes;
 };
 
 SceneView scene_view(const sbr_bvh *b, int s)
 {
-    if (b->scenes.empty()) return SceneView{0, b->eps, box_slack(b->diag), b->bbox};
+    if (b->scenes.empty()) return SceneView{0, b->eps, box_slack(b->diag), b->bbox, b->n_nodes};
     const SceneInfo &si = b->scenes[s];
-    return SceneView{si.root, si.eps, box_slack(si.diag), si.bbox};
+    return SceneView{si.root, si.eps, box_slack(si.diag), si.bbox, si.n_nodes};
 }
 
 int n_scenes(const sbr_bvh *b) { return b->scenes.empty() ? 1 : static_cast<int>(b->scenes.size()); }
@@ -156,6 +159,7 @@ int plan_batch(sbr_batch *b)
         p.root = sv.root;
         p.eps = sv.eps;
         p.slack = sv.slack;
+        mask_plan(p, sv.bbox, sv.n_nodes);
         PoAngle &q = ang[i];
         for (int k = 0; k < 3; ++k) {
             q.basis[k] = ap.k_hat[k];
@@ -174,7 +178,9 @@ int plan_batch(sbr_batch *b)
     b->c_units.clear();
     b->c_maxnf.clear();
     b->tile_off.clear();
-    int64_t max_rays = 0, max_rows = 0, tile_words = 0;
+    b->c_mask_bytes.clear();
+    b->c_mask_units.clear();
+    int64_t max_rays = 0, max_rows = 0, tile_words = 0, max_mask = 4;
     for (int64_t a = 0; a < ni;) {
         b->cstart.push_back(a);
         b->tile_off.push_back(tile_words);
@@ -198,6 +204,11 @@ int plan_batch(sbr_batch *b)
         b->c_tiles.push_back(tiles);
         b->c_units.push_back(units);
         b->c_maxnf.push_back(mnf);
+        int64_t mb = 0, mu = 0;
+        mask_layout(plans.data(), a, e, mb, mu);
+        b->c_mask_bytes.push_back(mb);
+        b->c_mask_units.push_back(mu);
+        max_mask = std::max(max_mask, mb);
         tile_words += (e - a) + 1;
         max_rays = std::max(max_rays, rays);
         max_rows = std::max(max_rows, rows);
@@ -224,6 +235,9 @@ int plan_batch(sbr_batch *b)
         (rc = b->dev.alloc(&b->d_part, 8 * static_cast<size_t>(max_rows))) ||
         (rc = b->dev.alloc(&b->d_ctr, kCounterBytes / 4)) ||
         (rc = b->dev.alloc(&b->d_spill, spill_words(bv, b->blocks))))
+        return rc;
+    b->d_mask = nullptr;
+    if (!(b->flags & SBR_OPT_NO_MASK) && (rc = b->dev.alloc(&b->d_mask, static_cast<size_t>(max_mask))))
         return rc;
     b->rec = Records{r0, r1, r2, rD};
     char *cb = reinterpret_cast<char *>(b->d_ctr);
@@ -278,6 +292,12 @@ int enqueue(sbr_batch *b, hipStream_t s, double *A, double *sigma, std::vector<h
         ta.rec = b->rec;
         ta.ctrs = b->ctrs;
         ta.spill = b->d_spill;
+        if (b->d_mask) {
+            ta.mask = b->d_mask;
+            if ((rc = launch_mask(s, b->bvh->nodes, ta.plans, ta.n_angles, b->c_mask_units[c], b->d_mask,
+                                  b->c_mask_bytes[c])))
+                return rc;
+        }
         if ((rc = run_trace(s, ta, b->qa, b->qb, nullptr))) return rc;
         if (ev) SBR_HIP(hipEventRecord((*ev)[3 * c + 1], s));
         PoArgs pa{};

@@ -53,8 +53,19 @@ struct AnglePlan {
     int32_t root;              // root node of the angle's scene in the node array
     float eps;                 // the scene's surface offset
     float slack;               // the scene's box padding for entry distances
-    int32_t pad_;
+    // primary-ray mask: cells of kMaskCell x kMaskCell rays, rows of mcu bytes
+    int32_t mcu;               // cells along u
+    int64_t mask_base;         // first byte of this angle's cells in the launch's mask
+    int64_t mwork_base;        // first build unit (one per node of the scene) of this angle
+    int32_t node_cnt;          // nodes of the scene: [root, root + node_cnt)
+    float mslack;              // margin of the projected leaf boxes, in ray spacings
 };
+
+// Primary-ray mask (silhouette of the leaf boxes, per angle): a ray whose
+// cell no projected leaf box touches cannot pass a leaf's box test, so it is
+// resolved as a miss without traversal.
+constexpr int kMaskShift = 3;
+constexpr int kMaskCell = 1 << kMaskShift;
 
 // In-flight ray state of the wavefront schedule's queues, 6 x 16 bytes
 // (structure of arrays): s0 = (o.xyz, tri_prev)  s1 = (d.xyz, tri_first)
@@ -77,11 +88,13 @@ struct Records {
 
 // Counter block, zeroed before each sweep chunk / trace call.  Counters that
 // many waves update sit on separate 256-byte lines (kLineU32 uint32 apart):
-//   stat:  u64[kStatU64] = [0] queries, [1] trapped, [8 + b] hits at bounce b
+//   stat:  u64[kStatU64] = [0] queries, [1] trapped, [8 + b] hits at bounce b,
+//          [kStatMasked] primary rays resolved by the mask (counted in [0] too)
 //   q_cnt: kQcnt lines; q_cnt[b] = rays pushed during bounce-b launch
 //   claim: kMaxLaunch x 8 lines; the 8 tile-claim counters of each launch
 constexpr int kLineU32 = 64;
-constexpr int kStatU64 = 8 + SBR_MAX_BOUNCES + 1;
+constexpr int kStatMasked = 8 + SBR_MAX_BOUNCES + 1;
+constexpr int kStatU64 = kStatMasked + 1;
 constexpr int kMaxLaunch = SBR_MAX_BOUNCES + 2;
 constexpr int kQcnt = SBR_MAX_BOUNCES + 2;
 constexpr size_t kStatBytes = 1024;
@@ -212,6 +225,7 @@ struct TraceArgs {
     const int64_t *tile_base; // device [n_angles + 1]
     int n_angles;
     int64_t n_tiles;
+    const uint8_t *mask;      // device primary-ray mask of the plans, or NULL (every ray traced)
     // user source / sink (sbr_trace)
     const sbr_rays *rays;
     int64_t n_rays;
@@ -225,6 +239,17 @@ struct TraceArgs {
 };
 // bounce = 1 for the stream schedule (one launch does every bounce)
 int launch_trace(hipStream_t s, const TraceArgs &a, int bounce);
+// Builds the primary-ray mask of plans [0, n_angles) of one launch: zeroes
+// mask[0, mask_bytes) (a kernel, so usable inside a captured graph), then
+// marks every cell that the padded projection of a leaf box of the angle's
+// scene touches; n_units = sum of the plans' node_cnt.
+int launch_mask(hipStream_t s, const BNode *nodes, const AnglePlan *plans, int n_angles, int64_t n_units,
+                uint8_t *mask, int64_t mask_bytes);
+// Host: margins and cell rows of a plan for the mask (scene bbox, node count)
+void mask_plan(AnglePlan &p, const double bbox[6], int64_t node_cnt);
+// Host: mask_base / mwork_base of plans [a0, a1) of one launch; returns the
+// launch's mask bytes (a multiple of 4) and build units.
+void mask_layout(AnglePlan *plans, int64_t a0, int64_t a1, int64_t &bytes, int64_t &units);
 int trace_persistent_blocks(sbr_ctx *ctx, int blocks_per_cu);  // 0 = occupancy limit
 int check_tune(const sbr_tune &t);
 int trace_block_threads();

@@ -83,6 +83,7 @@ struct Params {
     // grid source
     const AnglePlan *plans;
     const int64_t *tile_base;
+    const uint8_t *mask;  // primary-ray mask of the plans (NULL: trace every ray)
     int n_angles;
     // caller source / sink
     const float *uo, *ud, *uh, *uv;
@@ -414,9 +415,6 @@ __device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool want)
     return base + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
 }
 
-// Position q of the angle grid (tile = q / 64, position in the tile's
-// tile_w-wide patch = q % 64) -> a fresh ray; false if q lies outside the
-// angle's N_u x N_v grid.
 // The angle whose tiles hold `tile`, searched in angles [lo, hi).
 __device__ __forceinline__ int find_angle(const Params &p, int64_t tile, int lo, int hi)
 {
@@ -440,7 +438,14 @@ __device__ __forceinline__ void batch_angles(const Params &p, int64_t u, int64_t
     a_hi = __shfl(a, 1);
 }
 
-__device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r, int a_lo, int a_hi)
+// Position q of the angle grid (tile = q / 64, position in the tile's
+// tile_w-wide patch = q % 64) -> kGridRay with a fresh ray in r; kGridNone
+// if q lies outside the angle's N_u x N_v grid; kGridMasked if the ray's
+// mask cell is empty: no leaf box can be hit, so its record is written empty
+// (as for a miss) and the ray needs no traversal.
+constexpr int kGridNone = 0, kGridRay = 1, kGridMasked = 2;
+
+__device__ __forceinline__ int grid_ray(const Params &p, int64_t q, Ray &r, int a_lo, int a_hi)
 {
     const int64_t tile = q >> 6;
     const int k = static_cast<int>(q & 63);
@@ -450,7 +455,11 @@ __device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r, int
     const int tw = 1 << p.tile_shift;
     const int i = static_cast<int>(t % pl.tu) * tw + (k & (tw - 1));
     const int j = static_cast<int>(t / pl.tu) * (kTileRays >> p.tile_shift) + (k >> p.tile_shift);
-    if (i >= pl.nu || j >= pl.nv) return false;
+    if (i >= pl.nu || j >= pl.nv) return kGridNone;
+    if (p.mask && p.mask[pl.mask_base + static_cast<int64_t>(j >> kMaskShift) * pl.mcu + (i >> kMaskShift)] == 0) {
+        p.rec.r2[pl.rec_base + static_cast<int64_t>(j) * pl.nu + i] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
+        return kGridMasked;
+    }
     const double ui = pl.uc + ((static_cast<double>(i) + 0.5) - 0.5 * static_cast<double>(pl.nu)) * pl.ds;
     const double vj = pl.vc + ((static_cast<double>(j) + 0.5) - 0.5 * static_cast<double>(pl.nv)) * pl.ds;
     r.ox = static_cast<float>((ui * pl.u[0] + vj * pl.v[0]) + pl.s0 * pl.k[0]);
@@ -472,7 +481,7 @@ __device__ __forceinline__ bool grid_ray(const Params &p, int64_t q, Ray &r, int
     r.P = 0.0;
     r.comp = 0.0;
     r.kdo = dotk(plan_k(pl), r.ox, r.oy, r.oz);
-    return true;
+    return kGridRay;
 }
 
 // Ray e of the caller's arrays; false if e >= n_rays.
@@ -649,7 +658,7 @@ __device__ __forceinline__ K3 kvec(const Params &p, const Ray &r)
 
 // Per-block counters in LDS, flushed with one global atomic each at the end.
 struct BlockStats {
-    unsigned int queries, trapped;
+    unsigned int queries, trapped, masked;
     unsigned int hits[SBR_MAX_BOUNCES + 1];
     unsigned long long diag[6];
 };
@@ -671,6 +680,7 @@ __device__ __forceinline__ void flush_stats(const Params &p, BlockStats &bs)
     const int t = threadIdx.x;
     if (t == 0 && bs.queries) atomicAdd(p.stat + 0, static_cast<unsigned long long>(bs.queries));
     if (t == 1 && bs.trapped) atomicAdd(p.stat + 1, static_cast<unsigned long long>(bs.trapped));
+    if (t == 2 && bs.masked) atomicAdd(p.stat + kStatMasked, static_cast<unsigned long long>(bs.masked));
     if (t >= 8 && t <= 8 + SBR_MAX_BOUNCES && bs.hits[t - 8])
         atomicAdd(p.stat + t, static_cast<unsigned long long>(bs.hits[t - 8]));
 #ifdef SBR_TRACE_COUNTERS
@@ -684,6 +694,7 @@ __device__ __forceinline__ void init_stats(BlockStats &bs)
     if (t == 0) {
         bs.queries = 0;
         bs.trapped = 0;
+        bs.masked = 0;
     }
     if (t <= SBR_MAX_BOUNCES) bs.hits[t] = 0;
     if (t < 6) bs.diag[t] = 0;
@@ -738,7 +749,18 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_stream(Params p)
                 if (SRC == 0) batch_angles(p, u, e, a_lo, a_hi);
             }
             const int64_t q = pos + static_cast<int64_t>(__popcll(idle & lt));
-            if (!has && q < end) has = SRC == 0 ? grid_ray(p, q, r, a_lo, a_hi) : user_ray(p, q, r);
+            if (!has && q < end) {
+                if (SRC == 0) {
+                    const int g = grid_ray(p, q, r, a_lo, a_hi);
+                    has = g == kGridRay;
+                    if (g == kGridMasked) {
+                        atomicAdd(&bs.queries, 1u);
+                        atomicAdd(&bs.masked, 1u);
+                    }
+                } else {
+                    has = user_ray(p, q, r);
+                }
+            }
             pos = min(pos + static_cast<int64_t>(__popcll(idle)), end);
         }
         if (__ballot(has) == 0) break;
@@ -821,7 +843,12 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
         Ray r;
         bool active;
         if (SRC == 0) {
-            active = grid_ray(p, q, r, a_lo, a_hi);
+            const int g = grid_ray(p, q, r, a_lo, a_hi);
+            active = g == kGridRay;
+            if (g == kGridMasked) {
+                atomicAdd(&bs.queries, 1u);
+                atomicAdd(&bs.masked, 1u);
+            }
         } else if (SRC == 1) {
             active = user_ray(p, q, r);
         } else {
@@ -890,6 +917,84 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
 }
 
 
+// ---------------------------------------------------------------------------
+// Primary-ray mask: one unit per (angle, node of its scene); every leaf child
+// of the node marks the cells its box's projection (plus the plan's margin)
+// touches.  Every leaf is the child of exactly one node, so the union over
+// units is the silhouette of all leaf boxes of the scene at that angle.
+// ---------------------------------------------------------------------------
+constexpr int kMaskBlock = 256;
+constexpr int kMaskMaxPerThread = 16;  // units of a thread, kMaskBlock apart, in large launches
+
+// [min, max] of x . w over the box [lo, hi]
+__device__ __forceinline__ void project_box(const double lo[3], const double hi[3], const double w[3], double &mn,
+                                            double &mx)
+{
+    mn = 0.0;
+    mx = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double a = lo[k] * w[k], b = hi[k] * w[k];
+        mn += fmin(a, b);
+        mx += fmax(a, b);
+    }
+}
+
+// Ray indices [first, last] along one axis whose centres (c + (i + 0.5 - n / 2) ds)
+// lie in [mn, mx] widened by `slack` spacings; false if none.
+__device__ __forceinline__ bool ray_span(double mn, double mx, double c, double ds, int n, double slack, int &first,
+                                         int &last)
+{
+    const double f0 = (mn - c) / ds + 0.5 * n - 0.5 - slack;
+    const double f1 = (mx - c) / ds + 0.5 * n - 0.5 + slack;
+    if (!(f1 >= 0.0) || !(f0 <= static_cast<double>(n - 1)) || !(f0 <= f1)) return false;
+    first = static_cast<int>(ceil(fmax(f0, 0.0)));
+    last = static_cast<int>(floor(fmin(f1, static_cast<double>(n - 1))));
+    return first <= last;
+}
+
+__device__ void mask_box(const AnglePlan &pl, uint8_t *mask, const double lo[3], const double hi[3])
+{
+    double u0, u1, v0, v1;
+    project_box(lo, hi, pl.u, u0, u1);
+    project_box(lo, hi, pl.v, v0, v1);
+    int i0, i1, j0, j1;
+    if (!ray_span(u0, u1, pl.uc, pl.ds, pl.nu, pl.mslack, i0, i1)) return;
+    if (!ray_span(v0, v1, pl.vc, pl.ds, pl.nv, pl.mslack, j0, j1)) return;
+    for (int cj = j0 >> kMaskShift; cj <= (j1 >> kMaskShift); ++cj) {
+        uint8_t *row = mask + pl.mask_base + static_cast<int64_t>(cj) * pl.mcu;
+        for (int ci = i0 >> kMaskShift; ci <= (i1 >> kMaskShift); ++ci) row[ci] = 1;
+    }
+}
+
+__global__ __launch_bounds__(kMaskBlock) void k_mask(const BNode *__restrict__ nodes,
+                                                     const AnglePlan *__restrict__ plans, int n_angles,
+                                                     int64_t n_units, int per_thread, uint8_t *__restrict__ mask)
+{
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kMaskBlock * per_thread + threadIdx.x;
+    if (first >= n_units) return;
+    int a = 0, hi = n_angles;  // the angle of the first unit, then advanced
+    while (hi - a > 1) {
+        const int mid = (a + hi) >> 1;
+        if (plans[mid].mwork_base <= first) a = mid;
+        else hi = mid;
+    }
+    for (int k = 0; k < per_thread; ++k) {
+        const int64_t g = first + static_cast<int64_t>(k) * kMaskBlock;
+        if (g >= n_units) break;
+        while (a + 1 < n_angles && plans[a + 1].mwork_base <= g) ++a;
+        const AnglePlan &pl = plans[a];
+        const BNode nd = nodes[pl.root + (g - pl.mwork_base)];
+        if (nd.ch.x < 0) {
+            const double lo[3] = {nd.a.x, nd.a.y, nd.a.z}, hi3[3] = {nd.a.w, nd.b.x, nd.b.y};
+            mask_box(pl, mask, lo, hi3);
+        }
+        if (nd.ch.y < 0 && nd.ch.y != nd.ch.x) {
+            const double lo[3] = {nd.b.z, nd.b.w, nd.c.x}, hi3[3] = {nd.c.y, nd.c.z, nd.c.w};
+            mask_box(pl, mask, lo, hi3);
+        }
+    }
+}
+
 }  // namespace
 
 int trace_block_threads() { return kBlock; }
@@ -935,6 +1040,7 @@ static Params make_params(const TraceArgs &a, int launch)
     p.flags = a.flags;
     p.plans = a.plans;
     p.tile_base = a.tile_base;
+    p.mask = a.mask;
     p.n_angles = a.n_angles;
     p.uo = a.rays ? a.rays->o : nullptr;
     p.ud = a.rays ? a.rays->d : nullptr;
@@ -975,6 +1081,23 @@ static void launch_trace_t(hipStream_t s, const TraceArgs &a, const Params &p, i
     } else {
         k_wave<2, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
     }
+}
+
+int launch_mask(hipStream_t s, const BNode *nodes, const AnglePlan *plans, int n_angles, int64_t n_units,
+                uint8_t *mask, int64_t mask_bytes)
+{
+    if (mask_bytes % 4 != 0 || n_angles < 1) return fail(SBR_ERR_INVALID_ARG, "launch_mask: bad layout");
+    int rc;
+    if ((rc = launch_zero_u32(s, reinterpret_cast<uint32_t *>(mask), mask_bytes / 4))) return rc;
+    // at least ~4,096 workgroups before a thread takes several units
+    const int per = static_cast<int>(
+        std::min<int64_t>(kMaskMaxPerThread, std::max<int64_t>(1, n_units / (int64_t(kMaskBlock) * 4096))));
+    const int64_t per_block = static_cast<int64_t>(kMaskBlock) * per;
+    const int64_t blocks = (n_units + per_block - 1) / per_block;
+    if (blocks > 0)
+        k_mask<<<static_cast<unsigned>(blocks), kMaskBlock, 0, s>>>(nodes, plans, n_angles, n_units, per, mask);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
 }
 
 int launch_trace(hipStream_t s, const TraceArgs &a, int bounce)

@@ -23,6 +23,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 BUILD_LBVH, BUILD_SAH, BUILD_PLOC = 0, 1, 2
 REC_VALID, REC_TRAPPED, REC_BACK_LAST = 1, 2, 4
 OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRONT, OPT_NO_GRAPH = 1, 2, 4, 8, 16, 32
+OPT_NO_MASK = 64
 MAX_BOUNCES = 64
 
 _vp = C.c_void_p
@@ -62,13 +63,14 @@ class Stats(C.Structure):
     _fields_ = [("rays", C.c_int64), ("queries", C.c_int64), ("valid", C.c_int64), ("trapped", C.c_int64),
                 ("hits", C.c_int64 * (MAX_BOUNCES + 1)), ("angles", C.c_int64), ("ms_trace", C.c_double),
                 ("ms_po", C.c_double), ("ms_total", C.c_double), ("ms_bounce", C.c_double * (MAX_BOUNCES + 1)),
-                ("queries_bounce", C.c_int64 * (MAX_BOUNCES + 1)), ("trav", C.c_int64 * 6)]
+                ("queries_bounce", C.c_int64 * (MAX_BOUNCES + 1)), ("trav", C.c_int64 * 6),
+                ("masked", C.c_int64)]
 
     def as_dict(self):
         return dict(rays=self.rays, queries=self.queries, valid=self.valid, trapped=self.trapped,
                     hits=list(self.hits), angles=self.angles, ms_trace=self.ms_trace, ms_po=self.ms_po,
                     ms_total=self.ms_total, ms_bounce=list(self.ms_bounce),
-                    queries_bounce=list(self.queries_bounce), trav=list(self.trav))
+                    queries_bounce=list(self.queries_bounce), trav=list(self.trav), masked=self.masked)
 
 
 class PoDesc(C.Structure):

@@ -379,3 +379,22 @@ def test_bvh_fast_mode_keeps_the_nearer_sliver_on_a_seam(orc):
             assert np.array_equal(a[key], b[key]), (phi, key)
         # the configuration: both slivers are hit, the lower-t one is kept
         assert a["tri_first"][0] in (1164872, 1192872) and a["nb"][0] == 1
+
+
+def test_pricing_mask_drops_only_brute_force_misses():
+    """The primary-ray mask that prices masked sweeps (leaf boxes of the
+    oracle's SAH tree projected onto 8 x 8-ray cells) drops only rays that the
+    brute-force oracle, which has no tree at all, finds no hit for."""
+    import sbr_inputs as si
+    from oracle import oracle as O
+    from oracle import visit_counts as V
+    w = si.trihedral_case()
+    m = O.Mesh(w.V, w.T).build_bvh("sah", 4, 16)
+    ds = O.C0 / float(np.max(w.freqs_hz)) / w.samples_per_lambda
+    for i in (0, 37, 90, 160):
+        msk = V.masked_rays(m, w.theta_deg[i], w.phi_deg[i], ds)
+        assert 0.02 < msk.mean() < 0.98, msk.mean()
+        ids = np.flatnonzero(msk)
+        r = O.rcs_angle(m, w.theta_deg[i], w.phi_deg[i], w.freqs_hz, w.samples_per_lambda, ds=ds, bmax=1,
+                        use_bvh=False, ray_subset=ids)
+        assert int(r["nb"].sum()) == 0
