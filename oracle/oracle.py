@@ -21,6 +21,7 @@ C0 = 299_792_458.0
 F_VALID, F_TRAPPED, F_BACK_LAST, F_EDGE = 1, 2, 4, 8
 MODE_VECTOR, MODE_PAPER = 0, 1
 _USE_BVH, _DROP_TRAPPED, _PAPER_PATH, _EDGE_DIAG = 1, 2, 4, 8
+_FP32_PATH = 16  # precision study only: path, D and phase in float32
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -161,9 +162,11 @@ def gen_rays(bbox, theta_deg, phi_deg, ds, eta=0.1):
 
 
 def trace(mesh, o, d, eH0, eV0, k, bmax, use_bvh=False, drop_trapped=False, paper_path=False,
-          edge_diag=False, want_path=False):
+          edge_diag=False, want_path=False, fp32_path=False):
     """Algorithm 2 for every ray.  ``d`` may be one direction for all rays or
-    one per ray.  Returns a dict of per-ray arrays and counters."""
+    one per ray.  Returns a dict of per-ray arrays and counters.
+    ``fp32_path``: accumulate P and form D in float32 (the single-precision
+    variant whose phase error Sec. 6 discusses; a study, not the method)."""
     o = np.ascontiguousarray(o, dtype=np.float32).reshape(-1, 3)
     n = len(o)
     d = np.asarray(d, dtype=np.float32)
@@ -185,7 +188,8 @@ def trace(mesh, o, d, eH0, eV0, k, bmax, use_bvh=False, drop_trapped=False, pape
         setattr(out, name, _ptr(r[name], t))
     out.tri_path = _ptr(r["tri_path"], _ip) if want_path else None
     opts = ((_USE_BVH if use_bvh else 0) | (_DROP_TRAPPED if drop_trapped else 0)
-            | (_PAPER_PATH if paper_path else 0) | (_EDGE_DIAG if edge_diag else 0))
+            | (_PAPER_PATH if paper_path else 0) | (_EDGE_DIAG if edge_diag else 0)
+            | (_FP32_PATH if fp32_path else 0))
     if use_bvh and mesh.n_nodes == 0:
         mesh.build_bvh()
     rc = lib().orc_trace(mesh._h, n, _ptr(o, _fp), _ptr(d, _fp), _ptr(eH0, _dp), _ptr(eV0, _dp),
@@ -196,10 +200,11 @@ def trace(mesh, o, d, eH0, eV0, k, bmax, use_bvh=False, drop_trapped=False, pape
     return r
 
 
-def po(mesh, rec, mode, k, th_hat, ph_hat, dA, freqs):
+def po(mesh, rec, mode, k, th_hat, ph_hat, dA, freqs, fp32_phase=False):
     """Ray-tube PO sum over the valid rays of ``rec`` (a ``trace`` result).
     Returns complex A of shape (n_freq, 2, 2), [f, receive, transmit] with
-    polarisation index 0 = H (phi_hat), 1 = V (theta_hat)."""
+    polarisation index 0 = H (phi_hat), 1 = V (theta_hat).  ``fp32_phase``:
+    the phase k D formed in float32 (precision study only)."""
     freqs = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
     nf = len(freqs)
     A = np.zeros(nf * 8)
@@ -207,7 +212,8 @@ def po(mesh, rec, mode, k, th_hat, ph_hat, dA, freqs):
     k, th_hat, ph_hat = (np.ascontiguousarray(x, dtype=np.float64) for x in (k, th_hat, ph_hat))
     rc = lib().orc_po(mesh._h, n, _ptr(rec["nb"], _ip), _ptr(rec["tri_first"], _ip), _ptr(rec["tri_last"], _ip),
                       _ptr(rec["flags"], _ip), _ptr(rec["D"], _dp), _ptr(rec["d_last"], _fp),
-                      _ptr(rec["eH_last"], _dp), _ptr(rec["eV_last"], _dp), int(mode),
+                      _ptr(rec["eH_last"], _dp), _ptr(rec["eV_last"], _dp),
+                      int(mode) | (_FP32_PATH if fp32_phase else 0),
                       _ptr(k, _dp), _ptr(th_hat, _dp), _ptr(ph_hat, _dp), float(dA),
                       _ptr(freqs, _dp), nf, _ptr(A, _dp))
     if rc != 0:
@@ -225,10 +231,11 @@ def sigma_dbsm(A):
 
 def rcs_angle(mesh, theta_deg, phi_deg, freqs, samples_per_lambda=10.0, ds=None, eta=0.1, bmax=5,
               mode=MODE_VECTOR, use_bvh=False, drop_trapped=False, edge_diag=False, want_path=False,
-              ray_subset=None):
+              ray_subset=None, fp32_path=False):
     """One incidence angle end to end: ray grid at ds = lambda(f_max)/s (one
     trace serves every frequency), trace, PO sum.  ``ray_subset`` restricts
-    the trace to the given ray indices (the PO sum then covers only them)."""
+    the trace to the given ray indices (the PO sum then covers only them).
+    ``fp32_path``: path, D and phase in float32 (precision study only)."""
     freqs = np.atleast_1d(np.asarray(freqs, dtype=np.float64))
     if ds is None:
         ds = C0 / float(freqs.max()) / samples_per_lambda
@@ -236,7 +243,7 @@ def rcs_angle(mesh, theta_deg, phi_deg, freqs, samples_per_lambda=10.0, ds=None,
     o, d, Nu, Nv = gen_rays(mesh.bbox, theta_deg, phi_deg, ds, eta)
     ids = np.arange(len(o)) if ray_subset is None else np.asarray(ray_subset)
     rec = trace(mesh, o[ids], d, ph, th, k, bmax, use_bvh=use_bvh, drop_trapped=drop_trapped,
-                edge_diag=edge_diag, want_path=want_path)
-    A = po(mesh, rec, mode, k, th, ph, ds * ds, freqs)
+                edge_diag=edge_diag, want_path=want_path, fp32_path=fp32_path)
+    A = po(mesh, rec, mode, k, th, ph, ds * ds, freqs, fp32_phase=fp32_path)
     rec.update(A=A, Nu=Nu, Nv=Nv, ds=ds, o=o[ids], d=d, k=k, th_hat=th, ph_hat=ph, ray_ids=ids)
     return rec

@@ -51,6 +51,10 @@
 #define ORC_DROP_TRAPPED 2
 #define ORC_PAPER_PATH 4
 #define ORC_EDGE_DIAG 8
+/* Precision study of Sec. 6 (not the method's arithmetic): accumulate the
+ * path P and form D in float32 (orc_trace), and form the phase k D in float32
+ * (orc_po, or-ed into mode). */
+#define ORC_FP32_PATH 16
 
 typedef struct {
     float lo[3], hi[3];
@@ -665,11 +669,17 @@ int orc_trace(const orc_mesh *m, int64_t n, const float *o_in, const float *d_in
             if ((opts & ORC_EDGE_DIAG) && edge_ambiguous(m, o, d, prev, t, j)) edge = 1;
             if (j < 0) break;
             float x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-            P = P + (double)t;
+            const int fp32 = (opts & ORC_FP32_PATH) != 0;
+            P = fp32 ? (double)((float)P + t) : P + (double)t;
             if (b >= 2 && !(opts & ORC_PAPER_PATH)) {
                 /* first-order correction for starting the segment eps off the surface */
-                double c = ((double)nfp[0] * d[0] + (double)nfp[1] * d[1]) + (double)nfp[2] * d[2];
-                P = P + (double)m->eps * c;
+                if (fp32) {
+                    float c32 = (nfp[0] * d[0] + nfp[1] * d[1]) + nfp[2] * d[2];
+                    P = (double)((float)P + m->eps * c32);
+                } else {
+                    double c = ((double)nfp[0] * d[0] + (double)nfp[1] * d[1]) + (double)nfp[2] * d[2];
+                    P = P + (double)m->eps * c;
+                }
             }
             N = N + 1;
             if (N == 1) first = j;
@@ -714,7 +724,14 @@ int orc_trace(const orc_mesh *m, int64_t n, const float *o_in, const float *d_in
         double D = 0.0;
         if (N >= 1) {
             float o0[3] = {o_in[3 * r], o_in[3 * r + 1], o_in[3 * r + 2]};
-            D = (dotk(k, o0) + P) + dotk(k, xl);
+            if (opts & ORC_FP32_PATH) {
+                const float k32[3] = {(float)k[0], (float)k[1], (float)k[2]};
+                const float a = (k32[0] * o0[0] + k32[1] * o0[1]) + k32[2] * o0[2];
+                const float c = (k32[0] * xl[0] + k32[1] * xl[1]) + k32[2] * xl[2];
+                D = (double)((a + (float)P) + c);
+            } else {
+                D = (dotk(k, o0) + P) + dotk(k, xl);
+            }
         }
         if (out->nb) out->nb[r] = N;
         if (out->tri_first) out->tri_first[r] = first;
@@ -761,6 +778,8 @@ int orc_po(const orc_mesh *m, int64_t n, const int32_t *nb, const int32_t *tri_f
            const double *eV_last, int mode, const double k[3], const double th_hat[3], const double ph_hat[3],
            double dA, const double *freqs, int nf, double *A)
 {
+    const int fp32 = (mode & ORC_FP32_PATH) != 0;
+    mode &= ~ORC_FP32_PATH;
     double *S = (double *)calloc((size_t)nf * 8, sizeof(double));
     if (!S) return -4;
     const double *ph[2] = {ph_hat, th_hat};
@@ -790,7 +809,7 @@ int orc_po(const orc_mesh *m, int64_t n, const int32_t *nb, const int32_t *tri_f
         }
         for (int f = 0; f < nf; f++) {
             double kf = 2.0 * ORC_PI * freqs[f] / ORC_C0;
-            double phs = kf * D[i];
+            double phs = fp32 ? (double)((float)kf * (float)D[i]) : kf * D[i];
             double cr = cos(phs), si = sin(phs);
             for (int p = 0; p < 2; p++)
                 for (int q = 0; q < 2; q++) {

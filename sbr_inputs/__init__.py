@@ -6,13 +6,13 @@ frequency lists and random ray sets.  It holds none of the SBR arithmetic
 CPU oracle and the HIP path can take their inputs from it without sharing any
 of the method's computation.
 """
-from .meshes import (icosphere, plate, dihedral, trihedral, aircraft,
+from .meshes import (icosphere, plate, duct, dihedral, trihedral, aircraft,
                      random_triangles, mesh_area)
 from .workloads import (C_LIGHT, sphere_case, trihedral_case, aircraft_case,
                         random_rays, Workload)
 from .batch import batch_case, BatchWorkload, Scene, ellipsoid
 
-__all__ = ["icosphere", "plate", "dihedral", "trihedral", "aircraft",
+__all__ = ["icosphere", "plate", "duct", "dihedral", "trihedral", "aircraft",
            "random_triangles", "mesh_area", "C_LIGHT", "sphere_case",
            "trihedral_case", "aircraft_case", "random_rays", "Workload",
            "batch_case", "BatchWorkload", "Scene", "ellipsoid"]

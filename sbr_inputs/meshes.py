@@ -89,6 +89,26 @@ def plate(a=1.0, b=1.0, nx=8, ny=8, z=0.0):
     return _finish(V, T)
 
 
+def duct(length=6.0, width=0.1, height=0.1, n=24):
+    """Rectangular duct along +x, open at x = 0 and closed by a plate at
+    x = length; walls at y = +-width/2 and z = +-height/2 (an engine-intake
+    like cavity: rays entering at an angle bounce between the walls, hit the
+    back plate and come out again)."""
+    L, w, h = length, width / 2, height / 2
+    parts = [((0, -w, -h), (L, 0, 0), (0, 0, 2 * h)),   # y = -w
+             ((0, w, -h), (L, 0, 0), (0, 0, 2 * h)),    # y = +w
+             ((0, -w, -h), (L, 0, 0), (0, 2 * w, 0)),   # z = -h
+             ((0, -w, h), (L, 0, 0), (0, 2 * w, 0)),    # z = +h
+             ((L, -w, -h), (0, 2 * w, 0), (0, 0, 2 * h))]  # back plate
+    Vs, Ts, nv = [], [], 0
+    for i, (o, du, dv) in enumerate(parts):
+        V, T = _grid_quad(o, du, dv, n if i < 4 else 2, 2, vbase=nv)
+        Vs.append(V)
+        Ts.append(T)
+        nv += len(V)
+    return _finish(np.concatenate(Vs), np.concatenate(Ts))
+
+
 def dihedral(a=1.0, b=1.0, n=8):
     """90-degree dihedral: faces x=0 (y in [0,a]) and y=0 (x in [0,a]),
     both spanning z in [-b/2, b/2].  Its bisector is phi = 45 deg in the

@@ -398,3 +398,18 @@ def test_pricing_mask_drops_only_brute_force_misses():
         r = O.rcs_angle(m, w.theta_deg[i], w.phi_deg[i], w.freqs_hz, w.samples_per_lambda, ds=ds, bmax=1,
                         use_bvh=False, ray_subset=ids)
         assert int(r["nb"].sum()) == 0
+
+
+def test_fp32_path_phase_error_grows_with_depth():
+    """The single-precision variant of the path (P, D and the phase in
+    float32; a study option of the oracle, not the method) drifts from the
+    float64 one by a phase error that grows with the number of reflections,
+    as Sec. 6 describes; the float64 path is the one every sweep uses."""
+    from oracle import precision_study as ps
+    r = ps.study(6.0, 0.1)
+    rows = {(lo, hi): (n, rms) for lo, hi, n, rms, _ in r["rows"]}
+    assert r["max_bounces"] >= 30
+    shallow, deep = rows[(1, 2)], rows[(21, 64)]
+    assert shallow[0] > 1000 and deep[0] > 500
+    assert deep[1] > 5 * shallow[1]
+    assert 1e-5 < r["dev"] < 1e-2
