@@ -106,3 +106,20 @@ def test_plan_rejects_bad_spacing():
     with pytest.raises(sbr.SbrError) as e:
         sbr.plan_angle(np.zeros(6), 0.0, 0.0, 0.0)
     assert e.value.status == sbr.ERR_INVALID_ARG
+
+
+def test_constants_match_header():
+    """Every SBR_MODE_/SBR_BUILD_/SBR_REC_/SBR_OPT_/SBR_ACT_ constant and
+    SBR_MAX_BOUNCES of include/sbr.h has the same value in the binding."""
+    from paper_2604_09243_amd import sbr
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SBR_([A-Z_]+)\s+(\d+)\b", src)}
+    for body in re.findall(r"enum\s*\{([^}]*)\}", src):
+        for m in re.finditer(r"SBR_([A-Z_]+)\s*=\s*(-?\d+)", body):
+            vals[m.group(1)] = int(m.group(2))
+    checked = 0
+    for name, v in vals.items():
+        if name.split("_")[0] in ("MODE", "BUILD", "REC", "OPT", "ACT") or name == "MAX_BOUNCES":
+            assert getattr(sbr, name) == v, name
+            checked += 1
+    assert checked >= 16 and vals["OPT_NO_MASK"] == sbr.OPT_NO_MASK
