@@ -63,3 +63,22 @@ def test_duct_depth_64_matches_oracle(torch, ctx, mode, theta, phi):
     assert err.max() <= 1e-4
     assert np.abs(so - sg)[sel].max() <= 0.05
     bvh.free()
+
+
+def test_duct_depth_64_schedules_agree(torch, ctx):
+    """Sixty-four launches of the wavefront schedule (one per bounce, queues
+    compacted between them) give the same bits as the streaming launch."""
+    from paper_2604_09243_amd import sbr
+    V, T = si.duct(6.0, 0.1, 0.1, 24)
+    say("case duct, schedules at depth 64")
+    bvh = ctx.build_bvh(V, T)
+    out = []
+    for fl in (0, sbr.OPT_WAVEFRONT, sbr.OPT_NO_MASK, sbr.OPT_WAVEFRONT | sbr.OPT_NO_MASK):
+        A, S, st = ctx.rcs_sweep(bvh, [84.0, 86.0], [190.0, 186.0], [10e9, 10.5e9], 64, samples_per_lambda=10.0,
+                                 flags=fl)
+        out.append((A.cpu().numpy(), st))
+    for A, st in out[1:]:
+        assert np.array_equal(A.view(np.float64), out[0][0].view(np.float64))
+        assert st["hits"] == out[0][1]["hits"] and st["queries"] == out[0][1]["queries"]
+    assert out[0][1]["hits"][30] > 0
+    bvh.free()
