@@ -90,6 +90,11 @@ def priced_work(q_b, masked, nb, ref_all, ref_unmasked, mask_on):
             sum(q_b[b] * work_per_query(b, ref_unmasked) for b in range(2, nb + 1)))
 
 
+def sbr_default_tune():
+    from paper_2604_09243_amd import sbr
+    return sbr.default_tune()
+
+
 def mask_flag(args):
     from paper_2604_09243_amd import sbr
     return sbr.OPT_NO_MASK if args.no_mask else 0
@@ -197,7 +202,8 @@ def main():
                          "the aircraft (secondary measurements)")
     ap.add_argument("--target", choices=("trihedral", "aircraft"), default="trihedral",
                     help="surrogate: band-limited trihedral or the procedural aircraft")
-    ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch parameters first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="aircraft, batch: autotune the launch parameters first (set-up, not timed)")
     ap.add_argument("--no-mask", action="store_true",
                     help="trace every primary ray (no per-angle mask of empty cells)")
     ap.add_argument("--builder", choices=("lbvh", "sah", "ploc"), default="sah",
@@ -343,6 +349,8 @@ def bench_batch(args):
                   flags=mask_flag(args))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    if args.autotune:
+        print("autotuning the batch", file=sys.stderr, flush=True)
     tune = b.autotune().as_dict() if args.autotune else b.info()["tune"]
     for _ in range(args.warmup):
         b.run(stats=False)
@@ -535,10 +543,17 @@ def bench_aircraft(args):
     bvh = ctx.build_bvh(w.V, w.T, builder=BUILDER_ID[args.builder])
     torch.cuda.synchronize()
     build_ms = 1e3 * (time.perf_counter() - tb)
+    tune, tune_s = None, 0.0
+    if args.autotune:
+        print("autotuning the sweep", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        tune = ctx.autotune(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
+                            samples_per_lambda=w.samples_per_lambda, flags=mask_flag(args))
+        tune_s = time.perf_counter() - t0
 
     def step():
         A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
-                                 samples_per_lambda=w.samples_per_lambda, flags=mask_flag(args))
+                                 samples_per_lambda=w.samples_per_lambda, flags=mask_flag(args), tune=tune)
         return st
 
     for _ in range(args.warmup):
@@ -565,7 +580,9 @@ def bench_aircraft(args):
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": w.name + "_360az_lambda8_b8", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
-                   "bvh": args.builder, "primary_mask": not args.no_mask, "polarisations": "HH,HV,VH,VV"},
+                   "bvh": args.builder, "primary_mask": not args.no_mask, "polarisations": "HH,HV,VH,VV",
+                   "tune": (tune if tune is not None else sbr_default_tune()).as_dict()},
+        "autotune_s": tune_s,
         "masked_rays_per_step": masked / args.steps,
         "angles_per_s": w.n_angles * args.steps / dt,
         "trace_ms_per_step": 1e3 * t_kernel / args.steps,
