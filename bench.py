@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the SBR trace-integrate path on one MI355X.
 
-Workload: square trihedral corner reflector (a = 1 m, 1,536 triangles),
-10 GHz, elevation 35.26 deg, azimuth 0..90 deg in 0.5 deg steps (181 angles),
-ray spacing lambda/10 (48,377,932 rays in all), at most 5 bounces, VECTOR PO
-(all four H/V pairs from one trace).  One step = the whole path for the
-sweep: mesh preparation and BVH build (host binned SAH by default, GPU LBVH
-with --builder lbvh), ray generation, multi-bounce transport, PO sum and RCS
-for all 181 angles.
+Default workload: the procedural aircraft (1,505,310 triangles; fuselage
+15 m, wings 12 m span, fins, two open inlets), 10 GHz, elevation 0, azimuth
+0..359 deg in 1 deg steps (360 angles), ray spacing lambda/8, at most 8
+bounces, VECTOR PO (all four H/V pairs from one trace).  The tree is built
+once per mesh (its time is reported apart, as the paper amortises it over
+all angles); one step = the whole path for the 360-angle sweep: ray
+generation, multi-bounce transport, PO sum and RCS.  ``--workload
+trihedral`` is the 181-angle corner-reflector sweep, with the tree built in
+every step.
 
 Prints one JSON line.  ``value`` is closest-hit queries (rays x bounces) per
-second over the timed steps; angles/s is reported beside it.  ``roofline``
-prices the dominant trace kernel by the reference traversal work of the
-oracle's SAH tree against the non-packed VALU issue rate;
-``cpu_baseline`` times the CPU oracle (brute force, as it stands) on a
-bounded sample of the same sweep.
+second over the timed steps, the primary rays that the mask resolves
+without traversal included (``value_traced`` leaves them out); angles/s is
+reported beside it.  ``roofline`` prices the dominant trace kernel by the
+reference traversal work of the oracle's SAH tree against the non-packed
+VALU issue rate; ``cpu_baseline`` times the CPU oracle (its tree mode, which
+is pinned bit for bit to brute force) on a bounded sample of the same sweep
+and ``parity_sample`` compares those angles with the GPU result.
 """
 import argparse
 import hashlib
@@ -58,20 +62,23 @@ REF_VISITS_AIRCRAFT_UNMASKED = {1: (53.375, 5.299, 0.9734), 2: (53.527, 4.864, 0
                                 7: (67.586, 5.829, 0.6012), 8: (66.504, 6.346, 0.5812)}
 REF_VISITS_BATCH_UNMASKED = {1: (53.718, 7.731, 0.9405), 2: (48.168, 6.442, 0.0506), 3: (57.043, 8.326, 0.1284),
                              4: (68.321, 10.404, 0.3818), 5: (71.418, 10.881, 0.4266), 6: (74.625, 11.287, 0.4904)}
-# VALU lane operations per unit of work (float32 spec arithmetic, no fused
-# multiply-add in the triangle test): slab test of one box 15 (6 FMA, 6
-# min/max, min3/max3, compare); triangle test 66 (two cross products 18, four
-# dot products 20, s = o - v0 3, correctly rounded reciprocal ~10, three
-# products 3, barycentric/t tests and the closest-hit update 12); per query
-# 12 (reciprocal direction, scaled origin); per hit 80 (hit point, fp64 path
-# and offset correction, reflection of d and both field vectors, new origin,
-# fp64 phase path, record).
-C_BOX, C_TRI, C_QUERY, C_HIT = 15, 66, 12, 80
+# VALU lane operations per unit of traversal work, the survey's constants
+# (midpoints of its ranges): a slab test of one box 14 (6 FMA, min/max of the
+# three slabs, the compare), a triangle test 40 (the float32
+# Moller-Trumbore specification with its correctly rounded reciprocal, the
+# barycentric and t tests and the closest-hit update), and 60 per query for
+# the rest of a bounce (reciprocal direction, the box rule of the winner,
+# the hit point, the float64 path, the reflection of d and of both field
+# vectors, the new origin, the record).
+C_BOX, C_TRI, C_BOUNCE = 14, 40, 60
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s of
 # non-packed VALU issue (the 157.3 TFLOP/s fp32 figure counts packed FMA as 4).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-def pmc_file(builder):
+
+def pmc_file(builder, workload="trihedral"):
+    if workload == "aircraft":
+        return os.path.join(ROOT, "profiles", "trace_aircraft_360az_%s_pmc.json" % builder)
     return os.path.join(ROOT, "profiles", "trace_trihedral_%s_pmc.json" % builder)
 
 
@@ -106,8 +113,8 @@ def C_sizeof_tune(sbr):
 
 
 def work_per_query(b, ref=None):
-    box, tri, hit = (REF_VISITS if ref is None else ref).get(b, (0.0, 0.0, 0.0))
-    return box * C_BOX + tri * C_TRI + C_QUERY + hit * C_HIT
+    box, tri, _hit = (REF_VISITS if ref is None else ref).get(b, (0.0, 0.0, 0.0))
+    return box * C_BOX + tri * C_TRI + C_BOUNCE
 
 
 def source_hash(builder):
@@ -120,19 +127,20 @@ def source_hash(builder):
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(kernel, builder):
+def pmc_traffic(kernel, builder, workload="trihedral"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this builder's tree, scaled by the plain-copy calibration;
     None if absent or if the trace or builder source changed since the
     counters were taken."""
     try:
-        with open(pmc_file(builder)) as f:
+        with open(pmc_file(builder, workload)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
     if d.get("source_hash") != source_hash(builder) or kernel not in d.get("kernels", {}):
         return None
     k = d["kernels"][kernel]
+    # fetch_kib and write_kib are per-dispatch averages
     return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0
 
 
@@ -193,9 +201,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     ap.add_argument("--workload", choices=("trihedral", "aircraft", "batch", "surrogate", "mlp", "builders"),
-                    default="trihedral",
-                    help="trihedral: the 181-angle sweep (default); aircraft: the 360-angle sweep of the "
-                         "1.5 M-triangle aircraft (tree built once); batch: the 64-scene uneven batch, one graph "
+                    default="aircraft",
+                    help="aircraft: the 360-angle sweep of the 1.5 M-triangle aircraft (tree built once; the "
+                         "default); trihedral: the 181-angle corner-reflector sweep; batch: the 64-scene uneven batch, one graph "
                          "replay per step; surrogate: surrogate-plus-fallback fill vs plain SBR on a "
                          "3600 x 512 grid; mlp: network inference and training throughput; builders: build "
                          "time, tree quality and trace time of the three BVH builders on the trihedral and "
@@ -313,6 +321,7 @@ def main():
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
                    "bvh": args.builder, "primary_mask": not args.no_mask,
                    "polarisations": "HH,HV,VH,VV"},
+        "value_traced": (queries - masked) / dt,
         "masked_rays_per_step": masked / args.steps,
         "angles_per_s": angles / dt,
         "trace_ms_per_step": sum(s["ms_trace"] for s in stats) / args.steps,
@@ -527,12 +536,73 @@ def bench_mlp(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_baseline_aircraft(w, A_gpu, seconds):
+    """The oracle as it stands on a bounded sample of the aircraft sweep: its
+    binned-SAH tree (built once, timed apart) in fast mode, which the CPU
+    tests pin bit for bit to brute force, on whole angles taken in a fixed
+    order until about `seconds` have passed (at least two); brute force on
+    400 seeded rays of the first angle as a check of those angles; a
+    one-thread figure of the fast mode on 50,000 seeded rays.  Also compares
+    the sampled angles with the GPU result (parity sample)."""
+    from oracle import oracle as O
+    m = O.Mesh(w.V, w.T)
+    t0 = time.perf_counter()
+    m.build_bvh("sah")
+    build_s = time.perf_counter() - t0
+    order = [0, 90, 180, 270, 45, 135, 225, 315, 23, 157, 203, 337, 68, 112, 248, 292]
+    q = n = 0
+    worst_db, worst_rel = 0.0, 0.0
+    amax = float(np.abs(A_gpu).max())
+    t0 = time.perf_counter()
+    for i in order:
+        r = O.rcs_angle(m, w.theta_deg[i], w.phi_deg[i], w.freqs_hz, w.samples_per_lambda, bmax=w.max_bounces,
+                        use_bvh=True)
+        q += r["queries"]
+        n += 1
+        Ao, Ag = r["A"], A_gpu[i]
+        den = np.maximum(np.abs(Ao), 1e-3 * amax)
+        worst_rel = max(worst_rel, float((np.abs(Ag - Ao) / den).max()))
+        so, sg = O.sigma_dbsm(Ao), O.sigma_dbsm(Ag)
+        sel = so >= so.max() - 40.0
+        worst_db = max(worst_db, float(np.abs(so - sg)[sel].max()))
+        if n >= 2 and time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    # brute force on seeded rays of the first angle: the same results as the tree, at its own rate
+    th, ph = w.theta_deg[order[0]], w.phi_deg[order[0]]
+    k, tv, pv = O.frame(th, ph)
+    o, d, _, _ = O.gen_rays(m.bbox, th, ph, w.ds)
+    ids = np.sort(np.random.default_rng(11).choice(len(o), 400, replace=False))
+    tb = time.perf_counter()
+    rb = O.trace(m, o[ids], d, pv, tv, k, w.max_bounces, want_path=True)
+    tb = time.perf_counter() - tb
+    rf = O.trace(m, o[ids], d, pv, tv, k, w.max_bounces, want_path=True, use_bvh=True)
+    brute_equal = all(np.array_equal(rb[key], rf[key]) for key in ("tri_path", "nb", "D", "x_last"))
+    # one thread
+    threads = O.num_threads()
+    ids = np.sort(np.random.default_rng(12).choice(len(o), 50_000, replace=False))
+    O.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        r1 = O.trace(m, o[ids], d, pv, tv, k, w.max_bounces, use_bvh=True)
+        t1 = time.perf_counter() - t1
+    finally:
+        O.set_num_threads(threads)
+    base = dict(value=q / dt, unit="rays*bounces/s", cores=threads, kind="oracle",
+                sample="%d of the 360 angles (full ray grids) in the oracle's SAH-tree mode, %.1f s; tree build "
+                       "%.1f s apart" % (n, dt, build_s),
+                angles_per_s=n / dt, single_thread=r1["queries"] / t1, brute_force=rb["queries"] / tb,
+                brute_force_rays=400, brute_force_equal_to_tree=bool(brute_equal), cpu=cpu_model())
+    return base, dict(angles_checked=n, max_abs_db=worst_db, max_rel_complex=worst_rel,
+                      db_within="40 dB of each angle's maximum", brute_force_rays_equal=bool(brute_equal))
+
+
 def bench_aircraft(args):
     """The aircraft sweep (1.5 M triangles, 360 azimuths at elevation 0, 10 GHz,
     lambda/8, up to 8 bounces, HH/HV/VH/VV): the tree is built once (its
     time reported), each step is the whole 360-angle sweep (ray generation,
-    every bounce, PO, RCS).  Roofline of the trace kernel as for the
-    trihedral, priced on the oracle's SAH tree of the aircraft."""
+    every bounce, PO, RCS).  Roofline of the trace kernel priced on the
+    oracle's SAH tree of the aircraft."""
     import torch
     import sbr_inputs as si
     from paper_2604_09243_amd import Context
@@ -554,7 +624,7 @@ def bench_aircraft(args):
     def step():
         A, S, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
                                  samples_per_lambda=w.samples_per_lambda, flags=mask_flag(args), tune=tune)
-        return st
+        return A, st
 
     for _ in range(args.warmup):
         step()
@@ -562,7 +632,8 @@ def bench_aircraft(args):
     stats = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        stats.append(step())
+        A, st = step()
+        stats.append(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     queries = sum(s["queries"] for s in stats)
@@ -573,6 +644,7 @@ def bench_aircraft(args):
     masked = sum(s["masked"] for s in stats)
     work = priced_work(q_b, masked, nb, REF_VISITS_AIRCRAFT, REF_VISITS_AIRCRAFT_UNMASKED, not args.no_mask)
     t_kernel = sum(s["ms_trace"] for s in stats) * 1e-3
+    launches = sum(s["chunks"] for s in stats)
     out = {
         "metric": METRIC, "value": queries / dt, "unit": "rays*bounces/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -582,18 +654,29 @@ def bench_aircraft(args):
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
                    "bvh": args.builder, "primary_mask": not args.no_mask, "polarisations": "HH,HV,VH,VV",
                    "tune": (tune if tune is not None else sbr_default_tune()).as_dict()},
+        # the queries that traversed the tree: the mask's primary-ray misses left out
+        "value_traced": (queries - masked) / dt,
         "autotune_s": tune_s,
         "masked_rays_per_step": masked / args.steps,
         "angles_per_s": w.n_angles * args.steps / dt,
         "trace_ms_per_step": 1e3 * t_kernel / args.steps,
         "po_ms_per_step": sum(s["ms_po"] for s in stats) / args.steps,
         "build_ms_once": build_ms,
+        "angles_per_s_build_amortised": w.n_angles / (dt / args.steps + build_ms * 1e-3),
         "trace_queries_per_s": queries / t_kernel,
+        "angles_per_s_gpu": w.n_angles * args.steps / (sum(s["ms_trace"] + s["ms_po"] for s in stats) * 1e-3),
         "roofline": {"bound": "alu", "achieved": work / t_kernel / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlaneop/s", "frac": work / t_kernel / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "k_stream<0> (all bounces, angle grid)",
-                     "avg_launch_ms": 1e3 * t_kernel / args.steps, "work_per_launch_lane_ops": work / args.steps},
+                     "unit": "Tlaneop/s", "frac": work / t_kernel / PEAK_LANE_OPS,
+                     "traffic": pmc_traffic("k_stream", args.builder, "aircraft"),
+                     "kernel": "k_stream<0> (all bounces of a chunk of angles, angle grid)", "launches": launches,
+                     "avg_launch_ms": 1e3 * t_kernel / launches, "work_per_launch_lane_ops": work / launches,
+                     "pricing": "per query: box tests x %d + triangle tests x %d + %d, visit counts of the oracle's "
+                                "SAH tree" % (C_BOX, C_TRI, C_BOUNCE)},
     }
+    if not args.no_cpu_baseline:
+        cb, parity = cpu_baseline_aircraft(w, A.cpu().numpy(), args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["parity_sample"] = parity
     print(json.dumps(out), flush=True)
 
 

@@ -37,8 +37,8 @@
 extern "C" {
 #endif
 
-#define SBR_ABI_VERSION 1
-#define SBR_MAX_BOUNCES 64
+#define SBR_ABI_VERSION 2
+#define SBR_MAX_BOUNCES 127
 
 typedef struct sbr_ctx sbr_ctx; /* device + stream + workspace */
 typedef struct sbr_bvh sbr_bvh; /* prepared mesh + BVH in device memory */
@@ -85,6 +85,9 @@ enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
                                          the projected leaf boxes of the tree (with a margin above
                                          the box test's float32 rounding), resolves rays of empty
                                          cells as misses without traversal; results are identical */
+#define SBR_OPT_FP32_PATH 128         /* precision study of Sec. 6, not the method: the path P, the
+                                         distance D and the phase k D in float32 instead of float64
+                                         (sbr_trace and sbr_rcs_sweep; batches refuse it) */
 
 /* ------------------------------------------------------------------------ */
 /* Library and context                                                       */
@@ -242,13 +245,22 @@ typedef struct {
                         visits, triangle tests (summed over queries), and wave-level trips of the
                         node loop, the leaf step and the bounce loop */
     int64_t masked;  /* primary rays resolved as misses by the mask (included in queries) */
+    int64_t chunks;  /* trace launches of the streaming schedule (one per chunk of angles or items) */
 } sbr_stats;
 
-/* Traces n_rays rays (1 <= n_rays < 2^31) for up to max_bounces (1..64)
- * reflections.  Closest hit = smallest (t, input triangle index); triangles
- * are two-sided, the previous triangle is skipped, each new origin is
- * x + eps * (facing normal).  Errors: INVALID_ARG, OOM, HIP.  stats (host,
- * nullable) implies a synchronisation. */
+/* Traces n_rays rays (1 <= n_rays < 2^31) for up to max_bounces (1..SBR_MAX_BOUNCES)
+ * reflections (Algorithm 2, Sec. 4).  A triangle is hit when the float32
+ * Moller-Trumbore test accepts it (u >= 0, v >= 0, u + v <= 1, 0 < t) and
+ * the float32 hit point o + t d lies in the triangle's axis-aligned box
+ * widened by P = fl32(2^-20 M) on every side, with M = X + C + 1.5 |diag|
+ * (X: largest |coordinate| of the mesh's bounding box, C: that of its
+ * centre); the second condition refuses only hits whose float32 point has
+ * drifted off the triangle (slivers seen from afar, grazing rays).  Closest
+ * hit = smallest (t, input triangle index) over every triangle, whichever
+ * BVH builder made the tree; triangles are two-sided, the previous triangle
+ * is skipped, each new origin is x + eps * (facing normal).  Any origin is
+ * accepted; directions are expected near unit length.  Errors: INVALID_ARG,
+ * OOM, HIP.  stats (host, nullable) implies a synchronisation. */
 int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays, int max_bounces,
               const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats);
 
@@ -303,7 +315,7 @@ typedef struct {
     int64_t n_angles;        /* 1 .. 2^24 */
     const double *freqs_hz;  /* host [n_freq] */
     int32_t n_freq;          /* 1 .. 4096 */
-    int32_t max_bounces;     /* 1 .. 64 */
+    int32_t max_bounces;     /* 1 .. SBR_MAX_BOUNCES */
     double ds;               /* ray spacing (m); 0 = c / (f_max * samples_per_lambda) */
     double samples_per_lambda;
     double eta;              /* aperture margin of Eq. L2 (0.1 if negative) */
@@ -360,7 +372,7 @@ typedef struct {
     int64_t n_items;             /* 1 .. 2^24 */
     const double *freqs_hz;      /* host [n_freqs_total] */
     int64_t n_freqs_total;
-    int32_t max_bounces;         /* 1 .. 64 */
+    int32_t max_bounces;         /* 1 .. SBR_MAX_BOUNCES */
     int32_t mode;                /* SBR_MODE_* */
     uint32_t flags;              /* SBR_OPT_* */
     int32_t reserved;

@@ -22,6 +22,7 @@ F_VALID, F_TRAPPED, F_BACK_LAST, F_EDGE = 1, 2, 4, 8
 MODE_VECTOR, MODE_PAPER = 0, 1
 _USE_BVH, _DROP_TRAPPED, _PAPER_PATH, _EDGE_DIAG = 1, 2, 4, 8
 _FP32_PATH = 16  # precision study only: path, D and phase in float32
+_MT_ONLY = 32    # brute force without the hit rule's box test (to show what the rule refuses)
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -162,11 +163,13 @@ def gen_rays(bbox, theta_deg, phi_deg, ds, eta=0.1):
 
 
 def trace(mesh, o, d, eH0, eV0, k, bmax, use_bvh=False, drop_trapped=False, paper_path=False,
-          edge_diag=False, want_path=False, fp32_path=False):
+          edge_diag=False, want_path=False, fp32_path=False, mt_only=False):
     """Algorithm 2 for every ray.  ``d`` may be one direction for all rays or
     one per ray.  Returns a dict of per-ray arrays and counters.
     ``fp32_path``: accumulate P and form D in float32 (the single-precision
-    variant whose phase error Sec. 6 discusses; a study, not the method)."""
+    variant whose phase error Sec. 6 discusses; a study, not the method).
+    ``mt_only``: brute force with the Moller-Trumbore conditions alone, without
+    the hit rule's box test (a study of what the rule refuses)."""
     o = np.ascontiguousarray(o, dtype=np.float32).reshape(-1, 3)
     n = len(o)
     d = np.asarray(d, dtype=np.float32)
@@ -189,7 +192,9 @@ def trace(mesh, o, d, eH0, eV0, k, bmax, use_bvh=False, drop_trapped=False, pape
     out.tri_path = _ptr(r["tri_path"], _ip) if want_path else None
     opts = ((_USE_BVH if use_bvh else 0) | (_DROP_TRAPPED if drop_trapped else 0)
             | (_PAPER_PATH if paper_path else 0) | (_EDGE_DIAG if edge_diag else 0)
-            | (_FP32_PATH if fp32_path else 0))
+            | (_FP32_PATH if fp32_path else 0) | (_MT_ONLY if mt_only else 0))
+    if mt_only and use_bvh:
+        raise ValueError("mt_only is a brute-force study option")
     if use_bvh and mesh.n_nodes == 0:
         mesh.build_bvh()
     rc = lib().orc_trace(mesh._h, n, _ptr(o, _fp), _ptr(d, _fp), _ptr(eH0, _dp), _ptr(eV0, _dp),

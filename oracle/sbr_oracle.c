@@ -27,6 +27,18 @@
  * -ffp-contract=off), because that arithmetic decides integers (which
  * triangle is hit, how many bounces) and the HIP path must take the same
  * decisions.  Path length, polarisation and the PO sum are float64.
+ *
+ * Hit rule (a reading: the paper fixes no rounding).  A triangle is hit when
+ * the float32 Moller-Trumbore test accepts it AND the float32 hit point
+ * x = o + t d lies inside the triangle's axis-aligned box widened by
+ * P = fl32(2^-20 M) on every side, M = X + C + 1.5 |diag| (X = largest
+ * |coordinate| of the scene's box, C = that of its centre): every ray
+ * origin and hit point of a sweep lies within M.  The widening is about 16
+ * float32 units of that scale, many times the rounding of a well
+ * conditioned test; only hits whose float32 point has drifted off the
+ * triangle (grazing rays, slivers seen from afar) are refused, and the
+ * closest hit is then a minimum that a bounding-volume tree can find
+ * exactly.
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,6 +67,9 @@
  * path P and form D in float32 (orc_trace), and form the phase k D in float32
  * (orc_po, or-ed into mode). */
 #define ORC_FP32_PATH 16
+/* Brute force with the Moller-Trumbore conditions only (no box rule), to
+ * show which hits the rule refuses; not the method. */
+#define ORC_MT_ONLY 32
 
 typedef struct {
     float lo[3], hi[3];
@@ -69,6 +84,8 @@ typedef struct {
     double bbox[6];
     double diag;
     float eps;
+    float pbox;  /* the hit rule's widening P */
+    double xmax; /* largest |coordinate| of any widened triangle box */
     int64_t n_degen;
     /* optional BVH (fast mode) */
     orc_node *nodes;
@@ -116,6 +133,17 @@ orc_mesh *orc_mesh_new(const float *V, int64_t nv, const int32_t *T, int64_t nt,
     m->diag = sqrt((dx * dx + dy * dy) + dz * dz);
     /* offset distance: 1e-5 of the scene diagonal (the paper leaves its value open) */
     m->eps = (float)(1e-5 * m->diag);
+    /* hit rule widening P = fl32(2^-20 M), M = (X + C) + 1.5 |diag| */
+    {
+        double X = 0.0, C = 0.0;
+        for (int a = 0; a < 3; a++) {
+            X = fmax(X, fmax(fabs(lo[a]), fabs(hi[a])));
+            C = fmax(C, fabs(0.5 * (lo[a] + hi[a])));
+        }
+        double M = (X + C) + 1.5 * m->diag;
+        m->pbox = (float)(M * 0x1p-20);
+        m->xmax = X + 2.0 * (double)m->pbox;
+    }
     double amin = 1e-12 * m->diag * m->diag;
 
     for (int64_t j = 0; j < nt; j++) {
@@ -201,9 +229,26 @@ int64_t orc_mesh_leaf_boxes(const orc_mesh *m, double *out, int64_t cap)
 /* BVH of Algorithm 1 (fast mode): median split or binned SAH                 */
 /* ------------------------------------------------------------------------ */
 
+/* The hit rule's box of triangle j: the box of its float32 corners v0,
+ * v0 + e1, v0 + e2 (each sum rounded to float32), widened by P, in float32. */
+static void rule_box(const orc_mesh *m, int64_t j, float lo[3], float hi[3])
+{
+    const float *v0 = m->v0 + 3 * j, *e1 = m->e1 + 3 * j, *e2 = m->e2 + 3 * j;
+    for (int a = 0; a < 3; a++) {
+        float p1 = v0[a] + e1[a], p2 = v0[a] + e2[a];
+        float mn = v0[a], mx = v0[a];
+        if (p1 < mn) mn = p1;
+        if (p2 < mn) mn = p2;
+        if (p1 > mx) mx = p1;
+        if (p2 > mx) mx = p2;
+        lo[a] = mn - m->pbox;
+        hi[a] = mx + m->pbox;
+    }
+}
+
 typedef struct {
     const orc_mesh *m;
-    float *tlo, *thi; /* per-triangle boxes (padded) */
+    float *tlo, *thi; /* per-triangle boxes of the hit rule */
     float *cen;       /* centroids */
     int32_t *idx;     /* working permutation */
     orc_node *nodes;
@@ -340,8 +385,9 @@ static int32_t build_rec(bvh_build *B, int32_t first, int32_t count, int depth)
     return id;
 }
 
-/* rule: 0 = median split, 1 = binned SAH.  Boxes are padded by pad so the
- * box test never culls a triangle the float32 intersection test accepts. */
+/* rule: 0 = median split, 1 = binned SAH.  A triangle's box is exactly the
+ * widened box of the hit rule, so every accepted hit point lies inside the
+ * box of each node above its triangle. */
 int orc_mesh_build_bvh(orc_mesh *m, int rule, int nleaf, int nbins)
 {
     free_bvh(m);
@@ -363,15 +409,12 @@ int orc_mesh_build_bvh(orc_mesh *m, int rule, int nleaf, int nbins)
     B.nleaf = nleaf;
     B.nbins = nbins;
     B.rule = rule;
-    float pad = (float)(1e-6 * m->diag) + 1e-30f;
     int64_t w = 0;
     for (int64_t j = 0; j < nt; j++) {
+        rule_box(m, j, B.tlo + 3 * j, B.thi + 3 * j);
         const float *v0 = m->v0 + 3 * j, *e1 = m->e1 + 3 * j, *e2 = m->e2 + 3 * j;
         for (int a = 0; a < 3; a++) {
             double p0 = v0[a], p1 = (double)v0[a] + e1[a], p2 = (double)v0[a] + e2[a];
-            double lo = fmin(p0, fmin(p1, p2)), hi = fmax(p0, fmax(p1, p2));
-            B.tlo[3 * j + a] = (float)lo - pad - fabsf((float)lo) * 1e-6f;
-            B.thi[3 * j + a] = (float)hi + pad + fabsf((float)hi) * 1e-6f;
             B.cen[3 * j + a] = (float)((p0 + p1 + p2) / 3.0);
         }
         if (!m->degen[j]) B.idx[w++] = (int32_t)j;
@@ -498,9 +541,30 @@ typedef struct {
     int64_t box_tests, tri_tests;
 } orc_count;
 
+/* The hit rule's second condition: the float32 hit point o + t d (the point
+ * the bounce update uses) inside the triangle's widened box. */
+static inline int point_in_rule_box(const orc_mesh *m, int64_t j, const float o[3], const float d[3], float t)
+{
+    float lo[3], hi[3];
+    rule_box(m, j, lo, hi);
+    for (int a = 0; a < 3; a++) {
+        float x = o[a] + t * d[a];
+        if (!(x >= lo[a] && x <= hi[a])) return 0;
+    }
+    return 1;
+}
+
+static inline int rule_hit(const orc_mesh *m, int64_t j, const float o[3], const float d[3], float *t_out)
+{
+    float t;
+    if (!tri_hit(m, j, o, d, &t) || !point_in_rule_box(m, j, o, d, t)) return 0;
+    *t_out = t;
+    return 1;
+}
+
 /* Every triangle, in increasing id order; ties on t keep the smaller id. */
 static int32_t closest_brute(const orc_mesh *m, const float o[3], const float d[3], int32_t skip,
-                             float *tbest, orc_count *cnt)
+                             float *tbest, orc_count *cnt, int mt_only)
 {
     float best = INFINITY;
     int32_t bj = -1;
@@ -508,7 +572,7 @@ static int32_t closest_brute(const orc_mesh *m, const float o[3], const float d[
         if (m->degen[j] || j == skip) continue;
         float t;
         cnt->tri_tests++;
-        if (tri_hit(m, j, o, d, &t) && t < best) {
+        if ((mt_only ? tri_hit(m, j, o, d, &t) : rule_hit(m, j, o, d, &t)) && t < best) {
             best = t;
             bj = (int32_t)j;
         }
@@ -517,17 +581,19 @@ static int32_t closest_brute(const orc_mesh *m, const float o[3], const float d[
     return bj;
 }
 
-/* Slab test in float64 against a padded box, accepting entries up to a
- * relative 1e-6 beyond the current best t so equal-t ties are still seen. */
-static int box_hit(const orc_node *nd, const double o[3], const double d[3], double tmax_in, double *tenter)
+/* Slab test in float64 against a node box widened by E on every side; the
+ * interval is clipped to [0, tmax_in]. */
+static int box_hit(const orc_node *nd, const double o[3], const double d[3], double E, double tmax_in,
+                   double *tenter)
 {
     double tmin = 0.0, tmax = tmax_in;
     for (int a = 0; a < 3; a++) {
+        double lo = (double)nd->lo[a] - E, hi = (double)nd->hi[a] + E;
         if (d[a] == 0.0) {
-            if (o[a] < nd->lo[a] || o[a] > nd->hi[a]) return 0;
+            if (o[a] < lo || o[a] > hi) return 0;
             continue;
         }
-        double t0 = (nd->lo[a] - o[a]) / d[a], t1 = (nd->hi[a] - o[a]) / d[a];
+        double t0 = (lo - o[a]) / d[a], t1 = (hi - o[a]) / d[a];
         if (t0 > t1) { double x = t0; t0 = t1; t1 = x; }
         if (t0 > tmin) tmin = t0;
         if (t1 < tmax) tmax = t1;
@@ -536,6 +602,13 @@ static int box_hit(const orc_node *nd, const double o[3], const double d[3], dou
     return tmin <= tmax;
 }
 
+/* The same minimum as closest_brute, through the tree.  An accepted hit at t
+ * has its float32 point x inside every box above its triangle, and the exact
+ * point o + t d lies within 2^-24 (2 |x| + |o|) of x on each axis, less than
+ * E = 2^-21 (xmax + |o|); the float64 slab test of the box widened by E
+ * (rounding near 2^-52 of the same magnitudes) therefore meets the exact
+ * point, so a box is skipped only when it holds no accepted hit with t at
+ * most the best one so far (ties included: the entry is compared with >). */
 static int32_t closest_bvh(const orc_mesh *m, const float o[3], const float d[3], int32_t skip,
                            float *tbest, orc_count *cnt)
 {
@@ -543,12 +616,13 @@ static int32_t closest_bvh(const orc_mesh *m, const float o[3], const float d[3]
     int32_t bj = -1;
     if (m->n_nodes == 0) { *tbest = best; return -1; }
     double od[3] = {o[0], o[1], o[2]}, dd[3] = {d[0], d[1], d[2]};
-    double slack = 1e-6 * m->diag;
+    double om = fmax(fabs(od[0]), fmax(fabs(od[1]), fabs(od[2])));
+    double E = 0x1p-21 * (m->xmax + om);
     int32_t stack[256];
     int sp = 0;
     double te;
     cnt->box_tests++;
-    if (!box_hit(&m->nodes[0], od, dd, INFINITY, &te)) { *tbest = best; return -1; }
+    if (!box_hit(&m->nodes[0], od, dd, E, INFINITY, &te)) { *tbest = best; return -1; }
     stack[sp++] = 0;
     while (sp > 0) {
         int32_t ni = stack[--sp];
@@ -559,24 +633,18 @@ static int32_t closest_bvh(const orc_mesh *m, const float o[3], const float d[3]
                 if (j == skip) continue;
                 float t;
                 cnt->tri_tests++;
-                if (tri_hit(m, j, o, d, &t) && (t < best || (t == best && j < bj))) {
+                if (rule_hit(m, j, o, d, &t) && (t < best || (t == best && j < bj))) {
                     best = t;
                     bj = j;
                 }
             }
             continue;
         }
-        /* A box is skipped only when it starts beyond the best hit by more than
-         * 2^-11 of its distance (plus the box padding): the float32
-         * intersection t of an ill-conditioned triangle (a sliver seen from
-         * far away) can fall short of the triangle's own padded box, by
-         * 7e-6 of t on the aircraft's symmetry seam, so a tighter margin
-         * would let the visiting order decide which of two hits is kept. */
-        double lim = (best < INFINITY) ? (double)best * (1.0 + 0x1p-11) + slack : INFINITY;
+        double lim = (double)best;
         double tl, tr;
         cnt->box_tests += 2;
-        int hl = box_hit(&m->nodes[nd->left], od, dd, lim, &tl);
-        int hr = box_hit(&m->nodes[nd->right], od, dd, lim, &tr);
+        int hl = box_hit(&m->nodes[nd->left], od, dd, E, lim, &tl);
+        int hr = box_hit(&m->nodes[nd->right], od, dd, E, lim, &tr);
         /* push the far child first so the near one is visited next */
         if (hl && hr) {
             if (tl <= tr) { stack[sp++] = nd->right; stack[sp++] = nd->left; }
@@ -645,7 +713,7 @@ int orc_trace(const orc_mesh *m, int64_t n, const float *o_in, const float *d_in
               const double eH0[3], const double eV0[3], const double k[3], int bmax, int opts,
               orc_trace_out *out)
 {
-    if (bmax < 1 || bmax > 64) return -1;
+    if (bmax < 1 || bmax > 127) return -1;
     if ((opts & ORC_USE_BVH) && m->n_nodes == 0 && m->nt > 0) return -1;
     int64_t q_tot = 0, box_tot = 0, tri_tot = 0, edge_tot = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : q_tot, box_tot, tri_tot, edge_tot)
@@ -665,7 +733,7 @@ int orc_trace(const orc_mesh *m, int64_t n, const float *o_in, const float *d_in
             float t;
             queries++;
             int32_t j = (opts & ORC_USE_BVH) ? closest_bvh(m, o, d, prev, &t, &cnt)
-                                             : closest_brute(m, o, d, prev, &t, &cnt);
+                                             : closest_brute(m, o, d, prev, &t, &cnt, (opts & ORC_MT_ONLY) != 0);
             if ((opts & ORC_EDGE_DIAG) && edge_ambiguous(m, o, d, prev, t, j)) edge = 1;
             if (j < 0) break;
             float x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
@@ -717,7 +785,7 @@ int orc_trace(const orc_mesh *m, int64_t n, const float *o_in, const float *d_in
             float t;
             queries++;
             int32_t j = (opts & ORC_USE_BVH) ? closest_bvh(m, o, d, prev, &t, &cnt)
-                                             : closest_brute(m, o, d, prev, &t, &cnt);
+                                             : closest_brute(m, o, d, prev, &t, &cnt, (opts & ORC_MT_ONLY) != 0);
             if (j >= 0) flags = (flags | ORC_F_TRAPPED) & ~ORC_F_VALID;
         }
         if (edge) flags |= ORC_F_EDGE;

@@ -309,7 +309,7 @@ void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p)
     p.rec_base = 0;
     p.root = 0;
     p.eps = 0.f;
-    p.slack = 0.f;
+    p.pbox = 0.f;
     p.mcu = 0;
     p.mask_base = 0;
     p.mwork_base = 0;
@@ -329,6 +329,26 @@ void mask_plan(AnglePlan &p, const double bbox[6], int64_t node_cnt)
     for (int i = 0; i < 3; ++i) r += std::max(std::fabs(bbox[i]), std::fabs(bbox[3 + i]));
     const double ro = std::fabs(p.uc) + std::fabs(p.vc) + std::fabs(p.s0) + 0.5 * (double(p.nu) + p.nv) * p.ds;
     p.mslack = static_cast<float>(0.5 + 64.0 * 0x1p-24 * (r + ro) / p.ds);
+}
+
+int scene_plan(AnglePlan &p, int32_t root, float eps, const double bbox[6], double diag, int64_t node_cnt)
+{
+    const SceneScale sc = scene_scale(bbox, diag);
+    p.root = root;
+    p.eps = eps;
+    p.pbox = sc.pbox;
+    mask_plan(p, bbox, node_cnt);
+    // origins are affine in (i, j): the grid's corners bound them
+    double om = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const double i = (c & 1) ? p.nu - 1 : 0, j = (c & 2) ? p.nv - 1 : 0;
+        const double ui = p.uc + ((i + 0.5) - 0.5 * static_cast<double>(p.nu)) * p.ds;
+        const double vj = p.vc + ((j + 0.5) - 0.5 * static_cast<double>(p.nv)) * p.ds;
+        for (int a = 0; a < 3; ++a) om = std::max(om, std::fabs((ui * p.u[a] + vj * p.v[a]) + p.s0 * p.k[a]));
+    }
+    if (!(om <= sc.obound * (1.0 - 0x1p-20)))
+        return fail(SBR_ERR_SAMPLING, "ray spacing too coarse for the scene: aperture origins beyond its rounding bound");
+    return SBR_OK;
 }
 
 void mask_layout(AnglePlan *plans, int64_t a0, int64_t a1, int64_t &bytes, int64_t &units)
@@ -362,8 +382,10 @@ int log2i(int x)
     return s;
 }
 
-void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped)
+void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped,
+                int64_t chunks)
 {
+    st->chunks += chunks;
     st->queries += static_cast<int64_t>(hstat[0]);
     st->trapped += static_cast<int64_t>(hstat[1]);
     for (int b = 1; b <= bmax && b <= SBR_MAX_BOUNCES; ++b) st->hits[b] += static_cast<int64_t>(hstat[8 + b]);
@@ -516,7 +538,8 @@ extern "C" int sbr_bvh_validate(const sbr_bvh *bvh)
     std::vector<BTri> ht(static_cast<size_t>(bvh->n_live));
     SBR_HIP(hipMemcpy(hn.data(), bvh->nodes, sizeof(BNode) * hn.size(), hipMemcpyDeviceToHost));
     SBR_HIP(hipMemcpy(ht.data(), bvh->tris, sizeof(BTri) * ht.size(), hipMemcpyDeviceToHost));
-    return validate_layout(hn, static_cast<int>(bvh->n_live), bvh->leaf_size, bvh->depth, &ht, bvh->n_tris);
+    const SceneScale sc = scene_scale(bvh->bbox, bvh->diag);
+    return validate_layout(hn, static_cast<int>(bvh->n_live), bvh->leaf_size, bvh->depth, &ht, bvh->n_tris, &sc);
 }
 
 extern "C" int sbr_bvh_quality_of(const sbr_bvh *bvh, sbr_bvh_quality *out)
@@ -560,7 +583,7 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
         return fail(SBR_ERR_INVALID_ARG, "sbr_trace: rays->o, d, eH and eV are required");
     if (n_rays < 1 || n_rays > 2147483647LL) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: n_rays out of range");
     if (max_bounces < 1 || max_bounces > SBR_MAX_BOUNCES)
-        return fail(SBR_ERR_INVALID_ARG, "sbr_trace: max_bounces must be in [1, 64]");
+        return fail(SBR_ERR_INVALID_ARG, "sbr_trace: max_bounces must be in [1, " + std::to_string(SBR_MAX_BOUNCES) + "]");
     uint32_t flags = 0;
     double k[3] = {0, 0, -1};
     if (opts) {
@@ -617,7 +640,8 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
         if (want_stats) {
             std::memset(stats, 0, sizeof(*stats));
             stats->rays = n_rays;
-            fill_stats(stats, hstat, max_bounces, n_rays, (flags & SBR_OPT_DROP_TRAPPED) != 0);
+            fill_stats(stats, hstat, max_bounces, n_rays, (flags & SBR_OPT_DROP_TRAPPED) != 0,
+                       sched == kScheduleStream ? 1 : 0);
             const int nl = sched == kScheduleStream ? 1 : max_bounces;
             for (int b = 1; b <= nl; ++b) {
                 float ms = 0;
@@ -747,7 +771,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     if (sw->n_freq < 1 || sw->n_freq > 4096)
         return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: n_freq must be in [1, 4096]");
     if (sw->max_bounces < 1 || sw->max_bounces > SBR_MAX_BOUNCES)
-        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: max_bounces must be in [1, 64]");
+        return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: max_bounces must be in [1, " + std::to_string(SBR_MAX_BOUNCES) + "]");
     if (sw->mode != SBR_MODE_VECTOR && sw->mode != SBR_MODE_PAPER)
         return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: unknown mode");
     if (bvh->device != ctx->device) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: BVH lives on another device");
@@ -797,10 +821,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         if (ap.nu * ap.nv > (int64_t(1) << 31) - 1) return fail(SBR_ERR_OVERFLOW, "sbr_rcs_sweep: too many rays per angle");
         AnglePlan &p = plans[a];
         fill_plan(ap, ds, tw, p);
-        p.root = 0;
-        p.eps = bvh->eps;
-        p.slack = box_slack(bvh->diag);
-        mask_plan(p, bvh->bbox, bvh->n_nodes);
+        if ((rc = scene_plan(p, 0, bvh->eps, bvh->bbox, bvh->diag, bvh->n_nodes))) return rc;
         PoAngle &q = pang[a];
         for (int i = 0; i < 3; ++i) {
             q.basis[i] = ap.k_hat[i];
@@ -968,6 +989,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         pa.mode = sw->mode;
         pa.kf = static_cast<const double *>(dkf);
         pa.partial = static_cast<long long *>(dpart);
+        pa.fp32 = (sw->flags & SBR_OPT_FP32_PATH) ? 1 : 0;
         if ((rc = launch_po(s, pa))) return rc;
         if ((rc = launch_po_finalize(s, pa, A_out, sigma_dbsm))) return rc;
         if (want_stats) {
@@ -981,7 +1003,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     if (want_stats) {
         for (int c = 0; c < n_chunks; ++c) {
             fill_stats(stats, hstat.data() + static_cast<size_t>(kStatU64) * c, bm, chunk_rays[c],
-                       (sw->flags & SBR_OPT_DROP_TRAPPED) != 0);
+                       (sw->flags & SBR_OPT_DROP_TRAPPED) != 0, sched == kScheduleStream ? 1 : 0);
             const int nl = sched == kScheduleStream ? 1 : bm;
             for (int b = 1; b <= nl; ++b) {
                 float t = 0;

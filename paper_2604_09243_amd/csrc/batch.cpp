@@ -112,16 +112,17 @@ namespace {
 
 struct SceneView {
     int32_t root;
-    float eps, slack;
+    float eps;
+    double diag;
     const double *bbox;
     int64_t n_nodes;
 };
 
 SceneView scene_view(const sbr_bvh *b, int s)
 {
-    if (b->scenes.empty()) return SceneView{0, b->eps, box_slack(b->diag), b->bbox, b->n_nodes};
+    if (b->scenes.empty()) return SceneView{0, b->eps, b->diag, b->bbox, b->n_nodes};
     const SceneInfo &si = b->scenes[s];
-    return SceneView{si.root, si.eps, box_slack(si.diag), si.bbox, si.n_nodes};
+    return SceneView{si.root, si.eps, si.diag, si.bbox, si.n_nodes};
 }
 
 int n_scenes(const sbr_bvh *b) { return b->scenes.empty() ? 1 : static_cast<int>(b->scenes.size()); }
@@ -156,10 +157,8 @@ int plan_batch(sbr_batch *b)
         const SceneView sv = scene_view(bv, it.scene);
         AnglePlan &p = plans[i];
         fill_plan(ap, b->ds[i], tw, p);
-        p.root = sv.root;
-        p.eps = sv.eps;
-        p.slack = sv.slack;
-        mask_plan(p, sv.bbox, sv.n_nodes);
+        int rc;
+        if ((rc = scene_plan(p, sv.root, sv.eps, sv.bbox, sv.diag, sv.n_nodes))) return rc;
         PoAngle &q = ang[i];
         for (int k = 0; k < 3; ++k) {
             q.basis[k] = ap.k_hat[k];
@@ -466,7 +465,7 @@ extern "C" int sbr_batch_create(sbr_ctx *ctx, const sbr_bvh *scenes, const sbr_b
     if (!d->freqs_hz || d->n_freqs_total < 1 || d->n_freqs_total > 2147483647LL)
         return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: empty frequency array");
     if (d->max_bounces < 1 || d->max_bounces > SBR_MAX_BOUNCES)
-        return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: max_bounces must be in [1, 64]");
+        return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: max_bounces must be in [1, " + std::to_string(SBR_MAX_BOUNCES) + "]");
     if (d->mode != SBR_MODE_VECTOR && d->mode != SBR_MODE_PAPER)
         return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: unknown mode");
     if (scenes->device != ctx->device) return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: scenes on another device");
@@ -480,6 +479,8 @@ extern "C" int sbr_batch_create(sbr_ctx *ctx, const sbr_bvh *scenes, const sbr_b
             return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: tune->struct_size too small");
         tune = *d->tune;
     }
+    if (d->flags & SBR_OPT_FP32_PATH)
+        return fail(SBR_ERR_UNSUPPORTED, "sbr_batch_create: SBR_OPT_FP32_PATH is a study option of sweeps and traces");
     if (d->flags & SBR_OPT_WAVEFRONT) tune.schedule = kScheduleWavefront;
     int rc = normalize_tune(tune);
     if (rc) return rc;
@@ -612,7 +613,8 @@ extern "C" int sbr_batch_run(sbr_batch *b, double *A_out, double *sigma_dbsm, sb
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->rays = b->rays;
-        fill_stats(stats, b->h_stat, b->bmax, b->rays, (b->flags & SBR_OPT_DROP_TRAPPED) != 0);
+        fill_stats(stats, b->h_stat, b->bmax, b->rays, (b->flags & SBR_OPT_DROP_TRAPPED) != 0,
+                   b->tune.schedule == kScheduleStream ? n_chunks : 0);
         stats->angles = static_cast<int64_t>(b->items.size());
         if (eager) {
             for (int c = 0; c < n_chunks; ++c) {

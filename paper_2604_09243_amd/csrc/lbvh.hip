@@ -263,29 +263,30 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, int n, int *__restri
     if (i == 0) parent_int[0] = -1;
 }
 
-// Padded box of the triangle at sorted position j.
+// Box of the triangle at sorted position j: the hit rule's box (widened by
+// P) widened by the guard G (SceneScale).
 __device__ inline void leaf_box(const uint32_t *__restrict__ order, const float *__restrict__ v0,
-                                const float *__restrict__ e1, const float *__restrict__ e2, float pad, int j,
+                                const float *__restrict__ e1, const float *__restrict__ e2, float P, float G, int j,
                                 float *lo, float *hi)
 {
     const int li = static_cast<int>(order[j]);
     const float *a = v0 + 3 * li, *b = e1 + 3 * li, *c = e2 + 3 * li;
     for (int k = 0; k < 3; ++k) {
-        const float p0 = a[k], p1 = a[k] + b[k], p2 = a[k] + c[k];
-        const float l = fminf(p0, fminf(p1, p2)), h = fmaxf(p0, fmaxf(p1, p2));
-        lo[k] = l - pad - fabsf(l) * 4e-7f;
-        hi[k] = h + pad + fabsf(h) * 4e-7f;
+        float l, h;
+        spec_box_axis(a[k], b[k], c[k], P, l, h);
+        lo[k] = l - G;
+        hi[k] = h + G;
     }
 }
 
-// Padded leaf boxes in sorted order: lbox[6 j ..] = lo xyz, hi xyz.
+// Leaf boxes in sorted order: lbox[6 j ..] = lo xyz, hi xyz.
 __global__ void k_leaf_boxes(int n, const uint32_t *__restrict__ order, const float *__restrict__ v0,
-                             const float *__restrict__ e1, const float *__restrict__ e2, float pad,
+                             const float *__restrict__ e1, const float *__restrict__ e2, float P, float G,
                              float *__restrict__ lbox)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    leaf_box(order, v0, e1, e2, pad, j, lbox + 6 * j, lbox + 6 * j + 3);
+    leaf_box(order, v0, e1, e2, P, G, j, lbox + 6 * j, lbox + 6 * j + 3);
 }
 
 // Triangles and their normals at their leaf slots: the triangle at sorted
@@ -1032,8 +1033,8 @@ int build_front(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, bool cubic, 
         (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nrm_slot), sizeof(float4) * n)) ||
         (rc = tmp.alloc(&f.lbox, 6 * static_cast<size_t>(n))))
         return rc;
-    const float pad = static_cast<float>(1e-6 * pm.diag) + 1e-30f;
-    k_leaf_boxes<<<blocks_for(n, 256), 256, 0, s>>>(n, f.order, f.v0, f.e1, f.e2, pad, f.lbox);
+    const SceneScale scl = scene_scale(pm.bbox, pm.diag);
+    k_leaf_boxes<<<blocks_for(n, 256), 256, 0, s>>>(n, f.order, f.v0, f.e1, f.e2, scl.pbox, scl.guard, f.lbox);
     SBR_HIP(hipGetLastError());
     if (n <= leaf_max) {
         k_place<<<blocks_for(n, 256), 256, 0, s>>>(n, f.order, nullptr, f.v0, f.e1, f.e2, f.nrm, f.ids, bvh->tris,

@@ -42,6 +42,7 @@ struct PoP {
     int mode;
     const double *kf;
     long long *partial;
+    int fp32;  // precision study: phase = fl32(fl32(k) fl32(D)), one sine and cosine per frequency
 };
 
 template <int CTRL>
@@ -112,6 +113,13 @@ __device__ __forceinline__ void sincos_pi(double x, double &so, double &co)
     const double a = odd ? cs : sn, b = odd ? sn : cs;
     so = (qi & 2) ? -a : a;
     co = ((qi + 1) & 2) ? -b : b;
+}
+
+// The precision study's single-precision phase: k and D rounded to float32,
+// their product rounded to float32.
+__device__ __forceinline__ double phase32(double k, double D)
+{
+    return static_cast<double>(static_cast<float>(k) * static_cast<float>(D));
 }
 
 // sin and cos of the phase ph (any size; float64): ph reduced by the nearest
@@ -199,7 +207,8 @@ __device__ __forceinline__ void po_passes(const PoP &p, const PoAngle &A, int64_
     long long *out = p.partial + (A.part_base + c * nf) * 8;
     const int64_t r0i = c * kPoRecsPerBlock;
     const int64_t r1i = tid < kPoThreads ? min(r0i + kPoRecsPerBlock, A.rec_cnt) : r0i;
-    const bool uniform = A.dk != 0.0;
+    const bool f32 = p.fp32 != 0;
+    const bool uniform = A.dk != 0.0 && !f32;
     for (int f0 = f_begin; f0 < f_end; f0 += kFT) {
         double acc[kFT][8];
         for (int ft = 0; ft < kFT; ++ft)
@@ -212,7 +221,7 @@ __device__ __forceinline__ void po_passes(const PoP &p, const PoAngle &A, int64_
             double w[4];
             weights(p, A.basis, q0, q1, q2, w);
             double sd, cd, rs = 0.0, rc = 1.0;
-            phase_sincos(kf[f0] * D, sd, cd);
+            phase_sincos(f32 ? phase32(kf[f0], D) : kf[f0] * D, sd, cd);
             if (uniform) phase_sincos(A.dk * D, rs, rc);  // evenly spaced: each step turns the phasor by dk D
 #pragma unroll
             for (int ft = 0; ft < kFT; ++ft) {
@@ -224,7 +233,7 @@ __device__ __forceinline__ void po_passes(const PoP &p, const PoAngle &A, int64_
                         cd = __builtin_fma(cd, rc, -(sd * rs));
                         sd = s2;
                     } else {
-                        phase_sincos(kf[f] * D, sd, cd);
+                        phase_sincos(f32 ? phase32(kf[f], D) : kf[f] * D, sd, cd);
                     }
                 }
                 for (int k = 0; k < 4; ++k) {
@@ -560,6 +569,7 @@ static PoP make_pop(const PoArgs &a)
     p.mode = a.mode;
     p.kf = a.kf;
     p.partial = a.partial;
+    p.fp32 = a.fp32;
     return p;
 }
 
@@ -569,7 +579,7 @@ int launch_po(hipStream_t s, const PoArgs &a)
     if (a.n_units > 2147483647LL) return fail(SBR_ERR_OVERFLOW, "PO launch: too many blocks");
     // one frequency: the 1-wide pass keeps the register count (and the
     // occupancy that hides the record loads) of a single accumulator set
-    if (a.max_nf == 1) {
+    if (a.max_nf == 1 || a.fp32) {  // the precision study takes every frequency's phase on its own
         k_po<1><<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
     } else {
         const dim3 grid(static_cast<unsigned>(a.n_units), static_cast<unsigned>((a.max_nf + kMfChunk - 1) / kMfChunk));

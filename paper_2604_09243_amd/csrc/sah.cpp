@@ -202,18 +202,19 @@ int sah_layout(const PreparedMesh &pm, int leaf_max, std::vector<BNode> &hn, std
                std::vector<float4> &hs, int &depth)
 {
     const int n = static_cast<int>(pm.live.size());
-    // padded triangle boxes and centroids (same float32 arithmetic as the LBVH leaves)
-    const float pad = static_cast<float>(1e-6 * pm.diag) + 1e-30f;
+    // triangle boxes (the hit rule's box widened by the guard: the same float32
+    // arithmetic as the LBVH leaves) and centroids
+    const SceneScale sc = scene_scale(pm.bbox, pm.diag);
     std::vector<Box> pb(n);
     std::vector<float> cen(3 * static_cast<size_t>(n));
     for (int j = 0; j < n; ++j) {
         const int li = pm.live[j];
         const float *a = &pm.v0[3 * li], *b = &pm.e1[3 * li], *c = &pm.e2[3 * li];
         for (int k = 0; k < 3; ++k) {
-            const float p0 = a[k], p1 = a[k] + b[k], p2 = a[k] + c[k];
-            const float lo = std::min(p0, std::min(p1, p2)), hi = std::max(p0, std::max(p1, p2));
-            pb[j].lo[k] = lo - pad - std::fabs(lo) * 4e-7f;
-            pb[j].hi[k] = hi + pad + std::fabs(hi) * 4e-7f;
+            float lo, hi;
+            spec_box_axis(a[k], b[k], c[k], sc.pbox, lo, hi);
+            pb[j].lo[k] = lo - sc.guard;
+            pb[j].hi[k] = hi + sc.guard;
             cen[3 * j + k] = 0.5f * (pb[j].lo[k] + pb[j].hi[k]);
         }
     }
@@ -278,12 +279,13 @@ int sah_layout(const PreparedMesh &pm, int leaf_max, std::vector<BNode> &hn, std
 }
 
 int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth, const std::vector<BTri> *tris,
-                    int64_t n_ids)
+                    int64_t n_ids, const SceneScale *scale)
 {
     // every reference in range, every leaf slot covered exactly once, child
     // boxes inside their parent's box, the stack bound respected; with the
-    // triangles: every input id in exactly one slot and every triangle's
-    // corners inside the box its leaf is reached through
+    // triangles: every input id in exactly one slot and every triangle's box
+    // (the hit rule's box widened by the guard) inside the box its leaf is
+    // reached through
     const int nn = static_cast<int>(hn.size());
     std::vector<uint8_t> covered(n, 0);
     std::vector<std::pair<int, int>> st{{0, 0}};
@@ -317,13 +319,14 @@ int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth
                     covered[q] = 1;
                     if (!tris) continue;
                     const BTri &tr = (*tris)[q];
-                    const float v[3][3] = {{tr.p0.x, tr.p0.y, tr.p0.z},
-                                           {tr.p0.x + tr.p1.x, tr.p0.y + tr.p1.y, tr.p0.z + tr.p1.z},
-                                           {tr.p0.x + tr.p2.x, tr.p0.y + tr.p2.y, tr.p0.z + tr.p2.z}};
-                    for (int corner = 0; corner < 3; ++corner)
-                        for (int k = 0; k < 3; ++k)
-                            if (!(v[corner][k] >= pf[6 * s + k] && v[corner][k] <= pf[6 * s + 3 + k]))
-                                return fail(SBR_ERR_INVALID_MESH, "BVH layout: triangle outside its leaf box");
+                    const float v0[3] = {tr.p0.x, tr.p0.y, tr.p0.z}, e1[3] = {tr.p1.x, tr.p1.y, tr.p1.z},
+                                e2[3] = {tr.p2.x, tr.p2.y, tr.p2.z};
+                    for (int k = 0; k < 3; ++k) {
+                        float lo, hi;
+                        spec_box_axis(v0[k], e1[k], e2[k], scale->pbox, lo, hi);
+                        if (!(lo - scale->guard >= pf[6 * s + k] && hi + scale->guard <= pf[6 * s + 3 + k]))
+                            return fail(SBR_ERR_INVALID_MESH, "BVH layout: triangle box outside its leaf box");
+                    }
                 }
             }
         }
@@ -405,7 +408,7 @@ int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh)
     std::vector<BTri> ht;
     std::vector<float4> hs;
     int depth = 0;
-    if ((rc = sah_layout(pm, leaf_max, hn, ht, hs, depth)) || (rc = validate_layout(hn, n, leaf_max, depth, nullptr, 0))) return rc;
+    if ((rc = sah_layout(pm, leaf_max, hn, ht, hs, depth)) || (rc = validate_layout(hn, n, leaf_max, depth, nullptr, 0, nullptr))) return rc;
     if ((rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nodes), sizeof(BNode) * hn.size())) ||
         (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->tris), sizeof(BTri) * n)) ||
         (rc = bvh_alloc(bvh, reinterpret_cast<void **>(&bvh->nrm_slot), sizeof(float4) * n)))

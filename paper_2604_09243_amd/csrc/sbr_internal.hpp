@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <algorithm>
+#include <cmath>
 #include <map>
 #include <string>
 #include <vector>
@@ -52,7 +54,7 @@ struct AnglePlan {
     int64_t rec_base;          // first record slot of this angle
     int32_t root;              // root node of the angle's scene in the node array
     float eps;                 // the scene's surface offset
-    float slack;               // the scene's box padding for entry distances
+    float pbox;                // the scene's hit-rule box half-width P (SceneScale)
     // primary-ray mask: cells of kMaskCell x kMaskCell rays, rows of mcu bytes
     int32_t mcu;               // cells along u
     int64_t mask_base;         // first byte of this angle's cells in the launch's mask
@@ -97,7 +99,8 @@ constexpr int kStatMasked = 8 + SBR_MAX_BOUNCES + 1;
 constexpr int kStatU64 = kStatMasked + 1;
 constexpr int kMaxLaunch = SBR_MAX_BOUNCES + 2;
 constexpr int kQcnt = SBR_MAX_BOUNCES + 2;
-constexpr size_t kStatBytes = 1024;
+constexpr size_t kStatBytes = 2048;
+static_assert(8 * kStatU64 <= kStatBytes, "the stat counters fit their block");
 constexpr size_t kCounterBytes = kStatBytes + 4ull * kLineU32 * (kQcnt + 8 * kMaxLaunch);
 struct CounterPtrs {
     unsigned long long *stat;
@@ -120,8 +123,44 @@ struct SceneInfo {
     double bbox[6];
 };
 
-// Box padding added to entry distances (scales with the scene size).
-inline float box_slack(double diag) { return static_cast<float>(1e-6 * diag) + 1e-30f; }
+// Rounding scale of a scene.  M = X + C + 1.5 |diag| bounds the magnitude
+// of every coordinate that the trace handles: X = the largest |coordinate| of
+// the bounding box, C = the largest |coordinate| of its centre; the scene's
+// points lie within X, and every origin of the aperture grid of any angle
+// lies within `obound` = C + 1.5 |diag| (checked per plan by check_origins).
+//   pbox:  the hit rule's box half-width P = fl32(2^-20 M): a float32 hit
+//          point must lie in its triangle's box widened by P (the hit rule
+//          of the float32 specification, the same on the oracle's side);
+//   guard: G = fl32(2^-21 M), added around every widened triangle box in
+//          the BVH, so that the float32 slab test of a node (its rounding,
+//          and that of the hit point, are below 6 2^-24 M) never culls a
+//          box that holds a hit point the rule accepts.
+struct SceneScale {
+    float pbox, guard;
+    double obound;
+};
+inline SceneScale scene_scale(const double bbox[6], double diag)
+{
+    double X = 0.0, C = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        X = std::max(X, std::max(std::fabs(bbox[a]), std::fabs(bbox[3 + a])));
+        C = std::max(C, std::fabs(0.5 * (bbox[a] + bbox[3 + a])));
+    }
+    const double M = (X + C) + 1.5 * diag;
+    SceneScale s;
+    s.pbox = static_cast<float>(M * 0x1p-20);
+    s.guard = static_cast<float>(M * 0x1p-21);
+    s.obound = C + 1.5 * diag;
+    return s;
+}
+// Box of triangle (v0, v0 + e1, v0 + e2) along one axis, widened by the hit
+// rule's P (what the hit rule tests) and, for the BVH, by G as well.
+__host__ __device__ inline void spec_box_axis(float v0, float e1, float e2, float P, float &lo, float &hi)
+{
+    const float p1 = v0 + e1, p2 = v0 + e2;
+    lo = fminf(v0, fminf(p1, p2)) - P;
+    hi = fmaxf(v0, fmaxf(p1, p2)) + P;
+}
 
 }  // namespace sbr
 
@@ -208,7 +247,7 @@ int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
 // sah.cpp: structural check of a node layout over n leaf slots (and, given
 // the triangles in leaf order, of their ids in [0, n_ids) and leaf boxes).
 int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth, const std::vector<BTri> *tris,
-                    int64_t n_ids);
+                    int64_t n_ids, const SceneScale *scale);
 // sah.cpp: surface-area estimates of the traversal work of a node layout.
 void layout_quality(const std::vector<BNode> &hn, sbr_bvh_quality &q);
 
@@ -247,6 +286,11 @@ int launch_mask(hipStream_t s, const BNode *nodes, const AnglePlan *plans, int n
                 uint8_t *mask, int64_t mask_bytes);
 // Host: margins and cell rows of a plan for the mask (scene bbox, node count)
 void mask_plan(AnglePlan &p, const double bbox[6], int64_t node_cnt);
+// Ties plan p to its scene (root node, eps, the hit rule's P, the mask's
+// margin) and checks that every origin of its ray grid lies within the
+// scene's `obound` (SceneScale); SBR_ERR_SAMPLING otherwise (a spacing
+// coarser than a fifth of the scene's diagonal).
+int scene_plan(AnglePlan &p, int32_t root, float eps, const double bbox[6], double diag, int64_t node_cnt);
 // Host: mask_base / mwork_base of plans [a0, a1) of one launch; returns the
 // launch's mask bytes (a multiple of 4) and build units.
 void mask_layout(AnglePlan *plans, int64_t a0, int64_t a1, int64_t &bytes, int64_t &units);
@@ -260,7 +304,8 @@ bool trace_needs_spill(const sbr_bvh *bvh);
 sbr_tune default_tune();
 int normalize_tune(sbr_tune &t);           // check_tune, then chunk_log2 0 -> default
 int log2i(int x);
-void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped);
+void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped,
+                int64_t chunks);
 // Every bounce of one trace (one streaming launch, or one launch per bounce
 // with the queues swapped); ev (nullable) gets an event after each launch.
 int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector<hipEvent_t> *ev);
@@ -299,6 +344,7 @@ struct PoArgs {
     int mode;
     const double *kf;    // device wavenumbers
     long long *partial;  // device partial rows
+    int fp32;            // SBR_OPT_FP32_PATH: the phase k D in float32 (precision study)
 };
 constexpr int kPoRecsPerBlock = 4096;
 __host__ __device__ inline int64_t po_units(int64_t rec_cnt) { return (rec_cnt + kPoRecsPerBlock - 1) / kPoRecsPerBlock; }

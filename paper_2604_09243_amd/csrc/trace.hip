@@ -48,13 +48,28 @@ constexpr int kStackLds = SBR_TRACE_STACK;  // LDS stack entries per lane
 #define SBR_TRACE_SPILL_LDS 16
 #endif
 constexpr int kStackSpillLds = SBR_TRACE_SPILL_LDS;  // LDS part of the stack when deeper trees spill to global memory
-// A child box is skipped only when it starts beyond the best hit so far by
-// more than 2^-11 of that distance plus the box slack: the float32
-// intersection t of an ill-conditioned triangle (a sliver seen from far
-// away) can fall short of the triangle's own padded box (by 7e-6 of t on
-// the aircraft's symmetry seam), and a tighter margin would let the tree's
-// visiting order decide which of two hits is kept.  Costs under 1 % here.
-constexpr float kCullFactor = 1.0f + 0x1p-11f;
+// The closest hit is the minimum over every triangle of (t, id) among the
+// hits that the float32 rule accepts (Moller-Trumbore conditions and the hit
+// point inside its triangle's box widened by P).  The tree finds exactly that
+// minimum:
+//  * every BVH box contains the widened triangle boxes of its subtree plus a
+//    guard G (SceneScale), which exceeds the float32 rounding of the hit point
+//    and of the slab test below, so a box that holds an accepted hit point at
+//    distance t' <= the best t so far always passes the test (entry <= t' <=
+//    exit); no relative margin on t is needed;
+//  * the traversal first runs without checking the box rule per candidate;
+//    if its winner then passes the rule, every box it skipped was skipped
+//    against a best t no smaller than the winner's, so it held no better
+//    accepted hit.  Otherwise (a rounding-dominated hit of a sliver or of a
+//    grazing ray, about one query in 10^6) the query is traversed again with
+//    the rule applied to every candidate.
+// Slab-test rounding: with ix = rcp(d) (1 ulp) and ox = fl(o ix), the value
+// fma(b, ix, -ox) is within (3 2^-24 |b - o| + 2^-24 |o|) / |d| of (b - o) / d;
+// the hit point fl(o + fl(t d)) is within 2^-24 (2 |x| + |o|) of o + t d.
+// With every coordinate below M = X + obound that is less than 6 2^-24 M,
+// under G = 8 2^-24 M.  Caller rays whose origin lies beyond obound get the
+// difference as a per-ray widening of the slab values.
+constexpr float kGuardUlps = 0x1p-21f;  // G / M
 constexpr int kTileRays = 64;
 // Five waves per SIMD: the LDS stack (28 entries x 256 lanes = 28 KB per
 // block) lets five blocks share a CU, and the register allocator is held to
@@ -77,7 +92,8 @@ struct Params {
     const BNode *nodes;
     const BTri *tris;
     const float4 *nrm;  // by slot
-    float eps, slack;
+    float eps, pbox;    // caller rays: the scene's offset and the hit rule's P
+    float obound;       // caller rays: origin coordinates up to this are covered by the BVH's guard
     int bmax;
     uint32_t flags;
     // grid source
@@ -149,11 +165,25 @@ __device__ __forceinline__ bool tri_test(const BTri &tr, const Ray &r, float &t_
     return u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f && t < INFINITY;
 }
 
-__device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r, Best &b)
+// The hit rule's box test: the float32 hit point o + t d (the bounce update's
+// point) inside the triangle's box widened by P on every axis.
+__device__ __forceinline__ bool in_box(const BTri &tr, const Ray &r, float t, float P)
+{
+    const float x = r.ox + t * r.dx, y = r.oy + t * r.dy, z = r.oz + t * r.dz;
+    float lx, hx, ly, hy, lz, hz;
+    spec_box_axis(tr.p0.x, tr.p1.x, tr.p2.x, P, lx, hx);
+    spec_box_axis(tr.p0.y, tr.p1.y, tr.p2.y, P, ly, hy);
+    spec_box_axis(tr.p0.z, tr.p1.z, tr.p2.z, P, lz, hz);
+    return x >= lx && x <= hx && y >= ly && y <= hy && z >= lz && z <= hz;
+}
+
+// strict: apply the box rule to every candidate (the re-traversal).
+__device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r, Best &b, bool strict, float P)
 {
     const int id = __float_as_int(tr.p0.w);
     float t;
-    if (tri_test(tr, r, t) && id != r.prev && (t < b.t || (t == b.t && id < b.id))) {
+    if (tri_test(tr, r, t) && id != r.prev && (t < b.t || (t == b.t && id < b.id)) &&
+        (!strict || in_box(tr, r, t, P))) {
         b.t = t;
         b.id = id;
         b.slot = slot;
@@ -233,45 +263,48 @@ __device__ __forceinline__ bool wave_uniform(int v, int &v0)
 // The triangles [first, first + cnt) of a leaf, cnt <= 4, each 48-byte
 // record loaded one test ahead.
 template <typename TriPtr>
-__device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, const Ray &r, Best &b)
+__device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, const Ray &r, Best &b, bool strict,
+                                               float P)
 {
     SBR_COUNT(b.leaves += 1; b.tris += cnt);
     const BTri t0 = tris[first];
     BTri t1, t2, t3;
     if (cnt > 1) t1 = tris[first + 1];
-    test_tri(t0, first, r, b);
+    test_tri(t0, first, r, b, strict, P);
     if (cnt > 2) t2 = tris[first + 2];
-    if (cnt > 1) test_tri(t1, first + 1, r, b);
+    if (cnt > 1) test_tri(t1, first + 1, r, b, strict, P);
     if (cnt > 3) t3 = tris[first + 3];
-    if (cnt > 2) test_tri(t2, first + 2, r, b);
-    if (cnt > 3) test_tri(t3, first + 3, r, b);
+    if (cnt > 2) test_tri(t2, first + 2, r, b, strict, P);
+    if (cnt > 3) test_tri(t3, first + 3, r, b, strict, P);
 }
 
 // Leaf `code` (first triangle << 3 | count - 1).
-__device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &r, Best &b)
+__device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &r, Best &b, bool strict, float P)
 {
     int c0;
     if (wave_uniform(code, c0))
-        test_leaf_from(ScalarTriLoader{p.tris}, c0 >> 3, (c0 & 7) + 1, r, b);
+        test_leaf_from(ScalarTriLoader{p.tris}, c0 >> 3, (c0 & 7) + 1, r, b, strict, P);
     else
-        test_leaf_from(p.tris, code >> 3, (code & 7) + 1, r, b);
+        test_leaf_from(p.tris, code >> 3, (code & 7) + 1, r, b, strict, P);
 }
 
-// Entry and exit distances of the ray (inverse direction i, origin term o)
-// through both child boxes of node n, the exit clamped to tlim.
-__device__ __forceinline__ void node_boxes(const BNode &n, float ix, float iy, float iz, float ox, float oy, float oz,
-                                           float tlim, float &t0, float &u0, float &t1, float &u1, int &cx, int &cy)
+// Entry and exit distances of the ray (inverse direction i, origin terms l
+// for the low and h for the high planes of each axis) through both child
+// boxes of node n, the exit clamped to tlim.
+__device__ __forceinline__ void node_boxes(const BNode &n, float ix, float iy, float iz, float lx, float ly, float lz,
+                                           float hx, float hy, float hz, float tlim, float &t0, float &u0, float &t1,
+                                           float &u1, int &cx, int &cy)
 {
     // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
-    const float ax0 = __builtin_fmaf(n.a.x, ix, -ox), ax1 = __builtin_fmaf(n.a.w, ix, -ox);
-    const float ay0 = __builtin_fmaf(n.a.y, iy, -oy), ay1 = __builtin_fmaf(n.b.x, iy, -oy);
-    const float az0 = __builtin_fmaf(n.a.z, iz, -oz), az1 = __builtin_fmaf(n.b.y, iz, -oz);
+    const float ax0 = __builtin_fmaf(n.a.x, ix, -lx), ax1 = __builtin_fmaf(n.a.w, ix, -hx);
+    const float ay0 = __builtin_fmaf(n.a.y, iy, -ly), ay1 = __builtin_fmaf(n.b.x, iy, -hy);
+    const float az0 = __builtin_fmaf(n.a.z, iz, -lz), az1 = __builtin_fmaf(n.b.y, iz, -hz);
     t0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
     u0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tlim));
     // child 1: lo = (b.z, b.w, c.x), hi = (c.y, c.z, c.w)
-    const float bx0 = __builtin_fmaf(n.b.z, ix, -ox), bx1 = __builtin_fmaf(n.c.y, ix, -ox);
-    const float by0 = __builtin_fmaf(n.b.w, iy, -oy), by1 = __builtin_fmaf(n.c.z, iy, -oy);
-    const float bz0 = __builtin_fmaf(n.c.x, iz, -oz), bz1 = __builtin_fmaf(n.c.w, iz, -oz);
+    const float bx0 = __builtin_fmaf(n.b.z, ix, -lx), bx1 = __builtin_fmaf(n.c.y, ix, -hx);
+    const float by0 = __builtin_fmaf(n.b.w, iy, -ly), by1 = __builtin_fmaf(n.c.z, iy, -hy);
+    const float bz0 = __builtin_fmaf(n.c.x, iz, -lz), bz1 = __builtin_fmaf(n.c.w, iz, -hz);
     t1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
     u1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tlim));
     cx = n.ch.x;
@@ -289,23 +322,26 @@ __device__ __forceinline__ bool user_rays(const Params &p)
 }
 
 // The scene a ray belongs to: its root node in the (possibly multi-scene)
-// node array, its surface offset and its box padding.
+// node array, its surface offset and the hit rule's P.
 struct SceneRef {
     int root;
-    float eps, slack;
+    float eps, pbox;
 };
 
 template <int U = -1>
 __device__ __forceinline__ SceneRef scene_of(const Params &p, const Ray &r)
 {
-    if (user_rays<U>(p)) return SceneRef{0, p.eps, p.slack};
+    if (user_rays<U>(p)) return SceneRef{0, p.eps, p.pbox};
     const AnglePlan &pl = p.plans[r.meta >> 8];
-    return SceneRef{pl.root, pl.eps, pl.slack};
+    return SceneRef{pl.root, pl.eps, pl.pbox};
 }
 
-// Closest hit of ray r, skipping triangle r.prev.
-template <bool SPILL>
-__device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc)
+// One traversal for the closest hit of ray r, skipping triangle r.prev;
+// strict: candidates must pass the hit rule's box test.  FAR: widen the slab
+// values for an origin beyond the BVH guard's bound (caller rays).
+template <bool SPILL, bool FAR>
+__device__ __forceinline__ Best traverse(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc,
+                                         bool strict)
 {
     Best b;
     b.t = INFINITY;
@@ -317,20 +353,29 @@ __device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const Sc
     const float ddy = fabsf(r.dy) < tiny ? copysignf(tiny, r.dy) : r.dy;
     const float ddz = fabsf(r.dz) < tiny ? copysignf(tiny, r.dz) : r.dz;
     const float ix = __builtin_amdgcn_rcpf(ddx), iy = __builtin_amdgcn_rcpf(ddy), iz = __builtin_amdgcn_rcpf(ddz);
-    const float ox = r.ox * ix, oy = r.oy * iy, oz = r.oz * iz;
+    float lx = r.ox * ix, ly = r.oy * iy, lz = r.oz * iz;
+    float hx = lx, hy = ly, hz = lz;
+    if constexpr (FAR) {
+        // near planes earlier, far planes later by 8 2^-24 (|o| - obound) / |d|
+        const float gx = kGuardUlps * fmaxf(fabsf(r.ox) - p.obound, 0.0f) * ix;
+        const float gy = kGuardUlps * fmaxf(fabsf(r.oy) - p.obound, 0.0f) * iy;
+        const float gz = kGuardUlps * fmaxf(fabsf(r.oz) - p.obound, 0.0f) * iz;
+        lx += gx; hx -= gx;
+        ly += gy; hy -= gy;
+        lz += gz; hz -= gz;
+    }
     int sp = 0;
     int cur = sc.root;  // the root is an internal node
     for (;;) {
         // phase 1: descend through internal nodes until a leaf (or nothing) is next
         while (cur >= 0) {
             SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
-            const float tlim = __builtin_fmaf(b.t, kCullFactor, sc.slack);
             float t0, u0, t1, u1;
             int cx, cy, c0;
             if (wave_uniform(cur, c0))
-                node_boxes(node_scalar(p.nodes, c0), ix, iy, iz, ox, oy, oz, tlim, t0, u0, t1, u1, cx, cy);
+                node_boxes(node_scalar(p.nodes, c0), ix, iy, iz, lx, ly, lz, hx, hy, hz, b.t, t0, u0, t1, u1, cx, cy);
             else
-                node_boxes(p.nodes[cur], ix, iy, iz, ox, oy, oz, tlim, t0, u0, t1, u1, cx, cy);
+                node_boxes(p.nodes[cur], ix, iy, iz, lx, ly, lz, hx, hy, hz, b.t, t0, u0, t1, u1, cx, cy);
             const bool h0 = t0 <= u0, h1 = t1 <= u1;
             if (h0 && h1) {
                 int nr = cx, fr = cy;
@@ -355,13 +400,26 @@ __device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const Sc
         if (cur == kEmpty) break;
         // phase 2: the triangles of leaf `cur`
         SBR_COUNT(if (wave_leader()) b.wleaf += 1);
-        test_leaf(p, ~cur, r, b);
+        test_leaf(p, ~cur, r, b, strict, sc.pbox);
         if (sp > 0) {
             --sp;
             cur = st.pop(sp);
         } else {
             break;
         }
+    }
+    return b;
+}
+
+// Closest hit of ray r under the hit rule: one traversal, and a strict second
+// one in the rare case that the first one's winner fails the box test.
+template <bool SPILL, bool FAR = false>
+__device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc)
+{
+    Best b;
+    for (int pass = 0;; ++pass) {
+        b = traverse<SPILL, FAR>(p, r, st, sc, pass != 0);
+        if (pass != 0 || b.slot < 0 || in_box(p.tris[b.slot], r, b.t, sc.pbox)) break;
     }
     return b;
 }
@@ -376,6 +434,14 @@ __device__ __forceinline__ double dotk(const K3 &k, float x, float y, float z)
 }
 
 __device__ __forceinline__ K3 plan_k(const AnglePlan &pl) { return K3{pl.k[0], pl.k[1], pl.k[2]}; }
+
+// k . o of a fresh ray's origin: float64, or float32 in the precision study.
+__device__ __forceinline__ double kdot0(const Params &p, const K3 &k, const Ray &r)
+{
+    if (!(p.flags & SBR_OPT_FP32_PATH)) return dotk(k, r.ox, r.oy, r.oz);
+    const float kx = static_cast<float>(k.x), ky = static_cast<float>(k.y), kz = static_cast<float>(k.z);
+    return static_cast<double>((kx * r.ox + ky * r.oy) + kz * r.oz);
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
@@ -480,7 +546,7 @@ __device__ __forceinline__ int grid_ray(const Params &p, int64_t q, Ray &r, int 
     r.meta = lo << 8;
     r.P = 0.0;
     r.comp = 0.0;
-    r.kdo = dotk(plan_k(pl), r.ox, r.oy, r.oz);
+    r.kdo = kdot0(p, plan_k(pl), r);
     return kGridRay;
 }
 
@@ -506,7 +572,7 @@ __device__ __forceinline__ bool user_ray(const Params &p, int64_t e, Ray &r)
     r.meta = 0;
     r.P = 0.0;
     r.comp = 0.0;
-    r.kdo = dotk(K3{p.kx, p.ky, p.kz}, r.ox, r.oy, r.oz);
+    r.kdo = kdot0(p, K3{p.kx, p.ky, p.kz}, r);
     if (p.hits.tri_path)
         for (int b = 0; b < p.bmax; ++b) p.hits.tri_path[e * p.bmax + b] = -1;
     return true;
@@ -529,8 +595,15 @@ __device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, c
     L.xly = r.oy + t * r.dy;
     L.xlz = r.oz + t * r.dz;
     int N = r.meta & 127;
-    r.P = r.P + static_cast<double>(t);
-    if (N >= 1 && !(p.flags & SBR_OPT_PAPER_PATH)) r.P = r.P + r.comp;
+    const bool f32 = (p.flags & SBR_OPT_FP32_PATH) != 0;  // precision study: path, offset term and D in float32
+    if (!f32) {
+        r.P = r.P + static_cast<double>(t);
+        if (N >= 1 && !(p.flags & SBR_OPT_PAPER_PATH)) r.P = r.P + r.comp;
+    } else {
+        float P32 = static_cast<float>(r.P) + t;
+        if (N >= 1 && !(p.flags & SBR_OPT_PAPER_PATH)) P32 = P32 + static_cast<float>(r.comp);
+        r.P = static_cast<double>(P32);
+    }
     N += 1;
     if (N == 1) r.first = b.id;
     L.dlx = r.dx;
@@ -561,11 +634,21 @@ __device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, c
     r.ox = L.xlx + eps * nfx;
     r.oy = L.xly + eps * nfy;
     r.oz = L.xlz + eps * nfz;
-    r.comp = static_cast<double>(eps) * ((static_cast<double>(nfx) * r.dx + static_cast<double>(nfy) * r.dy) +
-                                           static_cast<double>(nfz) * r.dz);
+    if (!f32) {
+        r.comp = static_cast<double>(eps) * ((static_cast<double>(nfx) * r.dx + static_cast<double>(nfy) * r.dy) +
+                                             static_cast<double>(nfz) * r.dz);
+    } else {
+        r.comp = static_cast<double>(eps * ((nfx * r.dx + nfy * r.dy) + nfz * r.dz));
+    }
     r.prev = b.id;
     r.meta = (r.meta & ~0xff) | N | (back ? 128 : 0);
-    L.D = (r.kdo + r.P) + dotk(kv, L.xlx, L.xly, L.xlz);
+    if (!f32) {
+        L.D = (r.kdo + r.P) + dotk(kv, L.xlx, L.xly, L.xlz);
+    } else {
+        const float kx = static_cast<float>(kv.x), ky = static_cast<float>(kv.y), kz = static_cast<float>(kv.z);
+        L.D = static_cast<double>((static_cast<float>(r.kdo) + static_cast<float>(r.P)) +
+                                  ((kx * L.xlx + ky * L.xly) + kz * L.xlz));
+    }
     L.flags = SBR_REC_VALID | (back ? SBR_REC_BACK_LAST : 0);
     return N < p.bmax;
 }
@@ -770,7 +853,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_stream(Params p)
         b.slot = -1;
         SceneRef sc{0, 0.f, 0.f};
         if (has) sc = scene_of<kUser>(p, r);
-        if (has) b = closest(p, r, st, sc);
+        if (has) b = closest<SPILL, SRC == 1>(p, r, st, sc);
         if (has) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (has) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         if (has) {
@@ -783,7 +866,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_stream(Params p)
                 if (!cont) {
                     int fl = L.flags;
                     if (p.flags & SBR_OPT_DROP_TRAPPED) {
-                        const Best b2 = closest(p, r, st, sc);
+                        const Best b2 = closest<SPILL, SRC == 1>(p, r, st, sc);
                         atomicAdd(&bs.queries, 1u);
                         if (b2.slot >= 0) {  // trapped: flagged and dropped from the PO sum
                             if (kUser) flag_trapped<kUser>(p, r);
@@ -880,7 +963,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
         b.slot = -1;
         SceneRef sc{0, 0.f, 0.f};
         if (active) sc = scene_of(p, r);
-        if (active) b = closest(p, r, st, sc);
+        if (active) b = closest<SPILL, SRC == 1>(p, r, st, sc);
         if (active) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (active) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         bool cont = false;
@@ -892,7 +975,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
                 sink_hit(p, r, b, L);
                 if (!cont && (p.flags & SBR_OPT_DROP_TRAPPED)) {
-                    const Best b2 = closest(p, r, st, sc);
+                    const Best b2 = closest<SPILL, SRC == 1>(p, r, st, sc);
                     atomicAdd(&bs.queries, 1u);
                     if (b2.slot >= 0) {
                         flag_trapped(p, r);
@@ -1035,7 +1118,12 @@ static Params make_params(const TraceArgs &a, int launch)
     p.tris = a.bvh->tris;
     p.nrm = a.bvh->nrm_slot;
     p.eps = a.bvh->eps;
-    p.slack = box_slack(a.bvh->diag);
+    {
+        const SceneScale sc = scene_scale(a.bvh->bbox, a.bvh->diag);
+        p.pbox = sc.pbox;
+        p.obound = static_cast<float>(sc.obound);
+        if (static_cast<double>(p.obound) > sc.obound) p.obound = std::nextafter(p.obound, 0.0f);
+    }
     p.bmax = a.bmax;
     p.flags = a.flags;
     p.plans = a.plans;

@@ -24,7 +24,8 @@ BUILD_LBVH, BUILD_SAH, BUILD_PLOC = 0, 1, 2
 REC_VALID, REC_TRAPPED, REC_BACK_LAST = 1, 2, 4
 OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRONT, OPT_NO_GRAPH = 1, 2, 4, 8, 16, 32
 OPT_NO_MASK = 64
-MAX_BOUNCES = 64
+OPT_FP32_PATH = 128
+MAX_BOUNCES = 127
 
 _vp = C.c_void_p
 _d3 = C.c_double * 3
@@ -64,13 +65,14 @@ class Stats(C.Structure):
                 ("hits", C.c_int64 * (MAX_BOUNCES + 1)), ("angles", C.c_int64), ("ms_trace", C.c_double),
                 ("ms_po", C.c_double), ("ms_total", C.c_double), ("ms_bounce", C.c_double * (MAX_BOUNCES + 1)),
                 ("queries_bounce", C.c_int64 * (MAX_BOUNCES + 1)), ("trav", C.c_int64 * 6),
-                ("masked", C.c_int64)]
+                ("masked", C.c_int64), ("chunks", C.c_int64)]
 
     def as_dict(self):
         return dict(rays=self.rays, queries=self.queries, valid=self.valid, trapped=self.trapped,
                     hits=list(self.hits), angles=self.angles, ms_trace=self.ms_trace, ms_po=self.ms_po,
                     ms_total=self.ms_total, ms_bounce=list(self.ms_bounce),
-                    queries_bounce=list(self.queries_bounce), trav=list(self.trav), masked=self.masked)
+                    queries_bounce=list(self.queries_bounce), trav=list(self.trav), masked=self.masked,
+                    chunks=self.chunks)
 
 
 class PoDesc(C.Structure):
@@ -265,6 +267,25 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _dev_tensor(t, name, dtype, shape, device):
+    """Checks that a tensor handed to the library as a device pointer lives
+    on the context's GPU with the expected dtype and shape and is contiguous
+    (a host tensor, a wrong dtype or a short array would be read out of
+    bounds by the kernels).  ``shape`` entries of None match any size."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s: expected a torch tensor, got %s" % (name, type(t).__name__))
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError("%s: must be on cuda:%d, is on %s" % (name, device, t.device))
+    if t.dtype != dtype:
+        raise ValueError("%s: dtype must be %s, is %s" % (name, dtype, t.dtype))
+    if t.dim() != len(shape) or any(w is not None and w != g for w, g in zip(shape, t.shape)):
+        raise ValueError("%s: shape must be %s, is %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s: must be contiguous" % name)
+    return t
+
+
 class BVH:
     def __init__(self, ctx, handle):
         self.ctx = ctx
@@ -346,6 +367,10 @@ class Batch:
                              torch.empty(n, 2, 2, dtype=torch.float64, device=dev))
             out = self._out
         A, S = out
+        n = int(self.info()["n_rows"])
+        _dev_tensor(A, "out A", torch.float64, (n, 2, 2, 2), self.ctx.device)
+        if S is not None:
+            _dev_tensor(S, "out sigma", torch.float64, (n, 2, 2), self.ctx.device)
         st = Stats() if stats else None
         _check(load_library().sbr_batch_run(self.handle, A.data_ptr(), S.data_ptr() if S is not None else None,
                                             C.byref(st) if stats else None))
@@ -407,6 +432,7 @@ class MLP:
         torch = _torch()
         p = self._dev(pts, torch.float64)
         n = p.shape[0]
+        _dev_tensor(p, "pts", torch.float64, (n, 3), self.ctx.device)
         A = torch.empty(n, 2, 2, dtype=torch.float64, device=p.device)
         _check(load_library().sbr_mlp_predict(self.handle, p.data_ptr(), n, A.data_ptr()))
         return torch.view_as_complex(A)
@@ -419,10 +445,20 @@ class MLP:
             t = np.stack([np.real(t), np.imag(t)], axis=-1)
         return self._dev(t, torch.float64)
 
+    def _check_pairs(self, p, t):
+        """Points [n, 3] and targets of 4 reals per point (Re/Im of A_HH, A_VV)."""
+        torch = _torch()
+        n = p.shape[0]
+        _dev_tensor(p, "pts", torch.float64, (n, 3), self.ctx.device)
+        if t.numel() != 4 * n:
+            raise ValueError("targets: need 4 reals per point (%d points), got %d values" % (n, t.numel()))
+        _dev_tensor(t, "targets", torch.float64, tuple(t.shape), self.ctx.device)
+
     def gradients(self, pts, targets):
         """(grads float32 numpy [n_params], loss) for the points."""
         torch = _torch()
         p, t = self._dev(pts, torch.float64), self._targets(targets)
+        self._check_pairs(p, t)
         g = torch.empty(self.info()["n_params"], dtype=torch.float32, device=p.device)
         loss = C.c_float()
         _check(load_library().sbr_mlp_gradients(self.handle, p.data_ptr(), t.data_ptr(), p.shape[0], g.data_ptr(),
@@ -433,6 +469,7 @@ class MLP:
         """Adam training; returns the mean loss of every epoch."""
         torch = _torch()
         p, t = self._dev(pts, torch.float64), self._targets(targets)
+        self._check_pairs(p, t)
         o = TrainOpts(C.sizeof(TrainOpts), int(epochs), int(batch), 0, float(lr), float(lr_min), int(seed))
         hist = np.zeros(int(epochs), np.float32)
         _check(load_library().sbr_mlp_train(self.handle, p.data_ptr(), t.data_ptr(), p.shape[0], C.byref(o),
@@ -496,7 +533,12 @@ class Context:
         if isinstance(V, torch.Tensor):
             V = V.contiguous()
             T = T.contiguous()
-            assert V.dtype == torch.float32 and T.dtype == torch.int32
+            if V.dtype != torch.float32 or T.dtype != torch.int32:
+                raise ValueError("build_bvh: V must be float32 and T int32")
+            if V.dim() != 2 or V.shape[1] != 3 or T.dim() != 2 or T.shape[1] != 3:
+                raise ValueError("build_bvh: V and T must be [n, 3]")
+            if V.is_cuda != T.is_cuda or (V.is_cuda and (V.device.index != self.device or T.device.index != self.device)):
+                raise ValueError("build_bvh: V and T must both be host tensors or both on cuda:%d" % self.device)
             opts.mem = MEM_DEVICE if V.is_cuda else MEM_HOST
             pv, pt, nv, nt = V.data_ptr(), T.data_ptr(), V.shape[0], T.shape[0]
             keep = (V, T)
@@ -517,8 +559,9 @@ class Context:
         tensors (the sbr_hits arrays) and, if ``stats``, the statistics."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
-        o, d, eH, eV = (x.contiguous() for x in (o, d, eH, eV))
-        n = o.shape[0]
+        n = int(o.shape[0]) if hasattr(o, "shape") and len(o.shape) == 2 else -1
+        for name, x in (("o", o), ("d", d), ("eH", eH), ("eV", eV)):
+            _dev_tensor(x, name, torch.float32, (n, 3), self.device)
         out = dict(n_bounce=torch.empty(n, dtype=torch.int32, device=dev),
                    tri_first=torch.empty(n, dtype=torch.int32, device=dev),
                    tri_last=torch.empty(n, dtype=torch.int32, device=dev),
@@ -559,8 +602,14 @@ class Context:
         A = torch.empty(nf, 2, 2, 2, dtype=torch.float64, device=torch.device("cuda", self.device))
         desc = PoDesc(C.sizeof(PoDesc), int(mode), _d3(*map(float, k_hat)), _d3(*map(float, theta_hat)),
                       _d3(*map(float, phi_hat)), float(dA))
+        n = int(hits["n_bounce"].shape[0])
+        dtypes = dict(n_bounce=torch.int32, tri_first=torch.int32, tri_last=torch.int32, flags=torch.int32,
+                      path=torch.float64, D=torch.float64, d_last=torch.float32, x_last=torch.float32,
+                      eH_last=torch.float32, eV_last=torch.float32)
+        for name, dt in dtypes.items():
+            if hits.get(name) is not None:
+                _dev_tensor(hits[name], name, dt, (n, 3) if name.endswith("_last") else (n,), self.device)
         h = self._hits(hits)
-        n = hits["n_bounce"].shape[0]
         _check(load_library().sbr_po_integrate(self.handle, bvh.handle, C.byref(h), n, C.byref(desc),
                                                freqs.ctypes.data, nf, A.data_ptr()))
         return torch.view_as_complex(A)
@@ -594,6 +643,9 @@ class Context:
             S = torch.empty(na, nf, 2, 2, dtype=torch.float64, device=dev)
         else:
             A, S = out
+            _dev_tensor(A, "out A", torch.float64, (na, nf, 2, 2, 2), self.device)
+            if S is not None:
+                _dev_tensor(S, "out sigma", torch.float64, (na, nf, 2, 2), self.device)
         sw = Sweep(C.sizeof(Sweep), th.ctypes.data, ph.ctypes.data, na, fr.ctypes.data, nf, int(max_bounces),
                    float(ds), float(samples_per_lambda), float(eta), int(mode), int(flags),
                    C.pointer(tune) if tune is not None else None)

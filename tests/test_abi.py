@@ -34,7 +34,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_error_string(lib):
-    assert lib.sbr_version() == 1
+    src = open(HEADER).read()
+    assert lib.sbr_version() == int(re.search(r"#define SBR_ABI_VERSION (\d+)", src).group(1)) == 2
     assert isinstance(lib.sbr_last_error(), bytes)
 
 
@@ -123,3 +124,15 @@ def test_constants_match_header():
             assert getattr(sbr, name) == v, name
             checked += 1
     assert checked >= 16 and vals["OPT_NO_MASK"] == sbr.OPT_NO_MASK
+
+
+def test_binding_rejects_host_or_misshaped_tensors():
+    """Device pointers are only taken from tensors on the context's GPU with
+    the expected dtype, shape and layout; anything else fails in Python
+    before the library sees it."""
+    import torch
+    from paper_2604_09243_amd import sbr
+    with pytest.raises(ValueError, match="cuda:0"):
+        sbr._dev_tensor(torch.zeros(4, 3), "o", torch.float32, (4, 3), 0)
+    with pytest.raises(TypeError):
+        sbr._dev_tensor(np.zeros((4, 3), np.float32), "o", torch.float32, (4, 3), 0)

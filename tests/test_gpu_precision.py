@@ -1,0 +1,114 @@
+"""Precision and depth study (Sec. 6: single-precision phase drift after
+many reflections).  The GPU's study option SBR_OPT_FP32_PATH accumulates
+the path, forms D and the phase k D in float32; the method itself keeps
+them in float64.  On the duct (about a thousand rays past 100 reflections)
+and on the deep chains of the aircraft (its inlets and wing roots at
+phi = 135 deg), to B_max = 100:
+
+* the float32-path D equals the oracle's float32 study option bit for bit
+  (same rays, same operation order), as the float64 D does its own;
+* the phase error k |D32 - D64| grows with the number of reflections, and
+  the complex amplitude moves by |A32 - A64| / |A64|, printed per depth
+  band (the figures quoted in the design notes)."""
+import sys
+
+import numpy as np
+import pytest
+
+import sbr_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299_792_458.0
+BANDS = ((1, 2), (3, 10), (11, 30), (31, 60), (61, 100))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2604_09243_amd import Context
+    return Context(0)
+
+
+def gpu_trace(torch, ctx, bvh, o, d, pv, tv, k, bmax, flags):
+    n = len(o)
+    dev = torch.device("cuda", 0)
+    t = [torch.from_numpy(np.ascontiguousarray(np.broadcast_to(x, (n, 3)).astype(np.float32))).to(dev)
+         for x in (o, d, pv, tv)]
+    return {kk: v.cpu().numpy() for kk, v in ctx.trace(bvh, *t, bmax, k, flags=flags).items()}
+
+
+def drift(k0, nb, D32, D64):
+    err = k0 * np.abs(D32 - D64)
+    rows = []
+    for lo, hi in BANDS:
+        s = (nb >= lo) & (nb <= hi)
+        if s.sum() >= 10:
+            rows.append((lo, hi, int(s.sum()), float(np.sqrt((err[s] ** 2).mean())), float(err[s].max())))
+    return rows
+
+
+@pytest.mark.parametrize("case", ["duct", "aircraft"])
+def test_fp32_path_drift_by_depth(torch, ctx, orc, case):
+    from paper_2604_09243_amd import sbr
+    if case == "duct":
+        V, T = si.duct(10.0, 0.1, 0.1, 40)
+        th, ph, spl, bmax = 75.0, 200.0, 10.0, 100
+    else:
+        w = si.aircraft_case()
+        V, T = w.V, w.T
+        th, ph, spl, bmax = 90.0, 135.0, 8.0, 100
+    say("case fp32 path drift,", case)
+    freq = 10e9
+    k0 = 2 * np.pi * freq / C0
+    bvh = ctx.build_bvh(V, T, builder=sbr.BUILD_SAH)
+    m = orc.Mesh(V, T).build_bvh()
+    o, d, nu, nv = orc.gen_rays(m.bbox, th, ph, C0 / freq / spl)
+    k, tv, pv = orc.frame(th, ph)
+    g64 = gpu_trace(torch, ctx, bvh, o, d, pv, tv, k, bmax, 0)
+    g32 = gpu_trace(torch, ctx, bvh, o, d, pv, tv, k, bmax, sbr.OPT_FP32_PATH)
+    nb = g64["n_bounce"]
+    assert np.array_equal(nb, g32["n_bounce"])  # the geometry is float32 either way
+    # the oracle's study option on the deepest rays (and a sample of the rest): the same D bits
+    rng = np.random.default_rng(5)
+    deep = np.flatnonzero(nb >= 11)
+    some = rng.choice(np.flatnonzero(nb > 0), min(20_000, int((nb > 0).sum())), replace=False)
+    ids = np.union1d(deep, some)
+    for fp32, g in ((False, g64), (True, g32)):
+        r = orc.trace(m, o[ids], d, pv, tv, k, bmax, use_bvh=True, fp32_path=fp32)
+        assert np.array_equal(r["nb"], g["n_bounce"][ids])
+        assert np.array_equal(r["D"], g["D"][ids]), fp32
+    rows = drift(k0, nb, g32["D"], g64["D"])
+    for lo, hi, n, rms, mx in rows:
+        say("  N %3d-%3d: %8d rays, phase error rms %.2e rad, max %.2e rad" % (lo, hi, n, rms, mx))
+    assert rows[-1][1] >= 60 and rows[-1][2] >= 10
+    assert rows[-1][3] > 5 * rows[0][3]
+    # the RCS of the angle both ways
+    A64, _, _ = ctx.rcs_sweep(bvh, [th], [ph], [freq], bmax, samples_per_lambda=spl)
+    A32, _, _ = ctx.rcs_sweep(bvh, [th], [ph], [freq], bmax, samples_per_lambda=spl, flags=sbr.OPT_FP32_PATH)
+    A64, A32 = A64.cpu().numpy()[0, 0], A32.cpu().numpy()[0, 0]
+    dev = np.abs(A32 - A64).max() / np.abs(A64).max()
+    say("  |A32 - A64| / |A64| =", dev, "deepest", int(nb.max()))
+    assert dev < 0.05
+    bvh.free()
+
+
+def test_fp32_path_refused_by_batches(torch, ctx):
+    from paper_2604_09243_amd import sbr
+    V, T = si.trihedral(1.0, 4)
+    bvh = ctx.build_bvh(V, T)
+    with pytest.raises(sbr.SbrError) as e:
+        ctx.batch(bvh, [(0, 54.74, 45.0, 0, 1)], [10e9], 5, flags=sbr.OPT_FP32_PATH)
+    assert e.value.status == sbr.ERR_UNSUPPORTED

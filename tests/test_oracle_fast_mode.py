@@ -1,0 +1,123 @@
+"""The oracle's fast mode (the binned-SAH / median tree of Algorithm 1) gives
+the brute-force closest hit of Algorithm 2 (a minimum over every triangle)
+bit for bit: on every ray of the sphere case, on three trihedral angles at
+lambda/10, on 10^5 seeded aircraft rays over four azimuths and on the rays of
+the 64-scene batch whose result once depended on the tree.  The hit rule's
+box test refuses no well-conditioned hit: without it, brute force gives the
+same results on the sphere and trihedral grids."""
+import numpy as np
+import pytest
+
+import sbr_inputs as si
+
+C0 = 299_792_458.0
+KEYS = ("nb", "tri_first", "tri_last", "flags", "path", "D", "d_last", "x_last", "eH_last", "eV_last")
+
+
+def same(a, b, what):
+    for key in KEYS + ("tri_path",):
+        assert np.array_equal(a[key], b[key]), (what, key)
+
+
+def both(orc, m, o, d, th, ph, bmax):
+    k, tv, pv = orc.frame(th, ph)
+    a = orc.trace(m, o, d, pv, tv, k, bmax, want_path=True)
+    b = orc.trace(m, o, d, pv, tv, k, bmax, want_path=True, use_bvh=True)
+    return a, b
+
+
+def test_sphere_every_ray(orc):
+    """The sphere case: icosphere of 20,480 triangles, 3 GHz, lambda/10, all
+    48,841 rays, both trees."""
+    w = si.sphere_case()
+    ds = C0 / float(w.freqs_hz[0]) / w.samples_per_lambda
+    for rule in ("sah", "median"):
+        m = orc.Mesh(w.V, w.T).build_bvh(rule)
+        o, d, nu, nv = orc.gen_rays(m.bbox, w.theta_deg[0], w.phi_deg[0], ds)
+        assert nu * nv == 48_841
+        a, b = both(orc, m, o, d, w.theta_deg[0], w.phi_deg[0], w.max_bounces)
+        same(a, b, rule)
+        assert 0.5 < (a["nb"] > 0).mean() < 0.7
+        assert b["tri_tests"] * 50 < a["tri_tests"]
+
+
+@pytest.mark.parametrize("phi", [0.0, 31.5, 90.0])
+def test_trihedral_angles(orc, phi):
+    """Three azimuths of the trihedral sweep (el 35.26 deg, 10 GHz, lambda/10):
+    at 0 and 90 degrees the rays run parallel to one face."""
+    w = si.trihedral_case()
+    m = orc.Mesh(w.V, w.T).build_bvh("sah")
+    ds = C0 / float(np.max(w.freqs_hz)) / w.samples_per_lambda
+    th = float(w.theta_deg[0])
+    o, d, nu, nv = orc.gen_rays(m.bbox, th, phi, ds)
+    assert nu * nv > 180_000
+    a, b = both(orc, m, o, d, th, phi, w.max_bounces)
+    same(a, b, phi)
+    assert (a["nb"] >= 2).sum() > 50_000
+
+
+@pytest.fixture(scope="module")
+def aircraft(orc):
+    w = si.aircraft_case()
+    return w, orc.Mesh(w.V, w.T).build_bvh("sah")
+
+
+@pytest.mark.slow
+def test_aircraft_1e5_rays(orc, aircraft):
+    """10^5 seeded rays of the aircraft sweep (1.5 M triangles, el 0, 10 GHz,
+    lambda/8, 8 bounces): 25,000 per azimuth at 0, 90, 135 and 225 degrees (the
+    last two cross the symmetry seam where two mirror slivers meet), drawn
+    from the rays that meet the tree's root box so that every one is a real
+    query."""
+    w, m = aircraft
+    ds = C0 / float(np.max(w.freqs_hz)) / w.samples_per_lambda
+    rng = np.random.default_rng(2025)
+    total = hits = 0
+    for phi in (0.0, 90.0, 135.0, 225.0):
+        o, d, nu, nv = orc.gen_rays(m.bbox, 90.0, phi, ds)
+        # rays whose line meets the (padded) bounding box of the mesh
+        lo, hi = m.bbox[:3] - 1e-3, m.bbox[3:] + 1e-3
+        dd = np.where(d == 0, 1e-30, d).astype(np.float64)
+        t0 = (lo - o) / dd
+        t1 = (hi - o) / dd
+        near = np.minimum(t0, t1).max(axis=1)
+        far = np.maximum(t0, t1).min(axis=1)
+        cand = np.flatnonzero(near <= far)
+        ids = np.sort(rng.choice(cand, 25_000, replace=False))
+        a, b = both(orc, m, o[ids], d, 90.0, phi, w.max_bounces)
+        same(a, b, phi)
+        total += len(ids)
+        hits += int((a["nb"] > 0).sum())
+    assert total == 100_000 and hits > 20_000
+
+
+def test_aircraft_seam_rays(orc, aircraft):
+    """The two seam rays where the nearer of two mirror slivers has a float32
+    hit point ~1e-4 m off its own box: brute force and fast mode agree, with
+    the rule's widening (P = 2^-20 M) the nearer sliver is accepted."""
+    w, m = aircraft
+    for phi, ray in ((135.0, 2869565), (225.0, 2871510)):
+        o, d, _, _ = orc.gen_rays(m.bbox, 90.0, phi, C0 / 10e9 / 8)
+        a, b = both(orc, m, o[ray:ray + 1], d, 90.0, phi, w.max_bounces)
+        same(a, b, phi)
+        assert a["tri_first"][0] in (1164872, 1192872) and a["nb"][0] == 1
+
+
+@pytest.mark.parametrize("case", ["sphere", "trihedral"])
+def test_box_rule_refuses_no_well_conditioned_hit(orc, case):
+    """Brute force with and without the hit rule's box test agree on every
+    ray of the sphere grid and of a trihedral angle: the rule only removes
+    hits whose float32 point has drifted off the triangle."""
+    if case == "sphere":
+        w = si.sphere_case()
+        th, ph = w.theta_deg[0], w.phi_deg[0]
+    else:
+        w = si.trihedral_case()
+        th, ph = w.theta_deg[0], 17.0
+    m = orc.Mesh(w.V, w.T)
+    ds = C0 / float(np.max(w.freqs_hz)) / w.samples_per_lambda
+    o, d, _, _ = orc.gen_rays(m.bbox, th, ph, ds)
+    k, tv, pv = orc.frame(th, ph)
+    a = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True)
+    b = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True, mt_only=True)
+    same(a, b, case)

@@ -360,27 +360,6 @@ def test_bvh_fast_mode_bit_exact(orc, rule):
         assert b["tri_tests"] < a["tri_tests"]
 
 
-def test_bvh_fast_mode_keeps_the_nearer_sliver_on_a_seam(orc):
-    """Two mirror-image sliver triangles of the aircraft meet on its symmetry
-    plane.  A ray crossing the seam at 135 (or 225) degrees hits both; the
-    float32 intersection t of the nearer one lies ~1e-4 m in front of that
-    triangle's own padded box, so the fast mode must not skip boxes that start
-    just beyond the best hit.  With the median tree it kept the farther sliver
-    before the culling margin covered this."""
-    w = si.aircraft_case()
-    m = orc.Mesh(w.V, w.T).build_bvh("median", 1, 16)
-    for phi, ray in ((135.0, 2869565), (225.0, 2871510)):
-        k, tv, pv = orc.frame(90.0, phi)
-        o, d, _, _ = orc.gen_rays(m.bbox, 90.0, phi, C0 / 10e9 / 8)
-        o = o[ray:ray + 1]
-        a = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True)
-        b = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True, use_bvh=True)
-        for key in KEYS + ("tri_path",):
-            assert np.array_equal(a[key], b[key]), (phi, key)
-        # the configuration: both slivers are hit, the lower-t one is kept
-        assert a["tri_first"][0] in (1164872, 1192872) and a["nb"][0] == 1
-
-
 def test_pricing_mask_drops_only_brute_force_misses():
     """The primary-ray mask that prices masked sweeps (leaf boxes of the
     oracle's SAH tree projected onto 8 x 8-ray cells) drops only rays that the
