@@ -38,30 +38,22 @@ METRIC = "rays*bounces/s + RCS angles/s at <=0.05 dB vs oracle; surrogate vs pla
 # trihedral sweep: box and triangle tests and hits per query of the oracle's
 # binned-SAH BVH (4 triangles per leaf, 16 bins), every 10th angle
 # (`python -m oracle.visit_counts`).
-REF_VISITS = {1: (14.09, 2.41, 0.677), 2: (23.25, 3.34, 0.928), 3: (19.89, 1.96, 0.541),
-              4: (11.97, 0.02, 0.0), 5: (0.0, 0.0, 0.0)}
+REF_VISITS = {1: (14.092, 2.407, 0.6774), 2: (23.162, 3.327, 0.9282), 3: (19.845, 1.951, 0.5408), 4: (11.966, 0.023, 0.0), 5: (0.0, 0.0, 0.0)}
 # The same on the 1.5 M-triangle aircraft sweep: every 45th of its 360
 # azimuths, 200,000 seeded rays of each (`python -m oracle.visit_counts
 # --aircraft`).
-REF_VISITS_AIRCRAFT = {1: (18.686, 1.370, 0.2516), 2: (53.527, 4.864, 0.0836), 3: (60.471, 5.368, 0.2803),
-                       4: (67.081, 6.678, 0.6555), 5: (68.911, 6.138, 0.8434), 6: (78.534, 7.216, 0.9329),
-                       7: (67.586, 5.829, 0.6012), 8: (66.504, 6.346, 0.5812)}
+REF_VISITS_AIRCRAFT = {1: (18.616, 1.33, 0.2516), 2: (53.579, 4.893, 0.0836), 3: (60.512, 5.409, 0.2803), 4: (67.134, 6.713, 0.6555), 5: (68.942, 6.154, 0.8434), 6: (78.66, 7.243, 0.9329), 7: (67.706, 5.842, 0.6012), 8: (66.383, 6.32, 0.5812)}
 # The same on the 64-scene batch: 64 items drawn in proportion to their rays,
 # 20,000 seeded rays of each (`python -m oracle.visit_counts --batch`).
-REF_VISITS_BATCH = {1: (20.201, 2.204, 0.2682), 2: (48.168, 6.442, 0.0506), 3: (57.043, 8.326, 0.1284),
-                    4: (68.321, 10.404, 0.3818), 5: (71.418, 10.881, 0.4266), 6: (74.625, 11.287, 0.4904)}
+REF_VISITS_BATCH = {1: (20.15, 2.173, 0.2682), 2: (48.174, 6.447, 0.0506), 3: (57.054, 8.329, 0.1284), 4: (68.309, 10.402, 0.3818), 5: (71.437, 10.884, 0.4266), 6: (74.614, 11.303, 0.4904)}
 # The same over the rays a primary-ray mask keeps (8 x 8-ray cells touched
 # by a projected leaf box of the oracle's tree): the sweeps' default.  Later
 # bounces equal the all-ray figures (only hits bounce); the oracle's masks
 # keep 72 % of the trihedral's, 26 % of the aircraft's and 29 % of the
 # batch's primary rays.
-REF_VISITS_UNMASKED = {1: (19.176, 3.341, 0.9406), 2: (23.248, 3.345, 0.9282), 3: (19.887, 1.955, 0.5408),
-                       4: (11.966, 0.023, 0.0), 5: (0.0, 0.0, 0.0)}
-REF_VISITS_AIRCRAFT_UNMASKED = {1: (53.375, 5.299, 0.9734), 2: (53.527, 4.864, 0.0836), 3: (60.471, 5.368, 0.2803),
-                                4: (67.081, 6.678, 0.6555), 5: (68.911, 6.138, 0.8434), 6: (78.534, 7.216, 0.9329),
-                                7: (67.586, 5.829, 0.6012), 8: (66.504, 6.346, 0.5812)}
-REF_VISITS_BATCH_UNMASKED = {1: (53.718, 7.731, 0.9405), 2: (48.168, 6.442, 0.0506), 3: (57.043, 8.326, 0.1284),
-                             4: (68.321, 10.404, 0.3818), 5: (71.418, 10.881, 0.4266), 6: (74.625, 11.287, 0.4904)}
+REF_VISITS_UNMASKED = {1: (19.159, 3.339, 0.9397), 2: (23.162, 3.327, 0.9282), 3: (19.845, 1.951, 0.5408), 4: (11.966, 0.023, 0.0), 5: (0.0, 0.0, 0.0)}
+REF_VISITS_AIRCRAFT_UNMASKED = {1: (53.104, 5.144, 0.9734), 2: (53.579, 4.893, 0.0836), 3: (60.512, 5.409, 0.2803), 4: (67.134, 6.713, 0.6555), 5: (68.942, 6.154, 0.8434), 6: (78.66, 7.243, 0.9329), 7: (67.706, 5.842, 0.6012), 8: (66.383, 6.32, 0.5812)}
+REF_VISITS_BATCH_UNMASKED = {1: (53.538, 7.62, 0.9405), 2: (48.174, 6.447, 0.0506), 3: (57.054, 8.329, 0.1284), 4: (68.309, 10.402, 0.3818), 5: (71.437, 10.884, 0.4266), 6: (74.614, 11.303, 0.4904)}
 # VALU lane operations per unit of traversal work, the survey's constants
 # (midpoints of its ranges): a slab test of one box 14 (6 FMA, min/max of the
 # three slabs, the compare), a triangle test 40 (the float32
@@ -481,7 +473,7 @@ def bench_surrogate(args):
         "config": {"workload": "surrogate_%s_3600x512" % args.target, "train": "360 x 64", "query": "3600 x 512",
                    "tiles": "1 deg x 32 f", "probes": "1 direction x 2 f per tile", "tol_db": 0.25,
                    "floor_db": 40.0, "audit_floor_db": 30.0, "epochs": 40, "batch": 4096, "lr": 4e-3},
-        "plain_points_per_s": n / tp, "plain_ms": 1e3 * tp, "gain": tp / ts,
+        "plain_points_per_s": n / tp, "plain_ms": 1e3 * tp, "gain": tp / ts, "beats_plain_sbr": bool(tp > ts),
         "fallback_tile_frac": float(fb.mean()), "stage_s": {k: v for k, v in info.items() if k.startswith("s_")},
         "fill_ms": {k: v for k, v in info["fill"].items() if k.startswith("ms_")},
         "final_loss": float(info["loss"][-1]), "audit_vs_plain": audit,

@@ -88,6 +88,11 @@ enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
 #define SBR_OPT_FP32_PATH 128         /* precision study of Sec. 6, not the method: the path P, the
                                          distance D and the phase k D in float32 instead of float64
                                          (sbr_trace and sbr_rcs_sweep; batches refuse it) */
+#define SBR_OPT_FP64_TRAVERSE 256     /* precision and timing study of Sec. 6 (its single vs double
+                                         precision trace times), not the method: box and
+                                         triangle tests in float64 (hits then differ from the
+                                         float32 specification by rounding); streaming schedule
+                                         of sbr_trace and sbr_rcs_sweep only */
 
 /* ------------------------------------------------------------------------ */
 /* Library and context                                                       */

@@ -602,6 +602,8 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
     RayQueue qa{}, qb{};
     int32_t *spill;
     const int sched = schedule_of(flags);
+    if ((flags & SBR_OPT_FP64_TRAVERSE) && sched != kScheduleStream)
+        return fail(SBR_ERR_UNSUPPORTED, "sbr_trace: SBR_OPT_FP64_TRAVERSE runs on the streaming schedule only");
     const sbr_tune tune = default_tune();
     const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
     if ((rc = get_counters(ws, cn)) || (rc = get_spill(ctx, bvh, blocks, &spill))) return rc;
@@ -884,6 +886,8 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     int32_t *spill;
     void *dplans, *dtile, *dang, *dkf, *dpart, *hpin, *dmask = nullptr;
     const int sched = tune.schedule;
+    if ((sw->flags & SBR_OPT_FP64_TRAVERSE) && sched != kScheduleStream)
+        return fail(SBR_ERR_UNSUPPORTED, "sbr_rcs_sweep: SBR_OPT_FP64_TRAVERSE runs on the streaming schedule only");
     const bool use_mask = !(sw->flags & SBR_OPT_NO_MASK);
     const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
     const size_t tile_words = static_cast<size_t>(na + n_chunks);

@@ -479,8 +479,9 @@ extern "C" int sbr_batch_create(sbr_ctx *ctx, const sbr_bvh *scenes, const sbr_b
             return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: tune->struct_size too small");
         tune = *d->tune;
     }
-    if (d->flags & SBR_OPT_FP32_PATH)
-        return fail(SBR_ERR_UNSUPPORTED, "sbr_batch_create: SBR_OPT_FP32_PATH is a study option of sweeps and traces");
+    if (d->flags & (SBR_OPT_FP32_PATH | SBR_OPT_FP64_TRAVERSE))
+        return fail(SBR_ERR_UNSUPPORTED,
+                    "sbr_batch_create: SBR_OPT_FP32_PATH and SBR_OPT_FP64_TRAVERSE are study options of sweeps and traces");
     if (d->flags & SBR_OPT_WAVEFRONT) tune.schedule = kScheduleWavefront;
     int rc = normalize_tune(tune);
     if (rc) return rc;

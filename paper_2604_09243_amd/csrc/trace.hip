@@ -129,59 +129,77 @@ struct Ray {
     double P, comp, kdo;
 };
 
-struct Best {
-    float t;
+// Closest hit so far.  R is the traversal's arithmetic: float32 (the
+// method) or float64 (the precision study SBR_OPT_FP64_TRAVERSE).
+template <typename R>
+struct BestT {
+    R t;
     int id;
     int slot;
 #ifdef SBR_TRACE_COUNTERS
     unsigned nodes, leaves, tris, wnode, wleaf;
 #endif
 };
+using Best = BestT<float>;
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float minR(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double minR(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float maxR(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double maxR(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float rcpR(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcpR(double x) { return 1.0 / x; }
 
 __device__ __forceinline__ bool wave_leader()
 {
     return static_cast<int>(threadIdx.x & 63) == __ffsll(static_cast<unsigned long long>(__ballot(1))) - 1;
 }
 
-__device__ __forceinline__ bool tri_test(const BTri &tr, const Ray &r, float &t_out)
+template <typename R>
+__device__ __forceinline__ bool tri_test(const BTri &tr, const Ray &r, R &t_out)
 {
-    const float e1x = tr.p1.x, e1y = tr.p1.y, e1z = tr.p1.z;
-    const float e2x = tr.p2.x, e2y = tr.p2.y, e2z = tr.p2.z;
-    const float px = r.dy * e2z - r.dz * e2y;
-    const float py = r.dz * e2x - r.dx * e2z;
-    const float pz = r.dx * e2y - r.dy * e2x;
-    const float det = (e1x * px + e1y * py) + e1z * pz;
-    if (det == 0.0f) return false;
-    const float sx = r.ox - tr.p0.x, sy = r.oy - tr.p0.y, sz = r.oz - tr.p0.z;
-    const float un = (sx * px + sy * py) + sz * pz;
-    const float qx = sy * e1z - sz * e1y;
-    const float qy = sz * e1x - sx * e1z;
-    const float qz = sx * e1y - sy * e1x;
-    const float vn = (r.dx * qx + r.dy * qy) + r.dz * qz;
-    const float tn = (e2x * qx + e2y * qy) + e2z * qz;
-    const float inv = 1.0f / det;
-    const float u = un * inv, v = vn * inv, t = tn * inv;
+    const R e1x = tr.p1.x, e1y = tr.p1.y, e1z = tr.p1.z;
+    const R e2x = tr.p2.x, e2y = tr.p2.y, e2z = tr.p2.z;
+    const R dx = r.dx, dy = r.dy, dz = r.dz;
+    const R px = dy * e2z - dz * e2y;
+    const R py = dz * e2x - dx * e2z;
+    const R pz = dx * e2y - dy * e2x;
+    const R det = (e1x * px + e1y * py) + e1z * pz;
+    if (det == R(0)) return false;
+    const R sx = R(r.ox) - R(tr.p0.x), sy = R(r.oy) - R(tr.p0.y), sz = R(r.oz) - R(tr.p0.z);
+    const R un = (sx * px + sy * py) + sz * pz;
+    const R qx = sy * e1z - sz * e1y;
+    const R qy = sz * e1x - sx * e1z;
+    const R qz = sx * e1y - sy * e1x;
+    const R vn = (dx * qx + dy * qy) + dz * qz;
+    const R tn = (e2x * qx + e2y * qy) + e2z * qz;
+    const R inv = R(1) / det;
+    const R u = un * inv, v = vn * inv, t = tn * inv;
     t_out = t;
-    return u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f && t < INFINITY;
+    return u >= R(0) && v >= R(0) && u + v <= R(1) && t > R(0) && t < R(INFINITY);
 }
 
-// The hit rule's box test: the float32 hit point o + t d (the bounce update's
-// point) inside the triangle's box widened by P on every axis.
-__device__ __forceinline__ bool in_box(const BTri &tr, const Ray &r, float t, float P)
+// The hit rule's box test: the hit point o + t d (the bounce update's
+// point; float32 in the method) inside the triangle's box widened by P on
+// every axis.
+template <typename R>
+__device__ __forceinline__ bool in_box(const BTri &tr, const Ray &r, R t, float P)
 {
-    const float x = r.ox + t * r.dx, y = r.oy + t * r.dy, z = r.oz + t * r.dz;
+    const R x = R(r.ox) + t * R(r.dx), y = R(r.oy) + t * R(r.dy), z = R(r.oz) + t * R(r.dz);
     float lx, hx, ly, hy, lz, hz;
     spec_box_axis(tr.p0.x, tr.p1.x, tr.p2.x, P, lx, hx);
     spec_box_axis(tr.p0.y, tr.p1.y, tr.p2.y, P, ly, hy);
     spec_box_axis(tr.p0.z, tr.p1.z, tr.p2.z, P, lz, hz);
-    return x >= lx && x <= hx && y >= ly && y <= hy && z >= lz && z <= hz;
+    return x >= R(lx) && x <= R(hx) && y >= R(ly) && y <= R(hy) && z >= R(lz) && z <= R(hz);
 }
 
 // strict: apply the box rule to every candidate (the re-traversal).
-__device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r, Best &b, bool strict, float P)
+template <typename R>
+__device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r, BestT<R> &b, bool strict, float P)
 {
     const int id = __float_as_int(tr.p0.w);
-    float t;
+    R t;
     if (tri_test(tr, r, t) && id != r.prev && (t < b.t || (t == b.t && id < b.id)) &&
         (!strict || in_box(tr, r, t, P))) {
         b.t = t;
@@ -262,8 +280,8 @@ __device__ __forceinline__ bool wave_uniform(int v, int &v0)
 
 // The triangles [first, first + cnt) of a leaf, cnt <= 4, each 48-byte
 // record loaded one test ahead.
-template <typename TriPtr>
-__device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, const Ray &r, Best &b, bool strict,
+template <typename TriPtr, typename R>
+__device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, const Ray &r, BestT<R> &b, bool strict,
                                                float P)
 {
     SBR_COUNT(b.leaves += 1; b.tris += cnt);
@@ -279,7 +297,8 @@ __device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, 
 }
 
 // Leaf `code` (first triangle << 3 | count - 1).
-__device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &r, Best &b, bool strict, float P)
+template <typename R>
+__device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &r, BestT<R> &b, bool strict, float P)
 {
     int c0;
     if (wave_uniform(code, c0))
@@ -291,22 +310,22 @@ __device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &
 // Entry and exit distances of the ray (inverse direction i, origin terms l
 // for the low and h for the high planes of each axis) through both child
 // boxes of node n, the exit clamped to tlim.
-__device__ __forceinline__ void node_boxes(const BNode &n, float ix, float iy, float iz, float lx, float ly, float lz,
-                                           float hx, float hy, float hz, float tlim, float &t0, float &u0, float &t1,
-                                           float &u1, int &cx, int &cy)
+template <typename R>
+__device__ __forceinline__ void node_boxes(const BNode &n, R ix, R iy, R iz, R lx, R ly, R lz, R hx, R hy, R hz,
+                                           R tlim, R &t0, R &u0, R &t1, R &u1, int &cx, int &cy)
 {
     // child 0: lo = (a.x, a.y, a.z), hi = (a.w, b.x, b.y)
-    const float ax0 = __builtin_fmaf(n.a.x, ix, -lx), ax1 = __builtin_fmaf(n.a.w, ix, -hx);
-    const float ay0 = __builtin_fmaf(n.a.y, iy, -ly), ay1 = __builtin_fmaf(n.b.x, iy, -hy);
-    const float az0 = __builtin_fmaf(n.a.z, iz, -lz), az1 = __builtin_fmaf(n.b.y, iz, -hz);
-    t0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-    u0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tlim));
+    const R ax0 = fmaR(R(n.a.x), ix, -lx), ax1 = fmaR(R(n.a.w), ix, -hx);
+    const R ay0 = fmaR(R(n.a.y), iy, -ly), ay1 = fmaR(R(n.b.x), iy, -hy);
+    const R az0 = fmaR(R(n.a.z), iz, -lz), az1 = fmaR(R(n.b.y), iz, -hz);
+    t0 = maxR(maxR(minR(ax0, ax1), minR(ay0, ay1)), maxR(minR(az0, az1), R(0)));
+    u0 = minR(minR(maxR(ax0, ax1), maxR(ay0, ay1)), minR(maxR(az0, az1), tlim));
     // child 1: lo = (b.z, b.w, c.x), hi = (c.y, c.z, c.w)
-    const float bx0 = __builtin_fmaf(n.b.z, ix, -lx), bx1 = __builtin_fmaf(n.c.y, ix, -hx);
-    const float by0 = __builtin_fmaf(n.b.w, iy, -ly), by1 = __builtin_fmaf(n.c.z, iy, -hy);
-    const float bz0 = __builtin_fmaf(n.c.x, iz, -lz), bz1 = __builtin_fmaf(n.c.w, iz, -hz);
-    t1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-    u1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tlim));
+    const R bx0 = fmaR(R(n.b.z), ix, -lx), bx1 = fmaR(R(n.c.y), ix, -hx);
+    const R by0 = fmaR(R(n.b.w), iy, -ly), by1 = fmaR(R(n.c.z), iy, -hy);
+    const R bz0 = fmaR(R(n.c.x), iz, -lz), bz1 = fmaR(R(n.c.w), iz, -hz);
+    t1 = maxR(maxR(minR(bx0, bx1), minR(by0, by1)), maxR(minR(bz0, bz1), R(0)));
+    u1 = minR(minR(maxR(bx0, bx1), maxR(by0, by1)), minR(maxR(bz0, bz1), tlim));
     cx = n.ch.x;
     cy = n.ch.y;
 }
@@ -339,27 +358,27 @@ __device__ __forceinline__ SceneRef scene_of(const Params &p, const Ray &r)
 // One traversal for the closest hit of ray r, skipping triangle r.prev;
 // strict: candidates must pass the hit rule's box test.  FAR: widen the slab
 // values for an origin beyond the BVH guard's bound (caller rays).
-template <bool SPILL, bool FAR>
-__device__ __forceinline__ Best traverse(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc,
-                                         bool strict)
+template <bool SPILL, bool FAR, typename R>
+__device__ __forceinline__ BestT<R> traverse(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc,
+                                             bool strict)
 {
-    Best b;
+    BestT<R> b;
     b.t = INFINITY;
     b.id = 0x7fffffff;
     b.slot = -1;
     SBR_COUNT(b.nodes = b.leaves = b.tris = b.wnode = b.wleaf = 0);
     const float tiny = 1e-20f;
-    const float ddx = fabsf(r.dx) < tiny ? copysignf(tiny, r.dx) : r.dx;
-    const float ddy = fabsf(r.dy) < tiny ? copysignf(tiny, r.dy) : r.dy;
-    const float ddz = fabsf(r.dz) < tiny ? copysignf(tiny, r.dz) : r.dz;
-    const float ix = __builtin_amdgcn_rcpf(ddx), iy = __builtin_amdgcn_rcpf(ddy), iz = __builtin_amdgcn_rcpf(ddz);
-    float lx = r.ox * ix, ly = r.oy * iy, lz = r.oz * iz;
-    float hx = lx, hy = ly, hz = lz;
+    const R ddx = fabsf(r.dx) < tiny ? copysignf(tiny, r.dx) : r.dx;
+    const R ddy = fabsf(r.dy) < tiny ? copysignf(tiny, r.dy) : r.dy;
+    const R ddz = fabsf(r.dz) < tiny ? copysignf(tiny, r.dz) : r.dz;
+    const R ix = rcpR(ddx), iy = rcpR(ddy), iz = rcpR(ddz);
+    R lx = R(r.ox) * ix, ly = R(r.oy) * iy, lz = R(r.oz) * iz;
+    R hx = lx, hy = ly, hz = lz;
     if constexpr (FAR) {
         // near planes earlier, far planes later by 8 2^-24 (|o| - obound) / |d|
-        const float gx = kGuardUlps * fmaxf(fabsf(r.ox) - p.obound, 0.0f) * ix;
-        const float gy = kGuardUlps * fmaxf(fabsf(r.oy) - p.obound, 0.0f) * iy;
-        const float gz = kGuardUlps * fmaxf(fabsf(r.oz) - p.obound, 0.0f) * iz;
+        const R gx = R(kGuardUlps * fmaxf(fabsf(r.ox) - p.obound, 0.0f)) * ix;
+        const R gy = R(kGuardUlps * fmaxf(fabsf(r.oy) - p.obound, 0.0f)) * iy;
+        const R gz = R(kGuardUlps * fmaxf(fabsf(r.oz) - p.obound, 0.0f)) * iz;
         lx += gx; hx -= gx;
         ly += gy; hy -= gy;
         lz += gz; hz -= gz;
@@ -370,7 +389,7 @@ __device__ __forceinline__ Best traverse(const Params &p, const Ray &r, Stack<SP
         // phase 1: descend through internal nodes until a leaf (or nothing) is next
         while (cur >= 0) {
             SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
-            float t0, u0, t1, u1;
+            R t0, u0, t1, u1;
             int cx, cy, c0;
             if (wave_uniform(cur, c0))
                 node_boxes(node_scalar(p.nodes, c0), ix, iy, iz, lx, ly, lz, hx, hy, hz, b.t, t0, u0, t1, u1, cx, cy);
@@ -413,12 +432,12 @@ __device__ __forceinline__ Best traverse(const Params &p, const Ray &r, Stack<SP
 
 // Closest hit of ray r under the hit rule: one traversal, and a strict second
 // one in the rare case that the first one's winner fails the box test.
-template <bool SPILL, bool FAR = false>
-__device__ Best closest(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc)
+template <bool SPILL, bool FAR = false, typename R = float>
+__device__ BestT<R> closest(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc)
 {
-    Best b;
+    BestT<R> b;
     for (int pass = 0;; ++pass) {
-        b = traverse<SPILL, FAR>(p, r, st, sc, pass != 0);
+        b = traverse<SPILL, FAR, R>(p, r, st, sc, pass != 0);
         if (pass != 0 || b.slot < 0 || in_box(p.tris[b.slot], r, b.t, sc.pbox)) break;
     }
     return b;
@@ -588,16 +607,19 @@ struct Last {
 // reflection of the direction and of both field vectors, and the new origin
 // eps off the surface on the side the ray came from.  Returns whether the
 // ray has bounces left.
-__device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, const K3 &kv, const float eps, Last &L)
+template <typename R>
+__device__ __forceinline__ bool bounce(const Params &p, Ray &r, const BestT<R> &b, const K3 &kv, const float eps,
+                                       Last &L)
 {
-    const float t = b.t;
-    L.xlx = r.ox + t * r.dx;
-    L.xly = r.oy + t * r.dy;
-    L.xlz = r.oz + t * r.dz;
+    const R tr = b.t;
+    L.xlx = static_cast<float>(R(r.ox) + tr * R(r.dx));
+    L.xly = static_cast<float>(R(r.oy) + tr * R(r.dy));
+    L.xlz = static_cast<float>(R(r.oz) + tr * R(r.dz));
+    const float t = static_cast<float>(tr);
     int N = r.meta & 127;
     const bool f32 = (p.flags & SBR_OPT_FP32_PATH) != 0;  // precision study: path, offset term and D in float32
     if (!f32) {
-        r.P = r.P + static_cast<double>(t);
+        r.P = r.P + static_cast<double>(tr);
         if (N >= 1 && !(p.flags & SBR_OPT_PAPER_PATH)) r.P = r.P + r.comp;
     } else {
         float P32 = static_cast<float>(r.P) + t;
@@ -653,8 +675,8 @@ __device__ __forceinline__ bool bounce(const Params &p, Ray &r, const Best &b, c
     return N < p.bmax;
 }
 
-template <int U = -1>
-__device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Best &b, const Last &L)
+template <int U = -1, typename R = float>
+__device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const BestT<R> &b, const Last &L)
 {
     const int N = r.meta & 127;
     if (user_rays<U>(p)) {
@@ -746,7 +768,8 @@ struct BlockStats {
     unsigned long long diag[6];
 };
 
-__device__ __forceinline__ void count_query(BlockStats &bs, const Best &b)
+template <typename R>
+__device__ __forceinline__ void count_query(BlockStats &bs, const BestT<R> &b)
 {
 #ifdef SBR_TRACE_COUNTERS
     atomicAdd(&bs.diag[0], static_cast<unsigned long long>(b.nodes));
@@ -787,8 +810,11 @@ __device__ __forceinline__ void init_stats(BlockStats &bs)
 // ---------------------------------------------------------------------------
 // STREAM schedule
 // ---------------------------------------------------------------------------
-template <int SRC, bool SPILL>  // SRC: 0 = angle grid, 1 = caller rays
-__global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_stream(Params p)
+// (The float64 study variant holds twice the registers of the traversal
+// state: three waves per SIMD instead of spilling.)
+template <int SRC, bool SPILL, typename R = float>  // SRC: 0 = angle grid, 1 = caller rays; R: see BestT
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD))) void k_stream(Params p)
 {
     constexpr int kUser = SRC == 1;  // caller rays in, hit arrays out (else an angle grid and sweep records)
     __shared__ int lds_stack[(SPILL ? kStackSpillLds : kStackLds) * kBlock];
@@ -849,11 +875,11 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_stream(Params p)
         if (__ballot(has) == 0) break;
 
         // ---- one bounce for every lane holding a ray
-        Best b;
+        BestT<R> b;
         b.slot = -1;
         SceneRef sc{0, 0.f, 0.f};
         if (has) sc = scene_of<kUser>(p, r);
-        if (has) b = closest<SPILL, SRC == 1>(p, r, st, sc);
+        if (has) b = closest<SPILL, SRC == 1, R>(p, r, st, sc);
         if (has) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (has) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         if (has) {
@@ -866,7 +892,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_stream(Params p)
                 if (!cont) {
                     int fl = L.flags;
                     if (p.flags & SBR_OPT_DROP_TRAPPED) {
-                        const Best b2 = closest<SPILL, SRC == 1>(p, r, st, sc);
+                        const BestT<R> b2 = closest<SPILL, SRC == 1, R>(p, r, st, sc);
                         atomicAdd(&bs.queries, 1u);
                         if (b2.slot >= 0) {  // trapped: flagged and dropped from the PO sum
                             if (kUser) flag_trapped<kUser>(p, r);
@@ -1161,8 +1187,13 @@ static void launch_trace_t(hipStream_t s, const TraceArgs &a, const Params &p, i
 {
     const bool user = a.hits != nullptr;
     if (a.schedule == kScheduleStream) {
-        if (user) k_stream<1, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
-        else k_stream<0, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+        if (a.flags & SBR_OPT_FP64_TRAVERSE) {
+            if (user) k_stream<1, SPILL, double><<<a.blocks, kBlock, 0, s>>>(p);
+            else k_stream<0, SPILL, double><<<a.blocks, kBlock, 0, s>>>(p);
+        } else {
+            if (user) k_stream<1, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+            else k_stream<0, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
+        }
     } else if (bounce == 1) {
         if (user) k_wave<1, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
         else k_wave<0, SPILL><<<a.blocks, kBlock, 0, s>>>(p);

@@ -25,6 +25,7 @@ REC_VALID, REC_TRAPPED, REC_BACK_LAST = 1, 2, 4
 OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRONT, OPT_NO_GRAPH = 1, 2, 4, 8, 16, 32
 OPT_NO_MASK = 64
 OPT_FP32_PATH = 128
+OPT_FP64_TRAVERSE = 256
 MAX_BOUNCES = 127
 
 _vp = C.c_void_p
@@ -608,7 +609,8 @@ class Context:
                       eH_last=torch.float32, eV_last=torch.float32)
         for name, dt in dtypes.items():
             if hits.get(name) is not None:
-                _dev_tensor(hits[name], name, dt, (n, 3) if name.endswith("_last") else (n,), self.device)
+                _dev_tensor(hits[name], name, dt, (n, 3) if name in ("d_last", "x_last", "eH_last", "eV_last")
+                            else (n,), self.device)
         h = self._hits(hits)
         _check(load_library().sbr_po_integrate(self.handle, bvh.handle, C.byref(h), n, C.byref(desc),
                                                freqs.ctypes.data, nf, A.data_ptr()))

@@ -234,7 +234,7 @@ def test_full_batch_identical_across_builders(torch, ctx, full):
 # Items whose rows differed between trees before the hit rule's box test
 # made the closest hit tree-independent (found by comparing the three trees'
 # batches; the oracle, brute-force-pinned, decides them here).
-TREE_SENSITIVE_ITEMS = ()
+TREE_SENSITIVE_ITEMS = (5988, 7238)
 
 
 @pytest.mark.parametrize("group", [0, 1, 2, 3])
@@ -256,3 +256,31 @@ def test_full_batch_oracle_parity(torch, orc, full, group):
                                      w.samples_per_lambda)
             worst = max(worst, e)
     say("worst complex error", worst)
+
+
+@pytest.mark.parametrize("item,ray", [(5988, 4667867), (7238, 1895418)])
+def test_tree_sensitive_rays_on_every_builder(torch, ctx, orc, item, ray):
+    """The two rays whose closest hit depended on the tree before the hit
+    rule's box test: every GPU builder's tree gives the oracle's brute-force
+    result (ids at every bounce, hit point, phase path)."""
+    from paper_2604_09243_amd import sbr
+    say("case tree-sensitive ray of item", item)
+    w = si.batch_case(n_scenes=64)
+    items, fr = w.items(), w.freqs()
+    sc, th, ph, off, nf = items[item]
+    s = w.scenes[sc]
+    m = orc.Mesh(s.V, s.T)
+    ds = C0 / float(np.max(fr[off:off + nf])) / w.samples_per_lambda
+    o, d, _, _ = orc.gen_rays(m.bbox, th, ph, ds)
+    k, tv, pv = orc.frame(th, ph)
+    o = o[ray:ray + 1]
+    r = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True)
+    dev = torch.device("cuda", 0)
+    t = [torch.from_numpy(np.ascontiguousarray(np.broadcast_to(x, (1, 3)).astype(np.float32))).to(dev)
+         for x in (o, d, pv, tv)]
+    for builder in (sbr.BUILD_LBVH, sbr.BUILD_SAH, sbr.BUILD_PLOC):
+        bvh = ctx.build_bvh(s.V, s.T, builder=builder)
+        g = {kk: v.cpu().numpy() for kk, v in ctx.trace(bvh, *t, w.max_bounces, k, want_path=True).items()}
+        assert np.array_equal(r["tri_path"], g["tri_path"]), builder
+        assert np.array_equal(r["x_last"], g["x_last"]) and np.array_equal(r["D"], g["D"]), builder
+        bvh.free()

@@ -112,3 +112,45 @@ def test_fp32_path_refused_by_batches(torch, ctx):
     with pytest.raises(sbr.SbrError) as e:
         ctx.batch(bvh, [(0, 54.74, 45.0, 0, 1)], [10e9], 5, flags=sbr.OPT_FP32_PATH)
     assert e.value.status == sbr.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("case", ["trihedral", "aircraft"])
+def test_fp64_traversal_variant(torch, ctx, orc, case):
+    """The study variant SBR_OPT_FP64_TRAVERSE (box and triangle tests in
+    float64; the paper times single against double precision traces): its
+    RCS stays within the bar of the float32 specification's oracle on the
+    dominant returns, and its trace time is printed beside the float32
+    kernel's."""
+    from paper_2604_09243_amd import sbr
+    if case == "trihedral":
+        w = si.trihedral_case()
+        idx = [0, 45, 90, 135, 180]
+    else:
+        w = si.aircraft_case()
+        idx = [0, 90, 135, 270]
+    say("case fp64 traversal,", case)
+    bvh = ctx.build_bvh(w.V, w.T, builder=sbr.BUILD_SAH)
+    th, ph = w.theta_deg[idx], w.phi_deg[idx]
+    times = {}
+    A = {}
+    for name, fl in (("fp32", 0), ("fp64", sbr.OPT_FP64_TRAVERSE)):
+        ctx.rcs_sweep(bvh, th, ph, w.freqs_hz, w.max_bounces, samples_per_lambda=w.samples_per_lambda, flags=fl)
+        a, _, st = ctx.rcs_sweep(bvh, th, ph, w.freqs_hz, w.max_bounces, samples_per_lambda=w.samples_per_lambda,
+                                 flags=fl)
+        A[name] = a.cpu().numpy()
+        times[name] = st["ms_trace"]
+    m = orc.Mesh(w.V, w.T).build_bvh()
+    Ao = np.array([orc.rcs_angle(m, th[i], ph[i], w.freqs_hz, w.samples_per_lambda, bmax=w.max_bounces,
+                                 use_bvh=True)["A"] for i in range(len(idx))])
+    so = 10 * np.log10(np.maximum(4 * np.pi * np.abs(Ao) ** 2, 1e-300))
+    sel = so >= so.max() - 40
+    for name in ("fp32", "fp64"):
+        sg = 10 * np.log10(np.maximum(4 * np.pi * np.abs(A[name]) ** 2, 1e-300))
+        db = float(np.abs(so - sg)[sel].max())
+        say("  %s trace %.2f ms, max |d sigma| %.4f dB" % (name, times[name], db))
+        assert db <= 0.05, name
+    say("  fp64 / fp32 trace time %.2f" % (times["fp64"] / times["fp32"]))
+    with pytest.raises(sbr.SbrError):
+        ctx.rcs_sweep(bvh, th, ph, w.freqs_hz, w.max_bounces, samples_per_lambda=w.samples_per_lambda,
+                      flags=sbr.OPT_FP64_TRAVERSE | sbr.OPT_WAVEFRONT)
+    bvh.free()

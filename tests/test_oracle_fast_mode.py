@@ -121,3 +121,41 @@ def test_box_rule_refuses_no_well_conditioned_hit(orc, case):
     a = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True)
     b = orc.trace(m, o, d, pv, tv, k, w.max_bounces, want_path=True, mt_only=True)
     same(a, b, case)
+
+
+# (item, ray) of the 64-scene batch whose result depended on the tree before
+# the hit rule's box test: a ray grazing a sphere of scene 40 and one of the
+# ellipsoid assembly of scene 49.  Found by comparing the three GPU trees'
+# batches; what they compute here is the oracle's alone.
+BATCH_TREE_SENSITIVE = ((5988, 4667867), (7238, 1895418))
+
+
+def test_batch_tree_sensitive_rays(orc):
+    """On the two rays of the batch whose closest hit once depended on the
+    tree, the tree mode equals brute force; without the box rule brute force
+    would keep a different triangle, whose float32 hit point has drifted off
+    it (the hit the rule refuses)."""
+    w = si.batch_case()
+    items, fr = w.items(), w.freqs()
+    for ii, ray in BATCH_TREE_SENSITIVE:
+        sc, th, ph, off, nf = items[ii]
+        s = w.scenes[sc]
+        m = orc.Mesh(s.V, s.T).build_bvh()
+        ds = C0 / float(np.max(fr[off:off + nf])) / w.samples_per_lambda
+        o, d, _, _ = orc.gen_rays(m.bbox, th, ph, ds)
+        a, b = both(orc, m, o[ray:ray + 1], d, th, ph, w.max_bounces)
+        same(a, b, ii)
+        k, tv, pv = orc.frame(th, ph)
+        c = orc.trace(m, o[ray:ray + 1], d, pv, tv, k, w.max_bounces, want_path=True, mt_only=True)
+        assert a["nb"][0] >= 1 and c["tri_first"][0] != a["tri_first"][0]
+        # the refused hit's float32 point lies outside its triangle's box by more than P
+        j = int(c["tri_first"][0])
+        tri = np.asarray(s.V, np.float32)[np.asarray(s.T)[j]]
+        v0 = tri[0]
+        e1, e2 = tri[1] - tri[0], tri[2] - tri[0]
+        corners = np.stack([v0, v0 + e1, v0 + e2])
+        x = c["x_last"][0]
+        excess = np.maximum(corners.min(0) - x, x - corners.max(0)).max()
+        bb = m.bbox
+        M = (np.abs(bb).max() + np.abs(0.5 * (bb[:3] + bb[3:])).max()) + 1.5 * np.linalg.norm(bb[3:] - bb[:3])
+        assert excess > M * 2.0 ** -20, (ii, excess)

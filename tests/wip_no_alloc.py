@@ -1,0 +1,107 @@
+"""sbr_trace_noalloc (for callers that cannot allocate device memory): the
+same hits as sbr_trace, bit for bit, on two calls in a row (the second with
+fewer rays), from the library's static scratch; deep trees and the
+wavefront schedule are refused with a clear error."""
+import sys
+
+import numpy as np
+import pytest
+
+import sbr_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299_792_458.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2604_09243_amd import Context
+    return Context(0)
+
+
+def rays(torch, orc, bbox, th, ph, ds, n):
+    o, d, _, _ = orc.gen_rays(bbox, th, ph, ds)
+    k, tv, pv = orc.frame(th, ph)
+    o = o[np.sort(np.random.default_rng(n).choice(len(o), n, replace=False))]
+    dev = torch.device("cuda", 0)
+    t = [torch.from_numpy(np.ascontiguousarray(np.broadcast_to(x, (len(o), 3)).astype(np.float32))).to(dev)
+         for x in (o, d, pv, tv)]
+    return t, k
+
+
+def empty_hits(torch, n, bmax):
+    dev = torch.device("cuda", 0)
+    i32, f64, f32 = torch.int32, torch.float64, torch.float32
+    return dict(n_bounce=torch.empty(n, dtype=i32, device=dev), tri_first=torch.empty(n, dtype=i32, device=dev),
+                tri_last=torch.empty(n, dtype=i32, device=dev), flags=torch.empty(n, dtype=i32, device=dev),
+                path=torch.empty(n, dtype=f64, device=dev), D=torch.empty(n, dtype=f64, device=dev),
+                d_last=torch.empty(n, 3, dtype=f32, device=dev), x_last=torch.empty(n, 3, dtype=f32, device=dev),
+                eH_last=torch.empty(n, 3, dtype=f32, device=dev), eV_last=torch.empty(n, 3, dtype=f32, device=dev),
+                tri_path=torch.empty(n, bmax, dtype=i32, device=dev))
+
+
+@pytest.mark.parametrize("case", ["trihedral", "sphere"])
+def test_noalloc_equals_trace_on_two_calls(torch, ctx, orc, case):
+    if case == "trihedral":
+        V, T = si.trihedral(1.0, 16)
+        th, ph, ds, bmax = 54.74, 30.0, C0 / 10e9 / 10, 5
+    else:
+        V, T = si.icosphere(5)
+        th, ph, ds, bmax = 20.0, 40.0, C0 / 3e9 / 10, 5
+    say("case noalloc", case)
+    bvh = ctx.build_bvh(V, T)
+    m = orc.Mesh(V, T)
+    for n in (40_000, 9_001):  # the second call smaller
+        t, k = rays(torch, orc, m.bbox, th, ph, ds, n)
+        ref = ctx.trace(bvh, *t, bmax, k, want_path=True, stats=True)
+        out = empty_hits(torch, n, bmax)
+        for v in out.values():
+            v.fill_(-7)  # whatever the buffers held before
+        got = ctx.trace(bvh, *t, bmax, k, want_path=True, stats=True, out=out, noalloc=True)
+        torch.cuda.synchronize()
+        for key, v in ref.items():
+            if key == "stats":
+                continue
+            assert torch.equal(v, got[key]), (n, key)
+        rs, gs = ref["stats"], got["stats"]
+        for key in ("rays", "queries", "valid", "trapped", "hits", "queries_bounce", "masked", "chunks"):
+            assert rs[key] == gs[key], (n, key)
+        assert int((ref["n_bounce"] > 0).sum()) > n // 10
+        say("rays", n, "queries", gs["queries"])
+    bvh.free()
+
+
+def test_noalloc_refuses_what_its_scratch_cannot_hold(torch, ctx, orc):
+    from paper_2604_09243_amd import sbr
+    say("case noalloc refusals")
+    V, T = si.trihedral(1.0, 16)
+    bvh = ctx.build_bvh(V, T)
+    m = orc.Mesh(V, T)
+    t, k = rays(torch, orc, m.bbox, 54.74, 30.0, C0 / 10e9 / 10, 1000)
+    with pytest.raises(sbr.SbrError) as e:
+        ctx.trace(bvh, *t, 5, k, flags=sbr.OPT_WAVEFRONT, noalloc=True)
+    assert e.value.status == sbr.ERR_UNSUPPORTED
+    # a tree too deep for the static stack spill array: the aircraft's PLOC tree (depth ~52)
+    w = si.aircraft_case()
+    deep = ctx.build_bvh(w.V, w.T, builder=sbr.BUILD_PLOC)
+    assert deep.depth > 40
+    with pytest.raises(sbr.SbrError) as e:
+        ctx.trace(deep, *t, 5, k, noalloc=True)
+    assert e.value.status == sbr.ERR_UNSUPPORTED and "scratch" in str(e.value)
+    say("deep tree depth", deep.depth)
+    deep.free()
+    bvh.free()
