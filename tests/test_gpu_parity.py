@@ -337,7 +337,7 @@ def test_sweep_errors(torch, ctx):
     assert e.value.status == sbr.ERR_SAMPLING
     ctx.rcs_sweep(bvh, [45.0], [45.0], [10e9], 5, samples_per_lambda=4.0, flags=sbr.OPT_ALLOW_UNDERSAMPLING)
     with pytest.raises(sbr.SbrError) as e:
-        ctx.rcs_sweep(bvh, [45.0], [45.0], [10e9], 65)
+        ctx.rcs_sweep(bvh, [45.0], [45.0], [10e9], sbr.MAX_BOUNCES + 1)
     assert e.value.status == sbr.ERR_INVALID_ARG
     Vb = V.copy()
     Vb[3, 1] = np.nan
