@@ -269,6 +269,24 @@ typedef struct {
 int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays, int max_bounces,
               const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats);
 
+/* sbr_trace_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same transport, arguments and results as sbr_trace, bit
+ * for bit, but the call allocates nothing: its only scratch (the counter
+ * block of one streaming launch, 8 KiB) is a static array of the library,
+ * one copy per device, looked up when sbr_create sets up the device; the
+ * counters are cleared by a fill kernel (no memset node).  Limits: the
+ * streaming schedule only (SBR_OPT_WAVEFRONT -> SBR_ERR_UNSUPPORTED: its
+ * queues need memory) and trees no deeper than the on-chip traversal stack
+ * (28 levels; deeper -> SBR_ERR_UNSUPPORTED, use sbr_trace).  Every call on
+ * a device shares that device's scratch, which keeps the last call's
+ * contents: calls that overlap on one device (two streams, two threads)
+ * race and must be serialised by the caller.  stats (nullable) synchronises
+ * the stream and copies the counters to the host; its GPU times stay 0 (no
+ * events are created).  Errors as sbr_trace, plus UNSUPPORTED. */
+int sbr_trace_noalloc(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays, int max_bounces,
+                      const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats);
+
 /* ------------------------------------------------------------------------ */
 /* sbr_po_integrate -- ray-tube physical-optics sum (Eq. po_sum; em5-em6)    */
 /* ------------------------------------------------------------------------ */

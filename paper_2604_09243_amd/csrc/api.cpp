@@ -427,6 +427,13 @@ extern "C" int sbr_create(sbr_ctx **out, int device, void *hip_stream)
         delete c;
         return fail(SBR_ERR_HIP, "sbr_create: hipGetDeviceProperties failed");
     }
+    // the no-alloc trace's static scratch: this device's address, looked up once
+    int rc = noalloc_scratch_setup(device);
+    if (rc) {
+        delete c->ws;
+        delete c;
+        return rc;
+    }
     *out = c;
     return SBR_OK;
 }
@@ -574,26 +581,32 @@ extern "C" void sbr_free_bvh(sbr_bvh *bvh)
 }
 
 // ---------------------------------------------------------------- trace
-extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays, int max_bounces,
-                         const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats)
+// sbr_trace and sbr_trace_noalloc.  noalloc: the counter block lives in the
+// library's static per-device scratch, cleared by a fill kernel; nothing is
+// allocated (no workspace growth, no events), and what would need more
+// memory than the scratch holds (the wavefront schedule's queues, a stack
+// spill for deep trees) is refused.
+static int trace_impl(const char *fn, sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays,
+                      int max_bounces, const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats, bool noalloc)
 {
     const auto t_start = std::chrono::steady_clock::now();
-    if (!ctx || !bvh || !rays || !out) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: NULL argument");
+    const std::string f(fn);
+    if (!ctx || !bvh || !rays || !out) return fail(SBR_ERR_INVALID_ARG, f + ": NULL argument");
     if (!rays->o || !rays->d || !rays->eH || !rays->eV)
-        return fail(SBR_ERR_INVALID_ARG, "sbr_trace: rays->o, d, eH and eV are required");
-    if (n_rays < 1 || n_rays > 2147483647LL) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: n_rays out of range");
+        return fail(SBR_ERR_INVALID_ARG, f + ": rays->o, d, eH and eV are required");
+    if (n_rays < 1 || n_rays > 2147483647LL) return fail(SBR_ERR_INVALID_ARG, f + ": n_rays out of range");
     if (max_bounces < 1 || max_bounces > SBR_MAX_BOUNCES)
-        return fail(SBR_ERR_INVALID_ARG, "sbr_trace: max_bounces must be in [1, " + std::to_string(SBR_MAX_BOUNCES) + "]");
+        return fail(SBR_ERR_INVALID_ARG, f + ": max_bounces must be in [1, " + std::to_string(SBR_MAX_BOUNCES) + "]");
     uint32_t flags = 0;
     double k[3] = {0, 0, -1};
     if (opts) {
         if (opts->struct_size < sizeof(sbr_trace_opts))
-            return fail(SBR_ERR_INVALID_ARG, "sbr_trace: opts->struct_size too small");
+            return fail(SBR_ERR_INVALID_ARG, f + ": opts->struct_size too small");
         flags = opts->flags;
         for (int a = 0; a < 3; ++a) k[a] = opts->k_hat[a];
     }
-    if (bvh->device != ctx->device) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: BVH lives on another device");
-    if (!bvh->scenes.empty()) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: a multi-scene set serves batches only");
+    if (bvh->device != ctx->device) return fail(SBR_ERR_INVALID_ARG, f + ": BVH lives on another device");
+    if (!bvh->scenes.empty()) return fail(SBR_ERR_INVALID_ARG, f + ": a multi-scene set serves batches only");
     SBR_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     Workspace *ws = ctx->ws;
@@ -603,18 +616,34 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
     int32_t *spill;
     const int sched = schedule_of(flags);
     if ((flags & SBR_OPT_FP64_TRAVERSE) && sched != kScheduleStream)
-        return fail(SBR_ERR_UNSUPPORTED, "sbr_trace: SBR_OPT_FP64_TRAVERSE runs on the streaming schedule only");
+        return fail(SBR_ERR_UNSUPPORTED, f + ": SBR_OPT_FP64_TRAVERSE runs on the streaming schedule only");
     const sbr_tune tune = default_tune();
     const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
-    if ((rc = get_counters(ws, cn)) || (rc = get_spill(ctx, bvh, blocks, &spill))) return rc;
-    if (sched == kScheduleWavefront &&
-        ((rc = get_queue(ws, W_QA, n_rays, qa)) || (rc = get_queue(ws, W_QB, n_rays, qb))))
-        return rc;
-    if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_trace: the mesh has no non-degenerate triangle");
-    SBR_HIP(hipMemsetAsync(cn.base, 0, cn.bytes, s));
+    if (noalloc) {
+        if (sched != kScheduleStream)
+            return fail(SBR_ERR_UNSUPPORTED, f + ": the wavefront schedule needs ray queues beyond the static scratch");
+        if (trace_needs_spill(bvh))
+            return fail(SBR_ERR_UNSUPPORTED,
+                        f + ": the tree (depth " + std::to_string(bvh->depth) + ") needs more traversal stack "
+                            "than the on-chip one; the static scratch holds no stack spill (use sbr_trace)");
+        if ((rc = noalloc_counters(ctx->device, cn.p, &cn.base, &cn.bytes))) return rc;
+        spill = nullptr;  // never read: the tree fits the on-chip stack
+    } else {
+        if ((rc = get_counters(ws, cn)) || (rc = get_spill(ctx, bvh, blocks, &spill))) return rc;
+        if (sched == kScheduleWavefront &&
+            ((rc = get_queue(ws, W_QA, n_rays, qa)) || (rc = get_queue(ws, W_QB, n_rays, qb))))
+            return rc;
+    }
+    if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, f + ": the mesh has no non-degenerate triangle");
+    if (noalloc) {
+        if ((rc = launch_zero_u32(s, static_cast<uint32_t *>(cn.base), static_cast<int64_t>(cn.bytes / 4)))) return rc;
+    } else {
+        SBR_HIP(hipMemsetAsync(cn.base, 0, cn.bytes, s));
+    }
     const bool want_stats = stats != nullptr;
+    const bool timed = want_stats && !noalloc;
     std::vector<hipEvent_t> ev;
-    if (want_stats) {
+    if (timed) {
         ev.resize(max_bounces + 1);
         for (auto &e : ev) SBR_HIP(hipEventCreate(&e));
         SBR_HIP(hipEventRecord(ev[0], s));
@@ -634,7 +663,7 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
     for (int i = 0; i < 3; ++i) a.k_hat[i] = k[i];
     a.ctrs = cn.p;
     a.spill = spill;
-    if ((rc = run_trace(s, a, qa, qb, want_stats ? &ev : nullptr))) return rc;
+    if ((rc = run_trace(s, a, qa, qb, timed ? &ev : nullptr))) return rc;
     if (want_stats || (flags & SBR_OPT_SYNC)) {
         unsigned long long hstat[kStatU64];
         SBR_HIP(hipMemcpyAsync(hstat, cn.p.stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
@@ -644,7 +673,7 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
             stats->rays = n_rays;
             fill_stats(stats, hstat, max_bounces, n_rays, (flags & SBR_OPT_DROP_TRAPPED) != 0,
                        sched == kScheduleStream ? 1 : 0);
-            const int nl = sched == kScheduleStream ? 1 : max_bounces;
+            const int nl = !timed ? 0 : sched == kScheduleStream ? 1 : max_bounces;
             for (int b = 1; b <= nl; ++b) {
                 float ms = 0;
                 SBR_HIP(hipEventElapsedTime(&ms, ev[b - 1], ev[b]));
@@ -657,6 +686,18 @@ extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays,
         }
     }
     return SBR_OK;
+}
+
+extern "C" int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays, int max_bounces,
+                         const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats)
+{
+    return trace_impl("sbr_trace", ctx, bvh, rays, n_rays, max_bounces, opts, out, stats, false);
+}
+
+extern "C" int sbr_trace_noalloc(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_rays,
+                                 int max_bounces, const sbr_trace_opts *opts, sbr_hits *out, sbr_stats *stats)
+{
+    return trace_impl("sbr_trace_noalloc", ctx, bvh, rays, n_rays, max_bounces, opts, out, stats, true);
 }
 
 // ---------------------------------------------------------------- PO

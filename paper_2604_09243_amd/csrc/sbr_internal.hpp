@@ -278,6 +278,13 @@ struct TraceArgs {
 };
 // bounce = 1 for the stream schedule (one launch does every bounce)
 int launch_trace(hipStream_t s, const TraceArgs &a, int bounce);
+// Static scratch of the no-alloc trace (one per device, kNoallocScratchBytes):
+// noalloc_scratch_setup looks up this device's address (the device must be
+// current; done once by sbr_create); noalloc_counters lays the counter block
+// of one streaming launch over it (base and the bytes to clear).
+constexpr size_t kNoallocScratchBytes = 8192;
+int noalloc_scratch_setup(int device);
+int noalloc_counters(int device, CounterPtrs &c, void **base, size_t *bytes);
 // Builds the primary-ray mask of plans [0, n_angles) of one launch: zeroes
 // mask[0, mask_bytes) (a kernel, so usable inside a captured graph), then
 // marks every cell that the padded projection of a leaf box of the angle's

@@ -33,6 +33,8 @@
 // only in the (conservative) box test.
 #include <climits>
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "sbr_internal.hpp"
 
@@ -1216,6 +1218,64 @@ int launch_mask(hipStream_t s, const BNode *nodes, const AnglePlan *plans, int n
     if (blocks > 0)
         k_mask<<<static_cast<unsigned>(blocks), kMaskBlock, 0, s>>>(nodes, plans, n_angles, n_units, per, mask);
     SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of sbr_trace_noalloc (for callers that cannot allocate
+// device memory): the counter block of one streaming trace, laid out as
+//   [0, kStatBytes)               stat (u64 counters)
+//   2 lines                       q_cnt of launches 0 and 1 (not read by the
+//                                 streaming schedule, but addressed)
+//   16 lines                      claim counters of launches 0 and 1
+// Every device holds its own copy of the array at its own address.  In host
+// code the array's name is not a device address: the address of each
+// device's copy is looked up once, with that device current, and only that
+// pointer is handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoallocQcntOff = kStatBytes;
+constexpr size_t kNoallocClaimOff = kNoallocQcntOff + 2 * 4 * kLineU32;
+constexpr size_t kNoallocUsed = kNoallocClaimOff + 2 * 8 * 4 * kLineU32;
+static_assert(kNoallocUsed <= kNoallocScratchBytes, "the no-alloc counter layout fits its scratch");
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(SBR_ERR_UNSUPPORTED, "no-alloc scratch: device index beyond " + std::to_string(kMaxDevices));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return SBR_OK;
+    int cur = -1;
+    SBR_HIP(hipGetDevice(&cur));
+    if (cur != device) return fail(SBR_ERR_INVALID_ARG, "no-alloc scratch: set up with another device current");
+    void *ptr = nullptr;
+    SBR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SBR_ERR_HIP, "no-alloc scratch: hipGetSymbolAddress gave no address");
+    g_scratch_ptr[device] = ptr;
+    return SBR_OK;
+}
+
+int noalloc_counters(int device, CounterPtrs &c, void **base, size_t *bytes)
+{
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (device >= 0 && device < kMaxDevices) ptr = g_scratch_ptr[device];
+    }
+    if (!ptr) return fail(SBR_ERR_INVALID_ARG, "no-alloc scratch of this device was not set up (sbr_create)");
+    char *b = static_cast<char *>(ptr);
+    c.stat = reinterpret_cast<unsigned long long *>(b);
+    c.q_cnt = reinterpret_cast<uint32_t *>(b + kNoallocQcntOff);
+    c.claim = reinterpret_cast<uint32_t *>(b + kNoallocClaimOff);
+    *base = ptr;
+    *bytes = kNoallocUsed;
     return SBR_OK;
 }
 

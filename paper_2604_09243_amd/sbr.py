@@ -192,6 +192,8 @@ SIGNATURES = {
     "sbr_free_bvh": (None, [_vp]),
     "sbr_trace": (C.c_int, [_vp, _vp, C.POINTER(Rays), C.c_int64, C.c_int, C.POINTER(TraceOpts),
                             C.POINTER(Hits), C.POINTER(Stats)]),
+    "sbr_trace_noalloc": (C.c_int, [_vp, _vp, C.POINTER(Rays), C.c_int64, C.c_int, C.POINTER(TraceOpts),
+                                    C.POINTER(Hits), C.POINTER(Stats)]),
     "sbr_po_integrate": (C.c_int, [_vp, _vp, C.POINTER(Hits), C.c_int64, C.POINTER(PoDesc), _vp, C.c_int, _vp]),
     "sbr_rcs_sweep": (C.c_int, [_vp, _vp, C.POINTER(Sweep), _vp, _vp, C.POINTER(Stats)]),
     "sbr_plan_angle": (C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(AnglePlan)]),
@@ -555,32 +557,50 @@ class Context:
         return BVH(self, h)
 
     # ------------------------------------------------------------ trace
-    def trace(self, bvh, o, d, eH, eV, max_bounces, k_hat, flags=0, want_path=False, stats=False):
+    _HIT_DTYPES = dict(n_bounce="int32", tri_first="int32", tri_last="int32", flags="int32", path="float64",
+                       D="float64", d_last="float32", x_last="float32", eH_last="float32", eV_last="float32",
+                       tri_path="int32")
+
+    def trace(self, bvh, o, d, eH, eV, max_bounces, k_hat, flags=0, want_path=False, stats=False, out=None,
+              noalloc=False):
         """Rays as [n, 3] float32 CUDA tensors; returns a dict of device
-        tensors (the sbr_hits arrays) and, if ``stats``, the statistics."""
+        tensors (the sbr_hits arrays) and, if ``stats``, the statistics.
+        ``out``: caller-allocated result tensors (a dict with the sbr_hits
+        names; absent names are skipped).  ``noalloc``: call
+        sbr_trace_noalloc, which allocates nothing on the device."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = int(o.shape[0]) if hasattr(o, "shape") and len(o.shape) == 2 else -1
         for name, x in (("o", o), ("d", d), ("eH", eH), ("eV", eV)):
             _dev_tensor(x, name, torch.float32, (n, 3), self.device)
-        out = dict(n_bounce=torch.empty(n, dtype=torch.int32, device=dev),
-                   tri_first=torch.empty(n, dtype=torch.int32, device=dev),
-                   tri_last=torch.empty(n, dtype=torch.int32, device=dev),
-                   flags=torch.empty(n, dtype=torch.int32, device=dev),
-                   path=torch.empty(n, dtype=torch.float64, device=dev),
-                   D=torch.empty(n, dtype=torch.float64, device=dev),
-                   d_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
-                   x_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
-                   eH_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
-                   eV_last=torch.empty(n, 3, dtype=torch.float32, device=dev))
-        if want_path:
-            out["tri_path"] = torch.empty(n, max_bounces, dtype=torch.int32, device=dev)
+        if out is None:
+            out = dict(n_bounce=torch.empty(n, dtype=torch.int32, device=dev),
+                       tri_first=torch.empty(n, dtype=torch.int32, device=dev),
+                       tri_last=torch.empty(n, dtype=torch.int32, device=dev),
+                       flags=torch.empty(n, dtype=torch.int32, device=dev),
+                       path=torch.empty(n, dtype=torch.float64, device=dev),
+                       D=torch.empty(n, dtype=torch.float64, device=dev),
+                       d_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                       x_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                       eH_last=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                       eV_last=torch.empty(n, 3, dtype=torch.float32, device=dev))
+            if want_path:
+                out["tri_path"] = torch.empty(n, max_bounces, dtype=torch.int32, device=dev)
+        else:
+            out = dict(out)
+            for name, t in out.items():
+                if name not in self._HIT_DTYPES:
+                    raise ValueError("out: unknown result array %r" % name)
+                shape = ((n, 3) if name in ("d_last", "x_last", "eH_last", "eV_last") else
+                         (n, int(max_bounces)) if name == "tri_path" else (n,))
+                _dev_tensor(t, name, getattr(torch, self._HIT_DTYPES[name]), shape, self.device)
         hits = self._hits(out)
         rays = Rays(o.data_ptr(), d.data_ptr(), eH.data_ptr(), eV.data_ptr())
         opts = TraceOpts(C.sizeof(TraceOpts), int(flags), _d3(*[float(x) for x in k_hat]))
         st = Stats() if stats else None
-        _check(load_library().sbr_trace(self.handle, bvh.handle, C.byref(rays), n, int(max_bounces), C.byref(opts),
-                                        C.byref(hits), C.byref(st) if stats else None))
+        fn = load_library().sbr_trace_noalloc if noalloc else load_library().sbr_trace
+        _check(fn(self.handle, bvh.handle, C.byref(rays), n, int(max_bounces), C.byref(opts), C.byref(hits),
+                  C.byref(st) if stats else None))
         if stats:
             out["stats"] = st.as_dict()
         return out
