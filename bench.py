@@ -95,8 +95,9 @@ def sbr_default_tune():
 
 
 def mask_flag(args):
+    """Trace flags of the command line: the primary-ray mask off, the binary tree instead of its four-wide copy."""
     from paper_2604_09243_amd import sbr
-    return sbr.OPT_NO_MASK if args.no_mask else 0
+    return (sbr.OPT_NO_MASK if args.no_mask else 0) | (sbr.OPT_BVH4 if getattr(args, "bvh4", False) else 0)
 
 
 def C_sizeof_tune(sbr):
@@ -206,6 +207,8 @@ def main():
                     help="aircraft, batch: autotune the launch parameters first (set-up, not timed)")
     ap.add_argument("--no-mask", action="store_true",
                     help="trace every primary ray (no per-angle mask of empty cells)")
+    ap.add_argument("--bvh4", action="store_true",
+                    help="walk a four-wide copy of the tree (same results; a traversal study, slower on the aircraft)")
     ap.add_argument("--builder", choices=("lbvh", "sah", "ploc"), default="sah",
                     help="BVH builder of each step: host binned SAH (default; fewer node and triangle tests "
                          "per ray), the GPU LBVH, or GPU PLOC clustering")
@@ -311,7 +314,7 @@ def main():
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": w.name + "_181az_lambda10_b5", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
-                   "bvh": args.builder, "primary_mask": not args.no_mask,
+                   "bvh": args.builder, "tree_width": 4 if args.bvh4 else 2, "primary_mask": not args.no_mask,
                    "polarisations": "HH,HV,VH,VV"},
         "value_traced": (queries - masked) / dt,
         "masked_rays_per_step": masked / args.steps,
@@ -644,7 +647,7 @@ def bench_aircraft(args):
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": w.name + "_360az_lambda8_b8", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
-                   "bvh": args.builder, "primary_mask": not args.no_mask, "polarisations": "HH,HV,VH,VV",
+                   "bvh": args.builder, "tree_width": 4 if args.bvh4 else 2, "primary_mask": not args.no_mask, "polarisations": "HH,HV,VH,VV",
                    "tune": (tune if tune is not None else sbr_default_tune()).as_dict()},
         # the queries that traversed the tree: the mask's primary-ray misses left out
         "value_traced": (queries - masked) / dt,

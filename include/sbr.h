@@ -93,6 +93,13 @@ enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
                                          triangle tests in float64 (hits then differ from the
                                          float32 specification by rounding); streaming schedule
                                          of sbr_trace and sbr_rcs_sweep only */
+#define SBR_OPT_BVH4 512              /* traversal study: walk a four-wide copy of the tree
+                                         (four child boxes per 128-byte node, collapsed from the
+                                         binary tree on the host at the first such call and kept
+                                         with the BVH) instead of the binary tree.  The same
+                                         results bit for bit; measured slower on the aircraft,
+                                         so not the default.  sbr_trace and sbr_rcs_sweep on the
+                                         streaming schedule; sbr_trace_noalloc refuses it */
 
 /* ------------------------------------------------------------------------ */
 /* Library and context                                                       */
@@ -169,7 +176,10 @@ int sbr_bvh_get_info(const sbr_bvh *bvh, sbr_bvh_info *out);
  * reachable once from the root in preorder, child boxes inside their
  * parent's box, every leaf slot in exactly one leaf of at most leaf_size
  * triangles, every triangle's corners inside the box its leaf is reached
- * through, every input id in at most one slot, the depth bound kept.
+ * through, every input id in at most one slot, the depth bound kept; and
+ * the four-wide copy of SBR_OPT_BVH4 once it exists: every BVH2 leaf
+ * reached exactly once with the box the BVH2 gives it, child boxes inside
+ * their parent's, the child counts and its depth bound.
  * Copies the arrays to the host (synchronous).  Errors: INVALID_MESH with
  * the first violation, UNSUPPORTED for a scene set, INVALID_ARG, HIP. */
 int sbr_bvh_validate(const sbr_bvh *bvh);
@@ -322,7 +332,7 @@ typedef struct {
     int32_t claim_tiles;   /* tiles a wave claims per atomic, 1..64 */
     int32_t refill_min;    /* idle lanes that trigger a refill (streaming launch), 1..64 */
     int32_t blocks_per_cu; /* persistent blocks of 256 threads per compute unit; 0 = occupancy limit */
-    int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..26; 0 = 26.  Records of a
+    int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..28; 0 = 26.  Records of a
                               chunk stay in device memory between its trace and its PO stage. */
     int32_t reserved;
 } sbr_tune;

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(ROOT, "_build", "sbr")
 LIB = os.path.join(HERE, "libsbr.so")
-SOURCES = ["api.cpp", "batch.cpp", "surrogate.cpp", "mesh_prep.cpp", "plan.cpp", "sah.cpp", "lbvh.hip", "trace.hip",
+SOURCES = ["api.cpp", "batch.cpp", "surrogate.cpp", "mesh_prep.cpp", "plan.cpp", "sah.cpp", "bvh4.cpp", "lbvh.hip", "trace.hip",
            "po.hip", "scene.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

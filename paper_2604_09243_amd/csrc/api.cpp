@@ -170,6 +170,7 @@ enum Slot {
     W_SPILL = 23,
     W_MASK = 24,
     W_TUNE = 25,
+    W_HELD = 26,  // record-slot bytes
 };
 
 static int get_queue(Workspace *ws, int first, size_t cap, RayQueue &q)
@@ -193,13 +194,16 @@ static int get_records(Workspace *ws, size_t cap, Records &r)
 {
     void *p[4];
     int rc;
+    void *pv;
     if ((rc = ws->get(W_REC + 0, 16 * cap, &p[0])) || (rc = ws->get(W_REC + 1, 16 * cap, &p[1])) ||
-        (rc = ws->get(W_REC + 2, 16 * cap, &p[2])) || (rc = ws->get(W_REC + 3, 8 * cap, &p[3])))
+        (rc = ws->get(W_REC + 2, 16 * cap, &p[2])) || (rc = ws->get(W_REC + 3, 8 * cap, &p[3])) ||
+        (rc = ws->get(W_HELD, 4 * static_cast<size_t>(held_words(static_cast<int64_t>(cap))), &pv)))
         return rc;
     r.r0 = static_cast<float4 *>(p[0]);
     r.r1 = static_cast<float4 *>(p[1]);
     r.r2 = static_cast<float4 *>(p[2]);
     r.D = static_cast<double *>(p[3]);
+    r.held = static_cast<uint8_t *>(pv);
     return SBR_OK;
 }
 
@@ -250,7 +254,10 @@ int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector
 
 size_t spill_words(const sbr_bvh *bvh, int blocks)
 {
-    const int extra = trace_needs_spill(bvh) ? std::max(1, bvh->depth + 2 - trace_stack_lds()) : 1;
+    // enough for either traversal (the binary tree, or its BVH4 copy when there is one)
+    int extra = 1;
+    for (int wide = 0; wide <= (bvh->nodes4 ? 1 : 0); ++wide)
+        if (trace_needs_spill(bvh, wide != 0)) extra = std::max(extra, stack_need(bvh, wide != 0) + 2 - trace_stack_lds());
     return static_cast<size_t>(extra) * blocks * trace_block_threads();
 }
 
@@ -546,7 +553,11 @@ extern "C" int sbr_bvh_validate(const sbr_bvh *bvh)
     SBR_HIP(hipMemcpy(hn.data(), bvh->nodes, sizeof(BNode) * hn.size(), hipMemcpyDeviceToHost));
     SBR_HIP(hipMemcpy(ht.data(), bvh->tris, sizeof(BTri) * ht.size(), hipMemcpyDeviceToHost));
     const SceneScale sc = scene_scale(bvh->bbox, bvh->diag);
-    return validate_layout(hn, static_cast<int>(bvh->n_live), bvh->leaf_size, bvh->depth, &ht, bvh->n_tris, &sc);
+    int rc = validate_layout(hn, static_cast<int>(bvh->n_live), bvh->leaf_size, bvh->depth, &ht, bvh->n_tris, &sc);
+    if (rc || !bvh->nodes4) return rc;
+    std::vector<BNode4> hw(static_cast<size_t>(bvh->n_nodes4));
+    SBR_HIP(hipMemcpy(hw.data(), bvh->nodes4, sizeof(BNode4) * hw.size(), hipMemcpyDeviceToHost));
+    return validate_wide(hn, hw, bvh->depth4);
 }
 
 extern "C" int sbr_bvh_quality_of(const sbr_bvh *bvh, sbr_bvh_quality *out)
@@ -622,13 +633,16 @@ static int trace_impl(const char *fn, sbr_ctx *ctx, const sbr_bvh *bvh, const sb
     if (noalloc) {
         if (sched != kScheduleStream)
             return fail(SBR_ERR_UNSUPPORTED, f + ": the wavefront schedule needs ray queues beyond the static scratch");
-        if (trace_needs_spill(bvh))
+        if (flags & SBR_OPT_BVH4)
+            return fail(SBR_ERR_UNSUPPORTED, f + ": SBR_OPT_BVH4 may need to build the tree's wide copy");
+        if (trace_needs_spill(bvh, false))
             return fail(SBR_ERR_UNSUPPORTED,
                         f + ": the tree (depth " + std::to_string(bvh->depth) + ") needs more traversal stack "
                             "than the on-chip one; the static scratch holds no stack spill (use sbr_trace)");
         if ((rc = noalloc_counters(ctx->device, cn.p, &cn.base, &cn.bytes))) return rc;
         spill = nullptr;  // never read: the tree fits the on-chip stack
     } else {
+        if ((rc = ensure_wide(ctx, bvh, flags, sched))) return rc;
         if ((rc = get_counters(ws, cn)) || (rc = get_spill(ctx, bvh, blocks, &spill))) return rc;
         if (sched == kScheduleWavefront &&
             ((rc = get_queue(ws, W_QA, n_rays, qa)) || (rc = get_queue(ws, W_QB, n_rays, qb))))
@@ -930,6 +944,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     if ((sw->flags & SBR_OPT_FP64_TRAVERSE) && sched != kScheduleStream)
         return fail(SBR_ERR_UNSUPPORTED, "sbr_rcs_sweep: SBR_OPT_FP64_TRAVERSE runs on the streaming schedule only");
     const bool use_mask = !(sw->flags & SBR_OPT_NO_MASK);
+    if ((rc = ensure_wide(ctx, bvh, sw->flags, sched))) return rc;
     const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
     const size_t tile_words = static_cast<size_t>(na + n_chunks);
     if ((rc = get_counters(ws, cn)) || (rc = get_records(ws, max_chunk_rays, rec)) ||
@@ -998,6 +1013,8 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         chunk_rays[c] = n_rays;
         SBR_HIP(hipMemsetAsync(cn.base, 0, cn.bytes, s));
         if (want_stats) SBR_HIP(hipEventRecord(ev[epc * c], s));
+        // the chunk's record slots start empty
+        if ((rc = launch_zero_u32(s, reinterpret_cast<uint32_t *>(rec.held), held_words(n_rays)))) return rc;
         TraceArgs ta{};
         ta.bvh = bvh;
         ta.bmax = bm;

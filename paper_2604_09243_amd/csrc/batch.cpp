@@ -82,7 +82,7 @@ struct sbr_batch {
     std::vector<int64_t> out_base;
     int64_t n_rows = 0, rays = 0, min_rays = 0, max_rays = 0;
     // chunks: items [cstart[c], cstart[c + 1])
-    std::vector<int64_t> cstart, c_tiles, c_units, tile_off;
+    std::vector<int64_t> cstart, c_tiles, c_units, tile_off, c_rays;
     std::vector<int> c_maxnf;
     std::vector<int64_t> c_mask_bytes, c_mask_units;  // primary-ray mask of each chunk
     int blocks = 0;
@@ -176,6 +176,7 @@ int plan_batch(sbr_batch *b)
     b->c_tiles.clear();
     b->c_units.clear();
     b->c_maxnf.clear();
+    b->c_rays.clear();
     b->tile_off.clear();
     b->c_mask_bytes.clear();
     b->c_mask_units.clear();
@@ -201,6 +202,7 @@ int plan_batch(sbr_batch *b)
             ++e;
         }
         b->c_tiles.push_back(tiles);
+        b->c_rays.push_back(rays);
         b->c_units.push_back(units);
         b->c_maxnf.push_back(mnf);
         int64_t mb = 0, mu = 0;
@@ -227,10 +229,12 @@ int plan_batch(sbr_batch *b)
     int rc;
     float4 *r0, *r1, *r2;
     double *rD;
+    uint32_t *held;
     if ((rc = b->dev.alloc(&b->d_plans, ni)) || (rc = b->dev.alloc(&b->d_tile, tile_words)) ||
         (rc = b->dev.alloc(&b->d_ang, ni)) || (rc = b->dev.alloc(&b->d_kf, b->freqs.size())) ||
         (rc = b->dev.alloc(&r0, max_rays)) || (rc = b->dev.alloc(&r1, max_rays)) ||
         (rc = b->dev.alloc(&r2, max_rays)) || (rc = b->dev.alloc(&rD, max_rays)) ||
+        (rc = b->dev.alloc(&held, static_cast<size_t>(held_words(max_rays)))) ||
         (rc = b->dev.alloc(&b->d_part, 8 * static_cast<size_t>(max_rows))) ||
         (rc = b->dev.alloc(&b->d_ctr, kCounterBytes / 4)) ||
         (rc = b->dev.alloc(&b->d_spill, spill_words(bv, b->blocks))))
@@ -238,7 +242,7 @@ int plan_batch(sbr_batch *b)
     b->d_mask = nullptr;
     if (!(b->flags & SBR_OPT_NO_MASK) && (rc = b->dev.alloc(&b->d_mask, static_cast<size_t>(max_mask))))
         return rc;
-    b->rec = Records{r0, r1, r2, rD};
+    b->rec = Records{r0, r1, r2, rD, reinterpret_cast<uint8_t *>(held)};
     char *cb = reinterpret_cast<char *>(b->d_ctr);
     b->ctrs.stat = reinterpret_cast<unsigned long long *>(cb);
     b->ctrs.q_cnt = reinterpret_cast<uint32_t *>(cb + kStatBytes);
@@ -275,6 +279,8 @@ int enqueue(sbr_batch *b, hipStream_t s, double *A, double *sigma, std::vector<h
         // the statistics accumulate over chunks; queue and claim counters restart
         if (c > 0 && (rc = launch_zero_u32(s, b->d_ctr + stat_words, ctr_words - stat_words))) return rc;
         if (ev) SBR_HIP(hipEventRecord((*ev)[3 * c], s));
+        // the chunk's record slots start empty
+        if ((rc = launch_zero_u32(s, reinterpret_cast<uint32_t *>(b->rec.held), held_words(b->c_rays[c])))) return rc;
         TraceArgs ta{};
         ta.bvh = b->bvh;
         ta.bmax = b->bmax;

@@ -214,8 +214,9 @@ __device__ __forceinline__ void po_passes(const PoP &p, const PoAngle &A, int64_
         for (int ft = 0; ft < kFT; ++ft)
             for (int e = 0; e < 8; ++e) acc[ft][e] = 0.0;
         for (int64_t e = A.rec_base + r0i + tid; e < A.rec_base + r1i; e += kPoThreads) {
+            if (!p.rec.held[e]) continue;  // no record in this slot
             const float4 q2 = p.rec.r2[e];
-            if (!((__float_as_int(q2.w) >> 8) & SBR_REC_VALID)) continue;  // no hit (or dropped): no term
+            if (!((__float_as_int(q2.w) >> 8) & SBR_REC_VALID)) continue;  // dropped as trapped: no term
             const float4 q0 = p.rec.r0[e], q1 = p.rec.r1[e];
             const double D = p.rec.D[e];
             double w[4];
@@ -346,19 +347,30 @@ __global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
         // stage: thread t holds slots s0 + t + 256 j, j = 0, 1
         constexpr int kPer = kMfSub / kPoThreads;
         int vmask = 0, cnt = 0;
-        // all fields of the thread's slots are loaded at once (one round trip;
-        // empty slots cost their bytes)
+        // the slots' bytes first, then every field of the slots that hold a
+        // record at once (one more round trip; empty slots cost no bytes)
         float4 q0[kPer], q1[kPer], q2[kPer];
         double Dj[kPer];
+        bool held[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int64_t e = s0 + tid + j * kPoThreads;
-            const int64_t ec = A.rec_base + (e < r1i ? e : r0i);  // a valid address for every lane
-            q0[j] = p.rec.r0[ec];
-            q1[j] = p.rec.r1[ec];
-            q2[j] = p.rec.r2[ec];
-            Dj[j] = p.rec.D[ec];
-            if (e < r1i && ((__float_as_int(q2[j].w) >> 8) & SBR_REC_VALID)) {
+            const int64_t ea = A.rec_base + e;
+            held[j] = e < r1i && p.rec.held[ea] != 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int64_t ea = A.rec_base + s0 + tid + j * kPoThreads;
+            if (held[j]) {
+                q0[j] = p.rec.r0[ea];
+                q1[j] = p.rec.r1[ea];
+                q2[j] = p.rec.r2[ea];
+                Dj[j] = p.rec.D[ea];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (held[j] && ((__float_as_int(q2[j].w) >> 8) & SBR_REC_VALID)) {
                 vmask |= 1 << j;
                 ++cnt;
             }
@@ -539,16 +551,15 @@ __global__ __launch_bounds__(64) void k_po_final(PoP p, int max_nf, double *__re
     }
 }
 
-// Caller hit e -> record slot e.
+// Caller hit e -> record slot e (its byte says whether it holds a record).
 __global__ void k_pack(sbr_hits h, int64_t n, Records rec)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const int fl = h.flags[e];
-    if (!(fl & SBR_REC_VALID)) {
-        rec.r2[e] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
-        return;
-    }
+    const bool valid = (fl & SBR_REC_VALID) != 0;
+    rec.held[e] = valid ? 1 : 0;
+    if (!valid) return;
     rec.r0[e] = make_float4(h.d_last[3 * e], h.d_last[3 * e + 1], h.d_last[3 * e + 2], __int_as_float(h.tri_last[e]));
     rec.r1[e] = make_float4(h.eH_last[3 * e], h.eH_last[3 * e + 1], h.eH_last[3 * e + 2],
                             __int_as_float(h.tri_first[e]));

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <climits>
 #include <cstdint>
 #include <cstddef>
 #include <algorithm>
@@ -37,6 +38,21 @@ struct __align__(16) BNode {
     float4 a, b, c;
     int4 ch;
 };
+
+// BVH4 node (128 bytes, one cache line): the boxes of up to four children,
+// child i in component i of each float4 (lo.x of the four children, then
+// hi.x, lo.y, hi.y, lo.z, hi.z), their references in ch (as in BNode: >= 0 an
+// internal BVH4 node, < 0 a leaf code; kNoChild for an absent child, whose
+// box repeats child 0's) and the child count in m.x.  Every box is a box of
+// the BVH2 it is collapsed from (collapse_wide), so it holds the same
+// guard-widened triangle boxes.
+constexpr int kNoChild = INT32_MIN;
+struct __align__(128) BNode4 {
+    float4 lox, hix, loy, hiy, loz, hiz;
+    int4 ch;
+    int4 m;
+};
+static_assert(sizeof(BNode4) == 128, "a BVH4 node is one 128-byte line");
 
 // Triangle in leaf (slot) order: p0 = (v0.xyz, input id as int bits),
 // p1 = (e1.xyz, 0), p2 = (e2.xyz, 0).
@@ -79,14 +95,21 @@ struct RayQueue {
     double2 *s5;
 };
 
-// Hit record of one ray (structure of arrays); r2.w carries N | flags << 8,
-// zero for a ray that never hit.
+// Hit record of one ray (structure of arrays); r2.w carries N | flags << 8.
 //   r0 = (d_last.xyz, tri_last)  r1 = (eH_last.xyz, tri_first)
 //   r2 = (eV_last.xyz, N | flags << 8)  D
+// held: one byte per record slot, 1 when slot e holds a record.  The slots
+// of rays that never hit (or whose record was dropped) are neither written
+// nor read; their byte stays 0.  The bytes are cleared (a kernel) before
+// each launch that fills the records; every ray writes only its own byte,
+// so no atomics are needed.
 struct Records {
     float4 *r0, *r1, *r2;
     double *D;
+    uint8_t *held;
 };
+// 32-bit words of a slot-byte array (cleared as words)
+inline int64_t held_words(int64_t slots) { return (slots + 3) / 4; }
 
 // Counter block, zeroed before each sweep chunk / trace call.  Counters that
 // many waves update sit on separate 256-byte lines (kLineU32 uint32 apart):
@@ -173,6 +196,9 @@ struct sbr_bvh {
     double bbox[6] = {0, 0, 0, 0, 0, 0};
     double diag = 0.0;
     sbr::BNode *nodes = nullptr;  // [n_nodes]
+    sbr::BNode4 *nodes4 = nullptr;  // [n_nodes4] the same tree collapsed to four children per node (NULL: none)
+    int64_t n_nodes4 = 0;
+    int32_t depth4 = 0;
     sbr::BTri *tris = nullptr;    // [n_live] in leaf order
     float4 *nrm_slot = nullptr;   // [n_live] unit normal in leaf order
     float4 *nrm_id = nullptr;     // [n_tris] unit normal by input index
@@ -248,6 +274,24 @@ int build_sah(sbr_ctx *ctx, const PreparedMesh &pm, int leaf_max, sbr_bvh *bvh);
 // the triangles in leaf order, of their ids in [0, n_ids) and leaf boxes).
 int validate_layout(const std::vector<BNode> &hn, int n, int leaf_max, int depth, const std::vector<BTri> *tris,
                     int64_t n_ids, const SceneScale *scale);
+// bvh4.cpp: collapses the BVH2 rooted at node 0 of hn into BVH4 nodes (root
+// at 0, the four children of a node taken greedily by opening the child of
+// largest surface area, sibling nodes stored together); depth4 = levels.
+int collapse_wide(const std::vector<BNode> &hn, std::vector<BNode4> &out, int &depth4);
+// bvh4.cpp: structural check of a BVH4 against the BVH2 it was collapsed from.
+int validate_wide(const std::vector<BNode> &hn, const std::vector<BNode4> &w, int depth4);
+// bvh4.cpp: builds bvh->nodes4 from bvh->nodes (a device -> host copy, the
+// collapse on the host, an upload) unless it exists; SBR_OPT_BVH4 calls.
+int build_wide(sbr_ctx *ctx, sbr_bvh *bvh);
+// The wide copy for a call with these flags and schedule: built on first use
+// (the copy is a cache of the tree, hence the cast).
+inline int ensure_wide(sbr_ctx *ctx, const sbr_bvh *bvh, uint32_t flags, int schedule)
+{
+    if (!(flags & SBR_OPT_BVH4) || bvh->nodes4 || !bvh->scenes.empty() || schedule != kScheduleStream) return 0;
+    return build_wide(ctx, const_cast<sbr_bvh *>(bvh));
+}
+// Traversal stack entries the tree needs: BVH2 one per level, BVH4 three.
+inline int stack_need(const sbr_bvh *bvh, bool wide) { return wide ? 3 * bvh->depth4 + 1 : bvh->depth; }
 // sah.cpp: surface-area estimates of the traversal work of a node layout.
 void layout_quality(const std::vector<BNode> &hn, sbr_bvh_quality &q);
 
@@ -305,7 +349,10 @@ int trace_persistent_blocks(sbr_ctx *ctx, int blocks_per_cu);  // 0 = occupancy 
 int check_tune(const sbr_tune &t);
 int trace_block_threads();
 int trace_stack_lds();  // LDS entries of the stack when it spills
-bool trace_needs_spill(const sbr_bvh *bvh);
+bool trace_needs_spill(const sbr_bvh *bvh, bool wide);
+// Whether a launch over this tree walks its BVH4 copy (SBR_OPT_BVH4 on the
+// streaming schedule of a one-mesh tree whose copy exists).
+bool trace_walks_wide(const sbr_bvh *bvh, uint32_t flags, int schedule);
 
 // api.cpp helpers shared with the batch entry points
 sbr_tune default_tune();

@@ -59,12 +59,10 @@ constexpr int kStackSpillLds = SBR_TRACE_SPILL_LDS;  // LDS part of the stack wh
 //    and of the slab test below, so a box that holds an accepted hit point at
 //    distance t' <= the best t so far always passes the test (entry <= t' <=
 //    exit); no relative margin on t is needed;
-//  * the traversal first runs without checking the box rule per candidate;
-//    if its winner then passes the rule, every box it skipped was skipped
-//    against a best t no smaller than the winner's, so it held no better
-//    accepted hit.  Otherwise (a rounding-dominated hit of a sliver or of a
-//    grazing ray, about one query in 10^6) the query is traversed again with
-//    the rule applied to every candidate.
+//  * the rule is applied to every candidate that would improve the best hit
+//    (with the triangle's record already in registers), so the best t is
+//    always an accepted hit's and every box skipped against it held no
+//    better accepted hit.
 // Slab-test rounding: with ix = rcp(d) (1 ulp) and ox = fl(o ix), the value
 // fma(b, ix, -ox) is within (3 2^-24 |b - o| + 2^-24 |o|) / |d| of (b - o) / d;
 // the hit point fl(o + fl(t d)) is within 2^-24 (2 |x| + |o|) of o + t d.
@@ -92,6 +90,7 @@ constexpr int kTileRays = 64;
 
 struct Params {
     const BNode *nodes;
+    const BNode4 *nodes4;  // the same tree four-wide (single-scene launches that walk it)
     const BTri *tris;
     const float4 *nrm;  // by slot
     float eps, pbox;    // caller rays: the scene's offset and the hit rule's P
@@ -196,14 +195,15 @@ __device__ __forceinline__ bool in_box(const BTri &tr, const Ray &r, R t, float 
     return x >= R(lx) && x <= R(hx) && y >= R(ly) && y <= R(hy) && z >= R(lz) && z <= R(hz);
 }
 
-// strict: apply the box rule to every candidate (the re-traversal).
+// Candidate triangle tr (leaf slot `slot`): it becomes the best hit when the
+// float32 test accepts it, it is not the previous triangle, it improves
+// (t, id), and its hit point passes the box rule.
 template <typename R>
-__device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r, BestT<R> &b, bool strict, float P)
+__device__ __forceinline__ void test_tri(const BTri &tr, int slot, const Ray &r, BestT<R> &b, float P)
 {
     const int id = __float_as_int(tr.p0.w);
     R t;
-    if (tri_test(tr, r, t) && id != r.prev && (t < b.t || (t == b.t && id < b.id)) &&
-        (!strict || in_box(tr, r, t, P))) {
+    if (tri_test(tr, r, t) && id != r.prev && (t < b.t || (t == b.t && id < b.id)) && in_box(tr, r, t, P)) {
         b.t = t;
         b.id = id;
         b.slot = slot;
@@ -283,30 +283,29 @@ __device__ __forceinline__ bool wave_uniform(int v, int &v0)
 // The triangles [first, first + cnt) of a leaf, cnt <= 4, each 48-byte
 // record loaded one test ahead.
 template <typename TriPtr, typename R>
-__device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, const Ray &r, BestT<R> &b, bool strict,
-                                               float P)
+__device__ __forceinline__ void test_leaf_from(TriPtr tris, int first, int cnt, const Ray &r, BestT<R> &b, float P)
 {
     SBR_COUNT(b.leaves += 1; b.tris += cnt);
     const BTri t0 = tris[first];
     BTri t1, t2, t3;
     if (cnt > 1) t1 = tris[first + 1];
-    test_tri(t0, first, r, b, strict, P);
+    test_tri(t0, first, r, b, P);
     if (cnt > 2) t2 = tris[first + 2];
-    if (cnt > 1) test_tri(t1, first + 1, r, b, strict, P);
+    if (cnt > 1) test_tri(t1, first + 1, r, b, P);
     if (cnt > 3) t3 = tris[first + 3];
-    if (cnt > 2) test_tri(t2, first + 2, r, b, strict, P);
-    if (cnt > 3) test_tri(t3, first + 3, r, b, strict, P);
+    if (cnt > 2) test_tri(t2, first + 2, r, b, P);
+    if (cnt > 3) test_tri(t3, first + 3, r, b, P);
 }
 
 // Leaf `code` (first triangle << 3 | count - 1).
 template <typename R>
-__device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &r, BestT<R> &b, bool strict, float P)
+__device__ __forceinline__ void test_leaf(const Params &p, int code, const Ray &r, BestT<R> &b, float P)
 {
     int c0;
     if (wave_uniform(code, c0))
-        test_leaf_from(ScalarTriLoader{p.tris}, c0 >> 3, (c0 & 7) + 1, r, b, strict, P);
+        test_leaf_from(ScalarTriLoader{p.tris}, c0 >> 3, (c0 & 7) + 1, r, b, P);
     else
-        test_leaf_from(p.tris, code >> 3, (code & 7) + 1, r, b, strict, P);
+        test_leaf_from(p.tris, code >> 3, (code & 7) + 1, r, b, P);
 }
 
 // Entry and exit distances of the ray (inverse direction i, origin terms l
@@ -330,6 +329,82 @@ __device__ __forceinline__ void node_boxes(const BNode &n, R ix, R iy, R iz, R l
     u1 = minR(minR(maxR(bx0, bx1), maxR(by0, by1)), minR(maxR(bz0, bz1), tlim));
     cx = n.ch.x;
     cy = n.ch.y;
+}
+
+__device__ __forceinline__ BNode4 node4_scalar(const BNode4 *nodes, int i)
+{
+    const ScalarF4 q = (ScalarF4)(nodes + i);
+    const sf4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5];
+    const si4 ch = ((ScalarI4)(nodes + i))[6];
+    BNode4 n;
+    n.lox = make_float4(a.x, a.y, a.z, a.w);
+    n.hix = make_float4(b.x, b.y, b.z, b.w);
+    n.loy = make_float4(c.x, c.y, c.z, c.w);
+    n.hiy = make_float4(d.x, d.y, d.z, d.w);
+    n.loz = make_float4(e.x, e.y, e.z, e.w);
+    n.hiz = make_float4(f.x, f.y, f.z, f.w);
+    n.ch = make_int4(ch.x, ch.y, ch.z, ch.w);
+    n.m = make_int4(0, 0, 0, 0);
+    return n;
+}
+
+__device__ __forceinline__ BNode4 node4_vector(const BNode4 *nodes, int i)
+{
+    const BNode4 *q = nodes + i;
+    BNode4 n;
+    n.lox = q->lox;
+    n.hix = q->hix;
+    n.loy = q->loy;
+    n.hiy = q->hiy;
+    n.loz = q->loz;
+    n.hiz = q->hiz;
+    n.ch = q->ch;
+    n.m = make_int4(0, 0, 0, 0);
+    return n;
+}
+
+// Entry/exit test of the four child boxes of node n (same slab arithmetic as
+// node_boxes, exit clamped to tlim) -> the four sort keys.
+template <typename R>
+__device__ __forceinline__ void node4_keys(const BNode4 &n, R ix, R iy, R iz, R lx, R ly, R lz, R hx, R hy, R hz,
+                                           R tlim, uint32_t &k0, uint32_t &k1, uint32_t &k2, uint32_t &k3)
+{
+    uint32_t k[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float bx0 = (&n.lox.x)[c], bx1 = (&n.hix.x)[c];
+        const float by0 = (&n.loy.x)[c], by1 = (&n.hiy.x)[c];
+        const float bz0 = (&n.loz.x)[c], bz1 = (&n.hiz.x)[c];
+        const R ax0 = fmaR(R(bx0), ix, -lx), ax1 = fmaR(R(bx1), ix, -hx);
+        const R ay0 = fmaR(R(by0), iy, -ly), ay1 = fmaR(R(by1), iy, -hy);
+        const R az0 = fmaR(R(bz0), iz, -lz), az1 = fmaR(R(bz1), iz, -hz);
+        const R tn = maxR(maxR(minR(ax0, ax1), minR(ay0, ay1)), maxR(minR(az0, az1), R(0)));
+        const R tf = minR(minR(maxR(ax0, ax1), maxR(ay0, ay1)), minR(maxR(az0, az1), tlim));
+        const int ref = (&n.ch.x)[c];
+        // a passed child's key: its entry distance (>= 0, so the float bits
+        // order as unsigned integers; float precision is enough for an order)
+        // with its slot in the two low bits; ~0 for a missed or absent child
+        k[c] = (tn <= tf && ref != kNoChild)
+                   ? ((__float_as_uint(static_cast<float>(tn)) & ~3u) | static_cast<uint32_t>(c))
+                   : ~0u;
+    }
+    k0 = k[0];
+    k1 = k[1];
+    k2 = k[2];
+    k3 = k[3];
+}
+
+__device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b)
+{
+    const uint32_t lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
+__device__ __forceinline__ int pick_ref(const int4 &ch, uint32_t key)
+{
+    const uint32_t s = key & 3u;
+    return s == 0 ? ch.x : s == 1 ? ch.y : s == 2 ? ch.z : ch.w;
 }
 
 // Whether rays come from and go to the caller (sbr_trace) rather than an
@@ -357,12 +432,11 @@ __device__ __forceinline__ SceneRef scene_of(const Params &p, const Ray &r)
     return SceneRef{pl.root, pl.eps, pl.pbox};
 }
 
-// One traversal for the closest hit of ray r, skipping triangle r.prev;
-// strict: candidates must pass the hit rule's box test.  FAR: widen the slab
-// values for an origin beyond the BVH guard's bound (caller rays).
-template <bool SPILL, bool FAR, typename R>
-__device__ __forceinline__ BestT<R> traverse(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc,
-                                             bool strict)
+// One traversal for the closest hit of ray r, skipping triangle r.prev.
+// FAR: widen the slab values for an origin beyond the BVH guard's bound
+// (caller rays).
+template <bool SPILL, bool FAR, typename R, int W>
+__device__ __forceinline__ BestT<R> traverse(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc)
 {
     BestT<R> b;
     b.t = INFINITY;
@@ -386,10 +460,45 @@ __device__ __forceinline__ BestT<R> traverse(const Params &p, const Ray &r, Stac
         lz += gz; hz -= gz;
     }
     int sp = 0;
-    int cur = sc.root;  // the root is an internal node
+    int cur = W == 4 ? 0 : sc.root;  // the root is an internal node
     for (;;) {
         // phase 1: descend through internal nodes until a leaf (or nothing) is next
-        while (cur >= 0) {
+        while (W == 4 && cur >= 0) {
+            SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
+            int c0;
+            const BNode4 nd = wave_uniform(cur, c0) ? node4_scalar(p.nodes4, c0) : node4_vector(p.nodes4, cur);
+            uint32_t k0, k1, k2, k3;
+            node4_keys(nd, ix, iy, iz, lx, ly, lz, hx, hy, hz, b.t, k0, k1, k2, k3);
+            // nearest first: sort the four keys, go on with the nearest, push the rest far to near
+            cswap(k0, k1);
+            cswap(k2, k3);
+            cswap(k0, k2);
+            cswap(k1, k3);
+            cswap(k1, k2);
+            if (k0 == ~0u) {
+                if (sp > 0) {
+                    --sp;
+                    cur = st.pop(sp);
+                } else {
+                    cur = kEmpty;
+                }
+            } else {
+                if (k3 != ~0u) {
+                    st.push(sp, pick_ref(nd.ch, k3));
+                    ++sp;
+                }
+                if (k2 != ~0u) {
+                    st.push(sp, pick_ref(nd.ch, k2));
+                    ++sp;
+                }
+                if (k1 != ~0u) {
+                    st.push(sp, pick_ref(nd.ch, k1));
+                    ++sp;
+                }
+                cur = pick_ref(nd.ch, k0);
+            }
+        }
+        while (W == 2 && cur >= 0) {
             SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
             R t0, u0, t1, u1;
             int cx, cy, c0;
@@ -421,7 +530,7 @@ __device__ __forceinline__ BestT<R> traverse(const Params &p, const Ray &r, Stac
         if (cur == kEmpty) break;
         // phase 2: the triangles of leaf `cur`
         SBR_COUNT(if (wave_leader()) b.wleaf += 1);
-        test_leaf(p, ~cur, r, b, strict, sc.pbox);
+        test_leaf(p, ~cur, r, b, sc.pbox);
         if (sp > 0) {
             --sp;
             cur = st.pop(sp);
@@ -432,17 +541,12 @@ __device__ __forceinline__ BestT<R> traverse(const Params &p, const Ray &r, Stac
     return b;
 }
 
-// Closest hit of ray r under the hit rule: one traversal, and a strict second
-// one in the rare case that the first one's winner fails the box test.
-template <bool SPILL, bool FAR = false, typename R = float>
+// Closest hit of ray r under the hit rule: one traversal that applies the
+// rule to every candidate that would improve the best hit.
+template <bool SPILL, bool FAR = false, typename R = float, int W = 2>
 __device__ BestT<R> closest(const Params &p, const Ray &r, Stack<SPILL> st, const SceneRef sc)
 {
-    BestT<R> b;
-    for (int pass = 0;; ++pass) {
-        b = traverse<SPILL, FAR, R>(p, r, st, sc, pass != 0);
-        if (pass != 0 || b.slot < 0 || in_box(p.tris[b.slot], r, b.t, sc.pbox)) break;
-    }
-    return b;
+    return traverse<SPILL, FAR, R, W>(p, r, st, sc);
 }
 
 struct K3 {
@@ -528,8 +632,8 @@ __device__ __forceinline__ void batch_angles(const Params &p, int64_t u, int64_t
 // Position q of the angle grid (tile = q / 64, position in the tile's
 // tile_w-wide patch = q % 64) -> kGridRay with a fresh ray in r; kGridNone
 // if q lies outside the angle's N_u x N_v grid; kGridMasked if the ray's
-// mask cell is empty: no leaf box can be hit, so its record is written empty
-// (as for a miss) and the ray needs no traversal.
+// mask cell is empty: no leaf box can be hit, so the ray is a miss without
+// traversal (no record, as for a miss).
 constexpr int kGridNone = 0, kGridRay = 1, kGridMasked = 2;
 
 __device__ __forceinline__ int grid_ray(const Params &p, int64_t q, Ray &r, int a_lo, int a_hi)
@@ -543,10 +647,8 @@ __device__ __forceinline__ int grid_ray(const Params &p, int64_t q, Ray &r, int 
     const int i = static_cast<int>(t % pl.tu) * tw + (k & (tw - 1));
     const int j = static_cast<int>(t / pl.tu) * (kTileRays >> p.tile_shift) + (k >> p.tile_shift);
     if (i >= pl.nu || j >= pl.nv) return kGridNone;
-    if (p.mask && p.mask[pl.mask_base + static_cast<int64_t>(j >> kMaskShift) * pl.mcu + (i >> kMaskShift)] == 0) {
-        p.rec.r2[pl.rec_base + static_cast<int64_t>(j) * pl.nu + i] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
-        return kGridMasked;
-    }
+    if (p.mask && p.mask[pl.mask_base + static_cast<int64_t>(j >> kMaskShift) * pl.mcu + (i >> kMaskShift)] == 0)
+        return kGridMasked;  // no record (its byte stays 0)
     const double ui = pl.uc + ((static_cast<double>(i) + 0.5) - 0.5 * static_cast<double>(pl.nu)) * pl.ds;
     const double vj = pl.vc + ((static_cast<double>(j) + 0.5) - 0.5 * static_cast<double>(pl.nv)) * pl.ds;
     r.ox = static_cast<float>((ui * pl.u[0] + vj * pl.v[0]) + pl.s0 * pl.k[0]);
@@ -677,6 +779,9 @@ __device__ __forceinline__ bool bounce(const Params &p, Ray &r, const BestT<R> &
     return N < p.bmax;
 }
 
+// Slot e of the sweep records holds a record (the ray's own byte).
+__device__ __forceinline__ void mark_record(const Params &p, int64_t e) { p.rec.held[e] = 1; }
+
 template <int U = -1, typename R = float>
 __device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const BestT<R> &b, const Last &L)
 {
@@ -701,19 +806,24 @@ __device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Be
         p.rec.r1[e] = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
         p.rec.r2[e] = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (L.flags << 8)));
         p.rec.D[e] = L.D;
+        if (N == 1) mark_record(p, e);
     }
 }
 
 // The sweep record of ray r from its last hit (triangle tri_last, bookkeeping
-// L, record flags fl), written once when the ray ends.
+// L, record flags fl), written once when the ray ends, and only when it
+// enters the PO sum (a trapped ray dropped by SBR_OPT_DROP_TRAPPED writes
+// nothing).
 __device__ __forceinline__ void sink_record(const Params &p, const Ray &r, int tri_last, const Last &L, int fl)
 {
+    if (!(fl & SBR_REC_VALID)) return;
     const int N = r.meta & 127;
     const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
     p.rec.r0[e] = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(tri_last));
     p.rec.r1[e] = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
     p.rec.r2[e] = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (fl << 8)));
     p.rec.D[e] = L.D;
+    mark_record(p, e);
 }
 
 // A ray whose first query missed: an empty record.
@@ -735,10 +845,8 @@ __device__ __forceinline__ void sink_miss(const Params &p, const Ray &r)
             if (h.eH_last) h.eH_last[3 * e + a] = 0.f;
             if (h.eV_last) h.eV_last[3 * e + a] = 0.f;
         }
-    } else {
-        const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
-        p.rec.r2[e] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
     }
+    // sweep records: nothing (the slot's byte stays 0)
 }
 
 template <int U = -1>
@@ -814,7 +922,8 @@ __device__ __forceinline__ void init_stats(BlockStats &bs)
 // ---------------------------------------------------------------------------
 // (The float64 study variant holds twice the registers of the traversal
 // state: three waves per SIMD instead of spilling.)
-template <int SRC, bool SPILL, typename R = float>  // SRC: 0 = angle grid, 1 = caller rays; R: see BestT
+// W: node width of the tree walked (2: BNode, 4: BNode4).
+template <int SRC, bool SPILL, typename R = float, int W = 2>  // SRC: 0 = angle grid, 1 = caller rays; R: see BestT
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD))) void k_stream(Params p)
 {
@@ -881,7 +990,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
         b.slot = -1;
         SceneRef sc{0, 0.f, 0.f};
         if (has) sc = scene_of<kUser>(p, r);
-        if (has) b = closest<SPILL, SRC == 1, R>(p, r, st, sc);
+        if (has) b = closest<SPILL, SRC == 1, R, W>(p, r, st, sc);
         if (has) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (has) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         if (has) {
@@ -894,7 +1003,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
                 if (!cont) {
                     int fl = L.flags;
                     if (p.flags & SBR_OPT_DROP_TRAPPED) {
-                        const BestT<R> b2 = closest<SPILL, SRC == 1, R>(p, r, st, sc);
+                        const BestT<R> b2 = closest<SPILL, SRC == 1, R, W>(p, r, st, sc);
                         atomicAdd(&bs.queries, 1u);
                         if (b2.slot >= 0) {  // trapped: flagged and dropped from the PO sum
                             if (kUser) flag_trapped<kUser>(p, r);
@@ -1110,7 +1219,11 @@ __global__ __launch_bounds__(kMaskBlock) void k_mask(const BNode *__restrict__ n
 
 int trace_block_threads() { return kBlock; }
 int trace_stack_lds() { return kStackSpillLds; }
-bool trace_needs_spill(const sbr_bvh *bvh) { return bvh->depth > kStackLds; }
+bool trace_needs_spill(const sbr_bvh *bvh, bool wide) { return stack_need(bvh, wide) > kStackLds; }
+bool trace_walks_wide(const sbr_bvh *bvh, uint32_t flags, int schedule)
+{
+    return (flags & SBR_OPT_BVH4) && bvh->nodes4 != nullptr && bvh->scenes.empty() && schedule == kScheduleStream;
+}
 
 int trace_persistent_blocks(sbr_ctx *ctx, int blocks_per_cu)
 {
@@ -1134,8 +1247,8 @@ int check_tune(const sbr_tune &t)
     if (t.refill_min < 1 || t.refill_min > 64) return fail(SBR_ERR_INVALID_ARG, "sbr_tune: refill_min in [1, 64]");
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32)
         return fail(SBR_ERR_INVALID_ARG, "sbr_tune: blocks_per_cu in [0, 32]");
-    if (t.chunk_log2 != 0 && (t.chunk_log2 < 16 || t.chunk_log2 > 26))
-        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: chunk_log2 must be 0 or in [16, 26]");
+    if (t.chunk_log2 != 0 && (t.chunk_log2 < 16 || t.chunk_log2 > 28))
+        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: chunk_log2 must be 0 or in [16, 28]");
     return SBR_OK;
 }
 
@@ -1143,6 +1256,7 @@ static Params make_params(const TraceArgs &a, int launch)
 {
     Params p;
     p.nodes = a.bvh->nodes;
+    p.nodes4 = trace_walks_wide(a.bvh, a.flags, a.schedule) ? a.bvh->nodes4 : nullptr;
     p.tris = a.bvh->tris;
     p.nrm = a.bvh->nrm_slot;
     p.eps = a.bvh->eps;
@@ -1189,9 +1303,18 @@ static void launch_trace_t(hipStream_t s, const TraceArgs &a, const Params &p, i
 {
     const bool user = a.hits != nullptr;
     if (a.schedule == kScheduleStream) {
+        const bool wide = p.nodes4 != nullptr;
         if (a.flags & SBR_OPT_FP64_TRAVERSE) {
-            if (user) k_stream<1, SPILL, double><<<a.blocks, kBlock, 0, s>>>(p);
-            else k_stream<0, SPILL, double><<<a.blocks, kBlock, 0, s>>>(p);
+            if (wide) {
+                if (user) k_stream<1, SPILL, double, 4><<<a.blocks, kBlock, 0, s>>>(p);
+                else k_stream<0, SPILL, double, 4><<<a.blocks, kBlock, 0, s>>>(p);
+            } else {
+                if (user) k_stream<1, SPILL, double><<<a.blocks, kBlock, 0, s>>>(p);
+                else k_stream<0, SPILL, double><<<a.blocks, kBlock, 0, s>>>(p);
+            }
+        } else if (wide) {
+            if (user) k_stream<1, SPILL, float, 4><<<a.blocks, kBlock, 0, s>>>(p);
+            else k_stream<0, SPILL, float, 4><<<a.blocks, kBlock, 0, s>>>(p);
         } else {
             if (user) k_stream<1, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
             else k_stream<0, SPILL><<<a.blocks, kBlock, 0, s>>>(p);
@@ -1282,8 +1405,8 @@ int noalloc_counters(int device, CounterPtrs &c, void **base, size_t *bytes)
 int launch_trace(hipStream_t s, const TraceArgs &a, int bounce)
 {
     const Params p = make_params(a, bounce);
-    // the stack holds at most one entry per level of the current path
-    if (trace_needs_spill(a.bvh)) launch_trace_t<true>(s, a, p, bounce);
+    // the stack holds at most one entry per level of the current path (three for a BVH4)
+    if (trace_needs_spill(a.bvh, p.nodes4 != nullptr)) launch_trace_t<true>(s, a, p, bounce);
     else launch_trace_t<false>(s, a, p, bounce);
     SBR_HIP(hipGetLastError());
     return SBR_OK;

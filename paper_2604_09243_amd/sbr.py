@@ -26,6 +26,7 @@ OPT_DROP_TRAPPED, OPT_PAPER_PATH, OPT_ALLOW_UNDERSAMPLING, OPT_SYNC, OPT_WAVEFRO
 OPT_NO_MASK = 64
 OPT_FP32_PATH = 128
 OPT_FP64_TRAVERSE = 256
+OPT_BVH4 = 512
 MAX_BOUNCES = 127
 
 _vp = C.c_void_p
