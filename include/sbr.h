@@ -283,7 +283,7 @@ int sbr_trace(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_rays *rays, int64_t n_
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  The same transport, arguments and results as sbr_trace, bit
  * for bit, but the call allocates nothing: its only scratch (the counter
- * block of one streaming launch, 8 KiB) is a static array of the library,
+ * block of one streaming launch, 40 KiB) is a static array of the library,
  * one copy per device, looked up when sbr_create sets up the device; the
  * counters are cleared by a fill kernel (no memset node).  Limits: the
  * streaming schedule only (SBR_OPT_WAVEFRONT -> SBR_ERR_UNSUPPORTED: its
@@ -332,7 +332,7 @@ typedef struct {
     int32_t claim_tiles;   /* tiles a wave claims per atomic, 1..64 */
     int32_t refill_min;    /* idle lanes that trigger a refill (streaming launch), 1..64 */
     int32_t blocks_per_cu; /* persistent blocks of 256 threads per compute unit; 0 = occupancy limit */
-    int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..28; 0 = 26.  Records of a
+    int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..30; 0 = 28.  Records of a
                               chunk stay in device memory between its trace and its PO stage. */
     int32_t reserved;
 } sbr_tune;

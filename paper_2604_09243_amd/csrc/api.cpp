@@ -277,7 +277,7 @@ sbr_tune default_tune()
     t.struct_size = sizeof(sbr_tune);
     t.schedule = kScheduleStream;
     t.tile_w = 8;
-    t.claim_tiles = 4;
+    t.claim_tiles = 2;
     t.refill_min = 64;
     t.blocks_per_cu = 0;
     t.chunk_log2 = kDefaultChunkLog2;

@@ -480,6 +480,7 @@ extern "C" int sbr_batch_create(sbr_ctx *ctx, const sbr_bvh *scenes, const sbr_b
         if (!(d->freqs_hz[f] > 0.0) || !std::isfinite(d->freqs_hz[f]))
             return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: frequencies must be positive and finite");
     sbr_tune tune = default_tune();
+    tune.chunk_log2 = kBatchChunkLog2;
     if (d->tune) {
         if (d->tune->struct_size < sizeof(sbr_tune))
             return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: tune->struct_size too small");

@@ -116,15 +116,17 @@ inline int64_t held_words(int64_t slots) { return (slots + 3) / 4; }
 //   stat:  u64[kStatU64] = [0] queries, [1] trapped, [8 + b] hits at bounce b,
 //          [kStatMasked] primary rays resolved by the mask (counted in [0] too)
 //   q_cnt: kQcnt lines; q_cnt[b] = rays pushed during bounce-b launch
-//   claim: kMaxLaunch x 8 lines; the 8 tile-claim counters of each launch
+//   claim: kMaxLaunch x kClaimRanges lines; the tile-claim counters of each
+//          launch (kClaimRanges ranges, kClaimRanges / 8 per XCD)
 constexpr int kLineU32 = 64;
+constexpr int kClaimRanges = 64;
 constexpr int kStatMasked = 8 + SBR_MAX_BOUNCES + 1;
 constexpr int kStatU64 = kStatMasked + 1;
 constexpr int kMaxLaunch = SBR_MAX_BOUNCES + 2;
 constexpr int kQcnt = SBR_MAX_BOUNCES + 2;
 constexpr size_t kStatBytes = 2048;
 static_assert(8 * kStatU64 <= kStatBytes, "the stat counters fit their block");
-constexpr size_t kCounterBytes = kStatBytes + 4ull * kLineU32 * (kQcnt + 8 * kMaxLaunch);
+constexpr size_t kCounterBytes = kStatBytes + 4ull * kLineU32 * (kQcnt + size_t(kClaimRanges) * kMaxLaunch);
 struct CounterPtrs {
     unsigned long long *stat;
     uint32_t *q_cnt;
@@ -326,7 +328,7 @@ int launch_trace(hipStream_t s, const TraceArgs &a, int bounce);
 // noalloc_scratch_setup looks up this device's address (the device must be
 // current; done once by sbr_create); noalloc_counters lays the counter block
 // of one streaming launch over it (base and the bytes to clear).
-constexpr size_t kNoallocScratchBytes = 8192;
+constexpr size_t kNoallocScratchBytes = 40960;
 int noalloc_scratch_setup(int device);
 int noalloc_counters(int device, CounterPtrs &c, void **base, size_t *bytes);
 // Builds the primary-ray mask of plans [0, n_angles) of one launch: zeroes
@@ -366,7 +368,12 @@ int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector
 size_t spill_words(const sbr_bvh *bvh, int blocks);
 // Device plan of one angle from its host plan (tiles of tile_w x 64/tile_w).
 void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p);
-constexpr int kDefaultChunkLog2 = 26;
+// Rays per chunk by default: 2^28 for sweeps (records of up to 2^28 rays,
+// 15 GB, stay on the device between trace and PO; fewer launches, fewer
+// launch tails); batches keep 2^26 (their replayed graph holds every
+// chunk's launches).
+constexpr int kDefaultChunkLog2 = 28;
+constexpr int kBatchChunkLog2 = 26;
 // Autotuner cache: the context's map, then the JSON-lines file named by
 // $SBR_TUNE_CACHE (if any).
 bool tune_lookup(sbr_ctx *ctx, const std::string &key, sbr_tune *out);

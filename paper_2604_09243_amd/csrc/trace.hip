@@ -7,11 +7,11 @@
 //   refilled: a wave ballot of the idle lanes ranks them (mbcnt prefix count)
 //   and idle lane k takes the k-th unused ray of the wave's current batch,
 //   so the active rays stay packed into the wave without moving any ray
-//   state.  A batch (kClaimTiles 64-ray tiles) is claimed with one atomic on
-//   one of eight counters, each counter on its own 256-byte line and owning
-//   an XCD-sized contiguous range of tiles (a block's XCD is taken as
+//   state.  A batch of 64-ray tiles is claimed with one atomic on one of
+//   kClaimRanges counters, each on its own 256-byte line and owning a
+//   contiguous range of tiles served by one XCD (a block's XCD is taken as
 //   blockIdx % 8, the order in which workgroups are spread over the dies);
-//   a wave whose range is empty steals from the others.
+//   a wave whose range is empty steals, first within its XCD.
 // WAVEFRONT: one launch per bounce.  Rays that hit and have bounces left are
 //   compacted into the next bounce's queue with one atomic per wave (ballot
 //   + prefix popcount); the next launch reads that queue.
@@ -115,7 +115,7 @@ struct Params {
     Records rec;
     // misc
     int64_t n_tiles;
-    uint32_t *ctr;  // 8 claim counters, kLineU32 apart
+    uint32_t *ctr;  // kClaimRanges claim counters, kLineU32 apart
     unsigned long long *stat;
     int32_t *spill;
     int bounce;
@@ -574,19 +574,26 @@ __device__ __forceinline__ uint64_t lanemask_lt()
     return (1ull << lane) - 1ull;
 }
 
-// Claims a batch of up to `batch` units from eight contiguous ranges of
-// [0, n_units), starting with range `xcd`.  Returns the first unit and sets
-// *end, or returns -1 when every range is exhausted.
-__device__ __forceinline__ int64_t claim(uint32_t *ctr, int64_t n_units, int xcd, int batch, int64_t *end)
+// Claims a batch of up to `batch` units from kClaimRanges contiguous ranges
+// of [0, n_units), each with its own counter line; `home` = blockIdx %
+// kClaimRanges, so a range serves one XCD (home % 8) and a few of its CUs,
+// and every counter is shared by few waves.  When the home range is
+// exhausted the wave steals: first from the other ranges of its XCD, then
+// from the other XCDs'.  Returns the first unit and sets *end, or returns -1
+// when every range is exhausted.
+__device__ __forceinline__ int64_t claim(uint32_t *ctr, int64_t n_units, int home, int batch, int64_t *end)
 {
-    for (int kk = 0; kk < 8; ++kk) {
-        const int c = (xcd + kk) & 7;
-        const int64_t lo = n_units * c / 8, hi = n_units * (c + 1) / 8;
-        if (hi <= lo) continue;
-        const uint32_t t = atomicAdd(&ctr[c * kLineU32], static_cast<uint32_t>(batch));
-        if (lo + static_cast<int64_t>(t) < hi) {
-            *end = min(lo + static_cast<int64_t>(t) + batch, hi);
-            return lo + t;
+    constexpr int kPerXcd = kClaimRanges / 8;
+    for (int x = 0; x < 8; ++x) {
+        for (int y = 0; y < kPerXcd; ++y) {
+            const int c = ((home + x) & 7) + 8 * ((home / 8 + y) % kPerXcd);
+            const int64_t lo = n_units * c / kClaimRanges, hi = n_units * (c + 1) / kClaimRanges;
+            if (hi <= lo) continue;
+            const uint32_t t = atomicAdd(&ctr[c * kLineU32], static_cast<uint32_t>(batch));
+            if (lo + static_cast<int64_t>(t) < hi) {
+                *end = min(lo + static_cast<int64_t>(t) + batch, hi);
+                return lo + t;
+            }
         }
     }
     return -1;
@@ -936,7 +943,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
     st.gstride = static_cast<int64_t>(gridDim.x) * kBlock;
     st.gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const int xcd = blockIdx.x & 7;
+    const int home = blockIdx.x % kClaimRanges;  // this block's claim range (on XCD blockIdx % 8)
     const uint64_t lt = lanemask_lt();
     const int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
     int64_t pos = 0, end = 0;  // wave-uniform: unused positions [pos, end) of the claimed batch
@@ -957,7 +964,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
             if (__popcll(idle) < p.refill_min && idle != __ballot(1)) break;
             if (pos >= end) {
                 int64_t u = -1, e = 0;
-                if (lane == 0) u = claim(p.ctr, n_units, xcd, p.claim_tiles, &e);
+                if (lane == 0) u = claim(p.ctr, n_units, home, p.claim_tiles, &e);
                 u = __shfl(u, 0);
                 e = __shfl(e, 0);
                 if (u < 0) {
@@ -1038,7 +1045,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
     st.gstride = static_cast<int64_t>(gridDim.x) * kBlock;
     st.gst = p.spill + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const int xcd = blockIdx.x & 7;
+    const int home = blockIdx.x % kClaimRanges;  // this block's claim range (on XCD blockIdx % 8)
     int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
     int64_t n_in = 0;
     if (SRC == 2) {
@@ -1050,7 +1057,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
     for (;;) {
         if (tile >= tend) {
             int64_t u = -1, e = 0;
-            if (lane == 0) u = claim(p.ctr, n_units, xcd, p.claim_tiles, &e);
+            if (lane == 0) u = claim(p.ctr, n_units, home, p.claim_tiles, &e);
             u = __shfl(u, 0);
             e = __shfl(e, 0);
             if (u < 0) break;
@@ -1247,8 +1254,8 @@ int check_tune(const sbr_tune &t)
     if (t.refill_min < 1 || t.refill_min > 64) return fail(SBR_ERR_INVALID_ARG, "sbr_tune: refill_min in [1, 64]");
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32)
         return fail(SBR_ERR_INVALID_ARG, "sbr_tune: blocks_per_cu in [0, 32]");
-    if (t.chunk_log2 != 0 && (t.chunk_log2 < 16 || t.chunk_log2 > 28))
-        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: chunk_log2 must be 0 or in [16, 28]");
+    if (t.chunk_log2 != 0 && (t.chunk_log2 < 16 || t.chunk_log2 > 30))
+        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: chunk_log2 must be 0 or in [16, 30]");
     return SBR_OK;
 }
 
@@ -1287,7 +1294,7 @@ static Params make_params(const TraceArgs &a, int launch)
     p.qout_cnt = a.ctrs.q_cnt + launch * kLineU32;
     p.rec = a.rec;
     p.n_tiles = a.n_tiles;
-    p.ctr = a.ctrs.claim + launch * 8 * kLineU32;
+    p.ctr = a.ctrs.claim + static_cast<size_t>(launch) * kClaimRanges * kLineU32;
     p.stat = a.ctrs.stat;
     p.spill = a.spill;
     p.bounce = launch;
@@ -1350,7 +1357,7 @@ int launch_mask(hipStream_t s, const BNode *nodes, const AnglePlan *plans, int n
 //   [0, kStatBytes)               stat (u64 counters)
 //   2 lines                       q_cnt of launches 0 and 1 (not read by the
 //                                 streaming schedule, but addressed)
-//   16 lines                      claim counters of launches 0 and 1
+//   2 x kClaimRanges lines        claim counters of launches 0 and 1
 // Every device holds its own copy of the array at its own address.  In host
 // code the array's name is not a device address: the address of each
 // device's copy is looked up once, with that device current, and only that
@@ -1358,7 +1365,7 @@ int launch_mask(hipStream_t s, const BNode *nodes, const AnglePlan *plans, int n
 // ---------------------------------------------------------------------------
 constexpr size_t kNoallocQcntOff = kStatBytes;
 constexpr size_t kNoallocClaimOff = kNoallocQcntOff + 2 * 4 * kLineU32;
-constexpr size_t kNoallocUsed = kNoallocClaimOff + 2 * 8 * 4 * kLineU32;
+constexpr size_t kNoallocUsed = kNoallocClaimOff + 2 * size_t(kClaimRanges) * 4 * kLineU32;
 static_assert(kNoallocUsed <= kNoallocScratchBytes, "the no-alloc counter layout fits its scratch");
 
 static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
