@@ -418,9 +418,11 @@ def _copol_db(A):
 def bench_surrogate(args):
     """Dense grid 0.1 deg x 512 frequencies (3600 x 512 points, 8-12 GHz,
     ray spacing lambda(12 GHz)/8) filled two ways on the same GPU: plain SBR
-    (one trace per direction + 512-frequency PO) and the surrogate pipeline
-    (SBR training sweep at 1 deg x 64 frequencies, training, inference, SBR
-    probes per tile of 1 deg x 32 frequencies, SBR fallback on failing
+    (one trace per direction + 512-frequency PO) and the anchored surrogate
+    pipeline (SBR at the 1 deg training directions for every grid frequency,
+    training on 64 of them, a held-out check at the others that sends a
+    hopeless grid to plain SBR, else inference, SBR probes per tile of the
+    0.9 deg between anchors x 32 frequencies and SBR fallback on failing
     tiles).  Steps alternate the two; the error is audited on every grid
     point against the plain result."""
     import torch
@@ -437,18 +439,19 @@ def bench_surrogate(args):
         th0, bm = 90.0, 8
     bvh = ctx.build_bvh(V, T)
     ds = C0 / 12e9 / 8
-    train = (np.full(360, th0), np.arange(360.0), np.linspace(8e9, 12e9, 64))
     query = (np.full(3600, th0), np.arange(3600) * 0.1, np.linspace(8e9, 12e9, 512))
+    # training set on the grid: every 10th direction (1 deg) x every 8th frequency (64 in 8-12 GHz)
+    train = (np.full(360, th0), np.arange(360.0), query[2][::8])
     kw = dict(net_kw=dict(ff_sigma=2.0, seed=1), train_kw=dict(epochs=40, batch=4096, lr=4e-3, lr_min=4e-5, seed=0),
-              tile_angles=10, tile_freqs=32, tol_db=0.25, floor_db=40.0)
+              tile_freqs=32, tol_db=0.25, floor_db=40.0)
     for _ in range(args.warmup):
-        pipeline.surrogate_fill(ctx, bvh, train, query, ds, bm, **kw)
+        pipeline.anchored_fill(ctx, bvh, train, query, ds, bm, **kw)
         ctx.rcs_sweep(bvh, *query, bm, ds=ds, stats=False)
     t_sur, t_plain = [], []
     for _ in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        A, info = pipeline.surrogate_fill(ctx, bvh, train, query, ds, bm, **kw)
+        A, info = pipeline.anchored_fill(ctx, bvh, train, query, ds, bm, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         Ap, _, st = ctx.rcs_sweep(bvh, *query, bm, ds=ds)
@@ -474,10 +477,12 @@ def bench_surrogate(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16 MFMA (fp32 accumulation) + SBR f32/f64",
         "data": "synthetic (seeded procedural mesh)",
         "config": {"workload": "surrogate_%s_3600x512" % args.target, "train": "360 x 64", "query": "3600 x 512",
-                   "tiles": "1 deg x 32 f", "probes": "1 direction x 2 f per tile", "tol_db": 0.25,
+                   "tiles": "9 directions between anchors x 32 f", "probes": "1 direction x 2 f per tile",
+                   "tol_db": 0.25,
                    "floor_db": 40.0, "audit_floor_db": 30.0, "epochs": 40, "batch": 4096, "lr": 4e-3},
         "plain_points_per_s": n / tp, "plain_ms": 1e3 * tp, "gain": tp / ts, "beats_plain_sbr": bool(tp > ts),
         "fallback_tile_frac": float(fb.mean()), "stage_s": {k: v for k, v in info.items() if k.startswith("s_")},
+        "decision": info.get("decision"), "held_out_fail_frac": info.get("held_out_fail_frac"),
         "fill_ms": {k: v for k, v in info["fill"].items() if k.startswith("ms_")},
         "final_loss": float(info["loss"][-1]), "audit_vs_plain": audit,
         "plain_trace_ms": st["ms_trace"], "plain_po_ms": st["ms_po"], "plain_rays": st["rays"],
