@@ -161,7 +161,7 @@ enum Slot {
     W_COUNTERS = 0,
     W_QA = 1,   // 6 buffers: 1..6
     W_QB = 7,   // 7..12
-    W_REC = 13, // 13..16
+    W_REC = 13, // 13 (14..16 unused)
     W_PLANS = 17,
     W_TILEBASE = 18,
     W_BASIS = 20,
@@ -192,17 +192,12 @@ static int get_queue(Workspace *ws, int first, size_t cap, RayQueue &q)
 
 static int get_records(Workspace *ws, size_t cap, Records &r)
 {
-    void *p[4];
+    void *pr, *pv;
     int rc;
-    void *pv;
-    if ((rc = ws->get(W_REC + 0, 16 * cap, &p[0])) || (rc = ws->get(W_REC + 1, 16 * cap, &p[1])) ||
-        (rc = ws->get(W_REC + 2, 16 * cap, &p[2])) || (rc = ws->get(W_REC + 3, 8 * cap, &p[3])) ||
+    if ((rc = ws->get(W_REC, sizeof(Rec) * cap, &pr)) ||
         (rc = ws->get(W_HELD, 4 * static_cast<size_t>(held_words(static_cast<int64_t>(cap))), &pv)))
         return rc;
-    r.r0 = static_cast<float4 *>(p[0]);
-    r.r1 = static_cast<float4 *>(p[1]);
-    r.r2 = static_cast<float4 *>(p[2]);
-    r.D = static_cast<double *>(p[3]);
+    r.rec = static_cast<Rec *>(pr);
     r.held = static_cast<uint8_t *>(pv);
     return SBR_OK;
 }

@@ -227,13 +227,11 @@ int plan_batch(sbr_batch *b)
     }
     b->blocks = trace_persistent_blocks(b->ctx, b->tune.blocks_per_cu);
     int rc;
-    float4 *r0, *r1, *r2;
-    double *rD;
+    Rec *recs;
     uint32_t *held;
     if ((rc = b->dev.alloc(&b->d_plans, ni)) || (rc = b->dev.alloc(&b->d_tile, tile_words)) ||
         (rc = b->dev.alloc(&b->d_ang, ni)) || (rc = b->dev.alloc(&b->d_kf, b->freqs.size())) ||
-        (rc = b->dev.alloc(&r0, max_rays)) || (rc = b->dev.alloc(&r1, max_rays)) ||
-        (rc = b->dev.alloc(&r2, max_rays)) || (rc = b->dev.alloc(&rD, max_rays)) ||
+        (rc = b->dev.alloc(&recs, max_rays)) ||
         (rc = b->dev.alloc(&held, static_cast<size_t>(held_words(max_rays)))) ||
         (rc = b->dev.alloc(&b->d_part, 8 * static_cast<size_t>(max_rows))) ||
         (rc = b->dev.alloc(&b->d_ctr, kCounterBytes / 4)) ||
@@ -242,7 +240,7 @@ int plan_batch(sbr_batch *b)
     b->d_mask = nullptr;
     if (!(b->flags & SBR_OPT_NO_MASK) && (rc = b->dev.alloc(&b->d_mask, static_cast<size_t>(max_mask))))
         return rc;
-    b->rec = Records{r0, r1, r2, rD, reinterpret_cast<uint8_t *>(held)};
+    b->rec = Records{recs, reinterpret_cast<uint8_t *>(held)};
     char *cb = reinterpret_cast<char *>(b->d_ctr);
     b->ctrs.stat = reinterpret_cast<unsigned long long *>(cb);
     b->ctrs.q_cnt = reinterpret_cast<uint32_t *>(cb + kStatBytes);

@@ -215,10 +215,10 @@ __device__ __forceinline__ void po_passes(const PoP &p, const PoAngle &A, int64_
             for (int e = 0; e < 8; ++e) acc[ft][e] = 0.0;
         for (int64_t e = A.rec_base + r0i + tid; e < A.rec_base + r1i; e += kPoThreads) {
             if (!p.rec.held[e]) continue;  // no record in this slot
-            const float4 q2 = p.rec.r2[e];
+            const Rec &rec = p.rec.rec[e];
+            const float4 q2 = rec.r2, q0 = rec.r0, q1 = rec.r1;
+            const double D = rec.D.x;
             if (!((__float_as_int(q2.w) >> 8) & SBR_REC_VALID)) continue;  // dropped as trapped: no term
-            const float4 q0 = p.rec.r0[e], q1 = p.rec.r1[e];
-            const double D = p.rec.D[e];
             double w[4];
             weights(p, A.basis, q0, q1, q2, w);
             double sd, cd, rs = 0.0, rc = 1.0;
@@ -362,10 +362,11 @@ __global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
         for (int j = 0; j < kPer; ++j) {
             const int64_t ea = A.rec_base + s0 + tid + j * kPoThreads;
             if (held[j]) {
-                q0[j] = p.rec.r0[ea];
-                q1[j] = p.rec.r1[ea];
-                q2[j] = p.rec.r2[ea];
-                Dj[j] = p.rec.D[ea];
+                const Rec &rec = p.rec.rec[ea];
+                q0[j] = rec.r0;
+                q1[j] = rec.r1;
+                q2[j] = rec.r2;
+                Dj[j] = rec.D.x;
             }
         }
 #pragma unroll
@@ -560,12 +561,13 @@ __global__ void k_pack(sbr_hits h, int64_t n, Records rec)
     const bool valid = (fl & SBR_REC_VALID) != 0;
     rec.held[e] = valid ? 1 : 0;
     if (!valid) return;
-    rec.r0[e] = make_float4(h.d_last[3 * e], h.d_last[3 * e + 1], h.d_last[3 * e + 2], __int_as_float(h.tri_last[e]));
-    rec.r1[e] = make_float4(h.eH_last[3 * e], h.eH_last[3 * e + 1], h.eH_last[3 * e + 2],
+    Rec &q = rec.rec[e];
+    q.r0 = make_float4(h.d_last[3 * e], h.d_last[3 * e + 1], h.d_last[3 * e + 2], __int_as_float(h.tri_last[e]));
+    q.r1 = make_float4(h.eH_last[3 * e], h.eH_last[3 * e + 1], h.eH_last[3 * e + 2],
                             __int_as_float(h.tri_first[e]));
-    rec.r2[e] = make_float4(h.eV_last[3 * e], h.eV_last[3 * e + 1], h.eV_last[3 * e + 2],
+    q.r2 = make_float4(h.eV_last[3 * e], h.eV_last[3 * e + 1], h.eV_last[3 * e + 2],
                             __int_as_float((h.n_bounce[e] & 255) | (fl << 8)));
-    rec.D[e] = h.D[e];
+    q.D = make_double2(h.D[e], 0.0);
 }
 
 }  // namespace

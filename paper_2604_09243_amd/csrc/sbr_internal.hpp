@@ -95,17 +95,24 @@ struct RayQueue {
     double2 *s5;
 };
 
-// Hit record of one ray (structure of arrays); r2.w carries N | flags << 8.
+// Hit record of one ray: one 64-byte block per slot, written whole by the
+// lane whose ray ends (four 16-byte stores into one block, which the L2
+// merges into full-sector writes; four arrays of 8-16 bytes per slot cost
+// about twice the record bytes in partial-sector writes), read whole by PO.
 //   r0 = (d_last.xyz, tri_last)  r1 = (eH_last.xyz, tri_first)
-//   r2 = (eV_last.xyz, N | flags << 8)  D
+//   r2 = (eV_last.xyz, N | flags << 8)  D = (D, 0)
+struct __align__(64) Rec {
+    float4 r0, r1, r2;
+    double2 D;
+};
+static_assert(sizeof(Rec) == 64, "a record is one 64-byte block");
 // held: one byte per record slot, 1 when slot e holds a record.  The slots
 // of rays that never hit (or whose record was dropped) are neither written
 // nor read; their byte stays 0.  The bytes are cleared (a kernel) before
 // each launch that fills the records; every ray writes only its own byte,
 // so no atomics are needed.
 struct Records {
-    float4 *r0, *r1, *r2;
-    double *D;
+    Rec *rec;
     uint8_t *held;
 };
 // 32-bit words of a slot-byte array (cleared as words)

@@ -809,10 +809,11 @@ __device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Be
         if (h.tri_path) h.tri_path[e * p.bmax + (N - 1)] = b.id;
     } else {
         const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
-        p.rec.r0[e] = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(b.id));
-        p.rec.r1[e] = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
-        p.rec.r2[e] = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (L.flags << 8)));
-        p.rec.D[e] = L.D;
+        Rec &q = p.rec.rec[e];
+        q.r0 = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(b.id));
+        q.r1 = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
+        q.r2 = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (L.flags << 8)));
+        q.D = make_double2(L.D, 0.0);
         if (N == 1) mark_record(p, e);
     }
 }
@@ -826,10 +827,11 @@ __device__ __forceinline__ void sink_record(const Params &p, const Ray &r, int t
     if (!(fl & SBR_REC_VALID)) return;
     const int N = r.meta & 127;
     const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
-    p.rec.r0[e] = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(tri_last));
-    p.rec.r1[e] = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
-    p.rec.r2[e] = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (fl << 8)));
-    p.rec.D[e] = L.D;
+    Rec &q = p.rec.rec[e];
+    q.r0 = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(tri_last));
+    q.r1 = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
+    q.r2 = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (fl << 8)));
+    q.D = make_double2(L.D, 0.0);
     mark_record(p, e);
 }
 
@@ -864,10 +866,10 @@ __device__ __forceinline__ void flag_trapped(const Params &p, const Ray &r)
         if (p.hits.flags) p.hits.flags[r.id] = (p.hits.flags[r.id] | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
     } else {
         const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
-        float4 v = p.rec.r2[e];
+        float4 v = p.rec.rec[e].r2;
         const int fl = ((__float_as_int(v.w) >> 8) | SBR_REC_TRAPPED) & ~SBR_REC_VALID;
         v.w = __int_as_float(N | (fl << 8));
-        p.rec.r2[e] = v;
+        p.rec.rec[e].r2 = v;
     }
 }
 
