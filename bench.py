@@ -207,6 +207,8 @@ def main():
                     help="aircraft, batch: autotune the launch parameters first (set-up, not timed)")
     ap.add_argument("--no-mask", action="store_true",
                     help="trace every primary ray (no per-angle mask of empty cells)")
+    ap.add_argument("--chunk-log2", type=int, default=0,
+                    help="batch: rays per chunk = 2^N (16..30; 0 = the library default)")
     ap.add_argument("--bvh4", action="store_true",
                     help="walk a four-wide copy of the tree (same results; a traversal study, slower on the aircraft)")
     ap.add_argument("--builder", choices=("lbvh", "sah", "ploc"), default="sah",
@@ -349,8 +351,10 @@ def bench_batch(args):
     scn = ctx.pack_scenes(bvhs)
     for b in bvhs:
         b.free()
+    from paper_2604_09243_amd import sbr
     b = ctx.batch(scn, w.items(), w.freqs(), w.max_bounces, samples_per_lambda=w.samples_per_lambda,
-                  flags=mask_flag(args))
+                  flags=mask_flag(args),
+                  tune=sbr.make_tune(chunk_log2=args.chunk_log2) if args.chunk_log2 else None)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     if args.autotune:

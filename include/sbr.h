@@ -332,7 +332,7 @@ typedef struct {
     int32_t claim_tiles;   /* tiles a wave claims per atomic, 1..64 */
     int32_t refill_min;    /* idle lanes that trigger a refill (streaming launch), 1..64 */
     int32_t blocks_per_cu; /* persistent blocks of 256 threads per compute unit; 0 = occupancy limit */
-    int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..30; 0 = 28.  Records of a
+    int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..30; 0 = 29.  Records of a
                               chunk stay in device memory between its trace and its PO stage. */
     int32_t reserved;
 } sbr_tune;

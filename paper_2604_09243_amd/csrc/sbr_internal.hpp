@@ -375,12 +375,14 @@ int run_trace(hipStream_t s, TraceArgs &a, RayQueue qa, RayQueue qb, std::vector
 size_t spill_words(const sbr_bvh *bvh, int blocks);
 // Device plan of one angle from its host plan (tiles of tile_w x 64/tile_w).
 void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p);
-// Rays per chunk by default: 2^28 for sweeps (records of up to 2^28 rays,
-// 15 GB, stay on the device between trace and PO; fewer launches, fewer
-// launch tails); batches keep 2^26 (their replayed graph holds every
-// chunk's launches).
-constexpr int kDefaultChunkLog2 = 28;
-constexpr int kBatchChunkLog2 = 26;
+// Rays per chunk by default: 2^29 for sweeps and batches.  A chunk's records
+// (64 bytes per ray: 34 GB at 2^29) stay on the device between its trace and
+// its PO; larger chunks mean fewer launches and fewer launch tails (the
+// 64-scene batch replays in 2.18 / 1.89 / 1.82 s with 2^26 / 2^28 / 2^29-ray
+// chunks, the aircraft sweep traces in 233 / 200 / 194 ms; 2^30 gains 2 %
+// more for 69 GB).
+constexpr int kDefaultChunkLog2 = 29;
+constexpr int kBatchChunkLog2 = 29;
 // Autotuner cache: the context's map, then the JSON-lines file named by
 // $SBR_TUNE_CACHE (if any).
 bool tune_lookup(sbr_ctx *ctx, const std::string &key, sbr_tune *out);
