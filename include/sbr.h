@@ -535,7 +535,8 @@ int sbr_mlp_predict(sbr_mlp *mlp, const double *pts, int64_t n, double *A_out);
  * squared error.  Synchronises. */
 int sbr_mlp_gradients(sbr_mlp *mlp, const double *pts, const double *targets, int64_t n, float *grads, float *loss);
 /* Adam training over shuffled batches; loss_per_epoch host [epochs],
- * nullable.  Synchronises once per epoch. */
+ * nullable.  Synchronises at the end (and once per group of epochs whose
+ * shuffled orders exceed 2^24 indices). */
 int sbr_mlp_train(sbr_mlp *mlp, const double *pts, const double *targets, int64_t n, const sbr_train_opts *opts,
                   float *loss_per_epoch);
 void sbr_mlp_destroy(sbr_mlp *mlp);

@@ -496,9 +496,14 @@ extern "C" int sbr_mlp_train(sbr_mlp *M, const double *pts, const double *target
     const int64_t total = static_cast<int64_t>(o->epochs) * steps;
     if ((rc = ensure_train(M, rows))) return rc;
     Bufs tmp;
-    int32_t *didx = nullptr;
-    float *dl = nullptr, *dlr = nullptr;
-    if ((rc = tmp.alloc(&didx, n)) || (rc = tmp.alloc(&dl, steps)) || (rc = tmp.alloc(&dlr, total))) return rc;
+    int32_t *didx = nullptr, *dperm = nullptr;
+    float *dl = nullptr, *dlr = nullptr, *dlall = nullptr;
+    const int64_t ep = o->epochs;
+    // epochs per group: their orders (at most 2^24 indices) are uploaded in one copy
+    const int64_t grp = std::max<int64_t>(1, std::min<int64_t>(ep, (int64_t(1) << 24) / std::max<int64_t>(n, 1)));
+    if ((rc = tmp.alloc(&didx, n)) || (rc = tmp.alloc(&dl, steps)) || (rc = tmp.alloc(&dlr, total)) ||
+        (rc = tmp.alloc(&dperm, grp * n)) || (rc = tmp.alloc(&dlall, ep * steps)))
+        return rc;
     // cosine decay from lr to lr_min over all steps of this call
     std::vector<float> lr(total);
     for (int64_t t = 0; t < total; ++t)
@@ -528,30 +533,52 @@ extern "C" int sbr_mlp_train(sbr_mlp *M, const double *pts, const double *target
     if (rc == SBR_OK && (ec != hipSuccess || !graph)) rc = fail(SBR_ERR_HIP, "sbr_mlp_train: graph capture failed");
     if (rc == SBR_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
         rc = fail(SBR_ERR_HIP, "sbr_mlp_train: graph instantiation failed");
+    // the epochs' orders (the same shuffles as one per epoch, drawn a group
+    // at a time) go to the device in one copy per group; the epochs then run
+    // back to back, each an on-device copy of its order, a graph replay and a
+    // copy of its losses, with one synchronisation per group (before the
+    // pinned buffer is refilled) and one at the end
     float *hl = nullptr;
-    if (rc == SBR_OK && hipHostMalloc(reinterpret_cast<void **>(&hl), 4 * static_cast<size_t>(std::max<int64_t>(steps, n)),
-                                      hipHostMallocDefault) != hipSuccess) {
+    const size_t host_words = static_cast<size_t>(std::max<int64_t>(grp * n, ep * steps));
+    if (rc == SBR_OK &&
+        hipHostMalloc(reinterpret_cast<void **>(&hl), 4 * host_words, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         hl = nullptr;
         rc = fail(SBR_ERR_OOM, "sbr_mlp_train: pinned allocation failed");
     }
-    int32_t *hidx = reinterpret_cast<int32_t *>(hl);  // one pinned buffer: the order, then the losses
     std::mt19937_64 rng(o->seed);
     std::vector<int32_t> perm(n);
     for (int64_t i = 0; i < n; ++i) perm[i] = static_cast<int32_t>(i);
-    for (int e = 0; e < o->epochs && rc == SBR_OK; ++e) {
-        std::shuffle(perm.begin(), perm.end(), rng);
-        std::memcpy(hidx, perm.data(), 4 * n);
-        if (hipMemcpyAsync(didx, hidx, 4 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipGraphLaunch(exec, s) != hipSuccess ||
-            hipMemcpyAsync(hl, dl, 4 * steps, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
+    int32_t *hperm = reinterpret_cast<int32_t *>(hl);  // one pinned buffer: the orders, then the losses
+    for (int64_t e0 = 0; e0 < ep && rc == SBR_OK; e0 += grp) {
+        const int64_t g = std::min(grp, ep - e0);
+        if (e0 > 0 && hipStreamSynchronize(s) != hipSuccess) {  // the previous group's upload read hperm
             rc = fail(SBR_ERR_HIP, "sbr_mlp_train: epoch launch failed");
             break;
         }
-        if (loss_per_epoch) {
+        for (int64_t e = 0; e < g; ++e) {
+            std::shuffle(perm.begin(), perm.end(), rng);
+            std::memcpy(hperm + e * n, perm.data(), 4 * n);
+        }
+        if (hipMemcpyAsync(dperm, hperm, 4 * g * n, hipMemcpyHostToDevice, s) != hipSuccess) {
+            rc = fail(SBR_ERR_HIP, "sbr_mlp_train: order upload failed");
+            break;
+        }
+        for (int64_t e = 0; e < g && rc == SBR_OK; ++e) {
+            if (hipMemcpyAsync(didx, dperm + e * n, 4 * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipGraphLaunch(exec, s) != hipSuccess ||
+                hipMemcpyAsync(dlall + (e0 + e) * steps, dl, 4 * steps, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                rc = fail(SBR_ERR_HIP, "sbr_mlp_train: epoch launch failed");
+        }
+    }
+    if (rc == SBR_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(SBR_ERR_HIP, "sbr_mlp_train: epoch failed");
+    if (rc == SBR_OK && (hipMemcpyAsync(hl, dlall, 4 * ep * steps, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+        rc = fail(SBR_ERR_HIP, "sbr_mlp_train: loss copy failed");
+    if (rc == SBR_OK && loss_per_epoch) {
+        for (int64_t e = 0; e < ep; ++e) {
             double sum = 0.0;
-            for (int64_t st = 0; st < steps; ++st) sum += hl[st];
+            for (int64_t st = 0; st < steps; ++st) sum += hl[e * steps + st];
             loss_per_epoch[e] = static_cast<float>(sum / (4.0 * static_cast<double>(n)));
         }
     }
@@ -597,6 +624,11 @@ int run_batch(sbr_ctx *ctx, const sbr_bvh *bvh, const std::vector<sbr_batch_item
     bd.flags = (d->flags | SBR_OPT_NO_GRAPH) & ~static_cast<uint32_t>(SBR_OPT_SYNC);
     bd.samples_per_lambda = 0.0;
     bd.eta = d->eta;
+    // a short-lived batch: 2^26-ray chunks, so that its records (4 GB at most)
+    // are quick to allocate and free (the 2^29 default's 34 GB took ~1 s)
+    sbr_tune tune = default_tune();
+    tune.chunk_log2 = 26;
+    bd.tune = &tune;
     sbr_batch *b = nullptr;
     int rc = sbr_batch_create(ctx, bvh, &bd, &b);
     if (rc) return rc;
