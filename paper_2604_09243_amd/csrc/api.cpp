@@ -947,7 +947,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         (rc = ws->get(W_TILEBASE, 8 * tile_words, &dtile)) || (rc = ws->get(W_BASIS, sizeof(PoAngle) * na, &dang)) ||
         (rc = ws->get(W_KF, 8 * nf, &dkf)) ||
         (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(max_chunk_units) * nf, &dpart)) ||
-        (use_mask && (rc = ws->get(W_MASK, static_cast<size_t>(std::max<int64_t>(max_mask_bytes, 4)), &dmask))))
+        (use_mask && (rc = ws->get(W_MASK, static_cast<size_t>(std::max<int64_t>((max_mask_bytes + 3) & ~int64_t(3), 4)), &dmask))))
         return rc;
     if (sched == kScheduleWavefront &&
         ((rc = get_queue(ws, W_QA, max_chunk_rays, qa)) || (rc = get_queue(ws, W_QB, max_chunk_rays, qb))))

@@ -238,7 +238,7 @@ int plan_batch(sbr_batch *b)
         (rc = b->dev.alloc(&b->d_spill, spill_words(bv, b->blocks))))
         return rc;
     b->d_mask = nullptr;
-    if (!(b->flags & SBR_OPT_NO_MASK) && (rc = b->dev.alloc(&b->d_mask, static_cast<size_t>(max_mask))))
+    if (!(b->flags & SBR_OPT_NO_MASK) && (rc = b->dev.alloc(&b->d_mask, static_cast<size_t>((max_mask + 3) & ~int64_t(3)))))
         return rc;
     b->rec = Records{recs, reinterpret_cast<uint8_t *>(held)};
     char *cb = reinterpret_cast<char *>(b->d_ctr);

@@ -624,16 +624,49 @@ __device__ __forceinline__ int find_angle(const Params &p, int64_t tile, int lo,
     return lo;
 }
 
-// Angles of the first and the last tile of a claimed batch [u, e), found by
-// lanes 0 and 1 together; every later lookup in the batch searches only
-// between them (usually a single angle).
+typedef const __attribute__((address_space(4))) int64_t *ScalarI64;
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    return static_cast<int64_t>(static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(
+                                    static_cast<int>(v >> 32))))
+                                << 32) |
+           static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+}
+
+// The angle of a wave-uniform tile through the scalar unit: a galloping
+// search of tile_base up from angle `hint` when the tile lies at or past
+// it, else a search below it.
+__device__ __forceinline__ int find_angle_scalar(const Params &p, int64_t tile, int hint)
+{
+    const ScalarI64 tb = (ScalarI64)p.tile_base;
+    const int n = p.n_angles;
+    int lo = 0, hi = hint;
+    if (tb[hint] <= tile) {  // tb[lo] <= tile < tb[hi], tb[n] above every tile
+        lo = hint;
+        hi = hint + 1;
+        for (int step = 1; hi < n && tb[hi] <= tile; step *= 2) {
+            lo = hi;
+            hi = min(lo + step, n);
+        }
+    }
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tb[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Angles of the first and the last tile of a claimed batch [u, e); the
+// search starts from the previous batch's last angle (claims from one range
+// advance).  Every later lookup in the batch searches only between them
+// (usually a single angle).
 __device__ __forceinline__ void batch_angles(const Params &p, int64_t u, int64_t e, int &a_lo, int &a_hi)
 {
-    const int lane = threadIdx.x & 63;
-    int a = 0;
-    if (lane < 2) a = find_angle(p, lane == 0 ? u : e - 1, 0, p.n_angles);
-    a_lo = __shfl(a, 0);
-    a_hi = __shfl(a, 1);
+    const int hint = __builtin_amdgcn_readfirstlane(a_hi);
+    a_lo = find_angle_scalar(p, uniform64(u), hint);
+    a_hi = find_angle_scalar(p, uniform64(e - 1), a_lo);
 }
 
 // Position q of the angle grid (tile = q / 64, position in the tile's
@@ -649,10 +682,10 @@ __device__ __forceinline__ int grid_ray(const Params &p, int64_t q, Ray &r, int 
     const int k = static_cast<int>(q & 63);
     const int lo = find_angle(p, tile, a_lo, a_hi + 1);
     const AnglePlan &pl = p.plans[lo];
-    const int64_t t = tile - pl.tile_base;
+    const uint32_t t = static_cast<uint32_t>(tile - pl.tile_base);  // < tu tv < 2^32 (an angle holds < 2^31 rays)
     const int tw = 1 << p.tile_shift;
-    const int i = static_cast<int>(t % pl.tu) * tw + (k & (tw - 1));
-    const int j = static_cast<int>(t / pl.tu) * (kTileRays >> p.tile_shift) + (k >> p.tile_shift);
+    const int i = static_cast<int>(t % static_cast<uint32_t>(pl.tu)) * tw + (k & (tw - 1));
+    const int j = static_cast<int>(t / static_cast<uint32_t>(pl.tu)) * (kTileRays >> p.tile_shift) + (k >> p.tile_shift);
     if (i >= pl.nu || j >= pl.nv) return kGridNone;
     if (p.mask && p.mask[pl.mask_base + static_cast<int64_t>(j >> kMaskShift) * pl.mcu + (i >> kMaskShift)] == 0)
         return kGridMasked;  // no record (its byte stays 0)
@@ -678,6 +711,24 @@ __device__ __forceinline__ int grid_ray(const Params &p, int64_t q, Ray &r, int 
     r.comp = 0.0;
     r.kdo = kdot0(p, plan_k(pl), r);
     return kGridRay;
+}
+
+// A whole tile whose mask cells are all empty: its in-grid positions (every
+// one a miss without traversal, as grid_ray would find ray by ray), else -1.
+__device__ __forceinline__ int masked_tile(const Params &p, int64_t tile, int a_lo, int a_hi)
+{
+    const int lo = find_angle(p, tile, a_lo, a_hi + 1);
+    const AnglePlan &pl = p.plans[lo];
+    const uint32_t t = static_cast<uint32_t>(tile - pl.tile_base);
+    const int tw = 1 << p.tile_shift, th = kTileRays >> p.tile_shift;
+    const int i0 = static_cast<int>(t % static_cast<uint32_t>(pl.tu)) * tw;
+    const int j0 = static_cast<int>(t / static_cast<uint32_t>(pl.tu)) * th;
+    const int i1 = min(i0 + tw, pl.nu), j1 = min(j0 + th, pl.nv);  // i0 < nu, j0 < nv for every tile of the angle
+    const uint8_t *m = p.mask + pl.mask_base;
+    for (int cj = j0 >> kMaskShift; cj <= (j1 - 1) >> kMaskShift; ++cj)
+        for (int ci = i0 >> kMaskShift; ci <= (i1 - 1) >> kMaskShift; ++ci)
+            if (m[static_cast<int64_t>(cj) * pl.mcu + ci]) return -1;
+    return (i1 - i0) * (j1 - j0);
 }
 
 // Ray e of the caller's arrays; false if e >= n_rays.
@@ -950,6 +1001,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
     const int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
     int64_t pos = 0, end = 0;  // wave-uniform: unused positions [pos, end) of the claimed batch
     int a_lo = 0, a_hi = 0;    // wave-uniform: angles spanned by the claimed batch
+    int64_t ub = 0;            // wave-uniform: first tile of the claimed batch
+    int dead = -1;             // lane k: masked_tile of tile ub + k of the batch (-1: traced)
     bool src_done = false;
     bool has = false;
     Ray r;
@@ -975,7 +1028,27 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
                 }
                 pos = u * kTileRays;
                 end = e * kTileRays;
-                if (SRC == 0) batch_angles(p, u, e, a_lo, a_hi);
+                if (SRC == 0) {
+                    batch_angles(p, u, e, a_lo, a_hi);
+                    // the batch's tiles (at most 64) checked against the mask
+                    // at once, one per lane
+                    ub = u;
+                    if (p.mask) dead = lane < e - u ? masked_tile(p, u + lane, a_lo, a_hi) : -1;
+                }
+            }
+            if (SRC == 0 && p.mask && idle == __ballot(1) && (pos & (kTileRays - 1)) == 0) {
+                // a whole idle wave at a tile start: a tile whose mask cells
+                // are all empty is passed over in one wave-uniform step
+                const int k = __builtin_amdgcn_readfirstlane(static_cast<int>((pos >> 6) - ub));  // in [0, e - u)
+                const int n_in = __builtin_amdgcn_readlane(dead, k);
+                if (n_in >= 0) {
+                    if (lane == 0) {
+                        atomicAdd(&bs.queries, static_cast<unsigned>(n_in));
+                        atomicAdd(&bs.masked, static_cast<unsigned>(n_in));
+                    }
+                    pos = min(pos + kTileRays, end);
+                    continue;
+                }
             }
             const int64_t q = pos + static_cast<int64_t>(__popcll(idle & lt));
             if (!has && q < end) {
