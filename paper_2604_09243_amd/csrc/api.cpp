@@ -171,6 +171,8 @@ enum Slot {
     W_MASK = 24,
     W_TUNE = 25,
     W_HELD = 26,  // record-slot bytes
+    W_LIVE = 27,     // live tiles of a chunk
+    W_LIVEBLK = 28,  // their per-block offsets and count
 };
 
 static int get_queue(Workspace *ws, int first, size_t cap, RayQueue &q)
@@ -896,7 +898,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     // chunks of consecutive angles holding at most chunk_cap rays (or one angle)
     std::vector<int64_t> cstart;
     std::vector<int64_t> chunk_units, chunk_mask_bytes, chunk_mask_units;
-    int64_t max_chunk_rays = 0, max_chunk_units = 0, max_mask_bytes = 0;
+    int64_t max_chunk_rays = 0, max_chunk_units = 0, max_mask_bytes = 0, max_chunk_tiles = 0;
     {
         int64_t a = 0;
         while (a < na) {
@@ -923,6 +925,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
             max_mask_bytes = std::max(max_mask_bytes, mb);
             max_chunk_rays = std::max(max_chunk_rays, rays);
             max_chunk_units = std::max(max_chunk_units, units);
+            max_chunk_tiles = std::max(max_chunk_tiles, tiles);
             a = b;
         }
         cstart.push_back(na);
@@ -948,6 +951,12 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         (rc = ws->get(W_KF, 8 * nf, &dkf)) ||
         (rc = ws->get(W_PARTIAL, 64 * static_cast<size_t>(max_chunk_units) * nf, &dpart)) ||
         (use_mask && (rc = ws->get(W_MASK, static_cast<size_t>(std::max<int64_t>((max_mask_bytes + 3) & ~int64_t(3), 4)), &dmask))))
+        return rc;
+    // the streaming schedule claims the live tiles of the mask
+    void *dlive = nullptr, *dliveblk = nullptr;
+    const bool use_live = use_mask && sched == kScheduleStream;
+    if (use_live && ((rc = ws->get(W_LIVE, 4 * static_cast<size_t>(max_chunk_tiles), &dlive)) ||
+                     (rc = ws->get(W_LIVEBLK, 4 * static_cast<size_t>(live_blocks(max_chunk_tiles) + 1), &dliveblk))))
         return rc;
     if (sched == kScheduleWavefront &&
         ((rc = get_queue(ws, W_QA, max_chunk_rays, qa)) || (rc = get_queue(ws, W_QB, max_chunk_rays, qb))))
@@ -1031,6 +1040,12 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
             if ((rc = launch_mask(s, bvh->nodes, cp, m, chunk_mask_units[c], static_cast<uint8_t *>(dmask),
                                   chunk_mask_bytes[c])))
                 return rc;
+            if (use_live) {
+                uint32_t *blk = static_cast<uint32_t *>(dliveblk);
+                if ((rc = launch_live(s, ta, static_cast<int32_t *>(dlive), blk))) return rc;
+                ta.live = static_cast<const int32_t *>(dlive);
+                ta.live_count = blk + live_blocks(n_tiles);
+            }
         }
         std::vector<hipEvent_t> cev;
         if (want_stats) cev.assign(ev.begin() + epc * c, ev.begin() + epc * (c + 1));

@@ -98,6 +98,8 @@ struct sbr_batch {
     CounterPtrs ctrs{};
     int32_t *d_spill = nullptr;
     uint8_t *d_mask = nullptr;  // NULL with SBR_OPT_NO_MASK
+    int32_t *d_live = nullptr;  // live tiles of a chunk (streaming schedule with the mask)
+    uint32_t *d_liveblk = nullptr;
     RayQueue qa{}, qb{};
     unsigned long long *h_stat = nullptr;  // pinned [kStatU64]
     // graph
@@ -180,7 +182,7 @@ int plan_batch(sbr_batch *b)
     b->tile_off.clear();
     b->c_mask_bytes.clear();
     b->c_mask_units.clear();
-    int64_t max_rays = 0, max_rows = 0, tile_words = 0, max_mask = 4;
+    int64_t max_rays = 0, max_rows = 0, tile_words = 0, max_mask = 4, max_tiles = 1;
     for (int64_t a = 0; a < ni;) {
         b->cstart.push_back(a);
         b->tile_off.push_back(tile_words);
@@ -213,6 +215,7 @@ int plan_batch(sbr_batch *b)
         tile_words += (e - a) + 1;
         max_rays = std::max(max_rays, rays);
         max_rows = std::max(max_rows, rows);
+        max_tiles = std::max(max_tiles, tiles);
         a = e;
     }
     b->cstart.push_back(ni);
@@ -238,8 +241,16 @@ int plan_batch(sbr_batch *b)
         (rc = b->dev.alloc(&b->d_spill, spill_words(bv, b->blocks))))
         return rc;
     b->d_mask = nullptr;
-    if (!(b->flags & SBR_OPT_NO_MASK) && (rc = b->dev.alloc(&b->d_mask, static_cast<size_t>((max_mask + 3) & ~int64_t(3)))))
-        return rc;
+    b->d_live = nullptr;
+    b->d_liveblk = nullptr;
+    if (!(b->flags & SBR_OPT_NO_MASK)) {
+        if ((rc = b->dev.alloc(&b->d_mask, static_cast<size_t>((max_mask + 3) & ~int64_t(3))))) return rc;
+        // the streaming schedule claims the live tiles of the mask
+        if (b->tune.schedule == kScheduleStream &&
+            ((rc = b->dev.alloc(&b->d_live, static_cast<size_t>(max_tiles))) ||
+             (rc = b->dev.alloc(&b->d_liveblk, static_cast<size_t>(live_blocks(max_tiles) + 1)))))
+            return rc;
+    }
     b->rec = Records{recs, reinterpret_cast<uint8_t *>(held)};
     char *cb = reinterpret_cast<char *>(b->d_ctr);
     b->ctrs.stat = reinterpret_cast<unsigned long long *>(cb);
@@ -300,6 +311,11 @@ int enqueue(sbr_batch *b, hipStream_t s, double *A, double *sigma, std::vector<h
             if ((rc = launch_mask(s, b->bvh->nodes, ta.plans, ta.n_angles, b->c_mask_units[c], b->d_mask,
                                   b->c_mask_bytes[c])))
                 return rc;
+            if (b->d_live) {
+                if ((rc = launch_live(s, ta, b->d_live, b->d_liveblk))) return rc;
+                ta.live = b->d_live;
+                ta.live_count = b->d_liveblk + live_blocks(ta.n_tiles);
+            }
         }
         if ((rc = run_trace(s, ta, b->qa, b->qb, nullptr))) return rc;
         if (ev) SBR_HIP(hipEventRecord((*ev)[3 * c + 1], s));

@@ -318,6 +318,8 @@ struct TraceArgs {
     int n_angles;
     int64_t n_tiles;
     const uint8_t *mask;      // device primary-ray mask of the plans, or NULL (every ray traced)
+    const int32_t *live;      // streaming schedule: live tiles of the mask (launch_live), or NULL
+    const uint32_t *live_count;
     // user source / sink (sbr_trace)
     const sbr_rays *rays;
     int64_t n_rays;
@@ -331,6 +333,12 @@ struct TraceArgs {
 };
 // bounce = 1 for the stream schedule (one launch does every bounce)
 int launch_trace(hipStream_t s, const TraceArgs &a, int bounce);
+// The live tiles of a masked launch (at least one non-empty mask cell), in
+// tile order, into live[0, *count); the in-grid positions of the other tiles
+// are added to the masked and query statistics.  blk holds
+// live_blocks(n_tiles) + 1 words, the last of them the count.
+int64_t live_blocks(int64_t n_tiles);
+int launch_live(hipStream_t s, const TraceArgs &a, int32_t *live, uint32_t *blk);
 // Static scratch of the no-alloc trace (one per device, kNoallocScratchBytes):
 // noalloc_scratch_setup looks up this device's address (the device must be
 // current; done once by sbr_create); noalloc_counters lays the counter block

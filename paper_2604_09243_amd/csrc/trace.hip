@@ -101,6 +101,8 @@ struct Params {
     const AnglePlan *plans;
     const int64_t *tile_base;
     const uint8_t *mask;  // primary-ray mask of the plans (NULL: trace every ray)
+    const int32_t *live;  // streaming schedule with a mask: the live tiles in order (NULL: every tile)
+    const uint32_t *live_count;
     int n_angles;
     // caller source / sink
     const float *uo, *ud, *uh, *uv;
@@ -658,16 +660,18 @@ __device__ __forceinline__ int find_angle_scalar(const Params &p, int64_t tile, 
     return lo;
 }
 
-// Angles of the first and the last tile of a claimed batch [u, e); the
-// search starts from the previous batch's last angle (claims from one range
+// Angles of the first and the last tile of a claimed batch; the search
+// starts from the previous batch's last angle (claims from one range
 // advance).  Every later lookup in the batch searches only between them
 // (usually a single angle).
-__device__ __forceinline__ void batch_angles(const Params &p, int64_t u, int64_t e, int &a_lo, int &a_hi)
+__device__ __forceinline__ void batch_angles(const Params &p, int64_t first, int64_t last, int &a_lo, int &a_hi)
 {
     const int hint = __builtin_amdgcn_readfirstlane(a_hi);
-    a_lo = find_angle_scalar(p, uniform64(u), hint);
-    a_hi = find_angle_scalar(p, uniform64(e - 1), a_lo);
+    a_lo = find_angle_scalar(p, uniform64(first), hint);
+    a_hi = find_angle_scalar(p, uniform64(last), a_lo);
 }
+
+typedef const __attribute__((address_space(4))) int32_t *ScalarI32;
 
 // Position q of the angle grid (tile = q / 64, position in the tile's
 // tile_w-wide patch = q % 64) -> kGridRay with a fresh ray in r; kGridNone
@@ -998,11 +1002,12 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
     const int lane = threadIdx.x & 63;
     const int home = blockIdx.x % kClaimRanges;  // this block's claim range (on XCD blockIdx % 8)
     const uint64_t lt = lanemask_lt();
-    const int64_t n_units = SRC == 0 ? p.n_tiles : (p.n_rays + kTileRays - 1) / kTileRays;
+    // units: tiles of the angle grid (positions of the live-tile list when
+    // the mask made one), or 64-ray groups of caller rays
+    const int64_t n_units = SRC == 0 ? (p.live ? static_cast<int64_t>(*p.live_count) : p.n_tiles)
+                                     : (p.n_rays + kTileRays - 1) / kTileRays;
     int64_t pos = 0, end = 0;  // wave-uniform: unused positions [pos, end) of the claimed batch
     int a_lo = 0, a_hi = 0;    // wave-uniform: angles spanned by the claimed batch
-    int64_t ub = 0;            // wave-uniform: first tile of the claimed batch
-    int dead = -1;             // lane k: masked_tile of tile ub + k of the batch (-1: traced)
     bool src_done = false;
     bool has = false;
     Ray r;
@@ -1029,31 +1034,20 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
                 pos = u * kTileRays;
                 end = e * kTileRays;
                 if (SRC == 0) {
-                    batch_angles(p, u, e, a_lo, a_hi);
-                    // the batch's tiles (at most 64) checked against the mask
-                    // at once, one per lane
-                    ub = u;
-                    if (p.mask) dead = lane < e - u ? masked_tile(p, u + lane, a_lo, a_hi) : -1;
-                }
-            }
-            if (SRC == 0 && p.mask && idle == __ballot(1) && (pos & (kTileRays - 1)) == 0) {
-                // a whole idle wave at a tile start: a tile whose mask cells
-                // are all empty is passed over in one wave-uniform step
-                const int k = __builtin_amdgcn_readfirstlane(static_cast<int>((pos >> 6) - ub));  // in [0, e - u)
-                const int n_in = __builtin_amdgcn_readlane(dead, k);
-                if (n_in >= 0) {
-                    if (lane == 0) {
-                        atomicAdd(&bs.queries, static_cast<unsigned>(n_in));
-                        atomicAdd(&bs.masked, static_cast<unsigned>(n_in));
+                    int64_t first = u, last = e - 1;
+                    if (p.live) {
+                        first = ((ScalarI32)p.live)[uniform64(first)];
+                        last = ((ScalarI32)p.live)[uniform64(last)];
                     }
-                    pos = min(pos + kTileRays, end);
-                    continue;
+                    batch_angles(p, first, last, a_lo, a_hi);
                 }
             }
             const int64_t q = pos + static_cast<int64_t>(__popcll(idle & lt));
             if (!has && q < end) {
                 if (SRC == 0) {
-                    const int g = grid_ray(p, q, r, a_lo, a_hi);
+                    // position q of the list: ray q % 64 of live tile q / 64
+                    const int64_t qg = p.live ? (static_cast<int64_t>(p.live[q >> 6]) << 6) | (q & 63) : q;
+                    const int g = grid_ray(p, qg, r, a_lo, a_hi);
                     has = g == kGridRay;
                     if (g == kGridMasked) {
                         atomicAdd(&bs.queries, 1u);
@@ -1138,7 +1132,7 @@ __global__ __launch_bounds__(kBlock) SBR_TRACE_OCCUPANCY void k_wave(Params p)
             if (u < 0) break;
             tile = u;
             tend = e;
-            if (SRC == 0) batch_angles(p, u, e, a_lo, a_hi);
+            if (SRC == 0) batch_angles(p, u, e - 1, a_lo, a_hi);
         }
         const int64_t q = tile * kTileRays + lane;
         ++tile;
@@ -1297,6 +1291,109 @@ __global__ __launch_bounds__(kMaskBlock) void k_mask(const BNode *__restrict__ n
     }
 }
 
+// ---------------------------------------------------------------------------
+// Live tiles of a masked streaming launch: the tiles with a non-empty mask
+// cell, in tile order.  The trace claims positions of this list, so a tile
+// whose every ray the mask resolves is never claimed; its in-grid positions
+// are counted here as masked queries, the count grid_ray makes ray by ray.
+// Three launches: per-block counts, one block scanning them, the writes.
+// ---------------------------------------------------------------------------
+constexpr int kLiveBlock = 256;
+constexpr int kLivePer = 4;  // consecutive tiles of a thread
+constexpr int kLiveTiles = kLiveBlock * kLivePer;
+constexpr int kLiveScanThreads = 1024;
+
+// live flags of the thread's kLivePer tiles (bit j: tile first + j), the
+// masked positions of the others in *masked
+__device__ __forceinline__ uint32_t live_flags(const Params &p, int64_t first, uint32_t *masked)
+{
+    uint32_t f = 0, m = 0;
+    for (int j = 0; j < kLivePer; ++j) {
+        const int64_t t = first + j;
+        if (t >= p.n_tiles) break;
+        const int d = masked_tile(p, t, 0, p.n_angles - 1);
+        if (d < 0) f |= 1u << j;
+        else m += static_cast<uint32_t>(d);
+    }
+    *masked = m;
+    return f;
+}
+
+// exclusive prefix of v over the block's threads (kLiveBlock), and the total
+__device__ __forceinline__ uint32_t block_prefix(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kLiveBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;  // inclusive scan within the wave
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int k = 0; k < kLiveBlock / 64; ++k) {
+        if (k < w) before += wsum[k];
+        all += wsum[k];
+    }
+    *total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kLiveBlock) void k_live_count(Params p, uint32_t *blk)
+{
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kLiveTiles + static_cast<int64_t>(threadIdx.x) * kLivePer;
+    uint32_t masked;
+    const uint32_t f = live_flags(p, first, &masked);
+    uint32_t n_live, n_masked;
+    (void)block_prefix(static_cast<uint32_t>(__popc(f)), &n_live);
+    __syncthreads();
+    (void)block_prefix(masked, &n_masked);
+    if (threadIdx.x == 0) {
+        blk[blockIdx.x] = n_live;
+        if (n_masked) {
+            atomicAdd(p.stat + 0, static_cast<unsigned long long>(n_masked));
+            atomicAdd(p.stat + kStatMasked, static_cast<unsigned long long>(n_masked));
+        }
+    }
+}
+
+// blk[0, nb) counts -> exclusive offsets, blk[nb] = the total
+__global__ __launch_bounds__(kLiveScanThreads) void k_live_scan(uint32_t *blk, int64_t nb)
+{
+    __shared__ uint32_t part[kLiveScanThreads];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + kLiveScanThreads - 1) / kLiveScanThreads;
+    const int64_t lo = min(nb, per * t), hi = min(nb, lo + per);
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += blk[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < kLiveScanThreads; d <<= 1) {  // inclusive scan of part
+        const uint32_t y = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint32_t c = blk[i];
+        blk[i] = run;
+        run += c;
+    }
+    if (t == kLiveScanThreads - 1) blk[nb] = part[t];
+}
+
+__global__ __launch_bounds__(kLiveBlock) void k_live_write(Params p, const uint32_t *blk, int32_t *live)
+{
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kLiveTiles + static_cast<int64_t>(threadIdx.x) * kLivePer;
+    uint32_t masked, total;
+    uint32_t f = live_flags(p, first, &masked);
+    uint32_t o = blk[blockIdx.x] + block_prefix(static_cast<uint32_t>(__popc(f)), &total);
+    for (int j = 0; f; ++j, f >>= 1)
+        if (f & 1u) live[o++] = static_cast<int32_t>(first + j);
+}
+
 }  // namespace
 
 int trace_block_threads() { return kBlock; }
@@ -1353,6 +1450,8 @@ static Params make_params(const TraceArgs &a, int launch)
     p.plans = a.plans;
     p.tile_base = a.tile_base;
     p.mask = a.mask;
+    p.live = a.schedule == kScheduleStream ? a.live : nullptr;
+    p.live_count = a.live_count;
     p.n_angles = a.n_angles;
     p.uo = a.rays ? a.rays->o : nullptr;
     p.ud = a.rays ? a.rays->d : nullptr;
@@ -1422,6 +1521,28 @@ int launch_mask(hipStream_t s, const BNode *nodes, const AnglePlan *plans, int n
     const int64_t blocks = (n_units + per_block - 1) / per_block;
     if (blocks > 0)
         k_mask<<<static_cast<unsigned>(blocks), kMaskBlock, 0, s>>>(nodes, plans, n_angles, n_units, per, mask);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int64_t live_blocks(int64_t n_tiles) { return (n_tiles + kLiveTiles - 1) / kLiveTiles; }
+
+int launch_live(hipStream_t s, const TraceArgs &a, int32_t *live, uint32_t *blk)
+{
+    if (!a.mask || a.n_angles < 1 || a.n_tiles < 1) return fail(SBR_ERR_INVALID_ARG, "launch_live: bad launch");
+    if (a.n_tiles > INT32_MAX) return fail(SBR_ERR_OVERFLOW, "launch_live: too many tiles in one launch");
+    Params p{};
+    p.plans = a.plans;
+    p.tile_base = a.tile_base;
+    p.mask = a.mask;
+    p.n_angles = a.n_angles;
+    p.n_tiles = a.n_tiles;
+    p.tile_shift = a.tile_shift;
+    p.stat = a.ctrs.stat;
+    const int64_t nb = live_blocks(a.n_tiles);
+    k_live_count<<<static_cast<unsigned>(nb), kLiveBlock, 0, s>>>(p, blk);
+    k_live_scan<<<1, kLiveScanThreads, 0, s>>>(blk, nb);
+    k_live_write<<<static_cast<unsigned>(nb), kLiveBlock, 0, s>>>(p, blk, live);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

@@ -75,10 +75,35 @@ def test_wavefront_schedule_identical_with_mask(torch, ctx):
     m, u = both(lambda fl: ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
                                          samples_per_lambda=w.samples_per_lambda, flags=fl | sbr.OPT_WAVEFRONT))
     check_same(m, u, min_frac=0.05)
-    # and both equal the streaming schedule with the mask
-    A, _, _ = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
-                            samples_per_lambda=w.samples_per_lambda)
+    # and both equal the streaming schedule with the mask, which claims only
+    # the live tiles and counts the others' rays as masked: the same count as
+    # the wavefront schedule's ray-by-ray one
+    A, _, st = ctx.rcs_sweep(bvh, w.theta_deg, w.phi_deg, w.freqs_hz, w.max_bounces,
+                             samples_per_lambda=w.samples_per_lambda)
     assert np.array_equal(A.cpu().numpy().view(np.float64), m[0].view(np.float64))
+    assert st["masked"] == m[2]["masked"] and st["queries"] == m[2]["queries"]
+    bvh.free()
+
+
+@pytest.mark.parametrize("tile_w", [4, 8, 16, 64])
+def test_live_tiles_any_tile_width_and_chunking(torch, ctx, tile_w):
+    """The live-tile list at every tile shape (a tile spans 1 x 2, 1, 2 or
+    8 x 1 mask cells) and at chunks of one or a few angles: the results equal
+    the unmasked sweep bit for bit and the masked count equals the
+    ray-by-ray count of the wavefront schedule."""
+    from paper_2604_09243_amd import sbr
+    w = si.aircraft_case()
+    idx = np.arange(0, w.n_angles, 90)
+    say("case aircraft 4 azimuths, tile_w", tile_w)
+    bvh = ctx.build_bvh(w.V, w.T, builder=1)
+    run = lambda fl, **kw: ctx.rcs_sweep(bvh, w.theta_deg[idx], w.phi_deg[idx], w.freqs_hz, w.max_bounces,
+                                         samples_per_lambda=w.samples_per_lambda, flags=fl, **kw)
+    _, _, wf = run(sbr.OPT_WAVEFRONT)
+    for chunk in (16, 24):
+        tune = sbr.make_tune(tile_w=tile_w, chunk_log2=chunk)
+        m, u = both(lambda fl: run(fl, tune=tune))
+        check_same(m, u, min_frac=0.2)
+        assert m[2]["masked"] == wf["masked"] and m[2]["queries"] == wf["queries"]
     bvh.free()
 
 
@@ -135,5 +160,7 @@ def test_batch_identical_with_mask(torch, ctx):
         assert np.array_equal(r[0].view(np.float64), res[0][0].view(np.float64))
         assert r[2]["queries"] == res[0][2]["queries"]
     assert all(r[2]["masked"] > 0 for r in res[:3]) and all(r[2]["masked"] == 0 for r in res[3:])
+    # live-tile lists (graph and eager streaming) and the ray-by-ray wavefront count agree
+    assert res[0][2]["masked"] == res[1][2]["masked"] == res[2][2]["masked"]
     say("masked fraction", res[0][2]["masked"] / res[0][2]["rays"])
     scn.free()
