@@ -329,7 +329,8 @@ typedef struct {
     uint32_t struct_size;
     int32_t schedule;      /* 0 = streaming launch, 1 = one launch per bounce (SBR_OPT_WAVEFRONT) */
     int32_t tile_w;        /* aperture tile of one 64-lane wave: tile_w x (64 / tile_w) rays; 4, 8, 16, 32, 64 */
-    int32_t claim_tiles;   /* tiles a wave claims per atomic, 1..64 */
+    int32_t claim_tiles;   /* tiles a wave claims per atomic, 1..64; 0 = automatic: 1 when the tree
+                              (nodes and triangles) exceeds 4 MiB, one XCD's L2, else 2 */
     int32_t refill_min;    /* idle lanes that trigger a refill (streaming launch), 1..64 */
     int32_t blocks_per_cu; /* persistent blocks of 256 threads per compute unit; 0 = occupancy limit */
     int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..30; 0 = 29.  Records of a

@@ -274,12 +274,19 @@ sbr_tune default_tune()
     t.struct_size = sizeof(sbr_tune);
     t.schedule = kScheduleStream;
     t.tile_w = 8;
-    t.claim_tiles = 2;
+    t.claim_tiles = 0;  // automatic (auto_claim_tiles)
     t.refill_min = 64;
     t.blocks_per_cu = 0;
     t.chunk_log2 = kDefaultChunkLog2;
     t.reserved = 0;
     return t;
+}
+
+int auto_claim_tiles(const sbr_bvh *bvh)
+{
+    const int64_t bytes = bvh->n_nodes * static_cast<int64_t>(sizeof(BNode)) +
+                          bvh->n_tris * static_cast<int64_t>(sizeof(BTri));
+    return bytes > kL2BytesPerXcd ? 1 : 2;
 }
 
 int normalize_tune(sbr_tune &t)
@@ -625,7 +632,8 @@ static int trace_impl(const char *fn, sbr_ctx *ctx, const sbr_bvh *bvh, const sb
     const int sched = schedule_of(flags);
     if ((flags & SBR_OPT_FP64_TRAVERSE) && sched != kScheduleStream)
         return fail(SBR_ERR_UNSUPPORTED, f + ": SBR_OPT_FP64_TRAVERSE runs on the streaming schedule only");
-    const sbr_tune tune = default_tune();
+    sbr_tune tune = default_tune();
+    tune.claim_tiles = auto_claim_tiles(bvh);
     const int blocks = trace_persistent_blocks(ctx, tune.blocks_per_cu);
     if (noalloc) {
         if (sched != kScheduleStream)
@@ -855,6 +863,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
     if (sw->flags & SBR_OPT_WAVEFRONT) tune.schedule = kScheduleWavefront;
     int rc0 = normalize_tune(tune);
     if (rc0) return rc0;
+    if (tune.claim_tiles == 0) tune.claim_tiles = auto_claim_tiles(bvh);
     const int tw = tune.tile_w;
     const int64_t chunk_cap = int64_t(1) << tune.chunk_log2;
     if (bvh->n_live == 0) return fail(SBR_ERR_INVALID_ARG, "sbr_rcs_sweep: the mesh has no non-degenerate triangle");

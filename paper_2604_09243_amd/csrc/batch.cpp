@@ -296,7 +296,7 @@ int enqueue(sbr_batch *b, hipStream_t s, double *A, double *sigma, std::vector<h
         ta.flags = b->flags;
         ta.schedule = b->tune.schedule;
         ta.tile_shift = log2i(b->tune.tile_w);
-        ta.claim_tiles = b->tune.claim_tiles;
+        ta.claim_tiles = b->tune.claim_tiles ? b->tune.claim_tiles : auto_claim_tiles(b->bvh);
         ta.refill_min = b->tune.refill_min;
         ta.blocks = b->blocks;
         ta.plans = b->d_plans + a0;

@@ -374,6 +374,11 @@ bool trace_walks_wide(const sbr_bvh *bvh, uint32_t flags, int schedule);
 // api.cpp helpers shared with the batch entry points
 sbr_tune default_tune();
 int normalize_tune(sbr_tune &t);           // check_tune, then chunk_log2 0 -> default
+// claim_tiles 0 (automatic): one tile per claim when the tree outgrows an
+// XCD's L2 (waves on neighbouring tiles at once then share its node and
+// triangle lines), two otherwise (fewer claims of cheap tiles)
+constexpr int64_t kL2BytesPerXcd = int64_t(4) << 20;
+int auto_claim_tiles(const sbr_bvh *bvh);
 int log2i(int x);
 void fill_stats(sbr_stats *st, const unsigned long long *hstat, int bmax, int64_t rays, bool drop_trapped,
                 int64_t chunks);

@@ -1422,7 +1422,8 @@ int check_tune(const sbr_tune &t)
         return fail(SBR_ERR_INVALID_ARG, "sbr_tune: schedule must be 0 or 1");
     if (t.tile_w != 4 && t.tile_w != 8 && t.tile_w != 16 && t.tile_w != 32 && t.tile_w != 64)
         return fail(SBR_ERR_INVALID_ARG, "sbr_tune: tile_w must be 4, 8, 16, 32 or 64");
-    if (t.claim_tiles < 1 || t.claim_tiles > 64) return fail(SBR_ERR_INVALID_ARG, "sbr_tune: claim_tiles in [1, 64]");
+    if (t.claim_tiles < 0 || t.claim_tiles > 64)
+        return fail(SBR_ERR_INVALID_ARG, "sbr_tune: claim_tiles in [1, 64], or 0 (automatic)");
     if (t.refill_min < 1 || t.refill_min > 64) return fail(SBR_ERR_INVALID_ARG, "sbr_tune: refill_min in [1, 64]");
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32)
         return fail(SBR_ERR_INVALID_ARG, "sbr_tune: blocks_per_cu in [0, 32]");
