@@ -93,6 +93,10 @@ enum { SBR_MEM_HOST = 0, SBR_MEM_DEVICE = 1 };
                                          triangle tests in float64 (hits then differ from the
                                          float32 specification by rounding); streaming schedule
                                          of sbr_trace and sbr_rcs_sweep only */
+#define SBR_OPT_PACKET 1024           /* traversal study, sweeps and batches: the parallel primary
+                                         rays of a tile walk the tree together (one shared stack,
+                                         every node and triangle read once per wave) instead of each
+                                         on its own; results are identical either way */
 #define SBR_OPT_BVH4 512              /* traversal study: walk a four-wide copy of the tree
                                          (four child boxes per 128-byte node, collapsed from the
                                          binary tree on the host at the first such call and kept

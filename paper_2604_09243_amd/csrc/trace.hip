@@ -123,6 +123,7 @@ struct Params {
     int bounce;
     int user_sink;
     int tile_shift, claim_tiles, refill_min;  // launch parameters (sbr_tune)
+    int packet;  // primary tiles may walk the tree as packets (binary tree, depth <= kPacketStack)
 };
 
 struct Ray {
@@ -541,6 +542,96 @@ __device__ __forceinline__ BestT<R> traverse(const Params &p, const Ray &r, Stac
         }
     }
     return b;
+}
+
+// Closest hits of the active lanes by one shared walk of the tree (a
+// packet), for waves of parallel primary rays, which mostly want the same
+// nodes: each lane tests every visited node's child boxes with its own ray
+// (and its own best hit as the far limit), and the packet goes into a child
+// when any lane's test passes, nearer child first by the lanes' vote.  A lane
+// thus reaches every leaf its own traversal would, and may test extra
+// triangles, which cannot change the minimum of (t, id) under the hit rule:
+// the closest hit is the per-lane walk's.  Every node and triangle is read
+// through the scalar unit.  The shared stack lives in two registers (lane k
+// holds entry k, 128 entries; the launch checks the tree's depth), so the
+// walk runs with every lane of the wave enabled: lanes without a ray
+// (`act` false) take part in no vote and their results are not used.
+constexpr int kPacketStack = 128;
+
+__device__ __forceinline__ void packet_push(int &s0, int &s1, int &sp, int v, int lane)
+{
+    if (sp < 64) s0 = lane == sp ? v : s0;
+    else s1 = lane == sp - 64 ? v : s1;
+    ++sp;
+}
+
+__device__ __forceinline__ int packet_pop(int s0, int s1, int &sp)
+{
+    --sp;
+    return sp < 64 ? __builtin_amdgcn_readlane(s0, sp) : __builtin_amdgcn_readlane(s1, sp - 64);
+}
+
+template <typename R>
+__device__ __forceinline__ BestT<R> traverse_packet(const Params &p, const Ray &r, const SceneRef sc, bool act,
+                                                    int first)
+{
+    BestT<R> b;
+    b.t = INFINITY;
+    b.id = 0x7fffffff;
+    b.slot = -1;
+    SBR_COUNT(b.nodes = b.leaves = b.tris = b.wnode = b.wleaf = 0);
+    const float tiny = 1e-20f;
+    const R ddx = fabsf(r.dx) < tiny ? copysignf(tiny, r.dx) : r.dx;
+    const R ddy = fabsf(r.dy) < tiny ? copysignf(tiny, r.dy) : r.dy;
+    const R ddz = fabsf(r.dz) < tiny ? copysignf(tiny, r.dz) : r.dz;
+    const R ix = rcpR(ddx), iy = rcpR(ddy), iz = rcpR(ddz);
+    const R lx = R(r.ox) * ix, ly = R(r.oy) * iy, lz = R(r.oz) * iz;
+    const int lane = threadIdx.x & 63;
+    int s0 = 0, s1 = 0, sp = 0;
+    int cur = __builtin_amdgcn_readlane(sc.root, first);  // the scene of the first active lane: one per wave
+    for (;;) {
+        while (cur >= 0) {
+            SBR_COUNT(b.nodes += 1; if (wave_leader()) b.wnode += 1);
+            R t0, u0, t1, u1;
+            int cx, cy;
+            node_boxes(node_scalar(p.nodes, cur), ix, iy, iz, lx, ly, lz, lx, ly, lz, b.t, t0, u0, t1, u1, cx, cy);
+            const bool h0 = act && t0 <= u0, h1 = act && t1 <= u1;
+            const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+            if (m0 && m1) {
+                const int both = __popcll(m0 & m1), c1first = __popcll(__ballot(h0 && h1 && t1 < t0));
+                const bool swap = 2 * c1first > both;
+                packet_push(s0, s1, sp, swap ? cx : cy, lane);
+                cur = swap ? cy : cx;
+            } else if (m0) {
+                cur = cx;
+            } else if (m1) {
+                cur = cy;
+            } else if (sp > 0) {
+                cur = packet_pop(s0, s1, sp);
+            } else {
+                cur = kEmpty;
+            }
+        }
+        if (cur == kEmpty) break;
+        SBR_COUNT(if (wave_leader()) b.wleaf += 1);
+        test_leaf_from(ScalarTriLoader{p.tris}, (~cur) >> 3, ((~cur) & 7) + 1, r, b, sc.pbox);
+        if (sp > 0) cur = packet_pop(s0, s1, sp);
+        else break;
+    }
+    return b;
+}
+
+// Whether the lanes holding a ray (`act`; the first of them `first`) hold
+// parallel primary rays of one scene: those walk the tree as a packet.
+// Called with every lane of the wave enabled.
+__device__ __forceinline__ bool primary_wave(const Ray &r, const SceneRef &sc, bool act, int first)
+{
+    const int dx = __builtin_amdgcn_readlane(__float_as_int(r.dx), first);
+    const int dy = __builtin_amdgcn_readlane(__float_as_int(r.dy), first);
+    const int dz = __builtin_amdgcn_readlane(__float_as_int(r.dz), first);
+    const int root = __builtin_amdgcn_readlane(sc.root, first);
+    return __ballot(act && ((r.meta & 127) != 0 || __float_as_int(r.dx) != dx || __float_as_int(r.dy) != dy ||
+                            __float_as_int(r.dz) != dz || sc.root != root)) == 0;
 }
 
 // Closest hit of ray r under the hit rule: one traversal that applies the
@@ -1066,7 +1157,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
         b.slot = -1;
         SceneRef sc{0, 0.f, 0.f};
         if (has) sc = scene_of<kUser>(p, r);
-        if (has) b = closest<SPILL, SRC == 1, R, W>(p, r, st, sc);
+        // (every lane of the wave is enabled here)
+        const int first = __ffsll(static_cast<unsigned long long>(__ballot(has))) - 1;
+        if (SRC == 0 && W == 2 && sizeof(R) == 4 && p.packet && primary_wave(r, sc, has, first)) {
+            const BestT<R> bp = traverse_packet<R>(p, r, sc, has, first);
+            if (has) b = bp;
+        } else if (has) {
+            b = closest<SPILL, SRC == 1, R, W>(p, r, st, sc);
+        }
         if (has) atomicAdd(&bs.queries, 1u);
         SBR_COUNT(if (has) count_query(bs, b); if (threadIdx.x % 64 == 0) atomicAdd(&bs.diag[5], 1ull));
         if (has) {
@@ -1477,6 +1575,8 @@ static Params make_params(const TraceArgs &a, int launch)
     p.tile_shift = a.tile_shift;
     p.claim_tiles = a.claim_tiles;
     p.refill_min = a.refill_min;
+    p.packet = (a.flags & SBR_OPT_PACKET) && !(a.flags & SBR_OPT_FP64_TRAVERSE) && p.nodes4 == nullptr &&
+               stack_need(a.bvh, false) <= kPacketStack;
     return p;
 }
 

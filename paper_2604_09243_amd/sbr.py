@@ -27,6 +27,7 @@ OPT_NO_MASK = 64
 OPT_FP32_PATH = 128
 OPT_FP64_TRAVERSE = 256
 OPT_BVH4 = 512
+OPT_PACKET = 1024
 MAX_BOUNCES = 127
 
 _vp = C.c_void_p
