@@ -101,18 +101,18 @@ constexpr int kTileM = 64, kTileN = 128, kGemmRing = 4;
 // 32 x 64 piece per wave; NK > 0: exactly NK k steps per block (unrolled),
 // NK = 0: any multiple of 16.
 template <int EPI, int NK>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int bz)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m0 = blockIdx.x * kTileM + (wv & 1) * 32;
-    const int n0 = blockIdx.y * kTileN + (wv >> 1) * 64;
+    const int m0 = bx * kTileM + (wv & 1) * 32;
+    const int n0 = by * kTileN + (wv >> 1) * 64;
     const int r = lane & 31, kh = (lane >> 5) * 8;
     // split-K (kEpiF32): block z sums k in [z Kc, (z + 1) Kc) into slice z of fout
-    const int kc = g.K / g.ksplit, kb = blockIdx.z * kc;
+    const int kc = g.K / g.ksplit, kb = bz * kc;
     const uint16_t *pa = g.A + static_cast<int64_t>(m0 + r) * g.lda + kh + kb;
     const uint16_t *pb0 = g.B + static_cast<int64_t>(n0 + r) * g.ldb + kh + kb;
     const uint16_t *pb1 = g.B + static_cast<int64_t>(n0 + 32 + r) * g.ldb + kh + kb;
-    float *fout = g.fout ? g.fout + blockIdx.z * g.split_stride : nullptr;
+    float *fout = g.fout ? g.fout + bz * g.split_stride : nullptr;
     f32x16 acc0 = {}, acc1 = {};
     if constexpr (NK > 0) {
         // NK k steps, unrolled, with the fragments of kGemmRing steps in flight
@@ -180,6 +180,12 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
     }
 }
 
+template <int EPI, int NK>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
+{
+    gemm_tile<EPI, NK>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ---------------------------------------------------------------- features
 // Row m < M: normalised input xn = 2 (x - lo) / (hi - lo) - 1 and features
 // sin / cos(2 pi t), t = B xn in float64, reduced to t - rint(t) before the
@@ -204,6 +210,38 @@ __global__ void k_embed(const double *__restrict__ pts, int64_t M, int64_t Mpad,
         h0t[static_cast<int64_t>(f) * Mpad + m] = hs;
         h0t[static_cast<int64_t>(n_ff + f) * Mpad + m] = hc;
     }
+}
+
+// Training batch: rows m < count are rows idx[m] of the points and of the
+// complex targets (the targets divided by the output scale, as 4 reals),
+// rows in [count, Mpad) are zero; writes the rows' Fourier features (h0 and
+// its transpose) and targets.  *bump (nullable) += 1: the step count of a
+// training step (Adam reads it), kept on the device.
+__global__ void k_embed_batch(const double *__restrict__ pts, const double *__restrict__ tc,
+                              const int32_t *__restrict__ idx, int64_t count, int64_t Mpad, MlpNorm nm,
+                              const float *__restrict__ Bff, int n_ff, double inv_scale, uint16_t *__restrict__ h0,
+                              uint16_t *__restrict__ h0t, float *__restrict__ tb, int64_t *bump)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (bump && i == 0) *bump += 1;
+    if (i >= Mpad * n_ff) return;
+    const int64_t m = i / n_ff;
+    const int f = static_cast<int>(i % n_ff);
+    uint16_t hs = 0, hc = 0;
+    int64_t src = 0;
+    if (m < count) {
+        src = idx[m];
+        double xn[3];
+        for (int c = 0; c < 3; ++c) xn[c] = norm_coord(pts + 3 * src, nm, c);
+        ff_pair(xn, Bff + 3 * f, hs, hc);
+    }
+    const int w = 2 * n_ff;
+    h0[m * w + f] = hs;
+    h0[m * w + n_ff + f] = hc;
+    h0t[static_cast<int64_t>(f) * Mpad + m] = hs;
+    h0t[static_cast<int64_t>(n_ff + f) * Mpad + m] = hc;
+    if (f == 0)
+        for (int c = 0; c < 4; ++c) tb[4 * m + c] = m < count ? static_cast<float>(tc[4 * src + c] * inv_scale) : 0.f;
 }
 
 // ---------------------------------------------------------------- output layer
@@ -260,12 +298,12 @@ __global__ __launch_bounds__(256) void k_out(const uint16_t *__restrict__ h, int
 }
 
 // dh = dy W_out (float32, bf16 weights), dz = dh act'(z); writes dz, bf16(dz)
-// and its transpose.  One thread per (row, column).
-__global__ void k_out_back(const float *__restrict__ dy, const uint16_t *__restrict__ wo, int width, int64_t Mrows,
-                           const float *__restrict__ z, int act, float *__restrict__ dz, uint16_t *__restrict__ dzb,
-                           uint16_t *__restrict__ dzbt)
+// and its transpose.  One thread per (row, column); block b of 256.
+__device__ __forceinline__ void out_back(const float *__restrict__ dy, const uint16_t *__restrict__ wo, int width,
+                                         int64_t Mrows, const float *__restrict__ z, int act, float *__restrict__ dz,
+                                         uint16_t *__restrict__ dzb, uint16_t *__restrict__ dzbt, int64_t blk)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = blk * 256 + threadIdx.x;
     if (i >= Mrows * width) return;
     const int64_t m = i / width;
     const int k = static_cast<int>(i % width);
@@ -278,17 +316,17 @@ __global__ void k_out_back(const float *__restrict__ dy, const uint16_t *__restr
     dzbt[static_cast<int64_t>(k) * Mrows + m] = b;
 }
 
-// Output-layer gradient partials of rows [64 y, 64 y + 64) (block y):
+// Output-layer gradient partials of rows [64 y, 64 y + 64) (block (x, y)):
 // pw[y][o][k] = sum dy[m][o] h[m][k], pb[y][o] = sum dy[m][o]; 256 threads =
 // 4 row phases x 64 columns, combined in a fixed order.
-__global__ __launch_bounds__(256) void k_out_wgrad_part(const float *__restrict__ dy, const uint16_t *__restrict__ h,
-                                                        int width, int64_t Mrows, float *__restrict__ pw,
-                                                        float *__restrict__ pb)
+__device__ __forceinline__ void out_wgrad_part(const float *__restrict__ dy, const uint16_t *__restrict__ h, int width,
+                                               int64_t Mrows, float *__restrict__ pw, float *__restrict__ pb, int bx,
+                                               int by)
 {
     __shared__ float red[4][5][64];
     const int c = threadIdx.x & 63, t4 = threadIdx.x >> 6;
-    const int k = blockIdx.x * 64 + c;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 64, r1 = min(r0 + 64, Mrows);
+    const int k = bx * 64 + c;
+    const int64_t r0 = static_cast<int64_t>(by) * 64, r1 = min(r0 + 64, Mrows);
     float a[4] = {0.f, 0.f, 0.f, 0.f}, b = 0.f;
     for (int64_t m = r0 + t4; m < r1; m += 4) {
         const float hv = k < width ? from_bf16(h[m * width + k]) : 0.f;
@@ -301,41 +339,41 @@ __global__ __launch_bounds__(256) void k_out_wgrad_part(const float *__restrict_
     if (t4 == 0) {
         if (k < width)
             for (int o = 0; o < 4; ++o)
-                pw[(static_cast<int64_t>(blockIdx.y) * 4 + o) * width + k] =
+                pw[(static_cast<int64_t>(by) * 4 + o) * width + k] =
                     ((red[0][o][c] + red[1][o][c]) + red[2][o][c]) + red[3][o][c];
-        if (blockIdx.x == 0 && c < 4)
-            pb[static_cast<int64_t>(blockIdx.y) * 4 + c] = ((red[0][4][c] + red[1][4][c]) + red[2][4][c]) + red[3][4][c];
+        if (bx == 0 && c < 4)
+            pb[static_cast<int64_t>(by) * 4 + c] = ((red[0][4][c] + red[1][4][c]) + red[2][4][c]) + red[3][4][c];
     }
 }
 
 // Column-sum partials of rows [64 y, 64 y + 64) of a row-major float32
-// matrix (bias gradients), same layout of threads.
-__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ x, int64_t rows, int cols,
-                                                     float *__restrict__ part)
+// matrix (bias gradients), same layout of threads; block (x, y).
+__device__ __forceinline__ void colsum_part(const float *__restrict__ x, int64_t rows, int cols,
+                                            float *__restrict__ part, int bx, int by)
 {
     __shared__ float red[4][64];
     const int c = threadIdx.x & 63, t4 = threadIdx.x >> 6;
-    const int col = blockIdx.x * 64 + c;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 64, r1 = min(r0 + 64, rows);
+    const int col = bx * 64 + c;
+    const int64_t r0 = static_cast<int64_t>(by) * 64, r1 = min(r0 + 64, rows);
     float sum = 0.f;
     if (col < cols)
         for (int64_t m = r0 + t4; m < r1; m += 4) sum += x[m * cols + col];
     red[t4][c] = sum;
     __syncthreads();
     if (t4 == 0 && col < cols)
-        part[static_cast<int64_t>(blockIdx.y) * cols + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        part[static_cast<int64_t>(by) * cols + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
-// out[i] = sum over z = 0..nz-1 of part[z][i], in z order.
 // out[i] = sum over z of part[z][i].  A block of 256 threads takes 64
-// consecutive i; wave w sums the slices z = w, w + 4, ... in order, and the
-// four wave sums are added in wave order: a fixed order for every launch.
-__global__ __launch_bounds__(256) void k_sum_slices(const float *__restrict__ part, int nz, int64_t n,
-                                                    float *__restrict__ out)
+// consecutive i (block b: i in [64 b, 64 b + 64)); wave w sums the slices
+// z = w, w + 4, ... in order, and the four wave sums are added in wave
+// order: a fixed order for every launch.
+__device__ __forceinline__ void sum_slices(const float *__restrict__ part, int nz, int64_t n, float *__restrict__ out,
+                                           int64_t b)
 {
     __shared__ float red[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    const int64_t i = b * 64 + lane;
     float sum = 0.f;
     if (i < n) {
 #pragma unroll 4
@@ -346,10 +384,11 @@ __global__ __launch_bounds__(256) void k_sum_slices(const float *__restrict__ pa
     if (w == 0 && i < n) out[i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// *out = sum of x[0 .. n): one wave, lane-strided sums, then a fixed
-// butterfly over the 64 lanes.
-__global__ __launch_bounds__(64) void k_sum(const float *__restrict__ x, int n, float *__restrict__ out)
+// *out = sum of x[0 .. n): the block's first wave, lane-strided sums, then a
+// fixed butterfly over the 64 lanes.
+__device__ __forceinline__ void sum_wave(const float *__restrict__ x, int n, float *__restrict__ out)
 {
+    if (threadIdx.x >= 64) return;
     const int lane = threadIdx.x;
     float s = 0.f;
     for (int i = lane; i < n; i += 64) s += x[i];
@@ -357,48 +396,45 @@ __global__ __launch_bounds__(64) void k_sum(const float *__restrict__ x, int n, 
     if (lane == 0) *out = s;
 }
 
-// Training rows of a batch: rows idx[b] of the points and of the complex
-// targets (divided by the output scale, as 4 reals); rows b >= count are
-// zero.
-__global__ void k_gather(const double *__restrict__ pts, const double *__restrict__ tc, const int32_t *__restrict__ idx,
-                         int64_t count, int64_t Mrows, double inv_scale, double *__restrict__ pb, float *__restrict__ tb)
+// The output layer's backward pass in one launch: blocks [0, nb_back) the
+// hidden-layer gradient (out_back), the next gx R blocks the weight-gradient
+// partials (out_wgrad_part), the last block the batch loss (the sum of the
+// per-block squared errors of k_out).
+__global__ __launch_bounds__(256) void k_out_backward(OutBackArgs a)
 {
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= Mrows) return;
-    if (b < count) {
-        const int64_t s = idx[b];
-        for (int c = 0; c < 3; ++c) pb[3 * b + c] = pts[3 * s + c];
-        for (int c = 0; c < 4; ++c) tb[4 * b + c] = static_cast<float>(tc[4 * s + c] * inv_scale);
+    const int64_t b = blockIdx.x;
+    if (b < a.nb_back) {
+        out_back(a.dy, a.wo, a.width, a.Mrows, a.z, a.act, a.dz, a.dzb, a.dzbt, b);
+    } else if (b < a.nb_back + static_cast<int64_t>(a.gx) * a.R) {
+        const int q = static_cast<int>(b - a.nb_back);
+        out_wgrad_part(a.dy, a.h, a.width, a.Mrows, a.pw, a.pb, q % a.gx, q / a.gx);
     } else {
-        for (int c = 0; c < 3; ++c) pb[3 * b + c] = 0.0;
-        for (int c = 0; c < 4; ++c) tb[4 * b + c] = 0.f;
+        sum_wave(a.part, a.n_part, a.loss);
     }
 }
 
-// Adam step number t = *step + 1 (steps already taken, kept on the device so
-// that a captured training epoch replays unchanged), learning rate
-// lr_sched[*step - step0], bias corrections 1 - b^t.
-__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, int64_t n, const float *__restrict__ lr_sched,
-                       const int64_t *__restrict__ step, int64_t step0, float b1, float b2, float eps)
+// Two independent slice sums (sum_slices) in one launch: blocks [0, nba) the
+// first, the rest the second.
+__global__ __launch_bounds__(256) void k_sum2(SumJob a, SumJob b, int64_t nba)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t s = *step;
-    const float lr = lr_sched[s - step0];
-    const float t = static_cast<float>(s + 1);
-    const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    if (blockIdx.x < nba) sum_slices(a.part, a.nz, a.n, a.out, blockIdx.x);
+    else sum_slices(b.part, b.nz, b.n, b.out, blockIdx.x - nba);
 }
 
-__global__ void k_step_inc(int64_t *step)
+// A split-K weight-gradient product (gemm_tile, float32 slices) and the
+// column-sum partials of the layer's output gradient (the bias gradient)
+// in one launch: blocks [0, gx gy gz) the product, the rest the column sums
+// (cgx blocks per 64-row group).
+template <int NK>
+__global__ __launch_bounds__(kGemmThreads) void k_wgrad_colsum(GemmArgs g, int gx, int gy, int gz, ColsumArgs c)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+    const int b = blockIdx.x, ng = gx * gy * gz;
+    if (b < ng) {
+        gemm_tile<kEpiF32, NK>(g, b % gx, (b / gx) % gy, b / (gx * gy));
+    } else {
+        const int q = b - ng;
+        colsum_part(c.x, c.rows, c.cols, c.part, q % c.gx, q / c.gx);
+    }
 }
 
 // Fragment-major position of element (m, n) of a [rows][K] bf16 matrix
@@ -410,24 +446,54 @@ __device__ __forceinline__ int frag_index(int m, int n, int K)
     return ((((m >> 5) * (K >> 4) + (n >> 4)) * 64 + ((m & 31) + 32 * ((n >> 3) & 1))) << 3) + (n & 7);
 }
 
+// The bf16 copies of weight element j of layer l (value b): the plain copy,
+// the transpose where one exists, the fragment-major copy where asked.
+__device__ __forceinline__ void refresh_one(const RefreshTable &t, int l, int64_t j, uint16_t b)
+{
+    const int rows = t.rows[l], cols = t.cols[l];
+    t.wb[t.woff[l] + j] = b;
+    if (t.toff[l] >= 0) t.wt[t.toff[l] + static_cast<int64_t>(j % cols) * rows + j / cols] = b;
+    if (t.frag[l]) t.wf[t.woff[l] + frag_index(static_cast<int>(j / cols), static_cast<int>(j % cols), cols)] = b;
+}
+
+// Adam over the parameters, then the bf16 copies of the updated weights
+// (what k_refresh writes).  The step count *step (kept on the device so that
+// a captured training epoch replays unchanged) was advanced at the start of
+// this training step: the step number is t = *step, the learning rate
+// lr_sched[*step - 1 - step0], the bias corrections 1 - b^t.
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int64_t n, const float *__restrict__ lr_sched,
+                       const int64_t *__restrict__ step, int64_t step0, float b1, float b2, float eps, RefreshTable rt)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s = *step - 1;
+    const float lr = lr_sched[s - step0];
+    const float t = static_cast<float>(s + 1);
+    const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[i] = wi;
+    for (int l = 0; l < rt.n_layers; ++l) {  // weights (not biases) get bf16 copies
+        const int64_t j = i - rt.woff[l];
+        if (j >= 0 && j < static_cast<int64_t>(rt.rows[l]) * rt.cols[l]) refresh_one(rt, l, j, to_bf16(wi));
+    }
+}
+
 // bf16 copies of every weight matrix [rows][cols] and, where a transposed
 // copy exists, of its transpose, and where asked a fragment-major copy;
 // blockIdx.y = layer.
 __global__ void k_refresh(RefreshTable t)
 {
     const int l = blockIdx.y;
-    const int rows = t.rows[l], cols = t.cols[l];
     const float *w = t.w + t.woff[l];
-    uint16_t *wb = t.wb + t.woff[l];
-    uint16_t *wt = t.toff[l] >= 0 ? t.wt + t.toff[l] : nullptr;
-    uint16_t *wf = t.frag[l] ? t.wf + t.woff[l] : nullptr;  // fragment-major copy (fused inference)
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < static_cast<int64_t>(rows) * cols;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const uint16_t b = to_bf16(w[i]);
-        wb[i] = b;
-        if (wt) wt[static_cast<int64_t>(i % cols) * rows + i / cols] = b;
-        if (wf) wf[frag_index(static_cast<int>(i / cols), static_cast<int>(i % cols), cols)] = b;
-    }
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+         i < static_cast<int64_t>(t.rows[l]) * t.cols[l]; i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        refresh_one(t, l, i, to_bf16(w[i]));
 }
 
 // ---------------------------------------------------------------- fused inference
@@ -714,56 +780,60 @@ int launch_out(hipStream_t s, const uint16_t *h, int width, const uint16_t *wo, 
     return SBR_OK;
 }
 
-int launch_out_back(hipStream_t s, const float *dy, const uint16_t *wo, int width, int64_t Mrows, const float *z,
-                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h,
-                    float *scratch)
+int launch_embed_batch(hipStream_t s, const double *pts, const double *tc, const int32_t *idx, int64_t count,
+                       int64_t Mpad, const MlpNorm &nm, const float *Bff, int n_ff, double inv_scale, uint16_t *h0,
+                       uint16_t *h0t, float *tb, int64_t *bump)
 {
-    const int R = static_cast<int>((Mrows + 63) / 64);
-    float *pw = scratch, *pb = scratch + static_cast<int64_t>(R) * 4 * width;
-    k_out_back<<<nblk(Mrows * width, 256), 256, 0, s>>>(dy, wo, width, Mrows, z, act, dz, dzb, dzbt);
-    k_out_wgrad_part<<<dim3((width + 63) / 64, R), 256, 0, s>>>(dy, h, width, Mrows, pw, pb);
-    k_sum_slices<<<nblk(4 * width, 64), 256, 0, s>>>(pw, R, 4 * width, gw);
-    k_sum_slices<<<1, 256, 0, s>>>(pb, R, 4, gb);
+    k_embed_batch<<<nblk(Mpad * n_ff, 256), 256, 0, s>>>(pts, tc, idx, count, Mpad, nm, Bff, n_ff, inv_scale, h0, h0t, tb,
+                                                          bump);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
-int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out, float *scratch)
+int launch_out_backward(hipStream_t s, const OutBackIn &in, float *gw, float *gb, float *scratch)
 {
+    const int R = static_cast<int>((in.Mrows + 63) / 64);
+    OutBackArgs a{};
+    static_cast<OutBackIn &>(a) = in;
+    a.pw = scratch;
+    a.pb = scratch + static_cast<int64_t>(R) * 4 * in.width;
+    a.nb_back = nblk(in.Mrows * in.width, 256);
+    a.gx = (in.width + 63) / 64;
+    a.R = R;
+    k_out_backward<<<static_cast<unsigned>(a.nb_back + static_cast<int64_t>(a.gx) * R + 1), 256, 0, s>>>(a);
+    const SumJob jw{a.pw, R, 4 * static_cast<int64_t>(in.width), gw}, jb{a.pb, R, 4, gb};
+    const int64_t nw = nblk(jw.n, 64);
+    k_sum2<<<static_cast<unsigned>(nw + nblk(jb.n, 64)), 256, 0, s>>>(jw, jb, nw);
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_wgrad_colsum(hipStream_t s, const GemmArgs &g, const float *dz, int64_t rows, int cols, float *colpart,
+                        float *gw, float *gb)
+{
+    if (g.M % kTileM || g.N % kTileN || g.K % 16 || g.K <= 0 || g.ksplit < 1 || g.K % g.ksplit ||
+        (g.K / g.ksplit) % 16 || !g.fout)
+        return fail(SBR_ERR_INVALID_ARG, "MLP weight gradient: shape not a multiple of the tile");
+    const int gx = g.M / kTileM, gy = g.N / kTileN, gz = g.ksplit;
+    ColsumArgs c{dz, rows, cols, colpart, (cols + 63) / 64};
     const int R = static_cast<int>((rows + 63) / 64);
-    k_colsum_part<<<dim3((cols + 63) / 64, R), 256, 0, s>>>(x, rows, cols, scratch);
-    k_sum_slices<<<nblk(cols, 64), 256, 0, s>>>(scratch, R, cols, out);
-    SBR_HIP(hipGetLastError());
-    return SBR_OK;
-}
-
-int launch_sum_slices(hipStream_t s, const float *part, int nz, int64_t n, float *out)
-{
-    k_sum_slices<<<nblk(n, 64), 256, 0, s>>>(part, nz, n, out);
-    SBR_HIP(hipGetLastError());
-    return SBR_OK;
-}
-
-int launch_sum(hipStream_t s, const float *x, int n, float *out)
-{
-    k_sum<<<1, 64, 0, s>>>(x, n, out);
-    SBR_HIP(hipGetLastError());
-    return SBR_OK;
-}
-
-int launch_gather(hipStream_t s, const double *pts, const double *tc, const int32_t *idx, int64_t count,
-                  int64_t Mrows, double inv_scale, double *pb, float *tb)
-{
-    k_gather<<<nblk(Mrows, 256), 256, 0, s>>>(pts, tc, idx, count, Mrows, inv_scale, pb, tb);
+    const unsigned nb = static_cast<unsigned>(gx * gy * gz + c.gx * R);
+    const int nk = g.K / g.ksplit / 16;
+    if (nk == 8) k_wgrad_colsum<8><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c);
+    else if (nk == 16) k_wgrad_colsum<16><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c);
+    else k_wgrad_colsum<0><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c);
+    const SumJob jw{g.fout, g.ksplit, static_cast<int64_t>(g.M) * g.N, gw}, jb{colpart, R, cols, gb};
+    const int64_t nw = nblk(jw.n, 64);
+    k_sum2<<<static_cast<unsigned>(nw + nblk(jb.n, 64)), 256, 0, s>>>(jw, jb, nw);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
 int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, const float *lr_sched,
-                int64_t *step, int64_t step0, float b1, float b2, float eps)
+                const int64_t *step, int64_t step0, float b1, float b2, float eps, const RefreshTable &rt)
 {
-    k_adam<<<nblk(n, 256), 256, 0, s>>>(w, m, v, g, n, lr_sched, step, step0, b1, b2, eps);
-    k_step_inc<<<1, 64, 0, s>>>(step);
+    if (rt.n_layers < 1 || rt.n_layers > kMaxLayers) return fail(SBR_ERR_INVALID_ARG, "adam: layer count");
+    k_adam<<<nblk(n, 256), 256, 0, s>>>(w, m, v, g, n, lr_sched, step, step0, b1, b2, eps, rt);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

@@ -482,20 +482,6 @@ int launch_embed(hipStream_t s, const double *pts, int64_t M, int64_t Mpad, cons
                  int n_ff, uint16_t *h0, uint16_t *h0t);
 int launch_out(hipStream_t s, const uint16_t *h, int width, const uint16_t *wo, const float *bo, int64_t M,
                int64_t Mrows, int mode, double scale, double *A, const float *tgt, float *dy, float *partial);
-// scratch: at least ceil(Mrows / 64) (4 width + 4) floats
-int launch_out_back(hipStream_t s, const float *dy, const uint16_t *wo, int width, int64_t Mrows, const float *z,
-                    int act, float *dz, uint16_t *dzb, uint16_t *dzbt, float *gw, float *gb, const uint16_t *h,
-                    float *scratch);
-// scratch: at least ceil(rows / 64) cols floats
-int launch_colsum(hipStream_t s, const float *x, int64_t rows, int cols, float *out, float *scratch);
-int launch_sum_slices(hipStream_t s, const float *part, int nz, int64_t n, float *out);
-int launch_sum(hipStream_t s, const float *x, int n, float *out);
-int launch_gather(hipStream_t s, const double *pts, const double *tc, const int32_t *idx, int64_t count,
-                  int64_t Mrows, double inv_scale, double *pb, float *tb);
-// Adam over n parameters at step *step (device) with lr_sched[*step - step0],
-// then *step += 1.
-int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, const float *lr_sched,
-                int64_t *step, int64_t step0, float b1, float b2, float eps);
 constexpr int kMaxLayers = 9;
 struct RefreshTable {
     const float *w;
@@ -506,6 +492,60 @@ struct RefreshTable {
     int64_t woff[kMaxLayers], toff[kMaxLayers];
 };
 int launch_refresh(hipStream_t s, const RefreshTable &t);
+// Training batch rows idx[0, count) of the points and targets, their Fourier
+// features (h0 and its transpose) and targets / out_scale; *bump (nullable)
+// += 1, the device step count of a training step.
+int launch_embed_batch(hipStream_t s, const double *pts, const double *tc, const int32_t *idx, int64_t count,
+                       int64_t Mpad, const MlpNorm &nm, const float *Bff, int n_ff, double inv_scale, uint16_t *h0,
+                       uint16_t *h0t, float *tb, int64_t *bump);
+// The output layer's backward pass: the last hidden layer's gradient (dz,
+// bf16 dz and its transpose), the output weight and bias gradients (gw, gb)
+// and the batch loss (*loss = sum of part[0, n_part)).
+struct OutBackIn {
+    const float *dy;
+    const uint16_t *wo;
+    int width;
+    int64_t Mrows;
+    const float *z;
+    int act;
+    float *dz;
+    uint16_t *dzb, *dzbt;
+    const uint16_t *h;
+    const float *part;
+    int n_part;
+    float *loss;
+};
+struct OutBackArgs : OutBackIn {
+    float *pw, *pb;  // weight and bias partials per 64-row group
+    int64_t nb_back;
+    int gx, R;
+};
+struct SumJob {
+    const float *part;
+    int nz;
+    int64_t n;
+    float *out;
+};
+struct ColsumArgs {
+    const float *x;
+    int64_t rows;
+    int cols;
+    float *part;
+    int gx;
+};
+// scratch: at least ceil(Mrows / 64) (4 width + 4) floats
+int launch_out_backward(hipStream_t s, const OutBackIn &in, float *gw, float *gb, float *scratch);
+// A hidden layer's weight gradient (split-K product g into its float32
+// slices g.fout, summed into gw) and bias gradient (column sums of the
+// layer's output gradient dz [rows][cols] through colpart, at least
+// ceil(rows / 64) cols floats, into gb).
+int launch_wgrad_colsum(hipStream_t s, const GemmArgs &g, const float *dz, int64_t rows, int cols, float *colpart,
+                        float *gw, float *gb);
+// Adam over n parameters at step *step - 1 (the step count is advanced at
+// the start of each training step) with lr_sched[*step - 1 - step0], then
+// the bf16 copies of the updated weights (rt, as launch_refresh).
+int launch_adam(hipStream_t s, float *w, float *m, float *v, const float *g, int64_t n, const float *lr_sched,
+                const int64_t *step, int64_t step0, float b1, float b2, float eps, const RefreshTable &rt);
 // Whole-network inference for width 256 (activations in LDS).
 struct FusedArgs {
     const double *pts;

@@ -78,7 +78,6 @@ struct sbr_mlp {
     std::vector<float *> z;          // z[1..depth] stored at z[l - 1]
     float *dz[2] = {nullptr, nullptr};
     uint16_t *dzb[2] = {nullptr, nullptr}, *dzbt[2] = {nullptr, nullptr};
-    double *pb = nullptr;
     float *tb = nullptr, *dy = nullptr, *part = nullptr, *losses = nullptr;
     float *red = nullptr;  // reduction scratch (split-K slices, column-sum partials)
     int ksplit = 1;
@@ -90,7 +89,7 @@ struct sbr_mlp {
 
 namespace {
 
-int refresh_bf16(sbr_mlp *M, hipStream_t s)
+RefreshTable refresh_table(const sbr_mlp *M)
 {
     RefreshTable t{};
     t.w = M->w;
@@ -106,8 +105,10 @@ int refresh_bf16(sbr_mlp *M, hipStream_t s)
         t.woff[l] = M->woff[l];
         t.toff[l] = M->toff[l];
     }
-    return launch_refresh(s, t);
+    return t;
 }
+
+int refresh_bf16(sbr_mlp *M, hipStream_t s) { return launch_refresh(s, refresh_table(M)); }
 
 int ensure_pred(sbr_mlp *M, int64_t rows)
 {
@@ -145,8 +146,7 @@ int ensure_train(sbr_mlp *M, int64_t rows)
             (rc = M->ws_train.alloc(&M->dzb[q], static_cast<size_t>(rows) * W)) ||
             (rc = M->ws_train.alloc(&M->dzbt[q], static_cast<size_t>(rows) * W)))
             return rc;
-    if ((rc = M->ws_train.alloc(&M->pb, static_cast<size_t>(rows) * 3)) ||
-        (rc = M->ws_train.alloc(&M->tb, static_cast<size_t>(rows) * 4)) ||
+    if ((rc = M->ws_train.alloc(&M->tb, static_cast<size_t>(rows) * 4)) ||
         (rc = M->ws_train.alloc(&M->dy, static_cast<size_t>(rows) * 4)) ||
         (rc = M->ws_train.alloc(&M->part, static_cast<size_t>(rows / 16 + 1))))
         return rc;
@@ -156,20 +156,25 @@ int ensure_train(sbr_mlp *M, int64_t rows)
     M->ksplit = ks;
     const int64_t kin_max = std::max(W, 2 * M->n_ff);
     const int64_t R = (rows + 63) / 64;
-    const int64_t red = std::max({static_cast<int64_t>(ks) * W * kin_max, R * (4 * W + 4), R * W});
+    // the split-K slices of a weight gradient, then the column-sum partials of its bias
+    const int64_t red = std::max(static_cast<int64_t>(ks) * W * kin_max + R * W, R * (4 * W + 4));
     if ((rc = M->ws_train.alloc(&M->red, static_cast<size_t>(red)))) return rc;
     M->train_rows = rows;
     return SBR_OK;
 }
 
-// Forward, loss and gradients (into M->g) of one batch already gathered
-// into M->pb / M->tb (count real rows, rows padded to a multiple of 64).
-// The batch's summed squared error goes to *loss_slot (device).
-int batch_grad(sbr_mlp *M, hipStream_t s, int64_t count, int64_t rows, float *loss_slot)
+// Forward, loss and gradients (into M->g) of the batch of rows idx[0, count)
+// of the points and targets (rows padded to a multiple of 64).  The batch's
+// summed squared error goes to *loss_slot (device); *bump (nullable) += 1
+// first (the step count of a training step).
+int batch_grad(sbr_mlp *M, hipStream_t s, const double *pts, const double *targets, const int32_t *idx, int64_t count,
+               int64_t rows, float *loss_slot, int64_t *bump)
 {
     int rc;
     const int W = M->width, D = M->depth, K0 = 2 * M->n_ff;
-    if ((rc = launch_embed(s, M->pb, count, rows, M->norm, M->Bff, M->n_ff, M->h[0], M->ht[0]))) return rc;
+    if ((rc = launch_embed_batch(s, pts, targets, idx, count, rows, M->norm, M->Bff, M->n_ff, 1.0 / M->scale, M->h[0],
+                                 M->ht[0], M->tb, bump)))
+        return rc;
     for (int l = 1; l <= D; ++l) {
         GemmArgs a{};
         a.A = M->h[l - 1];
@@ -191,12 +196,23 @@ int batch_grad(sbr_mlp *M, hipStream_t s, int64_t count, int64_t rows, float *lo
     }
     const int64_t nblk = (rows + 15) / 16;
     if ((rc = launch_out(s, M->h[D], W, M->wb + M->woff[D], M->w + M->boff[D], count, rows, 1, 1.0, nullptr, M->tb,
-                         M->dy, M->part)) ||
-        (rc = launch_sum(s, M->part, static_cast<int>(nblk), loss_slot)))
+                         M->dy, M->part)))
         return rc;
-    if ((rc = launch_out_back(s, M->dy, M->wb + M->woff[D], W, rows, M->z[D - 1], M->act, M->dz[0], M->dzb[0],
-                              M->dzbt[0], M->g + M->woff[D], M->g + M->boff[D], M->h[D], M->red)))
-        return rc;
+    OutBackIn ob{};
+    ob.dy = M->dy;
+    ob.wo = M->wb + M->woff[D];
+    ob.width = W;
+    ob.Mrows = rows;
+    ob.z = M->z[D - 1];
+    ob.act = M->act;
+    ob.dz = M->dz[0];
+    ob.dzb = M->dzb[0];
+    ob.dzbt = M->dzbt[0];
+    ob.h = M->h[D];
+    ob.part = M->part;
+    ob.n_part = static_cast<int>(nblk);
+    ob.loss = loss_slot;
+    if ((rc = launch_out_backward(s, ob, M->g + M->woff[D], M->g + M->boff[D], M->red))) return rc;
     int cur = 0;
     for (int l = D; l >= 1; --l) {
         const int kin = M->n_in[l - 1];
@@ -212,10 +228,10 @@ int batch_grad(sbr_mlp *M, hipStream_t s, int64_t count, int64_t rows, float *lo
         a.ldf = kin;
         a.ksplit = M->ksplit;
         a.split_stride = static_cast<int64_t>(W) * kin;
-        if ((rc = launch_gemm(s, kEpiF32, a)) ||
-            (rc = launch_sum_slices(s, M->red, M->ksplit, static_cast<int64_t>(W) * kin, M->g + M->woff[l - 1])))
+        float *colpart = M->red + static_cast<int64_t>(M->ksplit) * W * kin;
+        if ((rc = launch_wgrad_colsum(s, a, M->dz[cur], rows, W, colpart, M->g + M->woff[l - 1],
+                                      M->g + M->boff[l - 1])))
             return rc;
-        if ((rc = launch_colsum(s, M->dz[cur], rows, W, M->g + M->boff[l - 1], M->red))) return rc;
         if (l > 1) {
             const int nxt = cur ^ 1;
             GemmArgs b{};
@@ -464,8 +480,7 @@ extern "C" int sbr_mlp_gradients(sbr_mlp *M, const double *pts, const double *ta
     Bufs tmp;
     if ((rc = tmp.alloc(&didx, n)) || (rc = tmp.alloc(&dl, 1))) return rc;
     SBR_HIP(hipMemcpyAsync(didx, id.data(), 4 * n, hipMemcpyHostToDevice, s));
-    if ((rc = launch_gather(s, pts, targets, didx, n, rows, 1.0 / M->scale, M->pb, M->tb))) return rc;
-    if ((rc = batch_grad(M, s, n, rows, dl))) return rc;
+    if ((rc = batch_grad(M, s, pts, targets, didx, n, rows, dl, nullptr))) return rc;
     SBR_HIP(hipMemcpyAsync(grads, M->g, 4 * M->P, hipMemcpyDeviceToDevice, s));
     float hl = 0.f;
     SBR_HIP(hipMemcpyAsync(&hl, dl, 4, hipMemcpyDeviceToHost, s));
@@ -512,6 +527,7 @@ extern "C" int sbr_mlp_train(sbr_mlp *M, const double *pts, const double *target
     SBR_HIP(hipMemcpyAsync(dlr, lr.data(), 4 * total, hipMemcpyHostToDevice, s));
     const int64_t step0 = M->adam_t;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const RefreshTable rt = refresh_table(M);
     // capture one epoch
     hipStream_t cap = nullptr;
     SBR_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -523,10 +539,8 @@ extern "C" int sbr_mlp_train(sbr_mlp *M, const double *pts, const double *target
     }
     for (int64_t st = 0; st < steps && rc == SBR_OK; ++st) {
         const int64_t cnt = std::min(bsz, n - st * bsz);
-        if ((rc = launch_gather(cap, pts, targets, didx + st * bsz, cnt, rows, 1.0 / M->scale, M->pb, M->tb)) ||
-            (rc = batch_grad(M, cap, cnt, rows, dl + st)) ||
-            (rc = launch_adam(cap, M->w, M->m, M->v, M->g, M->P, dlr, M->step, step0, b1, b2, eps)) ||
-            (rc = refresh_bf16(M, cap)))
+        if ((rc = batch_grad(M, cap, pts, targets, didx + st * bsz, cnt, rows, dl + st, M->step)) ||
+            (rc = launch_adam(cap, M->w, M->m, M->v, M->g, M->P, dlr, M->step, step0, b1, b2, eps, rt)))
             break;
     }
     const hipError_t ec = hipStreamEndCapture(cap, &graph);
