@@ -97,21 +97,24 @@ __device__ __forceinline__ void ff_pair(const double *xn, const float *Bq, uint1
 constexpr int kGemmThreads = 256;
 constexpr int kTileM = 64, kTileN = 128, kGemmRing = 4;
 
-// C = A B^T over k (both operands k-contiguous, bf16), 64 x 128 tiles, one
-// 32 x 64 piece per wave; NK > 0: exactly NK k steps per block (unrolled),
-// NK = 0: any multiple of 16.
-template <int EPI, int NK>
+// C = A B^T over k (both operands k-contiguous, bf16), 64 x TN tiles (TN =
+// 128: one 32 x 64 piece per wave, two accumulators; TN = 64: one 32 x 32
+// piece, for products too small to give every CU a 64 x 128 tile); NK > 0:
+// exactly NK k steps per block (unrolled), NK = 0: any multiple of 16.  Each
+// output element sums k in the same order whatever the tile.
+template <int EPI, int NK, int TN = kTileN>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int bz)
 {
+    constexpr int NC = TN / 64;  // 32-column accumulators per wave
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m0 = bx * kTileM + (wv & 1) * 32;
-    const int n0 = by * kTileN + (wv >> 1) * 64;
+    const int n0 = by * TN + (wv >> 1) * (32 * NC);
     const int r = lane & 31, kh = (lane >> 5) * 8;
     // split-K (kEpiF32): block z sums k in [z Kc, (z + 1) Kc) into slice z of fout
     const int kc = g.K / g.ksplit, kb = bz * kc;
     const uint16_t *pa = g.A + static_cast<int64_t>(m0 + r) * g.lda + kh + kb;
     const uint16_t *pb0 = g.B + static_cast<int64_t>(n0 + r) * g.ldb + kh + kb;
-    const uint16_t *pb1 = g.B + static_cast<int64_t>(n0 + 32 + r) * g.ldb + kh + kb;
+    const uint16_t *pb1 = g.B + static_cast<int64_t>(n0 + 32 * (NC - 1) + r) * g.ldb + kh + kb;
     float *fout = g.fout ? g.fout + bz * g.split_stride : nullptr;
     f32x16 acc0 = {}, acc1 = {};
     if constexpr (NK > 0) {
@@ -121,7 +124,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
         for (int u = 0; u < kGemmRing && u < NK; ++u) {
             ra[u] = *reinterpret_cast<const bf16x8 *>(pa + 16 * u);
             rb0[u] = *reinterpret_cast<const bf16x8 *>(pb0 + 16 * u);
-            rb1[u] = *reinterpret_cast<const bf16x8 *>(pb1 + 16 * u);
+            if (NC == 2) rb1[u] = *reinterpret_cast<const bf16x8 *>(pb1 + 16 * u);
         }
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
@@ -130,24 +133,26 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
             if (k + kGemmRing < NK) {
                 ra[u] = *reinterpret_cast<const bf16x8 *>(pa + 16 * (k + kGemmRing));
                 rb0[u] = *reinterpret_cast<const bf16x8 *>(pb0 + 16 * (k + kGemmRing));
-                rb1[u] = *reinterpret_cast<const bf16x8 *>(pb1 + 16 * (k + kGemmRing));
+                if (NC == 2) rb1[u] = *reinterpret_cast<const bf16x8 *>(pb1 + 16 * (k + kGemmRing));
             }
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+            if (NC == 2) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
         }
     } else {
         for (int k0 = 0; k0 < kc; k0 += 16) {
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(pa + k0);
             const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0 + k0);
-            const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+            if (NC == 2) {
+                const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1 + k0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+            }
         }
     }
     // register q holds row m0 + 8 (q / 4) + 4 (lane / 32) + q % 4 of column n:
     // the four rows of a quad are consecutive, so the transposed bf16 copy is
     // written as one 8-byte store per quad
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < NC; ++c) {
         const f32x16 &acc = c ? acc1 : acc0;
         const int n = n0 + 32 * c + r;
 #pragma unroll
@@ -180,10 +185,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
     }
 }
 
-template <int EPI, int NK>
+template <int EPI, int NK, int TN>
 __global__ __launch_bounds__(kGemmThreads) void k_gemm(GemmArgs g)
 {
-    gemm_tile<EPI, NK>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+    gemm_tile<EPI, NK, TN>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------- features
@@ -746,16 +751,21 @@ int launch_gemm(hipStream_t s, int epi, const GemmArgs &g)
         return fail(SBR_ERR_INVALID_ARG, "MLP product: bad k split");
     if (g.htout && (g.ldht % 4 || reinterpret_cast<uintptr_t>(g.htout) % 8))
         return fail(SBR_ERR_INVALID_ARG, "MLP product: transposed output not 8-byte aligned");
-    dim3 grid(g.M / kTileM, g.N / kTileN, g.ksplit);
+    // 64 x 64 tiles when 64 x 128 ones would leave CUs idle
+    const bool narrow = (g.M / kTileM) * (g.N / kTileN) * g.ksplit < 256;
+    dim3 grid(g.M / kTileM, g.N / (narrow ? 64 : kTileN), g.ksplit);
     const int nk = g.K / g.ksplit / 16;
     auto go = [&](auto epi_c) {
         constexpr int E = decltype(epi_c)::value;
-        if (nk == 8)
-            k_gemm<E, 8><<<grid, kGemmThreads, 0, s>>>(g);
-        else if (nk == 16)
-            k_gemm<E, 16><<<grid, kGemmThreads, 0, s>>>(g);
-        else
-            k_gemm<E, 0><<<grid, kGemmThreads, 0, s>>>(g);
+        if (narrow) {
+            if (nk == 8) k_gemm<E, 8, 64><<<grid, kGemmThreads, 0, s>>>(g);
+            else if (nk == 16) k_gemm<E, 16, 64><<<grid, kGemmThreads, 0, s>>>(g);
+            else k_gemm<E, 0, 64><<<grid, kGemmThreads, 0, s>>>(g);
+        } else {
+            if (nk == 8) k_gemm<E, 8, kTileN><<<grid, kGemmThreads, 0, s>>>(g);
+            else if (nk == 16) k_gemm<E, 16, kTileN><<<grid, kGemmThreads, 0, s>>>(g);
+            else k_gemm<E, 0, kTileN><<<grid, kGemmThreads, 0, s>>>(g);
+        }
     };
     if (epi == kEpiHidden) go(std::integral_constant<int, kEpiHidden>{});
     else if (epi == kEpiDz) go(std::integral_constant<int, kEpiDz>{});
