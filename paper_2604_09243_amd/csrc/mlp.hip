@@ -447,28 +447,46 @@ __global__ __launch_bounds__(256) void k_out_backward(OutBackArgs a)
     }
 }
 
-// Two independent slice sums (sum_slices) in one launch: blocks [0, nba) the
-// first, the rest the second.
-__global__ __launch_bounds__(256) void k_sum2(SumJob a, SumJob b, int64_t nba)
+// Block q of a pair of independent slice sums (sum_slices): the first sum's
+// blocks, then the second's.
+__device__ __forceinline__ void sum_pair(const SumPair &s, int64_t q)
 {
-    if (blockIdx.x < nba) sum_slices(a.part, a.nz, a.n, a.out, blockIdx.x);
-    else sum_slices(b.part, b.nz, b.n, b.out, blockIdx.x - nba);
+    if (q < s.nba) sum_slices(s.a.part, s.a.nz, s.a.n, s.a.out, q);
+    else sum_slices(s.b.part, s.b.nz, s.b.n, s.b.out, q - s.nba);
 }
 
-// A split-K weight-gradient product (gemm_tile, float32 slices) and the
+__global__ __launch_bounds__(256) void k_sum2(SumPair s) { sum_pair(s, blockIdx.x); }
+
+// A split-K weight-gradient product (gemm_tile, float32 slices), the
 // column-sum partials of the layer's output gradient (the bias gradient)
-// in one launch: blocks [0, gx gy gz) the product, the rest the column sums
-// (cgx blocks per 64-row group).
+// and the slice sums of an earlier layer's gradients, which read none of
+// this launch's outputs, in one launch: blocks [0, gx gy gz) the product,
+// the next c.gx R the column sums, the rest the sums.
 template <int NK>
-__global__ __launch_bounds__(kGemmThreads) void k_wgrad_colsum(GemmArgs g, int gx, int gy, int gz, ColsumArgs c)
+__global__ __launch_bounds__(kGemmThreads) void k_wgrad_colsum(GemmArgs g, int gx, int gy, int gz, ColsumArgs c,
+                                                               SumPair fold)
 {
-    const int b = blockIdx.x, ng = gx * gy * gz;
+    const int64_t b = blockIdx.x, ng = static_cast<int64_t>(gx) * gy * gz, nc = static_cast<int64_t>(c.gx) * c.R;
     if (b < ng) {
-        gemm_tile<kEpiF32, NK>(g, b % gx, (b / gx) % gy, b / (gx * gy));
-    } else {
-        const int q = b - ng;
+        gemm_tile<kEpiF32, NK>(g, static_cast<int>(b % gx), static_cast<int>((b / gx) % gy),
+                               static_cast<int>(b / (static_cast<int64_t>(gx) * gy)));
+    } else if (b < ng + nc) {
+        const int q = static_cast<int>(b - ng);
         colsum_part(c.x, c.rows, c.cols, c.part, q % c.gx, q / c.gx);
+    } else {
+        sum_pair(fold, b - ng - nc);
     }
+}
+
+// A product (no k split) and the slice sums of the previous layer's
+// gradients, which it does not read, in one launch: blocks [0, gx gy) the
+// product, the rest the sums.
+template <int EPI, int NK, int TN>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_fold(GemmArgs g, int gx, int gy, SumPair fold)
+{
+    const int64_t b = blockIdx.x, ng = static_cast<int64_t>(gx) * gy;
+    if (b < ng) gemm_tile<EPI, NK, TN>(g, static_cast<int>(b % gx), static_cast<int>(b / gx), 0);
+    else sum_pair(fold, b - ng);
 }
 
 // Fragment-major position of element (m, n) of a [rows][K] bf16 matrix
@@ -829,42 +847,80 @@ int launch_embed_batch(hipStream_t s, const double *pts, const double *tc, const
     return SBR_OK;
 }
 
-int launch_out_backward(hipStream_t s, const OutBackIn &in, float *gw, float *gb, float *scratch)
+SumPair sum_pair_of(const SumJob &a, const SumJob &b)
+{
+    return SumPair{a, b, static_cast<int64_t>(nblk(a.n, 64)), static_cast<int64_t>(nblk(b.n, 64))};
+}
+
+int launch_out_backward(hipStream_t s, const OutBackIn &in, float *gw, float *gb, float *scratch, SumPair *pending)
 {
     const int R = static_cast<int>((in.Mrows + 63) / 64);
+    if (in.Mrows % 64) return fail(SBR_ERR_INVALID_ARG, "MLP output backward: rows not a multiple of 64");
     OutBackArgs a{};
     static_cast<OutBackIn &>(a) = in;
     a.pw = scratch;
     a.pb = scratch + static_cast<int64_t>(R) * 4 * in.width;
-    if (in.Mrows % 64) return fail(SBR_ERR_INVALID_ARG, "MLP output backward: rows not a multiple of 64");
     a.nb_back = nblk((in.Mrows / 4) * in.width, 256);
     a.gx = (in.width + 63) / 64;
     a.R = R;
     k_out_backward<<<static_cast<unsigned>(a.nb_back + static_cast<int64_t>(a.gx) * R + 1), 256, 0, s>>>(a);
-    const SumJob jw{a.pw, R, 4 * static_cast<int64_t>(in.width), gw}, jb{a.pb, R, 4, gb};
-    const int64_t nw = nblk(jw.n, 64);
-    k_sum2<<<static_cast<unsigned>(nw + nblk(jb.n, 64)), 256, 0, s>>>(jw, jb, nw);
+    *pending = sum_pair_of(SumJob{a.pw, R, 4 * static_cast<int64_t>(in.width), gw}, SumJob{a.pb, R, 4, gb});
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }
 
 int launch_wgrad_colsum(hipStream_t s, const GemmArgs &g, const float *dz, int64_t rows, int cols, float *colpart,
-                        float *gw, float *gb)
+                        float *gw, float *gb, const SumPair &fold, SumPair *pending)
 {
     if (g.M % kTileM || g.N % kTileN || g.K % 16 || g.K <= 0 || g.ksplit < 1 || g.K % g.ksplit ||
         (g.K / g.ksplit) % 16 || !g.fout)
         return fail(SBR_ERR_INVALID_ARG, "MLP weight gradient: shape not a multiple of the tile");
     const int gx = g.M / kTileM, gy = g.N / kTileN, gz = g.ksplit;
-    ColsumArgs c{dz, rows, cols, colpart, (cols + 63) / 64};
     const int R = static_cast<int>((rows + 63) / 64);
-    const unsigned nb = static_cast<unsigned>(gx * gy * gz + c.gx * R);
+    ColsumArgs c{dz, rows, cols, colpart, (cols + 63) / 64, R};
+    const unsigned nb = static_cast<unsigned>(static_cast<int64_t>(gx) * gy * gz + static_cast<int64_t>(c.gx) * R +
+                                              fold.nba + fold.nbb);
     const int nk = g.K / g.ksplit / 16;
-    if (nk == 8) k_wgrad_colsum<8><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c);
-    else if (nk == 16) k_wgrad_colsum<16><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c);
-    else k_wgrad_colsum<0><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c);
-    const SumJob jw{g.fout, g.ksplit, static_cast<int64_t>(g.M) * g.N, gw}, jb{colpart, R, cols, gb};
-    const int64_t nw = nblk(jw.n, 64);
-    k_sum2<<<static_cast<unsigned>(nw + nblk(jb.n, 64)), 256, 0, s>>>(jw, jb, nw);
+    if (nk == 8) k_wgrad_colsum<8><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c, fold);
+    else if (nk == 16) k_wgrad_colsum<16><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c, fold);
+    else k_wgrad_colsum<0><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, gz, c, fold);
+    *pending = sum_pair_of(SumJob{g.fout, g.ksplit, static_cast<int64_t>(g.M) * g.N, gw}, SumJob{colpart, R, cols, gb});
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_gemm_fold(hipStream_t s, int epi, const GemmArgs &g, const SumPair &fold)
+{
+    if (g.M % kTileM || g.N % kTileN || g.K % 16 || g.K <= 0 || g.ksplit != 1 || epi == kEpiF32)
+        return fail(SBR_ERR_INVALID_ARG, "MLP product with sums: shape not a multiple of the tile");
+    if (g.htout && (g.ldht % 4 || reinterpret_cast<uintptr_t>(g.htout) % 8))
+        return fail(SBR_ERR_INVALID_ARG, "MLP product: transposed output not 8-byte aligned");
+    // 64 x 64 tiles when 64 x 128 ones would leave CUs idle (as launch_gemm)
+    const bool narrow = (g.M / kTileM) * (g.N / kTileN) < 256;
+    const int gx = g.M / kTileM, gy = g.N / (narrow ? 64 : kTileN);
+    const unsigned nb = static_cast<unsigned>(static_cast<int64_t>(gx) * gy + fold.nba + fold.nbb);
+    const int nk = g.K / 16;
+    auto go = [&](auto epi_c) {
+        constexpr int E = decltype(epi_c)::value;
+        if (narrow) {
+            if (nk == 8) k_gemm_fold<E, 8, 64><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, fold);
+            else if (nk == 16) k_gemm_fold<E, 16, 64><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, fold);
+            else k_gemm_fold<E, 0, 64><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, fold);
+        } else {
+            if (nk == 8) k_gemm_fold<E, 8, kTileN><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, fold);
+            else if (nk == 16) k_gemm_fold<E, 16, kTileN><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, fold);
+            else k_gemm_fold<E, 0, kTileN><<<nb, kGemmThreads, 0, s>>>(g, gx, gy, fold);
+        }
+    };
+    if (epi == kEpiHidden) go(std::integral_constant<int, kEpiHidden>{});
+    else go(std::integral_constant<int, kEpiDz>{});
+    SBR_HIP(hipGetLastError());
+    return SBR_OK;
+}
+
+int launch_sum_pair(hipStream_t s, const SumPair &p)
+{
+    if (p.nba + p.nbb > 0) k_sum2<<<static_cast<unsigned>(p.nba + p.nbb), 256, 0, s>>>(p);
     SBR_HIP(hipGetLastError());
     return SBR_OK;
 }

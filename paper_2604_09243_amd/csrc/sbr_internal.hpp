@@ -531,16 +531,30 @@ struct ColsumArgs {
     int64_t rows;
     int cols;
     float *part;
-    int gx;
+    int gx, R;
 };
-// scratch: at least ceil(Mrows / 64) (4 width + 4) floats
-int launch_out_backward(hipStream_t s, const OutBackIn &in, float *gw, float *gb, float *scratch);
+// Two slice sums (out[i] = sum over z of part[z][i]) and their block counts
+// (64 outputs per block; a count of 0: no sum).
+struct SumPair {
+    SumJob a, b;
+    int64_t nba, nbb;
+};
+// The gradient sums a launch leaves pending are run as extra blocks of the
+// next launch that reads none of their buffers (launch_wgrad_colsum,
+// launch_gemm_fold) or on their own (launch_sum_pair).
+// scratch: at least ceil(Mrows / 64) (4 width + 4) floats; *pending: the
+// output layer's weight and bias gradient sums.
+int launch_out_backward(hipStream_t s, const OutBackIn &in, float *gw, float *gb, float *scratch, SumPair *pending);
 // A hidden layer's weight gradient (split-K product g into its float32
-// slices g.fout, summed into gw) and bias gradient (column sums of the
-// layer's output gradient dz [rows][cols] through colpart, at least
-// ceil(rows / 64) cols floats, into gb).
+// slices g.fout) and the column-sum partials of its bias gradient (the
+// layer's output gradient dz [rows][cols] into colpart, at least
+// ceil(rows / 64) cols floats), plus the pending sums `fold`; *pending: the
+// sums into gw and gb.
 int launch_wgrad_colsum(hipStream_t s, const GemmArgs &g, const float *dz, int64_t rows, int cols, float *colpart,
-                        float *gw, float *gb);
+                        float *gw, float *gb, const SumPair &fold, SumPair *pending);
+// A product (launch_gemm, no k split, kEpiHidden or kEpiDz) plus the pending sums `fold`.
+int launch_gemm_fold(hipStream_t s, int epi, const GemmArgs &g, const SumPair &fold);
+int launch_sum_pair(hipStream_t s, const SumPair &p);
 // Adam over n parameters at step *step - 1 (the step count is advanced at
 // the start of each training step) with lr_sched[*step - 1 - step0], then
 // the bf16 copies of the updated weights (rt, as launch_refresh).

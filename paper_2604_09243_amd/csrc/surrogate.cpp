@@ -156,8 +156,9 @@ int ensure_train(sbr_mlp *M, int64_t rows)
     M->ksplit = ks;
     const int64_t kin_max = std::max(W, 2 * M->n_ff);
     const int64_t R = (rows + 63) / 64;
-    // the split-K slices of a weight gradient, then the column-sum partials of its bias
-    const int64_t red = std::max(static_cast<int64_t>(ks) * W * kin_max + R * W, R * (4 * W + 4));
+    // the split-K slices of a weight gradient, the column-sum partials of its
+    // bias, and the output layer's partials
+    const int64_t red = static_cast<int64_t>(ks) * W * kin_max + R * W + R * (4 * W + 4);
     if ((rc = M->ws_train.alloc(&M->red, static_cast<size_t>(red)))) return rc;
     M->train_rows = rows;
     return SBR_OK;
@@ -212,7 +213,14 @@ int batch_grad(sbr_mlp *M, hipStream_t s, const double *pts, const double *targe
     ob.part = M->part;
     ob.n_part = static_cast<int>(nblk);
     ob.loss = loss_slot;
-    if ((rc = launch_out_backward(s, ob, M->g + M->woff[D], M->g + M->boff[D], M->red))) return rc;
+    // scratch: the split-K slices of a layer's weight gradient, its bias
+    // partials, then the output layer's partials (pending while the next
+    // layer's slices are written)
+    const int64_t R = (rows + 63) / 64;
+    const int64_t kin_max = std::max(W, K0);
+    float *red_out = M->red + static_cast<int64_t>(M->ksplit) * W * kin_max + R * W;
+    SumPair pending{};
+    if ((rc = launch_out_backward(s, ob, M->g + M->woff[D], M->g + M->boff[D], red_out, &pending))) return rc;
     int cur = 0;
     for (int l = D; l >= 1; --l) {
         const int kin = M->n_in[l - 1];
@@ -229,9 +237,11 @@ int batch_grad(sbr_mlp *M, hipStream_t s, const double *pts, const double *targe
         a.ksplit = M->ksplit;
         a.split_stride = static_cast<int64_t>(W) * kin;
         float *colpart = M->red + static_cast<int64_t>(M->ksplit) * W * kin;
+        SumPair mine{};
         if ((rc = launch_wgrad_colsum(s, a, M->dz[cur], rows, W, colpart, M->g + M->woff[l - 1],
-                                      M->g + M->boff[l - 1])))
+                                      M->g + M->boff[l - 1], pending, &mine)))
             return rc;
+        pending = mine;
         if (l > 1) {
             const int nxt = cur ^ 1;
             GemmArgs b{};
@@ -251,11 +261,13 @@ int batch_grad(sbr_mlp *M, hipStream_t s, const double *pts, const double *targe
             b.ldh = W;
             b.htout = M->dzbt[nxt];
             b.ldht = rows;
-            if ((rc = launch_gemm(s, kEpiDz, b))) return rc;
+            // this layer's gradient sums ride along (the product reads none of their buffers)
+            if ((rc = launch_gemm_fold(s, kEpiDz, b, pending))) return rc;
+            pending = SumPair{};
             cur = nxt;
         }
     }
-    return SBR_OK;
+    return launch_sum_pair(s, pending);  // the first layer's sums
 }
 
 int check_pts(const double *pts, int64_t M, const char *fn)
