@@ -1063,6 +1063,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         PoArgs pa{};
         pa.bvh = bvh;
         pa.rec = rec;
+        pa.rec_slots = 1;
         pa.ang = static_cast<const PoAngle *>(dang) + a0;
         pa.n_angles = m;
         pa.n_units = chunk_units[c];

@@ -322,6 +322,7 @@ int enqueue(sbr_batch *b, hipStream_t s, double *A, double *sigma, std::vector<h
         PoArgs pa{};
         pa.bvh = b->bvh;
         pa.rec = b->rec;
+        pa.rec_slots = 1;
         pa.ang = b->d_ang + a0;
         pa.n_angles = static_cast<int>(a1 - a0);
         pa.n_units = b->c_units[c];

@@ -39,6 +39,8 @@ struct PoP {
     const PoAngle *ang;
     int n_angles;
     const float4 *nrm_id;
+    const float4 *nrm_slot;
+    int rec_slots;  // records name their last triangle by leaf slot (sweeps, batches) or by id (caller hits)
     int mode;
     const double *kf;
     long long *partial;
@@ -162,7 +164,7 @@ __device__ __forceinline__ void weights(const PoP &p, const double *B, const flo
         w[3] = s;
         return;
     }
-    const float4 n32 = p.nrm_id[__float_as_int(r0.w)];
+    const float4 n32 = p.rec_slots ? p.nrm_slot[__float_as_int(r0.w)] : p.nrm_id[__float_as_int(r0.w)];
     const double sg = (flags & SBR_REC_BACK_LAST) ? -1.0 : 1.0;
     const double nx = sg * n32.x, ny = sg * n32.y, nz = sg * n32.z;
     const double dx = r0.x, dy = r0.y, dz = r0.z;
@@ -579,6 +581,8 @@ static PoP make_pop(const PoArgs &a)
     p.ang = a.ang;
     p.n_angles = a.n_angles;
     p.nrm_id = a.bvh->nrm_id;
+    p.nrm_slot = a.bvh->nrm_slot;
+    p.rec_slots = a.rec_slots;
     p.mode = a.mode;
     p.kf = a.kf;
     p.partial = a.partial;

@@ -99,7 +99,8 @@ struct RayQueue {
 // lane whose ray ends (four 16-byte stores into one block, which the L2
 // merges into full-sector writes; four arrays of 8-16 bytes per slot cost
 // about twice the record bytes in partial-sector writes), read whole by PO.
-//   r0 = (d_last.xyz, tri_last)  r1 = (eH_last.xyz, tri_first)
+//   r0 = (d_last.xyz, last hit: leaf slot, or triangle id in records packed
+//   from caller hits)  r1 = (eH_last.xyz, tri_first)
 //   r2 = (eV_last.xyz, N | flags << 8)  D = (D, 0)
 struct __align__(64) Rec {
     float4 r0, r1, r2;
@@ -428,6 +429,7 @@ struct PoArgs {
     const double *kf;    // device wavenumbers
     long long *partial;  // device partial rows
     int fp32;            // SBR_OPT_FP32_PATH: the phase k D in float32 (precision study)
+    int rec_slots;       // the records' last triangle is a leaf slot (trace records), else an input id
 };
 constexpr int kPoRecsPerBlock = 4096;
 __host__ __device__ inline int64_t po_units(int64_t rec_cnt) { return (rec_cnt + kPoRecsPerBlock - 1) / kPoRecsPerBlock; }

@@ -956,7 +956,7 @@ __device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Be
     } else {
         const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
         Rec &q = p.rec.rec[e];
-        q.r0 = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(b.id));
+        q.r0 = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(b.slot));  // the triangle's leaf slot
         q.r1 = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
         q.r2 = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (L.flags << 8)));
         q.D = make_double2(L.D, 0.0);
@@ -964,17 +964,19 @@ __device__ __forceinline__ void sink_hit(const Params &p, const Ray &r, const Be
     }
 }
 
-// The sweep record of ray r from its last hit (triangle tri_last, bookkeeping
-// L, record flags fl), written once when the ray ends, and only when it
-// enters the PO sum (a trapped ray dropped by SBR_OPT_DROP_TRAPPED writes
-// nothing).
-__device__ __forceinline__ void sink_record(const Params &p, const Ray &r, int tri_last, const Last &L, int fl)
+// The sweep record of ray r from its last hit (the hit triangle's leaf slot
+// slot_last, bookkeeping L, record flags fl), written once when the ray
+// ends, and only when it enters the PO sum (a trapped ray dropped by
+// SBR_OPT_DROP_TRAPPED writes nothing).  The slot, not the triangle id:
+// the PO stage reads the normal in leaf order, where the normals of
+// neighbouring rays share cache lines.
+__device__ __forceinline__ void sink_record(const Params &p, const Ray &r, int slot_last, const Last &L, int fl)
 {
     if (!(fl & SBR_REC_VALID)) return;
     const int N = r.meta & 127;
     const int64_t e = p.plans[r.meta >> 8].rec_base + r.id;
     Rec &q = p.rec.rec[e];
-    q.r0 = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(tri_last));
+    q.r0 = make_float4(L.dlx, L.dly, L.dlz, __int_as_float(slot_last));
     q.r1 = make_float4(L.hlx, L.hly, L.hlz, __int_as_float(r.first));
     q.r2 = make_float4(L.vlx, L.vly, L.vlz, __int_as_float(N | (fl << 8)));
     q.D = make_double2(L.D, 0.0);
@@ -1105,7 +1107,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
     // the last hit of the lane's ray: a sweep record is written once, when the
     // ray ends (caller rays are written at every hit)
     Last L;
-    int tri_last = -1;
+    int slot_last = -1;
 
     for (;;) {
         // ---- refill: idle lanes, ranked by a ballot prefix count, take the next positions
@@ -1171,7 +1173,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
             if (b.slot >= 0) {
                 const K3 kv = kvec<kUser>(p, r);
                 const bool cont = bounce(p, r, b, kv, sc.eps, L);
-                tri_last = b.id;
+                slot_last = b.slot;
                 atomicAdd(&bs.hits[r.meta & 127], 1u);
                 if (kUser) sink_hit<kUser>(p, r, b, L);  // caller rays: every hit (the path of ids)
                 if (!cont) {
@@ -1185,12 +1187,12 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : SBR_TRACE_WAVES_PER_SIMD
                             atomicAdd(&bs.trapped, 1u);
                         }
                     }
-                    if (!kUser) sink_record(p, r, tri_last, L, fl);
+                    if (!kUser) sink_record(p, r, slot_last, L, fl);
                     has = false;
                 }
             } else {
                 if ((r.meta & 127) == 0) sink_miss<kUser>(p, r);
-                else if (!kUser) sink_record(p, r, tri_last, L, L.flags);
+                else if (!kUser) sink_record(p, r, slot_last, L, L.flags);
                 has = false;
             }
         }
