@@ -794,6 +794,7 @@ extern "C" int sbr_po_integrate(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_hits
     pa.n_angles = 1;
     pa.n_units = units;
     pa.max_nf = n_freq;
+    pa.kinds = po_kind(ang.dk);
     pa.mode = desc->mode;
     pa.kf = static_cast<const double *>(pkf);
     pa.partial = static_cast<long long *>(ppart);
@@ -1068,6 +1069,7 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         pa.n_angles = m;
         pa.n_units = chunk_units[c];
         pa.max_nf = nf;
+        pa.kinds = po_kind(pang[0].dk);  // one frequency list for every angle
         pa.mode = sw->mode;
         pa.kf = static_cast<const double *>(dkf);
         pa.partial = static_cast<long long *>(dpart);

@@ -84,6 +84,7 @@ struct sbr_batch {
     // chunks: items [cstart[c], cstart[c + 1])
     std::vector<int64_t> cstart, c_tiles, c_units, tile_off, c_rays;
     std::vector<int> c_maxnf;
+    std::vector<int> c_kinds;  // per chunk: kPoEven | kPoUneven of its items
     std::vector<int64_t> c_mask_bytes, c_mask_units;  // primary-ray mask of each chunk
     int blocks = 0;
     // device
@@ -178,6 +179,7 @@ int plan_batch(sbr_batch *b)
     b->c_tiles.clear();
     b->c_units.clear();
     b->c_maxnf.clear();
+    b->c_kinds.clear();
     b->c_rays.clear();
     b->tile_off.clear();
     b->c_mask_bytes.clear();
@@ -187,7 +189,7 @@ int plan_batch(sbr_batch *b)
         b->cstart.push_back(a);
         b->tile_off.push_back(tile_words);
         int64_t rays = 0, tiles = 0, units = 0, rows = 0, e = a;
-        int mnf = 1;
+        int mnf = 1, kinds = 0;
         while (e < ni) {
             const int64_t r = ang[e].rec_cnt;
             if (e > a && rays + r > cap) break;
@@ -201,12 +203,14 @@ int plan_batch(sbr_batch *b)
             units += po_units(r);
             rows += po_units(r) * ang[e].n_f;
             mnf = std::max(mnf, ang[e].n_f);
+            kinds |= po_kind(ang[e].dk);
             ++e;
         }
         b->c_tiles.push_back(tiles);
         b->c_rays.push_back(rays);
         b->c_units.push_back(units);
         b->c_maxnf.push_back(mnf);
+        b->c_kinds.push_back(kinds);
         int64_t mb = 0, mu = 0;
         mask_layout(plans.data(), a, e, mb, mu);
         b->c_mask_bytes.push_back(mb);
@@ -327,6 +331,7 @@ int enqueue(sbr_batch *b, hipStream_t s, double *A, double *sigma, std::vector<h
         pa.n_angles = static_cast<int>(a1 - a0);
         pa.n_units = b->c_units[c];
         pa.max_nf = b->c_maxnf[c];
+        pa.kinds = b->c_kinds[c];
         pa.mode = b->mode;
         pa.kf = b->d_kf;
         pa.partial = b->d_part;

@@ -143,12 +143,22 @@ __device__ __forceinline__ long long fix32(double x)
     return __double_as_longlong(y) - __double_as_longlong(magic);
 }
 
+// The facet normal a record's weights use: PAPER mode the first hit's
+// (r1.w: triangle id), VECTOR mode the last hit's (r0.w: leaf slot where the
+// records name slots, else triangle id).
+__device__ __forceinline__ float4 rec_normal(const PoP &p, const float4 r0, const float4 r1)
+{
+    if (p.mode == SBR_MODE_PAPER) return p.nrm_id[__float_as_int(r1.w)];
+    return p.rec_slots ? p.nrm_slot[__float_as_int(r0.w)] : p.nrm_id[__float_as_int(r0.w)];
+}
+
 // Per-record weights w[p * 2 + q] in float64 from the float32 record fields:
 // the cross-polar weights of VECTOR mode are differences of nearly equal
 // products, and their float32 rounding, identical for the many rays of a flat
-// facet, would add up coherently.
+// facet, would add up coherently.  n is the record's facet normal
+// (rec_normal).
 __device__ __forceinline__ void weights(const PoP &p, const double *B, const float4 r0, const float4 r1,
-                                        const float4 r2, double w[4])
+                                        const float4 r2, const float4 n, double w[4])
 {
     const int meta = __float_as_int(r2.w);
     const int N = meta & 255;
@@ -156,7 +166,7 @@ __device__ __forceinline__ void weights(const PoP &p, const double *B, const flo
     w[0] = w[1] = w[2] = w[3] = 0.0;
     if (!(flags & SBR_REC_VALID)) return;
     if (p.mode == SBR_MODE_PAPER) {
-        const float4 n0 = p.nrm_id[__float_as_int(r1.w)];
+        const float4 n0 = n;
         const double c0 = fabs((static_cast<double>(n0.x) * B[0] + static_cast<double>(n0.y) * B[1]) +
                                static_cast<double>(n0.z) * B[2]);
         const double s = (N & 1) ? c0 : -c0;
@@ -164,7 +174,7 @@ __device__ __forceinline__ void weights(const PoP &p, const double *B, const flo
         w[3] = s;
         return;
     }
-    const float4 n32 = p.rec_slots ? p.nrm_slot[__float_as_int(r0.w)] : p.nrm_id[__float_as_int(r0.w)];
+    const float4 n32 = n;
     const double sg = (flags & SBR_REC_BACK_LAST) ? -1.0 : 1.0;
     const double nx = sg * n32.x, ny = sg * n32.y, nz = sg * n32.z;
     const double dx = r0.x, dy = r0.y, dz = r0.z;
@@ -222,7 +232,7 @@ __device__ __forceinline__ void po_passes(const PoP &p, const PoAngle &A, int64_
             const double D = rec.D.x;
             if (!((__float_as_int(q2.w) >> 8) & SBR_REC_VALID)) continue;  // dropped as trapped: no term
             double w[4];
-            weights(p, A.basis, q0, q1, q2, w);
+            weights(p, A.basis, q0, q1, q2, rec_normal(p, q0, q1), w);
             double sd, cd, rs = 0.0, rc = 1.0;
             phase_sincos(f32 ? phase32(kf[f0], D) : kf[f0] * D, sd, cd);
             if (uniform) phase_sincos(A.dk * D, rs, rc);  // evenly spaced: each step turns the phasor by dk D
@@ -275,23 +285,30 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
     po_passes<kFT, kPoThreads>(p, A, u - A.unit_base, 0, A.n_f, red);
 }
 
-// Many frequencies: block (u, y) takes the records of unit u (as k_po) and
-// the frequencies [64 y, 64 y + 64) of its angle.  The records are staged in
-// LDS once per round of 512 (every field of a thread's two slots loaded in
-// one round trip), the valid ones packed in a fixed order (thread-major,
-// then the thread's slots in order), with what every frequency needs
-// computed once per record: the weights, D and, for evenly spaced
-// wavenumbers, the phasor exp(j k_fc D) at the chunk's first frequency and
-// the steps exp(j s dk D) for s = 1, F, 2F, 4F (F = kMfFT = 8, by repeated
-// squaring).  So the records leave HBM once per 64 frequencies, not once
-// per pass.  Thread t takes frequency group g = t mod G (F consecutive
-// frequencies; G = 1, 2, 4 or 8 groups as the chunk needs) and the packed
-// records t / G, t / G + 256 / G, ... of every round; its phasor starts at
-// exp(j k_fc D) turned by F g dk D (three complex products by a staged step
-// or by 1) and turns by dk D per frequency (where the spacing is uneven: one
-// sine and cosine per frequency).  Two blocks share a CU, so one stages
-// while the other sums.  A chunk of one frequency takes the k_po<1>
-// summation, so single-frequency angles give the same bits in either kernel.
+// Many frequencies, two kernels: k_po_mf<false> takes the angles whose
+// wavenumbers are evenly spaced (step dk), k_po_mf<true> the others; each
+// passes over the other's blocks at once, and the host launches only the
+// kinds a call has.  Block (u, y) takes the records of unit u (as k_po) and
+// the chunk of CH = 8 F frequencies [CH y, CH y + CH) of its angle (F per
+// thread: 8 evenly spaced, 4 uneven).  First the block lists the slots
+// that hold a record (one round trip over the slots' bytes); then rounds
+// of 512 listed slots stage the records in LDS (every field of a thread's
+// two slots in one round trip, then their facet normals), the valid ones
+// packed in a fixed order (thread-major, then the thread's slots in
+// order), with what every frequency needs computed once per record: the
+// weights, D and, evenly spaced, the phasor exp(j k_fc D) at the chunk's
+// first frequency and the steps exp(j s dk D) for s = 1, F, 2F, 4F (by
+// repeated squaring).  So the records leave HBM once per chunk, not once
+// per pass, and the empty slots of masked or missed rays cost no round.
+// Thread t takes frequency group g = t mod G (G = 1, 2, 4 or 8 groups as
+// the chunk needs) and the packed records t / G, t / G + 256 / G, ... of
+// every round.  Evenly spaced, a group is F consecutive frequencies: its
+// phasor starts at exp(j k_fc D) turned by F g dk D (three complex
+// products by a staged step or by 1) and turns by dk D per frequency.
+// Uneven, the chunk is split evenly over the groups (ceil(n / G) each) and
+// every frequency takes one sine and cosine.  A chunk of one frequency
+// takes the k_po<1> summation, so single-frequency angles give the same
+// bits in either kernel.
 #ifndef SBR_PO_FT
 #define SBR_PO_FT 8  // frequencies per thread in k_po_mf
 #endif
@@ -313,57 +330,121 @@ __device__ __forceinline__ long long shfl_xor64(long long x, int off)
                                   static_cast<unsigned>(lo));
 }
 
-__global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
+// Frequencies per thread and blocks per CU of the uneven-spacing kernel:
+// every frequency takes its own sine and cosine, so a smaller accumulator
+// set (and three blocks per CU) costs no extra record loads per frequency
+// worth having.
+constexpr int kMfFTu = 4, kMfBlocksU = 3;
+
+template <bool kUneven>  // the angles of the launch it takes: evenly spaced (false) or not (true)
+__global__ __launch_bounds__(kPoThreads, kUneven ? kMfBlocksU : 2) void k_po_mf(PoP p)
 {
-    __shared__ double sw[4][kMfSub];    // weights
-    __shared__ double sD[kMfSub];       // path length
-    __shared__ double sph[10][kMfSub];  // (cos, sin) of k_fc D, dk D, F dk D, 2F dk D, 4F dk D (F = kMfFT)
+    constexpr int FT = kUneven ? kMfFTu : kMfFT;  // frequencies per thread
+    constexpr int CH = 8 * FT;                    // frequencies per block
+    __shared__ double sw[4][kMfSub];              // weights
+    __shared__ double sD[kMfSub];                 // path length
+    // evenly spaced: (cos, sin) of k_fc D, dk D, F dk D, 2F dk D, 4F dk D (F = kMfFT)
+    __shared__ double sph[kUneven ? 1 : 10][kUneven ? 1 : kMfSub];
+    __shared__ double skf[CH];                    // uneven: the chunk's wavenumbers
     __shared__ int scnt[kPoThreads / 64];
-    __shared__ long long red[kPoThreads / 64][kMfChunk * 8];
+    __shared__ long long red[kPoThreads / 64][CH * 8];
     const int64_t u = blockIdx.x;
     const PoAngle &A = p.ang[po_angle_of(p, u)];
+    const bool uniform = A.dk != 0.0;
+    if (uniform == kUneven) return;  // the other kernel's angle
     const int nf = A.n_f;
-    const int fc = static_cast<int>(blockIdx.y) * kMfChunk;
+    const int fc = static_cast<int>(blockIdx.y) * CH;
     if (fc >= nf) return;  // the whole block
-    const int nfc = min(kMfChunk, nf - fc);
+    const int nfc = min(CH, nf - fc);
     const int64_t c = u - A.unit_base;
     if (nfc == 1) {
         po_passes<1, kPoThreads>(p, A, c, fc, fc + 1, reinterpret_cast<long long (*)[8]>(&red[0][0]));
         return;
     }
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int lg = nfc <= kMfFT ? 0 : nfc <= 2 * kMfFT ? 1 : nfc <= 4 * kMfFT ? 2 : 3;
+    const int lg = nfc <= FT ? 0 : nfc <= 2 * FT ? 1 : nfc <= 4 * FT ? 2 : 3;
     const int G = 1 << lg, g = tid & (G - 1), rl = tid >> lg, RL = kPoThreads >> lg;
-    const int fs = fc + g * kMfFT;                       // this thread's first frequency
-    const int nft = max(0, min(kMfFT, fc + nfc - fs));  // and how many
+    // frequencies per group: evenly spaced F (the staged steps F, 2F, 4F
+    // start the groups' phasors) unless one group takes the chunk, uneven
+    // the chunk split evenly over the groups
+    const int nfg = !kUneven && lg > 0 ? FT : (nfc + G - 1) >> lg;
+    const int fs = fc + g * nfg;                       // this thread's first frequency
+    const int nft = max(0, min(nfg, fc + nfc - fs));  // and how many
     const double *kf = p.kf + A.kf_off;
-    const bool uniform = A.dk != 0.0;
     const int64_t r0i = c * kPoRecsPerBlock;
     const int64_t r1i = min(r0i + kPoRecsPerBlock, A.rec_cnt);
-    double acc[kMfFT][8];
+    if (kUneven) {  // 0 past the chunk's end: summed by the idle slots of the last group, never stored
+        for (int i = tid; i < CH; i += kPoThreads) skf[i] = i < nfc ? kf[fc + i] : 0.0;
+    }
+    double acc[FT][8];
 #pragma unroll
-    for (int ft = 0; ft < kMfFT; ++ft)
+    for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
         for (int e = 0; e < 8; ++e) acc[ft][e] = 0.0;
-    for (int64_t s0 = r0i; s0 < r1i; s0 += kMfSub) {
-        // stage: thread t holds slots s0 + t + 256 j, j = 0, 1
+    // Uneven spacing: the block's slots that hold a record, listed once
+    // (their bytes in one round trip: slot r0i + i 256 + t read by thread
+    // t), in a fixed order (thread-major, then i); the rounds below then
+    // stage only those, so the empty slots of masked or missed rays cost
+    // neither rounds nor round trips.  The list lives in the reduction
+    // buffer, unused until the last round has ended.  Evenly spaced, the
+    // rounds take the slots as they come: a list costs those blocks more
+    // registers than the rounds it saves (their records fill most slots).
+    uint16_t *slist = reinterpret_cast<uint16_t *>(&red[0][0]);
+    static_assert(!kUneven || sizeof(red) >= kPoRecsPerBlock * sizeof(uint16_t), "k_po_mf: slot list does not fit");
+    static_assert(kPoRecsPerBlock <= 65536, "k_po_mf: slot offsets are 16-bit");
+    int nheld = static_cast<int>(r1i - r0i);
+    long long *out = p.partial + (A.part_base + c * nf + fc) * 8;
+    if constexpr (kUneven) {
+        nheld = 0;
+        constexpr int kSpt = kPoRecsPerBlock / kPoThreads;
+        static_assert(kSpt <= 32, "k_po_mf: a thread's slots are one 32-bit mask");
+        uint32_t hm = 0;
+#pragma unroll
+        for (int i = 0; i < kSpt; ++i) {
+            const int64_t e = r0i + i * kPoThreads + tid;
+            if (e < r1i && p.rec.held[A.rec_base + e] != 0) hm |= 1u << i;
+        }
+        const int hc = __popc(hm);
+        int inc = hc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += v;
+        }
+        if (lane == 63) scnt[wv] = inc;
+        __syncthreads();
+        int pos = inc - hc;
+        for (int x = 0; x < kPoThreads / 64; ++x) {
+            if (x < wv) pos += scnt[x];
+            nheld += scnt[x];
+        }
+        for (int i = 0; hm != 0; ++i, hm >>= 1)
+            if (hm & 1) slist[pos++] = static_cast<uint16_t>(i * kPoThreads + tid);
+        __syncthreads();
+        if (nheld == 0) {  // no record (the same for every thread): zero sums without the reduction
+            for (int i = tid; i < nfc * 8; i += kPoThreads) out[i] = 0;
+            return;
+        }
+    }
+    for (int s0 = 0; s0 < nheld; s0 += kMfSub) {
+        // stage: thread t holds list entries (uneven) or slots (evenly
+        // spaced) s0 + t + 256 j, j = 0, 1
         constexpr int kPer = kMfSub / kPoThreads;
         int vmask = 0, cnt = 0;
-        // the slots' bytes first, then every field of the slots that hold a
-        // record at once (one more round trip; empty slots cost no bytes)
+        // every field of the listed slots at once (one round trip), then the
+        // facet normals the weights need
         float4 q0[kPer], q1[kPer], q2[kPer];
         double Dj[kPer];
         bool held[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const int64_t e = s0 + tid + j * kPoThreads;
-            const int64_t ea = A.rec_base + e;
-            held[j] = e < r1i && p.rec.held[ea] != 0;
+            const int x = s0 + tid + j * kPoThreads;
+            held[j] = x < nheld && (kUneven || p.rec.held[A.rec_base + r0i + x] != 0);
         }
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const int64_t ea = A.rec_base + s0 + tid + j * kPoThreads;
             if (held[j]) {
+                const int x = s0 + tid + j * kPoThreads;
+                const int64_t ea = A.rec_base + r0i + (kUneven ? slist[x] : x);
                 const Rec &rec = p.rec.rec[ea];
                 q0[j] = rec.r0;
                 q1[j] = rec.r1;
@@ -396,10 +477,10 @@ __global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
             if (!((vmask >> j) & 1)) continue;
             const double D = Dj[j];
             double w[4];
-            weights(p, A.basis, q0[j], q1[j], q2[j], w);
+            weights(p, A.basis, q0[j], q1[j], q2[j], rec_normal(p, q0[j], q1[j]), w);
             for (int k = 0; k < 4; ++k) sw[k][pos] = w[k];
             sD[pos] = D;
-            if (uniform) {
+            if constexpr (!kUneven) {
                 double bs, bc, rs, rc;
                 phase_sincos(kf[fc] * D, bs, bc);
                 phase_sincos(A.dk * D, rs, rc);
@@ -421,16 +502,40 @@ __global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
             ++pos;
         }
         __syncthreads();
-        if (uniform && nft == kMfFT) {
-            // the common case, branch free: evenly spaced, a full group
+        if constexpr (kUneven) {
+            // one sine and cosine per frequency; every thread takes nfg
+            // (a trip count the same for the whole block)
+            const double *kq = skf + (fs - fc);
+            for (int q = rl; q < nvalid; q += RL) {
+                const double w0 = sw[0][q], w1 = sw[1][q], w2 = sw[2][q], w3 = sw[3][q];
+                const double D = sD[q];
+#pragma unroll
+                for (int ft = 0; ft < FT; ++ft) {
+                    if (ft >= nfg) break;
+                    double sd, cd;
+                    phase_sincos(kq[ft] * D, sd, cd);
+                    acc[ft][0] = __builtin_fma(w0, sd, acc[ft][0]);
+                    acc[ft][1] = __builtin_fma(w0, cd, acc[ft][1]);
+                    acc[ft][2] = __builtin_fma(w1, sd, acc[ft][2]);
+                    acc[ft][3] = __builtin_fma(w1, cd, acc[ft][3]);
+                    acc[ft][4] = __builtin_fma(w2, sd, acc[ft][4]);
+                    acc[ft][5] = __builtin_fma(w2, cd, acc[ft][5]);
+                    acc[ft][6] = __builtin_fma(w3, sd, acc[ft][6]);
+                    acc[ft][7] = __builtin_fma(w3, cd, acc[ft][7]);
+                }
+            }
+        } else if (nft == FT) {
+            // the common case, branch free: a full group
 #pragma unroll SBR_PO_QUNROLL
             for (int q = rl; q < nvalid; q += RL) {
                 const double w0 = sw[0][q], w1 = sw[1][q], w2 = sw[2][q], w3 = sw[3][q];
                 double cd = sph[0][q], sd = sph[1][q];
                 const double rc = sph[2][q], rs = sph[3][q];
-                // start at frequency fc + F g: turn by F g dk D (g < 8: the staged steps F, 2F, 4F)
+                // start at frequency fc + F g: turn by F g dk D (g < 8: the staged steps F, 2F, 4F;
+                // bits of g at or above lg are 0, a turn by exactly 1)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
+                    if (b >= lg) break;
                     // by the step (tc, ts) or by 1 (exactly: 0 t + 1 and 0 t), without a branch
                     const double on = static_cast<double>((g >> b) & 1);
                     const double tc = __builtin_fma(on, sph[4 + 2 * b][q], 1.0 - on), ts = on * sph[5 + 2 * b][q];
@@ -439,7 +544,7 @@ __global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
                     cd = c2;
                 }
 #pragma unroll
-                for (int ft = 0; ft < kMfFT; ++ft) {
+                for (int ft = 0; ft < FT; ++ft) {
                     if (ft > 0) {
                         const double s2 = __builtin_fma(sd, rc, cd * rs);
                         cd = __builtin_fma(cd, rc, -(sd * rs));
@@ -456,36 +561,27 @@ __global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
                 }
             }
         } else if (nft > 0) {
+            // a group of fewer than F frequencies
             for (int q = rl; q < nvalid; q += RL) {
                 const double w0 = sw[0][q], w1 = sw[1][q], w2 = sw[2][q], w3 = sw[3][q];
-                double sd, cd, rc = 1.0, rs = 0.0;
-                if (uniform) {
-                    cd = sph[0][q];
-                    sd = sph[1][q];
-                    rc = sph[2][q];
-                    rs = sph[3][q];
+                double cd = sph[0][q], sd = sph[1][q];
+                const double rc = sph[2][q], rs = sph[3][q];
 #pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        const bool on = (g >> b) & 1;
-                        const double tc = on ? sph[4 + 2 * b][q] : 1.0, ts = on ? sph[5 + 2 * b][q] : 0.0;
-                        const double c2 = __builtin_fma(cd, tc, -(sd * ts));
-                        sd = __builtin_fma(cd, ts, sd * tc);
-                        cd = c2;
-                    }
-                } else {
-                    phase_sincos(kf[fs] * sD[q], sd, cd);
+                for (int b = 0; b < 3; ++b) {
+                    if (b >= lg) break;
+                    const bool on = (g >> b) & 1;
+                    const double tc = on ? sph[4 + 2 * b][q] : 1.0, ts = on ? sph[5 + 2 * b][q] : 0.0;
+                    const double c2 = __builtin_fma(cd, tc, -(sd * ts));
+                    sd = __builtin_fma(cd, ts, sd * tc);
+                    cd = c2;
                 }
 #pragma unroll
-                for (int ft = 0; ft < kMfFT; ++ft) {
+                for (int ft = 0; ft < FT; ++ft) {
                     if (ft >= nft) break;
                     if (ft > 0) {
-                        if (uniform) {
-                            const double s2 = __builtin_fma(sd, rc, cd * rs);
-                            cd = __builtin_fma(cd, rc, -(sd * rs));
-                            sd = s2;
-                        } else {
-                            phase_sincos(kf[fs + ft] * sD[q], sd, cd);
-                        }
+                        const double s2 = __builtin_fma(sd, rc, cd * rs);
+                        cd = __builtin_fma(cd, rc, -(sd * rs));
+                        sd = s2;
                     }
                     acc[ft][0] = __builtin_fma(w0, sd, acc[ft][0]);
                     acc[ft][1] = __builtin_fma(w0, cd, acc[ft][1]);
@@ -501,20 +597,24 @@ __global__ __launch_bounds__(kPoThreads, 2) void k_po_mf(PoP p)
         __syncthreads();  // before the next round overwrites the stage
     }
     // fixed point, summed over the lanes of a group (lane = g mod G) of each
-    // wave, then over the waves
+    // wave, then over the waves; group g's sums at red[(g FT + ft) 8 + k]
 #pragma unroll
-    for (int ft = 0; ft < kMfFT; ++ft)
+    for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             long long v = fix32(acc[ft][k]);
             for (int off = 32; off >= G; off >>= 1) v += shfl_xor64(v, off);
-            if (lane < G) red[wv][(lane * kMfFT + ft) * 8 + k] = v;
+            if (lane < G) red[wv][(lane * FT + ft) * 8 + k] = v;
         }
     __syncthreads();
-    long long *out = p.partial + (A.part_base + c * nf + fc) * 8;
     for (int i = tid; i < nfc * 8; i += kPoThreads) {
+        int at = i;  // evenly spaced: nfg = F, or one group
+        if constexpr (kUneven) {
+            const int f = i >> 3, gf = f / nfg;  // frequency fc + f: group gf, its (f - gf nfg)-th
+            at = ((gf * FT + f - gf * nfg) << 3) | (i & 7);
+        }
         long long v = 0;
-        for (int x = 0; x < kPoThreads / 64; ++x) v += red[x][i];
+        for (int x = 0; x < kPoThreads / 64; ++x) v += red[x][at];
         out[i] = v;
     }
 }
@@ -599,8 +699,16 @@ int launch_po(hipStream_t s, const PoArgs &a)
     if (a.max_nf == 1 || a.fp32) {  // the precision study takes every frequency's phase on its own
         k_po<1><<<static_cast<unsigned>(a.n_units), kPoThreads, 0, s>>>(make_pop(a));
     } else {
-        const dim3 grid(static_cast<unsigned>(a.n_units), static_cast<unsigned>((a.max_nf + kMfChunk - 1) / kMfChunk));
-        k_po_mf<<<grid, kPoThreads, 0, s>>>(make_pop(a));
+        // each kernel passes over the other kind's blocks at once
+        if (a.kinds != kPoUneven) {
+            const dim3 grid(static_cast<unsigned>(a.n_units), static_cast<unsigned>((a.max_nf + kMfChunk - 1) / kMfChunk));
+            k_po_mf<false><<<grid, kPoThreads, 0, s>>>(make_pop(a));
+        }
+        if (a.kinds != kPoEven) {
+            constexpr int ch = 8 * kMfFTu;
+            const dim3 grid(static_cast<unsigned>(a.n_units), static_cast<unsigned>((a.max_nf + ch - 1) / ch));
+            k_po_mf<true><<<grid, kPoThreads, 0, s>>>(make_pop(a));
+        }
     }
     SBR_HIP(hipGetLastError());
     return SBR_OK;

@@ -430,7 +430,12 @@ struct PoArgs {
     long long *partial;  // device partial rows
     int fp32;            // SBR_OPT_FP32_PATH: the phase k D in float32 (precision study)
     int rec_slots;       // the records' last triangle is a leaf slot (trace records), else an input id
+    int kinds;           // kPoEven | kPoUneven: which spacings the angles have (0: not known, both)
 };
+// Angle kinds of a PO launch: evenly spaced wavenumbers (dk != 0), or not
+// (dk == 0, one frequency included); each has its own many-frequency kernel.
+constexpr int kPoEven = 1, kPoUneven = 2;
+inline int po_kind(double dk) { return dk != 0.0 ? kPoEven : kPoUneven; }
 constexpr int kPoRecsPerBlock = 4096;
 __host__ __device__ inline int64_t po_units(int64_t rec_cnt) { return (rec_cnt + kPoRecsPerBlock - 1) / kPoRecsPerBlock; }
 int launch_po(hipStream_t s, const PoArgs &a);

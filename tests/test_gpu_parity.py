@@ -298,13 +298,15 @@ def test_sweep_multifrequency_equals_single(torch, ctx):
         assert np.array_equal(A, A2.cpu().numpy())  # each bitwise reproducible
 
 
-@pytest.mark.parametrize("fs", [np.array([8e9, 9.3e9, 10e9, 8.5e9, 9.9e9]), np.linspace(8e9, 10e9, 9),
+@pytest.mark.parametrize("fs", [np.array([8e9, 9.3e9, 10e9, 8.5e9, 9.9e9]), np.linspace(8e9, 10e9, 6),
+                                np.linspace(8e9, 10e9, 8), np.linspace(8e9, 10e9, 9),
                                 np.linspace(8e9, 10e9, 30), np.linspace(8e9, 10e9, 65),
                                 np.sort(np.random.default_rng(5).uniform(8e9, 10e9, 100))],
-                         ids=["uneven5", "even9", "even30", "even65", "uneven100"])
+                         ids=["uneven5", "even6", "even8", "even9", "even30", "even65", "uneven100"])
 def test_po_many_frequencies_on_gpu_records(torch, ctx, orc, fs):
     """sbr_po_integrate over many frequencies (1, 2, 4 and 8 groups of 8
-    frequencies per block; chunks of 64, the last one of 1 for 65) against
+    frequencies per block, a group full or partly filled; chunks of 64, the
+    last one of 1 for 65) against
     the oracle's float64 PO sum (Eq. po_sum) over the very records the GPU
     traced."""
     say("case po many frequencies", len(fs))
