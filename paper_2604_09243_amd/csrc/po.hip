@@ -134,6 +134,51 @@ __device__ __forceinline__ void phase_sincos(double ph, double &so, double &co)
     sincos_pi(__builtin_fma(-nturn, two_pi_lo, __builtin_fma(-nturn, two_pi_hi, ph)), so, co);
 }
 
+// (cos, sin)(m pi / 32) for m = tid < 64 into tab[m]: sincos_pi of
+// j pi / 32, j = min(m mod 16, 16 - m mod 16) <= 8 (so |x| <= pi / 4), the
+// rest by exact symmetries (a swap for pi / 2 - x, a quarter turn per
+// m / 16).
+__device__ __forceinline__ void turn_table_entry(int m, double2 *tab)
+{
+    const double c_hi = 0.09817477042468103;   // fl64(pi / 32)
+    const double c_lo = 3.827021247335479e-18;  // pi / 32 - fl64(pi / 32)
+    const int k = m >> 4, j = m & 15, jj = j <= 8 ? j : 16 - j;
+    double s0, c0;
+    sincos_pi(__builtin_fma(static_cast<double>(jj), c_hi, jj * c_lo), s0, c0);
+    const double c = j <= 8 ? c0 : s0, s = j <= 8 ? s0 : c0;
+    // times j^k (j the imaginary unit): (c, s), (-s, c), (-c, -s), (s, -c)
+    tab[m] = k == 0 ? make_double2(c, s) : k == 1 ? make_double2(-s, c) : k == 2 ? make_double2(-c, -s)
+                                                                              : make_double2(s, -c);
+}
+
+// sin and cos of the phase ph (float64) by the table of turn_table_entry:
+// ph = q pi / 32 + r with q the nearest integer (pi / 32 as a two-term sum),
+// |r| <= pi / 64, where sin r and cos r need Taylor terms up to r^9 and r^8
+// (the next ones are below 1e-19); then the angle-addition formulas with
+// (cos, sin)(q pi / 32) = tab[q mod 64].
+__device__ __forceinline__ void phase_sincos_tab(double ph, const double2 *tab, double &so, double &co)
+{
+    const double c_hi = 0.09817477042468103;   // fl64(pi / 32)
+    const double c_lo = 3.827021247335479e-18;  // pi / 32 - fl64(pi / 32)
+    const double q = rint(ph * 10.185916357881302);  // 32 / pi
+    double r = __builtin_fma(-q, c_hi, ph);
+    r = __builtin_fma(-q, c_lo, r);
+    const double z = r * r;
+    double ps = 1.0 / 362880.0;
+    ps = __builtin_fma(ps, z, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, z, 1.0 / 120.0);
+    ps = __builtin_fma(ps, z, -1.0 / 6.0);
+    const double sn = __builtin_fma(r * z, ps, r);
+    double pc = 1.0 / 40320.0;
+    pc = __builtin_fma(pc, z, -1.0 / 720.0);
+    pc = __builtin_fma(pc, z, 1.0 / 24.0);
+    pc = __builtin_fma(pc, z, -0.5);
+    const double cs = __builtin_fma(z, pc, 1.0);
+    const double2 t = tab[static_cast<int>(q) & 63];  // two's complement: the residue mod 64 for q < 0 too
+    so = __builtin_fma(t.y, cs, t.x * sn);
+    co = __builtin_fma(t.x, cs, -(t.y * sn));
+}
+
 // round(x * 2^32) as a 64-bit integer for |x| < 2^19, via the float64
 // rounding of x * 2^32 + 1.5 * 2^52.
 __device__ __forceinline__ long long fix32(double x)
@@ -346,6 +391,7 @@ __global__ __launch_bounds__(kPoThreads, kUneven ? kMfBlocksU : 2) void k_po_mf(
     // evenly spaced: (cos, sin) of k_fc D, dk D, F dk D, 2F dk D, 4F dk D (F = kMfFT)
     __shared__ double sph[kUneven ? 1 : 10][kUneven ? 1 : kMfSub];
     __shared__ double skf[CH];                    // uneven: the chunk's wavenumbers
+    __shared__ double2 stab[kUneven ? 64 : 1];    // uneven: (cos, sin)(m pi / 32)
     __shared__ int scnt[kPoThreads / 64];
     __shared__ long long red[kPoThreads / 64][CH * 8];
     const int64_t u = blockIdx.x;
@@ -373,8 +419,9 @@ __global__ __launch_bounds__(kPoThreads, kUneven ? kMfBlocksU : 2) void k_po_mf(
     const double *kf = p.kf + A.kf_off;
     const int64_t r0i = c * kPoRecsPerBlock;
     const int64_t r1i = min(r0i + kPoRecsPerBlock, A.rec_cnt);
-    if (kUneven) {  // 0 past the chunk's end: summed by the idle slots of the last group, never stored
+    if constexpr (kUneven) {  // 0 past the chunk's end: summed by the idle slots of the last group, never stored
         for (int i = tid; i < CH; i += kPoThreads) skf[i] = i < nfc ? kf[fc + i] : 0.0;
+        if (tid < 64) turn_table_entry(tid, stab);
     }
     double acc[FT][8];
 #pragma unroll
@@ -513,7 +560,7 @@ __global__ __launch_bounds__(kPoThreads, kUneven ? kMfBlocksU : 2) void k_po_mf(
                 for (int ft = 0; ft < FT; ++ft) {
                     if (ft >= nfg) break;
                     double sd, cd;
-                    phase_sincos(kq[ft] * D, sd, cd);
+                    phase_sincos_tab(kq[ft] * D, stab, sd, cd);
                     acc[ft][0] = __builtin_fma(w0, sd, acc[ft][0]);
                     acc[ft][1] = __builtin_fma(w0, cd, acc[ft][1]);
                     acc[ft][2] = __builtin_fma(w1, sd, acc[ft][2]);
