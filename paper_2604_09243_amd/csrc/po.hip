@@ -376,9 +376,9 @@ __device__ __forceinline__ long long shfl_xor64(long long x, int off)
 }
 
 // Frequencies per thread and blocks per CU of the uneven-spacing kernel:
-// every frequency takes its own sine and cosine, so a smaller accumulator
-// set (and three blocks per CU) costs no extra record loads per frequency
-// worth having.
+// there every frequency takes its own sine and cosine, so a record's LDS
+// reads are a small part of its work per frequency, and 4 frequencies per
+// thread (half the accumulators of 8) buy a third block per CU.
 constexpr int kMfFTu = 4, kMfBlocksU = 3;
 
 template <bool kUneven>  // the angles of the launch it takes: evenly spaced (false) or not (true)
