@@ -334,26 +334,27 @@ __global__ __launch_bounds__(kPoThreads) void k_po(PoP p)
 // wavenumbers are evenly spaced (step dk), k_po_mf<true> the others; each
 // passes over the other's blocks at once, and the host launches only the
 // kinds a call has.  Block (u, y) takes the records of unit u (as k_po) and
-// the chunk of CH = 8 F frequencies [CH y, CH y + CH) of its angle (F per
-// thread: 8 evenly spaced, 4 uneven).  First the block lists the slots
-// that hold a record (one round trip over the slots' bytes); then rounds
-// of 512 listed slots stage the records in LDS (every field of a thread's
-// two slots in one round trip, then their facet normals), the valid ones
-// packed in a fixed order (thread-major, then the thread's slots in
-// order), with what every frequency needs computed once per record: the
-// weights, D and, evenly spaced, the phasor exp(j k_fc D) at the chunk's
-// first frequency and the steps exp(j s dk D) for s = 1, F, 2F, 4F (by
-// repeated squaring).  So the records leave HBM once per chunk, not once
-// per pass, and the empty slots of masked or missed rays cost no round.
-// Thread t takes frequency group g = t mod G (G = 1, 2, 4 or 8 groups as
+// the chunk of CH frequencies [CH y, CH y + CH) of its angle: evenly
+// spaced 64 (8 groups of F = 8 per thread), uneven 32 (16 groups of 2).
+// The rounds stage 512 record slots at a time in LDS (every field of a
+// thread's two slots in one round trip, then their facet normals), the
+// valid records packed in a fixed order (thread-major, then the thread's
+// slots in order), with what every frequency needs computed once per
+// record: the weights, D and, evenly spaced, the phasor exp(j k_fc D) at
+// the chunk's first frequency and the steps exp(j s dk D) for s = 1, F,
+// 2F, 4F (by repeated squaring).  So the records leave HBM once per chunk,
+// not once per pass.  Uneven, the block first lists the slots that hold a
+// record (one round trip over the slots' bytes) and the rounds take only
+// those, so the empty slots of masked or missed rays cost no round.
+// Thread t takes frequency group g = t mod G (G a power of two, as many as
 // the chunk needs) and the packed records t / G, t / G + 256 / G, ... of
 // every round.  Evenly spaced, a group is F consecutive frequencies: its
 // phasor starts at exp(j k_fc D) turned by F g dk D (three complex
 // products by a staged step or by 1) and turns by dk D per frequency.
 // Uneven, the chunk is split evenly over the groups (ceil(n / G) each) and
-// every frequency takes one sine and cosine.  A chunk of one frequency
-// takes the k_po<1> summation, so single-frequency angles give the same
-// bits in either kernel.
+// every frequency takes one sine and cosine (phase_sincos_tab).  A chunk of
+// one frequency takes the k_po<1> summation, so single-frequency angles
+// give the same bits in either kernel.
 #ifndef SBR_PO_FT
 #define SBR_PO_FT 8  // frequencies per thread in k_po_mf
 #endif
@@ -375,17 +376,29 @@ __device__ __forceinline__ long long shfl_xor64(long long x, int off)
                                   static_cast<unsigned>(lo));
 }
 
-// Frequencies per thread and blocks per CU of the uneven-spacing kernel:
-// there every frequency takes its own sine and cosine, so a record's LDS
-// reads are a small part of its work per frequency, and 4 frequencies per
-// thread (half the accumulators of 8) buy a third block per CU.
-constexpr int kMfFTu = 4, kMfBlocksU = 3;
+// Frequencies per thread, blocks per CU and frequency groups per block of
+// the uneven-spacing kernel: there every frequency takes its own sine and
+// cosine, so a record's LDS reads are a small part of its work per
+// frequency, and 2 frequencies per thread (a quarter of the accumulators of
+// 8) buy four blocks per CU, with up to 16 groups so that a chunk is still
+// 32 frequencies (its records staged once).
+#ifndef SBR_PO_FTU
+#define SBR_PO_FTU 2  // frequencies per thread, uneven spacing
+#endif
+#ifndef SBR_PO_BLOCKSU
+#define SBR_PO_BLOCKSU 4  // blocks per CU, uneven spacing
+#endif
+#ifndef SBR_PO_GROUPSU
+#define SBR_PO_GROUPSU 16  // at most this many frequency groups per block, uneven spacing
+#endif
+constexpr int kMfFTu = SBR_PO_FTU, kMfBlocksU = SBR_PO_BLOCKSU, kMfGroupsU = SBR_PO_GROUPSU;
 
 template <bool kUneven>  // the angles of the launch it takes: evenly spaced (false) or not (true)
 __global__ __launch_bounds__(kPoThreads, kUneven ? kMfBlocksU : 2) void k_po_mf(PoP p)
 {
     constexpr int FT = kUneven ? kMfFTu : kMfFT;  // frequencies per thread
-    constexpr int CH = 8 * FT;                    // frequencies per block
+    constexpr int GM = kUneven ? kMfGroupsU : 8;  // frequency groups per block, at most
+    constexpr int CH = GM * FT;                   // frequencies per block
     __shared__ double sw[4][kMfSub];              // weights
     __shared__ double sD[kMfSub];                 // path length
     // evenly spaced: (cos, sin) of k_fc D, dk D, F dk D, 2F dk D, 4F dk D (F = kMfFT)
@@ -408,7 +421,8 @@ __global__ __launch_bounds__(kPoThreads, kUneven ? kMfBlocksU : 2) void k_po_mf(
         return;
     }
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int lg = nfc <= FT ? 0 : nfc <= 2 * FT ? 1 : nfc <= 4 * FT ? 2 : 3;
+    int lg = 0;  // G = 2^lg groups of FT cover the chunk (lg <= 3 evenly spaced: the staged steps)
+    while ((FT << lg) < nfc) ++lg;
     const int G = 1 << lg, g = tid & (G - 1), rl = tid >> lg, RL = kPoThreads >> lg;
     // frequencies per group: evenly spaced F (the staged steps F, 2F, 4F
     // start the groups' phasors) unless one group takes the chunk, uneven
@@ -752,7 +766,7 @@ int launch_po(hipStream_t s, const PoArgs &a)
             k_po_mf<false><<<grid, kPoThreads, 0, s>>>(make_pop(a));
         }
         if (a.kinds != kPoEven) {
-            constexpr int ch = 8 * kMfFTu;
+            constexpr int ch = kMfGroupsU * kMfFTu;
             const dim3 grid(static_cast<unsigned>(a.n_units), static_cast<unsigned>((a.max_nf + ch - 1) / ch));
             k_po_mf<true><<<grid, kPoThreads, 0, s>>>(make_pop(a));
         }
