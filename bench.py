@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--no-mask", action="store_true",
                     help="trace every primary ray (no per-angle mask of empty cells)")
     ap.add_argument("--chunk-log2", type=int, default=0,
-                    help="batch: rays per chunk = 2^N (16..30; 0 = the library default)")
+                    help="batch and aircraft: rays per chunk = 2^N (16..30; 0 = the library default)")
     ap.add_argument("--bvh4", action="store_true",
                     help="walk a four-wide copy of the tree (same results; a traversal study, slower on the aircraft)")
     ap.add_argument("--builder", choices=("lbvh", "sah", "ploc"), default="sah",
@@ -619,6 +619,9 @@ def bench_aircraft(args):
     torch.cuda.synchronize()
     build_ms = 1e3 * (time.perf_counter() - tb)
     tune, tune_s = None, 0.0
+    if args.chunk_log2:
+        from paper_2604_09243_amd import sbr
+        tune = sbr.make_tune(chunk_log2=args.chunk_log2)
     if args.autotune:
         print("autotuning the sweep", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
@@ -658,7 +661,8 @@ def bench_aircraft(args):
         "config": {"workload": w.name + "_360az_lambda8_b8", "angles": w.n_angles, "rays_per_step": stats[-1]["rays"],
                    "queries_per_step": stats[-1]["queries"], "triangles": int(len(w.T)), "mode": "VECTOR",
                    "bvh": args.builder, "tree_width": 4 if args.bvh4 else 2, "primary_mask": not args.no_mask, "polarisations": "HH,HV,VH,VV",
-                   "tune": (tune if tune is not None else sbr_default_tune()).as_dict()},
+                   "tune": (tune if tune is not None else sbr_default_tune()).as_dict(),
+                   "chunks_per_step": launches // args.steps},  # chunk_log2 0: the library's automatic size
         # the queries that traversed the tree: the mask's primary-ray misses left out
         "value_traced": (queries - masked) / dt,
         "autotune_s": tune_s,

@@ -277,9 +277,28 @@ sbr_tune default_tune()
     t.claim_tiles = 0;  // automatic (auto_claim_tiles)
     t.refill_min = 64;
     t.blocks_per_cu = 0;
-    t.chunk_log2 = kDefaultChunkLog2;
+    t.chunk_log2 = 0;  // automatic (auto_sweep_chunk_log2; batches kDefaultChunkLog2)
     t.reserved = 0;
     return t;
+}
+
+// Automatic chunk of a sweep: 2^30 rays when their record slots (64 bytes
+// and a slot byte each, 69 GB) fit in a quarter of the device memory that is
+// free or already held by this workspace's record buffers, else 2^29.  The
+// chunking changes no result (each chunk is traced and summed the same
+// way); larger chunks mean fewer launch tails.
+static int auto_sweep_chunk_log2(Workspace *ws)
+{
+    const size_t need = (size_t(1) << 30) * (sizeof(Rec) + 1);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return kDefaultChunkLog2;
+    }
+    size_t held = 0;
+    for (const int w : {W_REC, W_HELD})
+        if (w < static_cast<int>(ws->bufs.size())) held += ws->bufs[w].bytes;
+    return (fr + held) / 4 >= need ? 30 : kDefaultChunkLog2;
 }
 
 int auto_claim_tiles(const sbr_bvh *bvh)
@@ -862,6 +881,10 @@ extern "C" int sbr_rcs_sweep(sbr_ctx *ctx, const sbr_bvh *bvh, const sbr_sweep *
         tune = *sw->tune;
     }
     if (sw->flags & SBR_OPT_WAVEFRONT) tune.schedule = kScheduleWavefront;
+    if (tune.chunk_log2 == 0) {
+        SBR_HIP(hipSetDevice(ctx->device));
+        tune.chunk_log2 = auto_sweep_chunk_log2(ctx->ws);
+    }
     int rc0 = normalize_tune(tune);
     if (rc0) return rc0;
     if (tune.claim_tiles == 0) tune.claim_tiles = auto_claim_tiles(bvh);

@@ -99,7 +99,7 @@ def test_plan_matches_oracle_exactly(orc, bbox, th, ph, ds):
 def test_default_tune():
     from paper_2604_09243_amd import sbr
     t = sbr.default_tune().as_dict()
-    assert t == dict(schedule=0, tile_w=8, claim_tiles=0, refill_min=64, blocks_per_cu=0, chunk_log2=29)
+    assert t == dict(schedule=0, tile_w=8, claim_tiles=0, refill_min=64, blocks_per_cu=0, chunk_log2=0)
 
 
 def test_plan_rejects_bad_spacing():
