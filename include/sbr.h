@@ -338,9 +338,9 @@ typedef struct {
     int32_t refill_min;    /* idle lanes that trigger a refill (streaming launch), 1..64 */
     int32_t blocks_per_cu; /* persistent blocks of 256 threads per compute unit; 0 = occupancy limit */
     int32_t chunk_log2;    /* rays per trace/PO chunk = 2^chunk_log2, 16..30; 0 = automatic: a sweep
-                              takes 30 when the chunk's record slots (65 bytes a ray, 69 GB) fit in a
-                              quarter of the device memory free or already held by the context's
-                              record buffers, else 29; a batch takes 29.  Records of a chunk stay in
+                              or batch takes 30 when the chunk's record slots (65 bytes a ray, 69 GB)
+                              fit in a quarter of the device memory free or already held by the context's
+                              or batch's record buffers, else 29.  Records of a chunk stay in
                               device memory between its trace and its PO stage. */
     int32_t reserved;
 } sbr_tune;

@@ -282,12 +282,7 @@ sbr_tune default_tune()
     return t;
 }
 
-// Automatic chunk of a sweep: 2^30 rays when their record slots (64 bytes
-// and a slot byte each, 69 GB) fit in a quarter of the device memory that is
-// free or already held by this workspace's record buffers, else 2^29.  The
-// chunking changes no result (each chunk is traced and summed the same
-// way); larger chunks mean fewer launch tails.
-static int auto_sweep_chunk_log2(Workspace *ws)
+int auto_chunk_log2(size_t held_bytes)
 {
     const size_t need = (size_t(1) << 30) * (sizeof(Rec) + 1);
     size_t fr = 0, tot = 0;
@@ -295,10 +290,16 @@ static int auto_sweep_chunk_log2(Workspace *ws)
         (void)hipGetLastError();
         return kDefaultChunkLog2;
     }
+    return (fr + held_bytes) / 4 >= need ? 30 : kDefaultChunkLog2;
+}
+
+// The sweep's: the record buffers its workspace already holds count as free.
+static int auto_sweep_chunk_log2(Workspace *ws)
+{
     size_t held = 0;
     for (const int w : {W_REC, W_HELD})
         if (w < static_cast<int>(ws->bufs.size())) held += ws->bufs[w].bytes;
-    return (fr + held) / 4 >= need ? 30 : kDefaultChunkLog2;
+    return auto_chunk_log2(held);
 }
 
 int auto_claim_tiles(const sbr_bvh *bvh)

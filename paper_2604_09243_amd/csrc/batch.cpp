@@ -499,8 +499,7 @@ extern "C" int sbr_batch_create(sbr_ctx *ctx, const sbr_bvh *scenes, const sbr_b
     for (int64_t f = 0; f < d->n_freqs_total; ++f)
         if (!(d->freqs_hz[f] > 0.0) || !std::isfinite(d->freqs_hz[f]))
             return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: frequencies must be positive and finite");
-    sbr_tune tune = default_tune();
-    tune.chunk_log2 = kBatchChunkLog2;
+    sbr_tune tune = default_tune();  // chunk_log2 0: automatic
     if (d->tune) {
         if (d->tune->struct_size < sizeof(sbr_tune))
             return fail(SBR_ERR_INVALID_ARG, "sbr_batch_create: tune->struct_size too small");
@@ -510,6 +509,10 @@ extern "C" int sbr_batch_create(sbr_ctx *ctx, const sbr_bvh *scenes, const sbr_b
         return fail(SBR_ERR_UNSUPPORTED,
                     "sbr_batch_create: SBR_OPT_FP32_PATH and SBR_OPT_FP64_TRAVERSE are study options of sweeps and traces");
     if (d->flags & SBR_OPT_WAVEFRONT) tune.schedule = kScheduleWavefront;
+    if (tune.chunk_log2 == 0) {
+        SBR_HIP(hipSetDevice(ctx->device));
+        tune.chunk_log2 = auto_chunk_log2(0);
+    }
     int rc = normalize_tune(tune);
     if (rc) return rc;
     const int ns = n_scenes(scenes);
@@ -604,6 +607,12 @@ extern "C" int sbr_batch_set_tune(sbr_batch *b, const sbr_tune *t)
     if (t->struct_size < sizeof(sbr_tune)) return fail(SBR_ERR_INVALID_ARG, "sbr_batch_set_tune: struct_size too small");
     sbr_tune n = *t;
     if (b->flags & SBR_OPT_WAVEFRONT) n.schedule = kScheduleWavefront;
+    if (n.chunk_log2 == 0) {  // the batch's own record slots count as free: the new plan replaces them
+        SBR_HIP(hipSetDevice(b->device));
+        int64_t mr = 0;
+        for (const int64_t r : b->c_rays) mr = std::max(mr, r);
+        n.chunk_log2 = auto_chunk_log2(static_cast<size_t>(mr) * (sizeof(Rec) + 1));
+    }
     int rc = normalize_tune(n);
     if (rc) return rc;
     b->tune = n;

@@ -375,6 +375,13 @@ bool trace_walks_wide(const sbr_bvh *bvh, uint32_t flags, int schedule);
 // api.cpp helpers shared with the batch entry points
 sbr_tune default_tune();
 int normalize_tune(sbr_tune &t);           // check_tune, then chunk_log2 0 -> default
+// Automatic chunk size (chunk_log2 0) of a sweep or batch, on the current
+// device: 2^30 rays when their record slots (64 bytes and a slot byte each,
+// 69 GB) fit in a quarter of the device memory that is free or already held
+// (held_bytes: the caller's own record buffers, about to be replaced), else
+// kDefaultChunkLog2.  The chunking changes no result (each chunk is traced
+// and summed the same way); larger chunks mean fewer launch tails.
+int auto_chunk_log2(size_t held_bytes);
 // claim_tiles 0 (automatic): one tile per claim when the tree outgrows an
 // XCD's L2 (waves on neighbouring tiles at once then share its node and
 // triangle lines), two otherwise (fewer claims of cheap tiles)
@@ -394,9 +401,8 @@ void fill_plan(const sbr_angle_plan &ap, double ds, int tile_w, AnglePlan &p);
 // its PO; larger chunks mean fewer launches and fewer launch tails (the
 // 64-scene batch replays in 2.18 / 1.89 / 1.82 s with 2^26 / 2^28 / 2^29-ray
 // chunks, the aircraft sweep traces in 233 / 200 / 194 ms; 2^30 gains 2 %
-// more for 69 GB).
+// more for 69 GB, taken where the device has room: auto_chunk_log2).
 constexpr int kDefaultChunkLog2 = 29;
-constexpr int kBatchChunkLog2 = 29;
 // Autotuner cache: the context's map, then the JSON-lines file named by
 // $SBR_TUNE_CACHE (if any).
 bool tune_lookup(sbr_ctx *ctx, const std::string &key, sbr_tune *out);
